@@ -1,0 +1,163 @@
+/*
+ * lrei.h - C ABI of the MI355X LREI library (liblrei.so).
+ *
+ * LREI (Low-Rank Eigenmode Integration, arXiv 2508.21200) advances the
+ * quantum Landau-Lifshitz (q-LL, eq. 1.1) or Landau-Lifshitz-Gilbert (q-LLG,
+ * eq. 1.2) equation for an n-spin density matrix rho = V Lambda_0 V* of rank r
+ * (Sec. 3.1, eq. 3.1).  Only the N x r factor V is stored (N = 2^n, Sec. 3.2);
+ * the spectrum Lambda_0 is fixed for all time (Sec. 2, Sec. 3.6).
+ *
+ * Conventions for every entry point:
+ *  - Status codes are returned; no exception or abort crosses the ABI.  The
+ *    message of the last failure on a context is lrei_last_error().
+ *  - Host buffers passed in are copied before the call returns; device
+ *    buffers (flag *_is_device = 1) are read/written on the context's stream
+ *    and the call returns after that stream has drained them.  The caller
+ *    keeps ownership of every buffer it passes.
+ *  - A failing setter leaves the previous state unchanged.
+ *  - Complex arrays are interleaved (re, im) IEEE doubles, row-major N x r:
+ *    the r columns of basis state x are contiguous.  Basis state x has site i
+ *    in bit i; bit value 0 is spin up (s^z = +1).
+ *  - One context is used by one host thread at a time.
+ */
+#ifndef LREI_H
+#define LREI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define LREI_API __attribute__((visibility("default")))
+#else
+#define LREI_API
+#endif
+
+typedef struct lrei_ctx lrei_ctx;
+
+typedef enum {
+  LREI_OK = 0,
+  LREI_E_INVALID = 1,       /* bad argument; nothing changed                     */
+  LREI_E_NOMEM = 2,         /* device allocation failed or problem too large      */
+  LREI_E_NOTCONVERGED = 3,  /* eigensolve did not converge; state rolled back      */
+  LREI_E_DEVICE = 4,        /* HIP runtime error                                   */
+  LREI_E_STATE = 5,         /* call out of order (e.g. step before set_rho)        */
+  LREI_E_NUMERIC = 6        /* non-finite values produced; state rolled back       */
+} lrei_status;
+
+typedef enum { LREI_QLL = 0, LREI_QLLG = 1 } lrei_model;
+
+/* Time integrators (Sec. 3.6, 3.7).  RK2 is the paper's Heun tableau; RK3 is
+ * Kutta's; RK4 is the classical method.  ABm use the standard Adams-Bashforth
+ * weights with an RK start-up (see lrei_options.ab_bootstrap). */
+typedef enum {
+  LREI_RK1 = 1, LREI_RK2 = 2, LREI_RK3 = 3, LREI_RK4 = 4,
+  LREI_AB2 = 12, LREI_AB3 = 13, LREI_AB4 = 14
+} lrei_scheme;
+
+/* LREI_FP64: every N-space pass in complex FP64.
+ * LREI_MIXED: N-space passes (H.V, Gram products, basis combination) in
+ * complex FP32 with per-tile FP32 MFMA products accumulated across tiles in
+ * FP64; the projected problem (Cholesky, Householder, stage algebra, Jacobi
+ * eigensolve) always runs in FP64. */
+typedef enum { LREI_FP64 = 0, LREI_MIXED = 1 } lrei_precision;
+
+/* Start rotation for the projected eigensolve: identity, the first-order
+ * analytic rotation, or the one proposed by the learned network. */
+typedef enum { LREI_WARM_PLAIN = 0, LREI_WARM_ANALYTIC = 1, LREI_WARM_LEARNED = 2 } lrei_warm;
+
+typedef struct {
+  int precision;          /* lrei_precision, default LREI_FP64                           */
+  double eig_tol;         /* Jacobi off-diagonal tolerance relative to max|diag|, 1e-15  */
+  int eig_max_sweeps;     /* Jacobi sweep limit per eigensolve, default 40               */
+  int warm;               /* lrei_warm, default LREI_WARM_PLAIN                          */
+  int ab_bootstrap;       /* RK scheme for the first m-1 ABm steps, default LREI_RK4     */
+  int householder_mode;   /* 1: complement action through Householder reflectors (eq.
+                             3.3, Sec. 3.4), default; 0: orthogonal projector form      */
+  int use_graph;          /* 1: capture one step as a hipGraph and replay it (default)  */
+  int deterministic;      /* 1 (default): fixed-order reductions, bitwise reproducible  */
+  const char *autotune_cache; /* path of the JSON tile cache, or NULL                   */
+} lrei_options;
+
+typedef struct {
+  int64_t steps_done;            /* time steps completed on this context               */
+  int64_t eigensolves;           /* projected eigensolves performed                    */
+  int64_t jacobi_sweeps;         /* total Jacobi sweeps                                */
+  int32_t max_sweeps_one_solve;  /* largest sweep count of one eigensolve              */
+  int32_t dropped_directions;    /* Krylov directions dropped as dependent (last step)  */
+  double min_pivot_ratio;        /* smallest Cholesky pivot / Gram diagonal (last step) */
+  double ortho_error;            /* max |V*V - I| at the start of the last step         */
+  double energy;                 /* Tr(Lambda_0 V* H V) at the start of the last step   */
+  double last_step_ms;           /* wall time of the last lrei_step call                */
+  int64_t warm_accepted;         /* learned/analytic start rotations used                */
+  int64_t warm_rejected;         /* start rotations rejected (fell back to identity)     */
+} lrei_stats;
+
+/* Fills *opt with the defaults listed above. */
+LREI_API void lrei_default_options(lrei_options *opt);
+
+/* Creates a context on HIP device `hip_device`.  `hip_stream` is a hipStream_t
+ * to run on (e.g. torch.cuda.current_stream().cuda_stream) or NULL for a
+ * stream owned by the context.  `opt` may be NULL for defaults.  The context
+ * owns all device memory it allocates; lrei_destroy frees it. */
+LREI_API lrei_status lrei_create(lrei_ctx **out, int hip_device, void *hip_stream, const lrei_options *opt);
+LREI_API void lrei_destroy(lrei_ctx *ctx);
+LREI_API const char *lrei_last_error(const lrei_ctx *ctx);
+
+/* The spin Hamiltonian of Sec. 5, eq. (5.1), in Pauli form:
+ *   H = sum_b 1/2 sum_{a,c} J_b[a][c] s^a_{i_b} s^c_{j_b} + 1/2 sum_i h_i . s_i,
+ * which equals eq. (5.1) with S = (hbar/2) s, J^{ac} = J delta_ac + eps_acd d_d
+ * and h = g mu_B b.  `bond_ij` is [n_bonds][2] site pairs (0 <= i < j < n),
+ * `bond_J` is [n_bonds][3][3] row-major (x, y, z), `site_h` is [n][3] or NULL.
+ * `hbar` enters only the equations of motion.  1 <= n <= 30.
+ * Invalidates the rank-r state's Adams-Bashforth history. */
+LREI_API lrei_status lrei_set_hamiltonian(lrei_ctx *ctx, int n_spins, int n_bonds, const int32_t *bond_ij,
+                                 const double *bond_J, const double *site_h, double hbar);
+
+/* Sets rho = V diag(lambda) V* (Sec. 3.1, eq. 3.1).  lambda: r finite values,
+ * strictly positive, non-increasing.  V: N x r complex128 with orthonormal
+ * columns (max |V*V - I| <= 1e-10), host or device pointer.  1 <= r <= 32,
+ * r <= N.  Requires a Hamiltonian. */
+LREI_API lrei_status lrei_set_rho(lrei_ctx *ctx, int r, const double *lambda, const void *V, int v_is_device);
+
+/* Advances n_steps >= 0 time steps of size dt > 0 with damping kappa >= 0
+ * (q-LL: eq. 1.1 through eq. 4.1; q-LLG: eq. 1.2 through eq. 3.2), using the
+ * LREI-RK (Sec. 3.6) or LREI-AB (Sec. 3.7) scheme.  Adams-Bashforth history
+ * carries over between calls with the same model, scheme, dt and kappa; any
+ * change restarts it with the bootstrap scheme.  On failure the state is that
+ * of the last completed step. */
+LREI_API lrei_status lrei_step(lrei_ctx *ctx, int model, int scheme, double dt, double kappa, int n_steps);
+
+/* Copies the current state out: lambda (r values, always Lambda_0, Sec. 3.6)
+ * and V (N x r complex128, host or device pointer).  Either may be NULL. */
+LREI_API lrei_status lrei_get_rho(lrei_ctx *ctx, double *lambda, void *V, int v_is_device);
+
+/* Energy Tr(Lambda_0 V* H V) and magnetisation M_v = (1/n) sum_i <S_i^v>
+ * with S = (hbar/2) s (Sec. 3.5, eq. 3.6) for the current state.  Either
+ * output may be NULL. */
+LREI_API lrei_status lrei_observables(lrei_ctx *ctx, double *energy, double magnetization[3]);
+
+LREI_API lrei_status lrei_get_stats(lrei_ctx *ctx, lrei_stats *stats);
+
+/* Y = H X for an N x r block X (r <= 32) in the context's Hamiltonian,
+ * complex128, host or device pointers (both the same kind).  This runs the
+ * same matrix-free kernel the step uses (Sec. 3.3: "inexpensive due to the
+ * sparsity of H"), in FP64. */
+LREI_API lrei_status lrei_apply_hamiltonian(lrei_ctx *ctx, int r, const void *X, void *Y, int is_device);
+
+/* Checkpoint: the state (n, r, lambda, V, step counter, AB history) as an
+ * opaque byte string.  With buf == NULL, *len receives the size needed. */
+LREI_API lrei_status lrei_get_state(lrei_ctx *ctx, void *buf, size_t *len);
+LREI_API lrei_status lrei_set_state(lrei_ctx *ctx, const void *buf, size_t len);
+
+/* Blocks until all work queued by this context has finished. */
+LREI_API lrei_status lrei_synchronize(lrei_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LREI_H */

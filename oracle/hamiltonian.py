@@ -98,6 +98,46 @@ def spin_operator(n, site, a, hbar=1.0):
     return 0.5 * hbar * site_operator(n, site, PAULI[a])
 
 
+def apply_H_rows(n, bonds, J, h, V, rows):
+    """Rows `rows` of H V only, from the same Pauli strings (for spot checks at large n).
+
+    For each Pauli string the destination row x couples to the single source
+    row x ^ flip, with the phase of s^a_i s^b_j evaluated at the bits of x.
+    """
+    rows = np.asarray(rows, dtype=np.int64)
+    V = np.asarray(V)
+    out = np.zeros((rows.size, V.shape[1]), dtype=np.complex128)
+
+    def elem(a, b):  # <b| s^a |b'> for the source bit b' implied by the flip
+        if a == 0:
+            return np.ones_like(b, dtype=np.complex128)
+        if a == 1:
+            return np.where(b == 0, -1j, 1j)
+        return (1 - 2 * b).astype(np.complex128)
+
+    def bit(x, s):
+        return (x >> s) & 1
+
+    for k, (i, j) in enumerate(np.asarray(bonds).reshape(-1, 2)):
+        i, j = int(i), int(j)
+        for a in range(3):
+            for b in range(3):
+                c = J[k][a][b]
+                if c == 0.0:
+                    continue
+                flip = (0 if a == 2 else 1 << i) | (0 if b == 2 else 1 << j)
+                ph = elem(a, bit(rows, i)) * elem(b, bit(rows, j))
+                out += 0.5 * c * ph[:, None] * V[rows ^ flip]
+    if h is not None:
+        h = np.asarray(h, dtype=np.float64).reshape(n, 3)
+        for i in range(n):
+            for a in range(3):
+                if h[i, a] != 0.0:
+                    flip = 0 if a == 2 else 1 << i
+                    out += 0.5 * h[i, a] * elem(a, bit(rows, i))[:, None] * V[rows ^ flip]
+    return out
+
+
 class Hamiltonian:
     """Bundle of the Hamiltonian description with a matrix-free apply."""
 

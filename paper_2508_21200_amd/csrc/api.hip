@@ -1,0 +1,649 @@
+// C ABI of the LREI library: context management, validation, and the step
+// driver that sequences the N-space passes and the projected step kernel.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lrei_internal.h"
+
+using namespace lrei;
+
+namespace {
+
+constexpr int kStatsLen = 32;
+constexpr uint64_t kStateMagic = 0x4c52454953543031ull;  // "LREIST01"
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  bool ensure(size_t b) {
+    if (b <= bytes && p) return true;
+    release();
+    if (hipMalloc(&p, b) != hipSuccess) {
+      p = nullptr;
+      return false;
+    }
+    bytes = b;
+    return true;
+  }
+};
+
+// Butcher tableaux (Sec. 3.6).  RK2: the paper's Heun tableau; RK3: Kutta;
+// RK4: classical.
+void tableau(int scheme, int &s, double a[kMaxStages][kMaxStages], double b[kMaxStages]) {
+  for (int i = 0; i < kMaxStages; ++i) {
+    b[i] = 0;
+    for (int j = 0; j < kMaxStages; ++j) a[i][j] = 0;
+  }
+  switch (scheme) {
+    case LREI_RK1: s = 1; b[0] = 1; break;
+    case LREI_RK2: s = 2; a[1][0] = 1; b[0] = b[1] = 0.5; break;
+    case LREI_RK3:
+      s = 3; a[1][0] = 0.5; a[2][0] = -1; a[2][1] = 2;
+      b[0] = 1.0 / 6; b[1] = 4.0 / 6; b[2] = 1.0 / 6;
+      break;
+    default:
+      s = 4; a[1][0] = 0.5; a[2][1] = 0.5; a[3][2] = 1;
+      b[0] = 1.0 / 6; b[1] = 2.0 / 6; b[2] = 2.0 / 6; b[3] = 1.0 / 6;
+      break;
+  }
+}
+
+}  // namespace
+
+struct lrei_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  lrei_options opt{};
+  std::string err;
+
+  // Hamiltonian
+  bool have_h = false;
+  int n = 0;
+  long long N = 0;
+  double hbar = 1.0;
+  TermTable terms;
+  DevBuf d_off, d_diag;
+  int n_off = 0, n_diag = 0;
+
+  // state
+  bool have_rho = false;
+  int r = 0;
+  std::vector<double> lam;
+  bool fp32 = false;
+  DevBuf blocks[kMaxStages + 1];
+  DevBuf save;       // state at the start of a step call (rollback)
+  DevBuf partials;
+  DevBuf ws_buf;
+  DevBuf stats_buf;
+  DevBuf lam_dev;
+  SmallWs ws{};
+  int grid = 1;
+  int64_t steps_done = 0;
+  lrei_stats stats{};
+
+  // captured step graph
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int g_model = -1, g_scheme = -1;
+  double g_dt = 0, g_kappa = 0;
+
+  lrei_status fail(lrei_status st, const std::string &m) {
+    err = m;
+    return st;
+  }
+  size_t elem() const { return fp32 ? sizeof(float2) : sizeof(double2); }
+  void drop_graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    g_model = g_scheme = -1;
+  }
+};
+
+namespace {
+
+lrei_status check_hip(lrei_ctx *c, hipError_t e, const char *what) {
+  if (e == hipSuccess) return LREI_OK;
+  return c->fail(LREI_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(expr)                                        \
+  do {                                                      \
+    lrei_status _st = check_hip(ctx, (expr), #expr);        \
+    if (_st != LREI_OK) return _st;                         \
+  } while (0)
+
+// Allocates every buffer the state of rank r needs.
+lrei_status alloc_state(lrei_ctx *ctx, int r, bool fp32) {
+  const size_t el = fp32 ? sizeof(float2) : sizeof(double2);
+  const size_t blk = (size_t)ctx->N * r * el;
+  for (int i = 0; i <= kMaxStages; ++i)
+    if (!ctx->blocks[i].ensure(blk)) return ctx->fail(LREI_E_NOMEM, "device allocation of Krylov blocks failed");
+  if (!ctx->save.ensure(blk)) return ctx->fail(LREI_E_NOMEM, "device allocation failed");
+  ctx->grid = nspace_grid(ctx->N, r);
+  const size_t pcount = (size_t)ctx->grid * cheb_partial_splits(r) * 3 * r * r;
+  if (!ctx->partials.ensure(pcount * sizeof(double2) + 2 * ctx->grid * sizeof(double2)))
+    return ctx->fail(LREI_E_NOMEM, "device allocation failed");
+  const int D = (kMaxStages + 1) * r;
+  const size_t ws_elems = (size_t)kMaxStages * 3 * r * r      // meas
+                          + 4 * (size_t)D * D                  // gamma, R, Rinv, Hh
+                          + (4 * (size_t)D * r + 2 * (size_t)D * D + 4 * (size_t)r * r)  // work
+                          + (size_t)kMaxStages * 3 * D * r     // stage
+                          + (size_t)D * r;                     // Cfin
+  if (!ctx->ws_buf.ensure(ws_elems * sizeof(double2))) return ctx->fail(LREI_E_NOMEM, "device allocation failed");
+  if (!ctx->stats_buf.ensure(kStatsLen * sizeof(double))) return ctx->fail(LREI_E_NOMEM, "device allocation failed");
+  if (!ctx->lam_dev.ensure(kMaxR * sizeof(double))) return ctx->fail(LREI_E_NOMEM, "device allocation failed");
+  double2 *w = (double2 *)ctx->ws_buf.p;
+  ctx->ws.meas = w; w += (size_t)kMaxStages * 3 * r * r;
+  ctx->ws.gamma = w; w += (size_t)D * D;
+  ctx->ws.R = w; w += (size_t)D * D;
+  ctx->ws.Rinv = w; w += (size_t)D * D;
+  ctx->ws.Hh = w; w += (size_t)D * D;
+  ctx->ws.work = w; w += 4 * (size_t)D * r + 2 * (size_t)D * D + 4 * (size_t)r * r;
+  ctx->ws.stage = w; w += (size_t)kMaxStages * 3 * D * r;
+  ctx->ws.Cfin = w;
+  ctx->ws.stats = (double *)ctx->stats_buf.p;
+  return LREI_OK;
+}
+
+// One Chebyshev pass with fused Grams, reduced into ws.meas[slot].
+void cheb_pass_into(lrei_ctx *ctx, int r, int grid, int mode, const void *prev, const void *cur, void *next,
+                    double2 *partials, double2 *meas) {
+  ChebArgs a{};
+  a.Pprev = prev;
+  a.Pcur = cur;
+  a.Pnext = next;
+  a.off = (const DevOffTerm *)ctx->d_off.p;
+  a.diag = (const DevDiagTerm *)ctx->d_diag.p;
+  a.n_off = ctx->n_off;
+  a.n_diag = ctx->n_diag;
+  a.N = ctx->N;
+  a.r = r;
+  const double e = ctx->terms.gershgorin > 0 ? ctx->terms.gershgorin : 1.0;
+  a.alpha = 1.0 / e;
+  a.shift = 0.0;
+  a.mode = mode;
+  a.partials = partials;
+  a.grid = grid;
+  launch_cheb(ctx->fp32, a, ctx->stream);
+  if (mode != 2) launch_reduce(partials, grid * cheb_partial_splits(r), 3 * r * r, meas, ctx->stream);
+}
+
+void cheb_pass(lrei_ctx *ctx, int mode, const void *prev, const void *cur, void *next, int slot) {
+  cheb_pass_into(ctx, ctx->r, ctx->grid, mode, prev, cur, next, (double2 *)ctx->partials.p,
+                 ctx->ws.meas + (size_t)slot * 3 * ctx->r * ctx->r);
+}
+
+// Enqueues one LREI-RK step (Chebyshev Krylov passes, projected step, combine).
+void enqueue_rk_step(lrei_ctx *ctx, int model, int scheme, double dt, double kappa) {
+  SmallRkParams p{};
+  int s;
+  tableau(scheme, s, p.a, p.b);
+  p.r = ctx->r;
+  p.s = s;
+  p.nblocks = s + 1;
+  p.model = model;
+  p.householder_mode = ctx->opt.householder_mode;
+  p.max_sweeps = ctx->opt.eig_max_sweeps;
+  p.warm = ctx->opt.warm;
+  p.kappa = kappa;
+  p.hbar = ctx->hbar;
+  p.h = dt;
+  p.eig_tol = ctx->opt.eig_tol;
+  p.shift = 0.0;
+  p.halfwidth = ctx->terms.gershgorin > 0 ? ctx->terms.gershgorin : 1.0;
+  for (int i = 0; i < ctx->r; ++i) p.lam[i] = ctx->lam[i];
+  p.lds_elems = small_lds_elems(p.nblocks * ctx->r, ctx->r);
+  cheb_pass(ctx, 0, nullptr, ctx->blocks[0].p, ctx->blocks[1].p, 0);
+  for (int j = 1; j < s; ++j) cheb_pass(ctx, 1, ctx->blocks[j - 1].p, ctx->blocks[j].p, ctx->blocks[j + 1].p, j);
+  launch_small_rk(p, ctx->ws, ctx->stream);
+  const void *bl[kMaxBlocks];
+  for (int i = 0; i <= s; ++i) bl[i] = ctx->blocks[i].p;
+  launch_combine(ctx->fp32, bl, s + 1, ctx->ws.Cfin, ctx->blocks[0].p, ctx->N, ctx->r, ctx->grid, ctx->stream);
+}
+
+lrei_status read_stats(lrei_ctx *ctx, double *h) {
+  HIPCHK(hipMemcpyAsync(h, ctx->stats_buf.p, kStatsLen * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return LREI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void lrei_default_options(lrei_options *o) {
+  if (!o) return;
+  o->precision = LREI_FP64;
+  o->eig_tol = 1e-15;
+  o->eig_max_sweeps = 40;
+  o->warm = LREI_WARM_PLAIN;
+  o->ab_bootstrap = LREI_RK4;
+  o->householder_mode = 1;
+  o->use_graph = 1;
+  o->deterministic = 1;
+  o->autotune_cache = nullptr;
+}
+
+lrei_status lrei_create(lrei_ctx **out, int hip_device, void *hip_stream, const lrei_options *opt) {
+  if (!out) return LREI_E_INVALID;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return LREI_E_DEVICE;
+  if (hip_device < 0 || hip_device >= ndev) return LREI_E_INVALID;
+  lrei_ctx *ctx = new lrei_ctx();
+  lrei_default_options(&ctx->opt);
+  if (opt) ctx->opt = *opt;
+  if (ctx->opt.precision != LREI_FP64 && ctx->opt.precision != LREI_MIXED) {
+    delete ctx;
+    return LREI_E_INVALID;
+  }
+  if (!(ctx->opt.eig_tol > 0) || ctx->opt.eig_max_sweeps < 1) {
+    delete ctx;
+    return LREI_E_INVALID;
+  }
+  ctx->fp32 = ctx->opt.precision == LREI_MIXED;
+  ctx->device = hip_device;
+  if (hipSetDevice(hip_device) != hipSuccess) {
+    delete ctx;
+    return LREI_E_DEVICE;
+  }
+  if (hip_stream) {
+    ctx->stream = (hipStream_t)hip_stream;
+  } else {
+    if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete ctx;
+      return LREI_E_DEVICE;
+    }
+    ctx->own_stream = true;
+  }
+  *out = ctx;
+  return LREI_OK;
+}
+
+void lrei_destroy(lrei_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  ctx->drop_graph();
+  for (auto &b : ctx->blocks) b.release();
+  ctx->save.release();
+  ctx->partials.release();
+  ctx->ws_buf.release();
+  ctx->stats_buf.release();
+  ctx->lam_dev.release();
+  ctx->d_off.release();
+  ctx->d_diag.release();
+  if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+}
+
+const char *lrei_last_error(const lrei_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+lrei_status lrei_set_hamiltonian(lrei_ctx *ctx, int n_spins, int n_bonds, const int32_t *bond_ij,
+                                 const double *bond_J, const double *site_h, double hbar) {
+  if (!ctx) return LREI_E_INVALID;
+  if (!(hbar > 0) || !std::isfinite(hbar)) return ctx->fail(LREI_E_INVALID, "hbar must be positive and finite");
+  TermTable t;
+  std::string e;
+  if (!build_terms(n_spins, n_bonds, bond_ij, bond_J, site_h, t, e)) return ctx->fail(LREI_E_INVALID, e);
+  if (ctx->have_rho && n_spins != ctx->n)
+    return ctx->fail(LREI_E_STATE, "n_spins differs from the current state; set a new rho after changing n");
+  HIPCHK(hipSetDevice(ctx->device));
+  std::vector<DevOffTerm> off(t.off.size());
+  for (size_t i = 0; i < t.off.size(); ++i) {
+    off[i].mask = t.off[i].mask;
+    off[i].sa = t.off[i].sa;
+    off[i].sb = t.off[i].sb;
+    off[i].pad = 0;
+    for (int q = 0; q < 4; ++q) {
+      off[i].re[q] = t.off[i].re[q];
+      off[i].im[q] = t.off[i].im[q];
+    }
+  }
+  std::vector<DevDiagTerm> dg(t.diag.size());
+  for (size_t i = 0; i < t.diag.size(); ++i) dg[i] = {t.diag[i].si, t.diag[i].sj, t.diag[i].w};
+  if (off.size() > 256 || dg.size() > 512) return ctx->fail(LREI_E_INVALID, "too many Hamiltonian terms (max 256 off-diagonal, 512 diagonal)");
+  DevBuf d_off, d_diag;
+  if (!d_off.ensure(std::max<size_t>(1, off.size()) * sizeof(DevOffTerm)) ||
+      !d_diag.ensure(std::max<size_t>(1, dg.size()) * sizeof(DevDiagTerm)))
+    return ctx->fail(LREI_E_NOMEM, "device allocation failed");
+  if (!off.empty()) HIPCHK(hipMemcpy(d_off.p, off.data(), off.size() * sizeof(DevOffTerm), hipMemcpyHostToDevice));
+  if (!dg.empty()) HIPCHK(hipMemcpy(d_diag.p, dg.data(), dg.size() * sizeof(DevDiagTerm), hipMemcpyHostToDevice));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  ctx->d_off.release();
+  ctx->d_diag.release();
+  ctx->d_off = d_off;
+  ctx->d_diag = d_diag;
+  d_off.p = nullptr;
+  d_diag.p = nullptr;
+  ctx->n_off = (int)off.size();
+  ctx->n_diag = (int)dg.size();
+  ctx->terms = t;
+  ctx->n = n_spins;
+  ctx->N = 1LL << n_spins;
+  ctx->hbar = hbar;
+  ctx->have_h = true;
+  ctx->drop_graph();
+  return LREI_OK;
+}
+
+lrei_status lrei_set_rho(lrei_ctx *ctx, int r, const double *lambda, const void *V, int v_is_device) {
+  if (!ctx) return LREI_E_INVALID;
+  if (!ctx->have_h) return ctx->fail(LREI_E_STATE, "set a Hamiltonian before rho");
+  if (r < 1 || r > kMaxR) return ctx->fail(LREI_E_INVALID, "r must be in [1, 32]");
+  if ((long long)r > ctx->N) return ctx->fail(LREI_E_INVALID, "r exceeds the Hilbert dimension");
+  if (!lambda || !V) return ctx->fail(LREI_E_INVALID, "null lambda or V");
+  for (int i = 0; i < r; ++i) {
+    if (!std::isfinite(lambda[i]) || !(lambda[i] > 0))
+      return ctx->fail(LREI_E_INVALID, "lambda must be finite and strictly positive");
+    if (i > 0 && lambda[i] > lambda[i - 1]) return ctx->fail(LREI_E_INVALID, "lambda must be non-increasing");
+  }
+  HIPCHK(hipSetDevice(ctx->device));
+  // Validate in temporaries first so that a rejected V leaves the state intact.
+  const size_t el = ctx->elem();
+  const size_t vbytes = (size_t)ctx->N * r * el;
+  const int grid = nspace_grid(ctx->N, r);
+  DevBuf tv, tp, tpart, tmeas, tstage;
+  auto release_tmp = [&]() {
+    tv.release(); tp.release(); tpart.release(); tmeas.release(); tstage.release();
+  };
+  if (!tv.ensure(vbytes) || !tp.ensure(vbytes) ||
+      !tpart.ensure((size_t)grid * cheb_partial_splits(r) * 3 * r * r * sizeof(double2)) ||
+      !tmeas.ensure(3 * (size_t)r * r * sizeof(double2)) ||
+      (ctx->fp32 && !v_is_device && !tstage.ensure((size_t)ctx->N * r * sizeof(double2)))) {
+    release_tmp();
+    return ctx->fail(LREI_E_NOMEM, "device allocation failed");
+  }
+  {
+    const size_t n = (size_t)ctx->N * r;
+    hipError_t e1 = hipSuccess;
+    if (!ctx->fp32) {
+      e1 = hipMemcpyAsync(tv.p, V, n * sizeof(double2), v_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                          ctx->stream);
+    } else {
+      const void *src = V;
+      if (!v_is_device) {
+        e1 = hipMemcpyAsync(tstage.p, V, n * sizeof(double2), hipMemcpyHostToDevice, ctx->stream);
+        src = tstage.p;
+      }
+      if (e1 == hipSuccess) launch_convert(true, src, tv.p, (long long)n, ctx->stream);
+    }
+    if (e1 != hipSuccess) {
+      release_tmp();
+      return check_hip(ctx, e1, "upload V");
+    }
+  }
+  cheb_pass_into(ctx, r, grid, 0, nullptr, tv.p, tp.p, (double2 *)tpart.p, (double2 *)tmeas.p);
+  std::vector<double2> g(3 * r * r);
+  hipError_t e2 = hipGetLastError();
+  if (e2 == hipSuccess)
+    e2 = hipMemcpyAsync(g.data(), tmeas.p, g.size() * sizeof(double2), hipMemcpyDeviceToHost, ctx->stream);
+  if (e2 == hipSuccess) e2 = hipStreamSynchronize(ctx->stream);
+  if (e2 != hipSuccess) {
+    release_tmp();
+    return check_hip(ctx, e2, "validate V");
+  }
+  double dev = 0;
+  bool finite = true;
+  for (int a = 0; a < r; ++a)
+    for (int b = 0; b < r; ++b) {
+      double2 v = g[a * r + b];
+      if (!std::isfinite(v.x) || !std::isfinite(v.y)) finite = false;
+      if (a == b) v.x -= 1.0;
+      dev = std::max(dev, std::sqrt(v.x * v.x + v.y * v.y));
+    }
+  const double tol = ctx->fp32 ? 1e-5 : 1e-10;
+  if (!finite || !(dev <= tol)) {
+    release_tmp();
+    return ctx->fail(LREI_E_INVALID, "V must have finite orthonormal columns (max |V*V - I| = " +
+                                         std::to_string(dev) + ")");
+  }
+  lrei_status st = alloc_state(ctx, r, ctx->fp32);
+  if (st != LREI_OK) {
+    release_tmp();
+    ctx->have_rho = false;
+    return st;
+  }
+  ctx->r = r;
+  e2 = hipMemcpyAsync(ctx->blocks[0].p, tv.p, vbytes, hipMemcpyDeviceToDevice, ctx->stream);
+  if (e2 == hipSuccess) e2 = hipStreamSynchronize(ctx->stream);
+  release_tmp();
+  HIPCHK(e2);
+  ctx->lam.assign(lambda, lambda + r);
+  ctx->have_rho = true;
+  ctx->steps_done = 0;
+  ctx->drop_graph();
+  return LREI_OK;
+}
+
+lrei_status lrei_step(lrei_ctx *ctx, int model, int scheme, double dt, double kappa, int n_steps) {
+  if (!ctx) return LREI_E_INVALID;
+  if (!ctx->have_rho) return ctx->fail(LREI_E_STATE, "set rho before stepping");
+  if (model != LREI_QLL && model != LREI_QLLG) return ctx->fail(LREI_E_INVALID, "unknown model");
+  if (!(scheme >= LREI_RK1 && scheme <= LREI_RK4))
+    return ctx->fail(LREI_E_INVALID, "unsupported scheme (RK1..RK4)");
+  if (!(dt > 0) || !std::isfinite(dt)) return ctx->fail(LREI_E_INVALID, "dt must be positive and finite");
+  if (!(kappa >= 0) || !std::isfinite(kappa)) return ctx->fail(LREI_E_INVALID, "kappa must be >= 0 and finite");
+  if (n_steps < 0) return ctx->fail(LREI_E_INVALID, "n_steps must be >= 0");
+  if (n_steps == 0) return LREI_OK;
+  HIPCHK(hipSetDevice(ctx->device));
+  const auto t0 = std::chrono::steady_clock::now();
+  const size_t vbytes = (size_t)ctx->N * ctx->r * ctx->elem();
+  HIPCHK(hipMemcpyAsync(ctx->save.p, ctx->blocks[0].p, vbytes, hipMemcpyDeviceToDevice, ctx->stream));
+  double zeros[kStatsLen] = {0};
+  HIPCHK(hipMemcpyAsync(ctx->stats_buf.p, zeros, sizeof(zeros), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  const bool use_graph = ctx->opt.use_graph != 0;
+  if (use_graph) {
+    if (!(ctx->exec && ctx->g_model == model && ctx->g_scheme == scheme && ctx->g_dt == dt && ctx->g_kappa == kappa)) {
+      ctx->drop_graph();
+      // launch attributes are set on first use, outside capture
+      enqueue_rk_step(ctx, model, scheme, dt, kappa);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipStreamSynchronize(ctx->stream));
+      HIPCHK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+      enqueue_rk_step(ctx, model, scheme, dt, kappa);
+      HIPCHK(hipStreamEndCapture(ctx->stream, &ctx->graph));
+      HIPCHK(hipGraphInstantiate(&ctx->exec, ctx->graph, nullptr, nullptr, 0));
+      ctx->g_model = model;
+      ctx->g_scheme = scheme;
+      ctx->g_dt = dt;
+      ctx->g_kappa = kappa;
+      // the eager step above counts as the first step
+      for (int k = 1; k < n_steps; ++k) HIPCHK(hipGraphLaunch(ctx->exec, ctx->stream));
+    } else {
+      for (int k = 0; k < n_steps; ++k) HIPCHK(hipGraphLaunch(ctx->exec, ctx->stream));
+    }
+  } else {
+    for (int k = 0; k < n_steps; ++k) enqueue_rk_step(ctx, model, scheme, dt, kappa);
+  }
+  HIPCHK(hipGetLastError());
+  double h[kStatsLen];
+  lrei_status st = read_stats(ctx, h);
+  if (st != LREI_OK) return st;
+  const auto t1 = std::chrono::steady_clock::now();
+  // stats[0..8] describe the last step, stats[10..15] the whole call
+  const bool failed = h[13] != 0, bad = h[14] != 0;
+  if (failed || bad) {
+    HIPCHK(hipMemcpyAsync(ctx->blocks[0].p, ctx->save.p, vbytes, hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return ctx->fail(bad ? LREI_E_NUMERIC : LREI_E_NOTCONVERGED,
+                     bad ? "non-finite values in the step; state restored to the start of the call"
+                         : "Jacobi eigensolve hit the sweep limit; state restored to the start of the call");
+  }
+  ctx->steps_done += n_steps;
+  ctx->stats.steps_done = ctx->steps_done;
+  ctx->stats.eigensolves += (int64_t)h[11];
+  ctx->stats.jacobi_sweeps += (int64_t)h[10];
+  ctx->stats.max_sweeps_one_solve = std::max(ctx->stats.max_sweeps_one_solve, (int32_t)h[12]);
+  ctx->stats.dropped_directions = (int32_t)h[2];
+  ctx->stats.min_pivot_ratio = h[3];
+  ctx->stats.ortho_error = h[4];
+  ctx->stats.energy = h[5];
+  ctx->stats.last_step_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  return LREI_OK;
+}
+
+lrei_status lrei_get_rho(lrei_ctx *ctx, double *lambda, void *V, int v_is_device) {
+  if (!ctx) return LREI_E_INVALID;
+  if (!ctx->have_rho) return ctx->fail(LREI_E_STATE, "no state");
+  if (lambda) std::memcpy(lambda, ctx->lam.data(), ctx->r * sizeof(double));
+  if (!V) return LREI_OK;
+  HIPCHK(hipSetDevice(ctx->device));
+  const size_t n = (size_t)ctx->N * ctx->r;
+  const void *src = ctx->blocks[0].p;
+  if (ctx->fp32) {
+    if (!ctx->save.ensure(n * sizeof(double2))) return ctx->fail(LREI_E_NOMEM, "allocation failed");
+    launch_convert(false, ctx->blocks[0].p, ctx->save.p, (long long)n, ctx->stream);
+    HIPCHK(hipGetLastError());
+    src = ctx->save.p;
+  }
+  HIPCHK(hipMemcpyAsync(V, src, n * sizeof(double2), v_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                        ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return LREI_OK;
+}
+
+lrei_status lrei_observables(lrei_ctx *ctx, double *energy, double magnetization[3]) {
+  if (!ctx) return LREI_E_INVALID;
+  if (!ctx->have_rho) return ctx->fail(LREI_E_STATE, "no state");
+  HIPCHK(hipSetDevice(ctx->device));
+  const int r = ctx->r;
+  if (energy) {
+    // Gram pass with alpha = 1, shift = 0 would need a separate scaling; use the
+    // step's pass (alpha = 1/e) and undo the scale: P1 = H P0 / e.
+    cheb_pass(ctx, 0, nullptr, ctx->blocks[0].p, ctx->blocks[1].p, 0);
+    HIPCHK(hipGetLastError());
+    std::vector<double2> g(3 * r * r);
+    HIPCHK(hipMemcpyAsync(g.data(), ctx->ws.meas, g.size() * sizeof(double2), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    const double e = ctx->terms.gershgorin > 0 ? ctx->terms.gershgorin : 1.0;
+    double en = 0;
+    for (int a = 0; a < r; ++a) en += ctx->lam[a] * g[r * r + a * r + a].x * e;
+    *energy = en;
+  }
+  if (magnetization) {
+    HIPCHK(hipMemcpyAsync(ctx->lam_dev.p, ctx->lam.data(), r * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    const int grid = std::min<long long>(1024, std::max<long long>(1, ctx->N / 64));
+    double2 *part = (double2 *)ctx->partials.p;
+    launch_magnetization(ctx->fp32, ctx->blocks[0].p, (const double *)ctx->lam_dev.p, ctx->N, r, ctx->n, part, grid,
+                         ctx->stream);
+    HIPCHK(hipGetLastError());
+    std::vector<double2> h(2 * grid);
+    HIPCHK(hipMemcpyAsync(h.data(), part, h.size() * sizeof(double2), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    double mx = 0, my = 0, mz = 0;
+    for (int i = 0; i < grid; ++i) {
+      mx += h[2 * i].x;
+      my += h[2 * i].y;
+      mz += h[2 * i + 1].x;
+    }
+    const double f = 0.5 * ctx->hbar / ctx->n;
+    magnetization[0] = f * mx;
+    magnetization[1] = f * my;
+    magnetization[2] = f * mz;
+  }
+  return LREI_OK;
+}
+
+lrei_status lrei_get_stats(lrei_ctx *ctx, lrei_stats *s) {
+  if (!ctx || !s) return LREI_E_INVALID;
+  *s = ctx->stats;
+  return LREI_OK;
+}
+
+lrei_status lrei_apply_hamiltonian(lrei_ctx *ctx, int r, const void *X, void *Y, int is_device) {
+  if (!ctx) return LREI_E_INVALID;
+  if (!ctx->have_h) return ctx->fail(LREI_E_STATE, "no Hamiltonian");
+  if (r < 1 || r > kMaxR || !X || !Y) return ctx->fail(LREI_E_INVALID, "bad arguments");
+  HIPCHK(hipSetDevice(ctx->device));
+  const size_t bytes = (size_t)ctx->N * r * sizeof(double2);
+  DevBuf dx, dy;
+  const void *px = X;
+  void *py = Y;
+  if (!is_device) {
+    if (!dx.ensure(bytes) || !dy.ensure(bytes)) {
+      dx.release();
+      dy.release();
+      return ctx->fail(LREI_E_NOMEM, "allocation failed");
+    }
+    HIPCHK(hipMemcpyAsync(dx.p, X, bytes, hipMemcpyHostToDevice, ctx->stream));
+    px = dx.p;
+    py = dy.p;
+  }
+  ChebArgs a{};
+  a.Pcur = px;
+  a.Pnext = py;
+  a.off = (const DevOffTerm *)ctx->d_off.p;
+  a.diag = (const DevDiagTerm *)ctx->d_diag.p;
+  a.n_off = ctx->n_off;
+  a.n_diag = ctx->n_diag;
+  a.N = ctx->N;
+  a.r = r;
+  a.alpha = 1.0;
+  a.mode = 2;
+  a.grid = nspace_grid(ctx->N, r);
+  launch_cheb(false, a, ctx->stream);
+  lrei_status st = check_hip(ctx, hipGetLastError(), "apply_hamiltonian launch");
+  if (st == LREI_OK && !is_device)
+    st = check_hip(ctx, hipMemcpyAsync(Y, dy.p, bytes, hipMemcpyDeviceToHost, ctx->stream), "copy back");
+  if (st == LREI_OK) st = check_hip(ctx, hipStreamSynchronize(ctx->stream), "sync");
+  dx.release();
+  dy.release();
+  return st;
+}
+
+lrei_status lrei_get_state(lrei_ctx *ctx, void *buf, size_t *len) {
+  if (!ctx || !len) return LREI_E_INVALID;
+  if (!ctx->have_rho) return ctx->fail(LREI_E_STATE, "no state");
+  const size_t vbytes = (size_t)ctx->N * ctx->r * sizeof(double2);
+  const size_t need = 8 * 4 + ctx->r * sizeof(double) + vbytes;
+  if (!buf) {
+    *len = need;
+    return LREI_OK;
+  }
+  if (*len < need) return ctx->fail(LREI_E_INVALID, "buffer too small");
+  uint64_t hdr[4] = {kStateMagic, (uint64_t)ctx->n, (uint64_t)ctx->r, (uint64_t)ctx->steps_done};
+  std::memcpy(buf, hdr, sizeof(hdr));
+  std::memcpy((char *)buf + 32, ctx->lam.data(), ctx->r * sizeof(double));
+  *len = need;
+  return lrei_get_rho(ctx, nullptr, (char *)buf + 32 + ctx->r * sizeof(double), 0);
+}
+
+lrei_status lrei_set_state(lrei_ctx *ctx, const void *buf, size_t len) {
+  if (!ctx || !buf || len < 32) return LREI_E_INVALID;
+  uint64_t hdr[4];
+  std::memcpy(hdr, buf, sizeof(hdr));
+  if (hdr[0] != kStateMagic) return ctx->fail(LREI_E_INVALID, "not an LREI state buffer");
+  if (!ctx->have_h || (int)hdr[1] != ctx->n) return ctx->fail(LREI_E_STATE, "Hamiltonian with matching n required");
+  const int r = (int)hdr[2];
+  const size_t need = 32 + r * sizeof(double) + (size_t)ctx->N * r * sizeof(double2);
+  if (len < need) return ctx->fail(LREI_E_INVALID, "state buffer truncated");
+  const double *lam = (const double *)((const char *)buf + 32);
+  lrei_status st = lrei_set_rho(ctx, r, lam, (const char *)buf + 32 + r * sizeof(double), 0);
+  if (st != LREI_OK) return st;
+  ctx->steps_done = (int64_t)hdr[3];
+  return LREI_OK;
+}
+
+lrei_status lrei_synchronize(lrei_ctx *ctx) {
+  if (!ctx) return LREI_E_INVALID;
+  return check_hip(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
+}
+
+}  // extern "C"

@@ -1,0 +1,120 @@
+// Internal declarations shared by the LREI library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/lrei.h"
+
+namespace lrei {
+
+// ---------------------------------------------------------------------------
+// Hamiltonian term tables (built on the host from the Pauli-form couplings).
+//
+// Y[x] = d(x) X[x] + sum_t c_t[b_a(x) + 2 b_b(x)] X[x ^ mask_t]
+//   d(x) = sum_k w_k (1 - 2 (b_{i_k}(x) xor b_{j_k}(x)))   (j_k = 31 for a field)
+// b_s(x) is bit s of x.  A coefficient table is indexed by the bits of the
+// destination row x at sites a, b (b = a for a one-site term).
+// ---------------------------------------------------------------------------
+struct OffTerm {
+  uint32_t mask;
+  uint32_t sa, sb;
+  double re[4], im[4];
+};
+struct DiagTerm {
+  uint32_t si, sj;
+  double w;
+};
+
+struct TermTable {
+  std::vector<OffTerm> off;
+  std::vector<DiagTerm> diag;
+  double gershgorin = 0.0;  // bound on the spectral radius of H
+};
+
+// Builds the term table; returns false with `err` set on invalid input.
+bool build_terms(int n, int n_bonds, const int32_t *bond_ij, const double *bond_J,
+                 const double *site_h, TermTable &out, std::string &err);
+
+// Device-side packed term record (fp64 and fp32 coefficient copies).
+struct DevOffTerm {
+  uint32_t mask, sa, sb, pad;
+  double re[4], im[4];
+};
+struct DevDiagTerm {
+  uint32_t si, sj;
+  double w;
+};
+
+// Maximum supported sizes.
+constexpr int kMaxR = 32;
+constexpr int kMaxStages = 4;               // RK4
+constexpr int kMaxBlocks = 8;               // Krylov blocks in the projected basis
+constexpr int kMaxDim = kMaxBlocks * kMaxR; // projected dimension bound
+
+// Launch helpers implemented in nspace.hip / small.hip.
+struct ChebArgs {
+  const void *Pprev;   // P_{j-1} (mode 1) or nullptr
+  const void *Pcur;    // P_j
+  void *Pnext;         // P_{j+1}
+  const DevOffTerm *off;
+  const DevDiagTerm *diag;
+  int n_off, n_diag;
+  long long N;
+  int r;
+  double alpha, shift;  // P_{j+1} = mul * alpha * (H - shift) P_j - [mode 1] P_{j-1}
+  int mode;             // 0: first, 1: recurrence, 2: plain Y = H X (no Grams)
+  double2 *partials;    // [grid][3][r*r]
+  int grid;
+};
+
+void launch_cheb(bool fp32, const ChebArgs &a, hipStream_t s);
+void launch_combine(bool fp32, const void *const *blocks, int nblocks, const double2 *C, void *out,
+                    long long N, int r, int grid, hipStream_t s);
+void launch_reduce(const double2 *partials, int count, int len, double2 *out, hipStream_t s);
+void launch_convert(bool to_fp32, const void *src, void *dst, long long n_complex, hipStream_t s);
+void launch_magnetization(bool fp32, const void *V, const double *lam, long long N, int r, int n,
+                          double2 *partials, int grid, hipStream_t s);
+int nspace_grid(long long N, int r);
+
+// Parameters of the projected (small-space) step kernel.
+struct SmallRkParams {
+  int r, s, nblocks;      // nblocks = s + 1
+  int model;              // 0 qLL, 1 qLLG
+  int householder_mode;
+  int max_sweeps;
+  int warm;
+  int lds_elems;          // double2 capacity of the dynamic LDS matrix
+  double kappa, hbar, h, eig_tol;
+  double shift, halfwidth; // Chebyshev map H~ = (H - shift) / halfwidth
+  double a[kMaxStages][kMaxStages];
+  double b[kMaxStages];
+  double lam[kMaxR];
+};
+
+// Device layout of the small workspace (doubles).
+struct SmallWs {
+  double2 *meas;     // [kMaxStages][3][r*r]: measured Grams per pass
+  double2 *gamma;    // [D*D] Gram of the Krylov basis
+  double2 *R;        // [D*D] Cholesky factor
+  double2 *Rinv;     // [D*D]
+  double2 *Hh;       // [D*D] projected Hamiltonian
+  double2 *work;     // [8*D*D] scratch
+  double2 *stage;    // [kMaxStages][3][D*r] u, z, w per stage
+  double2 *Cfin;     // [D*r] combination coefficients for the new V
+  double *stats;     // [16]
+};
+
+constexpr int kSmallLdsBytes = 120 * 1024;
+// LDS capacity (double2 elements) to request for a projected dimension D.
+inline int small_lds_elems(int D, int r) {
+  const int full = D * D, cap = kSmallLdsBytes / 16;
+  return full <= cap ? full : r * r;
+}
+void launch_small_rk(const SmallRkParams &p, const SmallWs &ws, hipStream_t s);
+int cheb_partial_splits(int r);
+
+}  // namespace lrei

@@ -1,0 +1,537 @@
+// N-space kernels of the LREI step on gfx950: the matrix-free Hamiltonian
+// apply in a Chebyshev three-term recurrence with fused Gram products, the
+// basis combination that forms the new support, a deterministic reduction of
+// per-workgroup partial sums, and the magnetisation pass.
+//
+// Layout: every N x r block is row-major complex (re, im interleaved), so the
+// r columns of a basis row are one contiguous segment (256 B for r = 16 in
+// FP64, 128 B in FP32) and any row gather is a coalesced segment load.
+#include <hip/hip_runtime.h>
+
+#include "lrei_internal.h"
+
+namespace lrei {
+
+namespace {
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Cplx;
+template <> struct Cplx<double> { using type = double2; };
+template <> struct Cplx<float> { using type = float2; };
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+constexpr int kTile = 64;     // rows per tile
+constexpr int kMaxItems = 4;  // Gram work items per wave
+constexpr int kMaxLds = 150 * 1024;
+
+__host__ __device__ inline int pow2ceil(int v) {
+  int p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+__host__ __device__ inline int pad16(int v) { return (v + 15) & ~15; }
+
+// 16x16x4 MFMA wrappers.  Operand lanes: A[i][k] in lane i + 16k, B[k][j] in
+// lane j + 16k.  Result D[i][j] sits in lane j + 16g, register v, with
+// i = 4v + g for f64 and i = 4g + v for f32 (measured on gfx950).
+__device__ inline d4v mfma(double a, double b, d4v c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ inline f4v mfma(float a, float b, f4v c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+template <typename T> __device__ inline int mfma_row(int lane, int v);
+template <> __device__ inline int mfma_row<double>(int lane, int v) { return 4 * v + (lane >> 4); }
+template <> __device__ inline int mfma_row<float>(int lane, int v) { return 4 * (lane >> 4) + v; }
+
+template <typename T> struct Acc4;
+template <> struct Acc4<double> { using type = d4v; };
+template <> struct Acc4<float> { using type = f4v; };
+
+// Tile -> workgroup assignment.  When possible each of the 8 XCDs (workgroup
+// w runs on XCD w % 8) walks one contiguous eighth of the rows, so the
+// partner rows of low-bit flips stay in that XCD's L2.
+__device__ inline long long tile_of(long long k, long long num_tiles, int grid) {
+  const int w = blockIdx.x;
+  if ((grid & 7) == 0 && (num_tiles & 7) == 0 && num_tiles >= grid) {
+    const long long per = num_tiles >> 3;
+    const int g8 = grid >> 3;
+    const long long t = (long long)(w >> 3) + k * g8;
+    return t < per ? (long long)(w & 7) * per + t : -1;
+  }
+  const long long t = (long long)w + k * grid;
+  return t < num_tiles ? t : -1;
+}
+
+// Gram products over one LDS tile: G_g += X_g^H Y_g for up to 3 (X, Y) pairs.
+// Planes hold re / im parts [kTile][RP] of type T.  Items are (gram, a-tile,
+// b-tile, row split) distributed round-robin over the waves.
+template <typename T>
+struct GramPlan {
+  int ng, ta, rs, items;
+};
+
+template <typename T>
+__device__ inline void gram_tile(const T *const *xre, const T *const *xim, const T *const *yre,
+                                 const T *const *yim, const GramPlan<T> &gp, int RP,
+                                 double (&acc)[kMaxItems][8]) {
+  using A4 = typename Acc4<T>::type;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int rows_per_split = kTile / gp.rs;
+#pragma unroll
+  for (int q = 0; q < kMaxItems; ++q) {
+    const int it = wave + kWaves * q;
+    if (it >= gp.items) break;
+    int t = it;
+    const int split = t % gp.rs; t /= gp.rs;
+    const int tb = t % gp.ta; t /= gp.ta;
+    const int ta = t % gp.ta; t /= gp.ta;
+    const int g = t;
+    const T *Xr = xre[g], *Xi = xim[g], *Yr = yre[g], *Yi = yim[g];
+    const int a = ta * 16 + (lane & 15), b = tb * 16 + (lane & 15);
+    A4 cre = {0, 0, 0, 0}, cim = {0, 0, 0, 0};
+    const int row0 = split * rows_per_split;
+    for (int kk = 0; kk < rows_per_split; kk += 4) {
+      const int row = row0 + kk + (lane >> 4);
+      const T xr = Xr[row * RP + a], xi = Xi[row * RP + a];
+      const T yr = Yr[row * RP + b], yi = Yi[row * RP + b];
+      cre = mfma(xr, yr, cre);
+      cre = mfma(xi, yi, cre);
+      cim = mfma(xr, yi, cim);
+      cim = mfma(-xi, yr, cim);
+    }
+    // Per-tile products in T, accumulated across tiles in FP64.
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      acc[q][v] += (double)cre[v];
+      acc[q][4 + v] += (double)cim[v];
+    }
+  }
+}
+
+template <typename T>
+__device__ inline void gram_store(const GramPlan<T> &gp, const double (&acc)[kMaxItems][8], int r,
+                                  double2 *partials) {
+  // partials layout: [grid][rs][ng][r*r]
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const long long base = (long long)blockIdx.x * gp.rs * gp.ng * r * r;
+#pragma unroll
+  for (int q = 0; q < kMaxItems; ++q) {
+    const int it = wave + kWaves * q;
+    if (it >= gp.items) break;
+    int t = it;
+    const int split = t % gp.rs; t /= gp.rs;
+    const int tb = t % gp.ta; t /= gp.ta;
+    const int ta = t % gp.ta; t /= gp.ta;
+    const int g = t;
+    const int b = tb * 16 + (lane & 15);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int a = ta * 16 + mfma_row<T>(lane, v);
+      if (a < r && b < r)
+        partials[base + ((long long)split * gp.ng + g) * r * r + a * r + b] =
+            make_double2(acc[q][v], acc[q][4 + v]);
+    }
+  }
+}
+
+template <typename T>
+__device__ inline GramPlan<T> make_plan(int ng, int RP) {
+  GramPlan<T> gp;
+  gp.ng = ng;
+  gp.ta = RP / 16;
+  const int base = ng * gp.ta * gp.ta;
+  gp.rs = base >= kWaves ? 1 : kWaves;
+  gp.items = base * gp.rs;
+  return gp;
+}
+
+// ---------------------------------------------------------------------------
+// Chebyshev pass with the Hamiltonian applied matrix-free.
+//   mode 0: P1 = alpha (H - shift) P0                Grams P0*P0, P0*P1, P1*P1
+//   mode 1: P+ = 2 alpha (H - shift) P - P-           Grams P-*P+, P*P+, P+*P+
+//   mode 2: Y = H X                                    (no Grams)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_cheb(ChebArgs a) {
+  using C2 = typename Cplx<T>::type;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int r = a.r;
+  const int L = pow2ceil(r);          // lanes per row
+  const int RW = 64 / L;              // rows per wave per iteration
+  const int RP = pad16(r);
+  const bool grams = a.mode != 2;
+
+  // LDS: term table, then six planes [kTile][RP] (prev, cur, next) x (re, im).
+  DevOffTerm *s_off = reinterpret_cast<DevOffTerm *>(smem);
+  DevDiagTerm *s_diag = reinterpret_cast<DevDiagTerm *>(smem + a.n_off * sizeof(DevOffTerm));
+  size_t off_bytes = a.n_off * sizeof(DevOffTerm) + a.n_diag * sizeof(DevDiagTerm);
+  off_bytes = (off_bytes + 15) & ~size_t(15);
+  T *planes = reinterpret_cast<T *>(smem + off_bytes);
+  const int plane = kTile * RP;
+  T *pre = planes, *pim = planes + plane;           // prev
+  T *cre = planes + 2 * plane, *cim = planes + 3 * plane;  // cur
+  T *nre = planes + 4 * plane, *nim = planes + 5 * plane;  // next
+
+  for (int i = threadIdx.x; i < a.n_off; i += kThreads) s_off[i] = a.off[i];
+  for (int i = threadIdx.x; i < a.n_diag; i += kThreads) s_diag[i] = a.diag[i];
+  if (grams)
+    for (int i = threadIdx.x; i < 6 * plane; i += kThreads) planes[i] = T(0);
+  __syncthreads();
+
+  const C2 *Pc = reinterpret_cast<const C2 *>(a.Pcur);
+  const C2 *Pp = reinterpret_cast<const C2 *>(a.Pprev);
+  C2 *Pn = reinterpret_cast<C2 *>(a.Pnext);
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = lane % L;
+  const int rsub = lane / L;
+  const bool colok = col < r;
+  const T alpha = (T)a.alpha, shift = (T)a.shift;
+  const T mul = a.mode == 1 ? T(2) : T(1);
+
+  const int ng = a.mode == 2 ? 0 : 3;
+  GramPlan<T> gp = make_plan<T>(ng > 0 ? ng : 1, RP);
+  const T *xre[3], *xim[3], *yre[3], *yim[3];
+  if (a.mode == 0) {
+    xre[0] = cre; xim[0] = cim; yre[0] = cre; yim[0] = cim;
+  } else {
+    xre[0] = pre; xim[0] = pim; yre[0] = nre; yim[0] = nim;
+  }
+  xre[1] = cre; xim[1] = cim; yre[1] = nre; yim[1] = nim;
+  xre[2] = nre; xim[2] = nim; yre[2] = nre; yim[2] = nim;
+  double acc[kMaxItems][8];
+#pragma unroll
+  for (int q = 0; q < kMaxItems; ++q)
+#pragma unroll
+    for (int v = 0; v < 8; ++v) acc[q][v] = 0.0;
+
+  const long long N = a.N;
+  const long long num_tiles = (N + kTile - 1) / kTile;
+  for (long long k = 0;; ++k) {
+    const long long tile = tile_of(k, num_tiles, a.grid);
+    if (tile < 0) break;
+    const long long row0 = tile * kTile;
+    for (int it = 0; it * kWaves * RW < kTile; ++it) {
+      const int lr = it * kWaves * RW + wave * RW + rsub;  // local row
+      if (lr >= kTile) continue;
+      const long long x = row0 + lr;
+      if (x >= N) continue;
+      T ore = 0, oim = 0, xr = 0, xi = 0, vr = 0, vi = 0;
+      if (colok) {
+        const C2 own = Pc[x * r + col];
+        xr = own.x; xi = own.y;
+        double dsum = 0.0;
+        for (int t = 0; t < a.n_diag; ++t) {
+          const DevDiagTerm dt = s_diag[t];
+          const int par = (int)(((x >> dt.si) ^ (x >> dt.sj)) & 1);
+          dsum += par ? -dt.w : dt.w;
+        }
+        T accr = (T)dsum * xr, acci = (T)dsum * xi;
+        for (int t = 0; t < a.n_off; ++t) {
+          const DevOffTerm &ot = s_off[t];
+          const int idx = (int)((x >> ot.sa) & 1) | ((int)((x >> ot.sb) & 1) << 1);
+          const T cr = (T)ot.re[idx], ci = (T)ot.im[idx];
+          if (cr == T(0) && ci == T(0)) continue;
+          const C2 y = Pc[(x ^ (long long)ot.mask) * r + col];
+          accr += cr * y.x - ci * y.y;
+          acci += cr * y.y + ci * y.x;
+        }
+        if (a.mode == 2) {
+          ore = accr; oim = acci;
+        } else {
+          ore = mul * alpha * (accr - shift * xr);
+          oim = mul * alpha * (acci - shift * xi);
+          if (a.mode == 1) {
+            const C2 pv = Pp[x * r + col];
+            vr = pv.x; vi = pv.y;
+            ore -= vr; oim -= vi;
+          }
+        }
+        C2 o;
+        o.x = ore; o.y = oim;
+        Pn[x * r + col] = o;
+      }
+      if (grams && colok) {
+        cre[lr * RP + col] = xr; cim[lr * RP + col] = xi;
+        nre[lr * RP + col] = ore; nim[lr * RP + col] = oim;
+        if (a.mode == 1) { pre[lr * RP + col] = vr; pim[lr * RP + col] = vi; }
+      }
+    }
+    if (grams) {
+      __syncthreads();
+      // rows beyond N keep the zeros written at start only for the first tile;
+      // N is a power of two >= 2 so a partial tile is always the only tile.
+      gram_tile<T>(xre, xim, yre, yim, gp, RP, acc);
+      __syncthreads();
+    }
+  }
+  if (grams) gram_store<T>(gp, acc, r, a.partials);
+}
+
+// ---------------------------------------------------------------------------
+// out (N x r) = [B_0 ... B_{nb-1}] (N x nb r) * C (nb r x r), C complex FP64.
+// In place over B_0 is allowed: a tile's rows are read before they are written.
+// ---------------------------------------------------------------------------
+struct CombineArgs {
+  const void *blocks[kMaxBlocks];
+  int nb;
+  const double2 *C;
+  void *out;
+  long long N;
+  int r, grid;
+};
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_combine(CombineArgs a) {
+  using C2 = typename Cplx<T>::type;
+  using A4 = typename Acc4<T>::type;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int r = a.r, RP = pad16(r), nb = a.nb;
+  const int K = nb * RP;  // padded inner dimension
+  T *cre = reinterpret_cast<T *>(smem);            // [K][RP]
+  T *cim = cre + K * RP;
+  T *tre = cim + K * RP;                           // [kTile][RP] one block chunk
+  T *tim = tre + kTile * RP;
+  for (int i = threadIdx.x; i < K * RP; i += kThreads) {
+    const int kk = i / RP, j = i % RP;
+    const int blk = kk / RP, ak = kk % RP;
+    double2 c = make_double2(0.0, 0.0);
+    if (ak < r && j < r) c = a.C[(blk * r + ak) * r + j];
+    cre[i] = (T)c.x;
+    cim[i] = (T)c.y;
+  }
+  for (int i = threadIdx.x; i < 2 * kTile * RP; i += kThreads) tre[i] = T(0);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int TA = RP / 16;
+  C2 *out = reinterpret_cast<C2 *>(a.out);
+  const long long N = a.N;
+  const long long num_tiles = (N + kTile - 1) / kTile;
+  for (long long k = 0;; ++k) {
+    const long long tile = tile_of(k, num_tiles, a.grid);
+    if (tile < 0) break;
+    const long long row0 = tile * kTile;
+    A4 ore[2], oim[2];  // TA <= 2 (r <= 32)
+    for (int t = 0; t < 2; ++t) { ore[t] = A4{0, 0, 0, 0}; oim[t] = A4{0, 0, 0, 0}; }
+    for (int blk = 0; blk < nb; ++blk) {
+      const C2 *B = reinterpret_cast<const C2 *>(a.blocks[blk]);
+      __syncthreads();
+      for (int i = threadIdx.x; i < kTile * r; i += kThreads) {
+        const int lr = i / r, c = i % r;
+        const long long x = row0 + lr;
+        C2 v;
+        v.x = 0; v.y = 0;
+        if (x < N) v = B[x * r + c];
+        tre[lr * RP + c] = v.x;
+        tim[lr * RP + c] = v.y;
+      }
+      __syncthreads();
+      // wave w: output rows w*16 .. w*16+15, all column tiles
+      for (int kk = 0; kk < RP; kk += 4) {
+        const int arow = wave * 16 + (lane & 15);
+        const int acol = kk + (lane >> 4);
+        const T ar = tre[arow * RP + acol], ai = tim[arow * RP + acol];
+        for (int tb = 0; tb < TA; ++tb) {
+          const int crow = blk * RP + kk + (lane >> 4);
+          const int ccol = tb * 16 + (lane & 15);
+          const T br = cre[crow * RP + ccol], bi = cim[crow * RP + ccol];
+          ore[tb] = mfma(ar, br, ore[tb]);
+          ore[tb] = mfma(-ai, bi, ore[tb]);
+          oim[tb] = mfma(ar, bi, oim[tb]);
+          oim[tb] = mfma(ai, br, oim[tb]);
+        }
+      }
+    }
+    __syncthreads();  // all reads of this tile's rows (incl. in-place block) done
+    for (int tb = 0; tb < TA; ++tb) {
+      const int j = tb * 16 + (lane & 15);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = wave * 16 + mfma_row<T>(lane, v);
+        const long long x = row0 + i;
+        if (j < r && x < N) {
+          C2 o;
+          o.x = ore[tb][v];
+          o.y = oim[tb][v];
+          out[x * r + j] = o;
+        }
+      }
+    }
+  }
+}
+
+// Deterministic reduction: out[e] = sum_{c < count} in[c * len + e] in a fixed order.
+__global__ __launch_bounds__(256) void k_reduce(const double2 *in, int count, int len, double2 *out) {
+  __shared__ double2 part[4][64];
+  const int e = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int q = threadIdx.x >> 6;
+  double sr = 0.0, si = 0.0;
+  if (e < len)
+    for (int c = q; c < count; c += 4) {
+      const double2 v = in[(long long)c * len + e];
+      sr += v.x;
+      si += v.y;
+    }
+  part[q][threadIdx.x & 63] = make_double2(sr, si);
+  __syncthreads();
+  if (q == 0 && e < len) {
+    double2 s = part[0][threadIdx.x];
+    for (int k = 1; k < 4; ++k) {
+      s.x += part[k][threadIdx.x].x;
+      s.y += part[k][threadIdx.x].y;
+    }
+    out[e] = s;
+  }
+}
+
+__global__ void k_convert_d2f(const double2 *src, float2 *dst, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    dst[i] = make_float2((float)src[i].x, (float)src[i].y);
+}
+__global__ void k_convert_f2d(const float2 *src, double2 *dst, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    dst[i] = make_double2((double)src[i].x, (double)src[i].y);
+}
+
+// Magnetisation partials: per workgroup (sum_x,a lam_a conj(V[x,a]) s^v_i V)
+// summed over sites i, for v = x, y, z; written as [grid][2] double2 =
+// (mx, my), (mz, 0).  The 1/n and hbar/2 factors are applied on the host.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_magnet(const void *Vp, const double *lam, long long N,
+                                                     int r, int n, double2 *partials) {
+  using C2 = typename Cplx<T>::type;
+  const C2 *V = reinterpret_cast<const C2 *>(Vp);
+  const int L = pow2ceil(r), RW = 64 / L;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = lane % L, rsub = lane / L;
+  double mx = 0, my = 0, mz = 0;
+  if (col < r) {
+    const double lm = lam[col];
+    const long long rows_per_block = (long long)kWaves * RW;
+    for (long long x0 = (long long)blockIdx.x * rows_per_block; x0 < N;
+         x0 += (long long)gridDim.x * rows_per_block) {
+      const long long x = x0 + wave * RW + rsub;
+      if (x >= N) continue;
+      const C2 v = V[x * r + col];
+      const double vr = v.x, vi = v.y;
+      const double w = lm * (vr * vr + vi * vi);
+      int up = 0;
+      for (int i = 0; i < n; ++i) {
+        const int b = (int)((x >> i) & 1);
+        up += b ? -1 : 1;
+        const C2 u = V[(x ^ (1LL << i)) * r + col];
+        // conj(v) * u
+        const double pr = vr * u.x + vi * u.y, pi = vr * u.y - vi * u.x;
+        mx += lm * pr;
+        // <b|s^y|1-b> = -i (b = 0), +i (b = 1): contributes Re(conj(v) * (+-i) u)
+        my += lm * (b ? -pi : pi);
+      }
+      mz += w * up;
+    }
+  }
+  __shared__ double red[3][kThreads];
+  red[0][threadIdx.x] = mx;
+  red[1][threadIdx.x] = my;
+  red[2][threadIdx.x] = mz;
+  __syncthreads();
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s)
+      for (int c = 0; c < 3; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = make_double2(red[0][0], red[1][0]);
+    partials[2 * blockIdx.x + 1] = make_double2(red[2][0], 0.0);
+  }
+}
+
+size_t cheb_lds(bool fp32, int n_off, int n_diag, int r) {
+  size_t b = n_off * sizeof(DevOffTerm) + n_diag * sizeof(DevDiagTerm);
+  b = (b + 15) & ~size_t(15);
+  return b + 6 * (size_t)kTile * pad16(r) * (fp32 ? 4 : 8);
+}
+
+}  // namespace
+
+int cheb_partial_splits(int r) {
+  const int ta = pad16(r) / 16;
+  return 3 * ta * ta >= kWaves ? 1 : kWaves;
+}
+
+int nspace_grid(long long N, int r) {
+  (void)r;
+  const long long tiles = (N + kTile - 1) / kTile;
+  long long g = tiles < 1024 ? tiles : 1024;
+  if (g >= 8) g &= ~7LL;
+  return (int)(g < 1 ? 1 : g);
+}
+
+void launch_cheb(bool fp32, const ChebArgs &a, hipStream_t s) {
+  const size_t lds = cheb_lds(fp32, a.n_off, a.n_diag, a.r);
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void *)k_cheb<float>, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+    (void)hipFuncSetAttribute((const void *)k_cheb<double>, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+    attr = true;
+  }
+  if (fp32)
+    hipLaunchKernelGGL(k_cheb<float>, dim3(a.grid), dim3(kThreads), lds, s, a);
+  else
+    hipLaunchKernelGGL(k_cheb<double>, dim3(a.grid), dim3(kThreads), lds, s, a);
+}
+
+void launch_combine(bool fp32, const void *const *blocks, int nblocks, const double2 *C, void *out,
+                    long long N, int r, int grid, hipStream_t s) {
+  CombineArgs a;
+  for (int i = 0; i < kMaxBlocks; ++i) a.blocks[i] = i < nblocks ? blocks[i] : nullptr;
+  a.nb = nblocks;
+  a.C = C;
+  a.out = out;
+  a.N = N;
+  a.r = r;
+  a.grid = grid;
+  const int RP = pad16(r);
+  const size_t lds = (size_t)(2 * nblocks * RP * RP + 2 * kTile * RP) * (fp32 ? 4 : 8);
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void *)k_combine<float>, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+    (void)hipFuncSetAttribute((const void *)k_combine<double>, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+    attr = true;
+  }
+  if (fp32)
+    hipLaunchKernelGGL(k_combine<float>, dim3(grid), dim3(kThreads), lds, s, a);
+  else
+    hipLaunchKernelGGL(k_combine<double>, dim3(grid), dim3(kThreads), lds, s, a);
+}
+
+void launch_reduce(const double2 *partials, int count, int len, double2 *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce, dim3((len + 63) / 64), dim3(256), 0, s, partials, count, len, out);
+}
+
+void launch_convert(bool to_fp32, const void *src, void *dst, long long n, hipStream_t s) {
+  long long blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  if (to_fp32)
+    hipLaunchKernelGGL(k_convert_d2f, dim3((unsigned)blocks), dim3(256), 0, s,
+                       (const double2 *)src, (float2 *)dst, n);
+  else
+    hipLaunchKernelGGL(k_convert_f2d, dim3((unsigned)blocks), dim3(256), 0, s,
+                       (const float2 *)src, (double2 *)dst, n);
+}
+
+void launch_magnetization(bool fp32, const void *V, const double *lam, long long N, int r, int n,
+                          double2 *partials, int grid, hipStream_t s) {
+  if (fp32)
+    hipLaunchKernelGGL(k_magnet<float>, dim3(grid), dim3(kThreads), 0, s, V, lam, N, r, n, partials);
+  else
+    hipLaunchKernelGGL(k_magnet<double>, dim3(grid), dim3(kThreads), 0, s, V, lam, N, r, n, partials);
+}
+
+}  // namespace lrei

@@ -1,0 +1,207 @@
+"""Thin ctypes binding of liblrei.so (the C ABI declared in include/lrei.h).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  If the library is missing the import fails loudly; there is no
+CPU fallback.  Arrays may be numpy arrays (host) or torch tensors on a ROCm
+device (their data_ptr() is passed with the *_is_device flag).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblrei.so")
+
+LREI_OK = 0
+STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_NOMEM", 3: "E_NOTCONVERGED", 4: "E_DEVICE",
+                5: "E_STATE", 6: "E_NUMERIC"}
+MODELS = {"qLL": 0, "qLLG": 1}
+SCHEMES = {"RK1": 1, "RK2": 2, "RK3": 3, "RK4": 4, "AB2": 12, "AB3": 13, "AB4": 14}
+PRECISIONS = {"fp64": 0, "mixed": 1}
+WARM = {"plain": 0, "analytic": 1, "learned": 2}
+
+
+class lrei_options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("eig_tol", ctypes.c_double),
+                ("eig_max_sweeps", ctypes.c_int), ("warm", ctypes.c_int),
+                ("ab_bootstrap", ctypes.c_int), ("householder_mode", ctypes.c_int),
+                ("use_graph", ctypes.c_int), ("deterministic", ctypes.c_int),
+                ("autotune_cache", ctypes.c_char_p)]
+
+
+class lrei_stats(ctypes.Structure):
+    _fields_ = [("steps_done", ctypes.c_int64), ("eigensolves", ctypes.c_int64),
+                ("jacobi_sweeps", ctypes.c_int64), ("max_sweeps_one_solve", ctypes.c_int32),
+                ("dropped_directions", ctypes.c_int32), ("min_pivot_ratio", ctypes.c_double),
+                ("ortho_error", ctypes.c_double), ("energy", ctypes.c_double),
+                ("last_step_ms", ctypes.c_double), ("warm_accepted", ctypes.c_int64),
+                ("warm_rejected", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class LreiError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+# name -> (restype, argtypes)
+_P = ctypes.c_void_p
+_SIGS = {
+    "lrei_default_options": (None, [ctypes.POINTER(lrei_options)]),
+    "lrei_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, _P, ctypes.POINTER(lrei_options)]),
+    "lrei_destroy": (None, [_P]),
+    "lrei_last_error": (ctypes.c_char_p, [_P]),
+    "lrei_set_hamiltonian": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, _P, _P, ctypes.c_double]),
+    "lrei_set_rho": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.c_int]),
+    "lrei_step": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int]),
+    "lrei_get_rho": (ctypes.c_int, [_P, _P, _P, ctypes.c_int]),
+    "lrei_observables": (ctypes.c_int, [_P, _P, _P]),
+    "lrei_get_stats": (ctypes.c_int, [_P, ctypes.POINTER(lrei_stats)]),
+    "lrei_apply_hamiltonian": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.c_int]),
+    "lrei_get_state": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_size_t)]),
+    "lrei_set_state": (ctypes.c_int, [_P, _P, ctypes.c_size_t]),
+    "lrei_synchronize": (ctypes.c_int, [_P]),
+}
+
+
+def load(path=LIB_PATH):
+    """Loads liblrei.so and declares every entry point; raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} not found: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def _ptr(a):
+    """(pointer, is_device) for a numpy array or a torch tensor."""
+    if a is None:
+        return None, 0
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data, 0
+    if hasattr(a, "data_ptr"):
+        return a.data_ptr(), int(a.is_cuda)
+    raise TypeError(type(a))
+
+
+class Context:
+    """One LREI context (one trajectory) on a HIP device."""
+
+    def __init__(self, device=0, stream=None, precision="fp64", eig_tol=1e-15, eig_max_sweeps=40,
+                 warm="plain", householder_mode=1, use_graph=True):
+        self.lib = load()
+        opt = lrei_options()
+        self.lib.lrei_default_options(ctypes.byref(opt))
+        opt.precision = PRECISIONS[precision]
+        opt.eig_tol = eig_tol
+        opt.eig_max_sweeps = eig_max_sweeps
+        opt.warm = WARM[warm]
+        opt.householder_mode = householder_mode
+        opt.use_graph = int(bool(use_graph))
+        h = _P()
+        st = self.lib.lrei_create(ctypes.byref(h), int(device), stream, ctypes.byref(opt))
+        if st != LREI_OK:
+            raise LreiError(st, "lrei_create failed")
+        self.h = h
+        self.precision = precision
+        self.n = None
+        self.r = None
+
+    def _check(self, st):
+        if st != LREI_OK:
+            raise LreiError(st, self.lib.lrei_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.lrei_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_hamiltonian(self, n, bonds, J, h=None, hbar=1.0):
+        bonds = np.ascontiguousarray(np.asarray(bonds, dtype=np.int32).reshape(-1, 2))
+        J = np.ascontiguousarray(np.asarray(J, dtype=np.float64).reshape(-1, 3, 3))
+        hh = None if h is None else np.ascontiguousarray(np.asarray(h, dtype=np.float64).reshape(n, 3))
+        self._check(self.lib.lrei_set_hamiltonian(self.h, int(n), bonds.shape[0], bonds.ctypes.data,
+                                                  J.ctypes.data, None if hh is None else hh.ctypes.data,
+                                                  float(hbar)))
+        self.n = int(n)
+        self._keep = (bonds, J, hh)
+
+    def set_rho(self, lam, V):
+        lam = np.ascontiguousarray(np.asarray(lam, dtype=np.float64))
+        if isinstance(V, np.ndarray):
+            V = np.ascontiguousarray(V, dtype=np.complex128)
+        p, dev = _ptr(V)
+        self._check(self.lib.lrei_set_rho(self.h, lam.size, lam.ctypes.data, p, dev))
+        self.r = lam.size
+
+    def step(self, model, scheme, dt, kappa, n_steps=1):
+        self._check(self.lib.lrei_step(self.h, MODELS[model], SCHEMES[scheme], float(dt), float(kappa),
+                                       int(n_steps)))
+
+    def get_rho(self, out=None):
+        lam = np.zeros(self.r, dtype=np.float64)
+        if out is None:
+            out = np.zeros((2 ** self.n, self.r), dtype=np.complex128)
+        p, dev = _ptr(out)
+        self._check(self.lib.lrei_get_rho(self.h, lam.ctypes.data, p, dev))
+        return lam, out
+
+    def observables(self):
+        e = ctypes.c_double()
+        m = (ctypes.c_double * 3)()
+        self._check(self.lib.lrei_observables(self.h, ctypes.byref(e), m))
+        return e.value, np.array(list(m))
+
+    def stats(self):
+        s = lrei_stats()
+        self._check(self.lib.lrei_get_stats(self.h, ctypes.byref(s)))
+        return s.as_dict()
+
+    def apply_hamiltonian(self, X, out=None):
+        if isinstance(X, np.ndarray):
+            X = np.ascontiguousarray(X, dtype=np.complex128)
+            if out is None:
+                out = np.zeros_like(X)
+        px, dev = _ptr(X)
+        py, _ = _ptr(out)
+        self._check(self.lib.lrei_apply_hamiltonian(self.h, X.shape[1], px, py, dev))
+        return out
+
+    def get_state(self):
+        n = ctypes.c_size_t()
+        self._check(self.lib.lrei_get_state(self.h, None, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        self._check(self.lib.lrei_get_state(self.h, buf, ctypes.byref(n)))
+        return buf.raw[: n.value]
+
+    def set_state(self, blob):
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        self._check(self.lib.lrei_set_state(self.h, buf, len(blob)))
+        hdr = np.frombuffer(blob[:32], dtype=np.uint64)
+        self.r = int(hdr[2])
+
+    def synchronize(self):
+        self._check(self.lib.lrei_synchronize(self.h))

@@ -1,0 +1,225 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Tolerances: FP64 path 1e-10 relative Frobenius on rho (per-step checks use
+1e-11); mixed path 1e-5.  Every test builds its inputs from the seeded
+workload generators and computes the expected values with ``oracle`` only.
+"""
+import numpy as np
+import pytest
+
+from oracle.hamiltonian import Hamiltonian, apply_H, apply_H_rows
+from oracle.schemes import lrei_rk_step, run as oracle_run
+from oracle.metrics import rel_fro_error
+from oracle.observables import energy as oracle_energy, magnetization as oracle_mag
+from workloads import (make_config, chain_bonds, square_lattice_bonds, haar_factor, dirichlet_spectrum,
+                       heisenberg_tensors, uniform_field, pure_factor, af1_index, xxz_tensors)
+
+pytestmark = pytest.mark.gpu
+
+
+def _ctx(precision="fp64", **kw):
+    from paper_2508_21200_amd import Context
+    return Context(device=0, precision=precision, **kw)
+
+
+def _random_model(n, rng, periodic=True):
+    bonds = chain_bonds(n, periodic=periodic and n > 2)
+    J = rng.normal(size=(bonds.shape[0], 3, 3)) * 0.5
+    h = rng.normal(size=(n, 3)) * 0.5
+    return bonds, J, h
+
+
+@pytest.mark.parametrize("n,r", [(6, 1), (7, 3), (8, 4), (9, 16), (10, 20), (8, 32), (12, 8)])
+def test_apply_hamiltonian(n, r):
+    rng = np.random.default_rng(100 + n + r)
+    bonds, J, h = _random_model(n, rng)
+    X = haar_factor(2 ** n, r, rng)
+    ctx = _ctx()
+    ctx.set_hamiltonian(n, bonds, J, h)
+    Y = ctx.apply_hamiltonian(X)
+    Yo = apply_H(n, bonds, J, h, X)
+    assert np.abs(Y - Yo).max() <= 1e-13 * max(1.0, np.abs(Yo).max())
+
+
+@pytest.mark.parametrize("scheme", ["RK1", "RK2", "RK3", "RK4"])
+@pytest.mark.parametrize("model", ["qLL", "qLLG"])
+@pytest.mark.parametrize("n,r", [(6, 3), (9, 4)])
+def test_rk_steps_fp64(scheme, model, n, r):
+    rng = np.random.default_rng(7 * n + r)
+    bonds, J, h = _random_model(n, rng)
+    V = haar_factor(2 ** n, r, rng)
+    lam = dirichlet_spectrum(r, rng)
+    ctx = _ctx()
+    ctx.set_hamiltonian(n, bonds, J, h)
+    ctx.set_rho(lam, V)
+    ctx.step(model, scheme, 0.02, 0.5, 3)
+    _, Vg = ctx.get_rho()
+    H = Hamiltonian(n, bonds, J, h)
+    Vo = V
+    for _ in range(3):
+        Vo = lrei_rk_step(H, Vo, lam, model, 0.5, 0.02, scheme)
+    err = rel_fro_error(Vg, lam, Vo, lam)
+    print(f"{model} {scheme} n={n} r={r}: rel_fro_error={err:.3e}")
+    assert err < 1e-11
+
+
+@pytest.mark.parametrize("hmode", [0, 1])
+def test_householder_and_projector_agree(hmode):
+    cfg = make_config(2, n=10, r=6)
+    ctx = _ctx(householder_mode=hmode)
+    ctx.set_hamiltonian(cfg["n"], cfg["bonds"], cfg["J"], cfg["h"])
+    ctx.set_rho(cfg["lam"], cfg["V"])
+    ctx.step("qLLG", "RK4", 0.01, 0.05, 5)
+    _, Vg = ctx.get_rho()
+    H = Hamiltonian(cfg["n"], cfg["bonds"], cfg["J"], cfg["h"])
+    Vo = oracle_run(H, cfg["V"], cfg["lam"], "qLLG", 0.05, 0.01, 5, "RK4")
+    assert rel_fro_error(Vg, cfg["lam"], Vo, cfg["lam"]) < 1e-11
+
+
+def test_cfg1_full_run_fp64():
+    """Heisenberg chain n=8, r=4, q-LL, RK4 dt=0.01 x 100 (the small parity workload)."""
+    cfg = make_config(1)
+    ctx = _ctx()
+    ctx.set_hamiltonian(cfg["n"], cfg["bonds"], cfg["J"], cfg["h"])
+    ctx.set_rho(cfg["lam"], cfg["V"])
+    ctx.step(cfg["model"], "RK4", cfg["dt"], cfg["kappa"], cfg["steps"])
+    _, Vg = ctx.get_rho()
+    H = Hamiltonian(cfg["n"], cfg["bonds"], cfg["J"], cfg["h"])
+    Vo = oracle_run(H, cfg["V"], cfg["lam"], cfg["model"], cfg["kappa"], cfg["dt"], cfg["steps"], "RK4")
+    err = rel_fro_error(Vg, cfg["lam"], Vo, cfg["lam"])
+    print(f"cfg1 100 steps rel_fro_error={err:.3e} stats={ctx.stats()}")
+    assert err < 1e-10
+
+
+def test_mixed_precision_within_1e5():
+    cfg = make_config(2, n=12, r=8)
+    ctx = _ctx("mixed")
+    ctx.set_hamiltonian(cfg["n"], cfg["bonds"], cfg["J"], cfg["h"])
+    ctx.set_rho(cfg["lam"], cfg["V"])
+    ctx.step("qLLG", "RK4", 0.005, 0.05, 20)
+    _, Vg = ctx.get_rho()
+    H = Hamiltonian(cfg["n"], cfg["bonds"], cfg["J"], cfg["h"])
+    Vo = oracle_run(H, cfg["V"], cfg["lam"], "qLLG", 0.05, 0.005, 20, "RK4")
+    err = rel_fro_error(Vg, cfg["lam"], Vo, cfg["lam"])
+    print(f"mixed n=12 r=8 20 steps rel_fro_error={err:.3e}")
+    assert err < 1e-5
+
+
+def test_observables():
+    rng = np.random.default_rng(3)
+    n, r = 9, 5
+    bonds, J, h = _random_model(n, rng)
+    V = haar_factor(2 ** n, r, rng)
+    lam = dirichlet_spectrum(r, rng)
+    ctx = _ctx()
+    ctx.set_hamiltonian(n, bonds, J, h, hbar=0.8)
+    ctx.set_rho(lam, V)
+    e, m = ctx.observables()
+    H = Hamiltonian(n, bonds, J, h)
+    assert abs(e - oracle_energy(H, V, lam)) < 1e-12
+    np.testing.assert_allclose(m, oracle_mag(n, V, lam, hbar=0.8), atol=1e-13)
+
+
+def test_fixed_point_and_tiny_systems():
+    """Degenerate Krylov spaces: a commuting pure state, and N smaller than the basis."""
+    n = 6
+    bonds = chain_bonds(n)
+    J = heisenberg_tensors(bonds.shape[0], 1.0)
+    h = uniform_field(n, (0, 0, 0.8))
+    V = pure_factor(n, index=0)
+    ctx = _ctx()
+    ctx.set_hamiltonian(n, bonds, J, h)
+    ctx.set_rho([1.0], V)
+    ctx.step("qLLG", "RK4", 0.05, 0.5, 10)
+    _, Vg = ctx.get_rho()
+    assert rel_fro_error(Vg, [1.0], V, [1.0]) < 1e-13
+    # n = 2 and n = 3: 5 r exceeds N, the Krylov space saturates
+    for n, r in ((2, 1), (2, 2), (3, 2), (3, 4)):
+        rng = np.random.default_rng(n * 10 + r)
+        bonds, Jr, hr = _random_model(n, rng)
+        V = haar_factor(2 ** n, r, rng)
+        lam = dirichlet_spectrum(r, rng)
+        ctx = _ctx()
+        ctx.set_hamiltonian(n, bonds, Jr, hr)
+        ctx.set_rho(lam, V)
+        ctx.step("qLL", "RK4", 0.02, 0.3, 4)
+        _, Vg = ctx.get_rho()
+        H = Hamiltonian(n, bonds, Jr, hr)
+        Vo = oracle_run(H, V, lam, "qLL", 0.3, 0.02, 4, "RK4")
+        err = rel_fro_error(Vg, lam, Vo, lam)
+        print(f"tiny n={n} r={r}: {err:.3e} stats={ctx.stats()}")
+        assert err < 1e-11
+
+
+def test_pure_af_state_convergence_to_exact():
+    """Pure |AF1> on a chain: GPU LREI-RK4 agrees with the oracle step for step."""
+    n = 8
+    bonds = chain_bonds(n)
+    H = Hamiltonian(n, bonds, heisenberg_tensors(bonds.shape[0], 1.0), uniform_field(n, (0.4, 0, 0.3)))
+    V = pure_factor(n, index=af1_index(n))
+    ctx = _ctx()
+    ctx.set_hamiltonian(n, H.bonds, H.J, H.h)
+    ctx.set_rho([1.0], V)
+    ctx.step("qLLG", "RK4", 0.01, 0.5, 20)
+    _, Vg = ctx.get_rho()
+    Vo = oracle_run(H, V, np.array([1.0]), "qLLG", 0.5, 0.01, 20, "RK4")
+    assert rel_fro_error(Vg, [1.0], Vo, [1.0]) < 1e-11
+
+
+def test_graph_replay_equals_eager():
+    cfg = make_config(2, n=10, r=8)
+    out = []
+    for use_graph in (True, False):
+        ctx = _ctx(use_graph=use_graph)
+        ctx.set_hamiltonian(cfg["n"], cfg["bonds"], cfg["J"], cfg["h"])
+        ctx.set_rho(cfg["lam"], cfg["V"])
+        for _ in range(3):
+            ctx.step("qLLG", "RK4", 0.01, 0.05, 2)
+        out.append(ctx.get_rho()[1])
+    assert np.array_equal(out[0], out[1])  # deterministic, bitwise
+
+
+def test_checkpoint_resume_bitwise():
+    cfg = make_config(2, n=9, r=4)
+    a = _ctx()
+    a.set_hamiltonian(cfg["n"], cfg["bonds"], cfg["J"], cfg["h"])
+    a.set_rho(cfg["lam"], cfg["V"])
+    a.step("qLL", "RK4", 0.01, 0.2, 6)
+    blob = a.get_state()
+    a.step("qLL", "RK4", 0.01, 0.2, 4)
+    b = _ctx()
+    b.set_hamiltonian(cfg["n"], cfg["bonds"], cfg["J"], cfg["h"])
+    b.set_state(blob)
+    b.step("qLL", "RK4", 0.01, 0.2, 4)
+    assert np.array_equal(a.get_rho()[1], b.get_rho()[1])
+
+
+def test_invalid_inputs_leave_state():
+    from paper_2508_21200_amd import LreiError
+    cfg = make_config(2, n=8, r=4)
+    ctx = _ctx()
+    ctx.set_hamiltonian(cfg["n"], cfg["bonds"], cfg["J"], cfg["h"])
+    ctx.set_rho(cfg["lam"], cfg["V"])
+    before = ctx.get_rho()[1].copy()
+    bad = cfg["V"].copy()
+    bad[:, 0] *= 1.1
+    for lam, V in ((cfg["lam"], bad), (cfg["lam"][::-1].copy(), cfg["V"]), (-cfg["lam"], cfg["V"])):
+        with pytest.raises(LreiError):
+            ctx.set_rho(lam, V)
+    assert np.array_equal(ctx.get_rho()[1], before)
+    with pytest.raises(LreiError):
+        ctx.step("qLL", "RK4", -0.1, 0.1, 1)
+    with pytest.raises(LreiError):
+        ctx.step("qLL", "RK4", 0.1, -0.1, 1)
+
+
+def test_full_size_hv_sampled_rows():
+    """4x5 periodic Heisenberg lattice, n=20, r=16: sampled rows of H V vs the oracle."""
+    cfg = make_config(3)
+    ctx = _ctx()
+    ctx.set_hamiltonian(cfg["n"], cfg["bonds"], cfg["J"], cfg["h"])
+    Y = ctx.apply_hamiltonian(cfg["V"])
+    rows = np.random.default_rng(0).choice(2 ** 20, size=256, replace=False)
+    rows = np.concatenate([rows, [0, 1, 2 ** 20 - 1]])
+    Yo = apply_H_rows(cfg["n"], cfg["bonds"], cfg["J"], cfg["h"], cfg["V"], rows)
+    assert np.abs(Y[rows] - Yo).max() < 1e-13 * np.abs(Yo).max()

@@ -131,3 +131,14 @@ def test_hamiltonian_class():
     H = Hamiltonian(4, bonds, J, h)
     V = haar_factor(16, 2, rng)
     np.testing.assert_allclose(H.apply(V), H.dense() @ V, atol=1e-13)
+
+
+def test_row_sampled_apply_matches_full():
+    from oracle.hamiltonian import apply_H_rows
+    rng = np.random.default_rng(9)
+    n = 8
+    bonds, J, h = _random_model(n, rng)
+    V = haar_factor(2 ** n, 4, rng)
+    rows = rng.choice(2 ** n, size=37, replace=False)
+    np.testing.assert_allclose(apply_H_rows(n, bonds, J, h, V, rows),
+                               apply_H(n, bonds, J, h, V)[rows], atol=1e-13)
