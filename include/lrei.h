@@ -153,6 +153,18 @@ LREI_API lrei_status lrei_apply_hamiltonian(lrei_ctx *ctx, int r, const void *X,
 LREI_API lrei_status lrei_get_state(lrei_ctx *ctx, void *buf, size_t *len);
 LREI_API lrei_status lrei_set_state(lrei_ctx *ctx, const void *buf, size_t len);
 
+/* Measurement: times each kernel of one step of the given configuration with
+ * HIP events on the context's stream, averaged over `iters` launches of the
+ * same kernel with the same arguments and launch shape the step uses:
+ *   ms[0] Chebyshev H.V pass with fused Gram products (recurrence form),
+ *   ms[1] partial-sum reduction, ms[2] projected step kernel,
+ *   ms[3] basis combination.
+ * Needs one completed lrei_step with this configuration (the projected
+ * kernel reads that step's Gram products).  The state is not modified: the
+ * combination writes to a scratch block. */
+LREI_API lrei_status lrei_profile_kernels(lrei_ctx *ctx, int model, int scheme, double dt, double kappa,
+                                          int iters, double ms[4]);
+
 /* Blocks until all work queued by this context has finished. */
 LREI_API lrei_status lrei_synchronize(lrei_ctx *ctx);
 

@@ -188,8 +188,7 @@ void cheb_pass(lrei_ctx *ctx, int mode, const void *prev, const void *cur, void 
                  ctx->ws.meas + (size_t)slot * 3 * ctx->r * ctx->r);
 }
 
-// Enqueues one LREI-RK step (Chebyshev Krylov passes, projected step, combine).
-void enqueue_rk_step(lrei_ctx *ctx, int model, int scheme, double dt, double kappa) {
+SmallRkParams rk_params(lrei_ctx *ctx, int model, int scheme, double dt, double kappa) {
   SmallRkParams p{};
   int s;
   tableau(scheme, s, p.a, p.b);
@@ -208,6 +207,13 @@ void enqueue_rk_step(lrei_ctx *ctx, int model, int scheme, double dt, double kap
   p.halfwidth = ctx->terms.gershgorin > 0 ? ctx->terms.gershgorin : 1.0;
   for (int i = 0; i < ctx->r; ++i) p.lam[i] = ctx->lam[i];
   p.lds_elems = small_lds_elems(p.nblocks * ctx->r, ctx->r);
+  return p;
+}
+
+// Enqueues one LREI-RK step (Chebyshev Krylov passes, projected step, combine).
+void enqueue_rk_step(lrei_ctx *ctx, int model, int scheme, double dt, double kappa) {
+  const SmallRkParams p = rk_params(ctx, model, scheme, dt, kappa);
+  const int s = p.s;
   cheb_pass(ctx, 0, nullptr, ctx->blocks[0].p, ctx->blocks[1].p, 0);
   for (int j = 1; j < s; ++j) cheb_pass(ctx, 1, ctx->blocks[j - 1].p, ctx->blocks[j].p, ctx->blocks[j + 1].p, j);
   launch_small_rk(p, ctx->ws, ctx->stream);
@@ -638,6 +644,67 @@ lrei_status lrei_set_state(lrei_ctx *ctx, const void *buf, size_t len) {
   lrei_status st = lrei_set_rho(ctx, r, lam, (const char *)buf + 32 + r * sizeof(double), 0);
   if (st != LREI_OK) return st;
   ctx->steps_done = (int64_t)hdr[3];
+  return LREI_OK;
+}
+
+lrei_status lrei_profile_kernels(lrei_ctx *ctx, int model, int scheme, double dt, double kappa, int iters,
+                                 double ms[4]) {
+  if (!ctx || !ms || iters < 1) return LREI_E_INVALID;
+  if (!ctx->have_rho || ctx->steps_done < 1) return ctx->fail(LREI_E_STATE, "run one step first");
+  if (!(scheme >= LREI_RK1 && scheme <= LREI_RK4)) return ctx->fail(LREI_E_INVALID, "RK schemes only");
+  HIPCHK(hipSetDevice(ctx->device));
+  const SmallRkParams p = rk_params(ctx, model, scheme, dt, kappa);
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  const int r = ctx->r;
+  auto timed = [&](int which) -> double {
+    // one untimed launch, then `iters` timed ones
+    for (int k = 0; k <= iters; ++k) {
+      if (k == 1) (void)hipEventRecord(e0, ctx->stream);
+      switch (which) {
+        case 0: {
+          ChebArgs a{};
+          a.Pprev = ctx->blocks[0].p;
+          a.Pcur = ctx->blocks[1].p;
+          a.Pnext = ctx->blocks[4].p;
+          a.off = (const DevOffTerm *)ctx->d_off.p;
+          a.diag = (const DevDiagTerm *)ctx->d_diag.p;
+          a.n_off = ctx->n_off;
+          a.n_diag = ctx->n_diag;
+          a.N = ctx->N;
+          a.r = r;
+          a.alpha = 1.0 / (ctx->terms.gershgorin > 0 ? ctx->terms.gershgorin : 1.0);
+          a.mode = 1;
+          a.partials = (double2 *)ctx->partials.p;
+          a.grid = ctx->grid;
+          launch_cheb(ctx->fp32, a, ctx->stream);
+          break;
+        }
+        case 1:
+          launch_reduce((const double2 *)ctx->partials.p, ctx->grid * cheb_partial_splits(r), 3 * r * r,
+                        ctx->ws.work, ctx->stream);  // scratch target: the step's Grams stay intact
+          break;
+        case 2:
+          launch_small_rk(p, ctx->ws, ctx->stream);
+          break;
+        default: {
+          const void *bl[kMaxBlocks];
+          for (int i = 0; i <= p.s; ++i) bl[i] = ctx->blocks[i].p;
+          launch_combine(ctx->fp32, bl, p.s + 1, ctx->ws.Cfin, ctx->save.p, ctx->N, r, ctx->grid, ctx->stream);
+        }
+      }
+    }
+    (void)hipEventRecord(e1, ctx->stream);
+    (void)hipEventSynchronize(e1);
+    float t = 0;
+    (void)hipEventElapsedTime(&t, e0, e1);
+    return (double)t / iters;
+  };
+  for (int w = 0; w < 4; ++w) ms[w] = timed(w);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  HIPCHK(hipGetLastError());
   return LREI_OK;
 }
 

@@ -66,6 +66,8 @@ _SIGS = {
     "lrei_apply_hamiltonian": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.c_int]),
     "lrei_get_state": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_size_t)]),
     "lrei_set_state": (ctypes.c_int, [_P, _P, ctypes.c_size_t]),
+    "lrei_profile_kernels": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                             ctypes.c_int, _P]),
     "lrei_synchronize": (ctypes.c_int, [_P]),
 }
 
@@ -202,6 +204,13 @@ class Context:
         self._check(self.lib.lrei_set_state(self.h, buf, len(blob)))
         hdr = np.frombuffer(blob[:32], dtype=np.uint64)
         self.r = int(hdr[2])
+
+    def profile_kernels(self, model, scheme, dt, kappa, iters=20):
+        """Average per-launch ms of (H.V pass, reduction, projected step, combination)."""
+        ms = (ctypes.c_double * 4)()
+        self._check(self.lib.lrei_profile_kernels(self.h, MODELS[model], SCHEMES[scheme], float(dt),
+                                                  float(kappa), int(iters), ms))
+        return dict(hv_pass=ms[0], reduce=ms[1], projected_step=ms[2], combine=ms[3])
 
     def synchronize(self):
         self._check(self.lib.lrei_synchronize(self.h))
