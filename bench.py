@@ -166,6 +166,9 @@ def main():
         "kernels_ms": {k: round(v, 5) for k, v in kms.items()},
         "eig_stats": {k: stats[k] for k in ("eigensolves", "jacobi_sweeps", "max_sweeps_one_solve",
                                             "dropped_directions", "min_pivot_ratio", "ortho_error")},
+        "projected_phase_ms_per_step": dict(zip(
+            ["gram_setup", "cholesky", "r_inverse", "h_apply", "householder", "stage_matrix", "jacobi", "tail"],
+            [round(v / args.steps, 4) for v in stats["phase_ms"]])),
     }
     print(json.dumps(line))
 

@@ -94,6 +94,9 @@ typedef struct {
   double last_step_ms;           /* wall time of the last lrei_step call                */
   int64_t warm_accepted;         /* learned/analytic start rotations used                */
   int64_t warm_rejected;         /* start rotations rejected (fell back to identity)     */
+  double phase_ms[8];            /* projected-step kernel time by phase over the last
+                                    call: Gram/Cholesky setup, Cholesky, R^-1, H u,
+                                    Householder, stage matrix, Jacobi, tail          */
 } lrei_stats;
 
 /* Fills *opt with the defaults listed above. */

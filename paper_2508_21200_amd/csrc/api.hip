@@ -180,7 +180,7 @@ void cheb_pass_into(lrei_ctx *ctx, int r, int grid, int mode, const void *prev, 
   a.partials = partials;
   a.grid = grid;
   launch_cheb(ctx->fp32, a, ctx->stream);
-  if (mode != 2) launch_reduce(partials, grid * cheb_partial_splits(r), 3 * r * r, meas, ctx->stream);
+  if (mode != 2) launch_reduce(partials, grid, (mode == 0 ? 3 : 2) * r * r, meas, ctx->stream);
 }
 
 void cheb_pass(lrei_ctx *ctx, int mode, const void *prev, const void *cur, void *next, int slot) {
@@ -502,6 +502,7 @@ lrei_status lrei_step(lrei_ctx *ctx, int model, int scheme, double dt, double ka
   ctx->stats.ortho_error = h[4];
   ctx->stats.energy = h[5];
   ctx->stats.last_step_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  for (int k = 0; k < 8; ++k) ctx->stats.phase_ms[k] = h[16 + k];
   return LREI_OK;
 }
 
@@ -682,7 +683,7 @@ lrei_status lrei_profile_kernels(lrei_ctx *ctx, int model, int scheme, double dt
           break;
         }
         case 1:
-          launch_reduce((const double2 *)ctx->partials.p, ctx->grid * cheb_partial_splits(r), 3 * r * r,
+          launch_reduce((const double2 *)ctx->partials.p, ctx->grid, 2 * r * r,
                         ctx->ws.work, ctx->stream);  // scratch target: the step's Grams stay intact
           break;
         case 2:

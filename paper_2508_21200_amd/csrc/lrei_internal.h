@@ -108,11 +108,20 @@ struct SmallWs {
   double *stats;     // [16]
 };
 
-constexpr int kSmallLdsBytes = 120 * 1024;
+// LDS arena of the projected-step kernel: an 80 x 80 Cholesky factor, or the
+// packed stage matrix plus inverse-iteration scratch (the largest problems kept
+// in LDS; bigger ones fall back to global memory).
+constexpr int kSmallLdsElems = 80 * 80;
+constexpr int kSmallLdsBytes = kSmallLdsElems * 16;
 // LDS capacity (double2 elements) to request for a projected dimension D.
 inline int small_lds_elems(int D, int r) {
-  const int full = D * D, cap = kSmallLdsBytes / 16;
-  return full <= cap ? full : r * r;
+  const int sl = r <= 16 ? 16 : 32;
+  int need = D * D;
+  const int tri = D * (D + 1) / 2 + 2 * D * sl;
+  if (tri > need) need = tri;
+  if (3 * D * r > need) need = 3 * D * r;
+  if (2 * r * r > need) need = 2 * r * r;
+  return need < kSmallLdsElems ? need : kSmallLdsElems;
 }
 void launch_small_rk(const SmallRkParams &p, const SmallWs &ws, hipStream_t s);
 int cheb_partial_splits(int r);

@@ -24,7 +24,7 @@ template <> struct Cplx<float> { using type = float2; };
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 constexpr int kTile = 64;     // rows per tile
-constexpr int kMaxItems = 4;  // Gram work items per wave
+constexpr int kMaxItems = 3;  // Gram work items per wave (upper bound)
 constexpr int kMaxLds = 150 * 1024;
 
 __host__ __device__ inline int pow2ceil(int v) {
@@ -74,15 +74,15 @@ struct GramPlan {
   int ng, ta, rs, items;
 };
 
-template <typename T>
+template <typename T, int MI>
 __device__ inline void gram_tile(const T *const *xre, const T *const *xim, const T *const *yre,
                                  const T *const *yim, const GramPlan<T> &gp, int RP,
-                                 double (&acc)[kMaxItems][8]) {
+                                 double (&acc)[MI][8]) {
   using A4 = typename Acc4<T>::type;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int rows_per_split = kTile / gp.rs;
 #pragma unroll
-  for (int q = 0; q < kMaxItems; ++q) {
+  for (int q = 0; q < MI; ++q) {
     const int it = wave + kWaves * q;
     if (it >= gp.items) break;
     int t = it;
@@ -112,30 +112,46 @@ __device__ inline void gram_tile(const T *const *xre, const T *const *xim, const
   }
 }
 
-template <typename T>
-__device__ inline void gram_store(const GramPlan<T> &gp, const double (&acc)[kMaxItems][8], int r,
-                                  double2 *partials) {
-  // partials layout: [grid][rs][ng][r*r]
+// Writes the workgroup's Gram partial sums, entry-major: partials[e * grid + wg]
+// with e = g * r * r + a * r + b.  Row splits (held by different waves) are
+// summed through LDS in a fixed wave order, so the result is deterministic.
+template <typename T, int MI>
+__device__ inline void gram_store(const GramPlan<T> &gp, const double (&acc)[MI][8], int r,
+                                  double2 *partials, double2 *stage /* LDS, ng * r * r */) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const long long base = (long long)blockIdx.x * gp.rs * gp.ng * r * r;
+  const int grid = gridDim.x;
+  for (int w = 0; w < kWaves; ++w) {
+    if (gp.rs == 1 || wave == w) {
 #pragma unroll
-  for (int q = 0; q < kMaxItems; ++q) {
-    const int it = wave + kWaves * q;
-    if (it >= gp.items) break;
-    int t = it;
-    const int split = t % gp.rs; t /= gp.rs;
-    const int tb = t % gp.ta; t /= gp.ta;
-    const int ta = t % gp.ta; t /= gp.ta;
-    const int g = t;
-    const int b = tb * 16 + (lane & 15);
+      for (int q = 0; q < MI; ++q) {
+        const int it = wave + kWaves * q;
+        if (it >= gp.items) break;
+        int t = it;
+        const int split = t % gp.rs; t /= gp.rs;
+        const int tb = t % gp.ta; t /= gp.ta;
+        const int ta = t % gp.ta; t /= gp.ta;
+        const int g = t;
+        const int b = tb * 16 + (lane & 15);
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int a = ta * 16 + mfma_row<T>(lane, v);
-      if (a < r && b < r)
-        partials[base + ((long long)split * gp.ng + g) * r * r + a * r + b] =
-            make_double2(acc[q][v], acc[q][4 + v]);
+        for (int v = 0; v < 4; ++v) {
+          const int a = ta * 16 + mfma_row<T>(lane, v);
+          if (a < r && b < r) {
+            const int e = (g * r + a) * r + b;
+            const double2 val = make_double2(acc[q][v], acc[q][4 + v]);
+            if (gp.rs == 1 || split == 0) {
+              stage[e] = val;
+            } else {
+              stage[e].x += val.x;
+              stage[e].y += val.y;
+            }
+          }
+        }
+      }
     }
+    __syncthreads();
+    if (gp.rs == 1) break;
   }
+  for (int e = threadIdx.x; e < gp.ng * r * r; e += kThreads) partials[(long long)e * grid + blockIdx.x] = stage[e];
 }
 
 template <typename T>
@@ -144,7 +160,7 @@ __device__ inline GramPlan<T> make_plan(int ng, int RP) {
   gp.ng = ng;
   gp.ta = RP / 16;
   const int base = ng * gp.ta * gp.ta;
-  gp.rs = base >= kWaves ? 1 : kWaves;
+  gp.rs = base >= kWaves ? 1 : kWaves / base;  // rows per split stays a multiple of 16
   gp.items = base * gp.rs;
   return gp;
 }
@@ -155,7 +171,7 @@ __device__ inline GramPlan<T> make_plan(int ng, int RP) {
 //   mode 1: P+ = 2 alpha (H - shift) P - P-           Grams P-*P+, P*P+, P+*P+
 //   mode 2: Y = H X                                    (no Grams)
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int MI>
 __global__ __launch_bounds__(kThreads) void k_cheb(ChebArgs a) {
   using C2 = typename Cplx<T>::type;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -193,19 +209,22 @@ __global__ __launch_bounds__(kThreads) void k_cheb(ChebArgs a) {
   const T alpha = (T)a.alpha, shift = (T)a.shift;
   const T mul = a.mode == 1 ? T(2) : T(1);
 
-  const int ng = a.mode == 2 ? 0 : 3;
+  const int ng = a.mode == 2 ? 0 : (a.mode == 0 ? 3 : 2);
   GramPlan<T> gp = make_plan<T>(ng > 0 ? ng : 1, RP);
   const T *xre[3], *xim[3], *yre[3], *yim[3];
   if (a.mode == 0) {
     xre[0] = cre; xim[0] = cim; yre[0] = cre; yim[0] = cim;
+    xre[1] = cre; xim[1] = cim; yre[1] = nre; yim[1] = nim;
+    xre[2] = nre; xim[2] = nim; yre[2] = nre; yim[2] = nim;
   } else {
-    xre[0] = pre; xim[0] = pim; yre[0] = nre; yim[0] = nim;
+    xre[0] = cre; xim[0] = cim; yre[0] = nre; yim[0] = nim;
+    xre[1] = nre; xim[1] = nim; yre[1] = nre; yim[1] = nim;
+    xre[2] = nre; xim[2] = nim; yre[2] = nre; yim[2] = nim;
   }
-  xre[1] = cre; xim[1] = cim; yre[1] = nre; yim[1] = nim;
-  xre[2] = nre; xim[2] = nim; yre[2] = nre; yim[2] = nim;
-  double acc[kMaxItems][8];
+  (void)pre; (void)pim;
+  double acc[MI][8];
 #pragma unroll
-  for (int q = 0; q < kMaxItems; ++q)
+  for (int q = 0; q < MI; ++q)
 #pragma unroll
     for (int v = 0; v < 8; ++v) acc[q][v] = 0.0;
 
@@ -222,21 +241,42 @@ __global__ __launch_bounds__(kThreads) void k_cheb(ChebArgs a) {
       if (x >= N) continue;
       T ore = 0, oim = 0, xr = 0, xi = 0, vr = 0, vi = 0;
       if (colok) {
-        const C2 own = Pc[x * r + col];
+        const uint32_t xu = (uint32_t)x;
+        const C2 own = Pc[(size_t)xu * r + col];
         xr = own.x; xi = own.y;
         double dsum = 0.0;
         for (int t = 0; t < a.n_diag; ++t) {
           const DevDiagTerm dt = s_diag[t];
-          const int par = (int)(((x >> dt.si) ^ (x >> dt.sj)) & 1);
-          dsum += par ? -dt.w : dt.w;
+          dsum += (((xu >> dt.si) ^ (xu >> dt.sj)) & 1u) ? -dt.w : dt.w;
         }
         T accr = (T)dsum * xr, acci = (T)dsum * xi;
-        for (int t = 0; t < a.n_off; ++t) {
+        const int nof = a.n_off;
+        int t = 0;
+        // Batches of 8 independent row gathers keep 8 loads in flight per lane.
+        for (; t + 8 <= nof; t += 8) {
+          C2 y[8];
+          T cr[8], ci[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const DevOffTerm &ot = s_off[t + u];
+            const uint32_t idx = ((xu >> ot.sa) & 1u) | (((xu >> ot.sb) & 1u) << 1);
+            cr[u] = (T)ot.re[idx];
+            ci[u] = (T)ot.im[idx];
+            y[u].x = 0; y[u].y = 0;
+            if (cr[u] != T(0) || ci[u] != T(0)) y[u] = Pc[(size_t)(xu ^ ot.mask) * r + col];
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            accr += cr[u] * y[u].x - ci[u] * y[u].y;
+            acci += cr[u] * y[u].y + ci[u] * y[u].x;
+          }
+        }
+        for (; t < nof; ++t) {
           const DevOffTerm &ot = s_off[t];
-          const int idx = (int)((x >> ot.sa) & 1) | ((int)((x >> ot.sb) & 1) << 1);
+          const uint32_t idx = ((xu >> ot.sa) & 1u) | (((xu >> ot.sb) & 1u) << 1);
           const T cr = (T)ot.re[idx], ci = (T)ot.im[idx];
           if (cr == T(0) && ci == T(0)) continue;
-          const C2 y = Pc[(x ^ (long long)ot.mask) * r + col];
+          const C2 y = Pc[(size_t)(xu ^ ot.mask) * r + col];
           accr += cr * y.x - ci * y.y;
           acci += cr * y.y + ci * y.x;
         }
@@ -246,30 +286,32 @@ __global__ __launch_bounds__(kThreads) void k_cheb(ChebArgs a) {
           ore = mul * alpha * (accr - shift * xr);
           oim = mul * alpha * (acci - shift * xi);
           if (a.mode == 1) {
-            const C2 pv = Pp[x * r + col];
+            const C2 pv = Pp[(size_t)xu * r + col];
             vr = pv.x; vi = pv.y;
             ore -= vr; oim -= vi;
           }
         }
         C2 o;
         o.x = ore; o.y = oim;
-        Pn[x * r + col] = o;
+        Pn[(size_t)xu * r + col] = o;
       }
       if (grams && colok) {
         cre[lr * RP + col] = xr; cim[lr * RP + col] = xi;
         nre[lr * RP + col] = ore; nim[lr * RP + col] = oim;
-        if (a.mode == 1) { pre[lr * RP + col] = vr; pim[lr * RP + col] = vi; }
       }
     }
     if (grams) {
       __syncthreads();
       // rows beyond N keep the zeros written at start only for the first tile;
       // N is a power of two >= 2 so a partial tile is always the only tile.
-      gram_tile<T>(xre, xim, yre, yim, gp, RP, acc);
+      gram_tile<T, MI>(xre, xim, yre, yim, gp, RP, acc);
       __syncthreads();
     }
   }
-  if (grams) gram_store<T>(gp, acc, r, a.partials);
+  if (grams) {
+    __syncthreads();
+    gram_store<T, MI>(gp, acc, r, a.partials, reinterpret_cast<double2 *>(planes));
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -364,28 +406,27 @@ __global__ __launch_bounds__(kThreads) void k_combine(CombineArgs a) {
   }
 }
 
-// Deterministic reduction: out[e] = sum_{c < count} in[c * len + e] in a fixed order.
+// Deterministic reduction of entry-major partials: out[e] = sum_c in[e * count + c],
+// one workgroup per entry, strided per-thread sums then a fixed tree.
 __global__ __launch_bounds__(256) void k_reduce(const double2 *in, int count, int len, double2 *out) {
-  __shared__ double2 part[4][64];
-  const int e = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int q = threadIdx.x >> 6;
+  __shared__ double2 part[256];
+  const int e = blockIdx.x;
   double sr = 0.0, si = 0.0;
-  if (e < len)
-    for (int c = q; c < count; c += 4) {
-      const double2 v = in[(long long)c * len + e];
-      sr += v.x;
-      si += v.y;
-    }
-  part[q][threadIdx.x & 63] = make_double2(sr, si);
-  __syncthreads();
-  if (q == 0 && e < len) {
-    double2 s = part[0][threadIdx.x];
-    for (int k = 1; k < 4; ++k) {
-      s.x += part[k][threadIdx.x].x;
-      s.y += part[k][threadIdx.x].y;
-    }
-    out[e] = s;
+  for (int c = threadIdx.x; c < count; c += 256) {
+    const double2 v = in[(long long)e * count + c];
+    sr += v.x;
+    si += v.y;
   }
+  part[threadIdx.x] = make_double2(sr, si);
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      part[threadIdx.x].x += part[threadIdx.x + w].x;
+      part[threadIdx.x].y += part[threadIdx.x + w].y;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[e] = part[0];
 }
 
 __global__ void k_convert_d2f(const double2 *src, float2 *dst, long long n) {
@@ -460,8 +501,8 @@ size_t cheb_lds(bool fp32, int n_off, int n_diag, int r) {
 }  // namespace
 
 int cheb_partial_splits(int r) {
-  const int ta = pad16(r) / 16;
-  return 3 * ta * ta >= kWaves ? 1 : kWaves;
+  (void)r;
+  return 1;  // row splits are summed inside the workgroup
 }
 
 int nspace_grid(long long N, int r) {
@@ -476,14 +517,21 @@ void launch_cheb(bool fp32, const ChebArgs &a, hipStream_t s) {
   const size_t lds = cheb_lds(fp32, a.n_off, a.n_diag, a.r);
   static bool attr = false;
   if (!attr) {
-    (void)hipFuncSetAttribute((const void *)k_cheb<float>, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
-    (void)hipFuncSetAttribute((const void *)k_cheb<double>, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+    (void)hipFuncSetAttribute((const void *)k_cheb<float, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+    (void)hipFuncSetAttribute((const void *)k_cheb<double, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+    (void)hipFuncSetAttribute((const void *)k_cheb<float, 3>, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+    (void)hipFuncSetAttribute((const void *)k_cheb<double, 3>, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
     attr = true;
   }
-  if (fp32)
-    hipLaunchKernelGGL(k_cheb<float>, dim3(a.grid), dim3(kThreads), lds, s, a);
-  else
-    hipLaunchKernelGGL(k_cheb<double>, dim3(a.grid), dim3(kThreads), lds, s, a);
+  // one Gram work item per wave up to r = 16 (keeps registers low), three above
+  const bool small_r = a.r <= 16;
+  if (fp32) {
+    if (small_r) hipLaunchKernelGGL((k_cheb<float, 1>), dim3(a.grid), dim3(kThreads), lds, s, a);
+    else hipLaunchKernelGGL((k_cheb<float, 3>), dim3(a.grid), dim3(kThreads), lds, s, a);
+  } else {
+    if (small_r) hipLaunchKernelGGL((k_cheb<double, 1>), dim3(a.grid), dim3(kThreads), lds, s, a);
+    else hipLaunchKernelGGL((k_cheb<double, 3>), dim3(a.grid), dim3(kThreads), lds, s, a);
+  }
 }
 
 void launch_combine(bool fp32, const void *const *blocks, int nblocks, const double2 *C, void *out,
@@ -511,7 +559,7 @@ void launch_combine(bool fp32, const void *const *blocks, int nblocks, const dou
 }
 
 void launch_reduce(const double2 *partials, int count, int len, double2 *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce, dim3((len + 63) / 64), dim3(256), 0, s, partials, count, len, out);
+  hipLaunchKernelGGL(k_reduce, dim3(len), dim3(256), 0, s, partials, count, len, out);
 }
 
 void launch_convert(bool to_fp32, const void *src, void *dst, long long n, hipStream_t s) {

@@ -22,6 +22,10 @@
 //     k = u_1 Lambda_0 u_1* + h sum a_l (z_l u_l* + u_l w_l*) and its r largest
 //     eigenvectors by a cyclic two-sided complex Jacobi method.
 //  4. C = R^{-1} u_final.
+//
+// The Jacobi sweeps are latency bound: the stage matrix (packed upper
+// triangle) and the accumulated rotations live in LDS, and rounds are
+// separated by LDS-only barriers.
 #include <hip/hip_runtime.h>
 
 #include "lrei_internal.h"
@@ -30,8 +34,10 @@ namespace lrei {
 
 namespace {
 
-constexpr int NT = 1024;
-constexpr int kMaxPairs = kMaxDim / 2;
+constexpr int NT = 512;
+constexpr int NW = NT / 64;
+constexpr int kMaxPairs = kMaxR / 2 + 1;  // Jacobi is used for r x r problems only
+constexpr int kLdsJacobiMaxM = 80;  // packed A + V fit in LDS up to m = 80
 
 __device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ inline double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
@@ -49,51 +55,68 @@ __device__ inline double2 cdiv(double2 a, double2 b) {
   return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
 }
 
+// Barrier for LDS traffic only: global memory operations may stay in flight.
+__device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+__device__ inline double2 wave_sum(double2 v) {
+  for (int off = 32; off > 0; off >>= 1) {
+    v.x += __shfl_xor(v.x, off);
+    v.y += __shfl_xor(v.y, off);
+  }
+  return v;
+}
+
 // phi(delta): q-LL (delta/hbar)(i - kappa delta) (eq. 4.1); q-LLG (i delta/hbar)/(1 - i kappa delta)
 // (eq. 3.2: D / (E + L + L*)).  X11_ab = phi(lam_a - lam_b) G_ab, X12 = diag(phi(lam)) V* H Vhat.
 __device__ inline double2 phi(double d, int model, double kappa, double hbar) {
   if (model == 0) return make_double2(-kappa * d * d / hbar, d / hbar);
-  // (i d / hbar) / (1 - i kappa d) = (i d / hbar)(1 + i kappa d) / (1 + kappa^2 d^2)
   const double den = hbar * (1.0 + kappa * kappa * d * d);
   return make_double2(-kappa * d * d / den, d / den);
 }
 
 // ----- workgroup-wide small dense helpers (row-major, leading dimension ld) ---
 
-// C (m x n) = A (m x k) * B (k x n)
-__device__ void gemm_nn(double2 *C, int ldc, const double2 *A, int lda, const double2 *B, int ldb,
-                        int m, int n, int k) {
+// C (m x n) = A (m x k) * B (k x n); upper_a: A is upper triangular (skip q < i)
+__device__ void gemm_nn(double2 *C, int ldc, const double2 *A, int lda, const double2 *B, int ldb, int m,
+                        int n, int k, bool upper_a = false) {
   for (int e = threadIdx.x; e < m * n; e += NT) {
     const int i = e / n, j = e % n;
-    double2 s = make_double2(0, 0);
-    for (int q = 0; q < k; ++q) s = cadd(s, cmul(A[i * lda + q], B[q * ldb + j]));
-    C[i * ldc + j] = s;
+    double sr = 0, si = 0;
+    const int q0 = upper_a ? i : 0;
+#pragma unroll 8
+    for (int q = q0; q < k; ++q) {
+      const double2 a = A[i * lda + q], b = B[q * ldb + j];
+      sr += a.x * b.x - a.y * b.y;
+      si += a.x * b.y + a.y * b.x;
+    }
+    C[i * ldc + j] = make_double2(sr, si);
   }
 }
 // C (m x n) = A^H (A: k x m) * B (k x n)
-__device__ void gemm_hn(double2 *C, int ldc, const double2 *A, int lda, const double2 *B, int ldb,
-                        int m, int n, int k) {
+__device__ void gemm_hn(double2 *C, int ldc, const double2 *A, int lda, const double2 *B, int ldb, int m, int n,
+                        int k) {
   for (int e = threadIdx.x; e < m * n; e += NT) {
     const int i = e / n, j = e % n;
-    double2 s = make_double2(0, 0);
-    for (int q = 0; q < k; ++q) s = cadd(s, cmulc(A[q * lda + i], B[q * ldb + j]));
-    C[i * ldc + j] = s;
+    double sr = 0, si = 0;
+#pragma unroll 8
+    for (int q = 0; q < k; ++q) {
+      const double2 a = A[q * lda + i], b = B[q * ldb + j];
+      sr += a.x * b.x + a.y * b.y;
+      si += a.x * b.y - a.y * b.x;
+    }
+    C[i * ldc + j] = make_double2(sr, si);
   }
 }
 
-// out[c] = sum_{i < m} conj(v[i * ldv]) M[i * ldm + c], c < nc (nc <= 32), via LDS partials
-__device__ void col_dots(double2 *out, const double2 *v, int ldv, const double2 *M, int ldm, int m,
-                         int nc, double2 *s_red /* NT entries */) {
-  const int c = threadIdx.x % nc, slice = threadIdx.x / nc, S = NT / nc;
-  double2 s = make_double2(0, 0);
-  if (slice < S)
-    for (int i = slice; i < m; i += S) s = cadd(s, cmulc(v[i * ldv], M[i * ldm + c]));
-  s_red[threadIdx.x] = s;
-  __syncthreads();
-  if (threadIdx.x < nc) {
-    double2 t = make_double2(0, 0);
-    for (int q = 0; q < S; ++q) t = cadd(t, s_red[q * nc + threadIdx.x]);
-    out[threadIdx.x] = t;
+// out[c] = sum_{i < m} conj(v[i * ldv]) M[i * ldm + c] for c < nc, one wave per
+// column (wave-level reduction, no LDS).  Ends with a barrier.
+__device__ void col_dots(double2 *out, const double2 *v, int ldv, const double2 *M, int ldm, int m, int nc) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int c = wave; c < nc; c += NW) {
+    double2 s = make_double2(0, 0);
+    for (int i = lane; i < m; i += 64) s = cadd(s, cmulc(v[i * ldv], M[i * ldm + c]));
+    s = wave_sum(s);
+    if (lane == 0) out[c] = s;
   }
   __syncthreads();
 }
@@ -105,48 +128,59 @@ struct JacobiShared {
   double cs[kMaxPairs], sn[kMaxPairs], t[kMaxPairs];
   double2 e[kMaxPairs];
   int rotated;
+  double scale;
   int order[kMaxR];
 };
 
 __device__ inline int rr_player(int pos, int round, int mp) {
   return pos == 0 ? 0 : 1 + (pos - 1 + round) % (mp - 1);
 }
+// packed upper triangle, column-major: element (i, j), i <= j
+__device__ inline int pk(int i, int j) { return j * (j + 1) / 2 + i; }
+__device__ inline double2 aget(const double2 *A, int i, int j) {
+  return i <= j ? A[pk(i, j)] : cconj(A[pk(j, i)]);
+}
+__device__ inline void aset(double2 *A, int i, int j, double2 v) {
+  if (i <= j)
+    A[pk(i, j)] = v;
+  else
+    A[pk(j, i)] = cconj(v);
+}
 
-// Diagonalises the Hermitian m x m matrix A (row-major, ld m) in place and
-// accumulates V = product of rotations (V starts as identity).  Returns the
-// sweep count, or -1 when max_sweeps is reached.
-__device__ int jacobi(double2 *A, double2 *V, int m, double tol, int max_sweeps, JacobiShared &js) {
+// Diagonalises the Hermitian m x m matrix A (packed upper triangle) in place and
+// accumulates V = product of rotations (m x m row-major, starts as identity).
+// A and V may live in LDS or global memory (lds says which barrier suffices).
+// Returns the sweep count, or -1 when max_sweeps is reached.
+__device__ int jacobi(double2 *A, double2 *V, int m, double tol, int max_sweeps, JacobiShared &js, bool lds) {
   const int mp = m + (m & 1), np = mp / 2;
   for (int e = threadIdx.x; e < m * m; e += NT)
     V[e] = make_double2((e / m) == (e % m) ? 1.0 : 0.0, 0.0);
-  // scale = max |A_ii|
-  __shared__ double s_scale;
   if (threadIdx.x == 0) {
     double sc = 0;
-    for (int i = 0; i < m; ++i) sc = fmax(sc, fabs(A[i * m + i].x));
-    s_scale = sc > 0 ? sc : 1.0;
+    for (int i = 0; i < m; ++i) sc = fmax(sc, fabs(A[pk(i, i)].x));
+    js.scale = sc > 0 ? sc : 1.0;
   }
   __syncthreads();
-  const double thresh = tol * s_scale;
+  const double thresh = tol * js.scale;
   if (m == 1) return 0;
-  int sweep = 0;
-  for (; sweep < max_sweeps; ++sweep) {
+  const int nblk = np * (np + 1) / 2;
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     if (threadIdx.x == 0) js.rotated = 0;
     __syncthreads();
     for (int round = 0; round < mp - 1; ++round) {
       if (threadIdx.x < np) {
         const int i = threadIdx.x;
-        int a = rr_player(i, round, mp), b = rr_player(mp - 1 - i, round, mp);
+        const int a = rr_player(i, round, mp), b = rr_player(mp - 1 - i, round, mp);
         const int p = a < b ? a : b, q = a < b ? b : a;
         js.p[i] = p;
         js.q[i] = q;
         double cs = 1, sn = 0, t = 0;
         double2 e = make_double2(1, 0);
         if (q < m) {
-          const double2 c = A[p * m + q];
+          const double2 c = A[pk(p, q)];
           const double x = sqrt(cabs2(c));
           if (x > thresh) {
-            const double app = A[p * m + p].x, aqq = A[q * m + q].x;
+            const double app = A[pk(p, p)].x, aqq = A[pk(q, q)].x;
             const double tau = (aqq - app) / (2.0 * x);
             t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
             cs = 1.0 / sqrt(1.0 + t * t);
@@ -160,79 +194,78 @@ __device__ int jacobi(double2 *A, double2 *V, int m, double tol, int max_sweeps,
         js.t[i] = t;
         js.e[i] = e;
       }
-      __syncthreads();
-      // two-sided update of 2x2 blocks (P rows, Q cols); diagonal blocks exact
-      for (int blk = threadIdx.x; blk < np * np; blk += NT) {
-        const int P = blk / np, Q = blk % np;
+      if (lds) lds_barrier(); else __syncthreads();
+      // two-sided update of the 2x2 blocks (P rows, Q cols), P <= Q; the
+      // (Q, P) blocks are their adjoints in the packed storage
+      for (int blk = threadIdx.x; blk < nblk; blk += NT) {
+        int P = 0, rem = blk;
+        while (rem >= np - P) {
+          rem -= np - P;
+          ++P;
+        }
+        const int Q = P + rem;
+        const double snP = js.sn[P], snQ = js.sn[Q];
+        if (snP == 0.0 && snQ == 0.0) continue;
         const int pP = js.p[P], qP = js.q[P], pQ = js.p[Q], qQ = js.q[Q];
-        if (js.sn[P] == 0.0 && js.sn[Q] == 0.0) continue;
         if (P == Q) {
           if (qP >= m) continue;
-          const double x = sqrt(cabs2(A[pP * m + qP]));
-          const double app = A[pP * m + pP].x, aqq = A[qP * m + qP].x;
-          A[pP * m + pP] = make_double2(app - js.t[P] * x, 0.0);
-          A[qP * m + qP] = make_double2(aqq + js.t[P] * x, 0.0);
-          A[pP * m + qP] = make_double2(0, 0);
-          A[qP * m + pP] = make_double2(0, 0);
+          const double x = sqrt(cabs2(A[pk(pP, qP)]));
+          const double app = A[pk(pP, pP)].x, aqq = A[pk(qP, qP)].x;
+          A[pk(pP, pP)] = make_double2(app - js.t[P] * x, 0.0);
+          A[pk(qP, qP)] = make_double2(aqq + js.t[P] * x, 0.0);
+          A[pk(pP, qP)] = make_double2(0, 0);
           continue;
         }
         const bool hq = qP < m, hqq = qQ < m;
         const double2 z = make_double2(0, 0);
-        double2 a = A[pP * m + pQ];
-        double2 b = hqq ? A[pP * m + qQ] : z;
-        double2 c = hq ? A[qP * m + pQ] : z;
-        double2 d = (hq && hqq) ? A[qP * m + qQ] : z;
-        // rows: J_P^H
-        const double csP = js.cs[P], snP = js.sn[P];
+        const double2 a = aget(A, pP, pQ);
+        const double2 b = hqq ? aget(A, pP, qQ) : z;
+        const double2 c = hq ? aget(A, qP, pQ) : z;
+        const double2 d = (hq && hqq) ? aget(A, qP, qQ) : z;
+        const double csP = js.cs[P];
         const double2 ebP = cconj(js.e[P]);
         const double2 a1 = csub(cscale(csP, a), cscale(snP, cmul(ebP, c)));
         const double2 b1 = csub(cscale(csP, b), cscale(snP, cmul(ebP, d)));
         const double2 c1 = cadd(cscale(snP, a), cscale(csP, cmul(ebP, c)));
         const double2 d1 = cadd(cscale(snP, b), cscale(csP, cmul(ebP, d)));
-        // cols: J_Q
-        const double csQ = js.cs[Q], snQ = js.sn[Q];
+        const double csQ = js.cs[Q];
         const double2 eQ = js.e[Q];
-        A[pP * m + pQ] = csub(cscale(csQ, a1), cscale(snQ, cmul(eQ, b1)));
-        if (hqq) A[pP * m + qQ] = cadd(cscale(snQ, a1), cscale(csQ, cmul(eQ, b1)));
-        if (hq) A[qP * m + pQ] = csub(cscale(csQ, c1), cscale(snQ, cmul(eQ, d1)));
-        if (hq && hqq) A[qP * m + qQ] = cadd(cscale(snQ, c1), cscale(csQ, cmul(eQ, d1)));
+        aset(A, pP, pQ, csub(cscale(csQ, a1), cscale(snQ, cmul(eQ, b1))));
+        if (hqq) aset(A, pP, qQ, cadd(cscale(snQ, a1), cscale(csQ, cmul(eQ, b1))));
+        if (hq) aset(A, qP, pQ, csub(cscale(csQ, c1), cscale(snQ, cmul(eQ, d1))));
+        if (hq && hqq) aset(A, qP, qQ, cadd(cscale(snQ, c1), cscale(csQ, cmul(eQ, d1))));
       }
       for (int e = threadIdx.x; e < np * m; e += NT) {
         const int P = e / m, i = e % m;
-        if (js.sn[P] == 0.0) continue;
+        const double sn = js.sn[P];
+        if (sn == 0.0) continue;
         const int p = js.p[P], q = js.q[P];
         const double2 vp = V[i * m + p], vq = V[i * m + q];
-        const double cs = js.cs[P], sn = js.sn[P];
+        const double cs = js.cs[P];
         const double2 ee = js.e[P];
         V[i * m + p] = csub(cscale(cs, vp), cscale(sn, cmul(ee, vq)));
         V[i * m + q] = cadd(cscale(sn, vp), cscale(cs, cmul(ee, vq)));
       }
-      __syncthreads();
+      if (lds) lds_barrier(); else __syncthreads();
     }
-    const int rot = js.rotated;
     __syncthreads();
-    if (!rot) return sweep + 1;
+    if (!js.rotated) return sweep + 1;
   }
   return -1;
 }
 
 // Largest-r eigenvalues of a diagonalised A (descending) -> columns of V into u.
-__device__ void take_top(const double2 *A, const double2 *V, int m, int r, double2 *u, int ldu,
-                         int rows_out, JacobiShared &js) {
-  if (threadIdx.x == 0) {
-    bool used[kMaxDim];
-    for (int i = 0; i < m; ++i) used[i] = false;
-    for (int k = 0; k < r; ++k) {
-      int best = -1;
-      double bv = 0;
-      for (int i = 0; i < m; ++i)
-        if (!used[i] && (best < 0 || A[i * m + i].x > bv)) {
-          best = i;
-          bv = A[i * m + i].x;
-        }
-      used[best] = true;
-      js.order[k] = best;
+// Each diagonal entry's rank (ties broken by index) is computed in parallel.
+__device__ void take_top(const double2 *A, const double2 *V, int m, int r, double2 *u, int ldu, int rows_out,
+                         JacobiShared &js) {
+  for (int i = threadIdx.x; i < m; i += NT) {
+    const double v = A[pk(i, i)].x;
+    int rank = 0;
+    for (int k = 0; k < m; ++k) {
+      const double w = A[pk(k, k)].x;
+      rank += (w > v) || (w == v && k < i);
     }
+    if (rank < r) js.order[rank] = i;
   }
   __syncthreads();
   for (int e = threadIdx.x; e < rows_out * r; e += NT) {
@@ -242,36 +275,317 @@ __device__ void take_top(const double2 *A, const double2 *V, int m, int r, doubl
   __syncthreads();
 }
 
+__device__ inline uint64_t now_ticks() { return __builtin_amdgcn_s_memrealtime(); }
+
+// ----- top-r eigenpairs by Householder tridiagonalisation ---------------------
+//
+// A (m x m Hermitian, packed lower triangle, column-major) is reduced to a
+// Hermitian tridiagonal T = Q^H A Q with m-2 Householder reflectors (vectors
+// kept in A's columns below the subdiagonal), T is made real by a diagonal
+// phase scaling, the r largest eigenvalues are found by multisection on Sturm
+// counts, their eigenvectors by inverse iteration with partial-pivoting
+// tridiagonal solves (re-orthogonalised within clusters of close eigenvalues),
+// and are mapped back through the phases and reflectors.
+
+constexpr int kTriDim = (kMaxStages + 1) * kMaxR;  // bound on m
+constexpr int kGroup = 16;                         // lanes per eigenvalue in the multisection
+
+struct TriShared {
+  double d[kTriDim], e2[kTriDim], ae[kTriDim], beta[kTriDim];
+  double2 e[kTriDim], ph[kTriDim], p[kTriDim];
+  double lam[kMaxR];
+  double glo, ghi, tnorm;
+};
+
+// packed lower triangle, column-major: element (i, j), i >= j
+__device__ inline int pl(int i, int j, int m) { return j * m - (j * (j - 1)) / 2 + (i - j); }
+__device__ inline double2 lget(const double2 *A, int i, int j, int m) {
+  return i >= j ? A[pl(i, j, m)] : cconj(A[pl(j, i, m)]);
+}
+
+__device__ inline double wave_sum_d(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+__device__ inline int sturm_count(const TriShared &ts, int m, double s, double pivmin) {
+  double q = ts.d[0] - s;
+  int c = q < 0.0;
+  for (int i = 1; i < m; ++i) {
+    if (fabs(q) < pivmin) q = -pivmin;
+    q = (ts.d[i] - s) - ts.e2[i - 1] / q;
+    c += q < 0.0;
+  }
+  return c;
+}
+
+// u (rows_out x r, ld ldu) <- eigenvectors of the r largest eigenvalues of A,
+// descending.  scr: >= 4 * m * SL doubles (SL = 16 for r <= 16, else 32), used
+// for the inverse-iteration LU and the back-transform.
+__device__ void eig_top(double2 *A, int m, int r, double2 *u, int ldu, int rows_out, double *scr, bool lds,
+                        TriShared &ts) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // ---- Householder tridiagonalisation
+  for (int k = 0; k + 2 < m; ++k) {
+    if (wave == 0) {
+      double s2 = 0;
+      for (int i = k + 1 + lane; i < m; i += 64) s2 += cabs2(A[pl(i, k, m)]);
+      s2 = wave_sum_d(s2);
+      if (lane == 0) {
+        const double2 x0 = A[pl(k + 1, k, m)];
+        const double nx = sqrt(s2), ax0 = sqrt(cabs2(x0));
+        if (nx == 0.0) {
+          ts.beta[k] = 0.0;
+          ts.e[k] = make_double2(0, 0);
+        } else {
+          const double2 ph = ax0 > 0 ? cscale(1.0 / ax0, x0) : make_double2(1, 0);
+          const double2 alpha = cscale(-nx, ph);
+          const double2 v0 = csub(x0, alpha);
+          const double vv = s2 - ax0 * ax0 + cabs2(v0);
+          ts.beta[k] = 2.0 / vv;
+          ts.e[k] = alpha;
+          A[pl(k + 1, k, m)] = v0;
+        }
+      }
+    }
+    if (lds) lds_barrier(); else __syncthreads();
+    const double beta = ts.beta[k];
+    if (beta != 0.0) {
+      // p = beta A22 v, eight lanes per row
+      const int g = threadIdx.x >> 3, sub = threadIdx.x & 7;
+      for (int i = k + 1 + g; i < m; i += NT / 8) {
+        double sr = 0, si = 0;
+        for (int j = k + 1 + sub; j < m; j += 8) {
+          const double2 a = lget(A, i, j, m), v = A[pl(j, k, m)];
+          sr += a.x * v.x - a.y * v.y;
+          si += a.x * v.y + a.y * v.x;
+        }
+        for (int off = 4; off > 0; off >>= 1) {
+          sr += __shfl_xor(sr, off);
+          si += __shfl_xor(si, off);
+        }
+        if (sub == 0) ts.p[i] = make_double2(beta * sr, beta * si);
+      }
+      if (lds) lds_barrier(); else __syncthreads();
+      // K = (beta/2) v^H p, redundantly per wave; w = p - K v
+      double kr = 0, ki = 0;
+      for (int i = k + 1 + lane; i < m; i += 64) {
+        const double2 t = cmulc(A[pl(i, k, m)], ts.p[i]);
+        kr += t.x;
+        ki += t.y;
+      }
+      kr = wave_sum_d(kr);
+      ki = wave_sum_d(ki);
+      const double2 K = make_double2(0.5 * beta * kr, 0.5 * beta * ki);
+      // lower triangle of the trailing block: A_ij -= v_i conj(w_j) + w_i conj(v_j)
+      const int n2 = m - k - 1;
+      for (int e = threadIdx.x; e < n2 * n2; e += NT) {
+        const int i = k + 1 + e / n2, j = k + 1 + e % n2;
+        if (i < j) continue;
+        const double2 vi = A[pl(i, k, m)], vj = A[pl(j, k, m)];
+        const double2 wi = csub(ts.p[i], cmul(K, vi)), wj = csub(ts.p[j], cmul(K, vj));
+        const int q = pl(i, j, m);
+        A[q] = csub(A[q], cadd(cmul(vi, cconj(wj)), cmul(wi, cconj(vj))));
+      }
+      if (lds) lds_barrier(); else __syncthreads();
+    }
+  }
+  // ---- real tridiagonal: d, |e|, phases
+  if (threadIdx.x == 0) {
+    if (m >= 2) ts.e[m - 2] = A[pl(m - 1, m - 2, m)];
+    double2 ph = make_double2(1, 0);
+    double lo = 1e300, hi = -1e300;
+    for (int i = 0; i < m; ++i) {
+      ts.d[i] = A[pl(i, i, m)].x;
+      ts.ph[i] = ph;
+      if (i + 1 < m) {
+        const double a = sqrt(cabs2(ts.e[i]));
+        ts.ae[i] = a;
+        ts.e2[i] = a * a;
+        if (a > 0) ph = cmul(ph, cscale(1.0 / a, ts.e[i]));
+      }
+    }
+    for (int i = 0; i < m; ++i) {
+      const double rad = (i > 0 ? ts.ae[i - 1] : 0.0) + (i + 1 < m ? ts.ae[i] : 0.0);
+      lo = fmin(lo, ts.d[i] - rad);
+      hi = fmax(hi, ts.d[i] + rad);
+    }
+    const double tn = fmax(fabs(lo), fabs(hi));
+    ts.tnorm = tn > 0 ? tn : 1.0;
+    ts.glo = lo - 1e-14 * ts.tnorm;
+    ts.ghi = hi + 1e-14 * ts.tnorm;
+  }
+  __syncthreads();
+  // ---- multisection: kGroup lanes per eigenvalue, all within one wave
+  {
+    const int k = threadIdx.x / kGroup, t = threadIdx.x % kGroup;
+    const double pivmin = 1e-290;
+    if (k < r) {
+      double a = ts.glo, b = ts.ghi;
+      const int target = m - 1 - k;
+      for (int round = 0; round < 14; ++round) {
+        const double x = a + (b - a) * (double)(t + 1) / (double)(kGroup + 1);
+        const bool ok = sturm_count(ts, m, x, pivmin) <= target;  // lambda_target >= x
+        double na = ok ? x : -1e300, nb = ok ? 1e300 : x;
+        for (int off = kGroup / 2; off > 0; off >>= 1) {
+          na = fmax(na, __shfl_xor(na, off));
+          nb = fmin(nb, __shfl_xor(nb, off));
+        }
+        if (na > -1e300) a = na;
+        if (nb < 1e300) b = nb;
+      }
+      if (t == 0) ts.lam[k] = 0.5 * (a + b);
+    }
+  }
+  __syncthreads();
+  // ---- inverse iteration (wave 0, lane k < r), interleaved per-lane arrays
+  const int SL = r <= 16 ? 16 : 32;
+  double *U0 = scr, *U1 = scr + m * SL, *U2 = scr + 2 * m * SL, *X = scr + 3 * m * SL;
+  if (wave == 0) {
+    const int k = lane;
+    const bool act = k < r;
+    const double lam = act ? ts.lam[k] : 0.0;
+    const double tiny = 1e-15 * ts.tnorm;
+    if (act)
+      for (int i = 0; i < m; ++i) X[i * SL + k] = 1.0 + 0.25 * (double)((7 * i + 3 * k) % 11);
+    for (int it = 0; it < 3; ++it) {
+      if (act) {
+        double u0 = ts.d[0] - lam, u1 = m > 1 ? ts.ae[0] : 0.0, u2 = 0.0;
+        double rc = X[0 * SL + k];
+        for (int i = 0; i + 1 < m; ++i) {
+          const double an = ts.ae[i], bn = ts.d[i + 1] - lam, cn = (i + 2 < m) ? ts.ae[i + 1] : 0.0;
+          const double rn = X[(i + 1) * SL + k];
+          if (fabs(u0) >= fabs(an)) {
+            const double piv = u0 != 0.0 ? u0 : tiny;
+            const double f = an / piv;
+            U0[i * SL + k] = piv; U1[i * SL + k] = u1; U2[i * SL + k] = u2;
+            X[i * SL + k] = rc;
+            const double nu0 = bn - f * u1, nu1 = cn - f * u2;
+            rc = rn - f * rc;
+            u0 = nu0; u1 = nu1; u2 = 0.0;
+          } else {
+            const double f = u0 / an;
+            U0[i * SL + k] = an; U1[i * SL + k] = bn; U2[i * SL + k] = cn;
+            X[i * SL + k] = rn;
+            const double nu0 = u1 - f * bn, nu1 = u2 - f * cn;
+            rc = rc - f * rn;
+            u0 = nu0; u1 = nu1; u2 = 0.0;
+          }
+        }
+        U0[(m - 1) * SL + k] = u0 != 0.0 ? u0 : tiny;
+        X[(m - 1) * SL + k] = rc;
+        double x2 = 0.0, x1 = X[(m - 1) * SL + k] / U0[(m - 1) * SL + k];
+        X[(m - 1) * SL + k] = x1;
+        double nrm = x1 * x1;
+        for (int i = m - 2; i >= 0; --i) {
+          const double xi = (X[i * SL + k] - U1[i * SL + k] * x1 - U2[i * SL + k] * x2) / U0[i * SL + k];
+          X[i * SL + k] = xi;
+          nrm += xi * xi;
+          x2 = x1;
+          x1 = xi;
+        }
+        const double inv = 1.0 / sqrt(nrm);
+        for (int i = 0; i < m; ++i) X[i * SL + k] *= inv;
+      }
+      // modified Gram-Schmidt within clusters of close eigenvalues (whole wave)
+      for (int kk = 1; kk < r; ++kk) {
+        bool any = false;
+        for (int j = 0; j < kk; ++j) {
+          if (fabs(ts.lam[kk] - ts.lam[j]) >= 1e-3 * ts.tnorm) continue;
+          any = true;
+          double dt = 0;
+          for (int i = lane; i < m; i += 64) dt += X[i * SL + kk] * X[i * SL + j];
+          dt = wave_sum_d(dt);
+          for (int i = lane; i < m; i += 64) X[i * SL + kk] -= dt * X[i * SL + j];
+        }
+        if (any) {
+          double nn = 0;
+          for (int i = lane; i < m; i += 64) nn += X[i * SL + kk] * X[i * SL + kk];
+          nn = wave_sum_d(nn);
+          const double inv = 1.0 / sqrt(nn);
+          for (int i = lane; i < m; i += 64) X[i * SL + kk] *= inv;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // ---- back-transform: Y = Q (ph o X); columns are independent, one wave each
+  double2 *Y = reinterpret_cast<double2 *>(scr);  // m x r over U0/U1 (dead); X is the last quarter
+  for (int e = threadIdx.x; e < m * r; e += NT) {
+    const int i = e / r, c = e % r;
+    Y[e] = cscale(X[i * SL + c], ts.ph[i]);
+  }
+  __syncthreads();
+  for (int c = wave; c < r; c += NW) {
+    for (int k = m - 3; k >= 0; --k) {
+      const double beta = ts.beta[k];
+      if (beta == 0.0) continue;
+      double sr = 0, si = 0;
+      for (int i = k + 1 + lane; i < m; i += 64) {
+        const double2 t = cmulc(A[pl(i, k, m)], Y[i * r + c]);
+        sr += t.x;
+        si += t.y;
+      }
+      sr = wave_sum_d(sr);
+      si = wave_sum_d(si);
+      const double2 dt = make_double2(beta * sr, beta * si);
+      for (int i = k + 1 + lane; i < m; i += 64) Y[i * r + c] = csub(Y[i * r + c], cmul(A[pl(i, k, m)], dt));
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < rows_out * r; e += NT) {
+    const int i = e / r, c = e % r;
+    u[i * ldu + c] = i < m ? Y[i * r + c] : make_double2(0, 0);
+  }
+  __syncthreads();
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(NT) void k_small_rk(SmallRkParams p, SmallWs ws) {
-  extern __shared__ __align__(16) double2 s_mat[];
+  extern __shared__ __align__(16) double2 s_arena[];
   __shared__ JacobiShared js;
-  __shared__ double2 s_red[NT];
-  __shared__ double2 s_vec[kMaxDim];
+  __shared__ TriShared ts;
+  __shared__ double2 s_vec[4 * kMaxR];
   __shared__ double s_beta[kMaxR];
-  __shared__ int s_drop[kMaxDim];
-  __shared__ double s_minpiv;
+  __shared__ unsigned char s_drop[kTriDim];
+  __shared__ double s_minpiv, s_dev;
   __shared__ int s_ndrop;
-  __shared__ double s_alpha;
 
   const int r = p.r, s = p.s, nb = p.nblocks, D = nb * r, rr = r * r;
   double2 *G = ws.gamma, *R = ws.R, *Ri = ws.Rinv;
   double2 *y = ws.work;                 // D x r
   double2 *t1 = y + D * r;              // D x r
-  double2 *Uh = t1 + D * r;             // D x r Householder vectors
+  double2 *Uh = t1 + D * r;             // D x r Householder vectors (global fallback)
   double2 *Yc = Uh + D * r;             // D x r
-  double2 *Vj = Yc + D * r;             // D x D Jacobi rotations
+  double2 *Vj = Yc + D * r;             // D x D Jacobi rotations (global fallback)
   double2 *Kg = Vj + D * D;             // D x D stage matrix (global fallback)
   double2 *X11 = Kg + D * D;            // r x r
   double2 *Gr = X11 + rr;               // r x r
   double2 *tmp = Gr + rr;               // r x r
   double2 *Lw = tmp + rr;               // r x r Lowdin factor
   double *stats = ws.stats;
+  const int arena = p.lds_elems;
+  // phase timers (100 MHz real-time counter), summed into stats[16..23]
+  __shared__ uint64_t s_tmark;
+  __shared__ double s_tacc[8];
+  if (threadIdx.x == 0) {
+    s_tmark = now_ticks();
+    for (int k = 0; k < 8; ++k) s_tacc[k] = 0.0;
+  }
+  auto lap = [&](int slot) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const uint64_t t = now_ticks();
+      s_tacc[slot] += (double)(t - s_tmark);
+      s_tmark = t;
+    }
+  };
 
   // ---- 1. Gram matrix of the Chebyshev blocks --------------------------------
+  // pass 0 measured P0*P0, P0*P1, P1*P1; pass j >= 1 measured P_j*P_{j+1}, P_{j+1}*P_{j+1}
   auto gblk = [&](int bi, int bj) { return G + (bi * r) * D + bj * r; };
   for (int e = threadIdx.x; e < D * D; e += NT) G[e] = make_double2(0, 0);
   __syncthreads();
@@ -282,141 +596,144 @@ __global__ __launch_bounds__(NT) void k_small_rk(SmallRkParams p, SmallWs ws) {
   put(0, 1, ws.meas + 1 * rr);
   put(1, 1, ws.meas + 2 * rr);
   for (int j = 1; j < s; ++j) {
-    put(j - 1, j + 1, ws.meas + (3 * j + 0) * rr);
-    put(j, j + 1, ws.meas + (3 * j + 1) * rr);
-    put(j + 1, j + 1, ws.meas + (3 * j + 2) * rr);
+    put(j, j + 1, ws.meas + (3 * j + 0) * rr);
+    put(j + 1, j + 1, ws.meas + (3 * j + 1) * rr);
   }
   __syncthreads();
+  // symmetrise the measured diagonal blocks before they enter the recurrence
+  for (int e = threadIdx.x; e < (s + 1) * rr; e += NT) {
+    const int bi = e / rr, a = (e % rr) / r, b = e % r;
+    double2 *M = gblk(bi, bi);
+    if (a < b) {
+      const double2 x1 = M[a * D + b], x2 = M[b * D + a];
+      const double2 hh = make_double2(0.5 * (x1.x + x2.x), 0.5 * (x1.y - x2.y));
+      M[a * D + b] = hh;
+      M[b * D + a] = cconj(hh);
+    } else if (a == b) {
+      M[a * D + a].y = 0.0;
+    }
+  }
+  __syncthreads();
+  auto gget = [&](int bi, int bj, int a, int b) {  // any block, via Hermitian symmetry
+    return bi <= bj ? gblk(bi, bj)[a * D + b] : cconj(gblk(bj, bi)[b * D + a]);
+  };
   for (int j = 1; j < s; ++j) {
-    // Gamma_{i, j+1} for i <= j-2 from P_{j+1} = 2 H~ P_j - P_{j-1}
-    for (int e = threadIdx.x; e < (j - 1) * rr; e += NT) {
+    // Gamma_{i, j+1} for i <= j-1 from P_{j+1} = 2 H~ P_j - P_{j-1}
+    for (int e = threadIdx.x; e < j * rr; e += NT) {
       const int i = e / rr, a = (e % rr) / r, b = e % r;
       double2 v;
       if (i == 0)
-        v = csub(cscale(2.0, gblk(1, j)[a * D + b]), gblk(0, j - 1)[a * D + b]);
+        v = csub(cscale(2.0, gget(1, j, a, b)), gget(0, j - 1, a, b));
       else
-        v = csub(cadd(gblk(i + 1, j)[a * D + b], gblk(i - 1, j)[a * D + b]), gblk(i, j - 1)[a * D + b]);
+        v = csub(cadd(gget(i + 1, j, a, b), gget(i - 1, j, a, b)), gget(i, j - 1, a, b));
       gblk(i, j + 1)[a * D + b] = v;
     }
     __syncthreads();
   }
-  // Hermitian completion (diagonal blocks symmetrised)
   for (int e = threadIdx.x; e < D * D; e += NT) {
     const int i = e / D, j = e % D;
-    const int bi = i / r, bj = j / r;
-    if (bi > bj) G[e] = cconj(G[j * D + i]);
+    if (i / r > j / r) G[e] = cconj(G[j * D + i]);
   }
-  __syncthreads();
-  for (int e = threadIdx.x; e < D * D; e += NT) {
-    const int i = e / D, j = e % D;
-    if (i / r == j / r && i < j) {
-      const double2 a = G[e], b = G[j * D + i];
-      const double2 h = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
-      G[e] = h;
-      G[j * D + i] = cconj(h);
-    }
-  }
-  __syncthreads();
-  for (int e = threadIdx.x; e < D; e += NT) G[e * D + e].y = 0.0;
   __syncthreads();
 
+  lap(0);
   // ---- Cholesky Gamma = R^H R (R upper), dependent directions dropped -------
-  for (int e = threadIdx.x; e < D * D; e += NT) R[e] = G[e];
+  const bool chol_lds = D * D <= arena;
+  double2 *C = chol_lds ? s_arena : R;
+  for (int e = threadIdx.x; e < D * D; e += NT) C[e] = G[e];
   if (threadIdx.x == 0) {
     s_minpiv = 1.0;
     s_ndrop = 0;
   }
   __syncthreads();
   for (int k = 0; k < D; ++k) {
+    const double piv = C[k * D + k].x, orig = G[k * D + k].x;
+    const bool dropped = !(piv > 1e-13 * orig) || !(orig > 0);
     if (threadIdx.x == 0) {
-      const double piv = R[k * D + k].x, orig = G[k * D + k].x;
-      const double ratio = orig > 0 ? piv / orig : 0.0;
-      if (!(piv > 1e-13 * orig) || !(orig > 0)) {
-        s_drop[k] = 1;
+      s_drop[k] = dropped;
+      if (dropped)
         s_ndrop += 1;
-      } else {
-        s_drop[k] = 0;
-        s_minpiv = fmin(s_minpiv, ratio);
-      }
+      else
+        s_minpiv = fmin(s_minpiv, piv / orig);
     }
-    __syncthreads();
-    const bool dropped = s_drop[k];
-    const double rkk = dropped ? 1.0 : sqrt(R[k * D + k].x);
-    // row k of R
+    const double rkk = dropped ? 1.0 : sqrt(piv);
+    const int w = D - k - 1;
     for (int j = k + 1 + threadIdx.x; j < D; j += NT)
-      R[k * D + j] = dropped ? make_double2(0, 0) : cscale(1.0 / rkk, R[k * D + j]);
-    __syncthreads();
-    if (threadIdx.x == 0) R[k * D + k] = make_double2(rkk, 0.0);
-    // trailing update
-    if (!dropped) {
-      const int w = D - k - 1;
+      C[k * D + j] = dropped ? make_double2(0, 0) : cscale(1.0 / rkk, C[k * D + j]);
+    if (chol_lds) lds_barrier(); else __syncthreads();
+    if (!dropped)
       for (int e = threadIdx.x; e < w * w; e += NT) {
         const int i = k + 1 + e / w, j = k + 1 + e % w;
-        if (j >= i) R[i * D + j] = csub(R[i * D + j], cmulc(R[k * D + i], R[k * D + j]));
+        if (j >= i) C[i * D + j] = csub(C[i * D + j], cmulc(C[k * D + i], C[k * D + j]));
       }
-    }
-    __syncthreads();
+    if (threadIdx.x == 0) C[k * D + k] = make_double2(rkk, 0.0);
+    if (chol_lds) lds_barrier(); else __syncthreads();
   }
-  for (int e = threadIdx.x; e < D * D; e += NT)
-    if (e / D > e % D) R[e] = make_double2(0, 0);
+  for (int e = threadIdx.x; e < D * D; e += NT) R[e] = (e / D > e % D) ? make_double2(0, 0) : C[e];
   __syncthreads();
-  // R^{-1}: column c by back substitution (one thread per column)
+  lap(1);
+  // R^{-1} (upper): thread c owns column c and back-substitutes bottom-up;
+  // the column's own earlier results are re-read by the same thread only.
   for (int e = threadIdx.x; e < D * D; e += NT) Ri[e] = make_double2(0, 0);
   __syncthreads();
   for (int c = threadIdx.x; c < D; c += NT) {
     Ri[c * D + c] = cdiv(make_double2(1, 0), R[c * D + c]);
     for (int i = c - 1; i >= 0; --i) {
-      double2 sum = make_double2(0, 0);
-      for (int k = i + 1; k <= c; ++k) sum = cadd(sum, cmul(R[i * D + k], Ri[k * D + c]));
-      Ri[i * D + c] = cdiv(make_double2(-sum.x, -sum.y), R[i * D + i]);
+      double sr = 0, si = 0;
+#pragma unroll 8
+      for (int k = i + 1; k <= c; ++k) {
+        const double2 a = R[i * D + k], b = Ri[k * D + c];
+        sr += a.x * b.x - a.y * b.y;
+        si += a.x * b.y + a.y * b.x;
+      }
+      Ri[i * D + c] = cdiv(make_double2(-sr, -si), R[i * D + i]);
     }
   }
   __syncthreads();
 
+  lap(2);
   // ---- 2. u_1 = R[:, :r] Gamma_00^{-1/2} ------------------------------------
   double2 *u1 = ws.stage;  // stage 0, slot u
-  {
-    // Lowdin factor from Gamma_00 (r x r) by Jacobi; skip when already orthonormal
-    __shared__ double s_dev;
-    if (threadIdx.x == 0) {
-      double dev = 0;
-      for (int a = 0; a < r; ++a)
-        for (int b = 0; b < r; ++b) {
-          double2 g = G[a * D + b];
-          if (a == b) g.x -= 1.0;
-          dev = fmax(dev, sqrt(cabs2(g)));
-        }
-      s_dev = dev;
-    }
-    __syncthreads();
-    const double dev = s_dev;
-    if (threadIdx.x == 0) stats[4] = dev;
-    if (dev > 1e-14) {
-      double2 *A = s_mat;
-      for (int e = threadIdx.x; e < rr; e += NT) A[e] = G[(e / r) * D + e % r];
-      __syncthreads();
-      jacobi(A, Vj, r, 1e-16, 60, js);
-      // Lw = E diag(mu^{-1/2}) E^H
-      for (int e = threadIdx.x; e < rr; e += NT) {
-        const int a = e / r, b = e % r;
-        double2 sacc = make_double2(0, 0);
-        for (int k = 0; k < r; ++k) {
-          const double mu = A[k * r + k].x;
-          sacc = cadd(sacc, cscale(1.0 / sqrt(mu), cmul(Vj[a * r + k], cconj(Vj[b * r + k]))));
-        }
-        Lw[e] = sacc;
+  if (threadIdx.x == 0) {
+    double dev = 0;
+    for (int a = 0; a < r; ++a)
+      for (int b = 0; b < r; ++b) {
+        double2 g = G[a * D + b];
+        if (a == b) g.x -= 1.0;
+        dev = fmax(dev, sqrt(cabs2(g)));
       }
-      __syncthreads();
-      gemm_nn(u1, r, R, D, Lw, r, D, r, r);
-    } else {
-      for (int e = threadIdx.x; e < D * r; e += NT) u1[e] = R[(e / r) * D + e % r];
+    s_dev = dev;
+    stats[4] = dev;
+  }
+  __syncthreads();
+  if (s_dev > 1e-14) {
+    // Lowdin factor E diag(mu^{-1/2}) E^H of Gamma_00 by Jacobi
+    double2 *A = s_arena, *E = s_arena + rr;
+    for (int e = threadIdx.x; e < rr; e += NT) {
+      const int a = e / r, b = e % r;
+      if (a <= b) A[pk(a, b)] = G[a * D + b];
     }
     __syncthreads();
+    jacobi(A, E, r, 1e-16, 60, js, true);
+    __syncthreads();
+    for (int e = threadIdx.x; e < rr; e += NT) {
+      const int a = e / r, b = e % r;
+      double2 acc = make_double2(0, 0);
+      for (int k = 0; k < r; ++k)
+        acc = cadd(acc, cscale(1.0 / sqrt(A[pk(k, k)].x), cmul(E[a * r + k], cconj(E[b * r + k]))));
+      Lw[e] = acc;
+    }
+    __syncthreads();
+    gemm_nn(u1, r, R, D, Lw, r, D, r, r);
+  } else {
+    for (int e = threadIdx.x; e < D * r; e += NT) u1[e] = R[(e / r) * D + e % r];
   }
+  __syncthreads();
 
   // ---- 3. stages -------------------------------------------------------------
   const double h = p.h;
-  double2 *cvec = s_vec;  // c_a = phi(lam_a) in s_vec[0..r)
+  double2 *cvec = s_vec;  // c_a = phi(lam_a)
+  double2 *dots = s_vec + kMaxR;
   if (threadIdx.x < r) cvec[threadIdx.x] = phi(p.lam[threadIdx.x], p.model, p.kappa, p.hbar);
   __syncthreads();
   int total_sweeps = 0, max_sw = 0, failed = 0;
@@ -424,10 +741,10 @@ __global__ __launch_bounds__(NT) void k_small_rk(SmallRkParams p, SmallWs ws) {
     double2 *u = ws.stage + (3 * j + 0) * D * r;
     double2 *z = ws.stage + (3 * j + 1) * D * r;
     double2 *w = ws.stage + (3 * j + 2) * D * r;
-    const int mi = (j + 1) * r;           // support of u
-    const int mo = (j + 2) * r;           // support of y = H u
+    const int mi = (j + 1) * r;  // support of u
+    const int mo = (j + 2) * r;  // support of y = H u
     // y = R That R^{-1} u
-    gemm_nn(t1, r, Ri, D, u, r, mi, r, mi);  // rows >= mi of R^{-1} u vanish (upper triangular)
+    gemm_nn(t1, r, Ri, D, u, r, mi, r, mi, true);
     __syncthreads();
     for (int e = threadIdx.x; e < mo * r; e += NT) {
       const int row = e / r, col = e % r, bi = row / r, a = row % r;
@@ -437,14 +754,15 @@ __global__ __launch_bounds__(NT) void k_small_rk(SmallRkParams p, SmallWs ws) {
         v = cadd(v, cscale(coef, t1[((bi - 1) * r + a) * r + col]));
       }
       if (bi + 1 <= j) v = cadd(v, cscale(0.5 * p.halfwidth, t1[((bi + 1) * r + a) * r + col]));
-      Yc[e] = v;  // That * t1 (temporarily in Yc)
+      Yc[e] = v;  // That * t1
     }
     __syncthreads();
-    gemm_nn(y, r, R, D, Yc, r, mo, r, mo);
+    gemm_nn(y, r, R, D, Yc, r, mo, r, mo, true);
     __syncthreads();
     for (int e = threadIdx.x; e < mo * r; e += NT)
       if (s_drop[e / r]) y[e] = make_double2(0, 0);
     __syncthreads();
+    lap(3);
     // G = u^H y ; X11
     gemm_hn(Gr, r, u, r, y, r, r, r, mo);
     __syncthreads();
@@ -452,8 +770,7 @@ __global__ __launch_bounds__(NT) void k_small_rk(SmallRkParams p, SmallWs ws) {
       const int a = e / r, b = e % r;
       const double2 g1 = Gr[a * r + b], g2 = Gr[b * r + a];
       const double2 gs = make_double2(0.5 * (g1.x + g2.x), 0.5 * (g1.y - g2.y));
-      X11[e] = cmul(phi(p.lam[a] - p.lam[b], p.model, p.kappa, p.hbar), gs);
-      if (a == b) X11[e] = make_double2(0, 0);
+      X11[e] = a == b ? make_double2(0, 0) : cmul(phi(p.lam[a] - p.lam[b], p.model, p.kappa, p.hbar), gs);
     }
     if (j == 0 && threadIdx.x == 0) {
       double en = 0;
@@ -462,55 +779,55 @@ __global__ __launch_bounds__(NT) void k_small_rk(SmallRkParams p, SmallWs ws) {
     }
     __syncthreads();
     // W = Vhat X12^*  (coordinates)
-    for (int e = threadIdx.x; e < mo * r; e += NT) Yc[e] = cmul(y[e], cconj(cvec[e % r]));
-    __syncthreads();
     if (p.householder_mode == 1) {
-      // Householder vectors of u (mo x r), eq. (3.3); working copy in w
-      for (int e = threadIdx.x; e < mo * r; e += NT) w[e] = u[e];
+      // Householder vectors of u (mo x r), eq. (3.3); work arrays in LDS
+      const bool hl = 3 * mo * r <= arena;
+      double2 *Wk = hl ? s_arena : w;
+      double2 *U_ = hl ? s_arena + mo * r : Uh;
+      double2 *Y_ = hl ? s_arena + 2 * mo * r : Yc;
+      for (int e = threadIdx.x; e < mo * r; e += NT) {
+        Wk[e] = u[e];
+        Y_[e] = cmul(y[e], cconj(cvec[e % r]));
+      }
       __syncthreads();
       for (int k = 0; k < r; ++k) {
-        // norm of w[k:mo, k]
-        col_dots(s_vec + r, w + k * r + k, r, w + k * r + k, r, mo - k, 1, s_red);
-        if (threadIdx.x == 0) s_alpha = sqrt(s_vec[r].x);
-        __syncthreads();
-        const double alpha = s_alpha;
-        const double2 x0 = w[k * r + k];
+        col_dots(dots, Wk + k * r + k, r, Wk + k * r + k, r, mo - k, 1);
+        const double alpha = sqrt(dots[0].x);
+        const double2 x0 = Wk[k * r + k];
         const double ax0 = sqrt(cabs2(x0));
         const double2 ph = ax0 > 0 ? cscale(1.0 / ax0, x0) : make_double2(1, 0);
         for (int i = threadIdx.x; i < mo; i += NT) {
-          double2 v = i < k ? make_double2(0, 0) : w[i * r + k];
+          double2 v = i < k ? make_double2(0, 0) : Wk[i * r + k];
           if (i == k) v = cadd(v, cscale(alpha, ph));
-          Uh[i * r + k] = v;
+          U_[i * r + k] = v;
         }
         if (threadIdx.x == 0) s_beta[k] = alpha > 0 ? 1.0 / (alpha * alpha + alpha * ax0) : 0.0;
         __syncthreads();
-        // apply P_k to the working copy columns k+1..r-1
         if (k + 1 < r) {
-          col_dots(s_vec + r, Uh + k, r, w, r, mo, r, s_red);
+          col_dots(dots, U_ + k, r, Wk, r, mo, r);
           for (int e = threadIdx.x; e < mo * r; e += NT) {
             const int i = e / r, c = e % r;
-            if (c > k) w[e] = csub(w[e], cscale(s_beta[k], cmul(Uh[i * r + k], s_vec[r + c])));
+            if (c > k) Wk[e] = csub(Wk[e], cscale(s_beta[k], cmul(U_[i * r + k], dots[c])));
           }
           __syncthreads();
         }
       }
-      // Q^H Yc = P_r ... P_1 Yc  (P_1 first)
+      // Q^H Yc = P_r ... P_1 Yc  (P_1 first), zero the span of u, then Q (P_r first)
       for (int k = 0; k < r; ++k) {
-        col_dots(s_vec + r, Uh + k, r, Yc, r, mo, r, s_red);
+        col_dots(dots, U_ + k, r, Y_, r, mo, r);
         for (int e = threadIdx.x; e < mo * r; e += NT)
-          Yc[e] = csub(Yc[e], cscale(s_beta[k], cmul(Uh[(e / r) * r + k], s_vec[r + e % r])));
+          Y_[e] = csub(Y_[e], cscale(s_beta[k], cmul(U_[(e / r) * r + k], dots[e % r])));
         __syncthreads();
       }
-      for (int e = threadIdx.x; e < r * r; e += NT) Yc[e] = make_double2(0, 0);
+      for (int e = threadIdx.x; e < r * r; e += NT) Y_[e] = make_double2(0, 0);
       __syncthreads();
-      // W = Q [0; .] = P_1 ... P_r (.)  (P_r first)
       for (int k = r - 1; k >= 0; --k) {
-        col_dots(s_vec + r, Uh + k, r, Yc, r, mo, r, s_red);
+        col_dots(dots, U_ + k, r, Y_, r, mo, r);
         for (int e = threadIdx.x; e < mo * r; e += NT)
-          Yc[e] = csub(Yc[e], cscale(s_beta[k], cmul(Uh[(e / r) * r + k], s_vec[r + e % r])));
+          Y_[e] = csub(Y_[e], cscale(s_beta[k], cmul(U_[(e / r) * r + k], dots[e % r])));
         __syncthreads();
       }
-      for (int e = threadIdx.x; e < D * r; e += NT) w[e] = e < mo * r ? Yc[e] : make_double2(0, 0);
+      for (int e = threadIdx.x; e < D * r; e += NT) w[e] = e < mo * r ? Y_[e] : make_double2(0, 0);
     } else {
       // projector form: W = (y - u G_raw) diag(conj c)
       gemm_nn(t1, r, u, r, Gr, r, mo, r, r);
@@ -519,64 +836,68 @@ __global__ __launch_bounds__(NT) void k_small_rk(SmallRkParams p, SmallWs ws) {
         w[e] = e < mo * r ? cmul(csub(y[e], t1[e]), cconj(cvec[e % r])) : make_double2(0, 0);
     }
     __syncthreads();
+    lap(4);
     // Z = u X11 + W
     gemm_nn(z, r, u, r, X11, r, mo, r, r);
     __syncthreads();
     for (int e = threadIdx.x; e < D * r; e += NT) z[e] = e < mo * r ? cadd(z[e], w[e]) : make_double2(0, 0);
     __syncthreads();
-    // stage matrix k (mo x mo): u1 Lam u1^H + h sum coef_l (z_l u_l^H + u_l w_l^H)
+    // stage matrix k (mo x mo, full storage): u1 Lam u1^H + h sum coef_l (z_l u_l^H + u_l w_l^H)
     const bool last = (j + 1 == s);
     const int m = mo;
-    double2 *K = (m * m <= p.lds_elems) ? s_mat : Kg;
+    const int SL = r <= 16 ? 16 : 32;
+    const int npl = m * (m + 1) / 2;
+    const bool jl = (npl + 2 * m * SL <= arena);
+    double2 *K = jl ? s_arena : Kg;
+    double *scr = jl ? reinterpret_cast<double *>(s_arena + npl) : reinterpret_cast<double *>(Vj);
     for (int e = threadIdx.x; e < m * m; e += NT) {
       const int a = e / m, b = e % m;
-      double2 sacc = make_double2(0, 0);
-      for (int c = 0; c < r; ++c)
-        sacc = cadd(sacc, cscale(p.lam[c], cmul(u1[a * r + c], cconj(u1[b * r + c]))));
+      if (a < b) continue;
+      double sr = 0, si = 0;
+      for (int c = 0; c < r; ++c) {
+        const double2 x = cmul(u1[a * r + c], cconj(u1[b * r + c]));
+        sr += p.lam[c] * x.x;
+        si += p.lam[c] * x.y;
+      }
       for (int l = 0; l <= j; ++l) {
         const double coef = h * (last ? p.b[l] : p.a[j + 1][l]);
         if (coef == 0.0) continue;
         const double2 *ul = ws.stage + (3 * l + 0) * D * r;
         const double2 *zl = ws.stage + (3 * l + 1) * D * r;
         const double2 *wl = ws.stage + (3 * l + 2) * D * r;
-        double2 t = make_double2(0, 0);
-        for (int c = 0; c < r; ++c)
-          t = cadd(t, cadd(cmul(zl[a * r + c], cconj(ul[b * r + c])), cmul(ul[a * r + c], cconj(wl[b * r + c]))));
-        sacc = cadd(sacc, cscale(coef, t));
+        double tr = 0, ti = 0;
+#pragma unroll 4
+        for (int c = 0; c < r; ++c) {
+          // (z u^H + u w^H)_ab, averaged with the conjugate of its (b, a) entry
+          const double2 x1 = cadd(cmul(zl[a * r + c], cconj(ul[b * r + c])), cmul(ul[a * r + c], cconj(wl[b * r + c])));
+          const double2 x2 = cadd(cmul(zl[b * r + c], cconj(ul[a * r + c])), cmul(ul[b * r + c], cconj(wl[a * r + c])));
+          tr += 0.5 * (x1.x + x2.x);
+          ti += 0.5 * (x1.y - x2.y);
+        }
+        sr += coef * tr;
+        si += coef * ti;
       }
-      K[e] = sacc;
+      K[pl(a, b, m)] = make_double2(sr, a == b ? 0.0 : si);
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < m * m; e += NT) {
-      const int a = e / m, b = e % m;
-      if (a < b) {
-        const double2 x1 = K[e], x2 = K[b * m + a];
-        const double2 hh = make_double2(0.5 * (x1.x + x2.x), 0.5 * (x1.y - x2.y));
-        K[e] = hh;
-        K[b * m + a] = cconj(hh);
-      } else if (a == b) {
-        K[e].y = 0.0;
-      }
-    }
-    __syncthreads();
-    const int sw = jacobi(K, Vj, m, p.eig_tol, p.max_sweeps, js);
-    if (sw < 0) failed = 1;
-    total_sweeps += sw < 0 ? p.max_sweeps : sw;
-    max_sw = max(max_sw, sw < 0 ? p.max_sweeps : sw);
+    lap(5);
     double2 *unext = last ? ws.Cfin /* temporary */ : ws.stage + (3 * (j + 1) + 0) * D * r;
-    take_top(K, Vj, m, r, unext, r, D, js);
+    eig_top(K, m, r, unext, r, D, scr, jl, ts);
+    lap(6);
     if (last) {
-      // C = R^{-1} u_final
       for (int e = threadIdx.x; e < D * r; e += NT) t1[e] = ws.Cfin[e];
       __syncthreads();
-      gemm_nn(ws.Cfin, r, Ri, D, t1, r, D, r, D);
+      gemm_nn(ws.Cfin, r, Ri, D, t1, r, D, r, D, true);  // C = R^{-1} u_final
       __syncthreads();
     }
   }
+  lap(7);
+  int bad_local = 0;
+  for (int e = threadIdx.x; e < D * r; e += NT)
+    if (!isfinite(ws.Cfin[e].x) || !isfinite(ws.Cfin[e].y)) bad_local = 1;
+  const int bad = __syncthreads_or(bad_local);
   if (threadIdx.x == 0) {
-    int bad = 0;
-    for (int e = 0; e < D * r; ++e)
-      if (!isfinite(ws.Cfin[e].x) || !isfinite(ws.Cfin[e].y)) bad = 1;
+    for (int k = 0; k < 8; ++k) stats[16 + k] += s_tacc[k] * 1e-5;  // ms
     stats[0] = total_sweeps;
     stats[1] = max_sw;
     stats[2] = s_ndrop;
@@ -598,7 +919,7 @@ void launch_small_rk(const SmallRkParams &p, const SmallWs &ws, hipStream_t s) {
   static bool attr = false;
   if (!attr) {
     (void)hipFuncSetAttribute((const void *)k_small_rk, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        kSmallLdsBytes);
+                              kSmallLdsBytes);
     attr = true;
   }
   const size_t lds = (size_t)p.lds_elems * sizeof(double2);
