@@ -40,7 +40,20 @@ def parse():
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--profile-only", action="store_true",
                     help="run warmup + timed steps only (for rocprofv3 runs)")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="set up the workload and launch each kernel of a step eagerly, 20 times "
+                         "(for rocprofv3 --pmc runs)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="run a plain device-to-device copy of MIB MiB five times and exit "
+                         "(reference kernel for scaling FETCH_SIZE / WRITE_SIZE counters)")
     return ap.parse_args()
+
+
+def source_digest():
+    """Digest of the N-space kernel source; a stored traffic figure is only used while it matches."""
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2508_21200_amd", "csrc", "nspace.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
 def cpu_baseline(cfg, n_rows=1 << 17, repeats=4):
@@ -75,6 +88,15 @@ def main():
                           "requested_gpus": args.gpus}))
         sys.exit(2)
     import torch
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": nbytes, "launches": 5}))
+        return
     from paper_2508_21200_amd import Context
     from workloads import make_config
 
@@ -91,6 +113,11 @@ def main():
         return c
 
     ctx = make_ctx(precision)
+    if args.kernels_only:
+        ctx.step(model, scheme, dt, kappa, 1)  # the per-kernel launches reuse the step's buffers
+        kms = ctx.profile_kernels(model, scheme, dt, kappa, iters=20)
+        print(json.dumps({"kernels_ms": kms}))
+        return
     print(f"[bench] workload {cfg['name']} precision={precision} warmup={args.warmup} "
           f"steps={args.steps}", file=sys.stderr, flush=True)
     if args.warmup > 0:
@@ -120,7 +147,8 @@ def main():
         try:
             with open(tfile) as f:
                 t = json.load(f)
-            if t.get("precision") == precision and t.get("workload") == cfg["name"] and t.get("valid", True):
+            if (t.get("precision") == precision and t.get("workload") == cfg["name"]
+                    and t.get("source_digest") == source_digest()):
                 traffic = t.get("bytes_per_launch")
         except Exception:
             traffic = None
@@ -167,7 +195,7 @@ def main():
         "eig_stats": {k: stats[k] for k in ("eigensolves", "jacobi_sweeps", "max_sweeps_one_solve",
                                             "dropped_directions", "min_pivot_ratio", "ortho_error")},
         "projected_phase_ms_per_step": dict(zip(
-            ["gram_setup", "cholesky", "r_inverse", "h_apply", "householder", "stage_matrix", "jacobi", "tail"],
+            ["gram_setup", "cholesky", "r_inverse", "h_apply", "householder", "stage_matrix", "eigensolve", "tail"],
             [round(v / args.steps, 4) for v in stats["phase_ms"]])),
     }
     print(json.dumps(line))

@@ -61,7 +61,7 @@ typedef enum {
 /* LREI_FP64: every N-space pass in complex FP64.
  * LREI_MIXED: N-space passes (H.V, Gram products, basis combination) in
  * complex FP32 with per-tile FP32 MFMA products accumulated across tiles in
- * FP64; the projected problem (Cholesky, Householder, stage algebra, Jacobi
+ * FP64; the projected problem (Cholesky, Householder, stage algebra, partial
  * eigensolve) always runs in FP64. */
 typedef enum { LREI_FP64 = 0, LREI_MIXED = 1 } lrei_precision;
 
@@ -71,8 +71,9 @@ typedef enum { LREI_WARM_PLAIN = 0, LREI_WARM_ANALYTIC = 1, LREI_WARM_LEARNED = 
 
 typedef struct {
   int precision;          /* lrei_precision, default LREI_FP64                           */
-  double eig_tol;         /* Jacobi off-diagonal tolerance relative to max|diag|, 1e-15  */
-  int eig_max_sweeps;     /* Jacobi sweep limit per eigensolve, default 40               */
+  double eig_tol;         /* Jacobi tolerance (relative to max|diag|) of the r x r Lowdin
+                             re-orthonormalisation, default 1e-15                       */
+  int eig_max_sweeps;     /* Jacobi sweep limit of that step, default 40                 */
   int warm;               /* lrei_warm, default LREI_WARM_PLAIN                          */
   int ab_bootstrap;       /* RK scheme for the first m-1 ABm steps, default LREI_RK4     */
   int householder_mode;   /* 1: complement action through Householder reflectors (eq.
@@ -85,7 +86,7 @@ typedef struct {
 typedef struct {
   int64_t steps_done;            /* time steps completed on this context               */
   int64_t eigensolves;           /* projected eigensolves performed                    */
-  int64_t jacobi_sweeps;         /* total Jacobi sweeps                                */
+  int64_t jacobi_sweeps;         /* total Jacobi sweeps (Lowdin step)                  */
   int32_t max_sweeps_one_solve;  /* largest sweep count of one eigensolve              */
   int32_t dropped_directions;    /* Krylov directions dropped as dependent (last step)  */
   double min_pivot_ratio;        /* smallest Cholesky pivot / Gram diagonal (last step) */
@@ -96,7 +97,7 @@ typedef struct {
   int64_t warm_rejected;         /* start rotations rejected (fell back to identity)     */
   double phase_ms[8];            /* projected-step kernel time by phase over the last
                                     call: Gram/Cholesky setup, Cholesky, R^-1, H u,
-                                    Householder, stage matrix, Jacobi, tail          */
+                                    Householder, stage matrix, eigensolve, tail      */
 } lrei_stats;
 
 /* Fills *opt with the defaults listed above. */
