@@ -94,6 +94,21 @@ struct lrei_ctx {
   int64_t steps_done = 0;
   lrei_stats stats{};
 
+  // ABm history (Sec. 3.8): orthonormal basis U of the recent supports and
+  // H-images, its Gram products and the U-coordinates of the history
+  struct AbState {
+    bool valid = false;
+    int scheme = 0, m = 0, model = -1;
+    double dt = 0, kappa = 0;
+    int count = 0;   // steps of this AB run so far (start-up steps included)
+    int nU = 0;      // blocks in U
+    int npairs = 0;  // history pairs held in coordinates
+    int cur = 0;     // current U set / coordinate buffer
+  } ab;
+  DevBuf ab_U[2][2 * kMaxAb - 1];
+  DevBuf ab_coords[2], ab_UUg, ab_c1g, ab_gBg, ab_Cb, ab_Cc, ab_work, ab_partials;
+  int ab_grid = 1;
+
   // captured step graph
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -222,6 +237,200 @@ void enqueue_rk_step(lrei_ctx *ctx, int model, int scheme, double dt, double kap
   launch_combine(ctx->fp32, bl, s + 1, ctx->ws.Cfin, ctx->blocks[0].p, ctx->N, ctx->r, ctx->grid, ctx->stream);
 }
 
+// ---- ABm schemes -------------------------------------------------------------
+
+int ab_order(int scheme) { return scheme - 10; }  // LREI_AB2 = 12 -> m = 2
+
+// Allocates the AB history buffers for order m at the current rank.
+lrei_status ab_alloc(lrei_ctx *ctx, int m) {
+  const int r = ctx->r;
+  const size_t blk = (size_t)ctx->N * r * ctx->elem();
+  for (auto &set : ctx->ab_U)
+    for (int i = 0; i < 2 * m - 1; ++i)
+      if (!set[i].ensure(blk)) return ctx->fail(LREI_E_NOMEM, "device allocation of the AB history failed");
+  const int Dmax = 2 * m * r, qmax = (2 * m - 1) * r, rr = r * r;
+  const size_t coords = (size_t)(2 * m - 1) * qmax * r;
+  bool ok = ctx->ab_coords[0].ensure(coords * sizeof(double2)) && ctx->ab_coords[1].ensure(coords * sizeof(double2)) &&
+            ctx->ab_UUg.ensure((size_t)kMaxGrams * rr * sizeof(double2)) &&
+            ctx->ab_c1g.ensure((size_t)kMaxGrams * rr * sizeof(double2)) &&
+            ctx->ab_gBg.ensure((size_t)kMaxGrams * rr * sizeof(double2)) &&
+            ctx->ab_Cb.ensure((size_t)Dmax * 3 * r * sizeof(double2)) &&
+            ctx->ab_Cc.ensure((size_t)Dmax * (qmax + r) * sizeof(double2)) &&
+            ctx->ab_work.ensure(small_ab_work_elems(Dmax, qmax, r) * sizeof(double2));
+  ctx->ab_grid = blocks_grid(ctx->N);
+  ok = ok && ctx->ab_partials.ensure((size_t)kMaxGrams * rr * ctx->ab_grid * sizeof(double2));
+  if (!ok) return ctx->fail(LREI_E_NOMEM, "device allocation of the AB workspace failed");
+  return LREI_OK;
+}
+
+void ab_reset(lrei_ctx *ctx) {
+  ctx->ab = lrei_ctx::AbState{};
+}
+
+// One block pass plus the reduction of its Gram products into dst.
+void block_pass(lrei_ctx *ctx, const std::vector<const void *> &in, const std::vector<void *> &out,
+                const double2 *C, int ldc, const std::vector<std::pair<int, int>> &grams, double2 *dst) {
+  BlocksArgs a{};
+  for (size_t i = 0; i < in.size(); ++i) a.in[i] = in[i];
+  for (size_t i = 0; i < out.size(); ++i) a.out[i] = out[i];
+  a.n_in = (int)in.size();
+  a.n_out = (int)out.size();
+  a.C = C;
+  a.ldc = ldc;
+  for (size_t g = 0; g < grams.size(); ++g) {
+    a.ga[g] = (signed char)grams[g].first;
+    a.gb[g] = (signed char)grams[g].second;
+  }
+  a.n_gram = (int)grams.size();
+  a.partials = (double2 *)ctx->ab_partials.p;
+  a.N = ctx->N;
+  a.r = ctx->r;
+  a.grid = ctx->ab_grid;
+  launch_blocks(ctx->fp32, a, ctx->stream);
+  if (a.n_gram > 0) launch_reduce(a.partials, a.grid, a.n_gram * ctx->r * ctx->r, dst, ctx->stream);
+}
+
+// Orthogonalises the new blocks X against the history basis U and rotates
+// [U, Y] into the next basis (after an RK start-up step, mode 0, or as the AB
+// step itself, mode 1).
+void ab_update(lrei_ctx *ctx, const std::vector<const void *> &X, SmallAbParams p) {
+  auto &ab = ctx->ab;
+  const int r = ctx->r, nU = ab.nU, qx = (int)X.size();
+  std::vector<const void *> U;
+  for (int i = 0; i < nU; ++i) U.push_back(ctx->ab_U[ab.cur][i].p);
+  std::vector<const void *> ux = U;
+  ux.insert(ux.end(), X.begin(), X.end());
+  std::vector<const void *> Y;
+  if (nU > 0) {
+    std::vector<std::pair<int, int>> ga;
+    for (int i = 0; i < nU; ++i)
+      for (int q = 0; q < qx; ++q) ga.push_back({i, nU + q});
+    block_pass(ctx, ux, {}, nullptr, 0, ga, (double2 *)ctx->ab_c1g.p);
+    launch_ab_cgs_coef((const double2 *)ctx->ab_c1g.p, nU, qx, r, (double2 *)ctx->ab_Cb.p, ctx->stream);
+    std::vector<void *> yout;
+    for (int q = 0; q < qx; ++q) yout.push_back(ctx->blocks[2 + q].p);
+    std::vector<std::pair<int, int>> gb;
+    const int y0 = nU + qx;
+    for (int i = 0; i < nU; ++i)
+      for (int q = 0; q < qx; ++q) gb.push_back({i, y0 + q});
+    for (int q = 0; q < qx; ++q)
+      for (int q2 = q; q2 < qx; ++q2) gb.push_back({y0 + q, y0 + q2});
+    block_pass(ctx, ux, yout, (const double2 *)ctx->ab_Cb.p, qx * r, gb, (double2 *)ctx->ab_gBg.p);
+    for (auto *y : yout) Y.push_back(y);
+  } else {
+    std::vector<std::pair<int, int>> gb;
+    for (int q = 0; q < qx; ++q)
+      for (int q2 = q; q2 < qx; ++q2) gb.push_back({q, q2});
+    block_pass(ctx, X, {}, nullptr, 0, gb, (double2 *)ctx->ab_gBg.p);
+    Y = X;
+  }
+  p.nU = nU;
+  p.qx = qx;
+  p.npairs_keep = std::min(ab.npairs, ab.m - 2);
+  if (p.npairs_keep < 0) p.npairs_keep = 0;
+  const int qn = (3 + 2 * p.npairs_keep) * r, nUn = qn / r;
+  p.lds_elems = small_lds_elems((nU + qx) * r, r);
+  SmallAbWs w{};
+  w.UUg = (const double2 *)ctx->ab_UUg.p;
+  w.c1g = (const double2 *)ctx->ab_c1g.p;
+  w.gBg = (const double2 *)ctx->ab_gBg.p;
+  w.coords_in = (const double2 *)ctx->ab_coords[ab.cur].p;
+  w.coords_out = (double2 *)ctx->ab_coords[1 - ab.cur].p;
+  w.Cc = (double2 *)ctx->ab_Cc.p;
+  w.work = (double2 *)ctx->ab_work.p;
+  w.stats = (double *)ctx->stats_buf.p;
+  launch_small_ab(p, w, ctx->stream);
+  std::vector<const void *> uy = U;
+  uy.insert(uy.end(), Y.begin(), Y.end());
+  std::vector<void *> out;
+  for (int i = 0; i < nUn; ++i) out.push_back(ctx->ab_U[1 - ab.cur][i].p);
+  if (p.mode == 1) out.push_back(ctx->blocks[0].p);
+  const int b0 = nU + qx;
+  std::vector<std::pair<int, int>> gc;
+  for (int i = 0; i < nUn; ++i)
+    for (int j = i; j < nUn; ++j) gc.push_back({b0 + i, b0 + j});
+  block_pass(ctx, uy, out, (const double2 *)ctx->ab_Cc.p, qn + r, gc, (double2 *)ctx->ab_UUg.p);
+  ab.cur ^= 1;
+  ab.nU = nUn;
+  ab.npairs = p.npairs_keep + 1;
+}
+
+SmallAbParams ab_params(lrei_ctx *ctx, int mode) {
+  SmallAbParams p{};
+  const auto &ab = ctx->ab;
+  p.r = ctx->r;
+  p.m_ab = ab.m;
+  p.mode = mode;
+  p.model = ab.model;
+  p.householder_mode = ctx->opt.householder_mode;
+  p.kappa = ab.kappa;
+  p.hbar = ctx->hbar;
+  p.h = ab.dt;
+  static const double b2[2] = {3.0 / 2, -1.0 / 2}, b3[3] = {23.0 / 12, -16.0 / 12, 5.0 / 12},
+                      b4[4] = {55.0 / 24, -59.0 / 24, 37.0 / 24, -9.0 / 24};
+  const double *b = ab.m == 2 ? b2 : (ab.m == 3 ? b3 : b4);
+  for (int l = 0; l < kMaxAb; ++l) p.bcoef[l] = l < ab.m ? b[l] : 0.0;
+  for (int i = 0; i < ctx->r; ++i) p.lam[i] = ctx->lam[i];
+  return p;
+}
+
+// One step of an ABm run: an RK start-up step plus a history update while
+// fewer than m - 1 steps are done, else the AB step.
+void enqueue_ab_step(lrei_ctx *ctx) {
+  auto &ab = ctx->ab;
+  const double e = ctx->terms.gershgorin > 0 ? ctx->terms.gershgorin : 1.0;
+  if (ab.count < ab.m - 1) {
+    const int j = ab.count;
+    int bs = ctx->opt.ab_bootstrap;
+    if (!(bs >= LREI_RK1 && bs <= LREI_RK4)) bs = LREI_RK4;
+    // V_j is needed after the combine overwrote blocks[0]: keep a copy at the first step
+    if (j == 0)
+      (void)hipMemcpyAsync(ctx->ab_U[1 - ab.cur][0].p, ctx->blocks[0].p, (size_t)ctx->N * ctx->r * ctx->elem(),
+                           hipMemcpyDeviceToDevice, ctx->stream);
+    enqueue_rk_step(ctx, ab.model, bs, ab.dt, ab.kappa);
+    SmallAbParams p = ab_params(ctx, 0);
+    std::vector<const void *> X;
+    if (j == 0) {
+      // U is empty: the copy of V_0 sits in a block of the set that the rotation writes;
+      // move it to a Krylov block first (blocks[1] holds alpha H V_0, blocks[0] V_1)
+      (void)hipMemcpyAsync(ctx->blocks[4].p, ctx->ab_U[1 - ab.cur][0].p, (size_t)ctx->N * ctx->r * ctx->elem(),
+                           hipMemcpyDeviceToDevice, ctx->stream);
+      X = {ctx->blocks[4].p, ctx->blocks[1].p, ctx->blocks[0].p};
+      p.x_v0 = 0;
+      p.x_hv = 1;
+      p.x_vnew = 2;
+    } else {
+      X = {ctx->blocks[1].p, ctx->blocks[0].p};
+      p.x_v0 = -1;
+      p.x_hv = 0;
+      p.x_vnew = 1;
+    }
+    p.hv_scale = e;  // blocks[1] = (1/e) H V_j
+    ab_update(ctx, X, p);
+  } else {
+    ChebArgs a{};
+    a.Pcur = ctx->blocks[0].p;
+    a.Pnext = ctx->blocks[1].p;
+    a.off = (const DevOffTerm *)ctx->d_off.p;
+    a.diag = (const DevDiagTerm *)ctx->d_diag.p;
+    a.n_off = ctx->n_off;
+    a.n_diag = ctx->n_diag;
+    a.N = ctx->N;
+    a.r = ctx->r;
+    a.alpha = 1.0;
+    a.mode = 2;
+    a.grid = ctx->grid;
+    launch_cheb(ctx->fp32, a, ctx->stream);
+    SmallAbParams p = ab_params(ctx, 1);
+    p.x_v0 = -1;
+    p.x_hv = 0;
+    p.x_vnew = -1;
+    p.hv_scale = 1.0;
+    ab_update(ctx, {ctx->blocks[1].p}, p);
+  }
+  ab.count += 1;
+}
+
 lrei_status read_stats(lrei_ctx *ctx, double *h) {
   HIPCHK(hipMemcpyAsync(h, ctx->stats_buf.p, kStatsLen * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -294,6 +503,16 @@ void lrei_destroy(lrei_ctx *ctx) {
   ctx->lam_dev.release();
   ctx->d_off.release();
   ctx->d_diag.release();
+  for (auto &set : ctx->ab_U)
+    for (auto &b : set) b.release();
+  for (auto &b : ctx->ab_coords) b.release();
+  ctx->ab_UUg.release();
+  ctx->ab_c1g.release();
+  ctx->ab_gBg.release();
+  ctx->ab_Cb.release();
+  ctx->ab_Cc.release();
+  ctx->ab_work.release();
+  ctx->ab_partials.release();
   if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
 }
@@ -433,6 +652,7 @@ lrei_status lrei_set_rho(lrei_ctx *ctx, int r, const double *lambda, const void 
   ctx->lam.assign(lambda, lambda + r);
   ctx->have_rho = true;
   ctx->steps_done = 0;
+  ab_reset(ctx);
   ctx->drop_graph();
   return LREI_OK;
 }
@@ -441,13 +661,37 @@ lrei_status lrei_step(lrei_ctx *ctx, int model, int scheme, double dt, double ka
   if (!ctx) return LREI_E_INVALID;
   if (!ctx->have_rho) return ctx->fail(LREI_E_STATE, "set rho before stepping");
   if (model != LREI_QLL && model != LREI_QLLG) return ctx->fail(LREI_E_INVALID, "unknown model");
-  if (!(scheme >= LREI_RK1 && scheme <= LREI_RK4))
-    return ctx->fail(LREI_E_INVALID, "unsupported scheme (RK1..RK4)");
+  const bool is_ab = scheme >= LREI_AB2 && scheme <= LREI_AB4;
+  if (!(scheme >= LREI_RK1 && scheme <= LREI_RK4) && !is_ab)
+    return ctx->fail(LREI_E_INVALID, "unsupported scheme (RK1..RK4, AB2..AB4)");
   if (!(dt > 0) || !std::isfinite(dt)) return ctx->fail(LREI_E_INVALID, "dt must be positive and finite");
   if (!(kappa >= 0) || !std::isfinite(kappa)) return ctx->fail(LREI_E_INVALID, "kappa must be >= 0 and finite");
   if (n_steps < 0) return ctx->fail(LREI_E_INVALID, "n_steps must be >= 0");
+  if (is_ab) {
+    const int m = ab_order(scheme);
+    if (ctx->r > 16) return ctx->fail(LREI_E_INVALID, "AB schemes support r <= 16");
+    if ((long long)(2 * m + 2) * ctx->r > ctx->N)
+      return ctx->fail(LREI_E_INVALID, "AB schemes need N >= (2m + 2) r");
+  }
   if (n_steps == 0) return LREI_OK;
   HIPCHK(hipSetDevice(ctx->device));
+  if (is_ab) {
+    auto &ab = ctx->ab;
+    if (!(ab.valid && ab.scheme == scheme && ab.model == model && ab.dt == dt && ab.kappa == kappa)) {
+      // a new AB run: the history is rebuilt from the current state
+      ab_reset(ctx);
+      ab.scheme = scheme;
+      ab.m = ab_order(scheme);
+      ab.model = model;
+      ab.dt = dt;
+      ab.kappa = kappa;
+      lrei_status st = ab_alloc(ctx, ab.m);
+      if (st != LREI_OK) return st;
+      ab.valid = true;
+    }
+  } else {
+    ab_reset(ctx);  // an RK step moves the state outside any AB history
+  }
   const auto t0 = std::chrono::steady_clock::now();
   const size_t vbytes = (size_t)ctx->N * ctx->r * ctx->elem();
   HIPCHK(hipMemcpyAsync(ctx->save.p, ctx->blocks[0].p, vbytes, hipMemcpyDeviceToDevice, ctx->stream));
@@ -455,7 +699,9 @@ lrei_status lrei_step(lrei_ctx *ctx, int model, int scheme, double dt, double ka
   HIPCHK(hipMemcpyAsync(ctx->stats_buf.p, zeros, sizeof(zeros), hipMemcpyHostToDevice, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   const bool use_graph = ctx->opt.use_graph != 0;
-  if (use_graph) {
+  if (is_ab) {
+    for (int k = 0; k < n_steps; ++k) enqueue_ab_step(ctx);
+  } else if (use_graph) {
     if (!(ctx->exec && ctx->g_model == model && ctx->g_scheme == scheme && ctx->g_dt == dt && ctx->g_kappa == kappa)) {
       ctx->drop_graph();
       // launch attributes are set on first use, outside capture
@@ -486,6 +732,7 @@ lrei_status lrei_step(lrei_ctx *ctx, int model, int scheme, double dt, double ka
   // stats[0..8] describe the last step, stats[10..15] the whole call
   const bool failed = h[13] != 0, bad = h[14] != 0;
   if (failed || bad) {
+    ab_reset(ctx);  // the history no longer matches the restored state
     HIPCHK(hipMemcpyAsync(ctx->blocks[0].p, ctx->save.p, vbytes, hipMemcpyDeviceToDevice, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return ctx->fail(bad ? LREI_E_NUMERIC : LREI_E_NOTCONVERGED,

@@ -80,6 +80,26 @@ void launch_magnetization(bool fp32, const void *V, const double *lam, long long
                           double2 *partials, int grid, hipStream_t s);
 int nspace_grid(long long N, int r);
 
+// Generic block pass (blocks.hip): out_o = sum_i in_i C[i, o] and Gram
+// products over the listed (a, b) pairs of [inputs..., outputs...], r <= 16.
+constexpr int kMaxIoBlocks = 10;
+constexpr int kMaxGrams = 32;
+struct BlocksArgs {
+  const void *in[kMaxIoBlocks];
+  void *out[kMaxIoBlocks];
+  int n_in, n_out;
+  const double2 *C;      // row (i * r + a), column (o * r + b), leading dimension ldc
+  int ldc;
+  signed char ga[kMaxGrams], gb[kMaxGrams];
+  int n_gram;
+  double2 *partials;     // [n_gram * r * r][grid], entry-major
+  long long N;
+  int r, grid;
+};
+bool launch_blocks(bool fp32, const BlocksArgs &a, hipStream_t s);
+int blocks_grid(long long N);
+size_t blocks_lds(bool fp32, int n_blocks);
+
 // Parameters of the projected (small-space) step kernel.
 struct SmallRkParams {
   int r, s, nblocks;      // nblocks = s + 1
@@ -124,6 +144,34 @@ inline int small_lds_elems(int D, int r) {
   return need < kSmallLdsElems ? need : kSmallLdsElems;
 }
 void launch_small_rk(const SmallRkParams &p, const SmallWs &ws, hipStream_t s);
+
+// Projected AB step / history update (small.hip).
+constexpr int kMaxAb = 4;  // AB4
+struct SmallAbParams {
+  int r, m_ab;             // rank, AB order m
+  int mode;                // 0: history update after an RK start-up step, 1: AB step
+  int nU, qx;              // history basis blocks U, new blocks X (and Y)
+  int x_v0, x_hv, x_vnew;  // X block holding V_k (-1: V_k is in U), H V_k (scaled), V_{k+1} (mode 0)
+  double hv_scale;         // H V_k = hv_scale * X[x_hv]
+  int npairs_keep;         // older history pairs carried into the new basis (<= m - 2)
+  int model, householder_mode, lds_elems;
+  double kappa, hbar, h;
+  double bcoef[kMaxAb];
+  double lam[kMaxR];
+};
+struct SmallAbWs {
+  const double2 *UUg;        // Grams of the U blocks, pairs i <= j in row order, r x r each
+  const double2 *c1g;        // U_i* X_q, index i * qx + q
+  const double2 *gBg;        // U_i* Y_q (index i * qx + q), then Y_q* Y_q' (q <= q', row order)
+  const double2 *coords_in;  // U-coordinates: V_k, then (V_{k-l}, H V_{k-l}) pairs, each nU r x r
+  double2 *coords_out;       // the same for the new basis (qn x r each)
+  double2 *Cc;               // [(nU + qx) r] x [qn + r]: new U blocks, then V_{k+1}
+  double2 *work;
+  double *stats;
+};
+void launch_small_ab(const SmallAbParams &p, const SmallAbWs &ws, hipStream_t s);
+size_t small_ab_work_elems(int D, int qn, int r);
+void launch_ab_cgs_coef(const double2 *c1g, int nU, int qx, int r, double2 *C, hipStream_t s);
 int cheb_partial_splits(int r);
 
 }  // namespace lrei

@@ -37,7 +37,6 @@ namespace {
 constexpr int NT = 512;
 constexpr int NW = NT / 64;
 constexpr int kMaxPairs = kMaxR / 2 + 1;  // Jacobi is used for r x r problems only
-constexpr int kLdsJacobiMaxM = 80;  // packed A + V fit in LDS up to m = 80
 
 __device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ inline double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
@@ -252,27 +251,6 @@ __device__ int jacobi(double2 *A, double2 *V, int m, double tol, int max_sweeps,
     if (!js.rotated) return sweep + 1;
   }
   return -1;
-}
-
-// Largest-r eigenvalues of a diagonalised A (descending) -> columns of V into u.
-// Each diagonal entry's rank (ties broken by index) is computed in parallel.
-__device__ void take_top(const double2 *A, const double2 *V, int m, int r, double2 *u, int ldu, int rows_out,
-                         JacobiShared &js) {
-  for (int i = threadIdx.x; i < m; i += NT) {
-    const double v = A[pk(i, i)].x;
-    int rank = 0;
-    for (int k = 0; k < m; ++k) {
-      const double w = A[pk(k, k)].x;
-      rank += (w > v) || (w == v && k < i);
-    }
-    if (rank < r) js.order[rank] = i;
-  }
-  __syncthreads();
-  for (int e = threadIdx.x; e < rows_out * r; e += NT) {
-    const int i = e / r, k = e % r;
-    u[i * ldu + k] = i < m ? V[i * m + js.order[k]] : make_double2(0, 0);
-  }
-  __syncthreads();
 }
 
 __device__ inline uint64_t now_ticks() { return __builtin_amdgcn_s_memrealtime(); }
@@ -540,19 +518,315 @@ __device__ void eig_top(double2 *A, int m, int r, double2 *u, int ldu, int rows_
   __syncthreads();
 }
 
+// ----- pieces shared by the RK and AB projected-step kernels -------------------
+
+struct StepShared {
+  JacobiShared js;
+  TriShared ts;
+  double2 vec[4 * kMaxR];
+  double hbeta[kTriDim];
+  unsigned char drop[kTriDim];
+  double minpiv, dev;
+  int ndrop;
+};
+
+// Cholesky Gamma = R* R (R upper, D x D row-major).  A direction whose pivot
+// falls below 1e-13 of its own Gram diagonal is dependent on the earlier ones:
+// its row of R is zeroed, its pivot set to 1 and sh.drop marks it.
+__device__ void chol_drop(const double2 *G, double2 *R, int D, double2 *arena, int arena_elems, StepShared &sh) {
+  const bool in_lds = D * D <= arena_elems;
+  double2 *C = in_lds ? arena : R;
+  for (int e = threadIdx.x; e < D * D; e += NT) C[e] = G[e];
+  if (threadIdx.x == 0) {
+    sh.minpiv = 1.0;
+    sh.ndrop = 0;
+  }
+  __syncthreads();
+  for (int k = 0; k < D; ++k) {
+    const double piv = C[k * D + k].x, orig = G[k * D + k].x;
+    const bool dropped = !(piv > 1e-13 * orig) || !(orig > 0);
+    if (threadIdx.x == 0) {
+      sh.drop[k] = dropped;
+      if (dropped)
+        sh.ndrop += 1;
+      else
+        sh.minpiv = fmin(sh.minpiv, piv / orig);
+    }
+    const double rkk = dropped ? 1.0 : sqrt(piv);
+    const int w = D - k - 1;
+    for (int j = k + 1 + threadIdx.x; j < D; j += NT)
+      C[k * D + j] = dropped ? make_double2(0, 0) : cscale(1.0 / rkk, C[k * D + j]);
+    if (in_lds) lds_barrier(); else __syncthreads();
+    if (!dropped)
+      for (int e = threadIdx.x; e < w * w; e += NT) {
+        const int i = k + 1 + e / w, j = k + 1 + e % w;
+        if (j >= i) C[i * D + j] = csub(C[i * D + j], cmulc(C[k * D + i], C[k * D + j]));
+      }
+    if (threadIdx.x == 0) C[k * D + k] = make_double2(rkk, 0.0);
+    if (in_lds) lds_barrier(); else __syncthreads();
+  }
+  for (int e = threadIdx.x; e < D * D; e += NT) R[e] = (e / D > e % D) ? make_double2(0, 0) : C[e];
+  __syncthreads();
+}
+
+// Ri = R^{-1} (upper): thread c owns column c and back-substitutes bottom-up;
+// the column's own earlier results are re-read by the same thread only.
+__device__ void upper_inverse(const double2 *R, double2 *Ri, int D) {
+  for (int e = threadIdx.x; e < D * D; e += NT) Ri[e] = make_double2(0, 0);
+  __syncthreads();
+  for (int c = threadIdx.x; c < D; c += NT) {
+    Ri[c * D + c] = cdiv(make_double2(1, 0), R[c * D + c]);
+    for (int i = c - 1; i >= 0; --i) {
+      double sr = 0, si = 0;
+#pragma unroll 8
+      for (int k = i + 1; k <= c; ++k) {
+        const double2 a = R[i * D + k], b = Ri[k * D + c];
+        sr += a.x * b.x - a.y * b.y;
+        si += a.x * b.y + a.y * b.x;
+      }
+      Ri[i * D + c] = cdiv(make_double2(-sr, -si), R[i * D + i]);
+    }
+  }
+  __syncthreads();
+}
+
+// u (m x r) <- u (u* u)^{-1/2} when max|u* u - I| > 1e-14 (Lowdin), by an r x r
+// Jacobi eigendecomposition.  S, Lw, T: r x r, r x r, m x r scratch (global);
+// the packed Jacobi matrices use the LDS arena (>= 2 r^2 elements).
+__device__ void lowdin(double2 *u, int m, int r, double2 *S, double2 *Lw, double2 *T, double2 *arena,
+                       StepShared &sh) {
+  const int rr = r * r;
+  gemm_hn(S, r, u, r, u, r, r, r, m);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double dev = 0;
+    for (int a = 0; a < r; ++a)
+      for (int b = 0; b < r; ++b) {
+        double2 g = S[a * r + b];
+        if (a == b) g.x -= 1.0;
+        dev = fmax(dev, sqrt(cabs2(g)));
+      }
+    sh.dev = dev;
+  }
+  __syncthreads();
+  if (!(sh.dev > 1e-14)) return;
+  double2 *A = arena, *E = arena + rr;
+  for (int e = threadIdx.x; e < rr; e += NT) {
+    const int a = e / r, b = e % r;
+    if (a <= b) {
+      const double2 x1 = S[a * r + b], x2 = S[b * r + a];
+      A[pk(a, b)] = a == b ? make_double2(x1.x, 0.0) : make_double2(0.5 * (x1.x + x2.x), 0.5 * (x1.y - x2.y));
+    }
+  }
+  __syncthreads();
+  jacobi(A, E, r, 1e-16, 60, sh.js, true);
+  __syncthreads();
+  for (int e = threadIdx.x; e < rr; e += NT) {
+    const int a = e / r, b = e % r;
+    double2 acc = make_double2(0, 0);
+    for (int k = 0; k < r; ++k)
+      acc = cadd(acc, cscale(1.0 / sqrt(A[pk(k, k)].x), cmul(E[a * r + k], cconj(E[b * r + k]))));
+    Lw[e] = acc;
+  }
+  for (int e = threadIdx.x; e < m * r; e += NT) T[e] = u[e];
+  __syncthreads();
+  gemm_nn(u, r, T, r, Lw, r, m, r, r);
+  __syncthreads();
+}
+
+struct ModelCoef {
+  int model;
+  double kappa, hbar;
+  const double *lam;
+};
+
+// Right-hand side f(rho) = z u* + u w* in coordinates (eqs. 3.2 / 4.1, 3.3-3.5):
+// u (m x r, orthonormal columns) are the coordinates of V, y those of H V;
+// G = u* y (symmetrised), X11 = Phi o G, c = phi(lam), w = (I - u u*) y diag(conj c)
+// through the r Householder reflectors of u (hmode 1) or the projector (hmode 0),
+// z = u X11 + w.  z, w are written with D rows (rows >= m zero).
+// Scratch: Gr, X11 (r x r), t1, Uh, Yc (m x r, global); LDS arena >= 3 m r
+// elements keeps the reflector work in LDS.  *energy (if set) = sum lam_a G_aa.
+__device__ void rhs_coords(const double2 *u, const double2 *y, int m, int D, int r, const ModelCoef &mc, int hmode,
+                           double2 *z, double2 *w, double2 *Gr, double2 *X11, double2 *t1, double2 *Uh,
+                           double2 *Yc, double2 *arena, int arena_elems, StepShared &sh, double *energy) {
+  const int rr = r * r;
+  double2 *cvec = sh.vec;  // c_a = phi(lam_a)
+  double2 *dots = sh.vec + kMaxR;
+  if (threadIdx.x < r) cvec[threadIdx.x] = phi(mc.lam[threadIdx.x], mc.model, mc.kappa, mc.hbar);
+  gemm_hn(Gr, r, u, r, y, r, r, r, m);
+  __syncthreads();
+  for (int e = threadIdx.x; e < rr; e += NT) {
+    const int a = e / r, b = e % r;
+    const double2 g1 = Gr[a * r + b], g2 = Gr[b * r + a];
+    const double2 gs = make_double2(0.5 * (g1.x + g2.x), 0.5 * (g1.y - g2.y));
+    X11[e] = a == b ? make_double2(0, 0) : cmul(phi(mc.lam[a] - mc.lam[b], mc.model, mc.kappa, mc.hbar), gs);
+  }
+  if (energy && threadIdx.x == 0) {
+    double en = 0;
+    for (int a = 0; a < r; ++a) en += mc.lam[a] * Gr[a * r + a].x;
+    *energy = en;
+  }
+  __syncthreads();
+  if (hmode == 1) {
+    // Householder vectors of u (m x r), eq. (3.3); work arrays in LDS when they fit
+    const bool hl = 3 * m * r <= arena_elems;
+    double2 *Wk = hl ? arena : w;
+    double2 *U_ = hl ? arena + m * r : Uh;
+    double2 *Y_ = hl ? arena + 2 * m * r : Yc;
+    for (int e = threadIdx.x; e < m * r; e += NT) {
+      Wk[e] = u[e];
+      Y_[e] = cmul(y[e], cconj(cvec[e % r]));
+    }
+    __syncthreads();
+    for (int k = 0; k < r; ++k) {
+      col_dots(dots, Wk + k * r + k, r, Wk + k * r + k, r, m - k, 1);
+      const double alpha = sqrt(dots[0].x);
+      const double2 x0 = Wk[k * r + k];
+      const double ax0 = sqrt(cabs2(x0));
+      const double2 ph = ax0 > 0 ? cscale(1.0 / ax0, x0) : make_double2(1, 0);
+      for (int i = threadIdx.x; i < m; i += NT) {
+        double2 v = i < k ? make_double2(0, 0) : Wk[i * r + k];
+        if (i == k) v = cadd(v, cscale(alpha, ph));
+        U_[i * r + k] = v;
+      }
+      if (threadIdx.x == 0) sh.hbeta[k] = alpha > 0 ? 1.0 / (alpha * alpha + alpha * ax0) : 0.0;
+      __syncthreads();
+      if (k + 1 < r) {
+        col_dots(dots, U_ + k, r, Wk, r, m, r);
+        for (int e = threadIdx.x; e < m * r; e += NT) {
+          const int i = e / r, c = e % r;
+          if (c > k) Wk[e] = csub(Wk[e], cscale(sh.hbeta[k], cmul(U_[i * r + k], dots[c])));
+        }
+        __syncthreads();
+      }
+    }
+    // Q^H Y = P_r ... P_1 Y (P_1 first), zero the span of u, then Q (P_r first)
+    for (int k = 0; k < r; ++k) {
+      col_dots(dots, U_ + k, r, Y_, r, m, r);
+      for (int e = threadIdx.x; e < m * r; e += NT)
+        Y_[e] = csub(Y_[e], cscale(sh.hbeta[k], cmul(U_[(e / r) * r + k], dots[e % r])));
+      __syncthreads();
+    }
+    for (int e = threadIdx.x; e < rr; e += NT) Y_[e] = make_double2(0, 0);
+    __syncthreads();
+    for (int k = r - 1; k >= 0; --k) {
+      col_dots(dots, U_ + k, r, Y_, r, m, r);
+      for (int e = threadIdx.x; e < m * r; e += NT)
+        Y_[e] = csub(Y_[e], cscale(sh.hbeta[k], cmul(U_[(e / r) * r + k], dots[e % r])));
+      __syncthreads();
+    }
+    for (int e = threadIdx.x; e < D * r; e += NT) w[e] = e < m * r ? Y_[e] : make_double2(0, 0);
+  } else {
+    // projector form: W = (y - u G_raw) diag(conj c)
+    gemm_nn(t1, r, u, r, Gr, r, m, r, r);
+    __syncthreads();
+    for (int e = threadIdx.x; e < D * r; e += NT)
+      w[e] = e < m * r ? cmul(csub(y[e], t1[e]), cconj(cvec[e % r])) : make_double2(0, 0);
+  }
+  __syncthreads();
+  gemm_nn(z, r, u, r, X11, r, m, r, r);
+  __syncthreads();
+  for (int e = threadIdx.x; e < D * r; e += NT) z[e] = e < m * r ? cadd(z[e], w[e]) : make_double2(0, 0);
+  __syncthreads();
+}
+
+// Packed (lower, column-major) Hermitian stage matrix of order m:
+// K = u1 diag(lam) u1* + sum_l coef_l (z_l u_l* + u_l w_l*)   (eqs. 3.7-3.9),
+// each term averaged with its adjoint so that K is Hermitian to the last bit.
+constexpr int kMaxTerms = 4;
+__device__ void stage_matrix(double2 *K, int m, int r, const double2 *u1, const double *lam, int nterm,
+                             const double2 *const *ul_, const double2 *const *zl_, const double2 *const *wl_,
+                             const double *coef) {
+  for (int e = threadIdx.x; e < m * m; e += NT) {
+    const int a = e / m, b = e % m;
+    if (a < b) continue;
+    double sr = 0, si = 0;
+    for (int c = 0; c < r; ++c) {
+      const double2 x = cmul(u1[a * r + c], cconj(u1[b * r + c]));
+      sr += lam[c] * x.x;
+      si += lam[c] * x.y;
+    }
+    for (int l = 0; l < nterm; ++l) {
+      if (coef[l] == 0.0) continue;
+      const double2 *ul = ul_[l], *zl = zl_[l], *wl = wl_[l];
+      double tr = 0, ti = 0;
+#pragma unroll 4
+      for (int c = 0; c < r; ++c) {
+        const double2 x1 = cadd(cmul(zl[a * r + c], cconj(ul[b * r + c])), cmul(ul[a * r + c], cconj(wl[b * r + c])));
+        const double2 x2 = cadd(cmul(zl[b * r + c], cconj(ul[a * r + c])), cmul(ul[b * r + c], cconj(wl[a * r + c])));
+        tr += 0.5 * (x1.x + x2.x);
+        ti += 0.5 * (x1.y - x2.y);
+      }
+      sr += coef[l] * tr;
+      si += coef[l] * ti;
+    }
+    K[pl(a, b, m)] = make_double2(sr, a == b ? 0.0 : si);
+  }
+  __syncthreads();
+}
+
+// Householder QR of M (m x q, row-major ld q, overwritten), m >= q:
+// Q (m x q, orthonormal columns, explicit) and Rm (q x q upper) with M = Q Rm.
+// Vh (m x q) holds the reflector vectors.
+__device__ void householder_qr(double2 *M, int m, int q, double2 *Q, double2 *Rm, double2 *Vh, StepShared &sh) {
+  double2 *dots = sh.vec;  // >= q entries needed: use Q's last row block as scratch when q > 4 r
+  for (int e = threadIdx.x; e < m * q; e += NT) Vh[e] = make_double2(0, 0);
+  __syncthreads();
+  for (int k = 0; k < q; ++k) {
+    col_dots(Rm + k * q + k, M + k * q + k, q, M + k * q + k, q, m - k, 1);  // |x|^2 parked in Rm
+    const double alpha = sqrt(Rm[k * q + k].x);
+    const double2 x0 = M[k * q + k];
+    const double ax0 = sqrt(cabs2(x0));
+    const double2 ph = ax0 > 0 ? cscale(1.0 / ax0, x0) : make_double2(1, 0);
+    for (int i = k + threadIdx.x; i < m; i += NT) {
+      double2 v = M[i * q + k];
+      if (i == k) v = cadd(v, cscale(alpha, ph));
+      Vh[i * q + k] = v;
+    }
+    if (threadIdx.x == 0) sh.hbeta[k] = alpha > 0 ? 1.0 / (alpha * alpha + alpha * ax0) : 0.0;
+    __syncthreads();
+    // columns c > k: M[:, c] -= beta v (v* M[:, c]); column k becomes -ph alpha e_k
+    for (int c = k + 1 + (threadIdx.x >> 6); c < q; c += NW) {
+      const int lane = threadIdx.x & 63;
+      double2 s = make_double2(0, 0);
+      for (int i = k + lane; i < m; i += 64) s = cadd(s, cmulc(Vh[i * q + k], M[i * q + c]));
+      s = wave_sum(s);
+      const double2 f = cscale(sh.hbeta[k], s);
+      for (int i = k + lane; i < m; i += 64) M[i * q + c] = csub(M[i * q + c], cmul(Vh[i * q + k], f));
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) M[k * q + k] = cscale(-alpha, ph);
+    for (int i = k + 1 + threadIdx.x; i < m; i += NT) M[i * q + k] = make_double2(0, 0);
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < q * q; e += NT) Rm[e] = (e / q > e % q) ? make_double2(0, 0) : M[e];
+  // Q = P_0 ... P_{q-1} [I; 0], reflectors applied last-first
+  for (int e = threadIdx.x; e < m * q; e += NT) Q[e] = make_double2((e / q) == (e % q) ? 1.0 : 0.0, 0.0);
+  __syncthreads();
+  (void)dots;
+  for (int k = q - 1; k >= 0; --k) {
+    for (int c = k + (threadIdx.x >> 6); c < q; c += NW) {
+      const int lane = threadIdx.x & 63;
+      double2 s = make_double2(0, 0);
+      for (int i = k + lane; i < m; i += 64) s = cadd(s, cmulc(Vh[i * q + k], Q[i * q + c]));
+      s = wave_sum(s);
+      const double2 f = cscale(sh.hbeta[k], s);
+      for (int i = k + lane; i < m; i += 64) Q[i * q + c] = csub(Q[i * q + c], cmul(Vh[i * q + k], f));
+    }
+    __syncthreads();
+  }
+}
+
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// LREI-RK projected step
 // ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(NT) void k_small_rk(SmallRkParams p, SmallWs ws) {
   extern __shared__ __align__(16) double2 s_arena[];
-  __shared__ JacobiShared js;
-  __shared__ TriShared ts;
-  __shared__ double2 s_vec[4 * kMaxR];
-  __shared__ double s_beta[kMaxR];
-  __shared__ unsigned char s_drop[kTriDim];
-  __shared__ double s_minpiv, s_dev;
-  __shared__ int s_ndrop;
+  __shared__ StepShared sh;
 
   const int r = p.r, s = p.s, nb = p.nblocks, D = nb * r, rr = r * r;
   double2 *G = ws.gamma, *R = ws.R, *Ri = ws.Rinv;
@@ -560,7 +834,7 @@ __global__ __launch_bounds__(NT) void k_small_rk(SmallRkParams p, SmallWs ws) {
   double2 *t1 = y + D * r;              // D x r
   double2 *Uh = t1 + D * r;             // D x r Householder vectors (global fallback)
   double2 *Yc = Uh + D * r;             // D x r
-  double2 *Vj = Yc + D * r;             // D x D Jacobi rotations (global fallback)
+  double2 *Vj = Yc + D * r;             // D x D eigensolver scratch (global fallback)
   double2 *Kg = Vj + D * D;             // D x D stage matrix (global fallback)
   double2 *X11 = Kg + D * D;            // r x r
   double2 *Gr = X11 + rr;               // r x r
@@ -637,106 +911,20 @@ __global__ __launch_bounds__(NT) void k_small_rk(SmallRkParams p, SmallWs ws) {
   __syncthreads();
 
   lap(0);
-  // ---- Cholesky Gamma = R^H R (R upper), dependent directions dropped -------
-  const bool chol_lds = D * D <= arena;
-  double2 *C = chol_lds ? s_arena : R;
-  for (int e = threadIdx.x; e < D * D; e += NT) C[e] = G[e];
-  if (threadIdx.x == 0) {
-    s_minpiv = 1.0;
-    s_ndrop = 0;
-  }
-  __syncthreads();
-  for (int k = 0; k < D; ++k) {
-    const double piv = C[k * D + k].x, orig = G[k * D + k].x;
-    const bool dropped = !(piv > 1e-13 * orig) || !(orig > 0);
-    if (threadIdx.x == 0) {
-      s_drop[k] = dropped;
-      if (dropped)
-        s_ndrop += 1;
-      else
-        s_minpiv = fmin(s_minpiv, piv / orig);
-    }
-    const double rkk = dropped ? 1.0 : sqrt(piv);
-    const int w = D - k - 1;
-    for (int j = k + 1 + threadIdx.x; j < D; j += NT)
-      C[k * D + j] = dropped ? make_double2(0, 0) : cscale(1.0 / rkk, C[k * D + j]);
-    if (chol_lds) lds_barrier(); else __syncthreads();
-    if (!dropped)
-      for (int e = threadIdx.x; e < w * w; e += NT) {
-        const int i = k + 1 + e / w, j = k + 1 + e % w;
-        if (j >= i) C[i * D + j] = csub(C[i * D + j], cmulc(C[k * D + i], C[k * D + j]));
-      }
-    if (threadIdx.x == 0) C[k * D + k] = make_double2(rkk, 0.0);
-    if (chol_lds) lds_barrier(); else __syncthreads();
-  }
-  for (int e = threadIdx.x; e < D * D; e += NT) R[e] = (e / D > e % D) ? make_double2(0, 0) : C[e];
-  __syncthreads();
+  chol_drop(G, R, D, s_arena, arena, sh);
   lap(1);
-  // R^{-1} (upper): thread c owns column c and back-substitutes bottom-up;
-  // the column's own earlier results are re-read by the same thread only.
-  for (int e = threadIdx.x; e < D * D; e += NT) Ri[e] = make_double2(0, 0);
-  __syncthreads();
-  for (int c = threadIdx.x; c < D; c += NT) {
-    Ri[c * D + c] = cdiv(make_double2(1, 0), R[c * D + c]);
-    for (int i = c - 1; i >= 0; --i) {
-      double sr = 0, si = 0;
-#pragma unroll 8
-      for (int k = i + 1; k <= c; ++k) {
-        const double2 a = R[i * D + k], b = Ri[k * D + c];
-        sr += a.x * b.x - a.y * b.y;
-        si += a.x * b.y + a.y * b.x;
-      }
-      Ri[i * D + c] = cdiv(make_double2(-sr, -si), R[i * D + i]);
-    }
-  }
-  __syncthreads();
-
+  upper_inverse(R, Ri, D);
   lap(2);
-  // ---- 2. u_1 = R[:, :r] Gamma_00^{-1/2} ------------------------------------
+  // ---- 2. u_1 = R[:, :r] (Lowdin re-orthonormalised) ---------------------------
   double2 *u1 = ws.stage;  // stage 0, slot u
-  if (threadIdx.x == 0) {
-    double dev = 0;
-    for (int a = 0; a < r; ++a)
-      for (int b = 0; b < r; ++b) {
-        double2 g = G[a * D + b];
-        if (a == b) g.x -= 1.0;
-        dev = fmax(dev, sqrt(cabs2(g)));
-      }
-    s_dev = dev;
-    stats[4] = dev;
-  }
+  for (int e = threadIdx.x; e < D * r; e += NT) u1[e] = R[(e / r) * D + e % r];
   __syncthreads();
-  if (s_dev > 1e-14) {
-    // Lowdin factor E diag(mu^{-1/2}) E^H of Gamma_00 by Jacobi
-    double2 *A = s_arena, *E = s_arena + rr;
-    for (int e = threadIdx.x; e < rr; e += NT) {
-      const int a = e / r, b = e % r;
-      if (a <= b) A[pk(a, b)] = G[a * D + b];
-    }
-    __syncthreads();
-    jacobi(A, E, r, 1e-16, 60, js, true);
-    __syncthreads();
-    for (int e = threadIdx.x; e < rr; e += NT) {
-      const int a = e / r, b = e % r;
-      double2 acc = make_double2(0, 0);
-      for (int k = 0; k < r; ++k)
-        acc = cadd(acc, cscale(1.0 / sqrt(A[pk(k, k)].x), cmul(E[a * r + k], cconj(E[b * r + k]))));
-      Lw[e] = acc;
-    }
-    __syncthreads();
-    gemm_nn(u1, r, R, D, Lw, r, D, r, r);
-  } else {
-    for (int e = threadIdx.x; e < D * r; e += NT) u1[e] = R[(e / r) * D + e % r];
-  }
-  __syncthreads();
+  lowdin(u1, D, r, tmp, Lw, t1, s_arena, sh);
+  if (threadIdx.x == 0) stats[4] = sh.dev;
 
   // ---- 3. stages -------------------------------------------------------------
   const double h = p.h;
-  double2 *cvec = s_vec;  // c_a = phi(lam_a)
-  double2 *dots = s_vec + kMaxR;
-  if (threadIdx.x < r) cvec[threadIdx.x] = phi(p.lam[threadIdx.x], p.model, p.kappa, p.hbar);
-  __syncthreads();
-  int total_sweeps = 0, max_sw = 0, failed = 0;
+  const ModelCoef mc{p.model, p.kappa, p.hbar, p.lam};
   for (int j = 0; j < s; ++j) {
     double2 *u = ws.stage + (3 * j + 0) * D * r;
     double2 *z = ws.stage + (3 * j + 1) * D * r;
@@ -760,89 +948,13 @@ __global__ __launch_bounds__(NT) void k_small_rk(SmallRkParams p, SmallWs ws) {
     gemm_nn(y, r, R, D, Yc, r, mo, r, mo, true);
     __syncthreads();
     for (int e = threadIdx.x; e < mo * r; e += NT)
-      if (s_drop[e / r]) y[e] = make_double2(0, 0);
+      if (sh.drop[e / r]) y[e] = make_double2(0, 0);
     __syncthreads();
     lap(3);
-    // G = u^H y ; X11
-    gemm_hn(Gr, r, u, r, y, r, r, r, mo);
-    __syncthreads();
-    for (int e = threadIdx.x; e < rr; e += NT) {
-      const int a = e / r, b = e % r;
-      const double2 g1 = Gr[a * r + b], g2 = Gr[b * r + a];
-      const double2 gs = make_double2(0.5 * (g1.x + g2.x), 0.5 * (g1.y - g2.y));
-      X11[e] = a == b ? make_double2(0, 0) : cmul(phi(p.lam[a] - p.lam[b], p.model, p.kappa, p.hbar), gs);
-    }
-    if (j == 0 && threadIdx.x == 0) {
-      double en = 0;
-      for (int a = 0; a < r; ++a) en += p.lam[a] * Gr[a * r + a].x;
-      stats[5] = en;
-    }
-    __syncthreads();
-    // W = Vhat X12^*  (coordinates)
-    if (p.householder_mode == 1) {
-      // Householder vectors of u (mo x r), eq. (3.3); work arrays in LDS
-      const bool hl = 3 * mo * r <= arena;
-      double2 *Wk = hl ? s_arena : w;
-      double2 *U_ = hl ? s_arena + mo * r : Uh;
-      double2 *Y_ = hl ? s_arena + 2 * mo * r : Yc;
-      for (int e = threadIdx.x; e < mo * r; e += NT) {
-        Wk[e] = u[e];
-        Y_[e] = cmul(y[e], cconj(cvec[e % r]));
-      }
-      __syncthreads();
-      for (int k = 0; k < r; ++k) {
-        col_dots(dots, Wk + k * r + k, r, Wk + k * r + k, r, mo - k, 1);
-        const double alpha = sqrt(dots[0].x);
-        const double2 x0 = Wk[k * r + k];
-        const double ax0 = sqrt(cabs2(x0));
-        const double2 ph = ax0 > 0 ? cscale(1.0 / ax0, x0) : make_double2(1, 0);
-        for (int i = threadIdx.x; i < mo; i += NT) {
-          double2 v = i < k ? make_double2(0, 0) : Wk[i * r + k];
-          if (i == k) v = cadd(v, cscale(alpha, ph));
-          U_[i * r + k] = v;
-        }
-        if (threadIdx.x == 0) s_beta[k] = alpha > 0 ? 1.0 / (alpha * alpha + alpha * ax0) : 0.0;
-        __syncthreads();
-        if (k + 1 < r) {
-          col_dots(dots, U_ + k, r, Wk, r, mo, r);
-          for (int e = threadIdx.x; e < mo * r; e += NT) {
-            const int i = e / r, c = e % r;
-            if (c > k) Wk[e] = csub(Wk[e], cscale(s_beta[k], cmul(U_[i * r + k], dots[c])));
-          }
-          __syncthreads();
-        }
-      }
-      // Q^H Yc = P_r ... P_1 Yc  (P_1 first), zero the span of u, then Q (P_r first)
-      for (int k = 0; k < r; ++k) {
-        col_dots(dots, U_ + k, r, Y_, r, mo, r);
-        for (int e = threadIdx.x; e < mo * r; e += NT)
-          Y_[e] = csub(Y_[e], cscale(s_beta[k], cmul(U_[(e / r) * r + k], dots[e % r])));
-        __syncthreads();
-      }
-      for (int e = threadIdx.x; e < r * r; e += NT) Y_[e] = make_double2(0, 0);
-      __syncthreads();
-      for (int k = r - 1; k >= 0; --k) {
-        col_dots(dots, U_ + k, r, Y_, r, mo, r);
-        for (int e = threadIdx.x; e < mo * r; e += NT)
-          Y_[e] = csub(Y_[e], cscale(s_beta[k], cmul(U_[(e / r) * r + k], dots[e % r])));
-        __syncthreads();
-      }
-      for (int e = threadIdx.x; e < D * r; e += NT) w[e] = e < mo * r ? Y_[e] : make_double2(0, 0);
-    } else {
-      // projector form: W = (y - u G_raw) diag(conj c)
-      gemm_nn(t1, r, u, r, Gr, r, mo, r, r);
-      __syncthreads();
-      for (int e = threadIdx.x; e < D * r; e += NT)
-        w[e] = e < mo * r ? cmul(csub(y[e], t1[e]), cconj(cvec[e % r])) : make_double2(0, 0);
-    }
-    __syncthreads();
+    rhs_coords(u, y, mo, D, r, mc, p.householder_mode, z, w, Gr, X11, t1, Uh, Yc, s_arena, arena, sh,
+               j == 0 ? &stats[5] : nullptr);
     lap(4);
-    // Z = u X11 + W
-    gemm_nn(z, r, u, r, X11, r, mo, r, r);
-    __syncthreads();
-    for (int e = threadIdx.x; e < D * r; e += NT) z[e] = e < mo * r ? cadd(z[e], w[e]) : make_double2(0, 0);
-    __syncthreads();
-    // stage matrix k (mo x mo, full storage): u1 Lam u1^H + h sum coef_l (z_l u_l^H + u_l w_l^H)
+    // stage matrix (eqs. 3.7-3.9) and its top-r eigenvectors
     const bool last = (j + 1 == s);
     const int m = mo;
     const int SL = r <= 16 ? 16 : 32;
@@ -850,39 +962,18 @@ __global__ __launch_bounds__(NT) void k_small_rk(SmallRkParams p, SmallWs ws) {
     const bool jl = (npl + 2 * m * SL <= arena);
     double2 *K = jl ? s_arena : Kg;
     double *scr = jl ? reinterpret_cast<double *>(s_arena + npl) : reinterpret_cast<double *>(Vj);
-    for (int e = threadIdx.x; e < m * m; e += NT) {
-      const int a = e / m, b = e % m;
-      if (a < b) continue;
-      double sr = 0, si = 0;
-      for (int c = 0; c < r; ++c) {
-        const double2 x = cmul(u1[a * r + c], cconj(u1[b * r + c]));
-        sr += p.lam[c] * x.x;
-        si += p.lam[c] * x.y;
-      }
-      for (int l = 0; l <= j; ++l) {
-        const double coef = h * (last ? p.b[l] : p.a[j + 1][l]);
-        if (coef == 0.0) continue;
-        const double2 *ul = ws.stage + (3 * l + 0) * D * r;
-        const double2 *zl = ws.stage + (3 * l + 1) * D * r;
-        const double2 *wl = ws.stage + (3 * l + 2) * D * r;
-        double tr = 0, ti = 0;
-#pragma unroll 4
-        for (int c = 0; c < r; ++c) {
-          // (z u^H + u w^H)_ab, averaged with the conjugate of its (b, a) entry
-          const double2 x1 = cadd(cmul(zl[a * r + c], cconj(ul[b * r + c])), cmul(ul[a * r + c], cconj(wl[b * r + c])));
-          const double2 x2 = cadd(cmul(zl[b * r + c], cconj(ul[a * r + c])), cmul(ul[b * r + c], cconj(wl[a * r + c])));
-          tr += 0.5 * (x1.x + x2.x);
-          ti += 0.5 * (x1.y - x2.y);
-        }
-        sr += coef * tr;
-        si += coef * ti;
-      }
-      K[pl(a, b, m)] = make_double2(sr, a == b ? 0.0 : si);
+    const double2 *ul[kMaxTerms], *zl[kMaxTerms], *wl[kMaxTerms];
+    double coef[kMaxTerms];
+    for (int l = 0; l <= j; ++l) {
+      ul[l] = ws.stage + (3 * l + 0) * D * r;
+      zl[l] = ws.stage + (3 * l + 1) * D * r;
+      wl[l] = ws.stage + (3 * l + 2) * D * r;
+      coef[l] = h * (last ? p.b[l] : p.a[j + 1][l]);
     }
-    __syncthreads();
+    stage_matrix(K, m, r, u1, p.lam, j + 1, ul, zl, wl, coef);
     lap(5);
     double2 *unext = last ? ws.Cfin /* temporary */ : ws.stage + (3 * (j + 1) + 0) * D * r;
-    eig_top(K, m, r, unext, r, D, scr, jl, ts);
+    eig_top(K, m, r, unext, r, D, scr, jl, sh.ts);
     lap(6);
     if (last) {
       for (int e = threadIdx.x; e < D * r; e += NT) t1[e] = ws.Cfin[e];
@@ -898,18 +989,15 @@ __global__ __launch_bounds__(NT) void k_small_rk(SmallRkParams p, SmallWs ws) {
   const int bad = __syncthreads_or(bad_local);
   if (threadIdx.x == 0) {
     for (int k = 0; k < 8; ++k) stats[16 + k] += s_tacc[k] * 1e-5;  // ms
-    stats[0] = total_sweeps;
-    stats[1] = max_sw;
-    stats[2] = s_ndrop;
-    stats[3] = s_minpiv;
-    stats[6] = failed;
+    stats[0] = 0;
+    stats[1] = 0;
+    stats[2] = sh.ndrop;
+    stats[3] = sh.minpiv;
+    stats[6] = 0;
     stats[7] = bad;
     stats[8] = s;  // eigensolves this step
     // running totals over the steps of one call (zeroed by the host per call)
-    stats[10] += total_sweeps;
     stats[11] += s;
-    stats[12] = fmax(stats[12], (double)max_sw);
-    stats[13] += failed;
     stats[14] += bad;
     stats[15] += 1;
   }
@@ -924,6 +1012,254 @@ void launch_small_rk(const SmallRkParams &p, const SmallWs &ws, hipStream_t s) {
   }
   const size_t lds = (size_t)p.lds_elems * sizeof(double2);
   hipLaunchKernelGGL(k_small_rk, dim3(1), dim3(NT), lds, s, p, ws);
+}
+
+// ---------------------------------------------------------------------------
+// LREI-AB projected step and history update
+//
+// The history of an ABm run, f(rho_{k-l}) for l = 1..m-1 (Sec. 3.8), needs the
+// supports V_{k-l} and H V_{k-l}.  Those blocks are nearly dependent (V_{k-1}
+// differs from V_k by O(dt)), so they are kept as an orthonormal basis U of
+// span{V_k, V_{k-l}, H V_{k-l}} in N-space together with their coordinates in
+// U.  One step: X = H V_k (or, after an RK start-up step, X = [H V_j, V_{j+1}]
+// and at the very first step also V_j) is orthogonalised against U in N-space,
+// Y = X - U (U* X), with the products U* Y, Y* Y measured again; the basis
+// B = [U, Y] then has a well-conditioned Gram matrix [[U*U, U*Y], [Y*U, Y*Y]].
+// In its orthonormal coordinates this kernel forms the AB stage matrix
+// rho_k + dt sum_l b_l f(rho_{k-l}), its top-r eigenvectors (spectrum reset to
+// Lambda_0), and a new orthonormal history basis for the next step by a
+// Householder QR of the coordinates of [V_{k+1}, V_k, H V_k, older pairs];
+// the N-space rotation U_new = B T and V_{k+1} = B C run in the block pass.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(NT) void k_small_ab(SmallAbParams p, SmallAbWs ws) {
+  extern __shared__ __align__(16) double2 s_arena[];
+  __shared__ StepShared sh;
+  const int r = p.r, rr = r * r, nU = p.nU, qx = p.qx, DU = nU * r, D = DU + qx * r;
+  const int npk = p.npairs_keep, qn = (3 + 2 * npk) * r, ldc = qn + r;
+  const int arena = p.lds_elems;
+  double2 *G = ws.work;                 // D x D
+  double2 *R = G + D * D;               // D x D
+  double2 *Ri = R + D * D;              // D x D
+  double2 *Mq = Ri + D * D;             // D x qn
+  double2 *Qm = Mq + D * qn;            // D x qn
+  double2 *Vh = Qm + D * qn;            // D x qn
+  double2 *Rm = Vh + D * qn;            // qn x qn
+  double2 *cu = Rm + qn * qn;           // [kMaxAb][2] x (D x r): u_l, y_l
+  double2 *cz = cu + 2 * kMaxAb * D * r;  // [kMaxAb][2] x (D x r): z_l, w_l
+  double2 *unew = cz + 2 * kMaxAb * D * r;  // D x r
+  double2 *t1 = unew + D * r, *Uh = t1 + D * r, *Yc = Uh + D * r;  // D x r each
+  double2 *Kg = Yc + D * r;             // D x D
+  double2 *Sg = Kg + D * D;             // D x D scratch (eigensolver, global fallback)
+  double2 *X11 = Sg + D * D, *Gr = X11 + rr, *tmp = Gr + rr, *Lw = tmp + rr;
+  double *stats = ws.stats;
+
+  // ---- Gram of B = [U, Y] from the measured products
+  for (int e = threadIdx.x; e < D * D; e += NT) {
+    const int i = e / D, j = e % D;
+    const int bi = i / r, bj = j / r, a = i % r, b = j % r;
+    double2 v;
+    if (bi < nU && bj < nU) {
+      const int lo = bi < bj ? bi : bj, hi = bi < bj ? bj : bi;
+      const int g = lo * nU - lo * (lo - 1) / 2 + (hi - lo);
+      v = bi <= bj ? ws.UUg[(g * r + a) * r + b] : cconj(ws.UUg[(g * r + b) * r + a]);
+    } else if (bi < nU || bj < nU) {
+      const int ui = bi < nU ? bi : bj, yq = (bi < nU ? bj : bi) - nU;
+      const int g = ui * qx + yq;
+      v = bi < nU ? ws.gBg[(g * r + a) * r + b] : cconj(ws.gBg[(g * r + b) * r + a]);
+    } else {
+      const int q1 = bi - nU, q2 = bj - nU;
+      const int lo = q1 < q2 ? q1 : q2, hi = q1 < q2 ? q2 : q1;
+      const int g = nU * qx + lo * qx - lo * (lo - 1) / 2 + (hi - lo);
+      v = q1 <= q2 ? ws.gBg[(g * r + a) * r + b] : cconj(ws.gBg[(g * r + b) * r + a]);
+    }
+    G[e] = v;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < D * D; e += NT) {  // exact Hermitian symmetry
+    const int i = e / D, j = e % D;
+    if (i < j) {
+      const double2 x1 = G[e], x2 = G[j * D + i];
+      const double2 hh = make_double2(0.5 * (x1.x + x2.x), 0.5 * (x1.y - x2.y));
+      G[e] = hh;
+      G[j * D + i] = cconj(hh);
+    } else if (i == j) {
+      G[e].y = 0.0;
+    }
+  }
+  __syncthreads();
+  chol_drop(G, R, D, s_arena, arena, sh);
+  upper_inverse(R, Ri, D);
+
+  // ---- coordinates in the orthonormal basis B R^{-1}
+  // of a vector held as U-coordinates x (DU x r): R[:, :DU] x
+  auto coord_u = [&](double2 *out, const double2 *x) {
+    for (int e = threadIdx.x; e < D * r; e += NT) {
+      const int i = e / r, c = e % r;
+      double sr = 0, si = 0;
+      if (!sh.drop[i])
+        for (int k = i; k < DU; ++k) {
+          const double2 a = R[i * D + k], b = x[k * r + c];
+          sr += a.x * b.x - a.y * b.y;
+          si += a.x * b.y + a.y * b.x;
+        }
+      out[e] = make_double2(sr, si);
+    }
+    __syncthreads();
+  };
+  // of X block q = U c1_q + Y_q: R[:, :DU] c1_q + R[:, DU + q r + (0..r)], times scale
+  auto coord_x = [&](double2 *out, int q, double scale) {
+    for (int e = threadIdx.x; e < D * r; e += NT) {
+      const int i = e / r, c = e % r;
+      double sr = 0, si = 0;
+      if (!sh.drop[i]) {
+        for (int k = i; k < DU; ++k) {
+          const int ui = k / r, a = k % r;
+          const double2 cc = ws.c1g[((ui * qx + q) * r + a) * r + c];
+          const double2 rv = R[i * D + k];
+          sr += rv.x * cc.x - rv.y * cc.y;
+          si += rv.x * cc.y + rv.y * cc.x;
+        }
+        const int col = DU + q * r + c;
+        if (col >= i) {
+          sr += R[i * D + col].x;
+          si += R[i * D + col].y;
+        }
+      }
+      out[e] = make_double2(scale * sr, scale * si);
+    }
+    __syncthreads();
+  };
+  double2 *u0 = cu, *y0 = cu + D * r;
+  const double2 *vc_in = ws.coords_in;
+  if (p.x_v0 >= 0) coord_x(u0, p.x_v0, 1.0); else coord_u(u0, vc_in);
+  coord_x(y0, p.x_hv, p.hv_scale);
+  const ModelCoef mc{p.model, p.kappa, p.hbar, p.lam};
+  if (p.mode == 1) {
+    lowdin(u0, D, r, tmp, Lw, t1, s_arena, sh);
+    if (threadIdx.x == 0) stats[4] = sh.dev;
+    const int m = p.m_ab;
+    for (int l = 1; l < m; ++l) {
+      coord_u(cu + (2 * l) * D * r, vc_in + (1 + 2 * (l - 1)) * DU * r);
+      coord_u(cu + (2 * l + 1) * D * r, vc_in + (2 + 2 * (l - 1)) * DU * r);
+    }
+    const double2 *ul[kMaxTerms], *zl[kMaxTerms], *wl[kMaxTerms];
+    double coef[kMaxTerms];
+    for (int l = 0; l < m; ++l) {
+      rhs_coords(cu + (2 * l) * D * r, cu + (2 * l + 1) * D * r, D, D, r, mc, p.householder_mode,
+                 cz + (2 * l) * D * r, cz + (2 * l + 1) * D * r, Gr, X11, t1, Uh, Yc, s_arena, arena, sh,
+                 l == 0 ? &stats[5] : nullptr);
+      ul[l] = cu + (2 * l) * D * r;
+      zl[l] = cz + (2 * l) * D * r;
+      wl[l] = cz + (2 * l + 1) * D * r;
+      coef[l] = p.h * p.bcoef[l];
+    }
+    const int SL = r <= 16 ? 16 : 32;
+    const int npl = D * (D + 1) / 2;
+    const bool jl = (npl + 2 * D * SL <= arena);
+    double2 *K = jl ? s_arena : Kg;
+    double *scr = jl ? reinterpret_cast<double *>(s_arena + npl) : reinterpret_cast<double *>(Sg);
+    stage_matrix(K, D, r, u0, p.lam, m, ul, zl, wl, coef);
+    eig_top(K, D, r, unew, r, D, scr, jl, sh.ts);
+  } else {
+    coord_x(unew, p.x_vnew, 1.0);
+  }
+  // ---- new history basis: Householder QR of [V_{k+1}, V_k, H V_k, pairs 1..npk]
+  for (int e = threadIdx.x; e < D * qn; e += NT) {
+    const int i = e / qn, col = e % qn, blk = col / r, c = col % r;
+    double2 v;
+    if (blk == 0) v = unew[i * r + c];
+    else if (blk == 1) v = u0[i * r + c];
+    else if (blk == 2) v = y0[i * r + c];
+    else {
+      const int l = (blk - 3) / 2 + 1, which = (blk - 3) % 2;
+      v = p.mode == 1 ? cu[(2 * l + which) * D * r + i * r + c] : make_double2(0, 0);
+    }
+    Mq[e] = v;
+  }
+  __syncthreads();
+  if (p.mode == 0 && npk > 0) {
+    // bootstrap: older pairs come straight from their U-coordinates
+    for (int l = 1; l <= npk; ++l)
+      for (int which = 0; which < 2; ++which) {
+        coord_u(t1, vc_in + (1 + 2 * (l - 1) + which) * DU * r);
+        const int blk = 3 + 2 * (l - 1) + which;
+        for (int e = threadIdx.x; e < D * r; e += NT) Mq[(e / r) * qn + blk * r + e % r] = t1[e];
+        __syncthreads();
+      }
+  }
+  householder_qr(Mq, D, qn, Qm, Rm, Vh, sh);
+  // ---- outputs: T = R^{-1} Q (new U), C = R^{-1} u_new (new V), coordinates = Rm
+  for (int e = threadIdx.x; e < D * ldc; e += NT) {
+    const int i = e / ldc, col = e % ldc;
+    double sr = 0, si = 0;
+    if (col < qn || p.mode == 1)
+      for (int k = i; k < D; ++k) {
+        const double2 a = Ri[i * D + k];
+        const double2 b = col < qn ? Qm[k * qn + col] : unew[k * r + (col - qn)];
+        if (sh.drop[k]) continue;
+        sr += a.x * b.x - a.y * b.y;
+        si += a.x * b.y + a.y * b.x;
+      }
+    ws.Cc[e] = make_double2(sr, si);
+  }
+  for (int e = threadIdx.x; e < (1 + 2 * (npk + 1)) * qn * r; e += NT) {
+    const int slot = e / (qn * r), rem = e % (qn * r), i = rem / r, c = rem % r;
+    ws.coords_out[e] = Rm[i * qn + slot * r + c];
+  }
+  __syncthreads();
+  int bad_local = 0;
+  for (int e = threadIdx.x; e < D * ldc; e += NT)
+    if (!isfinite(ws.Cc[e].x) || !isfinite(ws.Cc[e].y)) bad_local = 1;
+  const int bad = __syncthreads_or(bad_local);
+  if (threadIdx.x == 0) {
+    stats[2] = sh.ndrop;
+    stats[3] = sh.minpiv;
+    stats[7] = bad;
+    stats[14] += bad;
+    if (p.mode == 1) {
+      stats[8] = 1;
+      stats[11] += 1;
+      stats[15] += 1;
+    }
+  }
+}
+
+void launch_small_ab(const SmallAbParams &p, const SmallAbWs &ws, hipStream_t s) {
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void *)k_small_ab, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              kSmallLdsBytes);
+    attr = true;
+  }
+  hipLaunchKernelGGL(k_small_ab, dim3(1), dim3(NT), (size_t)p.lds_elems * sizeof(double2), s, p, ws);
+}
+
+size_t small_ab_work_elems(int D, int qn, int r) {
+  return 5 * (size_t)D * D + 3 * (size_t)D * qn + (size_t)qn * qn + 4 * (size_t)kMaxAb * D * r + 4 * (size_t)D * r +
+         4 * (size_t)r * r;
+}
+
+// Gram-Schmidt coefficients of the block pass: rows [U blocks..., X blocks...],
+// columns the Y blocks: C = [-c1; I] with c1_q = U* X_q.
+__global__ void k_ab_cgs_coef(const double2 *c1g, int nU, int qx, int r, double2 *C) {
+  const int DU = nU * r, D = DU + qx * r, ldc = qx * r;
+  for (int e = threadIdx.x + blockIdx.x * blockDim.x; e < D * ldc; e += blockDim.x * gridDim.x) {
+    const int i = e / ldc, col = e % ldc;
+    double2 v;
+    if (i < DU) {
+      const int ui = i / r, a = i % r, q = col / r, c = col % r;
+      const double2 g = c1g[((ui * qx + q) * r + a) * r + c];
+      v = make_double2(-g.x, -g.y);
+    } else {
+      v = make_double2(i - DU == col ? 1.0 : 0.0, 0.0);
+    }
+    C[e] = v;
+  }
+}
+
+void launch_ab_cgs_coef(const double2 *c1g, int nU, int qx, int r, double2 *C, hipStream_t s) {
+  hipLaunchKernelGGL(k_ab_cgs_coef, dim3(4), dim3(256), 0, s, c1g, nU, qx, r, C);
 }
 
 }  // namespace lrei

@@ -223,3 +223,118 @@ def test_full_size_hv_sampled_rows():
     rows = np.concatenate([rows, [0, 1, 2 ** 20 - 1]])
     Yo = apply_H_rows(cfg["n"], cfg["bonds"], cfg["J"], cfg["h"], cfg["V"], rows)
     assert np.abs(Y[rows] - Yo).max() < 1e-13 * np.abs(Yo).max()
+
+
+# ---- Adams-Bashforth schemes (Sec. 3.8) -------------------------------------
+
+@pytest.mark.parametrize("scheme", ["AB2", "AB3", "AB4"])
+@pytest.mark.parametrize("model", ["qLL", "qLLG"])
+def test_ab_steps_fp64(scheme, model):
+    """RK4 start-up, then AB steps with the orthonormal history basis, against the oracle."""
+    n, r, steps = 8, 4, 8
+    rng = np.random.default_rng(11 * n + r + len(scheme))
+    bonds, J, h = _random_model(n, rng)
+    V = haar_factor(2 ** n, r, rng)
+    lam = dirichlet_spectrum(r, rng)
+    ctx = _ctx()
+    ctx.set_hamiltonian(n, bonds, J, h)
+    ctx.set_rho(lam, V)
+    ctx.step(model, scheme, 0.01, 0.3, steps)
+    _, Vg = ctx.get_rho()
+    H = Hamiltonian(n, bonds, J, h)
+    Vo = oracle_run(H, V, lam, model, 0.3, 0.01, steps, scheme)
+    err = rel_fro_error(Vg, lam, Vo, lam)
+    print(f"{model} {scheme} n={n} r={r} {steps} steps: rel_fro_error={err:.3e} stats={ctx.stats()}")
+    assert err < 1e-11
+
+
+@pytest.mark.parametrize("householder_mode", [0, 1])
+def test_ab_split_calls_and_modes(householder_mode):
+    """An AB run split over calls equals one call (bitwise); both complement forms agree with the oracle."""
+    cfg = make_config(2, n=9, r=6)
+    out = []
+    for split in ((9,), (2, 3, 4)):
+        ctx = _ctx(householder_mode=householder_mode)
+        ctx.set_hamiltonian(cfg["n"], cfg["bonds"], cfg["J"], cfg["h"])
+        ctx.set_rho(cfg["lam"], cfg["V"])
+        for k in split:
+            ctx.step("qLLG", "AB3", 0.005, 0.05, k)
+        out.append(ctx.get_rho()[1])
+    assert np.array_equal(out[0], out[1])
+    H = Hamiltonian(cfg["n"], cfg["bonds"], cfg["J"], cfg["h"])
+    Vo = oracle_run(H, cfg["V"], cfg["lam"], "qLLG", 0.05, 0.005, 9, "AB3")
+    assert rel_fro_error(out[0], cfg["lam"], Vo, cfg["lam"]) < 1e-11
+
+
+def test_ab_restarts_when_dt_changes():
+    """Changing dt starts a new AB run (new RK start-up) from the current state, as the oracle does."""
+    cfg = make_config(2, n=8, r=4)
+    ctx = _ctx()
+    ctx.set_hamiltonian(cfg["n"], cfg["bonds"], cfg["J"], cfg["h"])
+    ctx.set_rho(cfg["lam"], cfg["V"])
+    ctx.step("qLL", "AB2", 0.01, 0.2, 4)
+    ctx.step("qLL", "AB2", 0.005, 0.2, 3)
+    _, Vg = ctx.get_rho()
+    H = Hamiltonian(cfg["n"], cfg["bonds"], cfg["J"], cfg["h"])
+    Vo = oracle_run(H, cfg["V"], cfg["lam"], "qLL", 0.2, 0.01, 4, "AB2")
+    Vo = oracle_run(H, Vo, cfg["lam"], "qLL", 0.2, 0.005, 3, "AB2")
+    assert rel_fro_error(Vg, cfg["lam"], Vo, cfg["lam"]) < 1e-11
+
+
+def test_ab_rejects_unsupported_sizes():
+    from paper_2508_21200_amd import LreiError
+    rng = np.random.default_rng(5)
+    n = 3
+    bonds, J, h = _random_model(n, rng)
+    ctx = _ctx()
+    ctx.set_hamiltonian(n, bonds, J, h)
+    ctx.set_rho(dirichlet_spectrum(2, rng), haar_factor(8, 2, rng))
+    with pytest.raises(LreiError):
+        ctx.step("qLL", "AB2", 0.01, 0.1, 1)  # N = 8 < (2m + 2) r = 12
+    n = 7
+    bonds, J, h = _random_model(n, rng)
+    ctx = _ctx()
+    ctx.set_hamiltonian(n, bonds, J, h)
+    ctx.set_rho(dirichlet_spectrum(20, rng), haar_factor(128, 20, rng))
+    with pytest.raises(LreiError):
+        ctx.step("qLL", "AB3", 0.01, 0.1, 1)  # r > 16
+
+
+@pytest.fixture(scope="module")
+def cfg2_oracle10():
+    """Oracle reference for the n = 16 XXZ chain, r = 8, q-LLG, AB3 dt 0.005: first 10 steps."""
+    cfg = make_config(2)
+    H = Hamiltonian(cfg["n"], cfg["bonds"], cfg["J"], cfg["h"])
+    return cfg, oracle_run(H, cfg["V"], cfg["lam"], cfg["model"], cfg["kappa"], cfg["dt"], 10, cfg["scheme"])
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-5)])
+def test_cfg2_ab3_parity(cfg2_oracle10, precision, tol):
+    cfg, Vo = cfg2_oracle10
+    ctx = _ctx(precision)
+    ctx.set_hamiltonian(cfg["n"], cfg["bonds"], cfg["J"], cfg["h"])
+    ctx.set_rho(cfg["lam"], cfg["V"])
+    ctx.step(cfg["model"], cfg["scheme"], cfg["dt"], cfg["kappa"], 10)
+    _, Vg = ctx.get_rho()
+    err = rel_fro_error(Vg, cfg["lam"], Vo, cfg["lam"])
+    print(f"n=16 r=8 AB3 {precision}: 10 steps rel_fro_error={err:.3e}")
+    assert err < tol
+
+
+def test_cfg2_ab3_full_run_properties():
+    """All 50 steps: mixed agrees with FP64 within 1e-5, the factor stays orthonormal, and the
+    q-LLG energy does not increase (kappa > 0 dissipates)."""
+    cfg = make_config(2)
+    res = {}
+    for precision in ("fp64", "mixed"):
+        ctx = _ctx(precision)
+        ctx.set_hamiltonian(cfg["n"], cfg["bonds"], cfg["J"], cfg["h"])
+        ctx.set_rho(cfg["lam"], cfg["V"])
+        e0, _ = ctx.observables()
+        ctx.step(cfg["model"], cfg["scheme"], cfg["dt"], cfg["kappa"], cfg["steps"])
+        e1, _ = ctx.observables()
+        res[precision] = (ctx.get_rho()[1], e0, e1)
+    V64, e0, e1 = res["fp64"]
+    assert np.abs(V64.conj().T @ V64 - np.eye(cfg["r"])).max() < 1e-12
+    assert e1 <= e0 + 1e-12
+    assert rel_fro_error(res["mixed"][0], cfg["lam"], V64, cfg["lam"]) < 1e-5
