@@ -172,6 +172,28 @@ LREI_API lrei_status lrei_profile_kernels(lrei_ctx *ctx, int model, int scheme, 
 /* Blocks until all work queued by this context has finished. */
 LREI_API lrei_status lrei_synchronize(lrei_ctx *ctx);
 
+/* Result of lrei_autotune. */
+typedef struct {
+  int epl;                 /* complex columns per lane chosen for the H.V pass          */
+  int grid;                /* workgroups per H.V launch chosen                           */
+  double ms;               /* time per launch of the chosen variant                      */
+  int from_cache;          /* 1: read from opt.autotune_cache without timing             */
+  int n_tried;             /* variants timed (at most 32)                                */
+  int tried_epl[32], tried_grid[32];
+  double tried_ms[32];
+} lrei_tune_result;
+
+/* Chooses the launch shape of the matrix-free H.V pass (eq. 5.1 applied in
+ * the Chebyshev passes) for the current Hamiltonian, rank and precision:
+ * every valid (columns per lane, workgroups) pair is timed on the device with
+ * the current state as input (5 launches each) and the fastest is kept for
+ * this context.  With opt.autotune_cache set, a matching line of that text
+ * file (device, n, r, precision, term count) is used instead of timing, and a
+ * new result is appended to it.  Results are unaffected; only speed changes.
+ * Requires lrei_set_rho; overwrites the scratch Krylov blocks (not the state).
+ * out may be NULL.  Errors: LREI_E_STATE without a state, LREI_E_DEVICE. */
+LREI_API lrei_status lrei_autotune(lrei_ctx *ctx, lrei_tune_result *out);
+
 #ifdef __cplusplus
 }
 #endif

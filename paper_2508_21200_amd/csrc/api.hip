@@ -75,8 +75,13 @@ struct lrei_ctx {
   long long N = 0;
   double hbar = 1.0;
   TermTable terms;
-  DevBuf d_off, d_diag;
+  DevBuf d_off, d_diag;           // term records (FP64) and diagonal terms
+  DevBuf d_terms32;               // term records (FP32)
+  DevBuf d_diag64, d_diag32;      // d(x) per row
   int n_off = 0, n_diag = 0;
+  int cplx = 0;                   // some off-diagonal coefficient is complex
+  int epl = 0;                    // H.V columns per lane (0: default)
+  int hv_grid = 0;                // H.V workgroups per launch (0: default)
 
   // state
   bool have_rho = false;
@@ -150,8 +155,9 @@ lrei_status alloc_state(lrei_ctx *ctx, int r, bool fp32) {
     if (!ctx->blocks[i].ensure(blk)) return ctx->fail(LREI_E_NOMEM, "device allocation of Krylov blocks failed");
   if (!ctx->save.ensure(blk)) return ctx->fail(LREI_E_NOMEM, "device allocation failed");
   ctx->grid = nspace_grid(ctx->N, r);
-  const size_t pcount = (size_t)ctx->grid * cheb_partial_splits(r) * 3 * r * r;
-  if (!ctx->partials.ensure(pcount * sizeof(double2) + 2 * ctx->grid * sizeof(double2)))
+  if (ctx->hv_grid <= 0) ctx->hv_grid = ctx->grid;
+  const size_t pcount = (size_t)kMaxHvGrid * cheb_partial_splits(r) * 3 * r * r;
+  if (!ctx->partials.ensure(pcount * sizeof(double2) + 2 * kMaxHvGrid * sizeof(double2)))
     return ctx->fail(LREI_E_NOMEM, "device allocation failed");
   const int D = (kMaxStages + 1) * r;
   const size_t ws_elems = (size_t)kMaxStages * 3 * r * r      // meas
@@ -175,6 +181,17 @@ lrei_status alloc_state(lrei_ctx *ctx, int r, bool fp32) {
   return LREI_OK;
 }
 
+// Hamiltonian tables of an H.V pass.
+void hv_args(lrei_ctx *ctx, ChebArgs &a) {
+  a.terms64 = (const DevTerm<double> *)ctx->d_off.p;
+  a.terms32 = (const DevTerm<float> *)ctx->d_terms32.p;
+  a.diag64 = (const double *)ctx->d_diag64.p;
+  a.diag32 = (const float *)ctx->d_diag32.p;
+  a.n_off = ctx->n_off;
+  a.cplx = ctx->cplx;
+  a.epl = ctx->epl;
+}
+
 // One Chebyshev pass with fused Grams, reduced into ws.meas[slot].
 void cheb_pass_into(lrei_ctx *ctx, int r, int grid, int mode, const void *prev, const void *cur, void *next,
                     double2 *partials, double2 *meas) {
@@ -182,10 +199,7 @@ void cheb_pass_into(lrei_ctx *ctx, int r, int grid, int mode, const void *prev, 
   a.Pprev = prev;
   a.Pcur = cur;
   a.Pnext = next;
-  a.off = (const DevOffTerm *)ctx->d_off.p;
-  a.diag = (const DevDiagTerm *)ctx->d_diag.p;
-  a.n_off = ctx->n_off;
-  a.n_diag = ctx->n_diag;
+  hv_args(ctx, a);
   a.N = ctx->N;
   a.r = r;
   const double e = ctx->terms.gershgorin > 0 ? ctx->terms.gershgorin : 1.0;
@@ -199,7 +213,7 @@ void cheb_pass_into(lrei_ctx *ctx, int r, int grid, int mode, const void *prev, 
 }
 
 void cheb_pass(lrei_ctx *ctx, int mode, const void *prev, const void *cur, void *next, int slot) {
-  cheb_pass_into(ctx, ctx->r, ctx->grid, mode, prev, cur, next, (double2 *)ctx->partials.p,
+  cheb_pass_into(ctx, ctx->r, ctx->hv_grid, mode, prev, cur, next, (double2 *)ctx->partials.p,
                  ctx->ws.meas + (size_t)slot * 3 * ctx->r * ctx->r);
 }
 
@@ -411,10 +425,7 @@ void enqueue_ab_step(lrei_ctx *ctx) {
     ChebArgs a{};
     a.Pcur = ctx->blocks[0].p;
     a.Pnext = ctx->blocks[1].p;
-    a.off = (const DevOffTerm *)ctx->d_off.p;
-    a.diag = (const DevDiagTerm *)ctx->d_diag.p;
-    a.n_off = ctx->n_off;
-    a.n_diag = ctx->n_diag;
+    hv_args(ctx, a);
     a.N = ctx->N;
     a.r = ctx->r;
     a.alpha = 1.0;
@@ -503,6 +514,9 @@ void lrei_destroy(lrei_ctx *ctx) {
   ctx->lam_dev.release();
   ctx->d_off.release();
   ctx->d_diag.release();
+  ctx->d_terms32.release();
+  ctx->d_diag64.release();
+  ctx->d_diag32.release();
   for (auto &set : ctx->ab_U)
     for (auto &b : set) b.release();
   for (auto &b : ctx->ab_coords) b.release();
@@ -543,19 +557,61 @@ lrei_status lrei_set_hamiltonian(lrei_ctx *ctx, int n_spins, int n_bonds, const 
   std::vector<DevDiagTerm> dg(t.diag.size());
   for (size_t i = 0; i < t.diag.size(); ++i) dg[i] = {t.diag[i].si, t.diag[i].sj, t.diag[i].w};
   if (off.size() > 256 || dg.size() > 512) return ctx->fail(LREI_E_INVALID, "too many Hamiltonian terms (max 256 off-diagonal, 512 diagonal)");
-  DevBuf d_off, d_diag;
+  std::vector<DevTerm<float>> off32(off.size());
+  int cplx = 0;
+  for (size_t i = 0; i < off.size(); ++i) {
+    off32[i].mask = off[i].mask;
+    off32[i].sa = off[i].sa;
+    off32[i].sb = off[i].sb;
+    off32[i].pad = 0;
+    for (int q = 0; q < 4; ++q) {
+      off32[i].re[q] = (float)off[i].re[q];
+      off32[i].im[q] = (float)off[i].im[q];
+      if (off[i].im[q] != 0.0) cplx = 1;
+    }
+  }
+  const long long N = 1LL << n_spins;
+  DevBuf d_off, d_diag, d_t32, d_d64, d_d32;
+  auto release_all = [&]() {
+    d_off.release(); d_diag.release(); d_t32.release(); d_d64.release(); d_d32.release();
+  };
   if (!d_off.ensure(std::max<size_t>(1, off.size()) * sizeof(DevOffTerm)) ||
-      !d_diag.ensure(std::max<size_t>(1, dg.size()) * sizeof(DevDiagTerm)))
+      !d_t32.ensure(std::max<size_t>(1, off.size()) * sizeof(DevTerm<float>)) ||
+      !d_diag.ensure(std::max<size_t>(1, dg.size()) * sizeof(DevDiagTerm)) ||
+      !d_d64.ensure((size_t)N * sizeof(double)) || !d_d32.ensure((size_t)N * sizeof(float))) {
+    release_all();
     return ctx->fail(LREI_E_NOMEM, "device allocation failed");
-  if (!off.empty()) HIPCHK(hipMemcpy(d_off.p, off.data(), off.size() * sizeof(DevOffTerm), hipMemcpyHostToDevice));
-  if (!dg.empty()) HIPCHK(hipMemcpy(d_diag.p, dg.data(), dg.size() * sizeof(DevDiagTerm), hipMemcpyHostToDevice));
-  HIPCHK(hipStreamSynchronize(ctx->stream));
+  }
+  hipError_t he = hipSuccess;
+  if (!off.empty()) {
+    he = hipMemcpy(d_off.p, off.data(), off.size() * sizeof(DevOffTerm), hipMemcpyHostToDevice);
+    if (he == hipSuccess)
+      he = hipMemcpy(d_t32.p, off32.data(), off32.size() * sizeof(DevTerm<float>), hipMemcpyHostToDevice);
+  }
+  if (he == hipSuccess && !dg.empty())
+    he = hipMemcpy(d_diag.p, dg.data(), dg.size() * sizeof(DevDiagTerm), hipMemcpyHostToDevice);
+  if (he == hipSuccess) {
+    launch_diag_values((const DevDiagTerm *)d_diag.p, (int)dg.size(), N, (double *)d_d64.p, (float *)d_d32.p,
+                       ctx->stream);
+    he = hipGetLastError();
+  }
+  if (he == hipSuccess) he = hipStreamSynchronize(ctx->stream);
+  if (he != hipSuccess) {
+    release_all();
+    return check_hip(ctx, he, "upload Hamiltonian tables");
+  }
   ctx->d_off.release();
   ctx->d_diag.release();
+  ctx->d_terms32.release();
+  ctx->d_diag64.release();
+  ctx->d_diag32.release();
   ctx->d_off = d_off;
   ctx->d_diag = d_diag;
-  d_off.p = nullptr;
-  d_diag.p = nullptr;
+  ctx->d_terms32 = d_t32;
+  ctx->d_diag64 = d_d64;
+  ctx->d_diag32 = d_d32;
+  d_off.p = d_diag.p = d_t32.p = d_d64.p = d_d32.p = nullptr;
+  ctx->cplx = cplx;
   ctx->n_off = (int)off.size();
   ctx->n_diag = (int)dg.size();
   ctx->terms = t;
@@ -843,10 +899,7 @@ lrei_status lrei_apply_hamiltonian(lrei_ctx *ctx, int r, const void *X, void *Y,
   ChebArgs a{};
   a.Pcur = px;
   a.Pnext = py;
-  a.off = (const DevOffTerm *)ctx->d_off.p;
-  a.diag = (const DevDiagTerm *)ctx->d_diag.p;
-  a.n_off = ctx->n_off;
-  a.n_diag = ctx->n_diag;
+  hv_args(ctx, a);
   a.N = ctx->N;
   a.r = r;
   a.alpha = 1.0;
@@ -862,36 +915,128 @@ lrei_status lrei_apply_hamiltonian(lrei_ctx *ctx, int r, const void *X, void *Y,
   return st;
 }
 
+// Checkpoint layout (little-endian): 16 x uint64 header {magic, n, r, steps_done,
+// fp32, ab_valid, ab_scheme, ab_model, ab_count, ab_nU, ab_npairs, dt bits,
+// kappa bits, 0, 0, 0}; lambda (r doubles); V (N x r complex128); with a valid
+// AB history also the U Gram products, the U-coordinates of the history and the
+// U blocks in the context's storage precision.
+namespace {
+constexpr uint64_t kStateMagic2 = 0x4c52454953543032ull;  // "LREIST02"
+size_t ab_blob_bytes(const lrei_ctx::AbState &ab, size_t r, long long N, size_t elem) {
+  if (!ab.valid) return 0;
+  const size_t DU = (size_t)ab.nU * r;
+  return ((size_t)ab.nU * (ab.nU + 1) / 2 * r * r + (1 + 2 * (size_t)ab.npairs) * DU * r) * sizeof(double2) +
+         (size_t)ab.nU * (size_t)N * r * elem;
+}
+}  // namespace
+
 lrei_status lrei_get_state(lrei_ctx *ctx, void *buf, size_t *len) {
   if (!ctx || !len) return LREI_E_INVALID;
   if (!ctx->have_rho) return ctx->fail(LREI_E_STATE, "no state");
   const size_t vbytes = (size_t)ctx->N * ctx->r * sizeof(double2);
-  const size_t need = 8 * 4 + ctx->r * sizeof(double) + vbytes;
+  const size_t head = 16 * 8 + ctx->r * sizeof(double);
+  const size_t need = head + vbytes + ab_blob_bytes(ctx->ab, ctx->r, ctx->N, ctx->elem());
   if (!buf) {
     *len = need;
     return LREI_OK;
   }
   if (*len < need) return ctx->fail(LREI_E_INVALID, "buffer too small");
-  uint64_t hdr[4] = {kStateMagic, (uint64_t)ctx->n, (uint64_t)ctx->r, (uint64_t)ctx->steps_done};
+  const auto &ab = ctx->ab;
+  uint64_t hdr[16] = {kStateMagic2, (uint64_t)ctx->n, (uint64_t)ctx->r, (uint64_t)ctx->steps_done,
+                      (uint64_t)ctx->fp32, (uint64_t)ab.valid, (uint64_t)ab.scheme, (uint64_t)ab.model,
+                      (uint64_t)ab.count, (uint64_t)ab.nU, (uint64_t)ab.npairs, 0, 0, 0, 0, 0};
+  std::memcpy(&hdr[11], &ab.dt, 8);
+  std::memcpy(&hdr[12], &ab.kappa, 8);
   std::memcpy(buf, hdr, sizeof(hdr));
-  std::memcpy((char *)buf + 32, ctx->lam.data(), ctx->r * sizeof(double));
+  std::memcpy((char *)buf + 128, ctx->lam.data(), ctx->r * sizeof(double));
   *len = need;
-  return lrei_get_rho(ctx, nullptr, (char *)buf + 32 + ctx->r * sizeof(double), 0);
+  lrei_status st = lrei_get_rho(ctx, nullptr, (char *)buf + head, 0);
+  if (st != LREI_OK || !ab.valid) return st;
+  char *q = (char *)buf + head + vbytes;
+  const size_t r = ctx->r, DU = (size_t)ab.nU * r;
+  const size_t ub = (size_t)ab.nU * (ab.nU + 1) / 2 * r * r * sizeof(double2);
+  const size_t cb = (1 + 2 * (size_t)ab.npairs) * DU * r * sizeof(double2);
+  if (ub) HIPCHK(hipMemcpyAsync(q, ctx->ab_UUg.p, ub, hipMemcpyDeviceToHost, ctx->stream));
+  q += ub;
+  if (cb) HIPCHK(hipMemcpyAsync(q, ctx->ab_coords[ab.cur].p, cb, hipMemcpyDeviceToHost, ctx->stream));
+  q += cb;
+  const size_t blk = (size_t)ctx->N * r * ctx->elem();
+  for (int i = 0; i < ab.nU; ++i, q += blk)
+    HIPCHK(hipMemcpyAsync(q, ctx->ab_U[ab.cur][i].p, blk, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return LREI_OK;
 }
 
 lrei_status lrei_set_state(lrei_ctx *ctx, const void *buf, size_t len) {
   if (!ctx || !buf || len < 32) return LREI_E_INVALID;
-  uint64_t hdr[4];
+  uint64_t magic;
+  std::memcpy(&magic, buf, 8);
+  if (magic == kStateMagic) {  // rank-r state without AB history
+    uint64_t hdr[4];
+    std::memcpy(hdr, buf, sizeof(hdr));
+    if (!ctx->have_h || (int)hdr[1] != ctx->n) return ctx->fail(LREI_E_STATE, "Hamiltonian with matching n required");
+    const int r = (int)hdr[2];
+    if (r < 1 || r > kMaxR) return ctx->fail(LREI_E_INVALID, "bad rank in state buffer");
+    const size_t need = 32 + r * sizeof(double) + (size_t)ctx->N * r * sizeof(double2);
+    if (len < need) return ctx->fail(LREI_E_INVALID, "state buffer truncated");
+    const double *lam = (const double *)((const char *)buf + 32);
+    lrei_status st = lrei_set_rho(ctx, r, lam, (const char *)buf + 32 + r * sizeof(double), 0);
+    if (st != LREI_OK) return st;
+    ctx->steps_done = (int64_t)hdr[3];
+    return LREI_OK;
+  }
+  if (magic != kStateMagic2 || len < 128) return ctx->fail(LREI_E_INVALID, "not an LREI state buffer");
+  uint64_t hdr[16];
   std::memcpy(hdr, buf, sizeof(hdr));
-  if (hdr[0] != kStateMagic) return ctx->fail(LREI_E_INVALID, "not an LREI state buffer");
   if (!ctx->have_h || (int)hdr[1] != ctx->n) return ctx->fail(LREI_E_STATE, "Hamiltonian with matching n required");
   const int r = (int)hdr[2];
-  const size_t need = 32 + r * sizeof(double) + (size_t)ctx->N * r * sizeof(double2);
-  if (len < need) return ctx->fail(LREI_E_INVALID, "state buffer truncated");
-  const double *lam = (const double *)((const char *)buf + 32);
-  lrei_status st = lrei_set_rho(ctx, r, lam, (const char *)buf + 32 + r * sizeof(double), 0);
+  if (r < 1 || r > kMaxR) return ctx->fail(LREI_E_INVALID, "bad rank in state buffer");
+  const size_t head = 128 + r * sizeof(double), vbytes = (size_t)ctx->N * r * sizeof(double2);
+  if (len < head + vbytes) return ctx->fail(LREI_E_INVALID, "state buffer truncated");
+  lrei_ctx::AbState ab{};
+  ab.valid = hdr[5] != 0;
+  if (ab.valid) {
+    if ((hdr[4] != 0) != ctx->fp32)
+      return ctx->fail(LREI_E_INVALID, "AB history was saved at another storage precision");
+    ab.scheme = (int)hdr[6];
+    ab.m = ab_order(ab.scheme);
+    ab.model = (int)hdr[7];
+    ab.count = (int)hdr[8];
+    ab.nU = (int)hdr[9];
+    ab.npairs = (int)hdr[10];
+    std::memcpy(&ab.dt, &hdr[11], 8);
+    std::memcpy(&ab.kappa, &hdr[12], 8);
+    if (ab.m < 2 || ab.m > kMaxAb || ab.nU < 0 || ab.nU > 2 * ab.m - 1 || ab.npairs < 0 || ab.npairs > ab.m - 1 ||
+        r > 16)
+      return ctx->fail(LREI_E_INVALID, "corrupt AB history in state buffer");
+  }
+  const lrei_ctx::AbState saved = ab;
+  if (len < head + vbytes + ab_blob_bytes(ab, r, ctx->N, ctx->elem()))
+    return ctx->fail(LREI_E_INVALID, "state buffer truncated");
+  const double *lam = (const double *)((const char *)buf + 128);
+  lrei_status st = lrei_set_rho(ctx, r, lam, (const char *)buf + head, 0);
   if (st != LREI_OK) return st;
   ctx->steps_done = (int64_t)hdr[3];
+  if (!saved.valid) return LREI_OK;
+  ctx->ab = saved;
+  st = ab_alloc(ctx, saved.m);
+  if (st != LREI_OK) {
+    ab_reset(ctx);
+    return st;
+  }
+  ctx->ab.cur = 0;
+  const char *q = (const char *)buf + head + vbytes;
+  const size_t DU = (size_t)saved.nU * r;
+  const size_t ub = (size_t)saved.nU * (saved.nU + 1) / 2 * r * r * sizeof(double2);
+  const size_t cb = (1 + 2 * (size_t)saved.npairs) * DU * r * sizeof(double2);
+  if (ub) HIPCHK(hipMemcpyAsync(ctx->ab_UUg.p, q, ub, hipMemcpyHostToDevice, ctx->stream));
+  q += ub;
+  if (cb) HIPCHK(hipMemcpyAsync(ctx->ab_coords[0].p, q, cb, hipMemcpyHostToDevice, ctx->stream));
+  q += cb;
+  const size_t blk = (size_t)ctx->N * r * ctx->elem();
+  for (int i = 0; i < saved.nU; ++i, q += blk)
+    HIPCHK(hipMemcpyAsync(ctx->ab_U[0][i].p, q, blk, hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
   return LREI_OK;
 }
 
@@ -916,21 +1061,18 @@ lrei_status lrei_profile_kernels(lrei_ctx *ctx, int model, int scheme, double dt
           a.Pprev = ctx->blocks[0].p;
           a.Pcur = ctx->blocks[1].p;
           a.Pnext = ctx->blocks[4].p;
-          a.off = (const DevOffTerm *)ctx->d_off.p;
-          a.diag = (const DevDiagTerm *)ctx->d_diag.p;
-          a.n_off = ctx->n_off;
-          a.n_diag = ctx->n_diag;
+          hv_args(ctx, a);
           a.N = ctx->N;
           a.r = r;
           a.alpha = 1.0 / (ctx->terms.gershgorin > 0 ? ctx->terms.gershgorin : 1.0);
           a.mode = 1;
           a.partials = (double2 *)ctx->partials.p;
-          a.grid = ctx->grid;
+          a.grid = ctx->hv_grid;
           launch_cheb(ctx->fp32, a, ctx->stream);
           break;
         }
         case 1:
-          launch_reduce((const double2 *)ctx->partials.p, ctx->grid, 2 * r * r,
+          launch_reduce((const double2 *)ctx->partials.p, ctx->hv_grid, 2 * r * r,
                         ctx->ws.work, ctx->stream);  // scratch target: the step's Grams stay intact
           break;
         case 2:
@@ -953,6 +1095,120 @@ lrei_status lrei_profile_kernels(lrei_ctx *ctx, int model, int scheme, double dt
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   HIPCHK(hipGetLastError());
+  return LREI_OK;
+}
+
+// Key of an H.V tuning result: device, problem shape and term table.
+static std::string tune_key(lrei_ctx *ctx) {
+  hipDeviceProp_t prop{};
+  (void)hipGetDeviceProperties(&prop, ctx->device);
+  std::string arch = prop.gcnArchName;
+  for (auto &c : arch)
+    if (c == ' ') c = '_';
+  char buf[256];
+  std::snprintf(buf, sizeof(buf), "lrei-hv %s %d %d %d %s %d %d", arch.c_str(), prop.multiProcessorCount, ctx->n,
+                ctx->r, ctx->fp32 ? "mixed" : "fp64", ctx->n_off, ctx->cplx);
+  return buf;
+}
+
+lrei_status lrei_autotune(lrei_ctx *ctx, lrei_tune_result *out) {
+  if (!ctx) return LREI_E_INVALID;
+  if (!ctx->have_rho) return ctx->fail(LREI_E_STATE, "set rho before tuning");
+  HIPCHK(hipSetDevice(ctx->device));
+  lrei_tune_result res{};
+  const std::string key = tune_key(ctx);
+  const char *cache = ctx->opt.autotune_cache;
+  if (cache) {
+    if (FILE *f = std::fopen(cache, "r")) {
+      char line[512];
+      while (std::fgets(line, sizeof(line), f)) {
+        const std::string l(line);
+        if (l.compare(0, key.size(), key) != 0 || l.size() <= key.size() || l[key.size()] != ' ') continue;
+        int e = 0, g = 0;
+        double ms = 0;
+        if (std::sscanf(l.c_str() + key.size(), " %d %d %lf", &e, &g, &ms) == 3 && e > 0 && g > 0 &&
+            g <= kMaxHvGrid) {
+          res.epl = e;
+          res.grid = g;
+          res.ms = ms;
+          res.from_cache = 1;
+        }
+      }
+      std::fclose(f);
+    }
+  }
+  if (!res.from_cache) {
+    const int r = ctx->r;
+    std::vector<int> epls;
+    for (int e : {1, 2, 4, 8}) {
+      if (r % e != 0) continue;
+      if (!ctx->fp32 && e > 4) continue;
+      if (r > 16 && e != cheb_elems_per_lane(ctx->fp32, r)) continue;
+      epls.push_back(e);
+    }
+    const long long tiles = (ctx->N + 63) / 64;
+    std::vector<int> grids;
+    for (int g : {256, 512, 768, 1024, 1280, 1536, 2048})
+      if (g <= tiles && g <= kMaxHvGrid) grids.push_back(g);
+    if (grids.empty()) grids.push_back(nspace_grid(ctx->N, r));
+    // valid data in the pass inputs: P = P- = the current state
+    const size_t vbytes = (size_t)ctx->N * r * ctx->elem();
+    HIPCHK(hipMemcpyAsync(ctx->blocks[1].p, ctx->blocks[0].p, vbytes, hipMemcpyDeviceToDevice, ctx->stream));
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    double best = 1e300;
+    for (int e : epls)
+      for (int g : grids) {
+        ChebArgs a{};
+        a.Pprev = ctx->blocks[0].p;
+        a.Pcur = ctx->blocks[1].p;
+        a.Pnext = ctx->blocks[4].p;
+        hv_args(ctx, a);
+        a.epl = e;
+        a.N = ctx->N;
+        a.r = r;
+        a.alpha = 1.0 / (ctx->terms.gershgorin > 0 ? ctx->terms.gershgorin : 1.0);
+        a.mode = 1;
+        a.partials = (double2 *)ctx->partials.p;
+        a.grid = g;
+        const int iters = 5;
+        bool ok = launch_cheb(ctx->fp32, a, ctx->stream);
+        (void)hipEventRecord(e0, ctx->stream);
+        for (int k = 0; k < iters && ok; ++k) ok = launch_cheb(ctx->fp32, a, ctx->stream);
+        (void)hipEventRecord(e1, ctx->stream);
+        HIPCHK(hipEventSynchronize(e1));
+        HIPCHK(hipGetLastError());
+        if (!ok) continue;
+        float t = 0;
+        (void)hipEventElapsedTime(&t, e0, e1);
+        const double ms = (double)t / iters;
+        if (res.n_tried < 32) {
+          res.tried_epl[res.n_tried] = e;
+          res.tried_grid[res.n_tried] = g;
+          res.tried_ms[res.n_tried] = ms;
+          res.n_tried++;
+        }
+        if (ms < best) {
+          best = ms;
+          res.epl = e;
+          res.grid = g;
+          res.ms = ms;
+        }
+      }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (res.epl == 0) return ctx->fail(LREI_E_DEVICE, "no H.V variant could be launched");
+    if (cache)
+      if (FILE *f = std::fopen(cache, "a")) {
+        std::fprintf(f, "%s %d %d %.6f\n", key.c_str(), res.epl, res.grid, res.ms);
+        std::fclose(f);
+      }
+  }
+  ctx->epl = res.epl;
+  ctx->hv_grid = res.grid;
+  ctx->drop_graph();
+  if (out) *out = res;
   return LREI_OK;
 }
 

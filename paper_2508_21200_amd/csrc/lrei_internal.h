@@ -39,11 +39,13 @@ struct TermTable {
 bool build_terms(int n, int n_bonds, const int32_t *bond_ij, const double *bond_J,
                  const double *site_h, TermTable &out, std::string &err);
 
-// Device-side packed term record (fp64 and fp32 coefficient copies).
-struct DevOffTerm {
+// Device-side term record in the storage precision T of the pass.
+template <typename T>
+struct DevTerm {
   uint32_t mask, sa, sb, pad;
-  double re[4], im[4];
+  T re[4], im[4];
 };
+using DevOffTerm = DevTerm<double>;
 struct DevDiagTerm {
   uint32_t si, sj;
   double w;
@@ -60,9 +62,15 @@ struct ChebArgs {
   const void *Pprev;   // P_{j-1} (mode 1) or nullptr
   const void *Pcur;    // P_j
   void *Pnext;         // P_{j+1}
-  const DevOffTerm *off;
-  const DevDiagTerm *diag;
-  int n_off, n_diag;
+  const DevTerm<double> *terms64;  // off-diagonal terms
+  const DevTerm<float> *terms32;
+  const double *diag64;            // d(x) per row
+  const float *diag32;
+  int n_off;
+  int cplx;             // some coefficient has a non-zero imaginary part
+  int epl;              // complex columns per lane (0: default)
+  int lanes;            // set by the launcher
+  const void *terms, *diagv;  // set by the launcher
   long long N;
   int r;
   double alpha, shift;  // P_{j+1} = mul * alpha * (H - shift) P_j - [mode 1] P_{j-1}
@@ -71,7 +79,9 @@ struct ChebArgs {
   int grid;
 };
 
-void launch_cheb(bool fp32, const ChebArgs &a, hipStream_t s);
+bool launch_cheb(bool fp32, const ChebArgs &a, hipStream_t s);
+void launch_diag_values(const DevDiagTerm *diag, int n_diag, long long N, double *d64, float *d32, hipStream_t s);
+int cheb_elems_per_lane(bool fp32, int r);
 void launch_combine(bool fp32, const void *const *blocks, int nblocks, const double2 *C, void *out,
                     long long N, int r, int grid, hipStream_t s);
 void launch_reduce(const double2 *partials, int count, int len, double2 *out, hipStream_t s);
@@ -79,6 +89,7 @@ void launch_convert(bool to_fp32, const void *src, void *dst, long long n_comple
 void launch_magnetization(bool fp32, const void *V, const double *lam, long long N, int r, int n,
                           double2 *partials, int grid, hipStream_t s);
 int nspace_grid(long long N, int r);
+constexpr int kMaxHvGrid = 2048;  // largest H.V launch the partial-sum buffer holds
 
 // Generic block pass (blocks.hip): out_o = sum_i in_i C[i, o] and Gram
 // products over the listed (a, b) pairs of [inputs..., outputs...], r <= 16.

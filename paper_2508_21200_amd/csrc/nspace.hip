@@ -24,7 +24,6 @@ template <> struct Cplx<float> { using type = float2; };
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 constexpr int kTile = 64;     // rows per tile
-constexpr int kMaxItems = 3;  // Gram work items per wave (upper bound)
 constexpr int kMaxLds = 150 * 1024;
 
 __host__ __device__ inline int pow2ceil(int v) {
@@ -168,44 +167,84 @@ __device__ inline GramPlan<T> make_plan(int ng, int RP) {
 // ---------------------------------------------------------------------------
 // Chebyshev pass with the Hamiltonian applied matrix-free.
 //   mode 0: P1 = alpha (H - shift) P0                Grams P0*P0, P0*P1, P1*P1
-//   mode 1: P+ = 2 alpha (H - shift) P - P-           Grams P-*P+, P*P+, P+*P+
+//   mode 1: P+ = 2 alpha (H - shift) P - P-           Grams P*P+, P+*P+
 //   mode 2: Y = H X                                    (no Grams)
+//
+// A row x of the output is d(x) X[x] + sum_t c_t(x) X[x ^ mask_t].  L lanes
+// share a row, each holding E consecutive complex columns (16-byte loads), so
+// the per-term index and coefficient work is done once per E columns.  The
+// diagonal d(x) is precomputed per row.  The term table is read with uniform
+// (scalar) loads; a coefficient is picked from the term's four entries by the
+// two destination bits.  Terms with a zero coefficient for the row skip the load.
 // ---------------------------------------------------------------------------
-template <typename T, int MI>
+template <typename T, int E>
+__device__ inline void load_ce(const T *p, T (&v)[2 * E]) {
+  if constexpr (sizeof(T) == 4 && E == 1) {
+    const float2 q = *reinterpret_cast<const float2 *>(p);
+    v[0] = q.x; v[1] = q.y;
+  } else if constexpr (sizeof(T) == 4) {
+#pragma unroll
+    for (int k = 0; k < E / 2; ++k) {
+      const float4 q = reinterpret_cast<const float4 *>(p)[k];
+      v[4 * k] = q.x; v[4 * k + 1] = q.y; v[4 * k + 2] = q.z; v[4 * k + 3] = q.w;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const double2 q = reinterpret_cast<const double2 *>(p)[k];
+      v[2 * k] = q.x; v[2 * k + 1] = q.y;
+    }
+  }
+}
+template <typename T, int E>
+__device__ inline void store_ce(T *p, const T (&v)[2 * E]) {
+  if constexpr (sizeof(T) == 4 && E == 1) {
+    *reinterpret_cast<float2 *>(p) = make_float2(v[0], v[1]);
+  } else if constexpr (sizeof(T) == 4) {
+#pragma unroll
+    for (int k = 0; k < E / 2; ++k)
+      reinterpret_cast<float4 *>(p)[k] = make_float4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
+  } else {
+#pragma unroll
+    for (int k = 0; k < E; ++k) reinterpret_cast<double2 *>(p)[k] = make_double2(v[2 * k], v[2 * k + 1]);
+  }
+}
+template <typename T>
+__device__ inline T pick4(int idx, T c0, T c1, T c2, T c3) {
+  const T lo = (idx & 1) ? c1 : c0, hi = (idx & 1) ? c3 : c2;
+  return (idx & 2) ? hi : lo;
+}
+
+// E complex columns per lane, CPLX: some coefficient has an imaginary part,
+// MI: Gram work items per wave.
+template <typename T, int E, bool CPLX, int MI>
 __global__ __launch_bounds__(kThreads) void k_cheb(ChebArgs a) {
-  using C2 = typename Cplx<T>::type;
   extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int B = (sizeof(T) == 4 ? 32 : 16) / E > 1 ? (sizeof(T) == 4 ? 32 : 16) / E : 2;  // loads in flight
   const int r = a.r;
-  const int L = pow2ceil(r);          // lanes per row
-  const int RW = 64 / L;              // rows per wave per iteration
+  const int L = a.lanes;   // lanes per row, power of two, L * E >= r
+  const int RW = 64 / L;   // rows per wave per iteration
   const int RP = pad16(r);
   const bool grams = a.mode != 2;
 
-  // LDS: term table, then six planes [kTile][RP] (prev, cur, next) x (re, im).
-  DevOffTerm *s_off = reinterpret_cast<DevOffTerm *>(smem);
-  DevDiagTerm *s_diag = reinterpret_cast<DevDiagTerm *>(smem + a.n_off * sizeof(DevOffTerm));
-  size_t off_bytes = a.n_off * sizeof(DevOffTerm) + a.n_diag * sizeof(DevDiagTerm);
-  off_bytes = (off_bytes + 15) & ~size_t(15);
-  T *planes = reinterpret_cast<T *>(smem + off_bytes);
+  // LDS: four planes [kTile][RP] (cur, next) x (re, im) for the Gram products
+  T *planes = reinterpret_cast<T *>(smem);
   const int plane = kTile * RP;
-  T *pre = planes, *pim = planes + plane;           // prev
-  T *cre = planes + 2 * plane, *cim = planes + 3 * plane;  // cur
-  T *nre = planes + 4 * plane, *nim = planes + 5 * plane;  // next
-
-  for (int i = threadIdx.x; i < a.n_off; i += kThreads) s_off[i] = a.off[i];
-  for (int i = threadIdx.x; i < a.n_diag; i += kThreads) s_diag[i] = a.diag[i];
+  T *cre = planes, *cim = planes + plane, *nre = planes + 2 * plane, *nim = planes + 3 * plane;
   if (grams)
-    for (int i = threadIdx.x; i < 6 * plane; i += kThreads) planes[i] = T(0);
+    for (int i = threadIdx.x; i < 4 * plane; i += kThreads) planes[i] = T(0);
   __syncthreads();
 
-  const C2 *Pc = reinterpret_cast<const C2 *>(a.Pcur);
-  const C2 *Pp = reinterpret_cast<const C2 *>(a.Pprev);
-  C2 *Pn = reinterpret_cast<C2 *>(a.Pnext);
+  const T *__restrict__ Pc = reinterpret_cast<const T *>(a.Pcur);
+  const T *__restrict__ Pp = reinterpret_cast<const T *>(a.Pprev);
+  T *__restrict__ Pn = reinterpret_cast<T *>(a.Pnext);
+  const DevTerm<T> *__restrict__ terms = reinterpret_cast<const DevTerm<T> *>(a.terms);
+  const T *__restrict__ dv = reinterpret_cast<const T *>(a.diagv);
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int col = lane % L;
-  const int rsub = lane / L;
-  const bool colok = col < r;
+  const int cl = lane % L, rsub = lane / L;
+  const int col0 = cl * E;
+  const bool active = col0 < r;
   const T alpha = (T)a.alpha, shift = (T)a.shift;
   const T mul = a.mode == 1 ? T(2) : T(1);
 
@@ -221,7 +260,6 @@ __global__ __launch_bounds__(kThreads) void k_cheb(ChebArgs a) {
     xre[1] = nre; xim[1] = nim; yre[1] = nre; yim[1] = nim;
     xre[2] = nre; xim[2] = nim; yre[2] = nre; yim[2] = nim;
   }
-  (void)pre; (void)pim;
   double acc[MI][8];
 #pragma unroll
   for (int q = 0; q < MI; ++q)
@@ -229,6 +267,7 @@ __global__ __launch_bounds__(kThreads) void k_cheb(ChebArgs a) {
     for (int v = 0; v < 8; ++v) acc[q][v] = 0.0;
 
   const long long N = a.N;
+  const int nof = a.n_off;
   const long long num_tiles = (N + kTile - 1) / kTile;
   for (long long k = 0;; ++k) {
     const long long tile = tile_of(k, num_tiles, a.grid);
@@ -238,66 +277,62 @@ __global__ __launch_bounds__(kThreads) void k_cheb(ChebArgs a) {
       const int lr = it * kWaves * RW + wave * RW + rsub;  // local row
       if (lr >= kTile) continue;
       const long long x = row0 + lr;
-      if (x >= N) continue;
-      T ore = 0, oim = 0, xr = 0, xi = 0, vr = 0, vi = 0;
-      if (colok) {
-        const uint32_t xu = (uint32_t)x;
-        const C2 own = Pc[(size_t)xu * r + col];
-        xr = own.x; xi = own.y;
-        double dsum = 0.0;
-        for (int t = 0; t < a.n_diag; ++t) {
-          const DevDiagTerm dt = s_diag[t];
-          dsum += (((xu >> dt.si) ^ (xu >> dt.sj)) & 1u) ? -dt.w : dt.w;
-        }
-        T accr = (T)dsum * xr, acci = (T)dsum * xi;
-        const int nof = a.n_off;
-        int t = 0;
-        // Batches of 8 independent row gathers keep 8 loads in flight per lane.
-        for (; t + 8 <= nof; t += 8) {
-          C2 y[8];
-          T cr[8], ci[8];
+      if (x >= N || !active) continue;
+      const uint32_t xu = (uint32_t)x;
+      const size_t base = (size_t)xu * r + col0;
+      T own[2 * E], o[2 * E];
+      load_ce<T, E>(Pc + 2 * base, own);
+      const T d = dv[xu];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            const DevOffTerm &ot = s_off[t + u];
-            const uint32_t idx = ((xu >> ot.sa) & 1u) | (((xu >> ot.sb) & 1u) << 1);
-            cr[u] = (T)ot.re[idx];
-            ci[u] = (T)ot.im[idx];
-            y[u].x = 0; y[u].y = 0;
-            if (cr[u] != T(0) || ci[u] != T(0)) y[u] = Pc[(size_t)(xu ^ ot.mask) * r + col];
-          }
+      for (int e = 0; e < 2 * E; ++e) o[e] = d * own[e];
+      for (int t = 0; t < nof; t += B) {
+        T y[B][2 * E];
+        T cr[B], ci[B];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            accr += cr[u] * y[u].x - ci[u] * y[u].y;
-            acci += cr[u] * y[u].y + ci[u] * y[u].x;
+        for (int u = 0; u < B; ++u) {
+          cr[u] = T(0);
+          ci[u] = T(0);
+#pragma unroll
+          for (int e = 0; e < 2 * E; ++e) y[u][e] = T(0);
+          if (t + u < nof) {
+            const DevTerm<T> &tm = terms[t + u];
+            const int idx = (int)(((xu >> tm.sa) & 1u) | (((xu >> tm.sb) & 1u) << 1));
+            cr[u] = pick4(idx, tm.re[0], tm.re[1], tm.re[2], tm.re[3]);
+            if (CPLX) ci[u] = pick4(idx, tm.im[0], tm.im[1], tm.im[2], tm.im[3]);
+            if (cr[u] != T(0) || ci[u] != T(0)) load_ce<T, E>(Pc + 2 * ((size_t)(xu ^ tm.mask) * r + col0), y[u]);
           }
         }
-        for (; t < nof; ++t) {
-          const DevOffTerm &ot = s_off[t];
-          const uint32_t idx = ((xu >> ot.sa) & 1u) | (((xu >> ot.sb) & 1u) << 1);
-          const T cr = (T)ot.re[idx], ci = (T)ot.im[idx];
-          if (cr == T(0) && ci == T(0)) continue;
-          const C2 y = Pc[(size_t)(xu ^ ot.mask) * r + col];
-          accr += cr * y.x - ci * y.y;
-          acci += cr * y.y + ci * y.x;
-        }
-        if (a.mode == 2) {
-          ore = accr; oim = acci;
-        } else {
-          ore = mul * alpha * (accr - shift * xr);
-          oim = mul * alpha * (acci - shift * xi);
-          if (a.mode == 1) {
-            const C2 pv = Pp[(size_t)xu * r + col];
-            vr = pv.x; vi = pv.y;
-            ore -= vr; oim -= vi;
+#pragma unroll
+        for (int u = 0; u < B; ++u)
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            o[2 * e] += cr[u] * y[u][2 * e];
+            o[2 * e + 1] += cr[u] * y[u][2 * e + 1];
+            if (CPLX) {
+              o[2 * e] -= ci[u] * y[u][2 * e + 1];
+              o[2 * e + 1] += ci[u] * y[u][2 * e];
+            }
           }
-        }
-        C2 o;
-        o.x = ore; o.y = oim;
-        Pn[(size_t)xu * r + col] = o;
       }
-      if (grams && colok) {
-        cre[lr * RP + col] = xr; cim[lr * RP + col] = xi;
-        nre[lr * RP + col] = ore; nim[lr * RP + col] = oim;
+      if (a.mode != 2) {
+        T pv[2 * E];
+        if (a.mode == 1) load_ce<T, E>(Pp + 2 * base, pv);
+#pragma unroll
+        for (int e = 0; e < 2 * E; ++e) {
+          o[e] = mul * alpha * (o[e] - shift * own[e]);
+          if (a.mode == 1) o[e] -= pv[e];
+        }
+      }
+      store_ce<T, E>(Pn + 2 * base, o);
+      if (grams) {
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+          if (col0 + e < r) {
+            cre[lr * RP + col0 + e] = own[2 * e];
+            cim[lr * RP + col0 + e] = own[2 * e + 1];
+            nre[lr * RP + col0 + e] = o[2 * e];
+            nim[lr * RP + col0 + e] = o[2 * e + 1];
+          }
       }
     }
     if (grams) {
@@ -311,6 +346,21 @@ __global__ __launch_bounds__(kThreads) void k_cheb(ChebArgs a) {
   if (grams) {
     __syncthreads();
     gram_store<T, MI>(gp, acc, r, a.partials, reinterpret_cast<double2 *>(planes));
+  }
+}
+
+// Diagonal of H per row: d(x) = sum_k w_k (1 - 2 (b_{i_k}(x) xor b_{j_k}(x))),
+// bit 31 of a row index being 0 (one-site terms use j_k = 31).
+__global__ void k_diag_values(const DevDiagTerm *diag, int n_diag, long long N, double *d64, float *d32) {
+  for (long long x = blockIdx.x * (long long)blockDim.x + threadIdx.x; x < N; x += (long long)gridDim.x * blockDim.x) {
+    const uint32_t xu = (uint32_t)x;
+    double s = 0.0;
+    for (int t = 0; t < n_diag; ++t) {
+      const DevDiagTerm dt = diag[t];
+      s += (((xu >> dt.si) ^ (xu >> dt.sj)) & 1u) ? -dt.w : dt.w;
+    }
+    d64[x] = s;
+    if (d32) d32[x] = (float)s;
   }
 }
 
@@ -492,11 +542,7 @@ __global__ __launch_bounds__(kThreads) void k_magnet(const void *Vp, const doubl
   }
 }
 
-size_t cheb_lds(bool fp32, int n_off, int n_diag, int r) {
-  size_t b = n_off * sizeof(DevOffTerm) + n_diag * sizeof(DevDiagTerm);
-  b = (b + 15) & ~size_t(15);
-  return b + 6 * (size_t)kTile * pad16(r) * (fp32 ? 4 : 8);
-}
+size_t cheb_lds(bool fp32, int r) { return 4 * (size_t)kTile * pad16(r) * (fp32 ? 4 : 8); }
 
 }  // namespace
 
@@ -513,25 +559,72 @@ int nspace_grid(long long N, int r) {
   return (int)(g < 1 ? 1 : g);
 }
 
-void launch_cheb(bool fp32, const ChebArgs &a, hipStream_t s) {
-  const size_t lds = cheb_lds(fp32, a.n_off, a.n_diag, a.r);
+// Complex columns per lane for the H.V pass: 16-byte lanes, E | r.
+int cheb_elems_per_lane(bool fp32, int r) {
+  if (r > 16) return (fp32 && r % 2 == 0) ? 2 : 1;
+  if (fp32) return r % 4 == 0 ? 4 : (r % 2 == 0 ? 2 : 1);
+  return r % 2 == 0 ? 2 : 1;
+}
+
+template <typename T, int E, bool C, int MI>
+static void launch_one(const ChebArgs &a, size_t lds, hipStream_t s) {
   static bool attr = false;
   if (!attr) {
-    (void)hipFuncSetAttribute((const void *)k_cheb<float, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
-    (void)hipFuncSetAttribute((const void *)k_cheb<double, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
-    (void)hipFuncSetAttribute((const void *)k_cheb<float, 3>, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
-    (void)hipFuncSetAttribute((const void *)k_cheb<double, 3>, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+    (void)hipFuncSetAttribute((const void *)k_cheb<T, E, C, MI>, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
     attr = true;
   }
-  // one Gram work item per wave up to r = 16 (keeps registers low), three above
-  const bool small_r = a.r <= 16;
+  hipLaunchKernelGGL((k_cheb<T, E, C, MI>), dim3(a.grid), dim3(kThreads), lds, s, a);
+}
+
+template <typename T, int E, int MI>
+static void launch_c(const ChebArgs &a, size_t lds, hipStream_t s) {
+  if (a.cplx) launch_one<T, E, true, MI>(a, lds, s);
+  else launch_one<T, E, false, MI>(a, lds, s);
+}
+
+bool launch_cheb(bool fp32, const ChebArgs &a0, hipStream_t s) {
+  ChebArgs a = a0;
+  const int E = a.epl > 0 ? a.epl : cheb_elems_per_lane(fp32, a.r);
+  if (a.r % E != 0) return false;
+  int L = 1;
+  while (L * E < a.r) L <<= 1;
+  if (L > 64) return false;
+  a.lanes = L;
+  a.epl = E;
+  a.terms = fp32 ? (const void *)a.terms32 : (const void *)a.terms64;
+  a.diagv = fp32 ? (const void *)a.diag32 : (const void *)a.diag64;
+  const size_t lds = cheb_lds(fp32, a.r);
+  const bool big = a.r > 16;  // three Gram work items per wave above r = 16
   if (fp32) {
-    if (small_r) hipLaunchKernelGGL((k_cheb<float, 1>), dim3(a.grid), dim3(kThreads), lds, s, a);
-    else hipLaunchKernelGGL((k_cheb<float, 3>), dim3(a.grid), dim3(kThreads), lds, s, a);
+    if (big) {
+      if (E == 2) launch_c<float, 2, 3>(a, lds, s); else launch_c<float, 1, 3>(a, lds, s);
+    } else {
+      switch (E) {
+        case 8: launch_c<float, 8, 1>(a, lds, s); break;
+        case 4: launch_c<float, 4, 1>(a, lds, s); break;
+        case 2: launch_c<float, 2, 1>(a, lds, s); break;
+        default: launch_c<float, 1, 1>(a, lds, s);
+      }
+    }
   } else {
-    if (small_r) hipLaunchKernelGGL((k_cheb<double, 1>), dim3(a.grid), dim3(kThreads), lds, s, a);
-    else hipLaunchKernelGGL((k_cheb<double, 3>), dim3(a.grid), dim3(kThreads), lds, s, a);
+    if (big) {
+      launch_c<double, 1, 3>(a, lds, s);
+      if (E != 1) return false;
+    } else {
+      switch (E) {
+        case 4: launch_c<double, 4, 1>(a, lds, s); break;
+        case 2: launch_c<double, 2, 1>(a, lds, s); break;
+        default: launch_c<double, 1, 1>(a, lds, s);
+      }
+    }
   }
+  return true;
+}
+
+void launch_diag_values(const DevDiagTerm *diag, int n_diag, long long N, double *d64, float *d32, hipStream_t s) {
+  long long blocks = (N + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_diag_values, dim3((unsigned)blocks), dim3(256), 0, s, diag, n_diag, N, d64, d32);
 }
 
 void launch_combine(bool fp32, const void *const *blocks, int nblocks, const double2 *C, void *out,

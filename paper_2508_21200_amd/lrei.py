@@ -44,6 +44,13 @@ class lrei_stats(ctypes.Structure):
         return d
 
 
+class lrei_tune_result(ctypes.Structure):
+    _fields_ = [("epl", ctypes.c_int), ("grid", ctypes.c_int), ("ms", ctypes.c_double),
+                ("from_cache", ctypes.c_int), ("n_tried", ctypes.c_int),
+                ("tried_epl", ctypes.c_int * 32), ("tried_grid", ctypes.c_int * 32),
+                ("tried_ms", ctypes.c_double * 32)]
+
+
 class LreiError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
@@ -71,6 +78,7 @@ _SIGS = {
     "lrei_profile_kernels": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                              ctypes.c_int, _P]),
     "lrei_synchronize": (ctypes.c_int, [_P]),
+    "lrei_autotune": (ctypes.c_int, [_P, ctypes.POINTER(lrei_tune_result)]),
 }
 
 
@@ -109,7 +117,7 @@ class Context:
     """One LREI context (one trajectory) on a HIP device."""
 
     def __init__(self, device=0, stream=None, precision="fp64", eig_tol=1e-15, eig_max_sweeps=40,
-                 warm="plain", householder_mode=1, use_graph=True):
+                 warm="plain", householder_mode=1, use_graph=True, autotune_cache=None):
         self.lib = load()
         opt = lrei_options()
         self.lib.lrei_default_options(ctypes.byref(opt))
@@ -119,6 +127,8 @@ class Context:
         opt.warm = WARM[warm]
         opt.householder_mode = householder_mode
         opt.use_graph = int(bool(use_graph))
+        self._cache = None if autotune_cache is None else str(autotune_cache).encode()
+        opt.autotune_cache = self._cache
         h = _P()
         st = self.lib.lrei_create(ctypes.byref(h), int(device), stream, ctypes.byref(opt))
         if st != LREI_OK:
@@ -204,7 +214,7 @@ class Context:
     def set_state(self, blob):
         buf = ctypes.create_string_buffer(blob, len(blob))
         self._check(self.lib.lrei_set_state(self.h, buf, len(blob)))
-        hdr = np.frombuffer(blob[:32], dtype=np.uint64)
+        hdr = np.frombuffer(blob[:24], dtype=np.uint64)
         self.r = int(hdr[2])
 
     def profile_kernels(self, model, scheme, dt, kappa, iters=20):
@@ -213,6 +223,13 @@ class Context:
         self._check(self.lib.lrei_profile_kernels(self.h, MODELS[model], SCHEMES[scheme], float(dt),
                                                   float(kappa), int(iters), ms))
         return dict(hv_pass=ms[0], reduce=ms[1], projected_step=ms[2], combine=ms[3])
+
+    def autotune(self):
+        """Times the H.V launch variants and keeps the fastest; returns the choice and all timings."""
+        t = lrei_tune_result()
+        self._check(self.lib.lrei_autotune(self.h, ctypes.byref(t)))
+        return {"epl": t.epl, "grid": t.grid, "ms": t.ms, "from_cache": bool(t.from_cache),
+                "tried": [(t.tried_epl[i], t.tried_grid[i], t.tried_ms[i]) for i in range(t.n_tried)]}
 
     def synchronize(self):
         self._check(self.lib.lrei_synchronize(self.h))

@@ -338,3 +338,45 @@ def test_cfg2_ab3_full_run_properties():
     assert np.abs(V64.conj().T @ V64 - np.eye(cfg["r"])).max() < 1e-12
     assert e1 <= e0 + 1e-12
     assert rel_fro_error(res["mixed"][0], cfg["lam"], V64, cfg["lam"]) < 1e-5
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_ab_checkpoint_resume_bitwise(precision):
+    """A checkpoint taken inside an AB3 run carries the history: resuming continues bitwise."""
+    cfg = make_config(2, n=9, r=4)
+    a = _ctx(precision)
+    a.set_hamiltonian(cfg["n"], cfg["bonds"], cfg["J"], cfg["h"])
+    a.set_rho(cfg["lam"], cfg["V"])
+    a.step("qLLG", "AB3", 0.005, 0.05, 5)
+    blob = a.get_state()
+    a.step("qLLG", "AB3", 0.005, 0.05, 4)
+    b = _ctx(precision)
+    b.set_hamiltonian(cfg["n"], cfg["bonds"], cfg["J"], cfg["h"])
+    b.set_state(blob)
+    b.step("qLLG", "AB3", 0.005, 0.05, 4)
+    assert np.array_equal(a.get_rho()[1], b.get_rho()[1])
+    if precision == "fp64":
+        H = Hamiltonian(cfg["n"], cfg["bonds"], cfg["J"], cfg["h"])
+        Vo = oracle_run(H, cfg["V"], cfg["lam"], "qLLG", 0.05, 0.005, 9, "AB3")
+        assert rel_fro_error(b.get_rho()[1], cfg["lam"], Vo, cfg["lam"]) < 1e-11
+
+
+def test_autotune_keeps_results_and_caches(tmp_path):
+    """Tuning the H.V launch shape changes speed only; a cache file replays the choice."""
+    cfg = make_config(2, n=12, r=8)
+    cache = tmp_path / "tune.txt"
+    out = []
+    for tune in (False, True, True):
+        ctx = _ctx(autotune_cache=cache)
+        ctx.set_hamiltonian(cfg["n"], cfg["bonds"], cfg["J"], cfg["h"])
+        ctx.set_rho(cfg["lam"], cfg["V"])
+        if tune:
+            res = ctx.autotune()
+            out.append(res)
+        ctx.step("qLLG", "RK4", 0.005, 0.05, 4)
+        out.append(ctx.get_rho()[1])
+    V0, t1, V1, t2, V2 = out
+    assert t1["from_cache"] is False and len(t1["tried"]) >= 2
+    assert t2["from_cache"] is True and (t2["epl"], t2["grid"]) == (t1["epl"], t1["grid"])
+    assert rel_fro_error(V1, cfg["lam"], V0, cfg["lam"]) < 1e-12
+    assert np.array_equal(V1, V2)
