@@ -202,6 +202,9 @@ def main():
         "projected_phase_ms_per_step": dict(zip(
             ["gram_setup", "cholesky", "r_inverse", "h_apply", "householder", "stage_matrix", "eigensolve", "tail"],
             [round(v / args.steps, 4) for v in stats["phase_ms"]])),
+        "eigensolve_parts_ms_per_step": dict(zip(
+            ["tridiagonalisation", "multisection", "inverse_iteration", "back_transform"],
+            [round(v / args.steps, 4) for v in stats["eig_phase_ms"]])),
     }
     print(json.dumps(line))
 

@@ -791,8 +791,13 @@ lrei_status lrei_step(lrei_ctx *ctx, int model, int scheme, double dt, double ka
     ab_reset(ctx);  // the history no longer matches the restored state
     HIPCHK(hipMemcpyAsync(ctx->blocks[0].p, ctx->save.p, vbytes, hipMemcpyDeviceToDevice, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
+    char where[96] = "";
+    if (h[28] >= 0)
+      std::snprintf(where, sizeof(where), " (first at stage %d, %s)", (int)h[28] / 10,
+                    (const char *[]){"", "u", "H u", "z/w", "stage matrix", "eigenvectors"}[(int)h[28] % 10]);
     return ctx->fail(bad ? LREI_E_NUMERIC : LREI_E_NOTCONVERGED,
-                     bad ? "non-finite values in the step; state restored to the start of the call"
+                     bad ? std::string("non-finite values in the step") + where +
+                               "; state restored to the start of the call"
                          : "Jacobi eigensolve hit the sweep limit; state restored to the start of the call");
   }
   ctx->steps_done += n_steps;
@@ -806,6 +811,7 @@ lrei_status lrei_step(lrei_ctx *ctx, int model, int scheme, double dt, double ka
   ctx->stats.energy = h[5];
   ctx->stats.last_step_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
   for (int k = 0; k < 8; ++k) ctx->stats.phase_ms[k] = h[16 + k];
+  for (int k = 0; k < 4; ++k) ctx->stats.eig_phase_ms[k] = h[24 + k];
   return LREI_OK;
 }
 

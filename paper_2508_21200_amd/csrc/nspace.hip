@@ -377,17 +377,20 @@ struct CombineArgs {
   int r, grid;
 };
 
-template <typename T>
+// Each wave forms 16 output rows at a time with 16x16x4 MFMA.  The MFMA inner
+// index is permuted so that lane (i, q) of the A operand holds CPL consecutive
+// complex columns q*CPL .. q*CPL+CPL-1 of row i (one contiguous vector load);
+// step s of the product uses column q*CPL + s, and C is read with the same
+// permutation.  C sits in LDS.  In place over block 0 is allowed: a wave reads
+// all of its rows before it writes them, and no other wave touches them.
+template <typename T, int RP>
 __global__ __launch_bounds__(kThreads) void k_combine(CombineArgs a) {
-  using C2 = typename Cplx<T>::type;
   using A4 = typename Acc4<T>::type;
   extern __shared__ __align__(16) unsigned char smem[];
-  const int r = a.r, RP = pad16(r), nb = a.nb;
-  const int K = nb * RP;  // padded inner dimension
-  T *cre = reinterpret_cast<T *>(smem);            // [K][RP]
+  const int r = a.r, nb = a.nb;
+  const int K = nb * RP;
+  T *cre = reinterpret_cast<T *>(smem);  // [K][RP]
   T *cim = cre + K * RP;
-  T *tre = cim + K * RP;                           // [kTile][RP] one block chunk
-  T *tim = tre + kTile * RP;
   for (int i = threadIdx.x; i < K * RP; i += kThreads) {
     const int kk = i / RP, j = i % RP;
     const int blk = kk / RP, ak = kk % RP;
@@ -396,40 +399,48 @@ __global__ __launch_bounds__(kThreads) void k_combine(CombineArgs a) {
     cre[i] = (T)c.x;
     cim[i] = (T)c.y;
   }
-  for (int i = threadIdx.x; i < 2 * kTile * RP; i += kThreads) tre[i] = T(0);
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int TA = RP / 16;
-  C2 *out = reinterpret_cast<C2 *>(a.out);
+  const int i16 = lane & 15, q = lane >> 4;
+  constexpr int CPL = RP / 4;  // 4 or 8 complex columns per lane
+  constexpr int TA = RP / 16;
+  T *out = reinterpret_cast<T *>(a.out);
   const long long N = a.N;
   const long long num_tiles = (N + kTile - 1) / kTile;
   for (long long k = 0;; ++k) {
     const long long tile = tile_of(k, num_tiles, a.grid);
     if (tile < 0) break;
-    const long long row0 = tile * kTile;
-    A4 ore[2], oim[2];  // TA <= 2 (r <= 32)
+    const long long x = tile * kTile + wave * 16 + i16;  // this lane's A row
+    A4 ore[2], oim[2];
     for (int t = 0; t < 2; ++t) { ore[t] = A4{0, 0, 0, 0}; oim[t] = A4{0, 0, 0, 0}; }
     for (int blk = 0; blk < nb; ++blk) {
-      const C2 *B = reinterpret_cast<const C2 *>(a.blocks[blk]);
-      __syncthreads();
-      for (int i = threadIdx.x; i < kTile * r; i += kThreads) {
-        const int lr = i / r, c = i % r;
-        const long long x = row0 + lr;
-        C2 v;
-        v.x = 0; v.y = 0;
-        if (x < N) v = B[x * r + c];
-        tre[lr * RP + c] = v.x;
-        tim[lr * RP + c] = v.y;
+      const T *B = reinterpret_cast<const T *>(a.blocks[blk]);
+      T v[16];  // up to 8 complex
+#pragma unroll
+      for (int e = 0; e < 16; ++e) v[e] = T(0);
+      const int c0 = q * CPL;
+      if (x < N) {
+        if (c0 + CPL <= r) {
+          if constexpr (CPL == 4) {
+            load_ce<T, 4>(B + 2 * ((size_t)x * r + c0), *reinterpret_cast<T(*)[8]>(v));
+          } else {
+            load_ce<T, 4>(B + 2 * ((size_t)x * r + c0), *reinterpret_cast<T(*)[8]>(v));
+            load_ce<T, 4>(B + 2 * ((size_t)x * r + c0 + 4), *reinterpret_cast<T(*)[8]>(v + 8));
+          }
+        } else {
+          for (int e = 0; e < CPL; ++e)
+            if (c0 + e < r) {
+              v[2 * e] = B[2 * ((size_t)x * r + c0 + e)];
+              v[2 * e + 1] = B[2 * ((size_t)x * r + c0 + e) + 1];
+            }
+        }
       }
-      __syncthreads();
-      // wave w: output rows w*16 .. w*16+15, all column tiles
-      for (int kk = 0; kk < RP; kk += 4) {
-        const int arow = wave * 16 + (lane & 15);
-        const int acol = kk + (lane >> 4);
-        const T ar = tre[arow * RP + acol], ai = tim[arow * RP + acol];
+#pragma unroll
+      for (int st = 0; st < CPL; ++st) {
+        const T ar = v[2 * st], ai = v[2 * st + 1];
+        const int crow = blk * RP + c0 + st;
         for (int tb = 0; tb < TA; ++tb) {
-          const int crow = blk * RP + kk + (lane >> 4);
-          const int ccol = tb * 16 + (lane & 15);
+          const int ccol = tb * 16 + i16;
           const T br = cre[crow * RP + ccol], bi = cim[crow * RP + ccol];
           ore[tb] = mfma(ar, br, ore[tb]);
           ore[tb] = mfma(-ai, bi, ore[tb]);
@@ -438,18 +449,16 @@ __global__ __launch_bounds__(kThreads) void k_combine(CombineArgs a) {
         }
       }
     }
-    __syncthreads();  // all reads of this tile's rows (incl. in-place block) done
+    // D[i][j] in lane j + 16 g, register v: row mfma_row(lane, v), column j = lane % 16
+#pragma unroll
     for (int tb = 0; tb < TA; ++tb) {
-      const int j = tb * 16 + (lane & 15);
+      const int j = tb * 16 + i16;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int i = wave * 16 + mfma_row<T>(lane, v);
-        const long long x = row0 + i;
-        if (j < r && x < N) {
-          C2 o;
-          o.x = ore[tb][v];
-          o.y = oim[tb][v];
-          out[x * r + j] = o;
+        const long long xo = tile * kTile + wave * 16 + mfma_row<T>(lane, v);
+        if (j < r && xo < N) {
+          out[2 * ((size_t)xo * r + j)] = ore[tb][v];
+          out[2 * ((size_t)xo * r + j) + 1] = oim[tb][v];
         }
       }
     }
@@ -638,17 +647,22 @@ void launch_combine(bool fp32, const void *const *blocks, int nblocks, const dou
   a.r = r;
   a.grid = grid;
   const int RP = pad16(r);
-  const size_t lds = (size_t)(2 * nblocks * RP * RP + 2 * kTile * RP) * (fp32 ? 4 : 8);
+  const size_t lds = (size_t)(2 * nblocks * RP * RP) * (fp32 ? 4 : 8);
   static bool attr = false;
   if (!attr) {
-    (void)hipFuncSetAttribute((const void *)k_combine<float>, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
-    (void)hipFuncSetAttribute((const void *)k_combine<double>, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+    (void)hipFuncSetAttribute((const void *)k_combine<float, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+    (void)hipFuncSetAttribute((const void *)k_combine<float, 32>, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+    (void)hipFuncSetAttribute((const void *)k_combine<double, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+    (void)hipFuncSetAttribute((const void *)k_combine<double, 32>, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
     attr = true;
   }
-  if (fp32)
-    hipLaunchKernelGGL(k_combine<float>, dim3(grid), dim3(kThreads), lds, s, a);
-  else
-    hipLaunchKernelGGL(k_combine<double>, dim3(grid), dim3(kThreads), lds, s, a);
+  if (fp32) {
+    if (RP == 16) hipLaunchKernelGGL((k_combine<float, 16>), dim3(grid), dim3(kThreads), lds, s, a);
+    else hipLaunchKernelGGL((k_combine<float, 32>), dim3(grid), dim3(kThreads), lds, s, a);
+  } else {
+    if (RP == 16) hipLaunchKernelGGL((k_combine<double, 16>), dim3(grid), dim3(kThreads), lds, s, a);
+    else hipLaunchKernelGGL((k_combine<double, 32>), dim3(grid), dim3(kThreads), lds, s, a);
+  }
 }
 
 void launch_reduce(const double2 *partials, int count, int len, double2 *out, hipStream_t s) {

@@ -273,6 +273,8 @@ struct TriShared {
   double2 e[kTriDim], ph[kTriDim], p[kTriDim];
   double lam[kMaxR];
   double glo, ghi, tnorm;
+  uint64_t tmark;
+  double tacc[4];  // real-time ticks: tridiagonalisation, multisection, inverse iteration, back-transform
 };
 
 // packed lower triangle, column-major: element (i, j), i >= j
@@ -286,12 +288,21 @@ __device__ inline double wave_sum_d(double v) {
   return v;
 }
 
+// 1/b from the hardware reciprocal refined by one Newton step (|b| >= pivmin,
+// so b is normal); within a couple of ulp of the correctly rounded quotient.
+__device__ inline double rcp_nr(double b) {
+  const double r = __builtin_amdgcn_rcp(b);
+  return r * fma(-b, r, 2.0);
+}
+
+// Number of eigenvalues of the real symmetric tridiagonal (d, e) below s, by
+// the ratio form of the Sturm sequence (pivots of LDL^T of T - s I).
 __device__ inline int sturm_count(const TriShared &ts, int m, double s, double pivmin) {
   double q = ts.d[0] - s;
   int c = q < 0.0;
   for (int i = 1; i < m; ++i) {
     if (fabs(q) < pivmin) q = -pivmin;
-    q = (ts.d[i] - s) - ts.e2[i - 1] / q;
+    q = (ts.d[i] - s) - ts.e2[i - 1] * rcp_nr(q);
     c += q < 0.0;
   }
   return c;
@@ -303,6 +314,15 @@ __device__ inline int sturm_count(const TriShared &ts, int m, double s, double p
 __device__ void eig_top(double2 *A, int m, int r, double2 *u, int ldu, int rows_out, double *scr, bool lds,
                         TriShared &ts) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  auto tlap = [&](int slot) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const uint64_t t = now_ticks();
+      ts.tacc[slot] += (double)(t - ts.tmark);
+      ts.tmark = t;
+    }
+  };
+  if (threadIdx.x == 0) ts.tmark = now_ticks();
   // ---- Householder tridiagonalisation
   for (int k = 0; k + 2 < m; ++k) {
     if (wave == 0) {
@@ -312,9 +332,11 @@ __device__ void eig_top(double2 *A, int m, int r, double2 *u, int ldu, int rows_
       if (lane == 0) {
         const double2 x0 = A[pl(k + 1, k, m)];
         const double nx = sqrt(s2), ax0 = sqrt(cabs2(x0));
-        if (nx == 0.0) {
+        if (!(s2 > 1e-300)) {
+          // column already reduced (below any meaningful scale): no reflector,
+          // the negligible remainder below the subdiagonal is dropped
           ts.beta[k] = 0.0;
-          ts.e[k] = make_double2(0, 0);
+          ts.e[k] = x0;
         } else {
           const double2 ph = ax0 > 0 ? cscale(1.0 / ax0, x0) : make_double2(1, 0);
           const double2 alpha = cscale(-nx, ph);
@@ -368,6 +390,7 @@ __device__ void eig_top(double2 *A, int m, int r, double2 *u, int ldu, int rows_
       if (lds) lds_barrier(); else __syncthreads();
     }
   }
+  tlap(0);
   // ---- real tridiagonal: d, |e|, phases
   if (threadIdx.x == 0) {
     if (m >= 2) ts.e[m - 2] = A[pl(m - 1, m - 2, m)];
@@ -394,18 +417,21 @@ __device__ void eig_top(double2 *A, int m, int r, double2 *u, int ldu, int rows_
     ts.ghi = hi + 1e-14 * ts.tnorm;
   }
   __syncthreads();
-  // ---- multisection: kGroup lanes per eigenvalue, all within one wave
+  // ---- multisection: G lanes per eigenvalue (32 when r <= 16, else 16), all
+  // within one wave; each round splits the bracket into G + 1 parts
   {
-    const int k = threadIdx.x / kGroup, t = threadIdx.x % kGroup;
+    const int G = r <= NT / 32 ? 32 : kGroup;
+    const int rounds = G == 32 ? 11 : 14;
+    const int k = threadIdx.x / G, t = threadIdx.x % G;
     const double pivmin = 1e-290;
     if (k < r) {
       double a = ts.glo, b = ts.ghi;
       const int target = m - 1 - k;
-      for (int round = 0; round < 14; ++round) {
-        const double x = a + (b - a) * (double)(t + 1) / (double)(kGroup + 1);
+      for (int round = 0; round < rounds; ++round) {
+        const double x = a + (b - a) * (double)(t + 1) / (double)(G + 1);
         const bool ok = sturm_count(ts, m, x, pivmin) <= target;  // lambda_target >= x
         double na = ok ? x : -1e300, nb = ok ? 1e300 : x;
-        for (int off = kGroup / 2; off > 0; off >>= 1) {
+        for (int off = G / 2; off > 0; off >>= 1) {
           na = fmax(na, __shfl_xor(na, off));
           nb = fmin(nb, __shfl_xor(nb, off));
         }
@@ -416,6 +442,7 @@ __device__ void eig_top(double2 *A, int m, int r, double2 *u, int ldu, int rows_
     }
   }
   __syncthreads();
+  tlap(1);
   // ---- inverse iteration (wave 0, lane k < r), interleaved per-lane arrays
   const int SL = r <= 16 ? 16 : 32;
   double *U0 = scr, *U1 = scr + m * SL, *U2 = scr + 2 * m * SL, *X = scr + 3 * m * SL;
@@ -426,7 +453,7 @@ __device__ void eig_top(double2 *A, int m, int r, double2 *u, int ldu, int rows_
     const double tiny = 1e-15 * ts.tnorm;
     if (act)
       for (int i = 0; i < m; ++i) X[i * SL + k] = 1.0 + 0.25 * (double)((7 * i + 3 * k) % 11);
-    for (int it = 0; it < 3; ++it) {
+    for (int it = 0; it < 2; ++it) {
       if (act) {
         double u0 = ts.d[0] - lam, u1 = m > 1 ? ts.ae[0] : 0.0, u2 = 0.0;
         double rc = X[0 * SL + k];
@@ -487,38 +514,63 @@ __device__ void eig_top(double2 *A, int m, int r, double2 *u, int ldu, int rows_
     }
   }
   __syncthreads();
-  // ---- back-transform: Y = Q (ph o X); columns are independent, one wave each
-  double2 *Y = reinterpret_cast<double2 *>(scr);  // m x r over U0/U1 (dead); X is the last quarter
-  for (int e = threadIdx.x; e < m * r; e += NT) {
-    const int i = e / r, c = e % r;
-    Y[e] = cscale(X[i * SL + c], ts.ph[i]);
-  }
-  __syncthreads();
-  for (int c = wave; c < r; c += NW) {
-    for (int k = m - 3; k >= 0; --k) {
-      const double beta = ts.beta[k];
-      if (beta == 0.0) continue;
-      double sr = 0, si = 0;
-      for (int i = k + 1 + lane; i < m; i += 64) {
-        const double2 t = cmulc(A[pl(i, k, m)], Y[i * r + c]);
-        sr += t.x;
-        si += t.y;
+  tlap(2);
+  // ---- back-transform: u = Q (ph o X), Q = H_0 ... H_{m-3}.  One half-wave per
+  // column: lane l of the half holds rows l, l + 32, ... in registers, so each
+  // reflector costs one half-wave reduction and no barrier.
+  {
+    const int half = threadIdx.x >> 5, hl = threadIdx.x & 31;
+    constexpr int kSlots = (kTriDim + 31) / 32;
+    for (int c = half; c < r; c += NT / 32) {
+      double2 y[kSlots];
+#pragma unroll
+      for (int q = 0; q < kSlots; ++q) {
+        const int l = hl + 32 * q;
+        y[q] = l < m ? cscale(X[l * SL + c], ts.ph[l]) : make_double2(0, 0);
       }
-      sr = wave_sum_d(sr);
-      si = wave_sum_d(si);
-      const double2 dt = make_double2(beta * sr, beta * si);
-      for (int i = k + 1 + lane; i < m; i += 64) Y[i * r + c] = csub(Y[i * r + c], cmul(A[pl(i, k, m)], dt));
+      for (int k = m - 3; k >= 0; --k) {
+        const double beta = ts.beta[k];
+        if (beta == 0.0) continue;
+        double sr = 0, si = 0;
+#pragma unroll
+        for (int q = 0; q < kSlots; ++q) {
+          const int l = hl + 32 * q;
+          if (l > k && l < m) {
+            const double2 t = cmulc(A[pl(l, k, m)], y[q]);
+            sr += t.x;
+            si += t.y;
+          }
+        }
+        for (int off = 16; off > 0; off >>= 1) {
+          sr += __shfl_xor(sr, off);
+          si += __shfl_xor(si, off);
+        }
+        const double2 f = make_double2(beta * sr, beta * si);
+#pragma unroll
+        for (int q = 0; q < kSlots; ++q) {
+          const int l = hl + 32 * q;
+          if (l > k && l < m) y[q] = csub(y[q], cmul(A[pl(l, k, m)], f));
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kSlots; ++q) {
+        const int l = hl + 32 * q;
+        if (l < rows_out) u[l * ldu + c] = l < m ? y[q] : make_double2(0, 0);
+      }
     }
   }
-  __syncthreads();
-  for (int e = threadIdx.x; e < rows_out * r; e += NT) {
-    const int i = e / r, c = e % r;
-    u[i * ldu + c] = i < m ? Y[i * r + c] : make_double2(0, 0);
-  }
-  __syncthreads();
+  tlap(3);
 }
 
 // ----- pieces shared by the RK and AB projected-step kernels -------------------
+
+// 1 if any of the n complex values is not finite (workgroup-uniform).
+__device__ int any_nonfinite(const double2 *x, int n) {
+  int bad = 0;
+  for (int e = threadIdx.x; e < n; e += NT)
+    if (!isfinite(x[e].x) || !isfinite(x[e].y)) bad = 1;
+  return __syncthreads_or(bad);
+}
 
 struct StepShared {
   JacobiShared js;
@@ -528,6 +580,7 @@ struct StepShared {
   unsigned char drop[kTriDim];
   double minpiv, dev;
   int ndrop;
+  double coef[kMaxAb];
 };
 
 // Cholesky Gamma = R* R (R upper, D x D row-major).  A direction whose pivot
@@ -690,7 +743,7 @@ __device__ void rhs_coords(const double2 *u, const double2 *y, int m, int D, int
         if (i == k) v = cadd(v, cscale(alpha, ph));
         U_[i * r + k] = v;
       }
-      if (threadIdx.x == 0) sh.hbeta[k] = alpha > 0 ? 1.0 / (alpha * alpha + alpha * ax0) : 0.0;
+      if (threadIdx.x == 0) sh.hbeta[k] = alpha > 1e-150 ? 1.0 / (alpha * alpha + alpha * ax0) : 0.0;
       __syncthreads();
       if (k + 1 < r) {
         col_dots(dots, U_ + k, r, Wk, r, m, r);
@@ -733,35 +786,69 @@ __device__ void rhs_coords(const double2 *u, const double2 *y, int m, int D, int
 
 // Packed (lower, column-major) Hermitian stage matrix of order m:
 // K = u1 diag(lam) u1* + sum_l coef_l (z_l u_l* + u_l w_l*)   (eqs. 3.7-3.9),
-// each term averaged with its adjoint so that K is Hermitian to the last bit.
+// formed as K = (P Q* + Q P*) / 2 over the factor pairs (P, Q) = (u1 diag(lam),
+// u1), (coef_l z_l, u_l), (coef_l u_l, w_l), so that K is Hermitian to the last
+// bit.  Lower 16 x 16 tiles, one per wave at a time, on FP64 MFMA with the
+// factor rows (m x r, row-major) read straight from memory.
 constexpr int kMaxTerms = 4;
+typedef double d4v_s __attribute__((ext_vector_type(4)));
+__device__ inline d4v_s mfma_d(double a, double b, d4v_s c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+// Term l's factors are u0 + l*su, z0 + l*sz, w0 + l*sw; coef[l] may be in LDS.
 __device__ void stage_matrix(double2 *K, int m, int r, const double2 *u1, const double *lam, int nterm,
-                             const double2 *const *ul_, const double2 *const *zl_, const double2 *const *wl_,
-                             const double *coef) {
-  for (int e = threadIdx.x; e < m * m; e += NT) {
-    const int a = e / m, b = e % m;
-    if (a < b) continue;
-    double sr = 0, si = 0;
-    for (int c = 0; c < r; ++c) {
-      const double2 x = cmul(u1[a * r + c], cconj(u1[b * r + c]));
-      sr += lam[c] * x.x;
-      si += lam[c] * x.y;
+                             const double2 *u0, size_t su, const double2 *z0, size_t sz, const double2 *w0,
+                             size_t sw, const double *coef) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int mt = (m + 15) / 16, ntile = mt * (mt + 1) / 2;
+  const int li = lane & 15, lk = lane >> 4;
+  for (int t = wave; t < ntile; t += NW) {
+    int ta = 0, rem = t;
+    while (rem > ta) {
+      rem -= ta + 1;
+      ++ta;
     }
-    for (int l = 0; l < nterm; ++l) {
-      if (coef[l] == 0.0) continue;
-      const double2 *ul = ul_[l], *zl = zl_[l], *wl = wl_[l];
-      double tr = 0, ti = 0;
-#pragma unroll 4
-      for (int c = 0; c < r; ++c) {
-        const double2 x1 = cadd(cmul(zl[a * r + c], cconj(ul[b * r + c])), cmul(ul[a * r + c], cconj(wl[b * r + c])));
-        const double2 x2 = cadd(cmul(zl[b * r + c], cconj(ul[a * r + c])), cmul(ul[b * r + c], cconj(wl[a * r + c])));
-        tr += 0.5 * (x1.x + x2.x);
-        ti += 0.5 * (x1.y - x2.y);
+    const int tb = rem;  // ta >= tb
+    d4v_s kre = {0, 0, 0, 0}, kim = {0, 0, 0, 0};
+    const int ra = ta * 16 + li, rb = tb * 16 + li;
+    for (int ch = 0; ch < 1 + 2 * nterm; ++ch) {
+      const double2 *P, *Q;
+      double sc = 1.0;
+      if (ch == 0) {
+        P = u1;
+        Q = u1;
+      } else {
+        const int l = (ch - 1) / 2;
+        sc = coef[l];
+        if (sc == 0.0) continue;
+        P = (ch & 1) ? z0 + l * sz : u0 + l * su;
+        Q = (ch & 1) ? u0 + l * su : w0 + l * sw;
       }
-      sr += coef[l] * tr;
-      si += coef[l] * ti;
+      for (int kk = 0; kk < r; kk += 4) {
+        const int c = kk + lk;
+        const double s = ch == 0 ? (c < r ? lam[c] : 0.0) : sc;
+        const bool ok = c < r;
+        const double2 z = make_double2(0, 0);
+        const double2 pa = (ok && ra < m) ? P[ra * r + c] : z, qa = (ok && ra < m) ? Q[ra * r + c] : z;
+        const double2 pb = (ok && rb < m) ? P[rb * r + c] : z, qb = (ok && rb < m) ? Q[rb * r + c] : z;
+        // (s pa) conj(qb) + qa conj(s pb)
+        const double a1r = s * pa.x, a1i = s * pa.y, b1r = qb.x, b1i = -qb.y;
+        const double a2r = qa.x, a2i = qa.y, b2r = s * pb.x, b2i = -s * pb.y;
+        kre = mfma_d(a1r, b1r, kre);
+        kre = mfma_d(-a1i, b1i, kre);
+        kim = mfma_d(a1r, b1i, kim);
+        kim = mfma_d(a1i, b1r, kim);
+        kre = mfma_d(a2r, b2r, kre);
+        kre = mfma_d(-a2i, b2i, kre);
+        kim = mfma_d(a2r, b2i, kim);
+        kim = mfma_d(a2i, b2r, kim);
+      }
     }
-    K[pl(a, b, m)] = make_double2(sr, a == b ? 0.0 : si);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = ta * 16 + 4 * v + lk, col = tb * 16 + li;
+      if (row < m && col <= row) K[pl(row, col, m)] = make_double2(0.5 * kre[v], row == col ? 0.0 : 0.5 * kim[v]);
+    }
   }
   __syncthreads();
 }
@@ -784,7 +871,7 @@ __device__ void householder_qr(double2 *M, int m, int q, double2 *Q, double2 *Rm
       if (i == k) v = cadd(v, cscale(alpha, ph));
       Vh[i * q + k] = v;
     }
-    if (threadIdx.x == 0) sh.hbeta[k] = alpha > 0 ? 1.0 / (alpha * alpha + alpha * ax0) : 0.0;
+    if (threadIdx.x == 0) sh.hbeta[k] = alpha > 1e-150 ? 1.0 / (alpha * alpha + alpha * ax0) : 0.0;
     __syncthreads();
     // columns c > k: M[:, c] -= beta v (v* M[:, c]); column k becomes -ph alpha e_k
     for (int c = k + 1 + (threadIdx.x >> 6); c < q; c += NW) {
@@ -848,6 +935,7 @@ __global__ __launch_bounds__(NT) void k_small_rk(SmallRkParams p, SmallWs ws) {
   if (threadIdx.x == 0) {
     s_tmark = now_ticks();
     for (int k = 0; k < 8; ++k) s_tacc[k] = 0.0;
+    for (int k = 0; k < 4; ++k) sh.ts.tacc[k] = 0.0;
   }
   auto lap = [&](int slot) {
     __syncthreads();
@@ -953,6 +1041,13 @@ __global__ __launch_bounds__(NT) void k_small_rk(SmallRkParams p, SmallWs ws) {
     lap(3);
     rhs_coords(u, y, mo, D, r, mc, p.householder_mode, z, w, Gr, X11, t1, Uh, Yc, s_arena, arena, sh,
                j == 0 ? &stats[5] : nullptr);
+    // first non-finite value: stats[28] = 10 * stage + phase (1 u, 2 y, 3 z/w, 4 K, 5 eigenvectors)
+    if (threadIdx.x == 0 && j == 0) stats[28] = -1;
+    {
+      const int f1 = any_nonfinite(u, D * r), f2 = any_nonfinite(y, D * r);
+      const int f3 = any_nonfinite(z, D * r) | any_nonfinite(w, D * r);
+      if (threadIdx.x == 0 && stats[28] < 0 && (f1 | f2 | f3)) stats[28] = 10 * j + (f1 ? 1 : (f2 ? 2 : 3));
+    }
     lap(4);
     // stage matrix (eqs. 3.7-3.9) and its top-r eigenvectors
     const bool last = (j + 1 == s);
@@ -962,18 +1057,24 @@ __global__ __launch_bounds__(NT) void k_small_rk(SmallRkParams p, SmallWs ws) {
     const bool jl = (npl + 2 * m * SL <= arena);
     double2 *K = jl ? s_arena : Kg;
     double *scr = jl ? reinterpret_cast<double *>(s_arena + npl) : reinterpret_cast<double *>(Vj);
-    const double2 *ul[kMaxTerms], *zl[kMaxTerms], *wl[kMaxTerms];
-    double coef[kMaxTerms];
-    for (int l = 0; l <= j; ++l) {
-      ul[l] = ws.stage + (3 * l + 0) * D * r;
-      zl[l] = ws.stage + (3 * l + 1) * D * r;
-      wl[l] = ws.stage + (3 * l + 2) * D * r;
-      coef[l] = h * (last ? p.b[l] : p.a[j + 1][l]);
-    }
-    stage_matrix(K, m, r, u1, p.lam, j + 1, ul, zl, wl, coef);
+    if (threadIdx.x <= j) sh.coef[threadIdx.x] = h * (last ? p.b[threadIdx.x] : p.a[j + 1][threadIdx.x]);
+    __syncthreads();
+    stage_matrix(K, m, r, u1, p.lam, j + 1, ws.stage, (size_t)3 * D * r, ws.stage + D * r, (size_t)3 * D * r,
+                 ws.stage + 2 * D * r, (size_t)3 * D * r, sh.coef);
     lap(5);
     double2 *unext = last ? ws.Cfin /* temporary */ : ws.stage + (3 * (j + 1) + 0) * D * r;
+    {
+      int fk = 0;
+      for (int e = threadIdx.x; e < m * (m + 1) / 2; e += NT)
+        if (!isfinite(K[e].x) || !isfinite(K[e].y)) fk = 1;
+      fk = __syncthreads_or(fk);
+      if (threadIdx.x == 0 && stats[28] < 0 && fk) stats[28] = 10 * j + 4;
+    }
     eig_top(K, m, r, unext, r, D, scr, jl, sh.ts);
+    {
+      const int fe = any_nonfinite(unext, D * r);
+      if (threadIdx.x == 0 && stats[28] < 0 && fe) stats[28] = 10 * j + 5;
+    }
     lap(6);
     if (last) {
       for (int e = threadIdx.x; e < D * r; e += NT) t1[e] = ws.Cfin[e];
@@ -989,6 +1090,7 @@ __global__ __launch_bounds__(NT) void k_small_rk(SmallRkParams p, SmallWs ws) {
   const int bad = __syncthreads_or(bad_local);
   if (threadIdx.x == 0) {
     for (int k = 0; k < 8; ++k) stats[16 + k] += s_tacc[k] * 1e-5;  // ms
+    for (int k = 0; k < 4; ++k) stats[24 + k] += sh.ts.tacc[k] * 1e-5;
     stats[0] = 0;
     stats[1] = 0;
     stats[2] = sh.ndrop;
@@ -1053,6 +1155,8 @@ __global__ __launch_bounds__(NT) void k_small_ab(SmallAbParams p, SmallAbWs ws) 
   double2 *Sg = Kg + D * D;             // D x D scratch (eigensolver, global fallback)
   double2 *X11 = Sg + D * D, *Gr = X11 + rr, *tmp = Gr + rr, *Lw = tmp + rr;
   double *stats = ws.stats;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 4; ++k) sh.ts.tacc[k] = 0.0;
 
   // ---- Gram of B = [U, Y] from the measured products
   for (int e = threadIdx.x; e < D * D; e += NT) {
@@ -1143,23 +1247,19 @@ __global__ __launch_bounds__(NT) void k_small_ab(SmallAbParams p, SmallAbWs ws) 
       coord_u(cu + (2 * l) * D * r, vc_in + (1 + 2 * (l - 1)) * DU * r);
       coord_u(cu + (2 * l + 1) * D * r, vc_in + (2 + 2 * (l - 1)) * DU * r);
     }
-    const double2 *ul[kMaxTerms], *zl[kMaxTerms], *wl[kMaxTerms];
-    double coef[kMaxTerms];
-    for (int l = 0; l < m; ++l) {
+    for (int l = 0; l < m; ++l)
       rhs_coords(cu + (2 * l) * D * r, cu + (2 * l + 1) * D * r, D, D, r, mc, p.householder_mode,
                  cz + (2 * l) * D * r, cz + (2 * l + 1) * D * r, Gr, X11, t1, Uh, Yc, s_arena, arena, sh,
                  l == 0 ? &stats[5] : nullptr);
-      ul[l] = cu + (2 * l) * D * r;
-      zl[l] = cz + (2 * l) * D * r;
-      wl[l] = cz + (2 * l + 1) * D * r;
-      coef[l] = p.h * p.bcoef[l];
-    }
+    if (threadIdx.x < m) sh.coef[threadIdx.x] = p.h * p.bcoef[threadIdx.x];
+    __syncthreads();
     const int SL = r <= 16 ? 16 : 32;
     const int npl = D * (D + 1) / 2;
     const bool jl = (npl + 2 * D * SL <= arena);
     double2 *K = jl ? s_arena : Kg;
     double *scr = jl ? reinterpret_cast<double *>(s_arena + npl) : reinterpret_cast<double *>(Sg);
-    stage_matrix(K, D, r, u0, p.lam, m, ul, zl, wl, coef);
+    stage_matrix(K, D, r, u0, p.lam, m, cu, (size_t)2 * D * r, cz, (size_t)2 * D * r, cz + D * r,
+                 (size_t)2 * D * r, sh.coef);
     eig_top(K, D, r, unew, r, D, scr, jl, sh.ts);
   } else {
     coord_x(unew, p.x_vnew, 1.0);

@@ -36,11 +36,13 @@ class lrei_stats(ctypes.Structure):
                 ("dropped_directions", ctypes.c_int32), ("min_pivot_ratio", ctypes.c_double),
                 ("ortho_error", ctypes.c_double), ("energy", ctypes.c_double),
                 ("last_step_ms", ctypes.c_double), ("warm_accepted", ctypes.c_int64),
-                ("warm_rejected", ctypes.c_int64), ("phase_ms", ctypes.c_double * 8)]
+                ("warm_rejected", ctypes.c_int64), ("phase_ms", ctypes.c_double * 8),
+                ("eig_phase_ms", ctypes.c_double * 4)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
         d["phase_ms"] = list(self.phase_ms)
+        d["eig_phase_ms"] = list(self.eig_phase_ms)
         return d
 
 
