@@ -203,7 +203,8 @@ def main():
             ["gram_setup", "cholesky", "r_inverse", "h_apply", "householder", "stage_matrix", "eigensolve", "tail"],
             [round(v / args.steps, 4) for v in stats["phase_ms"]])),
         "eigensolve_parts_ms_per_step": dict(zip(
-            ["tridiagonalisation", "multisection", "inverse_iteration", "back_transform"],
+            ["tridiagonalisation", "multisection", "inverse_iteration", "back_transform",
+             "tridiag_Av", "tridiag_update"],
             [round(v / args.steps, 4) for v in stats["eig_phase_ms"]])),
     }
     print(json.dumps(line))

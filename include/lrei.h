@@ -98,9 +98,11 @@ typedef struct {
   double phase_ms[8];            /* projected-step kernel time by phase over the last
                                     call: Gram/Cholesky setup, Cholesky, R^-1, H u,
                                     Householder, stage matrix, eigensolve, tail      */
-  double eig_phase_ms[4];        /* eigensolve time over the last call by part:
+  double eig_phase_ms[6];        /* eigensolve time over the last call by part:
                                     tridiagonalisation, multisection, inverse
-                                    iteration, back-transform                       */
+                                    iteration, back-transform; and of the
+                                    tridiagonalisation: its A v products, its
+                                    rank-2 updates                                  */
 } lrei_stats;
 
 /* Fills *opt with the defaults listed above. */

@@ -812,6 +812,8 @@ lrei_status lrei_step(lrei_ctx *ctx, int model, int scheme, double dt, double ka
   ctx->stats.last_step_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
   for (int k = 0; k < 8; ++k) ctx->stats.phase_ms[k] = h[16 + k];
   for (int k = 0; k < 4; ++k) ctx->stats.eig_phase_ms[k] = h[24 + k];
+  ctx->stats.eig_phase_ms[4] = h[29];
+  ctx->stats.eig_phase_ms[5] = h[30];
   return LREI_OK;
 }
 

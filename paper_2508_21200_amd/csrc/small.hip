@@ -57,13 +57,56 @@ __device__ inline double2 cdiv(double2 a, double2 b) {
 // Barrier for LDS traffic only: global memory operations may stay in flight.
 __device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
-__device__ inline double2 wave_sum(double2 v) {
-  for (int off = 32; off > 0; off >>= 1) {
-    v.x += __shfl_xor(v.x, off);
-    v.y += __shfl_xor(v.y, off);
-  }
+// Cross-lane reductions on DPP row operations (quad_perm, row_half_mirror,
+// row_mirror within 16 lanes), a swizzle for the swap of 16-lane halves, and
+// readlane across the two halves of the wave.  Every lane of the group must
+// be active.  Results are identical in all lanes of the group.
+template <int CTRL>
+__device__ inline double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ inline double swap16_d(double v) {  // lane i <-> lane i ^ 16 within each 32 lanes
+  const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), 0x401F);
+  const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), 0x401F);
+  return __hiloint2double(hi, lo);
+}
+__device__ inline double readlane_d(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+__device__ inline double sum16(double v) {
+  v += dpp_d<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_d<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_d<0x141>(v);  // row_half_mirror
+  v += dpp_d<0x140>(v);  // row_mirror
   return v;
 }
+__device__ inline double sum32(double v) {
+  v = sum16(v);
+  return v + swap16_d(v);
+}
+__device__ inline double sum64(double v) {
+  v = sum32(v);
+  return readlane_d(v, 0) + readlane_d(v, 32);
+}
+__device__ inline double max16(double v) {
+  v = fmax(v, dpp_d<0xB1>(v));
+  v = fmax(v, dpp_d<0x4E>(v));
+  v = fmax(v, dpp_d<0x141>(v));
+  return fmax(v, dpp_d<0x140>(v));
+}
+__device__ inline double min16(double v) {
+  v = fmin(v, dpp_d<0xB1>(v));
+  v = fmin(v, dpp_d<0x4E>(v));
+  v = fmin(v, dpp_d<0x141>(v));
+  return fmin(v, dpp_d<0x140>(v));
+}
+__device__ inline double max32(double v) { v = max16(v); return fmax(v, swap16_d(v)); }
+__device__ inline double min32(double v) { v = min16(v); return fmin(v, swap16_d(v)); }
+
+__device__ inline double2 wave_sum(double2 v) { return make_double2(sum64(v.x), sum64(v.y)); }
 
 // phi(delta): q-LL (delta/hbar)(i - kappa delta) (eq. 4.1); q-LLG (i delta/hbar)/(1 - i kappa delta)
 // (eq. 3.2: D / (E + L + L*)).  X11_ab = phi(lam_a - lam_b) G_ab, X12 = diag(phi(lam)) V* H Vhat.
@@ -270,11 +313,13 @@ constexpr int kGroup = 16;                         // lanes per eigenvalue in th
 
 struct TriShared {
   double d[kTriDim], e2[kTriDim], ae[kTriDim], beta[kTriDim];
-  double2 e[kTriDim], ph[kTriDim], p[kTriDim];
+  double2 e[kTriDim], ph[kTriDim], p[kTriDim], v[kTriDim];
+  double2 kpart[NT / 32];
   double lam[kMaxR];
   double glo, ghi, tnorm;
   uint64_t tmark;
-  double tacc[4];  // real-time ticks: tridiagonalisation, multisection, inverse iteration, back-transform
+  double tacc[7];  // real-time ticks: tridiagonalisation, multisection, inverse iteration, back-transform,
+                   // and inside the tridiagonalisation: reflector, A v, rank-2 update
 };
 
 // packed lower triangle, column-major: element (i, j), i >= j
@@ -283,10 +328,7 @@ __device__ inline double2 lget(const double2 *A, int i, int j, int m) {
   return i >= j ? A[pl(i, j, m)] : cconj(A[pl(j, i, m)]);
 }
 
-__device__ inline double wave_sum_d(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  return v;
-}
+__device__ inline double wave_sum_d(double v) { return sum64(v); }
 
 // 1/b from the hardware reciprocal refined by one Newton step (|b| >= pivmin,
 // so b is normal); within a couple of ulp of the correctly rounded quotient.
@@ -323,11 +365,17 @@ __device__ void eig_top(double2 *A, int m, int r, double2 *u, int ldu, int rows_
     }
   };
   if (threadIdx.x == 0) ts.tmark = now_ticks();
-  // ---- Householder tridiagonalisation
+  // ---- Householder tridiagonalisation.  Threads form a 16 x 32 grid: half-wave
+  // hw owns rows k+1+hw, +16, ...; its lane hl walks columns k+1+hl, +32, ...
+  const int hw = threadIdx.x >> 5, hl = threadIdx.x & 31;
   for (int k = 0; k + 2 < m; ++k) {
     if (wave == 0) {
       double s2 = 0;
-      for (int i = k + 1 + lane; i < m; i += 64) s2 += cabs2(A[pl(i, k, m)]);
+      for (int i = k + 1 + lane; i < m; i += 64) {
+        const double2 x = A[pl(i, k, m)];
+        s2 += cabs2(x);
+        ts.v[i] = x;
+      }
       s2 = wave_sum_d(s2);
       if (lane == 0) {
         const double2 x0 = A[pl(k + 1, k, m)];
@@ -344,50 +392,56 @@ __device__ void eig_top(double2 *A, int m, int r, double2 *u, int ldu, int rows_
           const double vv = s2 - ax0 * ax0 + cabs2(v0);
           ts.beta[k] = 2.0 / vv;
           ts.e[k] = alpha;
-          A[pl(k + 1, k, m)] = v0;
+          A[pl(k + 1, k, m)] = v0;  // the reflector vector stays in column k
+          ts.v[k + 1] = v0;
         }
       }
     }
     if (lds) lds_barrier(); else __syncthreads();
+    uint64_t t_a = 0;
+    if (threadIdx.x == 0) t_a = now_ticks();
     const double beta = ts.beta[k];
     if (beta != 0.0) {
-      // p = beta A22 v, eight lanes per row
-      const int g = threadIdx.x >> 3, sub = threadIdx.x & 7;
-      for (int i = k + 1 + g; i < m; i += NT / 8) {
+      // p = beta A22 v: half-wave rows, lane-strided columns, half-wave reduction
+      double2 kp = make_double2(0, 0);
+      for (int i = k + 1 + hw; i < m; i += NT / 32) {
         double sr = 0, si = 0;
-        for (int j = k + 1 + sub; j < m; j += 8) {
-          const double2 a = lget(A, i, j, m), v = A[pl(j, k, m)];
+        for (int j = k + 1 + hl; j < m; j += 32) {
+          const int hi = i > j ? i : j, lo = i > j ? j : i;
+          double2 a = A[pl(hi, lo, m)];
+          if (i < j) a.y = -a.y;
+          const double2 v = ts.v[j];
           sr += a.x * v.x - a.y * v.y;
           si += a.x * v.y + a.y * v.x;
         }
-        for (int off = 4; off > 0; off >>= 1) {
-          sr += __shfl_xor(sr, off);
-          si += __shfl_xor(si, off);
-        }
-        if (sub == 0) ts.p[i] = make_double2(beta * sr, beta * si);
+        sr = sum32(sr);
+        si = sum32(si);
+        const double2 pi = make_double2(beta * sr, beta * si);
+        if (hl == 0) ts.p[i] = pi;
+        kp = cadd(kp, cmulc(ts.v[i], pi));
       }
+      if (hl == 0) ts.kpart[hw] = kp;
       if (lds) lds_barrier(); else __syncthreads();
-      // K = (beta/2) v^H p, redundantly per wave; w = p - K v
-      double kr = 0, ki = 0;
-      for (int i = k + 1 + lane; i < m; i += 64) {
-        const double2 t = cmulc(A[pl(i, k, m)], ts.p[i]);
-        kr += t.x;
-        ki += t.y;
+      uint64_t t_b = 0;
+      if (threadIdx.x == 0) {
+        t_b = now_ticks();
+        ts.tacc[5] += (double)(t_b - t_a);
       }
-      kr = wave_sum_d(kr);
-      ki = wave_sum_d(ki);
-      const double2 K = make_double2(0.5 * beta * kr, 0.5 * beta * ki);
+      // K = (beta/2) v^H p (fixed summation order); w = p - K v
+      double2 ks = make_double2(0, 0);
+      for (int q = 0; q < NT / 32; ++q) ks = cadd(ks, ts.kpart[q]);
+      const double2 K = cscale(0.5 * beta, ks);
       // lower triangle of the trailing block: A_ij -= v_i conj(w_j) + w_i conj(v_j)
-      const int n2 = m - k - 1;
-      for (int e = threadIdx.x; e < n2 * n2; e += NT) {
-        const int i = k + 1 + e / n2, j = k + 1 + e % n2;
-        if (i < j) continue;
-        const double2 vi = A[pl(i, k, m)], vj = A[pl(j, k, m)];
-        const double2 wi = csub(ts.p[i], cmul(K, vi)), wj = csub(ts.p[j], cmul(K, vj));
-        const int q = pl(i, j, m);
-        A[q] = csub(A[q], cadd(cmul(vi, cconj(wj)), cmul(wi, cconj(vj))));
+      for (int i = k + 1 + hw; i < m; i += NT / 32) {
+        const double2 vi = ts.v[i], wi = csub(ts.p[i], cmul(K, vi));
+        for (int j = k + 1 + hl; j <= i; j += 32) {
+          const double2 vj = ts.v[j], wj = csub(ts.p[j], cmul(K, vj));
+          const int q = pl(i, j, m);
+          A[q] = csub(A[q], cadd(cmul(vi, cconj(wj)), cmul(wi, cconj(vj))));
+        }
       }
       if (lds) lds_barrier(); else __syncthreads();
+      if (threadIdx.x == 0) ts.tacc[6] += (double)(now_ticks() - t_b);
     }
   }
   tlap(0);
@@ -431,9 +485,12 @@ __device__ void eig_top(double2 *A, int m, int r, double2 *u, int ldu, int rows_
         const double x = a + (b - a) * (double)(t + 1) / (double)(G + 1);
         const bool ok = sturm_count(ts, m, x, pivmin) <= target;  // lambda_target >= x
         double na = ok ? x : -1e300, nb = ok ? 1e300 : x;
-        for (int off = G / 2; off > 0; off >>= 1) {
-          na = fmax(na, __shfl_xor(na, off));
-          nb = fmin(nb, __shfl_xor(nb, off));
+        if (G == 32) {
+          na = max32(na);
+          nb = min32(nb);
+        } else {
+          na = max16(na);
+          nb = min16(nb);
         }
         if (na > -1e300) a = na;
         if (nb < 1e300) b = nb;
@@ -541,10 +598,8 @@ __device__ void eig_top(double2 *A, int m, int r, double2 *u, int ldu, int rows_
             si += t.y;
           }
         }
-        for (int off = 16; off > 0; off >>= 1) {
-          sr += __shfl_xor(sr, off);
-          si += __shfl_xor(si, off);
-        }
+        sr = sum32(sr);
+        si = sum32(si);
         const double2 f = make_double2(beta * sr, beta * si);
 #pragma unroll
         for (int q = 0; q < kSlots; ++q) {
@@ -721,8 +776,106 @@ __device__ void rhs_coords(const double2 *u, const double2 *y, int m, int D, int
     *energy = en;
   }
   __syncthreads();
-  if (hmode == 1) {
-    // Householder vectors of u (m x r), eq. (3.3); work arrays in LDS when they fit
+  if (hmode == 1 && r <= NT / 32 && m <= kTriDim) {
+    // Householder vectors of u (m x r), eq. (3.3).  Half-wave c owns column c
+    // of u (and later of y diag(conj c)) in registers, rows lane + 32 q; the
+    // reflector vectors go to Vr (LDS when they fit), one barrier per reflector.
+    constexpr int kS = (kTriDim + 31) / 32;
+    const int hw = threadIdx.x >> 5, hl = threadIdx.x & 31, hbase = threadIdx.x & 32;
+    const bool own = hw < r;
+    double2 *Vr = (m * r <= arena_elems) ? arena : Uh;
+    double2 x[kS];
+#pragma unroll
+    for (int q = 0; q < kS; ++q) {
+      const int l = hl + 32 * q;
+      x[q] = (own && l < m) ? u[l * r + hw] : make_double2(0, 0);
+    }
+    auto hsum = [&](double2 v) { return make_double2(sum32(v.x), sum32(v.y)); };
+    for (int k = 0; k < r; ++k) {
+      if (hw == k) {
+        double s2 = 0;
+#pragma unroll
+        for (int q = 0; q < kS; ++q) {
+          const int l = hl + 32 * q;
+          if (l >= k && l < m) s2 += cabs2(x[q]);
+        }
+        s2 = sum32(s2);
+        const double alpha = sqrt(s2);
+        // x0 = row k of this column, held by lane k % 32 of the half-wave, slot k / 32
+        double2 x0 = make_double2(0, 0);
+#pragma unroll
+        for (int q = 0; q < kS; ++q)
+          if (q == k / 32) x0 = x[q];
+        x0.x = __shfl(x0.x, hbase | (k & 31));
+        x0.y = __shfl(x0.y, hbase | (k & 31));
+        const double ax0 = sqrt(cabs2(x0));
+        const double2 ph = ax0 > 0 ? cscale(1.0 / ax0, x0) : make_double2(1, 0);
+#pragma unroll
+        for (int q = 0; q < kS; ++q) {
+          const int l = hl + 32 * q;
+          if (l < m) {
+            double2 v = l < k ? make_double2(0, 0) : x[q];
+            if (l == k) v = cadd(v, cscale(alpha, ph));
+            Vr[l * r + k] = v;
+          }
+        }
+        if (hl == 0) sh.hbeta[k] = alpha > 1e-150 ? 1.0 / (alpha * alpha + alpha * ax0) : 0.0;
+      }
+      __syncthreads();
+      if (own && hw > k) {  // apply P_k to the remaining columns
+        double2 d = make_double2(0, 0);
+#pragma unroll
+        for (int q = 0; q < kS; ++q) {
+          const int l = hl + 32 * q;
+          if (l >= k && l < m) d = cadd(d, cmulc(Vr[l * r + k], x[q]));
+        }
+        d = cscale(sh.hbeta[k], hsum(d));
+#pragma unroll
+        for (int q = 0; q < kS; ++q) {
+          const int l = hl + 32 * q;
+          if (l >= k && l < m) x[q] = csub(x[q], cmul(Vr[l * r + k], d));
+        }
+      }
+    }
+    // w = Q [0; (Q^H y diag(conj c))_{r:}]: P_0 first, zero rows < r, then P_{r-1} first
+    if (own) {
+      const double2 cc = cconj(cvec[hw]);
+#pragma unroll
+      for (int q = 0; q < kS; ++q) {
+        const int l = hl + 32 * q;
+        x[q] = l < m ? cmul(y[l * r + hw], cc) : make_double2(0, 0);
+      }
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int kk = 0; kk < r; ++kk) {
+          const int k = pass == 0 ? kk : r - 1 - kk;
+          double2 d = make_double2(0, 0);
+#pragma unroll
+          for (int q = 0; q < kS; ++q) {
+            const int l = hl + 32 * q;
+            if (l >= k && l < m) d = cadd(d, cmulc(Vr[l * r + k], x[q]));
+          }
+          d = cscale(sh.hbeta[k], hsum(d));
+#pragma unroll
+          for (int q = 0; q < kS; ++q) {
+            const int l = hl + 32 * q;
+            if (l >= k && l < m) x[q] = csub(x[q], cmul(Vr[l * r + k], d));
+          }
+        }
+        if (pass == 0) {
+#pragma unroll
+          for (int q = 0; q < kS; ++q)
+            if (hl + 32 * q < r) x[q] = make_double2(0, 0);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kS; ++q) {
+        const int l = hl + 32 * q;
+        if (l < D) w[l * r + hw] = l < m ? x[q] : make_double2(0, 0);
+      }
+    }
+  } else if (hmode == 1) {
+    // Householder vectors of u (m x r), eq. (3.3), column-parallel form (r > 16);
+    // work arrays in LDS when they fit
     const bool hl = 3 * m * r <= arena_elems;
     double2 *Wk = hl ? arena : w;
     double2 *U_ = hl ? arena + m * r : Uh;
@@ -935,7 +1088,7 @@ __global__ __launch_bounds__(NT) void k_small_rk(SmallRkParams p, SmallWs ws) {
   if (threadIdx.x == 0) {
     s_tmark = now_ticks();
     for (int k = 0; k < 8; ++k) s_tacc[k] = 0.0;
-    for (int k = 0; k < 4; ++k) sh.ts.tacc[k] = 0.0;
+    for (int k = 0; k < 7; ++k) sh.ts.tacc[k] = 0.0;
   }
   auto lap = [&](int slot) {
     __syncthreads();
@@ -1091,6 +1244,8 @@ __global__ __launch_bounds__(NT) void k_small_rk(SmallRkParams p, SmallWs ws) {
   if (threadIdx.x == 0) {
     for (int k = 0; k < 8; ++k) stats[16 + k] += s_tacc[k] * 1e-5;  // ms
     for (int k = 0; k < 4; ++k) stats[24 + k] += sh.ts.tacc[k] * 1e-5;
+    stats[29] += sh.ts.tacc[5] * 1e-5;
+    stats[30] += sh.ts.tacc[6] * 1e-5;
     stats[0] = 0;
     stats[1] = 0;
     stats[2] = sh.ndrop;
@@ -1156,7 +1311,7 @@ __global__ __launch_bounds__(NT) void k_small_ab(SmallAbParams p, SmallAbWs ws) 
   double2 *X11 = Sg + D * D, *Gr = X11 + rr, *tmp = Gr + rr, *Lw = tmp + rr;
   double *stats = ws.stats;
   if (threadIdx.x == 0)
-    for (int k = 0; k < 4; ++k) sh.ts.tacc[k] = 0.0;
+    for (int k = 0; k < 7; ++k) sh.ts.tacc[k] = 0.0;
 
   // ---- Gram of B = [U, Y] from the measured products
   for (int e = threadIdx.x; e < D * D; e += NT) {

@@ -37,7 +37,7 @@ class lrei_stats(ctypes.Structure):
                 ("ortho_error", ctypes.c_double), ("energy", ctypes.c_double),
                 ("last_step_ms", ctypes.c_double), ("warm_accepted", ctypes.c_int64),
                 ("warm_rejected", ctypes.c_int64), ("phase_ms", ctypes.c_double * 8),
-                ("eig_phase_ms", ctypes.c_double * 4)]
+                ("eig_phase_ms", ctypes.c_double * 6)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}

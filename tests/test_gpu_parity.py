@@ -380,3 +380,23 @@ def test_autotune_keeps_results_and_caches(tmp_path):
     assert t2["from_cache"] is True and (t2["epl"], t2["grid"]) == (t1["epl"], t1["grid"])
     assert rel_fro_error(V1, cfg["lam"], V0, cfg["lam"]) < 1e-12
     assert np.array_equal(V1, V2)
+
+
+@pytest.mark.parametrize("r,hmode", [(20, 1), (20, 0), (32, 1)])
+def test_rk4_large_rank(r, hmode):
+    """r > 16: the column-parallel Householder path and projected problems up to order 5 r = 160."""
+    n = 9
+    rng = np.random.default_rng(900 + r + hmode)
+    bonds, J, h = _random_model(n, rng)
+    V = haar_factor(2 ** n, r, rng)
+    lam = dirichlet_spectrum(r, rng)
+    ctx = _ctx(householder_mode=hmode)
+    ctx.set_hamiltonian(n, bonds, J, h)
+    ctx.set_rho(lam, V)
+    ctx.step("qLLG", "RK4", 0.01, 0.3, 2)
+    _, Vg = ctx.get_rho()
+    H = Hamiltonian(n, bonds, J, h)
+    Vo = oracle_run(H, V, lam, "qLLG", 0.3, 0.01, 2, "RK4")
+    err = rel_fro_error(Vg, lam, Vo, lam)
+    print(f"r={r} hmode={hmode}: {err:.3e}")
+    assert err < 1e-11
