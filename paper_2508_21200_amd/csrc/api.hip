@@ -66,6 +66,9 @@ struct lrei_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  // the projected-step stages run on a second stream, each after its pass
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_pass[kMaxStages] = {};
   lrei_options opt{};
   std::string err;
 
@@ -164,7 +167,8 @@ lrei_status alloc_state(lrei_ctx *ctx, int r, bool fp32) {
                           + 4 * (size_t)D * D                  // gamma, R, Rinv, Hh
                           + (4 * (size_t)D * r + 2 * (size_t)D * D + 4 * (size_t)r * r)  // work
                           + (size_t)kMaxStages * 3 * D * r     // stage
-                          + (size_t)D * r;                     // Cfin
+                          + (size_t)D * r                      // Cfin
+                          + (size_t)D;                         // flags (as complex slots)
   if (!ctx->ws_buf.ensure(ws_elems * sizeof(double2))) return ctx->fail(LREI_E_NOMEM, "device allocation failed");
   if (!ctx->stats_buf.ensure(kStatsLen * sizeof(double))) return ctx->fail(LREI_E_NOMEM, "device allocation failed");
   if (!ctx->lam_dev.ensure(kMaxR * sizeof(double))) return ctx->fail(LREI_E_NOMEM, "device allocation failed");
@@ -176,7 +180,8 @@ lrei_status alloc_state(lrei_ctx *ctx, int r, bool fp32) {
   ctx->ws.Hh = w; w += (size_t)D * D;
   ctx->ws.work = w; w += 4 * (size_t)D * r + 2 * (size_t)D * D + 4 * (size_t)r * r;
   ctx->ws.stage = w; w += (size_t)kMaxStages * 3 * D * r;
-  ctx->ws.Cfin = w;
+  ctx->ws.Cfin = w; w += (size_t)D * r;
+  ctx->ws.flags = (double *)w;
   ctx->ws.stats = (double *)ctx->stats_buf.p;
   return LREI_OK;
 }
@@ -239,13 +244,26 @@ SmallRkParams rk_params(lrei_ctx *ctx, int model, int scheme, double dt, double 
   return p;
 }
 
-// Enqueues one LREI-RK step (Chebyshev Krylov passes, projected step, combine).
+// Enqueues one LREI-RK step: the Chebyshev Krylov passes on the context
+// stream; projected-step stage j on the side stream as soon as pass j is
+// reduced (it needs the Grams of P_0 .. P_{j+1} only), overlapping the later
+// passes; the combination after the last stage.
 void enqueue_rk_step(lrei_ctx *ctx, int model, int scheme, double dt, double kappa) {
   const SmallRkParams p = rk_params(ctx, model, scheme, dt, kappa);
   const int s = p.s;
-  cheb_pass(ctx, 0, nullptr, ctx->blocks[0].p, ctx->blocks[1].p, 0);
-  for (int j = 1; j < s; ++j) cheb_pass(ctx, 1, ctx->blocks[j - 1].p, ctx->blocks[j].p, ctx->blocks[j + 1].p, j);
-  launch_small_rk(p, ctx->ws, ctx->stream);
+  (void)hipEventRecord(ctx->ev_fork, ctx->stream);
+  (void)hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0);
+  for (int j = 0; j < s; ++j) {
+    if (j == 0)
+      cheb_pass(ctx, 0, nullptr, ctx->blocks[0].p, ctx->blocks[1].p, 0);
+    else
+      cheb_pass(ctx, 1, ctx->blocks[j - 1].p, ctx->blocks[j].p, ctx->blocks[j + 1].p, j);
+    (void)hipEventRecord(ctx->ev_pass[j], ctx->stream);
+    (void)hipStreamWaitEvent(ctx->side, ctx->ev_pass[j], 0);
+    launch_small_rk_stage(p, ctx->ws, j, ctx->side);
+  }
+  (void)hipEventRecord(ctx->ev_join, ctx->side);
+  (void)hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0);
   const void *bl[kMaxBlocks];
   for (int i = 0; i <= s; ++i) bl[i] = ctx->blocks[i].p;
   launch_combine(ctx->fp32, bl, s + 1, ctx->ws.Cfin, ctx->blocks[0].p, ctx->N, ctx->r, ctx->grid, ctx->stream);
@@ -497,6 +515,14 @@ lrei_status lrei_create(lrei_ctx **out, int hip_device, void *hip_stream, const 
     }
     ctx->own_stream = true;
   }
+  bool ok = hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) == hipSuccess &&
+            hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming) == hipSuccess;
+  for (auto &e : ctx->ev_pass) ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    lrei_destroy(ctx);
+    return LREI_E_DEVICE;
+  }
   *out = ctx;
   return LREI_OK;
 }
@@ -527,6 +553,14 @@ void lrei_destroy(lrei_ctx *ctx) {
   ctx->ab_Cc.release();
   ctx->ab_work.release();
   ctx->ab_partials.release();
+  if (ctx->side) {
+    (void)hipStreamSynchronize(ctx->side);
+    (void)hipStreamDestroy(ctx->side);
+  }
+  if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+  if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+  for (auto &e : ctx->ev_pass)
+    if (e) (void)hipEventDestroy(e);
   if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
 }

@@ -136,7 +136,8 @@ struct SmallWs {
   double2 *work;     // [8*D*D] scratch
   double2 *stage;    // [kMaxStages][3][D*r] u, z, w per stage
   double2 *Cfin;     // [D*r] combination coefficients for the new V
-  double *stats;     // [16]
+  double *flags;     // [D] directions dropped as dependent
+  double *stats;     // [32]
 };
 
 // LDS arena of the projected-step kernel: an 80 x 80 Cholesky factor, or the
@@ -155,6 +156,7 @@ inline int small_lds_elems(int D, int r) {
   return need < kSmallLdsElems ? need : kSmallLdsElems;
 }
 void launch_small_rk(const SmallRkParams &p, const SmallWs &ws, hipStream_t s);
+void launch_small_rk_stage(const SmallRkParams &p, const SmallWs &ws, int j, hipStream_t s);
 
 // Projected AB step / history update (small.hip).
 constexpr int kMaxAb = 4;  // AB4

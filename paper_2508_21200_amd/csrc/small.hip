@@ -118,36 +118,37 @@ __device__ inline double2 phi(double d, int model, double kappa, double hbar) {
 
 // ----- workgroup-wide small dense helpers (row-major, leading dimension ld) ---
 
-// C (m x n) = A (m x k) * B (k x n); upper_a: A is upper triangular (skip q < i)
-__device__ void gemm_nn(double2 *C, int ldc, const double2 *A, int lda, const double2 *B, int ldb, int m,
-                        int n, int k, bool upper_a = false) {
-  for (int e = threadIdx.x; e < m * n; e += NT) {
-    const int i = e / n, j = e % n;
-    double sr = 0, si = 0;
-    const int q0 = upper_a ? i : 0;
-#pragma unroll 8
-    for (int q = q0; q < k; ++q) {
-      const double2 a = A[i * lda + q], b = B[q * ldb + j];
-      sr += a.x * b.x - a.y * b.y;
-      si += a.x * b.y + a.y * b.x;
+// C (M x N, ldc) = op(A) B, op(A) = A (M x K, lda) or, with ah, A^H (A is K x M);
+// complex FP64 on 16x16x4 MFMA, one 16 x 16 tile of C per wave at a time,
+// operands read from memory (LDS or global).  C must not overlap A or B.
+// Ends with a barrier.
+typedef double d4v_g __attribute__((ext_vector_type(4)));
+__device__ void zgemm(double2 *C, int ldc, const double2 *A, int lda, bool ah, const double2 *B, int ldb, int M,
+                      int N, int K) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int mt = (M + 15) / 16, nt = (N + 15) / 16;
+  for (int t = wave; t < mt * nt; t += NW) {
+    const int ti = t / nt, tj = t % nt;
+    const int row = ti * 16 + li, col = tj * 16 + li;
+    d4v_g cre = {0, 0, 0, 0}, cim = {0, 0, 0, 0};
+    for (int kk = 0; kk < K; kk += 4) {
+      const int k = kk + lk;
+      double2 a = make_double2(0, 0), b = make_double2(0, 0);
+      if (k < K && row < M) a = ah ? cconj(A[k * lda + row]) : A[row * lda + k];
+      if (k < K && col < N) b = B[k * ldb + col];
+      cre = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, cre, 0, 0, 0);
+      cre = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, cre, 0, 0, 0);
+      cim = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, cim, 0, 0, 0);
+      cim = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, cim, 0, 0, 0);
     }
-    C[i * ldc + j] = make_double2(sr, si);
-  }
-}
-// C (m x n) = A^H (A: k x m) * B (k x n)
-__device__ void gemm_hn(double2 *C, int ldc, const double2 *A, int lda, const double2 *B, int ldb, int m, int n,
-                        int k) {
-  for (int e = threadIdx.x; e < m * n; e += NT) {
-    const int i = e / n, j = e % n;
-    double sr = 0, si = 0;
-#pragma unroll 8
-    for (int q = 0; q < k; ++q) {
-      const double2 a = A[q * lda + i], b = B[q * ldb + j];
-      sr += a.x * b.x + a.y * b.y;
-      si += a.x * b.y - a.y * b.x;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = ti * 16 + 4 * v + lk, j = tj * 16 + li;
+      if (i < M && j < N) C[i * ldc + j] = make_double2(cre[v], cim[v]);
     }
-    C[i * ldc + j] = make_double2(sr, si);
   }
+  __syncthreads();
 }
 
 // out[c] = sum_{i < m} conj(v[i * ldv]) M[i * ldm + c] for c < nc, one wave per
@@ -324,9 +325,6 @@ struct TriShared {
 
 // packed lower triangle, column-major: element (i, j), i >= j
 __device__ inline int pl(int i, int j, int m) { return j * m - (j * (j - 1)) / 2 + (i - j); }
-__device__ inline double2 lget(const double2 *A, int i, int j, int m) {
-  return i >= j ? A[pl(i, j, m)] : cconj(A[pl(j, i, m)]);
-}
 
 __device__ inline double wave_sum_d(double v) { return sum64(v); }
 
@@ -638,61 +636,69 @@ struct StepShared {
   double coef[kMaxAb];
 };
 
-// Cholesky Gamma = R* R (R upper, D x D row-major).  A direction whose pivot
-// falls below 1e-13 of its own Gram diagonal is dependent on the earlier ones:
-// its row of R is zeroed, its pivot set to 1 and sh.drop marks it.
-__device__ void chol_drop(const double2 *G, double2 *R, int D, double2 *arena, int arena_elems, StepShared &sh) {
-  const bool in_lds = D * D <= arena_elems;
+// Cholesky of the n x n Hermitian block G (leading dimension ldg) into the
+// upper triangle of R (ldr): G = R* R.  A direction whose pivot falls below
+// 1e-13 of its diagonal in the full Gram matrix (orig[c * ldo]) is dependent on
+// the earlier ones: its row of R is zeroed, its pivot set to 1 and drop[c] = 1.
+// sh.minpiv / sh.ndrop report the smallest kept pivot ratio and the drops.
+__device__ void chol_drop(const double2 *G, int ldg, const double2 *orig, int ldo, double2 *R, int ldr, int n,
+                          double2 *arena, int arena_elems, unsigned char *drop, StepShared &sh) {
+  const bool in_lds = n * n <= arena_elems;
   double2 *C = in_lds ? arena : R;
-  for (int e = threadIdx.x; e < D * D; e += NT) C[e] = G[e];
+  const int ldc = in_lds ? n : ldr;
+  for (int e = threadIdx.x; e < n * n; e += NT) C[(e / n) * ldc + e % n] = G[(e / n) * ldg + e % n];
   if (threadIdx.x == 0) {
     sh.minpiv = 1.0;
     sh.ndrop = 0;
   }
   __syncthreads();
-  for (int k = 0; k < D; ++k) {
-    const double piv = C[k * D + k].x, orig = G[k * D + k].x;
-    const bool dropped = !(piv > 1e-13 * orig) || !(orig > 0);
+  for (int k = 0; k < n; ++k) {
+    const double piv = C[k * ldc + k].x, og = orig[k * ldo].x;
+    const bool dropped = !(piv > 1e-13 * og) || !(og > 0);
     if (threadIdx.x == 0) {
-      sh.drop[k] = dropped;
+      drop[k] = dropped;
       if (dropped)
         sh.ndrop += 1;
       else
-        sh.minpiv = fmin(sh.minpiv, piv / orig);
+        sh.minpiv = fmin(sh.minpiv, piv / og);
     }
     const double rkk = dropped ? 1.0 : sqrt(piv);
-    const int w = D - k - 1;
-    for (int j = k + 1 + threadIdx.x; j < D; j += NT)
-      C[k * D + j] = dropped ? make_double2(0, 0) : cscale(1.0 / rkk, C[k * D + j]);
+    const int w = n - k - 1;
+    for (int j = k + 1 + threadIdx.x; j < n; j += NT)
+      C[k * ldc + j] = dropped ? make_double2(0, 0) : cscale(1.0 / rkk, C[k * ldc + j]);
     if (in_lds) lds_barrier(); else __syncthreads();
     if (!dropped)
       for (int e = threadIdx.x; e < w * w; e += NT) {
         const int i = k + 1 + e / w, j = k + 1 + e % w;
-        if (j >= i) C[i * D + j] = csub(C[i * D + j], cmulc(C[k * D + i], C[k * D + j]));
+        if (j >= i) C[i * ldc + j] = csub(C[i * ldc + j], cmulc(C[k * ldc + i], C[k * ldc + j]));
       }
-    if (threadIdx.x == 0) C[k * D + k] = make_double2(rkk, 0.0);
+    if (threadIdx.x == 0) C[k * ldc + k] = make_double2(rkk, 0.0);
     if (in_lds) lds_barrier(); else __syncthreads();
   }
-  for (int e = threadIdx.x; e < D * D; e += NT) R[e] = (e / D > e % D) ? make_double2(0, 0) : C[e];
+  for (int e = threadIdx.x; e < n * n; e += NT) {
+    const int i = e / n, j = e % n;
+    R[i * ldr + j] = i > j ? make_double2(0, 0) : C[i * ldc + j];
+  }
   __syncthreads();
 }
 
-// Ri = R^{-1} (upper): thread c owns column c and back-substitutes bottom-up;
-// the column's own earlier results are re-read by the same thread only.
-__device__ void upper_inverse(const double2 *R, double2 *Ri, int D) {
-  for (int e = threadIdx.x; e < D * D; e += NT) Ri[e] = make_double2(0, 0);
+// Ri = R^{-1} for the n x n upper triangular R: thread c owns column c and
+// back-substitutes bottom-up; the column's own earlier results are re-read by
+// the same thread only.  Begins and ends with a barrier.
+__device__ void upper_inverse(const double2 *R, int ldr, double2 *Ri, int ldi, int n) {
+  for (int e = threadIdx.x; e < n * n; e += NT) Ri[(e / n) * ldi + e % n] = make_double2(0, 0);
   __syncthreads();
-  for (int c = threadIdx.x; c < D; c += NT) {
-    Ri[c * D + c] = cdiv(make_double2(1, 0), R[c * D + c]);
+  for (int c = threadIdx.x; c < n; c += NT) {
+    Ri[c * ldi + c] = cdiv(make_double2(1, 0), R[c * ldr + c]);
     for (int i = c - 1; i >= 0; --i) {
       double sr = 0, si = 0;
 #pragma unroll 8
       for (int k = i + 1; k <= c; ++k) {
-        const double2 a = R[i * D + k], b = Ri[k * D + c];
+        const double2 a = R[i * ldr + k], b = Ri[k * ldi + c];
         sr += a.x * b.x - a.y * b.y;
         si += a.x * b.y + a.y * b.x;
       }
-      Ri[i * D + c] = cdiv(make_double2(-sr, -si), R[i * D + i]);
+      Ri[i * ldi + c] = cdiv(make_double2(-sr, -si), R[i * ldr + i]);
     }
   }
   __syncthreads();
@@ -704,7 +710,7 @@ __device__ void upper_inverse(const double2 *R, double2 *Ri, int D) {
 __device__ void lowdin(double2 *u, int m, int r, double2 *S, double2 *Lw, double2 *T, double2 *arena,
                        StepShared &sh) {
   const int rr = r * r;
-  gemm_hn(S, r, u, r, u, r, r, r, m);
+  zgemm(S, r, u, r, true, u, r, r, r, m);
   __syncthreads();
   if (threadIdx.x == 0) {
     double dev = 0;
@@ -738,7 +744,7 @@ __device__ void lowdin(double2 *u, int m, int r, double2 *S, double2 *Lw, double
   }
   for (int e = threadIdx.x; e < m * r; e += NT) T[e] = u[e];
   __syncthreads();
-  gemm_nn(u, r, T, r, Lw, r, m, r, r);
+  zgemm(u, r, T, r, false, Lw, r, m, r, r);
   __syncthreads();
 }
 
@@ -762,7 +768,7 @@ __device__ void rhs_coords(const double2 *u, const double2 *y, int m, int D, int
   double2 *cvec = sh.vec;  // c_a = phi(lam_a)
   double2 *dots = sh.vec + kMaxR;
   if (threadIdx.x < r) cvec[threadIdx.x] = phi(mc.lam[threadIdx.x], mc.model, mc.kappa, mc.hbar);
-  gemm_hn(Gr, r, u, r, y, r, r, r, m);
+  zgemm(Gr, r, u, r, true, y, r, r, r, m);
   __syncthreads();
   for (int e = threadIdx.x; e < rr; e += NT) {
     const int a = e / r, b = e % r;
@@ -925,13 +931,13 @@ __device__ void rhs_coords(const double2 *u, const double2 *y, int m, int D, int
     for (int e = threadIdx.x; e < D * r; e += NT) w[e] = e < m * r ? Y_[e] : make_double2(0, 0);
   } else {
     // projector form: W = (y - u G_raw) diag(conj c)
-    gemm_nn(t1, r, u, r, Gr, r, m, r, r);
+    zgemm(t1, r, u, r, false, Gr, r, m, r, r);
     __syncthreads();
     for (int e = threadIdx.x; e < D * r; e += NT)
       w[e] = e < m * r ? cmul(csub(y[e], t1[e]), cconj(cvec[e % r])) : make_double2(0, 0);
   }
   __syncthreads();
-  gemm_nn(z, r, u, r, X11, r, m, r, r);
+  zgemm(z, r, u, r, false, X11, r, m, r, r);
   __syncthreads();
   for (int e = threadIdx.x; e < D * r; e += NT) z[e] = e < m * r ? cadd(z[e], w[e]) : make_double2(0, 0);
   __syncthreads();
@@ -1061,10 +1067,15 @@ __device__ void householder_qr(double2 *M, int m, int q, double2 *Q, double2 *Rm
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// LREI-RK projected step
+// LREI-RK projected step, one launch per stage j = 0 .. s-1.  Stage j needs
+// only the Gram products of P_0 .. P_{j+1}, so it can run as soon as pass j
+// is reduced, while the later passes proceed.  Each launch extends the Gram
+// matrix, its Cholesky factor R (bordered form: R12 = R11^{-*} G12,
+// R22 = chol(G22 - R12* R12)) and R^{-1} by the new Krylov block, then runs
+// the stage.  State between launches lives in the workspace.
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(NT) void k_small_rk(SmallRkParams p, SmallWs ws) {
+__global__ __launch_bounds__(NT) void k_small_rk(SmallRkParams p, SmallWs ws, int j) {
   extern __shared__ __align__(16) double2 s_arena[];
   __shared__ StepShared sh;
 
@@ -1080,8 +1091,13 @@ __global__ __launch_bounds__(NT) void k_small_rk(SmallRkParams p, SmallWs ws) {
   double2 *Gr = X11 + rr;               // r x r
   double2 *tmp = Gr + rr;               // r x r
   double2 *Lw = tmp + rr;               // r x r Lowdin factor
+  double2 *S22 = ws.Hh;                 // 2r x 2r Schur complement / R22^{-1} scratch
+  double *flags = ws.flags;             // [D] dropped directions
   double *stats = ws.stats;
   const int arena = p.lds_elems;
+  const int k0 = j == 0 ? 0 : (j + 1) * r;  // first new column of the Gram matrix
+  const int k1 = (j + 2) * r;               // end of the new columns
+  const int nn = k1 - k0;
   // phase timers (100 MHz real-time counter), summed into stats[16..23]
   __shared__ uint64_t s_tmark;
   __shared__ double s_tacc[8];
@@ -1099,41 +1115,42 @@ __global__ __launch_bounds__(NT) void k_small_rk(SmallRkParams p, SmallWs ws) {
     }
   };
 
-  // ---- 1. Gram matrix of the Chebyshev blocks --------------------------------
-  // pass 0 measured P0*P0, P0*P1, P1*P1; pass j >= 1 measured P_j*P_{j+1}, P_{j+1}*P_{j+1}
+  // ---- 1. Gram columns [k0, k1) -----------------------------------------------
+  // pass 0 measured P0*P0, P0*P1, P1*P1; pass j >= 1 measured P_j*P_{j+1}, P_{j+1}*P_{j+1};
+  // the other blocks of column j+1 follow from P_{j+1} = 2 H~ P_j - P_{j-1}
   auto gblk = [&](int bi, int bj) { return G + (bi * r) * D + bj * r; };
-  for (int e = threadIdx.x; e < D * D; e += NT) G[e] = make_double2(0, 0);
-  __syncthreads();
   auto put = [&](int bi, int bj, const double2 *M) {
     for (int e = threadIdx.x; e < rr; e += NT) gblk(bi, bj)[(e / r) * D + e % r] = M[e];
   };
-  put(0, 0, ws.meas + 0 * rr);
-  put(0, 1, ws.meas + 1 * rr);
-  put(1, 1, ws.meas + 2 * rr);
-  for (int j = 1; j < s; ++j) {
+  if (j == 0) {
+    put(0, 0, ws.meas + 0 * rr);
+    put(0, 1, ws.meas + 1 * rr);
+    put(1, 1, ws.meas + 2 * rr);
+  } else {
     put(j, j + 1, ws.meas + (3 * j + 0) * rr);
     put(j + 1, j + 1, ws.meas + (3 * j + 1) * rr);
   }
   __syncthreads();
   // symmetrise the measured diagonal blocks before they enter the recurrence
-  for (int e = threadIdx.x; e < (s + 1) * rr; e += NT) {
-    const int bi = e / rr, a = (e % rr) / r, b = e % r;
-    double2 *M = gblk(bi, bi);
-    if (a < b) {
-      const double2 x1 = M[a * D + b], x2 = M[b * D + a];
-      const double2 hh = make_double2(0.5 * (x1.x + x2.x), 0.5 * (x1.y - x2.y));
-      M[a * D + b] = hh;
-      M[b * D + a] = cconj(hh);
-    } else if (a == b) {
-      M[a * D + a].y = 0.0;
+  for (int bi = (j == 0 ? 0 : j + 1); bi <= j + 1; ++bi) {
+    for (int e = threadIdx.x; e < rr; e += NT) {
+      const int a = e / r, b = e % r;
+      double2 *M = gblk(bi, bi);
+      if (a < b) {
+        const double2 x1 = M[a * D + b], x2 = M[b * D + a];
+        const double2 hh = make_double2(0.5 * (x1.x + x2.x), 0.5 * (x1.y - x2.y));
+        M[a * D + b] = hh;
+        M[b * D + a] = cconj(hh);
+      } else if (a == b) {
+        M[a * D + a].y = 0.0;
+      }
     }
+    __syncthreads();
   }
-  __syncthreads();
   auto gget = [&](int bi, int bj, int a, int b) {  // any block, via Hermitian symmetry
     return bi <= bj ? gblk(bi, bj)[a * D + b] : cconj(gblk(bj, bi)[b * D + a]);
   };
-  for (int j = 1; j < s; ++j) {
-    // Gamma_{i, j+1} for i <= j-1 from P_{j+1} = 2 H~ P_j - P_{j-1}
+  if (j >= 1) {
     for (int e = threadIdx.x; e < j * rr; e += NT) {
       const int i = e / rr, a = (e % rr) / r, b = e % r;
       double2 v;
@@ -1145,36 +1162,85 @@ __global__ __launch_bounds__(NT) void k_small_rk(SmallRkParams p, SmallWs ws) {
     }
     __syncthreads();
   }
-  for (int e = threadIdx.x; e < D * D; e += NT) {
-    const int i = e / D, j = e % D;
-    if (i / r > j / r) G[e] = cconj(G[j * D + i]);
+  // lower part of the new columns' rows
+  for (int e = threadIdx.x; e < nn * k1; e += NT) {
+    const int i = k0 + e / k1, c = e % k1;  // row i of the new block, column c
+    if (i / r > c / r) G[i * D + c] = cconj(G[c * D + i]);
   }
   __syncthreads();
 
   lap(0);
-  chol_drop(G, R, D, s_arena, arena, sh);
+  // ---- 2. Cholesky of the new columns (dependent directions dropped) -----------
+  if (j == 0) {
+    for (int c = threadIdx.x; c < D; c += NT) flags[c] = 0.0;
+    chol_drop(G, D, G, D + 1, R, D, k1, s_arena, arena, sh.drop, sh);
+    for (int c = threadIdx.x; c < k1; c += NT) flags[c] = sh.drop[c];
+    // rows and columns beyond k1 stay zero until their stage
+    for (int e = threadIdx.x; e < D * D; e += NT)
+      if (e / D >= k1 || e % D >= k1) R[e] = make_double2(0, 0);
+  } else {
+    // R12 = Ri11^* G12 (dropped rows of R12 are zero), S = G22 - R12^* R12
+    zgemm(t1, nn, Ri, D, true, G + k0, D, k0, nn, k0);
+    for (int e = threadIdx.x; e < k0 * nn; e += NT) {
+      const int i = e / nn, c = e % nn;
+      R[i * D + k0 + c] = flags[i] != 0.0 ? make_double2(0, 0) : t1[e];
+    }
+    __syncthreads();
+    zgemm(S22, nn, R + k0, D, true, R + k0, D, nn, nn, k0);
+    for (int e = threadIdx.x; e < nn * nn; e += NT) {
+      const int i = e / nn, c = e % nn;
+      S22[e] = csub(G[(k0 + i) * D + k0 + c], S22[e]);
+    }
+    __syncthreads();
+    chol_drop(S22, nn, G + k0 * (D + 1), D + 1, R + k0 * (D + 1), D, nn, s_arena, arena, sh.drop, sh);
+    for (int c = threadIdx.x; c < nn; c += NT) flags[k0 + c] = sh.drop[c];
+  }
+  if (threadIdx.x == 0) {
+    if (j == 0) {
+      stats[2] = sh.ndrop;
+      stats[3] = sh.minpiv;
+    } else {
+      stats[2] += sh.ndrop;
+      stats[3] = fmin(stats[3], sh.minpiv);
+    }
+  }
   lap(1);
-  upper_inverse(R, Ri, D);
+  // ---- 3. R^{-1} for the new columns: Ri22 = R22^{-1}, Ri12 = -Ri11 R12 Ri22 ------
+  if (j == 0) {
+    for (int e = threadIdx.x; e < D * D; e += NT) Ri[e] = make_double2(0, 0);
+    upper_inverse(R, D, Ri, D, k1);
+  } else {
+    upper_inverse(R + k0 * (D + 1), D, Ri + k0 * (D + 1), D, nn);
+    zgemm(t1, nn, Ri, D, false, R + k0, D, k0, nn, k0);       // Ri11 R12
+    zgemm(S22, nn, t1, nn, false, Ri + k0 * (D + 1), D, k0, nn, nn);  // (Ri11 R12) Ri22
+    for (int e = threadIdx.x; e < k0 * nn; e += NT) {
+      const int i = e / nn, c = e % nn;
+      Ri[i * D + k0 + c] = make_double2(-S22[e].x, -S22[e].y);
+    }
+    __syncthreads();
+  }
+  for (int c = threadIdx.x; c < k1; c += NT) sh.drop[c] = flags[c] != 0.0;
   lap(2);
-  // ---- 2. u_1 = R[:, :r] (Lowdin re-orthonormalised) ---------------------------
+  // ---- u_1 = R[:, :r] (Lowdin re-orthonormalised), at the first stage -------------
   double2 *u1 = ws.stage;  // stage 0, slot u
-  for (int e = threadIdx.x; e < D * r; e += NT) u1[e] = R[(e / r) * D + e % r];
-  __syncthreads();
-  lowdin(u1, D, r, tmp, Lw, t1, s_arena, sh);
-  if (threadIdx.x == 0) stats[4] = sh.dev;
+  if (j == 0) {
+    for (int e = threadIdx.x; e < D * r; e += NT) u1[e] = R[(e / r) * D + e % r];
+    __syncthreads();
+    lowdin(u1, D, r, tmp, Lw, t1, s_arena, sh);
+    if (threadIdx.x == 0) stats[4] = sh.dev;
+  }
 
-  // ---- 3. stages -------------------------------------------------------------
+  // ---- 3. stage j -------------------------------------------------------------
   const double h = p.h;
   const ModelCoef mc{p.model, p.kappa, p.hbar, p.lam};
-  for (int j = 0; j < s; ++j) {
+  {
     double2 *u = ws.stage + (3 * j + 0) * D * r;
     double2 *z = ws.stage + (3 * j + 1) * D * r;
     double2 *w = ws.stage + (3 * j + 2) * D * r;
     const int mi = (j + 1) * r;  // support of u
     const int mo = (j + 2) * r;  // support of y = H u
     // y = R That R^{-1} u
-    gemm_nn(t1, r, Ri, D, u, r, mi, r, mi, true);
-    __syncthreads();
+    zgemm(t1, r, Ri, D, false, u, r, mi, r, mi);
     for (int e = threadIdx.x; e < mo * r; e += NT) {
       const int row = e / r, col = e % r, bi = row / r, a = row % r;
       double2 v = cscale(p.shift, bi <= j ? t1[e] : make_double2(0, 0));
@@ -1186,8 +1252,7 @@ __global__ __launch_bounds__(NT) void k_small_rk(SmallRkParams p, SmallWs ws) {
       Yc[e] = v;  // That * t1
     }
     __syncthreads();
-    gemm_nn(y, r, R, D, Yc, r, mo, r, mo, true);
-    __syncthreads();
+    zgemm(y, r, R, D, false, Yc, r, mo, r, mo);
     for (int e = threadIdx.x; e < mo * r; e += NT)
       if (sh.drop[e / r]) y[e] = make_double2(0, 0);
     __syncthreads();
@@ -1215,7 +1280,6 @@ __global__ __launch_bounds__(NT) void k_small_rk(SmallRkParams p, SmallWs ws) {
     stage_matrix(K, m, r, u1, p.lam, j + 1, ws.stage, (size_t)3 * D * r, ws.stage + D * r, (size_t)3 * D * r,
                  ws.stage + 2 * D * r, (size_t)3 * D * r, sh.coef);
     lap(5);
-    double2 *unext = last ? ws.Cfin /* temporary */ : ws.stage + (3 * (j + 1) + 0) * D * r;
     {
       int fk = 0;
       for (int e = threadIdx.x; e < m * (m + 1) / 2; e += NT)
@@ -1223,6 +1287,7 @@ __global__ __launch_bounds__(NT) void k_small_rk(SmallRkParams p, SmallWs ws) {
       fk = __syncthreads_or(fk);
       if (threadIdx.x == 0 && stats[28] < 0 && fk) stats[28] = 10 * j + 4;
     }
+    double2 *unext = last ? ws.Cfin /* temporary */ : ws.stage + (3 * (j + 1) + 0) * D * r;
     eig_top(K, m, r, unext, r, D, scr, jl, sh.ts);
     {
       const int fe = any_nonfinite(unext, D * r);
@@ -1232,31 +1297,33 @@ __global__ __launch_bounds__(NT) void k_small_rk(SmallRkParams p, SmallWs ws) {
     if (last) {
       for (int e = threadIdx.x; e < D * r; e += NT) t1[e] = ws.Cfin[e];
       __syncthreads();
-      gemm_nn(ws.Cfin, r, Ri, D, t1, r, D, r, D, true);  // C = R^{-1} u_final
-      __syncthreads();
+      zgemm(ws.Cfin, r, Ri, D, false, t1, r, D, r, D);  // C = R^{-1} u_final
     }
   }
   lap(7);
-  int bad_local = 0;
-  for (int e = threadIdx.x; e < D * r; e += NT)
-    if (!isfinite(ws.Cfin[e].x) || !isfinite(ws.Cfin[e].y)) bad_local = 1;
-  const int bad = __syncthreads_or(bad_local);
+  int bad = 0;
+  if (j + 1 == s) {
+    int bad_local = 0;
+    for (int e = threadIdx.x; e < D * r; e += NT)
+      if (!isfinite(ws.Cfin[e].x) || !isfinite(ws.Cfin[e].y)) bad_local = 1;
+    bad = __syncthreads_or(bad_local);
+  }
   if (threadIdx.x == 0) {
     for (int k = 0; k < 8; ++k) stats[16 + k] += s_tacc[k] * 1e-5;  // ms
     for (int k = 0; k < 4; ++k) stats[24 + k] += sh.ts.tacc[k] * 1e-5;
     stats[29] += sh.ts.tacc[5] * 1e-5;
     stats[30] += sh.ts.tacc[6] * 1e-5;
-    stats[0] = 0;
-    stats[1] = 0;
-    stats[2] = sh.ndrop;
-    stats[3] = sh.minpiv;
-    stats[6] = 0;
-    stats[7] = bad;
-    stats[8] = s;  // eigensolves this step
-    // running totals over the steps of one call (zeroed by the host per call)
-    stats[11] += s;
-    stats[14] += bad;
-    stats[15] += 1;
+    if (j + 1 == s) {
+      stats[0] = 0;
+      stats[1] = 0;
+      stats[6] = 0;
+      stats[7] = bad;
+      stats[8] = s;  // eigensolves this step
+      // running totals over the steps of one call (zeroed by the host per call)
+      stats[11] += s;
+      stats[14] += bad;
+      stats[15] += 1;
+    }
   }
 }
 
@@ -1268,7 +1335,17 @@ void launch_small_rk(const SmallRkParams &p, const SmallWs &ws, hipStream_t s) {
     attr = true;
   }
   const size_t lds = (size_t)p.lds_elems * sizeof(double2);
-  hipLaunchKernelGGL(k_small_rk, dim3(1), dim3(NT), lds, s, p, ws);
+  for (int j = 0; j < p.s; ++j) hipLaunchKernelGGL(k_small_rk, dim3(1), dim3(NT), lds, s, p, ws, j);
+}
+
+void launch_small_rk_stage(const SmallRkParams &p, const SmallWs &ws, int j, hipStream_t s) {
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void *)k_small_rk, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              kSmallLdsBytes);
+    attr = true;
+  }
+  hipLaunchKernelGGL(k_small_rk, dim3(1), dim3(NT), (size_t)p.lds_elems * sizeof(double2), s, p, ws, j);
 }
 
 // ---------------------------------------------------------------------------
@@ -1347,8 +1424,8 @@ __global__ __launch_bounds__(NT) void k_small_ab(SmallAbParams p, SmallAbWs ws) 
     }
   }
   __syncthreads();
-  chol_drop(G, R, D, s_arena, arena, sh);
-  upper_inverse(R, Ri, D);
+  chol_drop(G, D, G, D + 1, R, D, D, s_arena, arena, sh.drop, sh);
+  upper_inverse(R, D, Ri, D, D);
 
   // ---- coordinates in the orthonormal basis B R^{-1}
   // of a vector held as U-coordinates x (DU x r): R[:, :DU] x
