@@ -195,8 +195,9 @@ def main():
         "parity": parity,
         "kernels_ms": {k: round(v, 5) for k, v in kms.items()},
         "hv_tuning": None if tuning is None else {
-            "epl": tuning["epl"], "grid": tuning["grid"], "ms": round(tuning["ms"], 5),
-            "tried": [[e, g, round(t, 5)] for e, g, t in tuning["tried"]]},
+            "epl": tuning["epl"], "grid": tuning["grid"], "win_bits": tuning["win_bits"],
+            "n_sweeps": tuning["n_sweeps"], "ms": round(tuning["ms"], 5),
+            "tried": [[e, g, w, round(t, 5)] for e, g, w, t in tuning["tried"]]},
         "eig_stats": {k: stats[k] for k in ("eigensolves", "jacobi_sweeps", "max_sweeps_one_solve",
                                             "dropped_directions", "min_pivot_ratio", "ortho_error")},
         "projected_phase_ms_per_step": dict(zip(

@@ -181,18 +181,22 @@ LREI_API lrei_status lrei_synchronize(lrei_ctx *ctx);
 typedef struct {
   int epl;                 /* complex columns per lane chosen for the H.V pass          */
   int grid;                /* workgroups per H.V launch chosen                           */
-  double ms;               /* time per launch of the chosen variant                      */
+  int win_bits;            /* row-bit window of the H.V sweeps (0: one sweep)            */
+  int n_sweeps;            /* sweeps per H.V pass for that window                        */
+  double ms;               /* time of one H.V pass (all sweeps) of the chosen variant    */
   int from_cache;          /* 1: read from opt.autotune_cache without timing             */
-  int n_tried;             /* variants timed (at most 32)                                */
-  int tried_epl[32], tried_grid[32];
-  double tried_ms[32];
+  int n_tried;             /* variants timed (at most 64)                                */
+  int tried_epl[64], tried_grid[64], tried_win[64];
+  double tried_ms[64];
 } lrei_tune_result;
 
 /* Chooses the launch shape of the matrix-free H.V pass (eq. 5.1 applied in
  * the Chebyshev passes) for the current Hamiltonian, rank and precision:
- * every valid (columns per lane, workgroups) pair is timed on the device with
- * the current state as input (5 launches each) and the fastest is kept for
- * this context.  With opt.autotune_cache set, a matching line of that text
+ * every valid (columns per lane, workgroups, row-bit window) choice is timed on
+ * the device with the current state as input (5 passes each) and the fastest
+ * is kept for this context.  A window of w row bits splits the pass into
+ * sweeps, each applying the terms whose flip masks fit one window, so that one
+ * XCD's L2 holds the rows a sweep gathers from.  With opt.autotune_cache set, a matching line of that text
  * file (device, n, r, precision, term count) is used instead of timing, and a
  * new result is appended to it.  Results are unaffected; only speed changes.
  * Requires lrei_set_rho; overwrites the scratch Krylov blocks (not the state).

@@ -2,6 +2,7 @@
 // driver that sequences the N-space passes and the projected step kernel.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -74,6 +75,7 @@ struct lrei_ctx {
 
   // Hamiltonian
   bool have_h = false;
+  std::vector<int> site_pos;     // physical site -> row bit of the internal storage order
   int n = 0;
   long long N = 0;
   double hbar = 1.0;
@@ -85,6 +87,15 @@ struct lrei_ctx {
   int cplx = 0;                   // some off-diagonal coefficient is complex
   int epl = 0;                    // H.V columns per lane (0: default)
   int hv_grid = 0;                // H.V workgroups per launch (0: default)
+  // H.V sweep plan: each sweep applies the terms whose flip masks lie in its
+  // window of row bits (one sweep = all bits, all terms)
+  struct HvSweep {
+    std::vector<int> win, fix;
+    int t0 = 0, t1 = 0;
+  };
+  int hv_w = 0;                   // window bits (0: one sweep)
+  std::vector<HvSweep> sweeps;
+  DevBuf acc;                     // partial sums between sweeps
 
   // state
   bool have_rho = false;
@@ -157,6 +168,7 @@ lrei_status alloc_state(lrei_ctx *ctx, int r, bool fp32) {
   for (int i = 0; i <= kMaxStages; ++i)
     if (!ctx->blocks[i].ensure(blk)) return ctx->fail(LREI_E_NOMEM, "device allocation of Krylov blocks failed");
   if (!ctx->save.ensure(blk)) return ctx->fail(LREI_E_NOMEM, "device allocation failed");
+  if (!ctx->acc.ensure(blk)) return ctx->fail(LREI_E_NOMEM, "device allocation failed");
   ctx->grid = nspace_grid(ctx->N, r);
   if (ctx->hv_grid <= 0) ctx->hv_grid = ctx->grid;
   const size_t pcount = (size_t)kMaxHvGrid * cheb_partial_splits(r) * 3 * r * r;
@@ -197,9 +209,13 @@ void hv_args(lrei_ctx *ctx, ChebArgs &a) {
   a.epl = ctx->epl;
 }
 
-// One Chebyshev pass with fused Grams, reduced into ws.meas[slot].
-void cheb_pass_into(lrei_ctx *ctx, int r, int grid, int mode, const void *prev, const void *cur, void *next,
-                    double2 *partials, double2 *meas) {
+// One Chebyshev pass with fused Grams, reduced into meas.  With a sweep plan
+// (sweeps = true and more than one sweep), the pass runs as one launch per
+// sweep: the first adds the diagonal, each writes its partial sum to ctx->acc,
+// the last adds its terms to that sum and forms the Chebyshev combination and
+// the Grams.
+void hv_launches(lrei_ctx *ctx, int r, int grid, int mode, const void *prev, const void *cur, void *next,
+                 double2 *partials, bool sweeps) {
   ChebArgs a{};
   a.Pprev = prev;
   a.Pcur = cur;
@@ -213,13 +229,142 @@ void cheb_pass_into(lrei_ctx *ctx, int r, int grid, int mode, const void *prev, 
   a.mode = mode;
   a.partials = partials;
   a.grid = grid;
-  launch_cheb(ctx->fp32, a, ctx->stream);
+  const size_t ns = ctx->sweeps.size();
+  if (!sweeps || ns <= 1) {
+    launch_cheb(ctx->fp32, a, ctx->stream);
+  } else {
+    for (size_t i = 0; i < ns; ++i) {
+      const auto &sw = ctx->sweeps[i];
+      ChebArgs b = a;
+      b.t0 = sw.t0;
+      b.t1 = sw.t1;
+      b.use_diag = i == 0;
+      b.acc_in = i == 0 ? nullptr : ctx->acc.p;
+      b.acc_out = i + 1 < ns;
+      if (b.acc_out) b.Pnext = ctx->acc.p;
+      b.win_bits = (int)sw.win.size();
+      b.n_fix = (int)sw.fix.size();
+      for (size_t q = 0; q < sw.win.size(); ++q) b.win_pos[q] = (unsigned char)sw.win[q];
+      for (size_t q = 0; q < sw.fix.size(); ++q) b.fix_pos[q] = (unsigned char)sw.fix[q];
+      launch_cheb(ctx->fp32, b, ctx->stream);
+    }
+  }
+}
+
+void cheb_pass_into(lrei_ctx *ctx, int r, int grid, int mode, const void *prev, const void *cur, void *next,
+                    double2 *partials, double2 *meas, bool sweeps = false) {
+  hv_launches(ctx, r, grid, mode, prev, cur, next, partials, sweeps);
   if (mode != 2) launch_reduce(partials, grid, (mode == 0 ? 3 : 2) * r * r, meas, ctx->stream);
 }
 
 void cheb_pass(lrei_ctx *ctx, int mode, const void *prev, const void *cur, void *next, int slot) {
   cheb_pass_into(ctx, ctx->r, ctx->hv_grid, mode, prev, cur, next, (double2 *)ctx->partials.p,
-                 ctx->ws.meas + (size_t)slot * 3 * ctx->r * ctx->r);
+                 ctx->ws.meas + (size_t)slot * 3 * ctx->r * ctx->r, true);
+}
+
+// Sweep plan for windows of w row bits: repeatedly choose the n - w fixed bits
+// that the fewest remaining flip masks touch (exhaustively when the choice is
+// small, else greedily bit by bit), give those masks' terms to a sweep, and
+// upload the term tables in sweep order.  w >= n (or 0) is one sweep.
+lrei_status hv_set_plan(lrei_ctx *ctx, int w) {
+  const int n = ctx->n;
+  const auto &off = ctx->terms.off;
+  std::vector<int> order;
+  std::vector<lrei_ctx::HvSweep> plan;
+  if (w <= 0 || w >= n) {
+    lrei_ctx::HvSweep sw;
+    for (int b = 0; b < n; ++b) sw.win.push_back(b);
+    sw.t0 = 0;
+    sw.t1 = (int)off.size();
+    for (size_t t = 0; t < off.size(); ++t) order.push_back((int)t);
+    plan.push_back(sw);
+    w = 0;
+  } else {
+    std::vector<int> left;
+    for (size_t t = 0; t < off.size(); ++t) left.push_back((int)t);
+    const int nf = n - w;
+    auto hits = [&](uint32_t fmask) {
+      int c = 0;
+      for (int t : left) c += (off[t].mask & fmask) != 0;
+      return c;
+    };
+    double combos = 1;
+    for (int i = 0; i < nf; ++i) combos = combos * (n - i) / (i + 1);
+    while (!left.empty()) {
+      uint32_t best = 0;
+      if (combos <= 2e5) {
+        int bestc = 1 << 30;
+        std::vector<int> idx(nf);
+        for (int i = 0; i < nf; ++i) idx[i] = i;
+        while (true) {
+          uint32_t fm = 0;
+          for (int i : idx) fm |= 1u << i;
+          const int c = hits(fm);
+          if (c < bestc) {
+            bestc = c;
+            best = fm;
+          }
+          int i = nf - 1;
+          while (i >= 0 && idx[i] == n - nf + i) --i;
+          if (i < 0) break;
+          ++idx[i];
+          for (int q = i + 1; q < nf; ++q) idx[q] = idx[q - 1] + 1;
+        }
+      } else {
+        for (int i = 0; i < nf; ++i) {
+          int bestc = 1 << 30, bb = -1;
+          for (int b = 0; b < n; ++b) {
+            if (best & (1u << b)) continue;
+            const int c = hits(best | (1u << b));
+            if (c < bestc) {
+              bestc = c;
+              bb = b;
+            }
+          }
+          best |= 1u << bb;
+        }
+      }
+      lrei_ctx::HvSweep sw;
+      for (int b = 0; b < n; ++b) (best & (1u << b) ? sw.fix : sw.win).push_back(b);
+      sw.t0 = (int)order.size();
+      std::vector<int> rest;
+      for (int t : left) {
+        if ((off[t].mask & best) == 0)
+          order.push_back(t);
+        else
+          rest.push_back(t);
+      }
+      sw.t1 = (int)order.size();
+      if (sw.t1 == sw.t0) return ctx->fail(LREI_E_INVALID, "H.V sweep plan: a term does not fit any window");
+      plan.push_back(sw);
+      left.swap(rest);
+    }
+  }
+  // term tables in sweep order
+  std::vector<DevOffTerm> o64(off.size());
+  std::vector<DevTerm<float>> o32(off.size());
+  for (size_t q = 0; q < order.size(); ++q) {
+    const OffTerm &t = off[order[q]];
+    o64[q].mask = o32[q].mask = t.mask;
+    o64[q].sa = o32[q].sa = t.sa;
+    o64[q].sb = o32[q].sb = t.sb;
+    o64[q].pad = o32[q].pad = 0;
+    for (int k = 0; k < 4; ++k) {
+      o64[q].re[k] = t.re[k];
+      o64[q].im[k] = t.im[k];
+      o32[q].re[k] = (float)t.re[k];
+      o32[q].im[k] = (float)t.im[k];
+    }
+  }
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (!o64.empty()) {
+    HIPCHK(hipMemcpy(ctx->d_off.p, o64.data(), o64.size() * sizeof(DevOffTerm), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(ctx->d_terms32.p, o32.data(), o32.size() * sizeof(DevTerm<float>), hipMemcpyHostToDevice));
+  }
+  ctx->sweeps = plan;
+  ctx->hv_w = w;
+  ctx->drop_graph();
+  return LREI_OK;
 }
 
 SmallRkParams rk_params(lrei_ctx *ctx, int model, int scheme, double dt, double kappa) {
@@ -460,6 +605,51 @@ void enqueue_ab_step(lrei_ctx *ctx) {
   ab.count += 1;
 }
 
+// Site -> row-bit map of the internal storage order.  The n - 14 highest bits
+// (the bits that change between the row blocks an XCD works on at one time)
+// go to sites that share no term where possible, so that every flip mask
+// touches at most one of them and the rows gathered across blocks fall into
+// few distinct partner blocks.  Greedy: minimum-degree sites first.
+std::vector<int> choose_site_order(int n, int n_bonds, const int32_t *bond_ij) {
+  std::vector<int> pos(n);
+  const int nh = n > 14 ? n - 14 : 0;
+  std::vector<std::vector<int>> adj(n);
+  for (int b = 0; b < n_bonds; ++b) {
+    const int i = bond_ij[2 * b], j = bond_ij[2 * b + 1];
+    if (i == j) continue;
+    adj[i].push_back(j);
+    adj[j].push_back(i);
+  }
+  std::vector<char> inH(n, 0), blocked(n, 0);
+  int cnt = 0;
+  while (cnt < nh) {
+    int best = -1;
+    for (int q = n - 1; q >= 0; --q)
+      if (!blocked[q] && (best < 0 || adj[q].size() < adj[best].size())) best = q;
+    if (best < 0) break;
+    inH[best] = blocked[best] = 1;
+    for (int nb : adj[best]) blocked[nb] = 1;
+    ++cnt;
+  }
+  while (cnt < nh) {
+    int best = -1, bestc = 1 << 30;
+    for (int q = n - 1; q >= 0; --q) {
+      if (inH[q]) continue;
+      int c = 0;
+      for (int nb : adj[q]) c += inH[nb];
+      if (c < bestc) {
+        bestc = c;
+        best = q;
+      }
+    }
+    inH[best] = 1;
+    ++cnt;
+  }
+  int lo = 0, hi = n - nh;
+  for (int q = 0; q < n; ++q) pos[q] = inH[q] ? hi++ : lo++;
+  return pos;
+}
+
 lrei_status read_stats(lrei_ctx *ctx, double *h) {
   HIPCHK(hipMemcpyAsync(h, ctx->stats_buf.p, kStatsLen * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -534,6 +724,7 @@ void lrei_destroy(lrei_ctx *ctx) {
   ctx->drop_graph();
   for (auto &b : ctx->blocks) b.release();
   ctx->save.release();
+  ctx->acc.release();
   ctx->partials.release();
   ctx->ws_buf.release();
   ctx->stats_buf.release();
@@ -571,11 +762,37 @@ lrei_status lrei_set_hamiltonian(lrei_ctx *ctx, int n_spins, int n_bonds, const 
                                  const double *bond_J, const double *site_h, double hbar) {
   if (!ctx) return LREI_E_INVALID;
   if (!(hbar > 0) || !std::isfinite(hbar)) return ctx->fail(LREI_E_INVALID, "hbar must be positive and finite");
-  TermTable t;
-  std::string e;
-  if (!build_terms(n_spins, n_bonds, bond_ij, bond_J, site_h, t, e)) return ctx->fail(LREI_E_INVALID, e);
+  if (n_spins < 1 || n_spins > 30) return ctx->fail(LREI_E_INVALID, "n_spins must be in [1, 30]");
+  if (n_bonds < 0 || (n_bonds > 0 && (!bond_ij || !bond_J))) return ctx->fail(LREI_E_INVALID, "bad bond arrays");
+  for (int b = 0; b < 2 * n_bonds; ++b)
+    if (bond_ij[b] < 0 || bond_ij[b] >= n_spins) return ctx->fail(LREI_E_INVALID, "bond site out of range");
   if (ctx->have_rho && n_spins != ctx->n)
     return ctx->fail(LREI_E_STATE, "n_spins differs from the current state; set a new rho after changing n");
+  // terms in the internal site order
+  const std::vector<int> pos = choose_site_order(n_spins, n_bonds, bond_ij);
+  // a bond whose sites swap order gets the transposed tensor (J^{ab} s^a_i s^b_j)
+  std::vector<int32_t> pbonds(2 * (size_t)n_bonds);
+  std::vector<double> pJ(bond_J ? bond_J : (const double *)nullptr, bond_J ? bond_J + 9 * (size_t)n_bonds : nullptr);
+  for (int b = 0; b < n_bonds; ++b) {
+    int i = pos[bond_ij[2 * b]], j = pos[bond_ij[2 * b + 1]];
+    if (i > j) {
+      std::swap(i, j);
+      for (int a = 0; a < 3; ++a)
+        for (int c = 0; c < a; ++c) std::swap(pJ[9 * b + 3 * a + c], pJ[9 * b + 3 * c + a]);
+    }
+    pbonds[2 * b] = i;
+    pbonds[2 * b + 1] = j;
+  }
+  std::vector<double> ph;
+  if (site_h) {
+    ph.assign(3 * (size_t)n_spins, 0.0);
+    for (int q = 0; q < n_spins; ++q)
+      for (int c = 0; c < 3; ++c) ph[3 * pos[q] + c] = site_h[3 * q + c];
+  }
+  TermTable t;
+  std::string e;
+  if (!build_terms(n_spins, n_bonds, pbonds.data(), pJ.data(), site_h ? ph.data() : nullptr, t, e))
+    return ctx->fail(LREI_E_INVALID, e);
   HIPCHK(hipSetDevice(ctx->device));
   std::vector<DevOffTerm> off(t.off.size());
   for (size_t i = 0; i < t.off.size(); ++i) {
@@ -646,9 +863,22 @@ lrei_status lrei_set_hamiltonian(lrei_ctx *ctx, int n_spins, int n_bonds, const 
   ctx->d_diag32 = d_d32;
   d_off.p = d_diag.p = d_t32.p = d_d64.p = d_d32.p = nullptr;
   ctx->cplx = cplx;
+  ctx->sweeps.clear();  // term tables are in their natural order: one sweep
+  ctx->hv_w = 0;
   ctx->n_off = (int)off.size();
   ctx->n_diag = (int)dg.size();
   ctx->terms = t;
+  if (ctx->have_rho && ctx->site_pos != pos) {
+    // the stored state follows the previous site order: move it to the new one
+    const size_t vb = (size_t)ctx->N * ctx->r * ctx->elem();
+    (void)vb;
+    launch_permute(ctx->fp32, ctx->blocks[0].p, ctx->acc.p, ctx->N, ctx->r, ctx->site_pos.data(), n_spins, true,
+                   ctx->stream);
+    launch_permute(ctx->fp32, ctx->acc.p, ctx->blocks[0].p, ctx->N, ctx->r, pos.data(), n_spins, false, ctx->stream);
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    ab_reset(ctx);
+  }
+  ctx->site_pos = pos;
   ctx->n = n_spins;
   ctx->N = 1LL << n_spins;
   ctx->hbar = hbar;
@@ -735,8 +965,10 @@ lrei_status lrei_set_rho(lrei_ctx *ctx, int r, const double *lambda, const void 
     return st;
   }
   ctx->r = r;
-  e2 = hipMemcpyAsync(ctx->blocks[0].p, tv.p, vbytes, hipMemcpyDeviceToDevice, ctx->stream);
+  launch_permute(ctx->fp32, tv.p, ctx->blocks[0].p, ctx->N, r, ctx->site_pos.data(), ctx->n, false, ctx->stream);
+  e2 = hipGetLastError();
   if (e2 == hipSuccess) e2 = hipStreamSynchronize(ctx->stream);
+  (void)vbytes;
   release_tmp();
   HIPCHK(e2);
   ctx->lam.assign(lambda, lambda + r);
@@ -858,10 +1090,14 @@ lrei_status lrei_get_rho(lrei_ctx *ctx, double *lambda, void *V, int v_is_device
   if (!V) return LREI_OK;
   HIPCHK(hipSetDevice(ctx->device));
   const size_t n = (size_t)ctx->N * ctx->r;
-  const void *src = ctx->blocks[0].p;
+  // back to the physical site order, then to complex128
+  launch_permute(ctx->fp32, ctx->blocks[0].p, ctx->acc.p, ctx->N, ctx->r, ctx->site_pos.data(), ctx->n, true,
+                 ctx->stream);
+  HIPCHK(hipGetLastError());
+  const void *src = ctx->acc.p;
   if (ctx->fp32) {
     if (!ctx->save.ensure(n * sizeof(double2))) return ctx->fail(LREI_E_NOMEM, "allocation failed");
-    launch_convert(false, ctx->blocks[0].p, ctx->save.p, (long long)n, ctx->stream);
+    launch_convert(false, ctx->acc.p, ctx->save.p, (long long)n, ctx->stream);
     HIPCHK(hipGetLastError());
     src = ctx->save.p;
   }
@@ -925,22 +1161,30 @@ lrei_status lrei_apply_hamiltonian(lrei_ctx *ctx, int r, const void *X, void *Y,
   if (r < 1 || r > kMaxR || !X || !Y) return ctx->fail(LREI_E_INVALID, "bad arguments");
   HIPCHK(hipSetDevice(ctx->device));
   const size_t bytes = (size_t)ctx->N * r * sizeof(double2);
-  DevBuf dx, dy;
-  const void *px = X;
-  void *py = Y;
-  if (!is_device) {
-    if (!dx.ensure(bytes) || !dy.ensure(bytes)) {
-      dx.release();
-      dy.release();
-      return ctx->fail(LREI_E_NOMEM, "allocation failed");
-    }
-    HIPCHK(hipMemcpyAsync(dx.p, X, bytes, hipMemcpyHostToDevice, ctx->stream));
-    px = dx.p;
-    py = dy.p;
+  DevBuf dx, dy, dp;
+  auto release_all = [&]() {
+    dx.release();
+    dy.release();
+    dp.release();
+  };
+  if (!dy.ensure(bytes) || !dp.ensure(bytes) || (!is_device && !dx.ensure(bytes))) {
+    release_all();
+    return ctx->fail(LREI_E_NOMEM, "allocation failed");
   }
+  const void *px = X;
+  if (!is_device) {
+    lrei_status st0 = check_hip(ctx, hipMemcpyAsync(dx.p, X, bytes, hipMemcpyHostToDevice, ctx->stream), "upload X");
+    if (st0 != LREI_OK) {
+      release_all();
+      return st0;
+    }
+    px = dx.p;
+  }
+  // physical -> internal site order, H X, internal -> physical
+  launch_permute(false, px, dp.p, ctx->N, r, ctx->site_pos.data(), ctx->n, false, ctx->stream);
   ChebArgs a{};
-  a.Pcur = px;
-  a.Pnext = py;
+  a.Pcur = dp.p;
+  a.Pnext = dy.p;
   hv_args(ctx, a);
   a.N = ctx->N;
   a.r = r;
@@ -948,12 +1192,13 @@ lrei_status lrei_apply_hamiltonian(lrei_ctx *ctx, int r, const void *X, void *Y,
   a.mode = 2;
   a.grid = nspace_grid(ctx->N, r);
   launch_cheb(false, a, ctx->stream);
+  void *py = is_device ? Y : dp.p;
+  launch_permute(false, dy.p, py, ctx->N, r, ctx->site_pos.data(), ctx->n, true, ctx->stream);
   lrei_status st = check_hip(ctx, hipGetLastError(), "apply_hamiltonian launch");
   if (st == LREI_OK && !is_device)
-    st = check_hip(ctx, hipMemcpyAsync(Y, dy.p, bytes, hipMemcpyDeviceToHost, ctx->stream), "copy back");
+    st = check_hip(ctx, hipMemcpyAsync(Y, dp.p, bytes, hipMemcpyDeviceToHost, ctx->stream), "copy back");
   if (st == LREI_OK) st = check_hip(ctx, hipStreamSynchronize(ctx->stream), "sync");
-  dx.release();
-  dy.release();
+  release_all();
   return st;
 }
 
@@ -1098,21 +1343,10 @@ lrei_status lrei_profile_kernels(lrei_ctx *ctx, int model, int scheme, double dt
     for (int k = 0; k <= iters; ++k) {
       if (k == 1) (void)hipEventRecord(e0, ctx->stream);
       switch (which) {
-        case 0: {
-          ChebArgs a{};
-          a.Pprev = ctx->blocks[0].p;
-          a.Pcur = ctx->blocks[1].p;
-          a.Pnext = ctx->blocks[4].p;
-          hv_args(ctx, a);
-          a.N = ctx->N;
-          a.r = r;
-          a.alpha = 1.0 / (ctx->terms.gershgorin > 0 ? ctx->terms.gershgorin : 1.0);
-          a.mode = 1;
-          a.partials = (double2 *)ctx->partials.p;
-          a.grid = ctx->hv_grid;
-          launch_cheb(ctx->fp32, a, ctx->stream);
+        case 0:
+          hv_launches(ctx, r, ctx->hv_grid, 1, ctx->blocks[0].p, ctx->blocks[1].p, ctx->blocks[4].p,
+                      (double2 *)ctx->partials.p, true);
           break;
-        }
         case 1:
           launch_reduce((const double2 *)ctx->partials.p, ctx->hv_grid, 2 * r * r,
                         ctx->ws.work, ctx->stream);  // scratch target: the step's Grams stay intact
@@ -1166,12 +1400,13 @@ lrei_status lrei_autotune(lrei_ctx *ctx, lrei_tune_result *out) {
       while (std::fgets(line, sizeof(line), f)) {
         const std::string l(line);
         if (l.compare(0, key.size(), key) != 0 || l.size() <= key.size() || l[key.size()] != ' ') continue;
-        int e = 0, g = 0;
+        int e = 0, g = 0, w = 0;
         double ms = 0;
-        if (std::sscanf(l.c_str() + key.size(), " %d %d %lf", &e, &g, &ms) == 3 && e > 0 && g > 0 &&
-            g <= kMaxHvGrid) {
+        if (std::sscanf(l.c_str() + key.size(), " %d %d %d %lf", &e, &g, &w, &ms) == 4 && e > 0 && g > 0 &&
+            g <= kMaxHvGrid && w >= 0 && w < ctx->n) {
           res.epl = e;
           res.grid = g;
+          res.win_bits = w;
           res.ms = ms;
           res.from_cache = 1;
         }
@@ -1193,6 +1428,10 @@ lrei_status lrei_autotune(lrei_ctx *ctx, lrei_tune_result *out) {
     for (int g : {256, 512, 768, 1024, 1280, 1536, 2048})
       if (g <= tiles && g <= kMaxHvGrid) grids.push_back(g);
     if (grids.empty()) grids.push_back(nspace_grid(ctx->N, r));
+    // window sizes: one sweep, and windows small enough to leave room in an XCD's L2
+    std::vector<int> wins = {0};
+    for (int w : {16, 15, 14, 13})
+      if (w < ctx->n && ctx->n - w >= 3) wins.push_back(w);
     // valid data in the pass inputs: P = P- = the current state
     const size_t vbytes = (size_t)ctx->N * r * ctx->elem();
     HIPCHK(hipMemcpyAsync(ctx->blocks[1].p, ctx->blocks[0].p, vbytes, hipMemcpyDeviceToDevice, ctx->stream));
@@ -1200,53 +1439,56 @@ lrei_status lrei_autotune(lrei_ctx *ctx, lrei_tune_result *out) {
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     double best = 1e300;
-    for (int e : epls)
-      for (int g : grids) {
-        ChebArgs a{};
-        a.Pprev = ctx->blocks[0].p;
-        a.Pcur = ctx->blocks[1].p;
-        a.Pnext = ctx->blocks[4].p;
-        hv_args(ctx, a);
-        a.epl = e;
-        a.N = ctx->N;
-        a.r = r;
-        a.alpha = 1.0 / (ctx->terms.gershgorin > 0 ? ctx->terms.gershgorin : 1.0);
-        a.mode = 1;
-        a.partials = (double2 *)ctx->partials.p;
-        a.grid = g;
-        const int iters = 5;
-        bool ok = launch_cheb(ctx->fp32, a, ctx->stream);
-        (void)hipEventRecord(e0, ctx->stream);
-        for (int k = 0; k < iters && ok; ++k) ok = launch_cheb(ctx->fp32, a, ctx->stream);
-        (void)hipEventRecord(e1, ctx->stream);
-        HIPCHK(hipEventSynchronize(e1));
-        HIPCHK(hipGetLastError());
-        if (!ok) continue;
-        float t = 0;
-        (void)hipEventElapsedTime(&t, e0, e1);
-        const double ms = (double)t / iters;
-        if (res.n_tried < 32) {
-          res.tried_epl[res.n_tried] = e;
-          res.tried_grid[res.n_tried] = g;
-          res.tried_ms[res.n_tried] = ms;
-          res.n_tried++;
+    for (int w : wins) {
+      lrei_status st = hv_set_plan(ctx, w);
+      if (st != LREI_OK) continue;
+      const int ns = (int)ctx->sweeps.size();
+      for (int e : epls)
+        for (int g : grids) {
+          if (ns > 1 && g != 768 && g != 1536) continue;
+          ctx->epl = e;
+          const int iters = 5;
+          auto pass = [&]() {
+            cheb_pass_into(ctx, r, g, 1, ctx->blocks[0].p, ctx->blocks[1].p, ctx->blocks[4].p,
+                           (double2 *)ctx->partials.p, ctx->ws.work, true);
+          };
+          pass();
+          (void)hipEventRecord(e0, ctx->stream);
+          for (int k = 0; k < iters; ++k) pass();
+          (void)hipEventRecord(e1, ctx->stream);
+          HIPCHK(hipEventSynchronize(e1));
+          HIPCHK(hipGetLastError());
+          float t = 0;
+          (void)hipEventElapsedTime(&t, e0, e1);
+          const double ms = (double)t / iters;
+          if (res.n_tried < 64) {
+            res.tried_epl[res.n_tried] = e;
+            res.tried_grid[res.n_tried] = g;
+            res.tried_win[res.n_tried] = w;
+            res.tried_ms[res.n_tried] = ms;
+            res.n_tried++;
+          }
+          if (ms < best) {
+            best = ms;
+            res.epl = e;
+            res.grid = g;
+            res.win_bits = w;
+            res.ms = ms;
+          }
         }
-        if (ms < best) {
-          best = ms;
-          res.epl = e;
-          res.grid = g;
-          res.ms = ms;
-        }
-      }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (res.epl == 0) return ctx->fail(LREI_E_DEVICE, "no H.V variant could be launched");
     if (cache)
       if (FILE *f = std::fopen(cache, "a")) {
-        std::fprintf(f, "%s %d %d %.6f\n", key.c_str(), res.epl, res.grid, res.ms);
+        std::fprintf(f, "%s %d %d %d %.6f\n", key.c_str(), res.epl, res.grid, res.win_bits, res.ms);
         std::fclose(f);
       }
   }
+  lrei_status st = hv_set_plan(ctx, res.win_bits);
+  if (st != LREI_OK) return st;
+  res.n_sweeps = (int)ctx->sweeps.size();
   ctx->epl = res.epl;
   ctx->hv_grid = res.grid;
   ctx->drop_graph();

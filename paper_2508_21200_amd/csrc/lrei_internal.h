@@ -71,6 +71,13 @@ struct ChebArgs {
   int epl;              // complex columns per lane (0: default)
   int lanes;            // set by the launcher
   const void *terms, *diagv;  // set by the launcher
+  // sweep over a window of row bits (default: one window of all bits, all terms)
+  int t0, t1;                   // off-diagonal terms of this sweep
+  int use_diag;                 // add d(x) X[x]
+  const void *acc_in;           // add this partial sum (or nullptr)
+  int acc_out;                  // write the raw sum, no combination, no Grams
+  int win_bits, n_fix;          // window bits (traversal order) and fixed bits
+  unsigned char win_pos[32], fix_pos[32];
   long long N;
   int r;
   double alpha, shift;  // P_{j+1} = mul * alpha * (H - shift) P_j - [mode 1] P_{j-1}
@@ -86,6 +93,9 @@ void launch_combine(bool fp32, const void *const *blocks, int nblocks, const dou
                     long long N, int r, int grid, hipStream_t s);
 void launch_reduce(const double2 *partials, int count, int len, double2 *out, hipStream_t s);
 void launch_convert(bool to_fp32, const void *src, void *dst, long long n_complex, hipStream_t s);
+// dst rows = src rows moved by the site -> bit map pos (forward) or gathered back (inverse).
+void launch_permute(bool fp32, const void *src, void *dst, long long N, int r, const int *pos, int n, bool inverse,
+                    hipStream_t s);
 void launch_magnetization(bool fp32, const void *V, const double *lam, long long N, int r, int n,
                           double2 *partials, int grid, hipStream_t s);
 int nspace_grid(long long N, int r);

@@ -225,7 +225,7 @@ __global__ __launch_bounds__(kThreads) void k_cheb(ChebArgs a) {
   const int L = a.lanes;   // lanes per row, power of two, L * E >= r
   const int RW = 64 / L;   // rows per wave per iteration
   const int RP = pad16(r);
-  const bool grams = a.mode != 2;
+  const bool grams = a.mode != 2 && !a.acc_out;
 
   // LDS: four planes [kTile][RP] (cur, next) x (re, im) for the Gram products
   T *planes = reinterpret_cast<T *>(smem);
@@ -240,6 +240,7 @@ __global__ __launch_bounds__(kThreads) void k_cheb(ChebArgs a) {
   T *__restrict__ Pn = reinterpret_cast<T *>(a.Pnext);
   const DevTerm<T> *__restrict__ terms = reinterpret_cast<const DevTerm<T> *>(a.terms);
   const T *__restrict__ dv = reinterpret_cast<const T *>(a.diagv);
+  const T *__restrict__ Yin = reinterpret_cast<const T *>(a.acc_in);
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int cl = lane % L, rsub = lane / L;
@@ -267,25 +268,67 @@ __global__ __launch_bounds__(kThreads) void k_cheb(ChebArgs a) {
     for (int v = 0; v < 8; ++v) acc[q][v] = 0.0;
 
   const long long N = a.N;
-  const int nof = a.n_off;
-  const long long num_tiles = (N + kTile - 1) / kTile;
+  const int t0 = a.t0, t1 = a.t1;
+  // Tiles of 64 rows.  One window (the default): the natural row order, each
+  // XCD walking a contiguous eighth.  Several windows (a sweep confined to the
+  // window bits of its terms): the XCD x = wg % 8 takes windows x, x + 8, ...,
+  // and its workgroups share each window's tiles, so the window's rows stay in
+  // that XCD's L2 while its partner rows are gathered.
+  const int nw = a.win_bits;
+  const long long nwin = 1LL << a.n_fix;
+  const long long tiles_per_win = ((1LL << nw) + kTile - 1) / kTile;
+  auto deposit = [&](long long v, const unsigned char *pos, int nb) {
+    uint32_t x = 0;
+    for (int i = 0; i < nb; ++i) x |= (uint32_t)((v >> i) & 1) << pos[i];
+    return x;
+  };
+  const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3, g8 = a.grid >> 3;
+  const bool by_window = nwin >= 8 && (a.grid & 7) == 0;
+  long long wi = by_window ? xcd : 0, lt = by_window ? slot : 0;
+  uint32_t wbase = by_window ? deposit(wi, a.fix_pos, a.n_fix) : 0;
   for (long long k = 0;; ++k) {
-    const long long tile = tile_of(k, num_tiles, a.grid);
-    if (tile < 0) break;
-    const long long row0 = tile * kTile;
+    long long row0 = 0;
+    uint32_t tbase = 0;
+    if (by_window) {
+      while (wi < nwin && lt >= tiles_per_win) {
+        wi += 8;
+        lt = slot;
+        if (wi < nwin) wbase = deposit(wi, a.fix_pos, a.n_fix);
+      }
+      if (wi >= nwin) break;
+      tbase = wbase | deposit(lt * kTile, a.win_pos, nw);
+      lt += g8;
+    } else {
+      const long long tile = tile_of(k, (N + kTile - 1) / kTile, a.grid);
+      if (tile < 0) break;
+      row0 = tile * kTile;
+    }
     for (int it = 0; it * kWaves * RW < kTile; ++it) {
       const int lr = it * kWaves * RW + wave * RW + rsub;  // local row
       if (lr >= kTile) continue;
-      const long long x = row0 + lr;
-      if (x >= N || !active) continue;
+      const long long x = by_window ? (long long)(tbase | deposit(lr, a.win_pos, nw < 6 ? nw : 6)) : row0 + lr;
+      if (x >= N || !active || (by_window && (lr >> (nw < 6 ? nw : 6)) != 0)) continue;
       const uint32_t xu = (uint32_t)x;
-      const size_t base = (size_t)xu * r + col0;
+      const size_t rowo = (size_t)xu * r;           // row offset (complex)
+      const size_t base = rowo + col0;
+      auto ld = [&](const T *P, size_t ro, T(&v)[2 * E]) { load_ce<T, E>(P + 2 * (ro + col0), v); };
       T own[2 * E], o[2 * E];
-      load_ce<T, E>(Pc + 2 * base, own);
-      const T d = dv[xu];
+      ld(Pc, rowo, own);
+      if (a.use_diag) {
+        const T d = dv[xu];
 #pragma unroll
-      for (int e = 0; e < 2 * E; ++e) o[e] = d * own[e];
-      for (int t = 0; t < nof; t += B) {
+        for (int e = 0; e < 2 * E; ++e) o[e] = d * own[e];
+      } else {
+#pragma unroll
+        for (int e = 0; e < 2 * E; ++e) o[e] = T(0);
+      }
+      if (Yin) {
+        T yv[2 * E];
+        ld(Yin, rowo, yv);
+#pragma unroll
+        for (int e = 0; e < 2 * E; ++e) o[e] += yv[e];
+      }
+      for (int t = t0; t < t1; t += B) {
         T y[B][2 * E];
         T cr[B], ci[B];
 #pragma unroll
@@ -294,12 +337,12 @@ __global__ __launch_bounds__(kThreads) void k_cheb(ChebArgs a) {
           ci[u] = T(0);
 #pragma unroll
           for (int e = 0; e < 2 * E; ++e) y[u][e] = T(0);
-          if (t + u < nof) {
+          if (t + u < t1) {
             const DevTerm<T> &tm = terms[t + u];
             const int idx = (int)(((xu >> tm.sa) & 1u) | (((xu >> tm.sb) & 1u) << 1));
             cr[u] = pick4(idx, tm.re[0], tm.re[1], tm.re[2], tm.re[3]);
             if (CPLX) ci[u] = pick4(idx, tm.im[0], tm.im[1], tm.im[2], tm.im[3]);
-            if (cr[u] != T(0) || ci[u] != T(0)) load_ce<T, E>(Pc + 2 * ((size_t)(xu ^ tm.mask) * r + col0), y[u]);
+            if (cr[u] != T(0) || ci[u] != T(0)) ld(Pc, (size_t)(xu ^ tm.mask) * r, y[u]);
           }
         }
 #pragma unroll
@@ -314,9 +357,9 @@ __global__ __launch_bounds__(kThreads) void k_cheb(ChebArgs a) {
             }
           }
       }
-      if (a.mode != 2) {
+      if (a.mode != 2 && !a.acc_out) {
         T pv[2 * E];
-        if (a.mode == 1) load_ce<T, E>(Pp + 2 * base, pv);
+        if (a.mode == 1) ld(Pp, rowo, pv);
 #pragma unroll
         for (int e = 0; e < 2 * E; ++e) {
           o[e] = mul * alpha * (o[e] - shift * own[e]);
@@ -325,14 +368,17 @@ __global__ __launch_bounds__(kThreads) void k_cheb(ChebArgs a) {
       }
       store_ce<T, E>(Pn + 2 * base, o);
       if (grams) {
+        const int gl = by_window ? lr : (int)(x - row0);
 #pragma unroll
-        for (int e = 0; e < E; ++e)
-          if (col0 + e < r) {
-            cre[lr * RP + col0 + e] = own[2 * e];
-            cim[lr * RP + col0 + e] = own[2 * e + 1];
-            nre[lr * RP + col0 + e] = o[2 * e];
-            nim[lr * RP + col0 + e] = o[2 * e + 1];
+        for (int e = 0; e < E; ++e) {
+          const int c = col0 + e;
+          if (c < r) {
+            cre[gl * RP + c] = own[2 * e];
+            cim[gl * RP + c] = own[2 * e + 1];
+            nre[gl * RP + c] = o[2 * e];
+            nim[gl * RP + c] = o[2 * e + 1];
           }
+        }
       }
     }
     if (grams) {
@@ -488,6 +534,28 @@ __global__ __launch_bounds__(256) void k_reduce(const double2 *in, int count, in
   if (threadIdx.x == 0) out[e] = part[0];
 }
 
+// Row permutation by a bit map: y(x) = sum_i bit_i(x) << pos[i].
+// forward: dst[y(x)] = src[x]; inverse: dst[x] = src[y(x)].
+struct PermArgs {
+  unsigned char pos[32];
+  int n;
+};
+template <typename C2>
+__global__ void k_permute_rows(const C2 *src, C2 *dst, long long N, int r, PermArgs pa, int inverse) {
+  const long long total = N * r;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long x = e / r;
+    const int c = (int)(e % r);
+    uint32_t y = 0;
+    for (int i = 0; i < pa.n; ++i) y |= (uint32_t)((x >> i) & 1) << pa.pos[i];
+    if (inverse)
+      dst[e] = src[(long long)y * r + c];
+    else
+      dst[(long long)y * r + c] = src[e];
+  }
+}
+
 __global__ void k_convert_d2f(const double2 *src, float2 *dst, long long n) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
@@ -593,6 +661,13 @@ static void launch_c(const ChebArgs &a, size_t lds, hipStream_t s) {
 
 bool launch_cheb(bool fp32, const ChebArgs &a0, hipStream_t s) {
   ChebArgs a = a0;
+  if (a.win_bits == 0) {  // default: one window over all row bits, every term, the diagonal
+    a.t0 = 0;
+    a.t1 = a.n_off;
+    a.use_diag = 1;
+    a.n_fix = 0;
+    a.win_bits = 31;
+  }
   const int E = a.epl > 0 ? a.epl : cheb_elems_per_lane(fp32, a.r);
   if (a.r % E != 0) return false;
   int L = 1;
@@ -679,6 +754,22 @@ void launch_convert(bool to_fp32, const void *src, void *dst, long long n, hipSt
   else
     hipLaunchKernelGGL(k_convert_f2d, dim3((unsigned)blocks), dim3(256), 0, s,
                        (const float2 *)src, (double2 *)dst, n);
+}
+
+void launch_permute(bool fp32, const void *src, void *dst, long long N, int r, const int *pos, int n, bool inverse,
+                    hipStream_t s) {
+  PermArgs pa{};
+  pa.n = n;
+  for (int i = 0; i < n; ++i) pa.pos[i] = (unsigned char)pos[i];
+  long long blocks = (N * r + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) blocks = 1;
+  if (fp32)
+    hipLaunchKernelGGL(k_permute_rows<float2>, dim3((unsigned)blocks), dim3(256), 0, s, (const float2 *)src,
+                       (float2 *)dst, N, r, pa, (int)inverse);
+  else
+    hipLaunchKernelGGL(k_permute_rows<double2>, dim3((unsigned)blocks), dim3(256), 0, s, (const double2 *)src,
+                       (double2 *)dst, N, r, pa, (int)inverse);
 }
 
 void launch_magnetization(bool fp32, const void *V, const double *lam, long long N, int r, int n,

@@ -47,10 +47,11 @@ class lrei_stats(ctypes.Structure):
 
 
 class lrei_tune_result(ctypes.Structure):
-    _fields_ = [("epl", ctypes.c_int), ("grid", ctypes.c_int), ("ms", ctypes.c_double),
+    _fields_ = [("epl", ctypes.c_int), ("grid", ctypes.c_int), ("win_bits", ctypes.c_int),
+                ("n_sweeps", ctypes.c_int), ("ms", ctypes.c_double),
                 ("from_cache", ctypes.c_int), ("n_tried", ctypes.c_int),
-                ("tried_epl", ctypes.c_int * 32), ("tried_grid", ctypes.c_int * 32),
-                ("tried_ms", ctypes.c_double * 32)]
+                ("tried_epl", ctypes.c_int * 64), ("tried_grid", ctypes.c_int * 64),
+                ("tried_win", ctypes.c_int * 64), ("tried_ms", ctypes.c_double * 64)]
 
 
 class LreiError(RuntimeError):
@@ -230,8 +231,10 @@ class Context:
         """Times the H.V launch variants and keeps the fastest; returns the choice and all timings."""
         t = lrei_tune_result()
         self._check(self.lib.lrei_autotune(self.h, ctypes.byref(t)))
-        return {"epl": t.epl, "grid": t.grid, "ms": t.ms, "from_cache": bool(t.from_cache),
-                "tried": [(t.tried_epl[i], t.tried_grid[i], t.tried_ms[i]) for i in range(t.n_tried)]}
+        return {"epl": t.epl, "grid": t.grid, "win_bits": t.win_bits, "n_sweeps": t.n_sweeps, "ms": t.ms,
+                "from_cache": bool(t.from_cache),
+                "tried": [(t.tried_epl[i], t.tried_grid[i], t.tried_win[i], t.tried_ms[i])
+                          for i in range(t.n_tried)]}
 
     def synchronize(self):
         self._check(self.lib.lrei_synchronize(self.h))
