@@ -220,7 +220,8 @@ __device__ inline T pick4(int idx, T c0, T c1, T c2, T c3) {
 template <typename T, int E, bool CPLX, int MI>
 __global__ __launch_bounds__(kThreads) void k_cheb(ChebArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  constexpr int B = (sizeof(T) == 4 ? 32 : 16) / E > 1 ? (sizeof(T) == 4 ? 32 : 16) / E : 2;  // loads in flight
+  // row gathers in flight per lane: kept small so that four waves fit per SIMD
+  constexpr int B = (sizeof(T) == 4 ? 16 : 8) / E > 1 ? (sizeof(T) == 4 ? 16 : 8) / E : 2;
   const int r = a.r;
   const int L = a.lanes;   // lanes per row, power of two, L * E >= r
   const int RW = 64 / L;   // rows per wave per iteration
