@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default H.V launch shape")
+    ap.add_argument("--tune-cache", default=None,
+                    help="autotuner cache file: a stored choice is reused without timing trials")
     ap.add_argument("--profile-only", action="store_true",
                     help="run warmup + timed steps only (for rocprofv3 runs)")
     ap.add_argument("--kernels-only", action="store_true",
@@ -108,7 +110,7 @@ def main():
     dt, kappa = cfg["dt"], cfg["kappa"]
 
     def make_ctx(prec):
-        c = Context(device=0, precision=prec)
+        c = Context(device=0, precision=prec, autotune_cache=args.tune_cache)
         c.set_hamiltonian(cfg["n"], cfg["bonds"], cfg["J"], cfg["h"])
         c.set_rho(cfg["lam"], cfg["V"])
         return c
