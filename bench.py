@@ -34,7 +34,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", type=int, default=3)
+    ap.add_argument("--config", type=int, default=3,
+                    help="3: the n=20 lattice (default); 4: 64 batched trajectories; 2, 5: other single "
+                         "workloads")
     ap.add_argument("--precision", default=None, choices=[None, "fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
@@ -84,6 +86,111 @@ def cpu_baseline(cfg, n_rows=1 << 17, repeats=4):
     }
 
 
+def cpu_baseline_batch(trajs, budget_s=20.0):
+    """The CPU oracle's full LREI-RK4 step on the batched workload, bounded.
+
+    Sample: one oracle RK4 step per trajectory, trajectories taken in order
+    until `budget_s` seconds have been spent; the rate is scaled to the whole
+    batch by the ratio of summed N*r (the oracle's work is linear in N*r at
+    these sizes)."""
+    from oracle.hamiltonian import Hamiltonian
+    from oracle.schemes import lrei_rk_step
+    done, nr_done, t_all = 0, 0, 0.0
+    for t in trajs:
+        H = Hamiltonian(t["n"], t["bonds"], t["J"], t["h"])
+        t0 = time.perf_counter()
+        lrei_rk_step(H, t["V"], t["lam"], t["model"], t["kappa"], 0.01, "RK4")
+        t_all += time.perf_counter() - t0
+        done += 1
+        nr_done += (2 ** t["n"]) * t["lam"].size
+        if t_all > budget_s:
+            break
+    nr_total = sum((2 ** t["n"]) * t["lam"].size for t in trajs)
+    t_batch_step = t_all * nr_total / nr_done
+    return {
+        "value": len(trajs) / t_batch_step, "unit": "trajectory-steps/s", "cores": 1, "kind": "oracle",
+        "sample": (f"oracle LREI-RK4 step (N-space Householder action, exact partial eigensolve) on "
+                   f"{done} of {len(trajs)} trajectories, {t_all:.2f} s, scaled by summed N*r to the "
+                   f"whole batch"),
+    }
+
+
+def run_batch(args, torch):
+    """The batched workload: 64 independent XXZ-chain trajectories (n 12..16,
+    r in {4, 8, 16}, half q-LL / half q-LLG, kappa log-uniform in [0.01, 1]),
+    LREI-RK4 dt = 0.01, mixed precision, advanced together."""
+    from paper_2508_21200_amd import Batch
+    from workloads import make_config, CONFIGS
+    k = 4
+    base = CONFIGS[k]
+    trajs = []
+    for t in range(base["n_traj"]):
+        c = make_config(k, traj=t)
+        trajs.append(dict(n=c["n"], bonds=c["bonds"], J=c["J"], h=c["h"], lam=c["lam"], V=c["V"],
+                          model=c["model"], kappa=c["kappa"]))
+    precision = args.precision or "mixed"
+    dt, scheme = base["dt"], base["scheme"]
+    steps = args.steps
+    b = Batch(trajs, precision=precision)
+    print(f"[bench] workload {base['name']} precision={precision} warmup={args.warmup} steps={steps}",
+          file=sys.stderr, flush=True)
+    if args.warmup > 0:
+        b.step(scheme, dt, args.warmup)
+    b.synchronize()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(scheme, dt, steps)
+    b.synchronize()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    print(f"[bench] timed {steps} steps in {elapsed:.4f} s", file=sys.stderr, flush=True)
+    if args.profile_only:
+        print(json.dumps({"steps": steps, "ms_per_step": 1e3 * elapsed / steps}))
+        return
+    kms = b.profile_kernels(scheme, dt, iters=20)
+    elem = 8 if precision == "mixed" else 16
+    nr_total = sum((2 ** t["n"]) * t["lam"].size for t in trajs)
+    hv_bytes = 3 * nr_total * elem
+    achieved = hv_bytes / (kms["hv_pass"] * 1e-3) / 1e9
+    parity = None
+    if not args.no_parity and precision == "mixed":
+        from oracle.metrics import rel_fro_error
+        ref = Batch(trajs, precision="fp64")
+        ref.step(scheme, dt, args.warmup + steps)
+        worst = 0.0
+        for q, t in enumerate(trajs):
+            worst = max(worst, rel_fro_error(b.get_rho(q)[1], t["lam"], ref.get_rho(q)[1], t["lam"]))
+        parity = {"vs": "FP64 GPU batch, same inputs and step count", "rel_fro_worst_trajectory": worst}
+        ref.close()
+    cpu = None if args.no_cpu_baseline else cpu_baseline_batch(trajs)
+    rs = sorted({t["lam"].size for t in trajs})
+    line = {
+        "metric": "LREI trajectory-steps/s (64 batched trajectories)",
+        "value": len(trajs) * steps / elapsed,
+        "unit": "trajectory-steps/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64+f64" if precision == "mixed" else "c128",
+        "data": "synthetic",
+        "config": {"workload": base["name"], "n_traj": len(trajs), "n_range": [12, 16], "r_values": rs,
+                   "sum_N_r": nr_total, "scheme": scheme, "dt": dt, "precision": precision,
+                   "models": "q-LL (even trajectories), q-LLG (odd)", "lattice": "open XXZ chains"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_cheb_batch (all trajectories' H.V passes, fused Grams)",
+                     "algorithmic_bytes_per_launch": hv_bytes},
+        "cpu_baseline": cpu,
+        "parity": parity,
+        "kernels_ms": {k2: round(v, 5) for k2, v in kms.items()},
+    }
+    print(json.dumps(line))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -99,6 +206,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": nbytes, "launches": 5}))
+        return
+    if args.config == 4:
+        run_batch(args, torch)
         return
     from paper_2508_21200_amd import Context
     from workloads import make_config

@@ -203,6 +203,73 @@ typedef struct {
  * out may be NULL.  Errors: LREI_E_STATE without a state, LREI_E_DEVICE. */
 LREI_API lrei_status lrei_autotune(lrei_ctx *ctx, lrei_tune_result *out);
 
+/* ---- Batched trajectories ---------------------------------------------------
+ * Many independent LREI trajectories (each its own Hamiltonian, rank, model
+ * and damping) advanced together: every kernel of a step runs once for the
+ * whole batch (one launch per kernel and launch shape, the trajectories'
+ * work concatenated in the grid), so small problems do not each pay for
+ * their own launches.  Each trajectory computes exactly what a single
+ * context would (Sec. 3.6 steps with the same stage algebra); only the
+ * launch packing differs.  Sites are stored in their natural order (site i in
+ * bit i). */
+typedef struct lrei_batch lrei_batch;
+
+/* One trajectory: Hamiltonian as for lrei_set_hamiltonian (eq. 5.1, Pauli
+ * form; site_h may be NULL), initial state as for lrei_set_rho (host
+ * complex128 V, N x r, orthonormal columns; lambda positive, non-increasing),
+ * model (lrei_model) and damping kappa >= 0.  The arrays are copied by
+ * lrei_batch_create. */
+typedef struct {
+  int n_spins;             /* 1 <= n <= 30                                      */
+  int n_bonds;
+  const int32_t *bond_ij;  /* [n_bonds][2], 0 <= i < j < n                      */
+  const double *bond_J;    /* [n_bonds][3][3]                                   */
+  const double *site_h;    /* [n][3] or NULL                                    */
+  int r;                   /* 1 <= r <= 32, r <= 2^n                            */
+  const double *lambda;    /* [r]                                               */
+  const void *V;           /* host [2^n][r] complex128                           */
+  int model;               /* LREI_QLL or LREI_QLLG                              */
+  double kappa;
+} lrei_traj_desc;
+
+/* Creates a batch of n_traj (1..1024) trajectories on HIP device hip_device
+ * (stream as for lrei_create; opt may be NULL; opt->precision applies to all
+ * trajectories).  Validates every trajectory (LREI_E_INVALID names the first
+ * bad one; nothing is created) and uploads the states.  hbar > 0 is shared. */
+LREI_API lrei_status lrei_batch_create(lrei_batch **out, int hip_device, void *hip_stream, const lrei_options *opt,
+                                       int n_traj, const lrei_traj_desc *traj, double hbar);
+LREI_API void lrei_batch_destroy(lrei_batch *b);
+/* Message of the last failure on b (or of the last failed lrei_batch_create
+ * when b is NULL). */
+LREI_API const char *lrei_batch_last_error(const lrei_batch *b);
+
+/* Advances every trajectory by n_steps >= 0 steps of size dt > 0 with the
+ * LREI-RK scheme `scheme` (RK1..RK4; Adams-Bashforth is not batched).  One
+ * step is captured as a hipGraph on first use of a (scheme, dt) pair and
+ * replayed (opt->use_graph).  If any trajectory produces non-finite values,
+ * every trajectory is restored to its state at the start of the call and
+ * LREI_E_NUMERIC names the first failing trajectory. */
+LREI_API lrei_status lrei_batch_step(lrei_batch *b, int scheme, double dt, int n_steps);
+
+/* Copies trajectory traj's state out (as lrei_get_rho); lambda or V may be NULL. */
+LREI_API lrei_status lrei_batch_get_rho(lrei_batch *b, int traj, double *lambda, void *V, int v_is_device);
+
+/* Energy Tr(Lambda_0 V* H V) of every trajectory's current state (Sec. 3.5),
+ * energy[n_traj]. */
+LREI_API lrei_status lrei_batch_energies(lrei_batch *b, double *energy);
+
+/* Measurement: average per-launch-set times (ms) over `iters` repetitions,
+ * with HIP events on the batch's stream, of the kernels of one step of the
+ * whole batch:  ms[0] one Chebyshev H.V pass (recurrence form) with fused
+ * Grams, all launch classes; ms[1] its reduction; ms[2] the s stages of the
+ * projected step run back to back; ms[3] the basis combinations (written to
+ * the rollback copies, so the state is unchanged).  Needs a completed
+ * lrei_batch_step with the same scheme and dt (LREI_E_STATE otherwise). */
+LREI_API lrei_status lrei_batch_profile_kernels(lrei_batch *b, int scheme, double dt, int iters, double ms[4]);
+
+/* Blocks until all work queued by the batch has finished. */
+LREI_API lrei_status lrei_batch_synchronize(lrei_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -11,55 +11,14 @@
 #include <string>
 #include <vector>
 
+#include "host_common.h"
 #include "lrei_internal.h"
 
 using namespace lrei;
 
 namespace {
 
-constexpr int kStatsLen = 32;
 constexpr uint64_t kStateMagic = 0x4c52454953543031ull;  // "LREIST01"
-
-struct DevBuf {
-  void *p = nullptr;
-  size_t bytes = 0;
-  void release() {
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    bytes = 0;
-  }
-  bool ensure(size_t b) {
-    if (b <= bytes && p) return true;
-    release();
-    if (hipMalloc(&p, b) != hipSuccess) {
-      p = nullptr;
-      return false;
-    }
-    bytes = b;
-    return true;
-  }
-};
-
-// Butcher tableaux (Sec. 3.6).  RK2: the paper's Heun tableau; RK3: Kutta;
-// RK4: classical.
-void tableau(int scheme, int &s, double a[kMaxStages][kMaxStages], double b[kMaxStages]) {
-  for (int i = 0; i < kMaxStages; ++i) {
-    b[i] = 0;
-    for (int j = 0; j < kMaxStages; ++j) a[i][j] = 0;
-  }
-  switch (scheme) {
-    case LREI_RK1: s = 1; b[0] = 1; break;
-    case LREI_RK2: s = 2; a[1][0] = 1; b[0] = b[1] = 0.5; break;
-    case LREI_RK3:
-      s = 3; a[1][0] = 0.5; a[2][0] = -1; a[2][1] = 2;
-      b[0] = 1.0 / 6; b[1] = 4.0 / 6; b[2] = 1.0 / 6;
-      break;
-    default:
-      s = 4; a[1][0] = 0.5; a[2][1] = 0.5; a[3][2] = 1;
-      b[0] = 1.0 / 6; b[1] = 2.0 / 6; b[2] = 2.0 / 6; b[3] = 1.0 / 6;
-      break;
-  }
-}
 
 }  // namespace
 
@@ -80,11 +39,7 @@ struct lrei_ctx {
   long long N = 0;
   double hbar = 1.0;
   TermTable terms;
-  DevBuf d_off, d_diag;           // term records (FP64) and diagonal terms
-  DevBuf d_terms32;               // term records (FP32)
-  DevBuf d_diag64, d_diag32;      // d(x) per row
-  int n_off = 0, n_diag = 0;
-  int cplx = 0;                   // some off-diagonal coefficient is complex
+  DevTerms dt;                    // device term tables and d(x) per row
   int epl = 0;                    // H.V columns per lane (0: default)
   int hv_grid = 0;                // H.V workgroups per launch (0: default)
   // H.V sweep plan: each sweep applies the terms whose flip masks lie in its
@@ -200,12 +155,12 @@ lrei_status alloc_state(lrei_ctx *ctx, int r, bool fp32) {
 
 // Hamiltonian tables of an H.V pass.
 void hv_args(lrei_ctx *ctx, ChebArgs &a) {
-  a.terms64 = (const DevTerm<double> *)ctx->d_off.p;
-  a.terms32 = (const DevTerm<float> *)ctx->d_terms32.p;
-  a.diag64 = (const double *)ctx->d_diag64.p;
-  a.diag32 = (const float *)ctx->d_diag32.p;
-  a.n_off = ctx->n_off;
-  a.cplx = ctx->cplx;
+  a.terms64 = (const DevTerm<double> *)ctx->dt.off64.p;
+  a.terms32 = (const DevTerm<float> *)ctx->dt.off32.p;
+  a.diag64 = (const double *)ctx->dt.d64.p;
+  a.diag32 = (const float *)ctx->dt.d32.p;
+  a.n_off = ctx->dt.n_off;
+  a.cplx = ctx->dt.cplx;
   a.epl = ctx->epl;
 }
 
@@ -358,8 +313,8 @@ lrei_status hv_set_plan(lrei_ctx *ctx, int w) {
   }
   HIPCHK(hipStreamSynchronize(ctx->stream));
   if (!o64.empty()) {
-    HIPCHK(hipMemcpy(ctx->d_off.p, o64.data(), o64.size() * sizeof(DevOffTerm), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(ctx->d_terms32.p, o32.data(), o32.size() * sizeof(DevTerm<float>), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(ctx->dt.off64.p, o64.data(), o64.size() * sizeof(DevOffTerm), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(ctx->dt.off32.p, o32.data(), o32.size() * sizeof(DevTerm<float>), hipMemcpyHostToDevice));
   }
   ctx->sweeps = plan;
   ctx->hv_w = w;
@@ -729,11 +684,7 @@ void lrei_destroy(lrei_ctx *ctx) {
   ctx->ws_buf.release();
   ctx->stats_buf.release();
   ctx->lam_dev.release();
-  ctx->d_off.release();
-  ctx->d_diag.release();
-  ctx->d_terms32.release();
-  ctx->d_diag64.release();
-  ctx->d_diag32.release();
+  ctx->dt.release();
   for (auto &set : ctx->ab_U)
     for (auto &b : set) b.release();
   for (auto &b : ctx->ab_coords) b.release();
@@ -794,79 +745,13 @@ lrei_status lrei_set_hamiltonian(lrei_ctx *ctx, int n_spins, int n_bonds, const 
   if (!build_terms(n_spins, n_bonds, pbonds.data(), pJ.data(), site_h ? ph.data() : nullptr, t, e))
     return ctx->fail(LREI_E_INVALID, e);
   HIPCHK(hipSetDevice(ctx->device));
-  std::vector<DevOffTerm> off(t.off.size());
-  for (size_t i = 0; i < t.off.size(); ++i) {
-    off[i].mask = t.off[i].mask;
-    off[i].sa = t.off[i].sa;
-    off[i].sb = t.off[i].sb;
-    off[i].pad = 0;
-    for (int q = 0; q < 4; ++q) {
-      off[i].re[q] = t.off[i].re[q];
-      off[i].im[q] = t.off[i].im[q];
-    }
-  }
-  std::vector<DevDiagTerm> dg(t.diag.size());
-  for (size_t i = 0; i < t.diag.size(); ++i) dg[i] = {t.diag[i].si, t.diag[i].sj, t.diag[i].w};
-  if (off.size() > 256 || dg.size() > 512) return ctx->fail(LREI_E_INVALID, "too many Hamiltonian terms (max 256 off-diagonal, 512 diagonal)");
-  std::vector<DevTerm<float>> off32(off.size());
-  int cplx = 0;
-  for (size_t i = 0; i < off.size(); ++i) {
-    off32[i].mask = off[i].mask;
-    off32[i].sa = off[i].sa;
-    off32[i].sb = off[i].sb;
-    off32[i].pad = 0;
-    for (int q = 0; q < 4; ++q) {
-      off32[i].re[q] = (float)off[i].re[q];
-      off32[i].im[q] = (float)off[i].im[q];
-      if (off[i].im[q] != 0.0) cplx = 1;
-    }
-  }
-  const long long N = 1LL << n_spins;
-  DevBuf d_off, d_diag, d_t32, d_d64, d_d32;
-  auto release_all = [&]() {
-    d_off.release(); d_diag.release(); d_t32.release(); d_d64.release(); d_d32.release();
-  };
-  if (!d_off.ensure(std::max<size_t>(1, off.size()) * sizeof(DevOffTerm)) ||
-      !d_t32.ensure(std::max<size_t>(1, off.size()) * sizeof(DevTerm<float>)) ||
-      !d_diag.ensure(std::max<size_t>(1, dg.size()) * sizeof(DevDiagTerm)) ||
-      !d_d64.ensure((size_t)N * sizeof(double)) || !d_d32.ensure((size_t)N * sizeof(float))) {
-    release_all();
-    return ctx->fail(LREI_E_NOMEM, "device allocation failed");
-  }
-  hipError_t he = hipSuccess;
-  if (!off.empty()) {
-    he = hipMemcpy(d_off.p, off.data(), off.size() * sizeof(DevOffTerm), hipMemcpyHostToDevice);
-    if (he == hipSuccess)
-      he = hipMemcpy(d_t32.p, off32.data(), off32.size() * sizeof(DevTerm<float>), hipMemcpyHostToDevice);
-  }
-  if (he == hipSuccess && !dg.empty())
-    he = hipMemcpy(d_diag.p, dg.data(), dg.size() * sizeof(DevDiagTerm), hipMemcpyHostToDevice);
-  if (he == hipSuccess) {
-    launch_diag_values((const DevDiagTerm *)d_diag.p, (int)dg.size(), N, (double *)d_d64.p, (float *)d_d32.p,
-                       ctx->stream);
-    he = hipGetLastError();
-  }
-  if (he == hipSuccess) he = hipStreamSynchronize(ctx->stream);
-  if (he != hipSuccess) {
-    release_all();
-    return check_hip(ctx, he, "upload Hamiltonian tables");
-  }
-  ctx->d_off.release();
-  ctx->d_diag.release();
-  ctx->d_terms32.release();
-  ctx->d_diag64.release();
-  ctx->d_diag32.release();
-  ctx->d_off = d_off;
-  ctx->d_diag = d_diag;
-  ctx->d_terms32 = d_t32;
-  ctx->d_diag64 = d_d64;
-  ctx->d_diag32 = d_d32;
-  d_off.p = d_diag.p = d_t32.p = d_d64.p = d_d32.p = nullptr;
-  ctx->cplx = cplx;
+  DevTerms dt;
+  const lrei_status ust = upload_terms(t, 1LL << n_spins, ctx->stream, dt, e);
+  if (ust != LREI_OK) return ctx->fail(ust, e);
+  ctx->dt.release();
+  ctx->dt = dt;
   ctx->sweeps.clear();  // term tables are in their natural order: one sweep
   ctx->hv_w = 0;
-  ctx->n_off = (int)off.size();
-  ctx->n_diag = (int)dg.size();
   ctx->terms = t;
   if (ctx->have_rho && ctx->site_pos != pos) {
     // the stored state follows the previous site order: move it to the new one
@@ -1383,7 +1268,7 @@ static std::string tune_key(lrei_ctx *ctx) {
     if (c == ' ') c = '_';
   char buf[256];
   std::snprintf(buf, sizeof(buf), "lrei-hv %s %d %d %d %s %d %d", arch.c_str(), prop.multiProcessorCount, ctx->n,
-                ctx->r, ctx->fp32 ? "mixed" : "fp64", ctx->n_off, ctx->cplx);
+                ctx->r, ctx->fp32 ? "mixed" : "fp64", ctx->dt.n_off, ctx->dt.cplx);
   return buf;
 }
 

@@ -87,6 +87,42 @@ struct ChebArgs {
 };
 
 bool launch_cheb(bool fp32, const ChebArgs &a, hipStream_t s);
+// Fills the launcher-set fields of a (columns per lane, lanes, table pointers,
+// the default single window); false if the shape is unsupported.
+bool prepare_cheb(bool fp32, ChebArgs &a);
+size_t cheb_lds_bytes(bool fp32, int r);
+
+// Launch tables of a batched kernel (many independent jobs in one launch):
+// workgroup w runs job wg_job[w] as that job's workgroup w - job_wg0[job].
+// jobs points to a device array of the kernel's per-job argument records.
+struct BatchLaunch {
+  const void *jobs;
+  const int *wg_job;
+  const int *job_wg0;
+};
+// Batched Chebyshev passes: every job is a ChebArgs prepared by prepare_cheb
+// with the same precision, columns per lane epl, complex flag and r > 16 flag.
+bool launch_cheb_batch(bool fp32, int epl, bool cplx, bool big, const BatchLaunch &b, int total_wg, size_t lds,
+                       hipStream_t s);
+// Basis combination out = [B_0 ... B_{nb-1}] C (nspace.hip).
+struct CombineArgs {
+  const void *blocks[kMaxBlocks];
+  int nb;
+  const double2 *C;
+  void *out;
+  long long N;
+  int r, grid;
+};
+// Batched combinations: every job has the same nb and padded width RP (16 or 32).
+void launch_combine_batch(bool fp32, int RP, int nblocks, const BatchLaunch &b, int total_wg, hipStream_t s);
+// Batched reductions: job q sums q.count partials per entry into q.out; one
+// workgroup per entry.
+struct ReduceJob {
+  const double2 *in;
+  int count;
+  double2 *out;
+};
+void launch_reduce_batch(const BatchLaunch &b, int total_wg, hipStream_t s);
 void launch_diag_values(const DevDiagTerm *diag, int n_diag, long long N, double *d64, float *d32, hipStream_t s);
 int cheb_elems_per_lane(bool fp32, int r);
 void launch_combine(bool fp32, const void *const *blocks, int nblocks, const double2 *C, void *out,
@@ -167,6 +203,10 @@ inline int small_lds_elems(int D, int r) {
 }
 void launch_small_rk(const SmallRkParams &p, const SmallWs &ws, hipStream_t s);
 void launch_small_rk_stage(const SmallRkParams &p, const SmallWs &ws, int j, hipStream_t s);
+// Stage j of many independent projected steps, one workgroup per job;
+// lds_elems is the largest p.lds_elems among the jobs.
+void launch_small_rk_stage_batch(const SmallRkParams *p, const SmallWs *ws, int n_jobs, int lds_elems, int j,
+                                 hipStream_t s);
 
 // Projected AB step / history update (small.hip).
 constexpr int kMaxAb = 4;  // AB4

@@ -8,6 +8,8 @@
 // FP64, 128 B in FP32) and any row gather is a coalesced segment load.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "lrei_internal.h"
 
 namespace lrei {
@@ -53,8 +55,7 @@ template <> struct Acc4<float> { using type = f4v; };
 // Tile -> workgroup assignment.  When possible each of the 8 XCDs (workgroup
 // w runs on XCD w % 8) walks one contiguous eighth of the rows, so the
 // partner rows of low-bit flips stay in that XCD's L2.
-__device__ inline long long tile_of(long long k, long long num_tiles, int grid) {
-  const int w = blockIdx.x;
+__device__ inline long long tile_of(long long k, long long num_tiles, int grid, int w) {
   if ((grid & 7) == 0 && (num_tiles & 7) == 0 && num_tiles >= grid) {
     const long long per = num_tiles >> 3;
     const int g8 = grid >> 3;
@@ -116,9 +117,8 @@ __device__ inline void gram_tile(const T *const *xre, const T *const *xim, const
 // summed through LDS in a fixed wave order, so the result is deterministic.
 template <typename T, int MI>
 __device__ inline void gram_store(const GramPlan<T> &gp, const double (&acc)[MI][8], int r,
-                                  double2 *partials, double2 *stage /* LDS, ng * r * r */) {
+                                  double2 *partials, double2 *stage /* LDS, ng * r * r */, int grid, int wg) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int grid = gridDim.x;
   for (int w = 0; w < kWaves; ++w) {
     if (gp.rs == 1 || wave == w) {
 #pragma unroll
@@ -150,7 +150,7 @@ __device__ inline void gram_store(const GramPlan<T> &gp, const double (&acc)[MI]
     __syncthreads();
     if (gp.rs == 1) break;
   }
-  for (int e = threadIdx.x; e < gp.ng * r * r; e += kThreads) partials[(long long)e * grid + blockIdx.x] = stage[e];
+  for (int e = threadIdx.x; e < gp.ng * r * r; e += kThreads) partials[(long long)e * grid + wg] = stage[e];
 }
 
 template <typename T>
@@ -216,10 +216,10 @@ __device__ inline T pick4(int idx, T c0, T c1, T c2, T c3) {
 }
 
 // E complex columns per lane, CPLX: some coefficient has an imaginary part,
-// MI: Gram work items per wave.
-template <typename T, int E, bool CPLX, int MI>
-__global__ __launch_bounds__(kThreads) void k_cheb(ChebArgs a) {
-  extern __shared__ __align__(16) unsigned char smem[];
+// MI: Gram work items per wave, WIN: row-bit window sweeps allowed.  wg is the
+// workgroup's index among the a.grid workgroups of this pass.
+template <typename T, int E, bool CPLX, int MI, bool WIN>
+__device__ __forceinline__ void cheb_body(const ChebArgs &a, int wg, unsigned char *smem) {
   // row gathers in flight per lane: kept small so that four waves fit per SIMD
   constexpr int B = (sizeof(T) == 4 ? 16 : 8) / E > 1 ? (sizeof(T) == 4 ? 16 : 8) / E : 2;
   const int r = a.r;
@@ -283,8 +283,8 @@ __global__ __launch_bounds__(kThreads) void k_cheb(ChebArgs a) {
     for (int i = 0; i < nb; ++i) x |= (uint32_t)((v >> i) & 1) << pos[i];
     return x;
   };
-  const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3, g8 = a.grid >> 3;
-  const bool by_window = nwin >= 8 && (a.grid & 7) == 0;
+  const int xcd = wg & 7, slot = wg >> 3, g8 = a.grid >> 3;
+  const bool by_window = WIN && nwin >= 8 && (a.grid & 7) == 0;
   long long wi = by_window ? xcd : 0, lt = by_window ? slot : 0;
   uint32_t wbase = by_window ? deposit(wi, a.fix_pos, a.n_fix) : 0;
   for (long long k = 0;; ++k) {
@@ -300,7 +300,7 @@ __global__ __launch_bounds__(kThreads) void k_cheb(ChebArgs a) {
       tbase = wbase | deposit(lt * kTile, a.win_pos, nw);
       lt += g8;
     } else {
-      const long long tile = tile_of(k, (N + kTile - 1) / kTile, a.grid);
+      const long long tile = tile_of(k, (N + kTile - 1) / kTile, a.grid, wg);
       if (tile < 0) break;
       row0 = tile * kTile;
     }
@@ -392,8 +392,27 @@ __global__ __launch_bounds__(kThreads) void k_cheb(ChebArgs a) {
   }
   if (grams) {
     __syncthreads();
-    gram_store<T, MI>(gp, acc, r, a.partials, reinterpret_cast<double2 *>(planes));
+    gram_store<T, MI>(gp, acc, r, a.partials, reinterpret_cast<double2 *>(planes), a.grid, wg);
   }
+}
+
+template <typename T, int E, bool CPLX, int MI>
+__global__ __launch_bounds__(kThreads) void k_cheb(ChebArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  cheb_body<T, E, CPLX, MI, true>(a, blockIdx.x, smem);
+}
+
+// Many independent passes in one launch (one per trajectory of a batch): the
+// workgroup's job and its index within that job come from the launch tables;
+// every job's workgroups start at a multiple of 8, so a workgroup keeps its
+// XCD slot within the job.
+template <typename T, int E, bool CPLX, int MI>
+__global__ __launch_bounds__(kThreads) void k_cheb_batch(BatchLaunch b) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int j = b.wg_job[blockIdx.x];
+  if (j < 0) return;  // alignment padding
+  const ChebArgs a = reinterpret_cast<const ChebArgs *>(b.jobs)[j];
+  cheb_body<T, E, CPLX, MI, false>(a, blockIdx.x - b.job_wg0[j], smem);
 }
 
 // Diagonal of H per row: d(x) = sum_k w_k (1 - 2 (b_{i_k}(x) xor b_{j_k}(x))),
@@ -415,14 +434,6 @@ __global__ void k_diag_values(const DevDiagTerm *diag, int n_diag, long long N, 
 // out (N x r) = [B_0 ... B_{nb-1}] (N x nb r) * C (nb r x r), C complex FP64.
 // In place over B_0 is allowed: a tile's rows are read before they are written.
 // ---------------------------------------------------------------------------
-struct CombineArgs {
-  const void *blocks[kMaxBlocks];
-  int nb;
-  const double2 *C;
-  void *out;
-  long long N;
-  int r, grid;
-};
 
 // Each wave forms 16 output rows at a time with 16x16x4 MFMA.  The MFMA inner
 // index is permuted so that lane (i, q) of the A operand holds CPL consecutive
@@ -431,9 +442,8 @@ struct CombineArgs {
 // permutation.  C sits in LDS.  In place over block 0 is allowed: a wave reads
 // all of its rows before it writes them, and no other wave touches them.
 template <typename T, int RP>
-__global__ __launch_bounds__(kThreads) void k_combine(CombineArgs a) {
+__device__ __forceinline__ void combine_body(const CombineArgs &a, int wg, unsigned char *smem) {
   using A4 = typename Acc4<T>::type;
-  extern __shared__ __align__(16) unsigned char smem[];
   const int r = a.r, nb = a.nb;
   const int K = nb * RP;
   T *cre = reinterpret_cast<T *>(smem);  // [K][RP]
@@ -455,7 +465,7 @@ __global__ __launch_bounds__(kThreads) void k_combine(CombineArgs a) {
   const long long N = a.N;
   const long long num_tiles = (N + kTile - 1) / kTile;
   for (long long k = 0;; ++k) {
-    const long long tile = tile_of(k, num_tiles, a.grid);
+    const long long tile = tile_of(k, num_tiles, a.grid, wg);
     if (tile < 0) break;
     const long long x = tile * kTile + wave * 16 + i16;  // this lane's A row
     A4 ore[2], oim[2];
@@ -512,11 +522,26 @@ __global__ __launch_bounds__(kThreads) void k_combine(CombineArgs a) {
   }
 }
 
+template <typename T, int RP>
+__global__ __launch_bounds__(kThreads) void k_combine(CombineArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  combine_body<T, RP>(a, blockIdx.x, smem);
+}
+
+template <typename T, int RP>
+__global__ __launch_bounds__(kThreads) void k_combine_batch(BatchLaunch b) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int j = b.wg_job[blockIdx.x];
+  if (j < 0) return;  // alignment padding
+  // read in place: a copy of the block-pointer array would live in scratch
+  const CombineArgs &a = reinterpret_cast<const CombineArgs *>(b.jobs)[j];
+  combine_body<T, RP>(a, blockIdx.x - b.job_wg0[j], smem);
+}
+
 // Deterministic reduction of entry-major partials: out[e] = sum_c in[e * count + c],
 // one workgroup per entry, strided per-thread sums then a fixed tree.
-__global__ __launch_bounds__(256) void k_reduce(const double2 *in, int count, int len, double2 *out) {
+__device__ __forceinline__ void reduce_body(const double2 *in, int count, double2 *out, int e) {
   __shared__ double2 part[256];
-  const int e = blockIdx.x;
   double sr = 0.0, si = 0.0;
   for (int c = threadIdx.x; c < count; c += 256) {
     const double2 v = in[(long long)e * count + c];
@@ -533,6 +558,19 @@ __global__ __launch_bounds__(256) void k_reduce(const double2 *in, int count, in
     __syncthreads();
   }
   if (threadIdx.x == 0) out[e] = part[0];
+}
+
+__global__ __launch_bounds__(256) void k_reduce(const double2 *in, int count, int len, double2 *out) {
+  (void)len;
+  reduce_body(in, count, out, blockIdx.x);
+}
+
+// One workgroup per entry of every job.
+__global__ __launch_bounds__(256) void k_reduce_batch(BatchLaunch b) {
+  const int j = b.wg_job[blockIdx.x];
+  if (j < 0) return;
+  const ReduceJob q = reinterpret_cast<const ReduceJob *>(b.jobs)[j];
+  reduce_body(q.in, q.count, q.out, blockIdx.x - b.job_wg0[j]);
 }
 
 // Row permutation by a bit map: y(x) = sum_i bit_i(x) << pos[i].
@@ -637,12 +675,19 @@ int nspace_grid(long long N, int r) {
   return (int)(g < 1 ? 1 : g);
 }
 
-// Complex columns per lane for the H.V pass: 16-byte lanes, E | r.
+// Complex columns per lane for the H.V pass: 16-byte lanes, E | r, and at
+// least four lanes per row where r allows, so that the four waves of a
+// 64-row tile all have rows.
 int cheb_elems_per_lane(bool fp32, int r) {
-  if (r > 16) return (fp32 && r % 2 == 0) ? 2 : 1;
-  if (fp32) return r % 4 == 0 ? 4 : (r % 2 == 0 ? 2 : 1);
-  return r % 2 == 0 ? 2 : 1;
+  int e;
+  if (r > 16) e = (fp32 && r % 2 == 0) ? 2 : 1;
+  else if (fp32) e = r % 4 == 0 ? 4 : (r % 2 == 0 ? 2 : 1);
+  else e = r % 2 == 0 ? 2 : 1;
+  while (e > 1 && r / e < 4) e >>= 1;
+  return e;
 }
+
+size_t cheb_lds_bytes(bool fp32, int r) { return cheb_lds(fp32, r); }
 
 template <typename T, int E, bool C, int MI>
 static void launch_one(const ChebArgs &a, size_t lds, hipStream_t s) {
@@ -654,14 +699,65 @@ static void launch_one(const ChebArgs &a, size_t lds, hipStream_t s) {
   hipLaunchKernelGGL((k_cheb<T, E, C, MI>), dim3(a.grid), dim3(kThreads), lds, s, a);
 }
 
-template <typename T, int E, int MI>
-static void launch_c(const ChebArgs &a, size_t lds, hipStream_t s) {
-  if (a.cplx) launch_one<T, E, true, MI>(a, lds, s);
-  else launch_one<T, E, false, MI>(a, lds, s);
+template <typename T, int E, bool C, int MI>
+static void launch_one_batch(const BatchLaunch &b, int total_wg, size_t lds, hipStream_t s) {
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void *)k_cheb_batch<T, E, C, MI>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              kMaxLds);
+    attr = true;
+  }
+  hipLaunchKernelGGL((k_cheb_batch<T, E, C, MI>), dim3(total_wg), dim3(kThreads), lds, s, b);
 }
 
-bool launch_cheb(bool fp32, const ChebArgs &a0, hipStream_t s) {
-  ChebArgs a = a0;
+// Dispatches on (precision, E, complex coefficients, Gram items per wave).
+// F is called as F.template operator()<T, E, C, MI>().
+template <typename Fn>
+static bool dispatch_cheb(bool fp32, int E, bool cplx, bool big, Fn &&f) {
+  auto c = [&](auto tag_t, auto tag_e, auto tag_mi) {
+    using T = typename decltype(tag_t)::type;
+    constexpr int EE = decltype(tag_e)::value, MI = decltype(tag_mi)::value;
+    if (cplx) f.template operator()<T, EE, true, MI>();
+    else f.template operator()<T, EE, false, MI>();
+  };
+  struct F32 { using type = float; };
+  struct F64 { using type = double; };
+  using I1 = std::integral_constant<int, 1>;
+  using I2 = std::integral_constant<int, 2>;
+  using I3 = std::integral_constant<int, 3>;
+  using I4 = std::integral_constant<int, 4>;
+  using I8 = std::integral_constant<int, 8>;
+  if (fp32) {
+    if (big) {
+      if (E == 2) c(F32{}, I2{}, I3{});
+      else if (E == 1) c(F32{}, I1{}, I3{});
+      else return false;
+    } else {
+      switch (E) {
+        case 8: c(F32{}, I8{}, I1{}); break;
+        case 4: c(F32{}, I4{}, I1{}); break;
+        case 2: c(F32{}, I2{}, I1{}); break;
+        case 1: c(F32{}, I1{}, I1{}); break;
+        default: return false;
+      }
+    }
+  } else {
+    if (big) {
+      if (E != 1) return false;
+      c(F64{}, I1{}, I3{});
+    } else {
+      switch (E) {
+        case 4: c(F64{}, I4{}, I1{}); break;
+        case 2: c(F64{}, I2{}, I1{}); break;
+        case 1: c(F64{}, I1{}, I1{}); break;
+        default: return false;
+      }
+    }
+  }
+  return true;
+}
+
+bool prepare_cheb(bool fp32, ChebArgs &a) {
   if (a.win_bits == 0) {  // default: one window over all row bits, every term, the diagonal
     a.t0 = 0;
     a.t1 = a.n_off;
@@ -674,36 +770,29 @@ bool launch_cheb(bool fp32, const ChebArgs &a0, hipStream_t s) {
   int L = 1;
   while (L * E < a.r) L <<= 1;
   if (L > 64) return false;
+  const bool big = a.r > 16;  // three Gram work items per wave above r = 16
+  if (fp32 ? (big && E > 2) || (!big && E > 8) : (big && E != 1) || (!big && E > 4)) return false;
   a.lanes = L;
   a.epl = E;
   a.terms = fp32 ? (const void *)a.terms32 : (const void *)a.terms64;
   a.diagv = fp32 ? (const void *)a.diag32 : (const void *)a.diag64;
-  const size_t lds = cheb_lds(fp32, a.r);
-  const bool big = a.r > 16;  // three Gram work items per wave above r = 16
-  if (fp32) {
-    if (big) {
-      if (E == 2) launch_c<float, 2, 3>(a, lds, s); else launch_c<float, 1, 3>(a, lds, s);
-    } else {
-      switch (E) {
-        case 8: launch_c<float, 8, 1>(a, lds, s); break;
-        case 4: launch_c<float, 4, 1>(a, lds, s); break;
-        case 2: launch_c<float, 2, 1>(a, lds, s); break;
-        default: launch_c<float, 1, 1>(a, lds, s);
-      }
-    }
-  } else {
-    if (big) {
-      launch_c<double, 1, 3>(a, lds, s);
-      if (E != 1) return false;
-    } else {
-      switch (E) {
-        case 4: launch_c<double, 4, 1>(a, lds, s); break;
-        case 2: launch_c<double, 2, 1>(a, lds, s); break;
-        default: launch_c<double, 1, 1>(a, lds, s);
-      }
-    }
-  }
   return true;
+}
+
+bool launch_cheb(bool fp32, const ChebArgs &a0, hipStream_t s) {
+  ChebArgs a = a0;
+  if (!prepare_cheb(fp32, a)) return false;
+  const size_t lds = cheb_lds(fp32, a.r);
+  return dispatch_cheb(fp32, a.epl, a.cplx != 0, a.r > 16, [&]<typename T, int E, bool C, int MI>() {
+    launch_one<T, E, C, MI>(a, lds, s);
+  });
+}
+
+bool launch_cheb_batch(bool fp32, int epl, bool cplx, bool big, const BatchLaunch &b, int total_wg, size_t lds,
+                       hipStream_t s) {
+  return dispatch_cheb(fp32, epl, cplx, big, [&]<typename T, int E, bool C, int MI>() {
+    launch_one_batch<T, E, C, MI>(b, total_wg, lds, s);
+  });
 }
 
 void launch_diag_values(const DevDiagTerm *diag, int n_diag, long long N, double *d64, float *d32, hipStream_t s) {
@@ -739,6 +828,29 @@ void launch_combine(bool fp32, const void *const *blocks, int nblocks, const dou
     if (RP == 16) hipLaunchKernelGGL((k_combine<double, 16>), dim3(grid), dim3(kThreads), lds, s, a);
     else hipLaunchKernelGGL((k_combine<double, 32>), dim3(grid), dim3(kThreads), lds, s, a);
   }
+}
+
+void launch_combine_batch(bool fp32, int RP, int nblocks, const BatchLaunch &b, int total_wg, hipStream_t s) {
+  const size_t lds = (size_t)(2 * nblocks * RP * RP) * (fp32 ? 4 : 8);
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void *)k_combine_batch<float, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+    (void)hipFuncSetAttribute((const void *)k_combine_batch<float, 32>, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+    (void)hipFuncSetAttribute((const void *)k_combine_batch<double, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+    (void)hipFuncSetAttribute((const void *)k_combine_batch<double, 32>, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+    attr = true;
+  }
+  if (fp32) {
+    if (RP == 16) hipLaunchKernelGGL((k_combine_batch<float, 16>), dim3(total_wg), dim3(kThreads), lds, s, b);
+    else hipLaunchKernelGGL((k_combine_batch<float, 32>), dim3(total_wg), dim3(kThreads), lds, s, b);
+  } else {
+    if (RP == 16) hipLaunchKernelGGL((k_combine_batch<double, 16>), dim3(total_wg), dim3(kThreads), lds, s, b);
+    else hipLaunchKernelGGL((k_combine_batch<double, 32>), dim3(total_wg), dim3(kThreads), lds, s, b);
+  }
+}
+
+void launch_reduce_batch(const BatchLaunch &b, int total_wg, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_batch, dim3(total_wg), dim3(256), 0, s, b);
 }
 
 void launch_reduce(const double2 *partials, int count, int len, double2 *out, hipStream_t s) {

@@ -949,7 +949,6 @@ __device__ void rhs_coords(const double2 *u, const double2 *y, int m, int D, int
 // u1), (coef_l z_l, u_l), (coef_l u_l, w_l), so that K is Hermitian to the last
 // bit.  Lower 16 x 16 tiles, one per wave at a time, on FP64 MFMA with the
 // factor rows (m x r, row-major) read straight from memory.
-constexpr int kMaxTerms = 4;
 typedef double d4v_s __attribute__((ext_vector_type(4)));
 __device__ inline d4v_s mfma_d(double a, double b, d4v_s c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -1075,8 +1074,7 @@ __device__ void householder_qr(double2 *M, int m, int q, double2 *Q, double2 *Rm
 // the stage.  State between launches lives in the workspace.
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(NT) void k_small_rk(SmallRkParams p, SmallWs ws, int j) {
-  extern __shared__ __align__(16) double2 s_arena[];
+__device__ __forceinline__ void small_rk_body(const SmallRkParams &p, const SmallWs &ws, int j, double2 *s_arena) {
   __shared__ StepShared sh;
 
   const int r = p.r, s = p.s, nb = p.nblocks, D = nb * r, rr = r * r;
@@ -1325,6 +1323,29 @@ __global__ __launch_bounds__(NT) void k_small_rk(SmallRkParams p, SmallWs ws, in
       stats[15] += 1;
     }
   }
+}
+
+__global__ __launch_bounds__(NT) void k_small_rk(SmallRkParams p, SmallWs ws, int j) {
+  extern __shared__ __align__(16) double2 s_arena[];
+  small_rk_body(p, ws, j, s_arena);
+}
+
+// One workgroup per job of a batch.
+__global__ __launch_bounds__(NT) void k_small_rk_batch(const SmallRkParams *__restrict__ ps,
+                                                      const SmallWs *__restrict__ wss, int j) {
+  extern __shared__ __align__(16) double2 s_arena[];
+  small_rk_body(ps[blockIdx.x], wss[blockIdx.x], j, s_arena);
+}
+
+void launch_small_rk_stage_batch(const SmallRkParams *p, const SmallWs *ws, int n_jobs, int lds_elems, int j,
+                                 hipStream_t s) {
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void *)k_small_rk_batch, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              kSmallLdsBytes);
+    attr = true;
+  }
+  hipLaunchKernelGGL(k_small_rk_batch, dim3(n_jobs), dim3(NT), (size_t)lds_elems * sizeof(double2), s, p, ws, j);
 }
 
 void launch_small_rk(const SmallRkParams &p, const SmallWs &ws, hipStream_t s) {

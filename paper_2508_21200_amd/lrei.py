@@ -54,6 +54,13 @@ class lrei_tune_result(ctypes.Structure):
                 ("tried_win", ctypes.c_int * 64), ("tried_ms", ctypes.c_double * 64)]
 
 
+class lrei_traj_desc(ctypes.Structure):
+    _fields_ = [("n_spins", ctypes.c_int), ("n_bonds", ctypes.c_int), ("bond_ij", ctypes.c_void_p),
+                ("bond_J", ctypes.c_void_p), ("site_h", ctypes.c_void_p), ("r", ctypes.c_int),
+                ("lambda_", ctypes.c_void_p), ("V", ctypes.c_void_p), ("model", ctypes.c_int),
+                ("kappa", ctypes.c_double)]
+
+
 class LreiError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
@@ -82,6 +89,15 @@ _SIGS = {
                                              ctypes.c_int, _P]),
     "lrei_synchronize": (ctypes.c_int, [_P]),
     "lrei_autotune": (ctypes.c_int, [_P, ctypes.POINTER(lrei_tune_result)]),
+    "lrei_batch_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, _P, ctypes.POINTER(lrei_options),
+                                         ctypes.c_int, ctypes.POINTER(lrei_traj_desc), ctypes.c_double]),
+    "lrei_batch_destroy": (None, [_P]),
+    "lrei_batch_last_error": (ctypes.c_char_p, [_P]),
+    "lrei_batch_step": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_double, ctypes.c_int]),
+    "lrei_batch_get_rho": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.c_int]),
+    "lrei_batch_energies": (ctypes.c_int, [_P, _P]),
+    "lrei_batch_profile_kernels": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_double, ctypes.c_int, _P]),
+    "lrei_batch_synchronize": (ctypes.c_int, [_P]),
 }
 
 
@@ -238,3 +254,97 @@ class Context:
 
     def synchronize(self):
         self._check(self.lib.lrei_synchronize(self.h))
+
+
+class Batch:
+    """Many independent trajectories advanced together (lrei_batch_* entry points).
+
+    trajs: list of dicts with keys n, bonds, J, h (or None), lam, V (host
+    complex128), model ("qLL"/"qLLG") and kappa.
+    """
+
+    def __init__(self, trajs, device=0, stream=None, precision="fp64", use_graph=True, hbar=1.0,
+                 householder_mode=1):
+        self.lib = load()
+        opt = lrei_options()
+        self.lib.lrei_default_options(ctypes.byref(opt))
+        opt.precision = PRECISIONS[precision]
+        opt.use_graph = int(bool(use_graph))
+        opt.householder_mode = householder_mode
+        descs = (lrei_traj_desc * len(trajs))()
+        keep = []
+        self.shapes = []
+        for q, t in enumerate(trajs):
+            n = int(t["n"])
+            bonds = np.ascontiguousarray(np.asarray(t["bonds"], dtype=np.int32).reshape(-1, 2))
+            J = np.ascontiguousarray(np.asarray(t["J"], dtype=np.float64).reshape(-1, 3, 3))
+            hh = None if t.get("h") is None else np.ascontiguousarray(
+                np.asarray(t["h"], dtype=np.float64).reshape(n, 3))
+            lam = np.ascontiguousarray(np.asarray(t["lam"], dtype=np.float64))
+            V = np.ascontiguousarray(np.asarray(t["V"]), dtype=np.complex128)
+            keep.append((bonds, J, hh, lam, V))
+            d = descs[q]
+            d.n_spins = n
+            d.n_bonds = bonds.shape[0]
+            d.bond_ij = bonds.ctypes.data
+            d.bond_J = J.ctypes.data
+            d.site_h = None if hh is None else hh.ctypes.data
+            d.r = lam.size
+            d.lambda_ = lam.ctypes.data
+            d.V = V.ctypes.data
+            d.model = MODELS[t["model"]]
+            d.kappa = float(t["kappa"])
+            self.shapes.append((n, lam.size))
+        h = _P()
+        st = self.lib.lrei_batch_create(ctypes.byref(h), int(device), stream, ctypes.byref(opt), len(trajs),
+                                        descs, float(hbar))
+        if st != LREI_OK:
+            raise LreiError(st, self.lib.lrei_batch_last_error(None).decode())
+        self.h = h
+        self.precision = precision
+
+    def _check(self, st):
+        if st != LREI_OK:
+            raise LreiError(st, self.lib.lrei_batch_last_error(self.h).decode())
+
+    def __len__(self):
+        return len(self.shapes)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.lrei_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, scheme, dt, n_steps=1):
+        self._check(self.lib.lrei_batch_step(self.h, SCHEMES[scheme], float(dt), int(n_steps)))
+
+    def get_rho(self, traj, out=None):
+        if not 0 <= traj < len(self.shapes):  # the library reports the bad index
+            self._check(self.lib.lrei_batch_get_rho(self.h, int(traj), None, None, 0))
+        n, r = self.shapes[traj]
+        lam = np.zeros(r, dtype=np.float64)
+        if out is None:
+            out = np.zeros((2 ** n, r), dtype=np.complex128)
+        p, dev = _ptr(out)
+        self._check(self.lib.lrei_batch_get_rho(self.h, int(traj), lam.ctypes.data, p, dev))
+        return lam, out
+
+    def profile_kernels(self, scheme, dt, iters=20):
+        """Average ms of (H.V pass, reduction, projected step, combination) for the whole batch."""
+        ms = (ctypes.c_double * 4)()
+        self._check(self.lib.lrei_batch_profile_kernels(self.h, SCHEMES[scheme], float(dt), int(iters), ms))
+        return dict(hv_pass=ms[0], reduce=ms[1], projected_step=ms[2], combine=ms[3])
+
+    def energies(self):
+        e = np.zeros(len(self.shapes), dtype=np.float64)
+        self._check(self.lib.lrei_batch_energies(self.h, e.ctypes.data))
+        return e
+
+    def synchronize(self):
+        self._check(self.lib.lrei_batch_synchronize(self.h))
