@@ -310,7 +310,7 @@ def main():
             "epl": tuning["epl"], "grid": tuning["grid"], "win_bits": tuning["win_bits"],
             "n_sweeps": tuning["n_sweeps"], "ms": round(tuning["ms"], 5),
             "tried": [[e, g, w, round(t, 5)] for e, g, w, t in tuning["tried"]]},
-        "eig_stats": {k: stats[k] for k in ("eigensolves", "jacobi_sweeps", "max_sweeps_one_solve",
+        "eig_stats": {k: stats[k] for k in ("eigensolves", "warm_accepted", "warm_rejected", "warm_iterations",
                                             "dropped_directions", "min_pivot_ratio", "ortho_error")},
         "projected_phase_ms_per_step": dict(zip(
             ["gram_setup", "cholesky", "r_inverse", "h_apply", "householder", "stage_matrix", "eigensolve", "tail"],

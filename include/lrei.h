@@ -65,8 +65,16 @@ typedef enum {
  * eigensolve) always runs in FP64. */
 typedef enum { LREI_FP64 = 0, LREI_MIXED = 1 } lrei_precision;
 
-/* Start rotation for the projected eigensolve: identity, the first-order
- * analytic rotation, or the one proposed by the learned network. */
+/* How each stage's partial eigensolve (Sec. 3.6: the r largest eigenpairs of
+ * the stage matrix) is computed in the projected coordinates.
+ *  LREI_WARM_PLAIN: direct solve (Householder tridiagonalisation, multisection,
+ *    inverse iteration), exact to FP64 rounding whatever the start.
+ *  LREI_WARM_ANALYTIC: subspace iteration started from the stage's input basis
+ *    (the predicted eigenvectors), accepted only with a certificate that its
+ *    r Ritz values are the r largest eigenvalues, else the direct solve.
+ *  LREI_WARM_LEARNED: a start rotation proposed by a trained network; not
+ *    provided (an r x r rotation of the start leaves the iterated subspace,
+ *    and so the result and the iteration count, unchanged); rejected. */
 typedef enum { LREI_WARM_PLAIN = 0, LREI_WARM_ANALYTIC = 1, LREI_WARM_LEARNED = 2 } lrei_warm;
 
 typedef struct {
@@ -74,7 +82,8 @@ typedef struct {
   double eig_tol;         /* Jacobi tolerance (relative to max|diag|) of the r x r Lowdin
                              re-orthonormalisation, default 1e-15                       */
   int eig_max_sweeps;     /* Jacobi sweep limit of that step, default 40                 */
-  int warm;               /* lrei_warm, default LREI_WARM_PLAIN                          */
+  int warm;               /* lrei_warm, default LREI_WARM_ANALYTIC (RK steps; the AB
+                             step always uses the direct solve)                     */
   int ab_bootstrap;       /* RK scheme for the first m-1 ABm steps, default LREI_RK4     */
   int householder_mode;   /* 1: complement action through Householder reflectors (eq.
                              3.3, Sec. 3.4), default; 0: orthogonal projector form      */
@@ -86,19 +95,21 @@ typedef struct {
 typedef struct {
   int64_t steps_done;            /* time steps completed on this context               */
   int64_t eigensolves;           /* projected eigensolves performed                    */
-  int64_t jacobi_sweeps;         /* total Jacobi sweeps (Lowdin step)                  */
-  int32_t max_sweeps_one_solve;  /* largest sweep count of one eigensolve              */
+  int64_t warm_accepted;         /* eigensolves done by subspace iteration from the
+                                    stage's input basis (LREI_WARM_ANALYTIC)           */
+  int64_t warm_rejected;         /* of those, the ones that fell back to the direct
+                                    solver (no convergence or no certificate)          */
+  int64_t warm_iterations;       /* subspace iterations run                             */
   int32_t dropped_directions;    /* Krylov directions dropped as dependent (last step)  */
+  int32_t reserved;
   double min_pivot_ratio;        /* smallest Cholesky pivot / Gram diagonal (last step) */
   double ortho_error;            /* max |V*V - I| at the start of the last step         */
   double energy;                 /* Tr(Lambda_0 V* H V) at the start of the last step   */
   double last_step_ms;           /* wall time of the last lrei_step call                */
-  int64_t warm_accepted;         /* learned/analytic start rotations used                */
-  int64_t warm_rejected;         /* start rotations rejected (fell back to identity)     */
   double phase_ms[8];            /* projected-step kernel time by phase over the last
                                     call: Gram/Cholesky setup, Cholesky, R^-1, H u,
                                     Householder, stage matrix, eigensolve, tail      */
-  double eig_phase_ms[6];        /* eigensolve time over the last call by part:
+  double eig_phase_ms[6];        /* direct-eigensolver time over the last call by part:
                                     tridiagonalisation, multisection, inverse
                                     iteration, back-transform; and of the
                                     tridiagonalisation: its A v products, its

@@ -620,7 +620,7 @@ void lrei_default_options(lrei_options *o) {
   o->precision = LREI_FP64;
   o->eig_tol = 1e-15;
   o->eig_max_sweeps = 40;
-  o->warm = LREI_WARM_PLAIN;
+  o->warm = LREI_WARM_ANALYTIC;
   o->ab_bootstrap = LREI_RK4;
   o->householder_mode = 1;
   o->use_graph = 1;
@@ -641,7 +641,8 @@ lrei_status lrei_create(lrei_ctx **out, int hip_device, void *hip_stream, const 
     delete ctx;
     return LREI_E_INVALID;
   }
-  if (!(ctx->opt.eig_tol > 0) || ctx->opt.eig_max_sweeps < 1) {
+  if (!(ctx->opt.eig_tol > 0) || ctx->opt.eig_max_sweeps < 1 ||
+      (ctx->opt.warm != LREI_WARM_PLAIN && ctx->opt.warm != LREI_WARM_ANALYTIC)) {
     delete ctx;
     return LREI_E_INVALID;
   }
@@ -954,8 +955,9 @@ lrei_status lrei_step(lrei_ctx *ctx, int model, int scheme, double dt, double ka
   ctx->steps_done += n_steps;
   ctx->stats.steps_done = ctx->steps_done;
   ctx->stats.eigensolves += (int64_t)h[11];
-  ctx->stats.jacobi_sweeps += (int64_t)h[10];
-  ctx->stats.max_sweeps_one_solve = std::max(ctx->stats.max_sweeps_one_solve, (int32_t)h[12]);
+  ctx->stats.warm_accepted += (int64_t)h[9];
+  ctx->stats.warm_rejected += (int64_t)h[31];
+  ctx->stats.warm_iterations += (int64_t)h[12];
   ctx->stats.dropped_directions = (int32_t)h[2];
   ctx->stats.min_pivot_ratio = h[3];
   ctx->stats.ortho_error = h[4];

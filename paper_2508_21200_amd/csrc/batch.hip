@@ -412,6 +412,8 @@ lrei_status lrei_batch_create(lrei_batch **out, int hip_device, void *hip_stream
   if (opt) o = *opt;
   if (o.precision != LREI_FP64 && o.precision != LREI_MIXED) return cfail(LREI_E_INVALID, "unknown precision");
   if (!(o.eig_tol > 0) || o.eig_max_sweeps < 1) return cfail(LREI_E_INVALID, "bad eigensolver options");
+  if (o.warm != LREI_WARM_PLAIN && o.warm != LREI_WARM_ANALYTIC)
+    return cfail(LREI_E_INVALID, "warm must be LREI_WARM_PLAIN or LREI_WARM_ANALYTIC");
   std::vector<TermTable> tabs(n_traj);
   for (int q = 0; q < n_traj; ++q) {
     std::string e;

@@ -132,15 +132,25 @@ __device__ void zgemm(double2 *C, int ldc, const double2 *A, int lda, bool ah, c
     const int ti = t / nt, tj = t % nt;
     const int row = ti * 16 + li, col = tj * 16 + li;
     d4v_g cre = {0, 0, 0, 0}, cim = {0, 0, 0, 0};
-    for (int kk = 0; kk < K; kk += 4) {
-      const int k = kk + lk;
-      double2 a = make_double2(0, 0), b = make_double2(0, 0);
-      if (k < K && row < M) a = ah ? cconj(A[k * lda + row]) : A[row * lda + k];
-      if (k < K && col < N) b = B[k * ldb + col];
-      cre = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, cre, 0, 0, 0);
-      cre = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, cre, 0, 0, 0);
-      cim = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, cim, 0, 0, 0);
-      cim = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, cim, 0, 0, 0);
+    // four k-steps of operands are loaded before their products, so that the
+    // loads (global memory here, mostly L2 hits) overlap
+    for (int kk = 0; kk < K; kk += 16) {
+      double2 a[4], b[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int k = kk + 4 * q + lk;
+        a[q] = make_double2(0, 0);
+        b[q] = make_double2(0, 0);
+        if (k < K && row < M) a[q] = ah ? cconj(A[k * lda + row]) : A[row * lda + k];
+        if (k < K && col < N) b[q] = B[k * ldb + col];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        cre = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q].x, b[q].x, cre, 0, 0, 0);
+        cre = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[q].y, b[q].y, cre, 0, 0, 0);
+        cim = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q].x, b[q].y, cim, 0, 0, 0);
+        cim = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q].y, b[q].x, cim, 0, 0, 0);
+      }
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -613,6 +623,241 @@ __device__ void eig_top(double2 *A, int m, int r, double2 *u, int ldu, int rows_
     }
   }
   tlap(3);
+}
+
+// ----- top-r eigenvectors by subspace iteration from a predicted basis -------
+//
+// The r largest eigenvalues of a stage matrix stay close to Lambda_0 while the
+// rest of its spectrum is small (the tangent part of f vanishes on the
+// complement of the support, so that part is second order in the step; for
+// the later stages of a step it is smaller still).  The span of the r
+// eigenvectors is then reached by subspace iteration X <- orth(K X D^-1) from
+// the stage's input basis in a few iterations: the error shrinks by
+// max|rest| / lambda_r per iteration.  Convergence is judged by the subspace
+// residual Res = K X - X G, G = X* K X.  The result is kept only with a
+// certificate that no other eigenvalue of K reaches the r found: the rest of
+// the spectrum lies within T + |Res| of zero, T^2 = |K|_F^2 - |G|_F^2 -
+// 2 |Res|_F^2 (the squared Frobenius norm of the compression of K to the
+// complement of X), and the r eigenvalues near G's lie above a Gershgorin
+// lower bound of G minus |Res|.  The eigenvectors then come from the r x r
+// eigenproblem of G.  Otherwise (slow contraction, a failed
+// orthonormalisation, no certificate) the caller runs the direct solver; K is
+// left intact for it.
+
+__device__ inline double2 kget(const double2 *K, int i, int j, int m) {
+  return i >= j ? K[pl(i, j, m)] : cconj(K[pl(j, i, m)]);
+}
+
+// Sum over the workgroup of one value per thread, fixed order; every thread
+// gets the result.
+__device__ double block_sum(double v, double *red) {
+  v = sum64(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double t = 0;
+  for (int w = 0; w < NW; ++w) t += red[w];
+  return t;
+}
+
+// Y (m x r, ld r) = K X for the packed Hermitian K; one 16 x 16 MFMA tile per
+// wave.  Ends with a barrier.
+__device__ void hemm_packed(double2 *Y, const double2 *K, int m, const double2 *X, int r) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int mt = (m + 15) / 16, nt = (r + 15) / 16;
+  for (int t = wave; t < mt * nt; t += NW) {
+    const int ti = t / nt, tj = t % nt;
+    const int row = ti * 16 + li, col = tj * 16 + li;
+    d4v_g cre = {0, 0, 0, 0}, cim = {0, 0, 0, 0};
+    for (int kk = 0; kk < m; kk += 4) {
+      const int k = kk + lk;
+      double2 a = make_double2(0, 0), b = make_double2(0, 0);
+      if (k < m && row < m) a = kget(K, row, k, m);
+      if (k < m && col < r) b = X[k * r + col];
+      cre = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, cre, 0, 0, 0);
+      cre = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, cre, 0, 0, 0);
+      cim = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, cim, 0, 0, 0);
+      cim = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, cim, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = ti * 16 + 4 * v + lk, j = tj * 16 + li;
+      if (i < m && j < r) Y[i * r + j] = make_double2(cre[v], cim[v]);
+    }
+  }
+  __syncthreads();
+}
+
+// Per-thread partial of |Y - X G|_F^2 (X, Y: m x r; G: r x r; all ld r),
+// formed tile by tile in MFMA registers.
+__device__ double resid_part(const double2 *Y, const double2 *X, const double2 *G, int m, int r) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int mt = (m + 15) / 16, nt = (r + 15) / 16;
+  double acc = 0;
+  for (int t = wave; t < mt * nt; t += NW) {
+    const int ti = t / nt, tj = t % nt;
+    const int row = ti * 16 + li, col = tj * 16 + li;
+    d4v_g cre = {0, 0, 0, 0}, cim = {0, 0, 0, 0};
+    for (int kk = 0; kk < r; kk += 4) {
+      const int k = kk + lk;
+      double2 a = make_double2(0, 0), b = make_double2(0, 0);
+      if (k < r && row < m) a = X[row * r + k];
+      if (k < r && col < r) b = G[k * r + col];
+      cre = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, cre, 0, 0, 0);
+      cre = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, cre, 0, 0, 0);
+      cim = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, cim, 0, 0, 0);
+      cim = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, cim, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = ti * 16 + 4 * v + lk, j = tj * 16 + li;
+      if (i < m && j < r) {
+        const double2 y = Y[i * r + j];
+        const double dr = y.x - cre[v], di = y.y - cim[v];
+        acc += dr * dr + di * di;
+      }
+    }
+  }
+  return acc;
+}
+
+// X (m x r) <- X R^{-1} with X* X = R* R (Cholesky QR); C: r x r scratch.
+// Returns false (workgroup-uniform) if X* X is not numerically positive definite.
+__device__ bool chol_qr(double2 *X, int m, int r, double2 *C, int &bad) {
+  zgemm(C, r, X, r, true, X, r, r, r, m);  // C = X* X (ends with a barrier)
+  if (threadIdx.x < 64) {  // upper Cholesky factor in place, lanes over columns
+    const int lane = threadIdx.x;
+    int fail = 0;
+    for (int k = 0; k < r; ++k) {
+      const double piv = C[k * r + k].x;
+      if (!(piv > 1e-280)) fail = 1;
+      const double rkk = fail ? 1.0 : sqrt(piv);
+      for (int j = k + 1 + lane; j < r; j += 64) C[k * r + j] = cscale(1.0 / rkk, C[k * r + j]);
+      __builtin_amdgcn_wave_barrier();
+      for (int j = k + 1 + lane; j < r; j += 64)
+        for (int i = k + 1; i <= j; ++i) C[i * r + j] = csub(C[i * r + j], cmulc(C[k * r + i], C[k * r + j]));
+      __builtin_amdgcn_wave_barrier();
+      if (lane == 0) C[k * r + k] = make_double2(rkk, 0.0);
+      __builtin_amdgcn_wave_barrier();
+    }
+    if (lane == 0) bad = fail;
+  }
+  __syncthreads();
+  if (bad) return false;
+  // rows of X times R^{-1}, in place: x_c = (y_c - sum_{k<c} x_k R_kc) / R_cc
+  for (int i = threadIdx.x; i < m; i += NT) {
+    double2 *x = X + i * r;
+    for (int c = 0; c < r; ++c) {
+      double2 v = x[c];
+      for (int k = 0; k < c; ++k) v = csub(v, cmul(x[k], C[k * r + c]));
+      x[c] = cscale(1.0 / C[c * r + c].x, v);
+    }
+  }
+  __syncthreads();
+  return true;
+}
+
+// Words (double2) of arena the subspace iteration needs beyond K, and whether
+// the arena holds them and the small eigenproblem (after C, or over K).
+__device__ inline int warm_need(int m, int r) { return 2 * m * r + 2 * r * r; }
+__device__ inline int warm_small(int r) { return r * (r + 1) / 2 + r * r + 2 * r * (r <= 16 ? 16 : 32); }
+__device__ inline bool warm_fits(int m, int r, int arena_elems) {
+  const int npl = m * (m + 1) / 2;
+  return npl + warm_need(m, r) <= arena_elems &&
+         (npl + warm_need(m, r) + warm_small(r) <= arena_elems || npl >= warm_small(r));
+}
+
+// u (rows_out x r, ld ldu, global) <- eigenvectors of the r largest eigenvalues
+// of the Hermitian K (m x m, packed lower, in the LDS arena at K), descending,
+// or false.  S: m x r start with orthonormal columns (ld lds_in).  The arena
+// must hold K (npl words), then X, Y (m x r) and G, C (r x r); after the
+// certificate the small eigenproblem's scratch goes after C if it fits there,
+// else over K.  iters: iterations run.
+__device__ bool warm_top(double2 *K, int m, int r, const double2 *S, int lds_in, double2 *u, int ldu,
+                         int rows_out, double2 *arena, int arena_elems, int maxit, TriShared &ts, int &iters) {
+  __shared__ double red[NW];
+  __shared__ int s_bad;
+  const int npl = m * (m + 1) / 2;
+  double2 *X = K + npl, *Y = X + m * r, *G = Y + m * r, *C = G + r * r;
+  for (int e = threadIdx.x; e < m * r; e += NT) X[e] = S[(e / r) * lds_in + e % r];
+  double kp = 0;
+  for (int e = threadIdx.x; e < npl; e += NT) kp += cabs2(K[e]);
+  double kd = 0;
+  for (int i = threadIdx.x; i < m; i += NT) kd += cabs2(K[pl(i, i, m)]);
+  const double kn2 = 2.0 * block_sum(kp, red) - block_sum(kd, red);  // ends with a barrier: X is visible
+  double prev = 0, res2 = 0, g2 = 0;
+  bool conv = false;
+  int it = 0;
+  for (; it < maxit; ++it) {
+    hemm_packed(Y, K, m, X, r);                  // Y = K X
+    zgemm(C, r, X, r, true, Y, r, r, r, m);      // C = X* Y
+    double gp = 0;
+    for (int e = threadIdx.x; e < r * r; e += NT) {  // G = Hermitian part
+      const int a = e / r, b = e % r;
+      const double2 x1 = C[a * r + b], x2 = C[b * r + a];
+      const double2 g = make_double2(0.5 * (x1.x + x2.x), 0.5 * (x1.y - x2.y));
+      G[e] = g;
+      gp += cabs2(g);
+    }
+    g2 = block_sum(gp, red);
+    res2 = block_sum(resid_part(Y, X, G, m, r), red);
+    // converged: |Res| <= 1e-14 |G|, or stalled at rounding level below 1e-12 |G|
+    conv = res2 <= 1e-28 * g2 || (it > 0 && res2 <= 1e-24 * g2 && res2 >= 0.25 * prev);
+    if (conv) break;
+    // give up early when the contraction measured from two residuals leaves
+    // too many iterations
+    if (it >= 1) {
+      const double q = sqrt(res2 / prev);
+      const double need = q < 1.0 ? log(sqrt(1e-28 * g2 / res2)) / log(q) : 1e30;
+      if (!(need <= (double)(maxit - it - 1))) {
+        iters = it + 1;
+        return false;
+      }
+    }
+    prev = res2;
+    // X <- orth(Y diag(1 / G_aa)): the scaling keeps the columns near unit length
+    for (int e = threadIdx.x; e < m * r; e += NT) {
+      const double d = G[(e % r) * (r + 1)].x;
+      X[e] = cscale(fabs(d) > 1e-280 ? 1.0 / d : 1.0, Y[e]);
+    }
+    __syncthreads();
+    if (!chol_qr(X, m, r, C, s_bad)) {
+      iters = it + 1;
+      return false;
+    }
+  }
+  iters = it + (conv ? 1 : 0);
+  if (!conv) return false;
+  // certificate (K still intact for the direct solver if it fails)
+  {
+    const double T = sqrt(fmax(kn2 - g2 - 2.0 * res2, 0.0)), res = sqrt(res2);
+    double lb = 1e300;
+    for (int a = 0; a < r; ++a) {
+      double rad = 0;
+      for (int b = 0; b < r; ++b)
+        if (b != a) rad += sqrt(cabs2(G[a * r + b]));
+      lb = fmin(lb, G[a * (r + 1)].x - rad);
+    }
+    if (!(lb - res > T + res + 1e-13 * sqrt(kn2))) return false;
+  }
+  // Ritz vectors: G = Z diag(theta) Z*, theta descending
+  double2 *Gp = (npl + warm_need(m, r) + warm_small(r) <= arena_elems) ? C + r * r : K;
+  double2 *Z = Gp + r * (r + 1) / 2;
+  double *scr = reinterpret_cast<double *>(Z + r * r);
+  for (int e = threadIdx.x; e < r * r; e += NT) {
+    const int i = e / r, j = e % r;
+    if (j <= i) Gp[pl(i, j, r)] = G[e];
+  }
+  __syncthreads();
+  eig_top(Gp, r, r, Z, r, r, scr, true, ts);
+  __syncthreads();
+  zgemm(u, ldu, X, r, false, Z, r, m, r, r);  // u = X Z
+  for (int e = threadIdx.x; e < (rows_out - m) * r; e += NT) u[(m + e / r) * ldu + e % r] = make_double2(0, 0);
+  __syncthreads();
+  return true;
 }
 
 // ----- pieces shared by the RK and AB projected-step kernels -------------------
@@ -1286,7 +1531,18 @@ __device__ __forceinline__ void small_rk_body(const SmallRkParams &p, const Smal
       if (threadIdx.x == 0 && stats[28] < 0 && fk) stats[28] = 10 * j + 4;
     }
     double2 *unext = last ? ws.Cfin /* temporary */ : ws.stage + (3 * (j + 1) + 0) * D * r;
-    eig_top(K, m, r, unext, r, D, scr, jl, sh.ts);
+    bool solved = false;
+    if (p.warm == LREI_WARM_ANALYTIC && jl && K == s_arena && warm_fits(m, r, arena)) {
+      // subspace iteration from the stage's input basis u, in the LDS arena
+      // after K (over the direct solver's scratch, which it rebuilds if it runs)
+      int its = 0;
+      solved = warm_top(K, m, r, u, r, unext, r, D, s_arena, arena, 10, sh.ts, its);
+      if (threadIdx.x == 0) {
+        stats[solved ? 9 : 31] += 1;
+        stats[12] += its;
+      }
+    }
+    if (!solved) eig_top(K, m, r, unext, r, D, scr, jl, sh.ts);
     {
       const int fe = any_nonfinite(unext, D * r);
       if (threadIdx.x == 0 && stats[28] < 0 && fe) stats[28] = 10 * j + 5;

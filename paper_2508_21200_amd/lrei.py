@@ -32,15 +32,15 @@ class lrei_options(ctypes.Structure):
 
 class lrei_stats(ctypes.Structure):
     _fields_ = [("steps_done", ctypes.c_int64), ("eigensolves", ctypes.c_int64),
-                ("jacobi_sweeps", ctypes.c_int64), ("max_sweeps_one_solve", ctypes.c_int32),
-                ("dropped_directions", ctypes.c_int32), ("min_pivot_ratio", ctypes.c_double),
+                ("warm_accepted", ctypes.c_int64), ("warm_rejected", ctypes.c_int64),
+                ("warm_iterations", ctypes.c_int64), ("dropped_directions", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("min_pivot_ratio", ctypes.c_double),
                 ("ortho_error", ctypes.c_double), ("energy", ctypes.c_double),
-                ("last_step_ms", ctypes.c_double), ("warm_accepted", ctypes.c_int64),
-                ("warm_rejected", ctypes.c_int64), ("phase_ms", ctypes.c_double * 8),
+                ("last_step_ms", ctypes.c_double), ("phase_ms", ctypes.c_double * 8),
                 ("eig_phase_ms", ctypes.c_double * 6)]
 
     def as_dict(self):
-        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
         d["phase_ms"] = list(self.phase_ms)
         d["eig_phase_ms"] = list(self.eig_phase_ms)
         return d
@@ -136,7 +136,7 @@ class Context:
     """One LREI context (one trajectory) on a HIP device."""
 
     def __init__(self, device=0, stream=None, precision="fp64", eig_tol=1e-15, eig_max_sweeps=40,
-                 warm="plain", householder_mode=1, use_graph=True, autotune_cache=None):
+                 warm="analytic", householder_mode=1, use_graph=True, autotune_cache=None):
         self.lib = load()
         opt = lrei_options()
         self.lib.lrei_default_options(ctypes.byref(opt))
@@ -264,13 +264,14 @@ class Batch:
     """
 
     def __init__(self, trajs, device=0, stream=None, precision="fp64", use_graph=True, hbar=1.0,
-                 householder_mode=1):
+                 householder_mode=1, warm="analytic"):
         self.lib = load()
         opt = lrei_options()
         self.lib.lrei_default_options(ctypes.byref(opt))
         opt.precision = PRECISIONS[precision]
         opt.use_graph = int(bool(use_graph))
         opt.householder_mode = householder_mode
+        opt.warm = WARM[warm]
         descs = (lrei_traj_desc * len(trajs))()
         keep = []
         self.shapes = []

@@ -400,3 +400,65 @@ def test_rk4_large_rank(r, hmode):
     err = rel_fro_error(Vg, lam, Vo, lam)
     print(f"r={r} hmode={hmode}: {err:.3e}")
     assert err < 1e-11
+
+
+@pytest.mark.parametrize("case", ["chain_n10_r6", "lattice_n12_r16", "chain_n9_r20", "tiny_n4_r4"])
+def test_warm_start_matches_direct_solve(case):
+    """Stage eigensolves by subspace iteration from the predicted basis (the
+    default) against the direct tridiagonal solver: same rho to rounding, and
+    every eigensolve accounted for as accepted or fallen back."""
+    if case == "chain_n10_r6":
+        cfg = make_config(2, n=10, r=6)
+    elif case == "lattice_n12_r16":
+        cfg = make_config(3, n=12, r=16)
+    elif case == "chain_n9_r20":
+        cfg = make_config(2, n=9, r=20)
+    else:
+        cfg = make_config(2, n=4, r=4)
+    out, st = {}, {}
+    for warm in ("plain", "analytic"):
+        ctx = _ctx(warm=warm)
+        ctx.set_hamiltonian(cfg["n"], cfg["bonds"], cfg["J"], cfg["h"])
+        ctx.set_rho(cfg["lam"], cfg["V"])
+        ctx.step(cfg["model"], "RK4", 0.01, cfg["kappa"], 5)
+        out[warm] = ctx.get_rho()[1]
+        st[warm] = ctx.stats()
+        ctx.close()
+    err = rel_fro_error(out["analytic"], cfg["lam"], out["plain"], cfg["lam"])
+    s = st["analytic"]
+    print(f"{case}: warm vs direct {err:.3e}; accepted {s['warm_accepted']} rejected {s['warm_rejected']} "
+          f"iterations {s['warm_iterations']} of {s['eigensolves']} eigensolves")
+    assert err < 1e-12
+    # stages whose workspace does not fit the on-chip arena go straight to the direct solver
+    assert s["warm_accepted"] + s["warm_rejected"] <= s["eigensolves"] == 20
+    assert st["plain"]["warm_accepted"] == st["plain"]["warm_rejected"] == 0
+    if case != "tiny_n4_r4":
+        assert s["warm_accepted"] > 0
+
+
+def test_warm_start_falls_back_on_large_steps():
+    """A step far beyond the usual size: the rest of each stage spectrum is no
+    longer small, so subspace iteration may not converge or certify; whatever
+    path each eigensolve takes, the result must match the oracle."""
+    rng = np.random.default_rng(41)
+    n, r = 7, 4
+    bonds, J, h = _random_model(n, rng)
+    V = haar_factor(2 ** n, r, rng)
+    lam = dirichlet_spectrum(r, rng)
+    ctx = _ctx()
+    ctx.set_hamiltonian(n, bonds, J, h)
+    ctx.set_rho(lam, V)
+    ctx.step("qLLG", "RK4", 0.4, 0.3, 2)
+    s = ctx.stats()
+    H = Hamiltonian(n, bonds, J, h)
+    Vo = oracle_run(H, V, lam, "qLLG", 0.3, 0.4, 2, "RK4")
+    err = rel_fro_error(ctx.get_rho()[1], lam, Vo, lam)
+    print(f"large step: {err:.3e}; accepted {s['warm_accepted']} rejected {s['warm_rejected']}")
+    assert err < 1e-10
+    assert s["warm_accepted"] + s["warm_rejected"] <= s["eigensolves"]
+
+
+def test_learned_start_rotation_is_rejected():
+    from paper_2508_21200_amd import LreiError
+    with pytest.raises(LreiError):
+        _ctx(warm="learned")
