@@ -969,23 +969,41 @@ __device__ void lowdin(double2 *u, int m, int r, double2 *S, double2 *Lw, double
   }
   __syncthreads();
   if (!(sh.dev > 1e-14)) return;
-  double2 *A = arena, *E = arena + rr;
-  for (int e = threadIdx.x; e < rr; e += NT) {
-    const int a = e / r, b = e % r;
-    if (a <= b) {
+  if (sh.dev <= 1e-6) {
+    // S = I + E with |E|_2 <= r * 1e-6: S^{-1/2} = I - E/2 + 3/8 E^2 - 5/16 E^3,
+    // the next term below 1e-19
+    double2 *E = arena, *E2 = arena + rr, *E3 = arena + 2 * rr;
+    for (int e = threadIdx.x; e < rr; e += NT) {
+      const int a = e / r, b = e % r;
       const double2 x1 = S[a * r + b], x2 = S[b * r + a];
-      A[pk(a, b)] = a == b ? make_double2(x1.x, 0.0) : make_double2(0.5 * (x1.x + x2.x), 0.5 * (x1.y - x2.y));
+      E[e] = a == b ? make_double2(x1.x - 1.0, 0.0) : make_double2(0.5 * (x1.x + x2.x), 0.5 * (x1.y - x2.y));
     }
-  }
-  __syncthreads();
-  jacobi(A, E, r, 1e-16, 60, sh.js, true);
-  __syncthreads();
-  for (int e = threadIdx.x; e < rr; e += NT) {
-    const int a = e / r, b = e % r;
-    double2 acc = make_double2(0, 0);
-    for (int k = 0; k < r; ++k)
-      acc = cadd(acc, cscale(1.0 / sqrt(A[pk(k, k)].x), cmul(E[a * r + k], cconj(E[b * r + k]))));
-    Lw[e] = acc;
+    __syncthreads();
+    zgemm(E2, r, E, r, false, E, r, r, r, r);
+    zgemm(E3, r, E2, r, false, E, r, r, r, r);
+    for (int e = threadIdx.x; e < rr; e += NT) {
+      const double2 t = cadd(cscale(-0.5, E[e]), cadd(cscale(0.375, E2[e]), cscale(-0.3125, E3[e])));
+      Lw[e] = (e / r == e % r) ? make_double2(1.0 + t.x, t.y) : t;
+    }
+  } else {
+    double2 *A = arena, *E = arena + rr;
+    for (int e = threadIdx.x; e < rr; e += NT) {
+      const int a = e / r, b = e % r;
+      if (a <= b) {
+        const double2 x1 = S[a * r + b], x2 = S[b * r + a];
+        A[pk(a, b)] = a == b ? make_double2(x1.x, 0.0) : make_double2(0.5 * (x1.x + x2.x), 0.5 * (x1.y - x2.y));
+      }
+    }
+    __syncthreads();
+    jacobi(A, E, r, 1e-16, 60, sh.js, true);
+    __syncthreads();
+    for (int e = threadIdx.x; e < rr; e += NT) {
+      const int a = e / r, b = e % r;
+      double2 acc = make_double2(0, 0);
+      for (int k = 0; k < r; ++k)
+        acc = cadd(acc, cscale(1.0 / sqrt(A[pk(k, k)].x), cmul(E[a * r + k], cconj(E[b * r + k]))));
+      Lw[e] = acc;
+    }
   }
   for (int e = threadIdx.x; e < m * r; e += NT) T[e] = u[e];
   __syncthreads();
