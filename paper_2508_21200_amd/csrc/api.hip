@@ -51,6 +51,7 @@ struct lrei_ctx {
   int hv_w = 0;                   // window bits (0: one sweep)
   std::vector<HvSweep> sweeps;
   DevBuf acc;                     // partial sums between sweeps
+  DevBuf sched;                   // H.V tile-scheduling counters (16 ints, zero between launches)
 
   // state
   bool have_rho = false;
@@ -162,6 +163,8 @@ void hv_args(lrei_ctx *ctx, ChebArgs &a) {
   a.n_off = ctx->dt.n_off;
   a.cplx = ctx->dt.cplx;
   a.epl = ctx->epl;
+  a.sched = (int *)ctx->sched.p;
+  a.partial_cap = kMaxHvGrid;  // ctx->partials holds this many slots
 }
 
 // One Chebyshev pass with fused Grams, reduced into meas.  With a sweep plan
@@ -169,8 +172,8 @@ void hv_args(lrei_ctx *ctx, ChebArgs &a) {
 // sweep: the first adds the diagonal, each writes its partial sum to ctx->acc,
 // the last adds its terms to that sum and forms the Chebyshev combination and
 // the Grams.
-void hv_launches(lrei_ctx *ctx, int r, int grid, int mode, const void *prev, const void *cur, void *next,
-                 double2 *partials, bool sweeps) {
+int hv_launches(lrei_ctx *ctx, int r, int grid, int mode, const void *prev, const void *cur, void *next,
+                double2 *partials, bool sweeps, int partial_cap = kMaxHvGrid) {
   ChebArgs a{};
   a.Pprev = prev;
   a.Pcur = cur;
@@ -184,9 +187,11 @@ void hv_launches(lrei_ctx *ctx, int r, int grid, int mode, const void *prev, con
   a.mode = mode;
   a.partials = partials;
   a.grid = grid;
+  a.partial_cap = partial_cap;
   const size_t ns = ctx->sweeps.size();
+  int slots = 0;
   if (!sweeps || ns <= 1) {
-    launch_cheb(ctx->fp32, a, ctx->stream);
+    slots = launch_cheb(ctx->fp32, a, ctx->stream);
   } else {
     for (size_t i = 0; i < ns; ++i) {
       const auto &sw = ctx->sweeps[i];
@@ -201,15 +206,16 @@ void hv_launches(lrei_ctx *ctx, int r, int grid, int mode, const void *prev, con
       b.n_fix = (int)sw.fix.size();
       for (size_t q = 0; q < sw.win.size(); ++q) b.win_pos[q] = (unsigned char)sw.win[q];
       for (size_t q = 0; q < sw.fix.size(); ++q) b.fix_pos[q] = (unsigned char)sw.fix[q];
-      launch_cheb(ctx->fp32, b, ctx->stream);
+      slots = launch_cheb(ctx->fp32, b, ctx->stream);
     }
   }
+  return slots;  // Gram partial slots written by the (last) launch
 }
 
 void cheb_pass_into(lrei_ctx *ctx, int r, int grid, int mode, const void *prev, const void *cur, void *next,
-                    double2 *partials, double2 *meas, bool sweeps = false) {
-  hv_launches(ctx, r, grid, mode, prev, cur, next, partials, sweeps);
-  if (mode != 2) launch_reduce(partials, grid, (mode == 0 ? 3 : 2) * r * r, meas, ctx->stream);
+                    double2 *partials, double2 *meas, bool sweeps = false, int partial_cap = kMaxHvGrid) {
+  const int slots = hv_launches(ctx, r, grid, mode, prev, cur, next, partials, sweeps, partial_cap);
+  if (mode != 2 && slots > 0) launch_reduce(partials, slots, (mode == 0 ? 3 : 2) * r * r, meas, ctx->stream);
 }
 
 void cheb_pass(lrei_ctx *ctx, int mode, const void *prev, const void *cur, void *next, int slot) {
@@ -665,6 +671,7 @@ lrei_status lrei_create(lrei_ctx **out, int hip_device, void *hip_stream, const 
             hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming) == hipSuccess &&
             hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming) == hipSuccess;
   for (auto &e : ctx->ev_pass) ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+  ok = ok && ctx->sched.ensure(16 * sizeof(int)) && hipMemset(ctx->sched.p, 0, 16 * sizeof(int)) == hipSuccess;
   if (!ok) {
     lrei_destroy(ctx);
     return LREI_E_DEVICE;
@@ -681,6 +688,7 @@ void lrei_destroy(lrei_ctx *ctx) {
   for (auto &b : ctx->blocks) b.release();
   ctx->save.release();
   ctx->acc.release();
+  ctx->sched.release();
   ctx->partials.release();
   ctx->ws_buf.release();
   ctx->stats_buf.release();
@@ -819,7 +827,7 @@ lrei_status lrei_set_rho(lrei_ctx *ctx, int r, const double *lambda, const void 
       return check_hip(ctx, e1, "upload V");
     }
   }
-  cheb_pass_into(ctx, r, grid, 0, nullptr, tv.p, tp.p, (double2 *)tpart.p, (double2 *)tmeas.p);
+  cheb_pass_into(ctx, r, grid, 0, nullptr, tv.p, tp.p, (double2 *)tpart.p, (double2 *)tmeas.p, false, grid);
   std::vector<double2> g(3 * r * r);
   hipError_t e2 = hipGetLastError();
   if (e2 == hipSuccess)
@@ -1225,17 +1233,18 @@ lrei_status lrei_profile_kernels(lrei_ctx *ctx, int model, int scheme, double dt
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   const int r = ctx->r;
+  int slots = ctx->hv_grid;  // Gram partial slots of the timed pass (set by its launch)
   auto timed = [&](int which) -> double {
     // one untimed launch, then `iters` timed ones
     for (int k = 0; k <= iters; ++k) {
       if (k == 1) (void)hipEventRecord(e0, ctx->stream);
       switch (which) {
         case 0:
-          hv_launches(ctx, r, ctx->hv_grid, 1, ctx->blocks[0].p, ctx->blocks[1].p, ctx->blocks[4].p,
-                      (double2 *)ctx->partials.p, true);
+          slots = hv_launches(ctx, r, ctx->hv_grid, 1, ctx->blocks[0].p, ctx->blocks[1].p, ctx->blocks[4].p,
+                              (double2 *)ctx->partials.p, true);
           break;
         case 1:
-          launch_reduce((const double2 *)ctx->partials.p, ctx->hv_grid, 2 * r * r,
+          launch_reduce((const double2 *)ctx->partials.p, slots, 2 * r * r,
                         ctx->ws.work, ctx->stream);  // scratch target: the step's Grams stay intact
           break;
         case 2:

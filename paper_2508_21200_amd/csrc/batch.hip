@@ -117,7 +117,7 @@ struct lrei_batch {
   // reduction of pass j, projected step, combination by padded width
   struct ChebGroup {
     int epl = 1;
-    bool cplx = false, big = false;
+    bool cplx = false, big = false, dyn = false;
     size_t lds = 0;
     LaunchTables t;
   };
@@ -195,7 +195,7 @@ lrei_status alloc_traj(lrei_batch *b, lrei_batch::Traj &t, int idx) {
 // Tables of the Chebyshev passes and their reductions (independent of the scheme).
 lrei_status build_pass_tables(lrei_batch *b) {
   for (int j = 0; j < kMaxStages; ++j) {
-    std::map<std::tuple<int, int>, std::vector<int>> cls;  // (epl, big) -> trajectories
+    std::map<std::tuple<int, int, int>, std::vector<int>> cls;  // (epl, big, dynamic) -> trajectories
     std::vector<ChebArgs> args(b->tr.size());
     for (size_t q = 0; q < b->tr.size(); ++q) {
       auto &t = b->tr[q];
@@ -216,9 +216,13 @@ lrei_status build_pass_tables(lrei_batch *b) {
       a.mode = j == 0 ? 0 : 1;
       a.partials = (double2 *)t.partials.p;
       a.grid = t.grid;
+      // static tile schedule: a batched launch holds many workgroups per CU
+      // slot, which the hardware dispatcher balances by itself
+      a.sched = nullptr;
+      a.partial_cap = t.grid;
       if (!prepare_cheb(b->fp32, a)) return b->fail(LREI_E_INVALID, "unsupported rank for the H.V pass");
       args[q] = a;
-      cls[{a.epl, a.r > 16 ? 1 : 0}].push_back((int)q);
+      cls[{a.epl, a.r > 16 ? 1 : 0, a.chunks > 0 ? 1 : 0}].push_back((int)q);
     }
     for (auto &g : b->cheb[j]) g.t.release();
     b->cheb[j].clear();
@@ -226,22 +230,25 @@ lrei_status build_pass_tables(lrei_batch *b) {
       lrei_batch::ChebGroup g;
       g.epl = std::get<0>(kv.first);
       g.big = std::get<1>(kv.first) != 0;
+      g.dyn = std::get<2>(kv.first) != 0;
       std::vector<ChebArgs> recs;
       std::vector<int> wgs;
       for (int q : kv.second) {
         recs.push_back(args[q]);
         wgs.push_back(args[q].grid);
         g.cplx = g.cplx || args[q].cplx;
-        g.lds = std::max(g.lds, cheb_lds_bytes(b->fp32, args[q].r));
+        g.lds = std::max(g.lds, cheb_launch_lds(b->fp32, args[q]));
       }
       if (!build_tables(recs, wgs, true, g.t)) return b->fail(LREI_E_NOMEM, "launch table upload failed");
       b->cheb[j].push_back(std::move(g));
     }
     std::vector<ReduceJob> rj;
     std::vector<int> lens;
-    for (auto &t : b->tr) {
+    for (size_t q = 0; q < b->tr.size(); ++q) {
+      auto &t = b->tr[q];
       const int rr = t.r * t.r;
-      rj.push_back(ReduceJob{(const double2 *)t.partials.p, t.grid, t.ws.meas + (size_t)j * 3 * rr});
+      const int slots = args[q].chunks > 0 ? args[q].chunks : args[q].grid;
+      rj.push_back(ReduceJob{(const double2 *)t.partials.p, slots, t.ws.meas + (size_t)j * 3 * rr});
       lens.push_back((j == 0 ? 3 : 2) * rr);
     }
     if (!build_tables(rj, lens, false, b->reduce[j])) return b->fail(LREI_E_NOMEM, "launch table upload failed");
@@ -322,7 +329,7 @@ lrei_status build_step_tables(lrei_batch *b, int scheme, double dt) {
 // Pass j of every trajectory: H.V with fused Grams, then the reduction into meas.
 void enqueue_pass(lrei_batch *b, int j, hipStream_t s) {
   for (auto &g : b->cheb[j])
-    launch_cheb_batch(b->fp32, g.epl, g.cplx, g.big, g.t.view(), g.t.total_wg, g.lds, s);
+    launch_cheb_batch(b->fp32, g.epl, g.cplx, g.big, g.dyn, g.t.view(), g.t.total_wg, g.lds, s);
   launch_reduce_batch(b->reduce[j].view(), b->reduce[j].total_wg, s);
 }
 
@@ -658,7 +665,7 @@ lrei_status lrei_batch_profile_kernels(lrei_batch *b, int scheme, double dt, int
   const int j = s > 1 ? 1 : 0;  // the recurrence-form pass where it exists
   ms[0] = timed([&] {
     for (auto &g : b->cheb[j])
-      launch_cheb_batch(b->fp32, g.epl, g.cplx, g.big, g.t.view(), g.t.total_wg, g.lds, b->stream);
+      launch_cheb_batch(b->fp32, g.epl, g.cplx, g.big, g.dyn, g.t.view(), g.t.total_wg, g.lds, b->stream);
   });
   ms[1] = timed([&] { launch_reduce_batch(b->reduce[j].view(), b->reduce[j].total_wg, b->stream); });
   ms[2] = timed([&] {

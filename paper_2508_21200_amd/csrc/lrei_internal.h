@@ -82,15 +82,23 @@ struct ChebArgs {
   int r;
   double alpha, shift;  // P_{j+1} = mul * alpha * (H - shift) P_j - [mode 1] P_{j-1}
   int mode;             // 0: first, 1: recurrence, 2: plain Y = H X (no Grams)
-  double2 *partials;    // [grid][3][r*r]
+  double2 *partials;    // Gram partial sums, entry-major [entry][slot]
   int grid;
+  // dynamic tile schedule: counters (16 ints, zero between launches; nullptr:
+  // static schedule) and the number of partial-sum slots the buffer holds
+  int *sched;
+  int partial_cap;
+  int chunks;           // set by prepare_cheb: Gram partial slots used (0: one per workgroup)
 };
 
-bool launch_cheb(bool fp32, const ChebArgs &a, hipStream_t s);
+// Launches one H.V pass; returns the number of Gram partial slots written
+// (the reduction's count), 0 if the shape is unsupported.
+int launch_cheb(bool fp32, const ChebArgs &a, hipStream_t s);
 // Fills the launcher-set fields of a (columns per lane, lanes, table pointers,
 // the default single window); false if the shape is unsupported.
 bool prepare_cheb(bool fp32, ChebArgs &a);
 size_t cheb_lds_bytes(bool fp32, int r);
+size_t cheb_launch_lds(bool fp32, const ChebArgs &a);  // dynamic LDS of a prepared pass
 
 // Launch tables of a batched kernel (many independent jobs in one launch):
 // workgroup w runs job wg_job[w] as that job's workgroup w - job_wg0[job].
@@ -102,8 +110,9 @@ struct BatchLaunch {
 };
 // Batched Chebyshev passes: every job is a ChebArgs prepared by prepare_cheb
 // with the same precision, columns per lane epl, complex flag and r > 16 flag.
-bool launch_cheb_batch(bool fp32, int epl, bool cplx, bool big, const BatchLaunch &b, int total_wg, size_t lds,
-                       hipStream_t s);
+bool launch_cheb_batch(bool fp32, int epl, bool cplx, bool big, bool dyn, const BatchLaunch &b, int total_wg,
+                       size_t lds, hipStream_t s);
+size_t cheb_lds_dyn_extra();  // LDS added by the dynamic schedule (Gram accumulators)
 // Basis combination out = [B_0 ... B_{nb-1}] C (nspace.hip).
 struct CombineArgs {
   const void *blocks[kMaxBlocks];

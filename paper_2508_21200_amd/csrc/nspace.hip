@@ -112,6 +112,41 @@ __device__ inline void gram_tile(const T *const *xre, const T *const *xim, const
   }
 }
 
+// As gram_tile with one work item per wave, the per-tile products added to the
+// FP64 accumulators in LDS (lacc[v * kThreads + thread], v < 8) instead of registers.
+template <typename T>
+__device__ inline void gram_tile_lds(const T *const *xre, const T *const *xim, const T *const *yre,
+                                     const T *const *yim, const GramPlan<T> &gp, int RP, double *lacc) {
+  using A4 = typename Acc4<T>::type;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int rows_per_split = kTile / gp.rs;
+  const int it = wave;
+  if (it >= gp.items) return;
+  int t = it;
+  const int split = t % gp.rs; t /= gp.rs;
+  const int tb = t % gp.ta; t /= gp.ta;
+  const int ta = t % gp.ta; t /= gp.ta;
+  const int g = t;
+  const T *Xr = xre[g], *Xi = xim[g], *Yr = yre[g], *Yi = yim[g];
+  const int a = ta * 16 + (lane & 15), b = tb * 16 + (lane & 15);
+  A4 cre = {0, 0, 0, 0}, cim = {0, 0, 0, 0};
+  const int row0 = split * rows_per_split;
+  for (int kk = 0; kk < rows_per_split; kk += 4) {
+    const int row = row0 + kk + (lane >> 4);
+    const T xr = Xr[row * RP + a], xi = Xi[row * RP + a];
+    const T yr = Yr[row * RP + b], yi = Yi[row * RP + b];
+    cre = mfma(xr, yr, cre);
+    cre = mfma(xi, yi, cre);
+    cim = mfma(xr, yi, cim);
+    cim = mfma(-xi, yr, cim);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    lacc[v * kThreads + threadIdx.x] += (double)cre[v];
+    lacc[(4 + v) * kThreads + threadIdx.x] += (double)cim[v];
+  }
+}
+
 // Writes the workgroup's Gram partial sums, entry-major: partials[e * grid + wg]
 // with e = g * r * r + a * r + b.  Row splits (held by different waves) are
 // summed through LDS in a fixed wave order, so the result is deterministic.
@@ -218,8 +253,9 @@ __device__ inline T pick4(int idx, T c0, T c1, T c2, T c3) {
 // E complex columns per lane, CPLX: some coefficient has an imaginary part,
 // MI: Gram work items per wave, WIN: row-bit window sweeps allowed.  wg is the
 // workgroup's index among the a.grid workgroups of this pass.
-template <typename T, int E, bool CPLX, int MI, bool WIN>
+template <typename T, int E, bool CPLX, int MI, bool WIN, bool DYN>
 __device__ __forceinline__ void cheb_body(const ChebArgs &a, int wg, unsigned char *smem) {
+  static_assert(!DYN || (MI == 1 && !WIN), "the dynamic schedule keeps one Gram item per wave in LDS");
   // row gathers in flight per lane: kept small so that four waves fit per SIMD
   constexpr int B = (sizeof(T) == 4 ? 16 : 8) / E > 1 ? (sizeof(T) == 4 ? 16 : 8) / E : 2;
   const int r = a.r;
@@ -287,10 +323,57 @@ __device__ __forceinline__ void cheb_body(const ChebArgs &a, int wg, unsigned ch
   const bool by_window = WIN && nwin >= 8 && (a.grid & 7) == 0;
   long long wi = by_window ? xcd : 0, lt = by_window ? slot : 0;
   uint32_t wbase = by_window ? deposit(wi, a.fix_pos, a.n_fix) : 0;
+  const long long num_tiles = (N + kTile - 1) / kTile;
+  // Dynamic schedule: the tiles of XCD slot x = wg % 8 (a contiguous eighth of
+  // the rows) form cpx chunks, chunk c holding tiles c, c + cpx, ... of the
+  // slot (so the chunks being worked on at one time cover consecutive tiles).
+  // The slot's workgroups take chunks from counter sched[x]: a workgroup on a
+  // CU shared with other work takes fewer, instead of holding up the pass.
+  // Gram partial sums are kept per chunk (accumulated in LDS), so the result
+  // does not depend on which workgroup took which chunk.  Each workgroup
+  // makes one failing take; the slot's last one to finish (counted in
+  // sched[8 + x]) resets both counters for the next launch.
+  const int cpx = DYN ? a.chunks >> 3 : 1;
+  const long long per = num_tiles >> 3, cs = DYN ? per / cpx : 0;
+  double *lacc = reinterpret_cast<double *>(smem + 4 * (size_t)plane * sizeof(T));
+  __shared__ int s_chunk;
+  int chunk = -1;
+  long long kc = cs;
+  if constexpr (DYN) {
+    for (int v = 0; v < 8; ++v) lacc[v * kThreads + threadIdx.x] = 0.0;
+  }
   for (long long k = 0;; ++k) {
     long long row0 = 0;
     uint32_t tbase = 0;
-    if (by_window) {
+    if constexpr (DYN) {
+      if (kc == cs) {
+        if (grams && chunk >= 0) {  // the finished chunk's partial sums
+          double av[1][8];
+#pragma unroll
+          for (int v = 0; v < 8; ++v) {
+            av[0][v] = lacc[v * kThreads + threadIdx.x];
+            lacc[v * kThreads + threadIdx.x] = 0.0;
+          }
+          gram_store<T, 1>(gp, av, r, a.partials, reinterpret_cast<double2 *>(planes), a.chunks, xcd * cpx + chunk);
+          __syncthreads();
+          for (int i = threadIdx.x; i < 4 * plane; i += kThreads) planes[i] = T(0);
+        }
+        if (threadIdx.x == 0) s_chunk = atomicAdd(&a.sched[xcd], 1);
+        __syncthreads();
+        chunk = s_chunk;
+        __syncthreads();
+        if (chunk >= cpx) {
+          if (threadIdx.x == 0 && atomicAdd(&a.sched[8 + xcd], 1) == g8 - 1) {
+            atomicExch(&a.sched[xcd], 0);
+            atomicExch(&a.sched[8 + xcd], 0);
+          }
+          break;
+        }
+        kc = 0;
+      }
+      row0 = ((long long)xcd * per + chunk + kc * cpx) * kTile;
+      ++kc;
+    } else if (by_window) {
       while (wi < nwin && lt >= tiles_per_win) {
         wi += 8;
         lt = slot;
@@ -300,7 +383,7 @@ __device__ __forceinline__ void cheb_body(const ChebArgs &a, int wg, unsigned ch
       tbase = wbase | deposit(lt * kTile, a.win_pos, nw);
       lt += g8;
     } else {
-      const long long tile = tile_of(k, (N + kTile - 1) / kTile, a.grid, wg);
+      const long long tile = tile_of(k, num_tiles, a.grid, wg);
       if (tile < 0) break;
       row0 = tile * kTile;
     }
@@ -386,33 +469,38 @@ __device__ __forceinline__ void cheb_body(const ChebArgs &a, int wg, unsigned ch
       __syncthreads();
       // rows beyond N keep the zeros written at start only for the first tile;
       // N is a power of two >= 2 so a partial tile is always the only tile.
-      gram_tile<T, MI>(xre, xim, yre, yim, gp, RP, acc);
+      if constexpr (DYN)
+        gram_tile_lds<T>(xre, xim, yre, yim, gp, RP, lacc);
+      else
+        gram_tile<T, MI>(xre, xim, yre, yim, gp, RP, acc);
       __syncthreads();
     }
   }
-  if (grams) {
-    __syncthreads();
-    gram_store<T, MI>(gp, acc, r, a.partials, reinterpret_cast<double2 *>(planes), a.grid, wg);
+  if constexpr (!DYN) {
+    if (grams) {
+      __syncthreads();
+      gram_store<T, MI>(gp, acc, r, a.partials, reinterpret_cast<double2 *>(planes), a.grid, wg);
+    }
   }
 }
 
-template <typename T, int E, bool CPLX, int MI>
+template <typename T, int E, bool CPLX, int MI, bool DYN>
 __global__ __launch_bounds__(kThreads) void k_cheb(ChebArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  cheb_body<T, E, CPLX, MI, true>(a, blockIdx.x, smem);
+  cheb_body<T, E, CPLX, MI, !DYN, DYN>(a, blockIdx.x, smem);
 }
 
 // Many independent passes in one launch (one per trajectory of a batch): the
 // workgroup's job and its index within that job come from the launch tables;
 // every job's workgroups start at a multiple of 8, so a workgroup keeps its
 // XCD slot within the job.
-template <typename T, int E, bool CPLX, int MI>
+template <typename T, int E, bool CPLX, int MI, bool DYN>
 __global__ __launch_bounds__(kThreads) void k_cheb_batch(BatchLaunch b) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int j = b.wg_job[blockIdx.x];
   if (j < 0) return;  // alignment padding
   const ChebArgs a = reinterpret_cast<const ChebArgs *>(b.jobs)[j];
-  cheb_body<T, E, CPLX, MI, false>(a, blockIdx.x - b.job_wg0[j], smem);
+  cheb_body<T, E, CPLX, MI, false, DYN>(a, blockIdx.x - b.job_wg0[j], smem);
 }
 
 // Diagonal of H per row: d(x) = sum_k w_k (1 - 2 (b_{i_k}(x) xor b_{j_k}(x))),
@@ -689,36 +777,48 @@ int cheb_elems_per_lane(bool fp32, int r) {
 
 size_t cheb_lds_bytes(bool fp32, int r) { return cheb_lds(fp32, r); }
 
-template <typename T, int E, bool C, int MI>
+size_t cheb_lds_dyn_extra() { return (size_t)8 * kThreads * sizeof(double); }
+
+template <typename T, int E, bool C, int MI, bool DYN>
 static void launch_one(const ChebArgs &a, size_t lds, hipStream_t s) {
   static bool attr = false;
   if (!attr) {
-    (void)hipFuncSetAttribute((const void *)k_cheb<T, E, C, MI>, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
-    attr = true;
-  }
-  hipLaunchKernelGGL((k_cheb<T, E, C, MI>), dim3(a.grid), dim3(kThreads), lds, s, a);
-}
-
-template <typename T, int E, bool C, int MI>
-static void launch_one_batch(const BatchLaunch &b, int total_wg, size_t lds, hipStream_t s) {
-  static bool attr = false;
-  if (!attr) {
-    (void)hipFuncSetAttribute((const void *)k_cheb_batch<T, E, C, MI>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute((const void *)k_cheb<T, E, C, MI, DYN>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               kMaxLds);
     attr = true;
   }
-  hipLaunchKernelGGL((k_cheb_batch<T, E, C, MI>), dim3(total_wg), dim3(kThreads), lds, s, b);
+  hipLaunchKernelGGL((k_cheb<T, E, C, MI, DYN>), dim3(a.grid), dim3(kThreads), lds, s, a);
 }
 
-// Dispatches on (precision, E, complex coefficients, Gram items per wave).
-// F is called as F.template operator()<T, E, C, MI>().
+template <typename T, int E, bool C, int MI, bool DYN>
+static void launch_one_batch(const BatchLaunch &b, int total_wg, size_t lds, hipStream_t s) {
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void *)k_cheb_batch<T, E, C, MI, DYN>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+    attr = true;
+  }
+  hipLaunchKernelGGL((k_cheb_batch<T, E, C, MI, DYN>), dim3(total_wg), dim3(kThreads), lds, s, b);
+}
+
+// Dispatches on (precision, E, complex coefficients, Gram items per wave,
+// schedule).  f is called as f.template operator()<T, E, C, MI, DYN>().  The
+// dynamic schedule exists for FP32 storage with one Gram item per wave.
 template <typename Fn>
-static bool dispatch_cheb(bool fp32, int E, bool cplx, bool big, Fn &&f) {
+static bool dispatch_cheb(bool fp32, int E, bool cplx, bool big, bool dyn, Fn &&f) {
+  if (dyn && (!fp32 || big)) return false;
   auto c = [&](auto tag_t, auto tag_e, auto tag_mi) {
     using T = typename decltype(tag_t)::type;
     constexpr int EE = decltype(tag_e)::value, MI = decltype(tag_mi)::value;
-    if (cplx) f.template operator()<T, EE, true, MI>();
-    else f.template operator()<T, EE, false, MI>();
+    if constexpr (std::is_same_v<T, float> && MI == 1) {
+      if (dyn) {
+        if (cplx) f.template operator()<T, EE, true, MI, true>();
+        else f.template operator()<T, EE, false, MI, true>();
+        return;
+      }
+    }
+    if (cplx) f.template operator()<T, EE, true, MI, false>();
+    else f.template operator()<T, EE, false, MI, false>();
   };
   struct F32 { using type = float; };
   struct F64 { using type = double; };
@@ -776,22 +876,41 @@ bool prepare_cheb(bool fp32, ChebArgs &a) {
   a.epl = E;
   a.terms = fp32 ? (const void *)a.terms32 : (const void *)a.terms64;
   a.diagv = fp32 ? (const void *)a.diag32 : (const void *)a.diag64;
+  // dynamic schedule with two chunks per workgroup where the partial buffer
+  // holds them (one per workgroup otherwise); single window, grid a multiple of 8
+  a.chunks = 0;
+  const long long tiles = (a.N + kTile - 1) / kTile;
+  const bool grams = a.mode != 2 && !a.acc_out;
+  const long long cap = grams ? (a.partial_cap > 0 ? a.partial_cap : a.grid) : (1LL << 40);
+  if (fp32 && !big && a.sched && a.n_fix == 0 && a.grid >= 8 && a.grid % 8 == 0) {
+    for (long long ch = 2LL * a.grid; ch >= a.grid; ch /= 2)
+      if (ch <= cap && tiles % ch == 0) {
+        a.chunks = (int)ch;
+        break;
+      }
+  }
   return true;
 }
 
-bool launch_cheb(bool fp32, const ChebArgs &a0, hipStream_t s) {
-  ChebArgs a = a0;
-  if (!prepare_cheb(fp32, a)) return false;
-  const size_t lds = cheb_lds(fp32, a.r);
-  return dispatch_cheb(fp32, a.epl, a.cplx != 0, a.r > 16, [&]<typename T, int E, bool C, int MI>() {
-    launch_one<T, E, C, MI>(a, lds, s);
-  });
+size_t cheb_launch_lds(bool fp32, const ChebArgs &a) {
+  return cheb_lds(fp32, a.r) + (a.chunks > 0 ? cheb_lds_dyn_extra() : 0);
 }
 
-bool launch_cheb_batch(bool fp32, int epl, bool cplx, bool big, const BatchLaunch &b, int total_wg, size_t lds,
-                       hipStream_t s) {
-  return dispatch_cheb(fp32, epl, cplx, big, [&]<typename T, int E, bool C, int MI>() {
-    launch_one_batch<T, E, C, MI>(b, total_wg, lds, s);
+int launch_cheb(bool fp32, const ChebArgs &a0, hipStream_t s) {
+  ChebArgs a = a0;
+  if (!prepare_cheb(fp32, a)) return 0;
+  const size_t lds = cheb_launch_lds(fp32, a);
+  const bool ok = dispatch_cheb(fp32, a.epl, a.cplx != 0, a.r > 16, a.chunks > 0,
+                                [&]<typename T, int E, bool C, int MI, bool DYN>() {
+                                  launch_one<T, E, C, MI, DYN>(a, lds, s);
+                                });
+  return ok ? (a.chunks > 0 ? a.chunks : a.grid) : 0;
+}
+
+bool launch_cheb_batch(bool fp32, int epl, bool cplx, bool big, bool dyn, const BatchLaunch &b, int total_wg,
+                       size_t lds, hipStream_t s) {
+  return dispatch_cheb(fp32, epl, cplx, big, dyn, [&]<typename T, int E, bool C, int MI, bool DYN>() {
+    launch_one_batch<T, E, C, MI, DYN>(b, total_wg, lds, s);
   });
 }
 

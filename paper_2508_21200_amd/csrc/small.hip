@@ -726,27 +726,24 @@ __device__ double resid_part(const double2 *Y, const double2 *X, const double2 *
 
 // X (m x r) <- X R^{-1} with X* X = R* R (Cholesky QR); C: r x r scratch.
 // Returns false (workgroup-uniform) if X* X is not numerically positive definite.
-__device__ bool chol_qr(double2 *X, int m, int r, double2 *C, int &bad) {
+__device__ bool chol_qr(double2 *X, int m, int r, double2 *C) {
   zgemm(C, r, X, r, true, X, r, r, r, m);  // C = X* X (ends with a barrier)
-  if (threadIdx.x < 64) {  // upper Cholesky factor in place, lanes over columns
-    const int lane = threadIdx.x;
-    int fail = 0;
-    for (int k = 0; k < r; ++k) {
-      const double piv = C[k * r + k].x;
-      if (!(piv > 1e-280)) fail = 1;
-      const double rkk = fail ? 1.0 : sqrt(piv);
-      for (int j = k + 1 + lane; j < r; j += 64) C[k * r + j] = cscale(1.0 / rkk, C[k * r + j]);
-      __builtin_amdgcn_wave_barrier();
-      for (int j = k + 1 + lane; j < r; j += 64)
-        for (int i = k + 1; i <= j; ++i) C[i * r + j] = csub(C[i * r + j], cmulc(C[k * r + i], C[k * r + j]));
-      __builtin_amdgcn_wave_barrier();
-      if (lane == 0) C[k * r + k] = make_double2(rkk, 0.0);
-      __builtin_amdgcn_wave_barrier();
+  // upper Cholesky factor in place, right-looking, all threads on each update
+  for (int k = 0; k < r; ++k) {
+    const double piv = C[k * r + k].x;
+    if (!(piv > 1e-280)) return false;  // every thread read the same pivot
+    const double inv = 1.0 / sqrt(piv);
+    __syncthreads();
+    for (int j = k + 1 + threadIdx.x; j < r; j += NT) C[k * r + j] = cscale(inv, C[k * r + j]);
+    if (threadIdx.x == 0) C[k * r + k] = make_double2(sqrt(piv), 0.0);
+    __syncthreads();
+    const int w = r - k - 1;
+    for (int e = threadIdx.x; e < w * w; e += NT) {
+      const int i = k + 1 + e / w, j = k + 1 + e % w;
+      if (j >= i) C[i * r + j] = csub(C[i * r + j], cmulc(C[k * r + i], C[k * r + j]));
     }
-    if (lane == 0) bad = fail;
+    __syncthreads();
   }
-  __syncthreads();
-  if (bad) return false;
   // rows of X times R^{-1}, in place: x_c = (y_c - sum_{k<c} x_k R_kc) / R_cc
   for (int i = threadIdx.x; i < m; i += NT) {
     double2 *x = X + i * r;
@@ -779,7 +776,7 @@ __device__ inline bool warm_fits(int m, int r, int arena_elems) {
 __device__ bool warm_top(double2 *K, int m, int r, const double2 *S, int lds_in, double2 *u, int ldu,
                          int rows_out, double2 *arena, int arena_elems, int maxit, TriShared &ts, int &iters) {
   __shared__ double red[NW];
-  __shared__ int s_bad;
+  __shared__ double s_lb[kMaxR];
   const int npl = m * (m + 1) / 2;
   double2 *X = K + npl, *Y = X + m * r, *G = Y + m * r, *C = G + r * r;
   for (int e = threadIdx.x; e < m * r; e += NT) X[e] = S[(e / r) * lds_in + e % r];
@@ -824,7 +821,7 @@ __device__ bool warm_top(double2 *K, int m, int r, const double2 *S, int lds_in,
       X[e] = cscale(fabs(d) > 1e-280 ? 1.0 / d : 1.0, Y[e]);
     }
     __syncthreads();
-    if (!chol_qr(X, m, r, C, s_bad)) {
+    if (!chol_qr(X, m, r, C)) {
       iters = it + 1;
       return false;
     }
@@ -834,13 +831,15 @@ __device__ bool warm_top(double2 *K, int m, int r, const double2 *S, int lds_in,
   // certificate (K still intact for the direct solver if it fails)
   {
     const double T = sqrt(fmax(kn2 - g2 - 2.0 * res2, 0.0)), res = sqrt(res2);
-    double lb = 1e300;
-    for (int a = 0; a < r; ++a) {
+    for (int a = threadIdx.x; a < r; a += NT) {  // Gershgorin lower end of row a
       double rad = 0;
       for (int b = 0; b < r; ++b)
         if (b != a) rad += sqrt(cabs2(G[a * r + b]));
-      lb = fmin(lb, G[a * (r + 1)].x - rad);
+      s_lb[a] = G[a * (r + 1)].x - rad;
     }
+    __syncthreads();
+    double lb = 1e300;
+    for (int a = 0; a < r; ++a) lb = fmin(lb, s_lb[a]);
     if (!(lb - res > T + res + 1e-13 * sqrt(kn2))) return false;
   }
   // Ritz vectors: G = Z diag(theta) Z*, theta descending
