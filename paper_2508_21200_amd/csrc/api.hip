@@ -343,6 +343,8 @@ SmallRkParams rk_params(lrei_ctx *ctx, int model, int scheme, double dt, double 
   p.hbar = ctx->hbar;
   p.h = dt;
   p.eig_tol = ctx->opt.eig_tol;
+  // the warm-started eigensolve stops well below the storage rounding of the path
+  p.warm_tol = ctx->fp32 ? 1e-11 : 1e-14;
   p.shift = 0.0;
   p.halfwidth = ctx->terms.gershgorin > 0 ? ctx->terms.gershgorin : 1.0;
   for (int i = 0; i < ctx->r; ++i) p.lam[i] = ctx->lam[i];

@@ -277,6 +277,7 @@ lrei_status build_step_tables(lrei_batch *b, int scheme, double dt) {
     p.hbar = b->hbar;
     p.h = dt;
     p.eig_tol = b->opt.eig_tol;
+    p.warm_tol = b->fp32 ? 1e-11 : 1e-14;
     p.shift = 0.0;
     p.halfwidth = t.terms.gershgorin > 0 ? t.terms.gershgorin : 1.0;
     for (int i = 0; i < t.r; ++i) p.lam[i] = t.lam[i];

@@ -175,6 +175,7 @@ struct SmallRkParams {
   int warm;
   int lds_elems;          // double2 capacity of the dynamic LDS matrix
   double kappa, hbar, h, eig_tol;
+  double warm_tol;        // relative subspace residual at which the warm-started eigensolve stops
   double shift, halfwidth; // Chebyshev map H~ = (H - shift) / halfwidth
   double a[kMaxStages][kMaxStages];
   double b[kMaxStages];

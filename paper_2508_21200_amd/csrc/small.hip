@@ -105,6 +105,10 @@ __device__ inline double min16(double v) {
 }
 __device__ inline double max32(double v) { v = max16(v); return fmax(v, swap16_d(v)); }
 __device__ inline double min32(double v) { v = min16(v); return fmin(v, swap16_d(v)); }
+__device__ inline double max64(double v) {
+  v = max32(v);
+  return fmax(readlane_d(v, 0), readlane_d(v, 32));
+}
 
 __device__ inline double2 wave_sum(double2 v) { return make_double2(sum64(v.x), sum64(v.y)); }
 
@@ -757,10 +761,41 @@ __device__ bool chol_qr(double2 *X, int m, int r, double2 *C) {
   return true;
 }
 
+// X (m x r) <- its polar factor X (X* X)^{-1/2} by Newton-Schulz steps
+// X <- X (3 I - X* X) / 2 (products on MFMA; the error squares each step), with
+// Y (m x r) as scratch.  Returns false (workgroup-uniform, X unchanged in
+// span) if X* X is too far from I for the iteration or it does not settle.
+__device__ bool polar_ns(double2 *X, double2 *Y, int m, int r, double2 *C, double *red) {
+  for (int k = 0; k < 8; ++k) {
+    zgemm(C, r, X, r, true, X, r, r, r, m);  // C = X* X
+    double dv = 0;
+    for (int e = threadIdx.x; e < r * r; e += NT) {
+      double2 c = C[e];
+      if (e / r == e % r) c.x -= 1.0;
+      dv = fmax(dv, fmax(fabs(c.x), fabs(c.y)));
+    }
+    dv = max64(dv);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = dv;
+    __syncthreads();
+    double dev = 0;
+    for (int w = 0; w < NW; ++w) dev = fmax(dev, red[w]);
+    if (dev <= 4e-16) return true;
+    if (!(dev < 0.25) || k == 7) return false;
+    for (int e = threadIdx.x; e < r * r; e += NT)  // C <- (3 I - C) / 2
+      C[e] = e / r == e % r ? make_double2(1.5 - 0.5 * C[e].x, -0.5 * C[e].y) : cscale(-0.5, C[e]);
+    __syncthreads();
+    zgemm(Y, r, X, r, false, C, r, m, r, r);  // Y = X C
+    for (int e = threadIdx.x; e < m * r; e += NT) X[e] = Y[e];
+    __syncthreads();
+  }
+  return false;
+}
+
 // Words (double2) of arena the subspace iteration needs beyond K, and whether
 // the arena holds them and the small eigenproblem (after C, or over K).
 __device__ inline int warm_need(int m, int r) { return 2 * m * r + 2 * r * r; }
-__device__ inline int warm_small(int r) { return r * (r + 1) / 2 + r * r + 2 * r * (r <= 16 ? 16 : 32); }
+__device__ inline int warm_small(int r) { return r * (r + 1) / 2 + 2 * r * r; }
 __device__ inline bool warm_fits(int m, int r, int arena_elems) {
   const int npl = m * (m + 1) / 2;
   return npl + warm_need(m, r) <= arena_elems &&
@@ -774,7 +809,8 @@ __device__ inline bool warm_fits(int m, int r, int arena_elems) {
 // certificate the small eigenproblem's scratch goes after C if it fits there,
 // else over K.  iters: iterations run.
 __device__ bool warm_top(double2 *K, int m, int r, const double2 *S, int lds_in, double2 *u, int ldu,
-                         int rows_out, double2 *arena, int arena_elems, int maxit, TriShared &ts, int &iters) {
+                         int rows_out, double2 *arena, int arena_elems, int maxit, double tol, JacobiShared &js,
+                         int &iters) {
   __shared__ double red[NW];
   __shared__ double s_lb[kMaxR];
   const int npl = m * (m + 1) / 2;
@@ -801,14 +837,15 @@ __device__ bool warm_top(double2 *K, int m, int r, const double2 *S, int lds_in,
     }
     g2 = block_sum(gp, red);
     res2 = block_sum(resid_part(Y, X, G, m, r), red);
-    // converged: |Res| <= 1e-14 |G|, or stalled at rounding level below 1e-12 |G|
-    conv = res2 <= 1e-28 * g2 || (it > 0 && res2 <= 1e-24 * g2 && res2 >= 0.25 * prev);
+    // converged: |Res| <= tol |G|, or stalled at rounding level below 100 tol |G|
+    const double tol2 = tol * tol;
+    conv = res2 <= tol2 * g2 || (it > 0 && res2 <= 1e4 * tol2 * g2 && res2 >= 0.25 * prev);
     if (conv) break;
     // give up early when the contraction measured from two residuals leaves
     // too many iterations
     if (it >= 1) {
       const double q = sqrt(res2 / prev);
-      const double need = q < 1.0 ? log(sqrt(1e-28 * g2 / res2)) / log(q) : 1e30;
+      const double need = q < 1.0 ? log(sqrt(tol2 * g2 / res2)) / log(q) : 1e30;
       if (!(need <= (double)(maxit - it - 1))) {
         iters = it + 1;
         return false;
@@ -821,7 +858,7 @@ __device__ bool warm_top(double2 *K, int m, int r, const double2 *S, int lds_in,
       X[e] = cscale(fabs(d) > 1e-280 ? 1.0 / d : 1.0, Y[e]);
     }
     __syncthreads();
-    if (!chol_qr(X, m, r, C)) {
+    if (!polar_ns(X, Y, m, r, C, red) && !chol_qr(X, m, r, C)) {
       iters = it + 1;
       return false;
     }
@@ -842,16 +879,29 @@ __device__ bool warm_top(double2 *K, int m, int r, const double2 *S, int lds_in,
     for (int a = 0; a < r; ++a) lb = fmin(lb, s_lb[a]);
     if (!(lb - res > T + res + 1e-13 * sqrt(kn2))) return false;
   }
-  // Ritz vectors: G = Z diag(theta) Z*, theta descending
+  // Ritz vectors: G = Z diag(theta) Z*, theta descending, by cyclic Jacobi (G is
+  // close to diagonal: few sweeps) on its packed upper triangle
   double2 *Gp = (npl + warm_need(m, r) + warm_small(r) <= arena_elems) ? C + r * r : K;
-  double2 *Z = Gp + r * (r + 1) / 2;
-  double *scr = reinterpret_cast<double *>(Z + r * r);
+  double2 *Zj = Gp + r * (r + 1) / 2, *Z = Zj + r * r;
   for (int e = threadIdx.x; e < r * r; e += NT) {
     const int i = e / r, j = e % r;
-    if (j <= i) Gp[pl(i, j, r)] = G[e];
+    if (i <= j) Gp[pk(i, j)] = G[e];
   }
   __syncthreads();
-  eig_top(Gp, r, r, Z, r, r, scr, true, ts);
+  jacobi(Gp, Zj, r, 4e-16, 12, js, true);
+  __syncthreads();
+  if (threadIdx.x == 0) {  // columns by eigenvalue, descending
+    for (int k = 0; k < r; ++k) js.order[k] = k;
+    for (int k = 0; k < r; ++k)
+      for (int l = k + 1; l < r; ++l)
+        if (Gp[pk(js.order[l], js.order[l])].x > Gp[pk(js.order[k], js.order[k])].x) {
+          const int t = js.order[k];
+          js.order[k] = js.order[l];
+          js.order[l] = t;
+        }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < r * r; e += NT) Z[e] = Zj[(e / r) * r + js.order[e % r]];
   __syncthreads();
   zgemm(u, ldu, X, r, false, Z, r, m, r, r);  // u = X Z
   for (int e = threadIdx.x; e < (rows_out - m) * r; e += NT) u[(m + e / r) * ldu + e % r] = make_double2(0, 0);
@@ -1553,7 +1603,7 @@ __device__ __forceinline__ void small_rk_body(const SmallRkParams &p, const Smal
       // subspace iteration from the stage's input basis u, in the LDS arena
       // after K (over the direct solver's scratch, which it rebuilds if it runs)
       int its = 0;
-      solved = warm_top(K, m, r, u, r, unext, r, D, s_arena, arena, 10, sh.ts, its);
+      solved = warm_top(K, m, r, u, r, unext, r, D, s_arena, arena, 10, p.warm_tol, sh.js, its);
       if (threadIdx.x == 0) {
         stats[solved ? 9 : 31] += 1;
         stats[12] += its;
