@@ -80,7 +80,9 @@ typedef enum { LREI_WARM_PLAIN = 0, LREI_WARM_ANALYTIC = 1, LREI_WARM_LEARNED = 
 typedef struct {
   int precision;          /* lrei_precision, default LREI_FP64                           */
   double eig_tol;         /* Jacobi tolerance (relative to max|diag|) of the r x r Lowdin
-                             re-orthonormalisation, default 1e-15                       */
+                             re-orthonormalisation of the projected basis, used when its
+                             deviation from orthonormality exceeds 1e-6 (smaller ones
+                             use a series for S^-1/2), default 1e-15                    */
   int eig_max_sweeps;     /* Jacobi sweep limit of that step, default 40                 */
   int warm;               /* lrei_warm, default LREI_WARM_ANALYTIC (RK steps; the AB
                              step always uses the direct solve)                     */
@@ -88,8 +90,9 @@ typedef struct {
   int householder_mode;   /* 1: complement action through Householder reflectors (eq.
                              3.3, Sec. 3.4), default; 0: orthogonal projector form      */
   int use_graph;          /* 1: capture one step as a hipGraph and replay it (default)  */
-  int deterministic;      /* 1 (default): fixed-order reductions, bitwise reproducible  */
-  const char *autotune_cache; /* path of the JSON tile cache, or NULL                   */
+  int deterministic;      /* ignored: every reduction runs in a fixed order, so results
+                             are bitwise reproducible for a given launch shape        */
+  const char *autotune_cache; /* path of the autotuner's text cache file, or NULL     */
 } lrei_options;
 
 typedef struct {

@@ -503,6 +503,8 @@ SmallAbParams ab_params(lrei_ctx *ctx, int mode) {
   p.mode = mode;
   p.model = ab.model;
   p.householder_mode = ctx->opt.householder_mode;
+  p.max_sweeps = ctx->opt.eig_max_sweeps;
+  p.eig_tol = ctx->opt.eig_tol;
   p.kappa = ab.kappa;
   p.hbar = ctx->hbar;
   p.h = ab.dt;

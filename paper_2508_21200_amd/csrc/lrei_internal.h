@@ -228,7 +228,9 @@ struct SmallAbParams {
   double hv_scale;         // H V_k = hv_scale * X[x_hv]
   int npairs_keep;         // older history pairs carried into the new basis (<= m - 2)
   int model, householder_mode, lds_elems;
+  int max_sweeps;          // Jacobi sweep limit of the Lowdin step
   double kappa, hbar, h;
+  double eig_tol;          // Jacobi tolerance of the Lowdin step
   double bcoef[kMaxAb];
   double lam[kMaxR];
 };

@@ -1002,7 +1002,7 @@ __device__ void upper_inverse(const double2 *R, int ldr, double2 *Ri, int ldi, i
 // Jacobi eigendecomposition.  S, Lw, T: r x r, r x r, m x r scratch (global);
 // the packed Jacobi matrices use the LDS arena (>= 2 r^2 elements).
 __device__ void lowdin(double2 *u, int m, int r, double2 *S, double2 *Lw, double2 *T, double2 *arena,
-                       StepShared &sh) {
+                       StepShared &sh, double tol, int max_sweeps) {
   const int rr = r * r;
   zgemm(S, r, u, r, true, u, r, r, r, m);
   __syncthreads();
@@ -1044,7 +1044,7 @@ __device__ void lowdin(double2 *u, int m, int r, double2 *S, double2 *Lw, double
       }
     }
     __syncthreads();
-    jacobi(A, E, r, 1e-16, 60, sh.js, true);
+    jacobi(A, E, r, tol, max_sweeps, sh.js, true);
     __syncthreads();
     for (int e = threadIdx.x; e < rr; e += NT) {
       const int a = e / r, b = e % r;
@@ -1536,7 +1536,7 @@ __device__ __forceinline__ void small_rk_body(const SmallRkParams &p, const Smal
   if (j == 0) {
     for (int e = threadIdx.x; e < D * r; e += NT) u1[e] = R[(e / r) * D + e % r];
     __syncthreads();
-    lowdin(u1, D, r, tmp, Lw, t1, s_arena, sh);
+    lowdin(u1, D, r, tmp, Lw, t1, s_arena, sh, p.eig_tol, p.max_sweeps);
     if (threadIdx.x == 0) stats[4] = sh.dev;
   }
 
@@ -1816,7 +1816,7 @@ __global__ __launch_bounds__(NT) void k_small_ab(SmallAbParams p, SmallAbWs ws) 
   coord_x(y0, p.x_hv, p.hv_scale);
   const ModelCoef mc{p.model, p.kappa, p.hbar, p.lam};
   if (p.mode == 1) {
-    lowdin(u0, D, r, tmp, Lw, t1, s_arena, sh);
+    lowdin(u0, D, r, tmp, Lw, t1, s_arena, sh, p.eig_tol, p.max_sweeps);
     if (threadIdx.x == 0) stats[4] = sh.dev;
     const int m = p.m_ab;
     for (int l = 1; l < m; ++l) {
