@@ -662,17 +662,13 @@ lrei_status lrei_create(lrei_ctx **out, int hip_device, void *hip_stream, const 
     delete ctx;
     return LREI_E_DEVICE;
   }
-  if (hip_stream) {
-    ctx->stream = (hipStream_t)hip_stream;
-  } else {
-    if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
-      delete ctx;
-      return LREI_E_DEVICE;
-    }
-    ctx->own_stream = true;
+  if (hip_stream) ctx->stream = (hipStream_t)hip_stream;
+  ctx->own_stream = !hip_stream;
+  if (create_streams(!hip_stream, &ctx->stream, &ctx->side) != hipSuccess) {
+    lrei_destroy(ctx);
+    return LREI_E_DEVICE;
   }
-  bool ok = hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) == hipSuccess &&
-            hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming) == hipSuccess &&
+  bool ok = hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming) == hipSuccess &&
             hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming) == hipSuccess;
   for (auto &e : ctx->ev_pass) ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
   ok = ok && ctx->sched.ensure(16 * sizeof(int)) && hipMemset(ctx->sched.p, 0, 16 * sizeof(int)) == hipSuccess;

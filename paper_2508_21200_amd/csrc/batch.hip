@@ -444,17 +444,13 @@ lrei_status lrei_batch_create(lrei_batch **out, int hip_device, void *hip_stream
     destroy_batch(b);
     return cfail(st, m);
   };
-  if (hip_stream) {
-    b->stream = (hipStream_t)hip_stream;
-  } else {
-    if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
-      b->err = "stream creation failed";
-      return bail(LREI_E_DEVICE);
-    }
-    b->own_stream = true;
+  if (hip_stream) b->stream = (hipStream_t)hip_stream;
+  b->own_stream = !hip_stream;
+  if (create_streams(!hip_stream, &b->stream, &b->side) != hipSuccess) {
+    b->err = "stream creation failed";
+    return bail(LREI_E_DEVICE);
   }
-  bool ok = hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) == hipSuccess &&
-            hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) == hipSuccess &&
+  bool ok = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) == hipSuccess &&
             hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming) == hipSuccess;
   for (auto &e : b->ev_pass) ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
   if (!ok) {

@@ -36,6 +36,17 @@ struct DevBuf {
   }
 };
 
+// The two streams of a context: the work stream (N-space passes; the
+// caller's, or one owned by the library) and the side stream the projected
+// step runs on, both non-blocking and at the default priority.
+inline hipError_t create_streams(bool own_work, hipStream_t *work, hipStream_t *side) {
+  if (own_work) {
+    hipError_t e = hipStreamCreateWithFlags(work, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+  }
+  return hipStreamCreateWithFlags(side, hipStreamNonBlocking);
+}
+
 // Butcher tableaux (Sec. 3.6).  RK2: the paper's Heun tableau; RK3: Kutta;
 // RK4: classical.
 inline void tableau(int scheme, int &s, double a[kMaxStages][kMaxStages], double b[kMaxStages]) {

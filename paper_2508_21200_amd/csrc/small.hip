@@ -311,6 +311,114 @@ __device__ int jacobi(double2 *A, double2 *V, int m, double tol, int max_sweeps,
   return -1;
 }
 
+// The same Jacobi iteration run by one wave (called by the 64 lanes of one
+// wave only; A, V and js in LDS): each round costs wave-level
+// synchronisation instead of workgroup barriers, which is what dominates
+// for r x r problems.  Same rotations, same arithmetic per element.
+__device__ int jacobi_wave(double2 *A, double2 *V, int m, double tol, int max_sweeps, JacobiShared &js) {
+  const int lane = threadIdx.x & 63;
+  const int mp = m + (m & 1), np = mp / 2;
+  for (int e = lane; e < m * m; e += 64)
+    V[e] = make_double2((e / m) == (e % m) ? 1.0 : 0.0, 0.0);
+  if (lane == 0) {
+    double sc = 0;
+    for (int i = 0; i < m; ++i) sc = fmax(sc, fabs(A[pk(i, i)].x));
+    js.scale = sc > 0 ? sc : 1.0;
+  }
+  __builtin_amdgcn_wave_barrier();
+  const double thresh = tol * js.scale;
+  if (m == 1) return 0;
+  const int nblk = np * (np + 1) / 2;
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    if (lane == 0) js.rotated = 0;
+    __builtin_amdgcn_wave_barrier();
+    for (int round = 0; round < mp - 1; ++round) {
+      if (lane < np) {
+        const int i = lane;
+        const int a = rr_player(i, round, mp), b = rr_player(mp - 1 - i, round, mp);
+        const int p = a < b ? a : b, q = a < b ? b : a;
+        js.p[i] = p;
+        js.q[i] = q;
+        double cs = 1, sn = 0, t = 0;
+        double2 e = make_double2(1, 0);
+        if (q < m) {
+          const double2 c = A[pk(p, q)];
+          const double x = sqrt(cabs2(c));
+          if (x > thresh) {
+            const double app = A[pk(p, p)].x, aqq = A[pk(q, q)].x;
+            const double tau = (aqq - app) / (2.0 * x);
+            t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            cs = 1.0 / sqrt(1.0 + t * t);
+            sn = t * cs;
+            e = make_double2(c.x / x, -c.y / x);  // e^{-i arg c}
+            js.rotated = 1;
+          }
+        }
+        js.cs[i] = cs;
+        js.sn[i] = sn;
+        js.t[i] = t;
+        js.e[i] = e;
+      }
+      __builtin_amdgcn_wave_barrier();
+      // two-sided update of the 2x2 blocks (P rows, Q cols), P <= Q; the
+      // (Q, P) blocks are their adjoints in the packed storage
+      for (int blk = lane; blk < nblk; blk += 64) {
+        int P = 0, rem = blk;
+        while (rem >= np - P) {
+          rem -= np - P;
+          ++P;
+        }
+        const int Q = P + rem;
+        const double snP = js.sn[P], snQ = js.sn[Q];
+        if (snP == 0.0 && snQ == 0.0) continue;
+        const int pP = js.p[P], qP = js.q[P], pQ = js.p[Q], qQ = js.q[Q];
+        if (P == Q) {
+          if (qP >= m) continue;
+          const double x = sqrt(cabs2(A[pk(pP, qP)]));
+          const double app = A[pk(pP, pP)].x, aqq = A[pk(qP, qP)].x;
+          A[pk(pP, pP)] = make_double2(app - js.t[P] * x, 0.0);
+          A[pk(qP, qP)] = make_double2(aqq + js.t[P] * x, 0.0);
+          A[pk(pP, qP)] = make_double2(0, 0);
+          continue;
+        }
+        const bool hq = qP < m, hqq = qQ < m;
+        const double2 z = make_double2(0, 0);
+        const double2 a = aget(A, pP, pQ);
+        const double2 b = hqq ? aget(A, pP, qQ) : z;
+        const double2 c = hq ? aget(A, qP, pQ) : z;
+        const double2 d = (hq && hqq) ? aget(A, qP, qQ) : z;
+        const double csP = js.cs[P];
+        const double2 ebP = cconj(js.e[P]);
+        const double2 a1 = csub(cscale(csP, a), cscale(snP, cmul(ebP, c)));
+        const double2 b1 = csub(cscale(csP, b), cscale(snP, cmul(ebP, d)));
+        const double2 c1 = cadd(cscale(snP, a), cscale(csP, cmul(ebP, c)));
+        const double2 d1 = cadd(cscale(snP, b), cscale(csP, cmul(ebP, d)));
+        const double csQ = js.cs[Q];
+        const double2 eQ = js.e[Q];
+        aset(A, pP, pQ, csub(cscale(csQ, a1), cscale(snQ, cmul(eQ, b1))));
+        if (hqq) aset(A, pP, qQ, cadd(cscale(snQ, a1), cscale(csQ, cmul(eQ, b1))));
+        if (hq) aset(A, qP, pQ, csub(cscale(csQ, c1), cscale(snQ, cmul(eQ, d1))));
+        if (hq && hqq) aset(A, qP, qQ, cadd(cscale(snQ, c1), cscale(csQ, cmul(eQ, d1))));
+      }
+      for (int e = lane; e < np * m; e += 64) {
+        const int P = e / m, i = e % m;
+        const double sn = js.sn[P];
+        if (sn == 0.0) continue;
+        const int p = js.p[P], q = js.q[P];
+        const double2 vp = V[i * m + p], vq = V[i * m + q];
+        const double cs = js.cs[P];
+        const double2 ee = js.e[P];
+        V[i * m + p] = csub(cscale(cs, vp), cscale(sn, cmul(ee, vq)));
+        V[i * m + q] = cadd(cscale(sn, vp), cscale(cs, cmul(ee, vq)));
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (!js.rotated) return sweep + 1;
+  }
+  return -1;
+}
+
 __device__ inline uint64_t now_ticks() { return __builtin_amdgcn_s_memrealtime(); }
 
 // ----- top-r eigenpairs by Householder tridiagonalisation ---------------------
@@ -762,32 +870,75 @@ __device__ bool chol_qr(double2 *X, int m, int r, double2 *C) {
 }
 
 // X (m x r) <- its polar factor X (X* X)^{-1/2} by Newton-Schulz steps
-// X <- X (3 I - X* X) / 2 (products on MFMA; the error squares each step), with
-// Y (m x r) as scratch.  Returns false (workgroup-uniform, X unchanged in
-// span) if X* X is too far from I for the iteration or it does not settle.
-__device__ bool polar_ns(double2 *X, double2 *Y, int m, int r, double2 *C, double *red) {
+// X <- X (3 I - X* X) / 2 (products on MFMA; the error squares each step).
+// X and Y (m x r) swap roles as the iteration proceeds.  Returns false
+// (workgroup-uniform; X spans the same space) if X* X is too far from I for
+// the iteration or it does not settle.  For r <= 16 one wave forms X* X, its
+// distance from I and the step matrix in registers: two barriers per step.
+__device__ bool polar_ns(double2 *&X, double2 *&Y, int m, int r, double2 *C, double *red, int *flag) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int k = 0; k < 8; ++k) {
-    zgemm(C, r, X, r, true, X, r, r, r, m);  // C = X* X
-    double dv = 0;
-    for (int e = threadIdx.x; e < r * r; e += NT) {
-      double2 c = C[e];
-      if (e / r == e % r) c.x -= 1.0;
-      dv = fmax(dv, fmax(fabs(c.x), fabs(c.y)));
+    if (r <= 16) {
+      if (wave == 0) {
+        const int li = lane & 15, lk = lane >> 4;
+        d4v_g cre = {0, 0, 0, 0}, cim = {0, 0, 0, 0};
+        for (int kk = 0; kk < m; kk += 16) {
+          double2 a[4], b[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int kr = kk + 4 * q + lk;
+            a[q] = (kr < m && li < r) ? cconj(X[kr * r + li]) : make_double2(0, 0);
+            b[q] = (kr < m && li < r) ? X[kr * r + li] : make_double2(0, 0);
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            cre = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q].x, b[q].x, cre, 0, 0, 0);
+            cre = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[q].y, b[q].y, cre, 0, 0, 0);
+            cim = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q].x, b[q].y, cim, 0, 0, 0);
+            cim = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q].y, b[q].x, cim, 0, 0, 0);
+          }
+        }
+        double dv = 0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = 4 * v + lk, j = li;
+          if (i < r && j < r) {
+            const double cr = cre[v] - (i == j ? 1.0 : 0.0);
+            dv = fmax(dv, fmax(fabs(cr), fabs(cim[v])));
+            C[i * r + j] = make_double2((i == j ? 1.0 : 0.0) - 0.5 * cr, -0.5 * cim[v]);  // (3 I - X* X) / 2
+          }
+        }
+        dv = max64(dv);
+        if (lane == 0) *flag = dv <= 4e-16 ? 1 : ((!(dv < 0.25) || k == 7) ? 2 : 0);
+      }
+      __syncthreads();
+    } else {
+      zgemm(C, r, X, r, true, X, r, r, r, m);  // C = X* X
+      double dv = 0;
+      for (int e = threadIdx.x; e < r * r; e += NT) {
+        double2 c = C[e];
+        if (e / r == e % r) c.x -= 1.0;
+        dv = fmax(dv, fmax(fabs(c.x), fabs(c.y)));
+      }
+      dv = max64(dv);
+      __syncthreads();
+      if (lane == 0) red[wave] = dv;
+      __syncthreads();
+      double dev = 0;
+      for (int w = 0; w < NW; ++w) dev = fmax(dev, red[w]);
+      for (int e = threadIdx.x; e < r * r; e += NT)  // C <- (3 I - C) / 2
+        C[e] = e / r == e % r ? make_double2(1.5 - 0.5 * C[e].x, -0.5 * C[e].y) : cscale(-0.5, C[e]);
+      if (threadIdx.x == 0) *flag = dev <= 4e-16 ? 1 : ((!(dev < 0.25) || k == 7) ? 2 : 0);
+      __syncthreads();
     }
-    dv = max64(dv);
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = dv;
-    __syncthreads();
-    double dev = 0;
-    for (int w = 0; w < NW; ++w) dev = fmax(dev, red[w]);
-    if (dev <= 4e-16) return true;
-    if (!(dev < 0.25) || k == 7) return false;
-    for (int e = threadIdx.x; e < r * r; e += NT)  // C <- (3 I - C) / 2
-      C[e] = e / r == e % r ? make_double2(1.5 - 0.5 * C[e].x, -0.5 * C[e].y) : cscale(-0.5, C[e]);
-    __syncthreads();
-    zgemm(Y, r, X, r, false, C, r, m, r, r);  // Y = X C
-    for (int e = threadIdx.x; e < m * r; e += NT) X[e] = Y[e];
-    __syncthreads();
+    const int f = *flag;
+    __syncthreads();  // every thread has read the flag before it is rewritten
+    if (f == 1) return true;
+    if (f == 2) return false;
+    zgemm(Y, r, X, r, false, C, r, m, r, r);  // Y = X (3 I - X* X) / 2
+    double2 *t = X;
+    X = Y;
+    Y = t;
   }
   return false;
 }
@@ -813,6 +964,7 @@ __device__ bool warm_top(double2 *K, int m, int r, const double2 *S, int lds_in,
                          int &iters) {
   __shared__ double red[NW];
   __shared__ double s_lb[kMaxR];
+  __shared__ int s_flag;
   const int npl = m * (m + 1) / 2;
   double2 *X = K + npl, *Y = X + m * r, *G = Y + m * r, *C = G + r * r;
   for (int e = threadIdx.x; e < m * r; e += NT) X[e] = S[(e / r) * lds_in + e % r];
@@ -858,7 +1010,7 @@ __device__ bool warm_top(double2 *K, int m, int r, const double2 *S, int lds_in,
       X[e] = cscale(fabs(d) > 1e-280 ? 1.0 / d : 1.0, Y[e]);
     }
     __syncthreads();
-    if (!polar_ns(X, Y, m, r, C, red) && !chol_qr(X, m, r, C)) {
+    if (!polar_ns(X, Y, m, r, C, red, &s_flag) && !chol_qr(X, m, r, C)) {
       iters = it + 1;
       return false;
     }
@@ -888,7 +1040,7 @@ __device__ bool warm_top(double2 *K, int m, int r, const double2 *S, int lds_in,
     if (i <= j) Gp[pk(i, j)] = G[e];
   }
   __syncthreads();
-  jacobi(Gp, Zj, r, 4e-16, 12, js, true);
+  if (threadIdx.x < 64) jacobi_wave(Gp, Zj, r, 4e-16, 12, js);
   __syncthreads();
   if (threadIdx.x == 0) {  // columns by eigenvalue, descending
     for (int k = 0; k < r; ++k) js.order[k] = k;
