@@ -275,7 +275,12 @@ __device__ __forceinline__ void cheb_body(const ChebArgs &a, int wg, unsigned ch
   const T *__restrict__ Pc = reinterpret_cast<const T *>(a.Pcur);
   const T *__restrict__ Pp = reinterpret_cast<const T *>(a.Pprev);
   T *__restrict__ Pn = reinterpret_cast<T *>(a.Pnext);
-  const DevTerm<T> *__restrict__ terms = reinterpret_cast<const DevTerm<T> *>(a.terms);
+  // The term table is read-only during the launch and every lane of a wave
+  // reads the same record: reading it through the constant address space
+  // makes these scalar loads, which are waited for separately from the row
+  // gathers, so the gathers of several terms stay in flight together.
+  using TermC = const __attribute__((address_space(4))) DevTerm<T>;
+  TermC *terms = (TermC *)(a.terms);
   const T *__restrict__ dv = reinterpret_cast<const T *>(a.diagv);
   const T *__restrict__ Yin = reinterpret_cast<const T *>(a.acc_in);
 
@@ -422,7 +427,7 @@ __device__ __forceinline__ void cheb_body(const ChebArgs &a, int wg, unsigned ch
 #pragma unroll
           for (int e = 0; e < 2 * E; ++e) y[u][e] = T(0);
           if (t + u < t1) {
-            const DevTerm<T> &tm = terms[t + u];
+            TermC &tm = terms[t + u];
             const int idx = (int)(((xu >> tm.sa) & 1u) | (((xu >> tm.sb) & 1u) << 1));
             cr[u] = pick4(idx, tm.re[0], tm.re[1], tm.re[2], tm.re[3]);
             if (CPLX) ci[u] = pick4(idx, tm.im[0], tm.im[1], tm.im[2], tm.im[3]);
