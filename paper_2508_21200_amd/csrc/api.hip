@@ -26,9 +26,11 @@ struct lrei_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
-  // the projected-step stages run on a second stream, each after its pass
-  hipStream_t side = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_pass[kMaxStages] = {};
+  // the projected-step stages run on a second stream, each after its pass;
+  // their basis extensions on a third, each after its pass
+  hipStream_t side = nullptr, basis = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_join_basis = nullptr;
+  hipEvent_t ev_pass[kMaxStages] = {}, ev_basis[kMaxStages] = {};
   lrei_options opt{};
   std::string err;
 
@@ -136,7 +138,8 @@ lrei_status alloc_state(lrei_ctx *ctx, int r, bool fp32) {
                           + (4 * (size_t)D * r + 2 * (size_t)D * D + 4 * (size_t)r * r)  // work
                           + (size_t)kMaxStages * 3 * D * r     // stage
                           + (size_t)D * r                      // Cfin
-                          + (size_t)D;                         // flags (as complex slots)
+                          + (size_t)D                          // flags (as complex slots)
+                          + (size_t)kMaxStages;                // warm_skip (as complex slots)
   if (!ctx->ws_buf.ensure(ws_elems * sizeof(double2))) return ctx->fail(LREI_E_NOMEM, "device allocation failed");
   if (!ctx->stats_buf.ensure(kStatsLen * sizeof(double))) return ctx->fail(LREI_E_NOMEM, "device allocation failed");
   if (!ctx->lam_dev.ensure(kMaxR * sizeof(double))) return ctx->fail(LREI_E_NOMEM, "device allocation failed");
@@ -149,7 +152,8 @@ lrei_status alloc_state(lrei_ctx *ctx, int r, bool fp32) {
   ctx->ws.work = w; w += 4 * (size_t)D * r + 2 * (size_t)D * D + 4 * (size_t)r * r;
   ctx->ws.stage = w; w += (size_t)kMaxStages * 3 * D * r;
   ctx->ws.Cfin = w; w += (size_t)D * r;
-  ctx->ws.flags = (double *)w;
+  ctx->ws.flags = (double *)w; w += (size_t)D;
+  ctx->ws.warm_skip = (double *)w;
   ctx->ws.stats = (double *)ctx->stats_buf.p;
   return LREI_OK;
 }
@@ -353,23 +357,31 @@ SmallRkParams rk_params(lrei_ctx *ctx, int model, int scheme, double dt, double 
 }
 
 // Enqueues one LREI-RK step: the Chebyshev Krylov passes on the context
-// stream; projected-step stage j on the side stream as soon as pass j is
-// reduced (it needs the Grams of P_0 .. P_{j+1} only), overlapping the later
-// passes; the combination after the last stage.
+// stream; as soon as pass j is reduced (stage j needs the Grams of
+// P_0 .. P_{j+1} only) the basis extension of stage j on the basis stream,
+// then stage j itself on the side stream, so that the extension of stage
+// j + 1 and the later passes overlap stage j; the combination after the last
+// stage.
 void enqueue_rk_step(lrei_ctx *ctx, int model, int scheme, double dt, double kappa) {
   const SmallRkParams p = rk_params(ctx, model, scheme, dt, kappa);
   const int s = p.s;
   (void)hipEventRecord(ctx->ev_fork, ctx->stream);
   (void)hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0);
+  (void)hipStreamWaitEvent(ctx->basis, ctx->ev_fork, 0);
   for (int j = 0; j < s; ++j) {
     if (j == 0)
       cheb_pass(ctx, 0, nullptr, ctx->blocks[0].p, ctx->blocks[1].p, 0);
     else
       cheb_pass(ctx, 1, ctx->blocks[j - 1].p, ctx->blocks[j].p, ctx->blocks[j + 1].p, j);
     (void)hipEventRecord(ctx->ev_pass[j], ctx->stream);
-    (void)hipStreamWaitEvent(ctx->side, ctx->ev_pass[j], 0);
+    (void)hipStreamWaitEvent(ctx->basis, ctx->ev_pass[j], 0);
+    launch_small_rk_basis(p, ctx->ws, j, ctx->basis);
+    (void)hipEventRecord(ctx->ev_basis[j], ctx->basis);
+    (void)hipStreamWaitEvent(ctx->side, ctx->ev_basis[j], 0);
     launch_small_rk_stage(p, ctx->ws, j, ctx->side);
   }
+  (void)hipEventRecord(ctx->ev_join_basis, ctx->basis);
+  (void)hipStreamWaitEvent(ctx->stream, ctx->ev_join_basis, 0);
   (void)hipEventRecord(ctx->ev_join, ctx->side);
   (void)hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0);
   const void *bl[kMaxBlocks];
@@ -664,13 +676,16 @@ lrei_status lrei_create(lrei_ctx **out, int hip_device, void *hip_stream, const 
   }
   if (hip_stream) ctx->stream = (hipStream_t)hip_stream;
   ctx->own_stream = !hip_stream;
-  if (create_streams(!hip_stream, &ctx->stream, &ctx->side) != hipSuccess) {
+  if (create_streams(!hip_stream, &ctx->stream, &ctx->side) != hipSuccess ||
+      hipStreamCreateWithFlags(&ctx->basis, hipStreamNonBlocking) != hipSuccess) {
     lrei_destroy(ctx);
     return LREI_E_DEVICE;
   }
   bool ok = hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming) == hipSuccess &&
-            hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming) == hipSuccess;
+            hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&ctx->ev_join_basis, hipEventDisableTiming) == hipSuccess;
   for (auto &e : ctx->ev_pass) ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+  for (auto &e : ctx->ev_basis) ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
   ok = ok && ctx->sched.ensure(16 * sizeof(int)) && hipMemset(ctx->sched.p, 0, 16 * sizeof(int)) == hipSuccess;
   if (!ok) {
     lrei_destroy(ctx);
@@ -704,13 +719,16 @@ void lrei_destroy(lrei_ctx *ctx) {
   ctx->ab_Cc.release();
   ctx->ab_work.release();
   ctx->ab_partials.release();
-  if (ctx->side) {
-    (void)hipStreamSynchronize(ctx->side);
-    (void)hipStreamDestroy(ctx->side);
-  }
-  if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
-  if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+  for (hipStream_t *st : {&ctx->side, &ctx->basis})
+    if (*st) {
+      (void)hipStreamSynchronize(*st);
+      (void)hipStreamDestroy(*st);
+    }
+  for (hipEvent_t e : {ctx->ev_fork, ctx->ev_join, ctx->ev_join_basis})
+    if (e) (void)hipEventDestroy(e);
   for (auto &e : ctx->ev_pass)
+    if (e) (void)hipEventDestroy(e);
+  for (auto &e : ctx->ev_basis)
     if (e) (void)hipEventDestroy(e);
   if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
@@ -859,8 +877,11 @@ lrei_status lrei_set_rho(lrei_ctx *ctx, int r, const double *lambda, const void 
     return st;
   }
   ctx->r = r;
-  launch_permute(ctx->fp32, tv.p, ctx->blocks[0].p, ctx->N, r, ctx->site_pos.data(), ctx->n, false, ctx->stream);
-  e2 = hipGetLastError();
+  // a new state: every stage tries the warm-started eigensolve again
+  e2 = hipMemsetAsync(ctx->ws.warm_skip, 0, kMaxStages * sizeof(double), ctx->stream);
+  if (e2 == hipSuccess)
+    launch_permute(ctx->fp32, tv.p, ctx->blocks[0].p, ctx->N, r, ctx->site_pos.data(), ctx->n, false, ctx->stream);
+  if (e2 == hipSuccess) e2 = hipGetLastError();
   if (e2 == hipSuccess) e2 = hipStreamSynchronize(ctx->stream);
   (void)vbytes;
   release_tmp();

@@ -176,7 +176,7 @@ lrei_status alloc_traj(lrei_batch *b, lrei_batch::Traj &t, int idx) {
     return b->fail(LREI_E_NOMEM, "device allocation failed");
   const size_t ws_elems = (size_t)kMaxStages * 3 * r * r + 4 * (size_t)D * D +
                           (4 * (size_t)D * r + 2 * (size_t)D * D + 4 * (size_t)r * r) +
-                          (size_t)kMaxStages * 3 * D * r + (size_t)D * r + (size_t)D;
+                          (size_t)kMaxStages * 3 * D * r + (size_t)D * r + (size_t)D + (size_t)kMaxStages;
   if (!t.ws_buf.ensure(ws_elems * sizeof(double2))) return b->fail(LREI_E_NOMEM, "device allocation failed");
   double2 *w = (double2 *)t.ws_buf.p;
   t.ws.meas = w; w += (size_t)kMaxStages * 3 * r * r;
@@ -187,7 +187,10 @@ lrei_status alloc_traj(lrei_batch *b, lrei_batch::Traj &t, int idx) {
   t.ws.work = w; w += 4 * (size_t)D * r + 2 * (size_t)D * D + 4 * (size_t)r * r;
   t.ws.stage = w; w += (size_t)kMaxStages * 3 * D * r;
   t.ws.Cfin = w; w += (size_t)D * r;
-  t.ws.flags = (double *)w;
+  t.ws.flags = (double *)w; w += (size_t)D;
+  t.ws.warm_skip = (double *)w;
+  if (hipMemset(t.ws.warm_skip, 0, kMaxStages * sizeof(double)) != hipSuccess)
+    return b->fail(LREI_E_DEVICE, "device memset failed");
   t.ws.stats = (double *)b->stats.p + (size_t)idx * kStatsLen;
   return LREI_OK;
 }

@@ -193,6 +193,7 @@ struct SmallWs {
   double2 *stage;    // [kMaxStages][3][D*r] u, z, w per stage
   double2 *Cfin;     // [D*r] combination coefficients for the new V
   double *flags;     // [D] directions dropped as dependent
+  double *warm_skip; // [kMaxStages] steps left before stage j tries the warm start again
   double *stats;     // [32]
 };
 
@@ -212,6 +213,9 @@ inline int small_lds_elems(int D, int r) {
   return need < kSmallLdsElems ? need : kSmallLdsElems;
 }
 void launch_small_rk(const SmallRkParams &p, const SmallWs &ws, hipStream_t s);
+// Stage j of an RK step in two launches: the basis extension (needs the Grams
+// of pass j), then the stage (needs the extension and stage j - 1).
+void launch_small_rk_basis(const SmallRkParams &p, const SmallWs &ws, int j, hipStream_t s);
 void launch_small_rk_stage(const SmallRkParams &p, const SmallWs &ws, int j, hipStream_t s);
 // Stage j of many independent projected steps, one workgroup per job;
 // lds_elems is the largest p.lds_elems among the jobs.

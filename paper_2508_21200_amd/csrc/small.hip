@@ -1130,24 +1130,41 @@ __device__ void chol_drop(const double2 *G, int ldg, const double2 *orig, int ld
 
 // Ri = R^{-1} for the n x n upper triangular R: thread c owns column c and
 // back-substitutes bottom-up; the column's own earlier results are re-read by
-// the same thread only.  Begins and ends with a barrier.
-__device__ void upper_inverse(const double2 *R, int ldr, double2 *Ri, int ldi, int n) {
-  for (int e = threadIdx.x; e < n * n; e += NT) Ri[(e / n) * ldi + e % n] = make_double2(0, 0);
+// the same thread only.  The substitution is a chain of dependent reads, so R
+// and Ri are staged in the LDS arena when 2 n^2 elements fit there (in global
+// memory otherwise).  Begins and ends with a barrier; the arena is scratch.
+__device__ void upper_inverse(const double2 *R, int ldr, double2 *Ri, int ldi, int n, double2 *arena,
+                              int arena_elems) {
+  const bool in_lds = 2 * n * n <= arena_elems;
+  const double2 *Rs = R;
+  double2 *Is = Ri;
+  int lr = ldr, li = ldi;
+  if (in_lds) {
+    for (int e = threadIdx.x; e < n * n; e += NT) arena[e] = R[(e / n) * ldr + e % n];
+    Rs = arena;
+    Is = arena + n * n;
+    lr = li = n;
+  }
+  for (int e = threadIdx.x; e < n * n; e += NT) Is[(e / n) * li + e % n] = make_double2(0, 0);
   __syncthreads();
   for (int c = threadIdx.x; c < n; c += NT) {
-    Ri[c * ldi + c] = cdiv(make_double2(1, 0), R[c * ldr + c]);
+    Is[c * li + c] = cdiv(make_double2(1, 0), Rs[c * lr + c]);
     for (int i = c - 1; i >= 0; --i) {
       double sr = 0, si = 0;
 #pragma unroll 8
       for (int k = i + 1; k <= c; ++k) {
-        const double2 a = R[i * ldr + k], b = Ri[k * ldi + c];
+        const double2 a = Rs[i * lr + k], b = Is[k * li + c];
         sr += a.x * b.x - a.y * b.y;
         si += a.x * b.y + a.y * b.x;
       }
-      Ri[i * ldi + c] = cdiv(make_double2(-sr, -si), R[i * ldr + i]);
+      Is[i * li + c] = cdiv(make_double2(-sr, -si), Rs[i * lr + i]);
     }
   }
   __syncthreads();
+  if (in_lds) {
+    for (int e = threadIdx.x; e < n * n; e += NT) Ri[(e / n) * ldi + e % n] = Is[e];
+    __syncthreads();
+  }
 }
 
 // u (m x r) <- u (u* u)^{-1/2} when max|u* u - I| > 1e-14 (Lowdin), by an r x r
@@ -1536,47 +1553,51 @@ __device__ void householder_qr(double2 *M, int m, int q, double2 *Q, double2 *Rm
 // matrix, its Cholesky factor R (bordered form: R12 = R11^{-*} G12,
 // R22 = chol(G22 - R12* R12)) and R^{-1} by the new Krylov block, then runs
 // the stage.  State between launches lives in the workspace.
+//
+// The two halves are separate device functions: the basis extension (Gram
+// columns, Cholesky, R^{-1}) needs only the Grams of pass j, the stage itself
+// also the output of stage j - 1.  The single-trajectory step runs them as two
+// kernels on two streams, so that the basis extension of stage j + 1 runs
+// while stage j does; the batch kernel runs both in one launch.  They share no
+// scratch: the extension writes columns [k0, k1) of the Gram, R and R^{-1}
+// (rows and columns below k0 are all stage j reads of them), the drop flags
+// of those columns, and its own scratch in the Hh block.
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ void small_rk_body(const SmallRkParams &p, const SmallWs &ws, int j, double2 *s_arena) {
-  __shared__ StepShared sh;
+// phase timers (100 MHz real-time counter): slots 0..2 the extension, 3..7 the
+// stage, each part adding only its own slots into stats[16..23]
+// steps a stage goes to the direct eigensolver after a rejected warm start
+constexpr int kWarmRetry = 8;
 
-  const int r = p.r, s = p.s, nb = p.nblocks, D = nb * r, rr = r * r;
+struct PhaseClock {
+  uint64_t mark;
+  double acc[8];
+};
+
+__device__ __forceinline__ void rk_basis(const SmallRkParams &p, const SmallWs &ws, int j, double2 *s_arena,
+                                         StepShared &sh, PhaseClock &pc) {
+  const int r = p.r, nb = p.nblocks, D = nb * r, rr = r * r;
   double2 *G = ws.gamma, *R = ws.R, *Ri = ws.Rinv;
-  double2 *y = ws.work;                 // D x r
-  double2 *t1 = y + D * r;              // D x r
-  double2 *Uh = t1 + D * r;             // D x r Householder vectors (global fallback)
-  double2 *Yc = Uh + D * r;             // D x r
-  double2 *Vj = Yc + D * r;             // D x D eigensolver scratch (global fallback)
-  double2 *Kg = Vj + D * D;             // D x D stage matrix (global fallback)
-  double2 *X11 = Kg + D * D;            // r x r
-  double2 *Gr = X11 + rr;               // r x r
-  double2 *tmp = Gr + rr;               // r x r
-  double2 *Lw = tmp + rr;               // r x r Lowdin factor
   double2 *S22 = ws.Hh;                 // 2r x 2r Schur complement / R22^{-1} scratch
+  double2 *t1 = ws.Hh + 4 * rr;         // k0 x r products (k0 <= s r; fits after S22 in D x D)
   double *flags = ws.flags;             // [D] dropped directions
   double *stats = ws.stats;
   const int arena = p.lds_elems;
   const int k0 = j == 0 ? 0 : (j + 1) * r;  // first new column of the Gram matrix
   const int k1 = (j + 2) * r;               // end of the new columns
   const int nn = k1 - k0;
-  // phase timers (100 MHz real-time counter), summed into stats[16..23]
-  __shared__ uint64_t s_tmark;
-  __shared__ double s_tacc[8];
   if (threadIdx.x == 0) {
-    s_tmark = now_ticks();
-    for (int k = 0; k < 8; ++k) s_tacc[k] = 0.0;
-    for (int k = 0; k < 7; ++k) sh.ts.tacc[k] = 0.0;
+    pc.mark = now_ticks();
+    for (int k = 0; k < 3; ++k) pc.acc[k] = 0.0;
   }
   auto lap = [&](int slot) {
     __syncthreads();
     if (threadIdx.x == 0) {
       const uint64_t t = now_ticks();
-      s_tacc[slot] += (double)(t - s_tmark);
-      s_tmark = t;
+      pc.acc[slot] += (double)(t - pc.mark);
+      pc.mark = t;
     }
   };
-
   // ---- 1. Gram columns [k0, k1) -----------------------------------------------
   // pass 0 measured P0*P0, P0*P1, P1*P1; pass j >= 1 measured P_j*P_{j+1}, P_{j+1}*P_{j+1};
   // the other blocks of column j+1 follow from P_{j+1} = 2 H~ P_j - P_{j-1}
@@ -1670,9 +1691,9 @@ __device__ __forceinline__ void small_rk_body(const SmallRkParams &p, const Smal
   // ---- 3. R^{-1} for the new columns: Ri22 = R22^{-1}, Ri12 = -Ri11 R12 Ri22 ------
   if (j == 0) {
     for (int e = threadIdx.x; e < D * D; e += NT) Ri[e] = make_double2(0, 0);
-    upper_inverse(R, D, Ri, D, k1);
+    upper_inverse(R, D, Ri, D, k1, s_arena, arena);
   } else {
-    upper_inverse(R + k0 * (D + 1), D, Ri + k0 * (D + 1), D, nn);
+    upper_inverse(R + k0 * (D + 1), D, Ri + k0 * (D + 1), D, nn, s_arena, arena);
     zgemm(t1, nn, Ri, D, false, R + k0, D, k0, nn, k0);       // Ri11 R12
     zgemm(S22, nn, t1, nn, false, Ri + k0 * (D + 1), D, k0, nn, nn);  // (Ri11 R12) Ri22
     for (int e = threadIdx.x; e < k0 * nn; e += NT) {
@@ -1681,8 +1702,44 @@ __device__ __forceinline__ void small_rk_body(const SmallRkParams &p, const Smal
     }
     __syncthreads();
   }
-  for (int c = threadIdx.x; c < k1; c += NT) sh.drop[c] = flags[c] != 0.0;
   lap(2);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 3; ++k) stats[16 + k] += pc.acc[k] * 1e-5;  // ms
+}
+
+__device__ __forceinline__ void rk_stage(const SmallRkParams &p, const SmallWs &ws, int j, double2 *s_arena,
+                                         StepShared &sh, PhaseClock &pc) {
+  const int r = p.r, s = p.s, nb = p.nblocks, D = nb * r, rr = r * r;
+  double2 *R = ws.R, *Ri = ws.Rinv;
+  double2 *y = ws.work;                 // D x r
+  double2 *t1 = y + D * r;              // D x r
+  double2 *Uh = t1 + D * r;             // D x r Householder vectors (global fallback)
+  double2 *Yc = Uh + D * r;             // D x r
+  double2 *Vj = Yc + D * r;             // D x D eigensolver scratch (global fallback)
+  double2 *Kg = Vj + D * D;             // D x D stage matrix (global fallback)
+  double2 *X11 = Kg + D * D;            // r x r
+  double2 *Gr = X11 + rr;               // r x r
+  double2 *tmp = Gr + rr;               // r x r
+  double2 *Lw = tmp + rr;               // r x r Lowdin factor
+  double *flags = ws.flags;             // [D] dropped directions
+  double *stats = ws.stats;
+  const int arena = p.lds_elems;
+  const int k1 = (j + 2) * r;
+  if (threadIdx.x == 0) {
+    pc.mark = now_ticks();
+    for (int k = 3; k < 8; ++k) pc.acc[k] = 0.0;
+    for (int k = 0; k < 7; ++k) sh.ts.tacc[k] = 0.0;
+  }
+  auto lap = [&](int slot) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const uint64_t t = now_ticks();
+      pc.acc[slot] += (double)(t - pc.mark);
+      pc.mark = t;
+    }
+  };
+  for (int c = threadIdx.x; c < k1; c += NT) sh.drop[c] = flags[c] != 0.0;
+  __syncthreads();
   // ---- u_1 = R[:, :r] (Lowdin re-orthonormalised), at the first stage -------------
   double2 *u1 = ws.stage;  // stage 0, slot u
   if (j == 0) {
@@ -1717,7 +1774,6 @@ __device__ __forceinline__ void small_rk_body(const SmallRkParams &p, const Smal
     zgemm(y, r, R, D, false, Yc, r, mo, r, mo);
     for (int e = threadIdx.x; e < mo * r; e += NT)
       if (sh.drop[e / r]) y[e] = make_double2(0, 0);
-    __syncthreads();
     lap(3);
     rhs_coords(u, y, mo, D, r, mc, p.householder_mode, z, w, Gr, X11, t1, Uh, Yc, s_arena, arena, sh,
                j == 0 ? &stats[5] : nullptr);
@@ -1753,12 +1809,22 @@ __device__ __forceinline__ void small_rk_body(const SmallRkParams &p, const Smal
     bool solved = false;
     if (p.warm == LREI_WARM_ANALYTIC && jl && K == s_arena && warm_fits(m, r, arena)) {
       // subspace iteration from the stage's input basis u, in the LDS arena
-      // after K (over the direct solver's scratch, which it rebuilds if it runs)
-      int its = 0;
-      solved = warm_top(K, m, r, u, r, unext, r, D, s_arena, arena, 10, p.warm_tol, sh.js, its);
-      if (threadIdx.x == 0) {
-        stats[solved ? 9 : 31] += 1;
-        stats[12] += its;
+      // after K (over the direct solver's scratch, which it rebuilds if it
+      // runs).  A stage whose last attempt was rejected goes to the direct
+      // solver for the next kWarmRetry steps: the spectrum of a stage matrix
+      // changes little from one step to the next.
+      const double skip = ws.warm_skip[j];
+      __syncthreads();  // every thread has read the counter before it changes
+      if (skip > 0.0) {
+        if (threadIdx.x == 0) ws.warm_skip[j] = skip - 1.0;
+      } else {
+        int its = 0;
+        solved = warm_top(K, m, r, u, r, unext, r, D, s_arena, arena, 10, p.warm_tol, sh.js, its);
+        if (threadIdx.x == 0) {
+          stats[solved ? 9 : 31] += 1;
+          stats[12] += its;
+          ws.warm_skip[j] = solved ? 0.0 : (double)kWarmRetry;
+        }
       }
     }
     if (!solved) eig_top(K, m, r, unext, r, D, scr, jl, sh.ts);
@@ -1782,7 +1848,7 @@ __device__ __forceinline__ void small_rk_body(const SmallRkParams &p, const Smal
     bad = __syncthreads_or(bad_local);
   }
   if (threadIdx.x == 0) {
-    for (int k = 0; k < 8; ++k) stats[16 + k] += s_tacc[k] * 1e-5;  // ms
+    for (int k = 3; k < 8; ++k) stats[16 + k] += pc.acc[k] * 1e-5;  // ms
     for (int k = 0; k < 4; ++k) stats[24 + k] += sh.ts.tacc[k] * 1e-5;
     stats[29] += sh.ts.tacc[5] * 1e-5;
     stats[30] += sh.ts.tacc[6] * 1e-5;
@@ -1800,16 +1866,33 @@ __device__ __forceinline__ void small_rk_body(const SmallRkParams &p, const Smal
   }
 }
 
-__global__ __launch_bounds__(NT) void k_small_rk(SmallRkParams p, SmallWs ws, int j) {
+// Basis extension of stage j (one workgroup).
+__global__ __launch_bounds__(NT) void k_small_rk_basis(SmallRkParams p, SmallWs ws, int j) {
   extern __shared__ __align__(16) double2 s_arena[];
-  small_rk_body(p, ws, j, s_arena);
+  __shared__ StepShared sh;
+  __shared__ PhaseClock pc;
+  rk_basis(p, ws, j, s_arena, sh, pc);
 }
 
-// One workgroup per job of a batch.
+// Stage j after its basis extension (one workgroup).
+__global__ __launch_bounds__(NT) void k_small_rk(SmallRkParams p, SmallWs ws, int j) {
+  extern __shared__ __align__(16) double2 s_arena[];
+  __shared__ StepShared sh;
+  __shared__ PhaseClock pc;
+  rk_stage(p, ws, j, s_arena, sh, pc);
+}
+
+// One workgroup per job of a batch: extension and stage in one launch.
 __global__ __launch_bounds__(NT) void k_small_rk_batch(const SmallRkParams *__restrict__ ps,
                                                       const SmallWs *__restrict__ wss, int j) {
   extern __shared__ __align__(16) double2 s_arena[];
-  small_rk_body(ps[blockIdx.x], wss[blockIdx.x], j, s_arena);
+  __shared__ StepShared sh;
+  __shared__ PhaseClock pc;
+  const SmallRkParams &p = ps[blockIdx.x];
+  const SmallWs &ws = wss[blockIdx.x];
+  rk_basis(p, ws, j, s_arena, sh, pc);
+  __syncthreads();  // the stage reads the flags, R and R^{-1} the extension wrote
+  rk_stage(p, ws, j, s_arena, sh, pc);
 }
 
 void launch_small_rk_stage_batch(const SmallRkParams *p, const SmallWs *ws, int n_jobs, int lds_elems, int j,
@@ -1823,24 +1906,35 @@ void launch_small_rk_stage_batch(const SmallRkParams *p, const SmallWs *ws, int 
   hipLaunchKernelGGL(k_small_rk_batch, dim3(n_jobs), dim3(NT), (size_t)lds_elems * sizeof(double2), s, p, ws, j);
 }
 
-void launch_small_rk(const SmallRkParams &p, const SmallWs &ws, hipStream_t s) {
+namespace {
+void small_rk_attrs() {
   static bool attr = false;
   if (!attr) {
     (void)hipFuncSetAttribute((const void *)k_small_rk, hipFuncAttributeMaxDynamicSharedMemorySize,
                               kSmallLdsBytes);
+    (void)hipFuncSetAttribute((const void *)k_small_rk_basis, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              kSmallLdsBytes);
     attr = true;
   }
+}
+}  // namespace
+
+void launch_small_rk(const SmallRkParams &p, const SmallWs &ws, hipStream_t s) {
+  small_rk_attrs();
   const size_t lds = (size_t)p.lds_elems * sizeof(double2);
-  for (int j = 0; j < p.s; ++j) hipLaunchKernelGGL(k_small_rk, dim3(1), dim3(NT), lds, s, p, ws, j);
+  for (int j = 0; j < p.s; ++j) {
+    hipLaunchKernelGGL(k_small_rk_basis, dim3(1), dim3(NT), lds, s, p, ws, j);
+    hipLaunchKernelGGL(k_small_rk, dim3(1), dim3(NT), lds, s, p, ws, j);
+  }
+}
+
+void launch_small_rk_basis(const SmallRkParams &p, const SmallWs &ws, int j, hipStream_t s) {
+  small_rk_attrs();
+  hipLaunchKernelGGL(k_small_rk_basis, dim3(1), dim3(NT), (size_t)p.lds_elems * sizeof(double2), s, p, ws, j);
 }
 
 void launch_small_rk_stage(const SmallRkParams &p, const SmallWs &ws, int j, hipStream_t s) {
-  static bool attr = false;
-  if (!attr) {
-    (void)hipFuncSetAttribute((const void *)k_small_rk, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              kSmallLdsBytes);
-    attr = true;
-  }
+  small_rk_attrs();
   hipLaunchKernelGGL(k_small_rk, dim3(1), dim3(NT), (size_t)p.lds_elems * sizeof(double2), s, p, ws, j);
 }
 
@@ -1921,7 +2015,7 @@ __global__ __launch_bounds__(NT) void k_small_ab(SmallAbParams p, SmallAbWs ws) 
   }
   __syncthreads();
   chol_drop(G, D, G, D + 1, R, D, D, s_arena, arena, sh.drop, sh);
-  upper_inverse(R, D, Ri, D, D);
+  upper_inverse(R, D, Ri, D, D, s_arena, arena);
 
   // ---- coordinates in the orthonormal basis B R^{-1}
   // of a vector held as U-coordinates x (DU x r): R[:, :DU] x
