@@ -70,12 +70,22 @@ typedef enum { LREI_FP64 = 0, LREI_MIXED = 1 } lrei_precision;
  *  LREI_WARM_PLAIN: direct solve (Householder tridiagonalisation, multisection,
  *    inverse iteration), exact to FP64 rounding whatever the start.
  *  LREI_WARM_ANALYTIC: subspace iteration started from the stage's input basis
- *    (the predicted eigenvectors), accepted only with a certificate that its
+ *    u (the predicted eigenvectors), accepted only with a certificate that its
  *    r Ritz values are the r largest eigenvalues, else the direct solve.
- *  LREI_WARM_LEARNED: a start rotation proposed by a trained network; not
- *    provided (an r x r rotation of the start leaves the iterated subspace,
- *    and so the result and the iteration count, unchanged); rejected. */
-typedef enum { LREI_WARM_PLAIN = 0, LREI_WARM_ANALYTIC = 1, LREI_WARM_LEARNED = 2 } lrei_warm;
+ *  LREI_WARM_PREDICT_IDENTITY, LREI_WARM_PREDICT_CAYLEY, LREI_WARM_LEARNED:
+ *    the same iteration and judge, started from the first-order predictor
+ *    Y0 = u R + (I - u u*) K u R Lambda^-1 built from an r x r rotation R:
+ *    R = I; R = Cayley(-i s G) with G = u* H u and s the stage's step over
+ *    hbar; or R from the network attached with lrei_attach_net (features G,
+ *    s, kappa).  Only R's effect through Lambda^-1 changes the start's span.
+ *    The three need r <= 16; the batch context accepts PLAIN and ANALYTIC. */
+typedef enum {
+  LREI_WARM_PLAIN = 0,
+  LREI_WARM_ANALYTIC = 1,
+  LREI_WARM_LEARNED = 2,
+  LREI_WARM_PREDICT_IDENTITY = 3,
+  LREI_WARM_PREDICT_CAYLEY = 4
+} lrei_warm;
 
 typedef struct {
   int precision;          /* lrei_precision, default LREI_FP64                           */
@@ -98,11 +108,12 @@ typedef struct {
 typedef struct {
   int64_t steps_done;            /* time steps completed on this context               */
   int64_t eigensolves;           /* projected eigensolves performed                    */
-  int64_t warm_accepted;         /* eigensolves done by subspace iteration from the
-                                    stage's input basis (LREI_WARM_ANALYTIC)           */
+  int64_t warm_accepted;         /* eigensolves done by the warm-started subspace
+                                    iteration (every mode but LREI_WARM_PLAIN)         */
   int64_t warm_rejected;         /* of those, the ones that fell back to the direct
                                     solver (no convergence or no certificate)          */
-  int64_t warm_iterations;       /* subspace iterations run                             */
+  int64_t warm_iterations;       /* stage-matrix block products of the warm start
+                                    (subspace iterations, plus one per predictor)      */
   int32_t dropped_directions;    /* Krylov directions dropped as dependent (last step)  */
   int32_t reserved;
   double min_pivot_ratio;        /* smallest Cholesky pivot / Gram diagonal (last step) */
@@ -283,6 +294,71 @@ LREI_API lrei_status lrei_batch_profile_kernels(lrei_batch *b, int scheme, doubl
 
 /* Blocks until all work queued by the batch has finished. */
 LREI_API lrei_status lrei_batch_synchronize(lrei_batch *b);
+
+/* ---- Learned start rotation (production form on top of the stage
+ * eigensolve of Sec. 3.6; the paper has no such component) ----------------
+ *
+ * A network (lrei_net) is a multilayer perceptron for one rank r (1..16): 2 r^2 + 2 inputs
+ * (Re, Im of G / |G|_F with G = u* H u the stage input basis' projected
+ * generator, s |G|_F with s the stage's step over hbar, kappa), three hidden
+ * layers of width 256 with SiLU, r^2 outputs parametrising a skew-Hermitian
+ * A (A_aa = i o_a, then the upper off-diagonal entries row by row as
+ * (re, im) pairs), and R = (I - A/2)^{-1} (I + A/2).  Parameters: one FP32
+ * vector, W1 [in x 256] row-major, b1, W2, b2, W3, b3, W4 [256 x r^2], b4.
+ *
+ * A training sample (net_sample_floats(r) = 2 r^2 + 2 + 2 r^2 floats) is the
+ * features of one RK stage followed by T = u* u_next, r x r row-major (re, im)
+ * pairs, u_next the stage's output eigenvectors.  The loss of a sample is
+ * sum_a (1 - |(R* T)_aa|^2).  Sample buffers are device memory of the
+ * caller; every call below is synchronous. */
+typedef struct lrei_net lrei_net;
+
+/* Number of parameters of a network of rank r, or -1 if r is out of range. */
+LREI_API long long lrei_net_param_count(int r);
+
+/* New network on HIP device hip_device.  init: host array of
+ * lrei_net_param_count(r) floats, or NULL for a seeded initialisation
+ * (weights uniform in +-1/sqrt(fan_in), the output layer's times 0.1, zero
+ * biases; splitmix64 from seed).  Errors: LREI_E_INVALID (r), LREI_E_DEVICE,
+ * LREI_E_NOMEM; *out is NULL then. */
+LREI_API lrei_status lrei_net_create(lrei_net **out, int hip_device, int r, const float *init, uint64_t seed);
+LREI_API void lrei_net_destroy(lrei_net *m);
+LREI_API const char *lrei_net_last_error(const lrei_net *m);
+LREI_API int lrei_net_rank(const lrei_net *m);
+
+/* Copies of the parameters to / from host memory (set also resets Adam). */
+LREI_API lrei_status lrei_net_get_params(lrei_net *m, float *host);
+LREI_API lrei_status lrei_net_set_params(lrei_net *m, const float *host);
+
+/* Mean loss over the n (1..65536) samples at device address samples and, if
+ * grad_host is not NULL, its gradient with respect to the parameters. */
+LREI_API lrei_status lrei_net_loss_grad(lrei_net *m, const float *samples, int n, double *loss_out,
+                                          float *grad_host);
+
+/* The network's rotations for the features of n samples: R_host receives
+ * n r x r complex matrices, row-major, as (re, im) doubles. */
+LREI_API lrei_status lrei_net_rotations(lrei_net *m, const float *samples, int n, double *R_host);
+
+/* Adam (beta 0.9, 0.999, eps 1e-8, step size lr) over `epochs` passes of the
+ * n samples in batches of `batch` (1..4096; a last partial batch is skipped),
+ * reshuffled per epoch from shuffle_seed.  epoch_loss (host, `epochs`
+ * doubles, or NULL) receives each epoch's mean loss before its updates. */
+LREI_API lrei_status lrei_net_train(lrei_net *m, const float *samples, int n, int batch, int epochs, float lr,
+                                      uint64_t shuffle_seed, double *epoch_loss);
+
+/* Recording of training samples by a context's RK steps: every stage whose
+ * rank is <= 16 appends one sample to `samples` (device memory, room for
+ * `capacity` samples of the context's rank) until it is full; capacity 0
+ * stops recording.  The count restarts at 0 with each call. */
+LREI_API lrei_status lrei_record(lrei_ctx *ctx, float *samples, int capacity);
+/* Samples written so far (at most the capacity). */
+LREI_API lrei_status lrei_record_count(lrei_ctx *ctx, int *count);
+
+/* Attaches a network (its rank must equal the context's) for LREI_WARM_LEARNED;
+ * NULL detaches.  The context reads the network's parameters while stepping,
+ * so the network must outlive the attachment; training it in between changes
+ * what the next steps use. */
+LREI_API lrei_status lrei_attach_net(lrei_ctx *ctx, const lrei_net *m);
 
 #ifdef __cplusplus
 }

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["terms.cpp", "nspace.hip", "blocks.hip", "small.hip", "api.hip", "batch.hip"]
+SOURCES = ["terms.cpp", "nspace.hip", "blocks.hip", "small.hip", "api.hip", "batch.hip", "learned.hip"]
 LIB = os.path.join(HERE, "liblrei.so")
 
 FLAGS = [

@@ -55,6 +55,13 @@ struct lrei_ctx {
   DevBuf acc;                     // partial sums between sweeps
   DevBuf sched;                   // H.V tile-scheduling counters (16 ints, zero between launches)
 
+  // learned start rotation: attached network, training-sample recorder
+  const float *net = nullptr;
+  int net_r = 0;
+  float *rec = nullptr;
+  int rec_cap = 0;
+  DevBuf rec_count;               // one int
+
   // state
   bool have_rho = false;
   int r = 0;
@@ -343,6 +350,10 @@ SmallRkParams rk_params(lrei_ctx *ctx, int model, int scheme, double dt, double 
   p.householder_mode = ctx->opt.householder_mode;
   p.max_sweeps = ctx->opt.eig_max_sweeps;
   p.warm = ctx->opt.warm;
+  p.net = ctx->net;
+  p.rec = ctx->rec_cap > 0 ? ctx->rec : nullptr;
+  p.rec_count = (int *)ctx->rec_count.p;
+  p.rec_cap = ctx->rec_cap;
   p.kappa = kappa;
   p.hbar = ctx->hbar;
   p.h = dt;
@@ -664,7 +675,7 @@ lrei_status lrei_create(lrei_ctx **out, int hip_device, void *hip_stream, const 
     return LREI_E_INVALID;
   }
   if (!(ctx->opt.eig_tol > 0) || ctx->opt.eig_max_sweeps < 1 ||
-      (ctx->opt.warm != LREI_WARM_PLAIN && ctx->opt.warm != LREI_WARM_ANALYTIC)) {
+      ctx->opt.warm < LREI_WARM_PLAIN || ctx->opt.warm > LREI_WARM_PREDICT_CAYLEY) {
     delete ctx;
     return LREI_E_INVALID;
   }
@@ -735,6 +746,43 @@ void lrei_destroy(lrei_ctx *ctx) {
 }
 
 const char *lrei_last_error(const lrei_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+lrei_status lrei_record(lrei_ctx *ctx, float *samples, int capacity) {
+  if (!ctx) return LREI_E_INVALID;
+  if (capacity < 0 || (capacity > 0 && !samples)) return ctx->fail(LREI_E_INVALID, "invalid sample buffer");
+  (void)hipSetDevice(ctx->device);
+  if (!ctx->rec_count.ensure(sizeof(int))) return ctx->fail(LREI_E_NOMEM, "device allocation failed");
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e == hipSuccess) e = hipMemset(ctx->rec_count.p, 0, sizeof(int));
+  if (e != hipSuccess) return ctx->fail(LREI_E_DEVICE, std::string("record: ") + hipGetErrorString(e));
+  ctx->rec = capacity > 0 ? samples : nullptr;
+  ctx->rec_cap = capacity;
+  ctx->drop_graph();  // the recorder is a launch argument of the stage kernel
+  return LREI_OK;
+}
+
+lrei_status lrei_record_count(lrei_ctx *ctx, int *count) {
+  if (!ctx || !count) return LREI_E_INVALID;
+  *count = 0;
+  if (!ctx->rec_count.p) return LREI_OK;
+  (void)hipSetDevice(ctx->device);
+  int c = 0;
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e == hipSuccess) e = hipMemcpy(&c, ctx->rec_count.p, sizeof(int), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return ctx->fail(LREI_E_DEVICE, std::string("record count: ") + hipGetErrorString(e));
+  *count = std::min(c, ctx->rec_cap);
+  return LREI_OK;
+}
+
+lrei_status lrei_attach_net(lrei_ctx *ctx, const lrei_net *m) {
+  if (!ctx) return LREI_E_INVALID;
+  if (m && ctx->have_rho && lrei_net_rank(m) != ctx->r)
+    return ctx->fail(LREI_E_INVALID, "the network's rank differs from the state's");
+  ctx->net = m ? (const float *)lrei_net_device_params(m) : nullptr;
+  ctx->net_r = m ? lrei_net_rank(m) : 0;
+  ctx->drop_graph();
+  return LREI_OK;
+}
 
 lrei_status lrei_set_hamiltonian(lrei_ctx *ctx, int n_spins, int n_bonds, const int32_t *bond_ij,
                                  const double *bond_J, const double *site_h, double hbar) {
@@ -904,6 +952,8 @@ lrei_status lrei_step(lrei_ctx *ctx, int model, int scheme, double dt, double ka
   if (!(dt > 0) || !std::isfinite(dt)) return ctx->fail(LREI_E_INVALID, "dt must be positive and finite");
   if (!(kappa >= 0) || !std::isfinite(kappa)) return ctx->fail(LREI_E_INVALID, "kappa must be >= 0 and finite");
   if (n_steps < 0) return ctx->fail(LREI_E_INVALID, "n_steps must be >= 0");
+  if (!is_ab && ctx->opt.warm == LREI_WARM_LEARNED && (!ctx->net || ctx->net_r != ctx->r))
+    return ctx->fail(LREI_E_STATE, "LREI_WARM_LEARNED needs an attached network of the state's rank");
   if (is_ab) {
     const int m = ab_order(scheme);
     if (ctx->r > 16) return ctx->fail(LREI_E_INVALID, "AB schemes support r <= 16");

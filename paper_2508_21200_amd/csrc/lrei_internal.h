@@ -180,6 +180,12 @@ struct SmallRkParams {
   double a[kMaxStages][kMaxStages];
   double b[kMaxStages];
   double lam[kMaxR];
+  // learned start rotation: network parameters (LREI_WARM_LEARNED) and the
+  // training-sample recorder (rec == nullptr: off)
+  const float *net;
+  float *rec;
+  int *rec_count;
+  int rec_cap;
 };
 
 // Device layout of the small workspace (doubles).
@@ -254,3 +260,6 @@ void launch_ab_cgs_coef(const double2 *c1g, int nU, int qx, int r, double2 *C, h
 int cheb_partial_splits(int r);
 
 }  // namespace lrei
+
+// Device address of a model's parameters (learned.hip).
+extern "C" const void *lrei_net_device_params(const lrei_net *m);

@@ -29,6 +29,7 @@
 #include <hip/hip_runtime.h>
 
 #include "lrei_internal.h"
+#include "learned_dev.h"
 
 namespace lrei {
 
@@ -959,9 +960,9 @@ __device__ inline bool warm_fits(int m, int r, int arena_elems) {
 // must hold K (npl words), then X, Y (m x r) and G, C (r x r); after the
 // certificate the small eigenproblem's scratch goes after C if it fits there,
 // else over K.  iters: iterations run.
-__device__ bool warm_top(double2 *K, int m, int r, const double2 *S, int lds_in, double2 *u, int ldu,
+__device__ __forceinline__ bool warm_top(double2 *K, int m, int r, const double2 *S, int lds_in, double2 *u, int ldu,
                          int rows_out, double2 *arena, int arena_elems, int maxit, double tol, JacobiShared &js,
-                         int &iters) {
+                         int &iters, const double2 *rot = nullptr, const double *lam = nullptr) {
   __shared__ double red[NW];
   __shared__ double s_lb[kMaxR];
   __shared__ int s_flag;
@@ -973,6 +974,26 @@ __device__ bool warm_top(double2 *K, int m, int r, const double2 *S, int lds_in,
   double kd = 0;
   for (int i = threadIdx.x; i < m; i += NT) kd += cabs2(K[pl(i, i, m)]);
   const double kn2 = 2.0 * block_sum(kp, red) - block_sum(kd, red);  // ends with a barrier: X is visible
+  int pre = 0;  // block products spent on the start
+  if (rot) {
+    // first-order predictor in the rotated basis (one block product):
+    // X <- orth(S R + (I - S S*) K S R diag(1 / lam))
+    zgemm(X, r, S, lds_in, false, rot, r, m, r, r);  // X = S R
+    hemm_packed(Y, K, m, X, r);                      // Y = K X
+    zgemm(C, r, S, lds_in, true, Y, r, r, r, m);     // C = S* Y
+    for (int e = threadIdx.x; e < m * r; e += NT) {
+      const int i = e / r, a = e % r;
+      double2 v = Y[e];
+      for (int c = 0; c < r; ++c) v = csub(v, cmul(S[i * lds_in + c], C[c * r + a]));
+      X[e] = cadd(X[e], cscale(1.0 / lam[a], v));
+    }
+    __syncthreads();
+    pre = 1;
+    if (!polar_ns(X, Y, m, r, C, red, &s_flag) && !chol_qr(X, m, r, C)) {
+      iters = pre;
+      return false;
+    }
+  }
   double prev = 0, res2 = 0, g2 = 0;
   bool conv = false;
   int it = 0;
@@ -999,7 +1020,7 @@ __device__ bool warm_top(double2 *K, int m, int r, const double2 *S, int lds_in,
       const double q = sqrt(res2 / prev);
       const double need = q < 1.0 ? log(sqrt(tol2 * g2 / res2)) / log(q) : 1e30;
       if (!(need <= (double)(maxit - it - 1))) {
-        iters = it + 1;
+        iters = pre + it + 1;
         return false;
       }
     }
@@ -1011,11 +1032,11 @@ __device__ bool warm_top(double2 *K, int m, int r, const double2 *S, int lds_in,
     }
     __syncthreads();
     if (!polar_ns(X, Y, m, r, C, red, &s_flag) && !chol_qr(X, m, r, C)) {
-      iters = it + 1;
+      iters = pre + it + 1;
       return false;
     }
   }
-  iters = it + (conv ? 1 : 0);
+  iters = pre + it + (conv ? 1 : 0);
   if (!conv) return false;
   // certificate (K still intact for the direct solver if it fails)
   {
@@ -1569,6 +1590,106 @@ __device__ void householder_qr(double2 *M, int m, int q, double2 *Q, double2 *Rm
 // steps a stage goes to the direct eigensolver after a rejected warm start
 constexpr int kWarmRetry = 8;
 
+// ---- learned start rotation: features and rotation of a stage -------------
+//
+// Stage j maps its input basis u (the state at c_in h, c_in = sum_l a_jl) to
+// the eigenvectors of its stage matrix (the state at c_out h, c_out =
+// sum_l a_{j+1,l}, or sum_l b_l at the last stage); s = (c_out - c_in) h /
+// hbar is the step the in-span rotation covers.  Features: Re, Im of G / |G|_F
+// (G = Herm(u* y), y = H u), s |G|_F, kappa.
+
+__device__ double stage_step(const SmallRkParams &p, int j) {
+  double cin = 0, cout = 0;
+  for (int l = 0; l < p.s; ++l) {
+    cin += j > 0 ? p.a[j][l] : 0.0;
+    cout += (j + 1 == p.s) ? p.b[l] : p.a[j + 1][l];
+  }
+  return (cout - cin) * p.h / p.hbar;
+}
+
+// G (r x r, Hermitian part of Gu = u* y, global) -> features f (2 r^2 + 2, LDS).
+__device__ __forceinline__ void stage_features(const SmallRkParams &p, int j, const double2 *Gu, int r,
+                                                       float *f, double *s_nrm) {
+  if (threadIdx.x == 0) {
+    double n2 = 0;
+    for (int a = 0; a < r; ++a)
+      for (int b = 0; b < r; ++b) {
+        const double2 x = Gu[a * r + b], y = Gu[b * r + a];
+        const double gr = 0.5 * (x.x + y.x), gi = 0.5 * (x.y - y.y);
+        n2 += gr * gr + gi * gi;
+      }
+    *s_nrm = sqrt(n2);
+  }
+  __syncthreads();
+  const double nrm = *s_nrm, inv = nrm > 0 ? 1.0 / nrm : 0.0;
+  for (int e = threadIdx.x; e < r * r; e += NT) {
+    const int a = e / r, b = e % r;
+    const double2 x = Gu[a * r + b], y = Gu[b * r + a];
+    f[e] = (float)(0.5 * (x.x + y.x) * inv);
+    f[r * r + e] = (float)(0.5 * (x.y - y.y) * inv);
+  }
+  if (threadIdx.x == 0) {
+    f[2 * r * r] = (float)(stage_step(p, j) * nrm);
+    f[2 * r * r + 1] = (float)p.kappa;
+  }
+  __syncthreads();
+}
+
+// Scratch of the rotation at the arena's start, in floats (every region a
+// multiple of 4 floats, so the FP64 regions stay 16-byte aligned): features,
+// two hidden layers, NT partial sums, r^2 outputs, then [I - A/2 | I] and R.
+struct RotScratch {
+  int f, h0, h1, part, out, aug, R, total;
+};
+__device__ inline RotScratch rot_scratch(int r) {
+  RotScratch q;
+  q.f = 0;
+  q.h0 = 4 * ((net_in(r) + 3) / 4);
+  q.h1 = q.h0 + kNetWidth;
+  q.part = q.h1 + kNetWidth;
+  q.out = q.part + NT;
+  q.aug = q.out + 4 * ((r * r + 3) / 4);
+  q.R = q.aug + 4 * 2 * r * r;
+  q.total = q.R + 4 * r * r;
+  return q;
+}
+
+// The predictor's rotation R (r x r, written to Rg in global memory): I,
+// Cayley(-i s G), or the network's.  ar: the arena (features at its start).
+// Ends with a barrier.
+__device__ __attribute__((noinline)) void stage_rotation(const SmallRkParams &p, int j, const double2 *Gu, int r,
+                                                       float *ar, double2 *Rg) {
+  const RotScratch q = rot_scratch(r);
+  float *f = ar + q.f, *h0 = ar + q.h0, *h1 = ar + q.h1, *part = ar + q.part, *out = ar + q.out;
+  double2 *aug = reinterpret_cast<double2 *>(ar + q.aug), *R = reinterpret_cast<double2 *>(ar + q.R);
+  if (p.warm == LREI_WARM_LEARNED) {
+    net_forward_wg(p.net, r, f, h0, h1, part, out, NT);
+  } else if (p.warm == LREI_WARM_PREDICT_CAYLEY) {
+    // A = -i s G: o_a = -s G_aa; upper pairs (re, im) = (s Im G_ab, -s Re G_ab)
+    const double st = stage_step(p, j);
+    for (int e = threadIdx.x; e < r * r; e += NT) {
+      const int a = e / r, b = e % r;
+      const double2 x = Gu[a * r + b], y = Gu[b * r + a];
+      const double gr = 0.5 * (x.x + y.x), gi = 0.5 * (x.y - y.y);
+      if (a == b) {
+        out[a] = (float)(-st * gr);
+      } else if (a < b) {
+        const int k = r + 2 * (a * r - a * (a + 1) / 2 + (b - a - 1));
+        out[k] = (float)(st * gi);
+        out[k + 1] = (float)(-st * gr);
+      }
+    }
+    __syncthreads();
+  } else {
+    for (int e = threadIdx.x; e < r * r; e += NT) out[e] = 0.0f;  // A = 0: R = I
+    __syncthreads();
+  }
+  if (threadIdx.x < 64) cayley_wave(out, r, aug, R, nullptr);
+  __syncthreads();
+  for (int e = threadIdx.x; e < r * r; e += NT) Rg[e] = R[e];
+  __syncthreads();
+}
+
 struct PhaseClock {
   uint64_t mark;
   double acc[8];
@@ -1785,6 +1906,29 @@ __device__ __forceinline__ void rk_stage(const SmallRkParams &p, const SmallWs &
       if (threadIdx.x == 0 && stats[28] < 0 && (f1 | f2 | f3)) stats[28] = 10 * j + (f1 ? 1 : (f2 ? 2 : 3));
     }
     lap(4);
+    // learned start rotation: the stage's features (recorded as a training
+    // sample and/or fed to the network) and the predictor's rotation R (into
+    // tmp), in the arena before the stage matrix takes it
+    __shared__ int s_slot;
+    __shared__ double s_nrm;
+    const bool fits = r <= kNetMaxR && rot_scratch(r).total <= 4 * arena;
+    const bool record = p.rec != nullptr && fits;
+    const bool use_rot = fits && (p.warm == LREI_WARM_PREDICT_IDENTITY || p.warm == LREI_WARM_PREDICT_CAYLEY ||
+                                  (p.warm == LREI_WARM_LEARNED && p.net != nullptr));
+    if (use_rot || record) {
+      float *ar = reinterpret_cast<float *>(s_arena);
+      stage_features(p, j, Gr, r, ar, &s_nrm);
+      if (record) {
+        if (threadIdx.x == 0) s_slot = atomicAdd(p.rec_count, 1);
+        __syncthreads();
+        if (s_slot < p.rec_cap) {
+          float *dst = p.rec + (size_t)s_slot * net_sample_floats(r);
+          for (int e = threadIdx.x; e < net_in(r); e += NT) dst[e] = ar[e];
+        }
+      }
+      if (use_rot) stage_rotation(p, j, Gr, r, ar, tmp);
+      __syncthreads();
+    }
     // stage matrix (eqs. 3.7-3.9) and its top-r eigenvectors
     const bool last = (j + 1 == s);
     const int m = mo;
@@ -1807,7 +1951,7 @@ __device__ __forceinline__ void rk_stage(const SmallRkParams &p, const SmallWs &
     }
     double2 *unext = last ? ws.Cfin /* temporary */ : ws.stage + (3 * (j + 1) + 0) * D * r;
     bool solved = false;
-    if (p.warm == LREI_WARM_ANALYTIC && jl && K == s_arena && warm_fits(m, r, arena)) {
+    if ((p.warm == LREI_WARM_ANALYTIC || use_rot) && jl && K == s_arena && warm_fits(m, r, arena)) {
       // subspace iteration from the stage's input basis u, in the LDS arena
       // after K (over the direct solver's scratch, which it rebuilds if it
       // runs).  A stage whose last attempt was rejected goes to the direct
@@ -1819,7 +1963,8 @@ __device__ __forceinline__ void rk_stage(const SmallRkParams &p, const SmallWs &
         if (threadIdx.x == 0) ws.warm_skip[j] = skip - 1.0;
       } else {
         int its = 0;
-        solved = warm_top(K, m, r, u, r, unext, r, D, s_arena, arena, 10, p.warm_tol, sh.js, its);
+        solved = warm_top(K, m, r, u, r, unext, r, D, s_arena, arena, 10, p.warm_tol, sh.js, its,
+                          use_rot ? tmp : nullptr, p.lam);
         if (threadIdx.x == 0) {
           stats[solved ? 9 : 31] += 1;
           stats[12] += its;
@@ -1828,6 +1973,14 @@ __device__ __forceinline__ void rk_stage(const SmallRkParams &p, const SmallWs &
       }
     }
     if (!solved) eig_top(K, m, r, unext, r, D, scr, jl, sh.ts);
+    if (record && s_slot < p.rec_cap) {  // training target T = u* u_next
+      zgemm(X11, r, u, r, true, unext, r, r, r, D);
+      float *dst = p.rec + (size_t)s_slot * net_sample_floats(r) + net_in(r);
+      for (int e = threadIdx.x; e < r * r; e += NT) {
+        dst[2 * e] = (float)X11[e].x;
+        dst[2 * e + 1] = (float)X11[e].y;
+      }
+    }
     {
       const int fe = any_nonfinite(unext, D * r);
       if (threadIdx.x == 0 && stats[28] < 0 && fe) stats[28] = 10 * j + 5;

@@ -14,12 +14,13 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblrei.so")
 
 LREI_OK = 0
+LREI_E_INVALID = 1
 STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_NOMEM", 3: "E_NOTCONVERGED", 4: "E_DEVICE",
                 5: "E_STATE", 6: "E_NUMERIC"}
 MODELS = {"qLL": 0, "qLLG": 1}
 SCHEMES = {"RK1": 1, "RK2": 2, "RK3": 3, "RK4": 4, "AB2": 12, "AB3": 13, "AB4": 14}
 PRECISIONS = {"fp64": 0, "mixed": 1}
-WARM = {"plain": 0, "analytic": 1, "learned": 2}
+WARM = {"plain": 0, "analytic": 1, "learned": 2, "predict_identity": 3, "predict_cayley": 4}
 
 
 class lrei_options(ctypes.Structure):
@@ -98,6 +99,20 @@ _SIGS = {
     "lrei_batch_energies": (ctypes.c_int, [_P, _P]),
     "lrei_batch_profile_kernels": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_double, ctypes.c_int, _P]),
     "lrei_batch_synchronize": (ctypes.c_int, [_P]),
+    "lrei_net_param_count": (ctypes.c_longlong, [ctypes.c_int]),
+    "lrei_net_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, ctypes.c_int, _P, ctypes.c_uint64]),
+    "lrei_net_destroy": (None, [_P]),
+    "lrei_net_last_error": (ctypes.c_char_p, [_P]),
+    "lrei_net_rank": (ctypes.c_int, [_P]),
+    "lrei_net_get_params": (ctypes.c_int, [_P, _P]),
+    "lrei_net_set_params": (ctypes.c_int, [_P, _P]),
+    "lrei_net_loss_grad": (ctypes.c_int, [_P, _P, ctypes.c_int, _P, _P]),
+    "lrei_net_rotations": (ctypes.c_int, [_P, _P, ctypes.c_int, _P]),
+    "lrei_net_train": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_float,
+                                      ctypes.c_uint64, _P]),
+    "lrei_record": (ctypes.c_int, [_P, _P, ctypes.c_int]),
+    "lrei_record_count": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int)]),
+    "lrei_attach_net": (ctypes.c_int, [_P, _P]),
 }
 
 
@@ -254,6 +269,114 @@ class Context:
 
     def synchronize(self):
         self._check(self.lib.lrei_synchronize(self.h))
+
+    def record(self, samples, capacity=None):
+        """Records a training sample per RK stage into `samples` (a device
+        float32 tensor of capacity x net_sample_floats(r)); None stops."""
+        if samples is None:
+            self._check(self.lib.lrei_record(self.h, None, 0))
+            self._rec = None
+            return
+        cap = samples.shape[0] if capacity is None else int(capacity)
+        p, dev = _ptr(samples)
+        if not dev:
+            raise LreiError(LREI_E_INVALID, "the sample buffer must be device memory")
+        self._check(self.lib.lrei_record(self.h, p, cap))
+        self._rec = samples
+
+    def record_count(self):
+        c = ctypes.c_int()
+        self._check(self.lib.lrei_record_count(self.h, ctypes.byref(c)))
+        return c.value
+
+    def attach_net(self, net):
+        """Network for warm="learned" (None detaches); it must outlive the attachment."""
+        self._check(self.lib.lrei_attach_net(self.h, None if net is None else net.h))
+        self._net = net
+
+
+def net_sample_floats(r):
+    return 4 * r * r + 2
+
+
+class Net:
+    """The learned start rotation's network for rank r (lrei_net_* entry points)."""
+
+    def __init__(self, r, device=0, params=None, seed=0):
+        self.lib = load()
+        self.r = int(r)
+        h = _P()
+        init = None
+        if params is not None:
+            init = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+            if init.size != self.param_count(self.r):
+                raise LreiError(LREI_E_INVALID, "wrong parameter count")
+        st = self.lib.lrei_net_create(ctypes.byref(h), int(device), self.r,
+                                      None if init is None else init.ctypes.data, int(seed))
+        if st != LREI_OK:
+            raise LreiError(st, "lrei_net_create failed")
+        self.h = h
+
+    @staticmethod
+    def param_count(r):
+        return int(load().lrei_net_param_count(int(r)))
+
+    def _check(self, st):
+        if st != LREI_OK:
+            raise LreiError(st, self.lib.lrei_net_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.lrei_net_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self):
+        out = np.zeros(self.param_count(self.r), dtype=np.float32)
+        self._check(self.lib.lrei_net_get_params(self.h, out.ctypes.data))
+        return out
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(np.asarray(p, dtype=np.float32))
+        if p.size != self.param_count(self.r):
+            raise LreiError(LREI_E_INVALID, "wrong parameter count")
+        self._check(self.lib.lrei_net_set_params(self.h, p.ctypes.data))
+
+    def loss_grad(self, samples, n=None, grad=True):
+        """Mean loss over the first n samples (device float32 tensor) and the gradient."""
+        n = samples.shape[0] if n is None else int(n)
+        loss = ctypes.c_double()
+        g = np.zeros(self.param_count(self.r), dtype=np.float32) if grad else None
+        p, dev = _ptr(samples)
+        if not dev:
+            raise LreiError(LREI_E_INVALID, "the samples must be device memory")
+        self._check(self.lib.lrei_net_loss_grad(self.h, p, n, ctypes.byref(loss),
+                                                None if g is None else g.ctypes.data))
+        return loss.value, g
+
+    def rotations(self, samples, n=None):
+        n = samples.shape[0] if n is None else int(n)
+        R = np.zeros((n, self.r, self.r), dtype=np.complex128)
+        p, dev = _ptr(samples)
+        if not dev:
+            raise LreiError(LREI_E_INVALID, "the samples must be device memory")
+        self._check(self.lib.lrei_net_rotations(self.h, p, n, R.ctypes.data))
+        return R
+
+    def train(self, samples, n=None, batch=256, epochs=10, lr=1e-3, seed=0):
+        n = samples.shape[0] if n is None else int(n)
+        losses = np.zeros(max(epochs, 1), dtype=np.float64)
+        p, dev = _ptr(samples)
+        if not dev:
+            raise LreiError(LREI_E_INVALID, "the samples must be device memory")
+        self._check(self.lib.lrei_net_train(self.h, p, n, int(batch), int(epochs), float(lr), int(seed),
+                                            losses.ctypes.data))
+        return losses[:epochs]
 
 
 class Batch:
