@@ -48,10 +48,34 @@ def parse():
     ap.add_argument("--kernels-only", action="store_true",
                     help="set up the workload and launch each kernel of a step eagerly, 20 times "
                          "(for rocprofv3 --pmc runs)")
+    ap.add_argument("--learned-report", action="store_true",
+                    help="train the learned start rotation on recorded n=14 chain stages and compare the "
+                         "eigensolve start modes on the n=22 chain (config 5); prints one JSON line")
+    ap.add_argument("--train-traj", type=int, default=100)
+    ap.add_argument("--train-steps", type=int, default=200)
+    ap.add_argument("--train-epochs", type=int, default=20)
+    ap.add_argument("--train-lr", type=float, nargs="+", default=[1e-6, 3e-7, 1e-7],
+                    help="Adam step sizes tried; the best on the validation trajectories is kept")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="run a plain device-to-device copy of MIB MiB five times and exit "
                          "(reference kernel for scaling FETCH_SIZE / WRITE_SIZE counters)")
     return ap.parse_args()
+
+
+def rel_fro(torch, V1, V2, lam):
+    """Relative Frobenius distance of V1 diag(lam) V1* and V2 diag(lam) V2*
+    (measurement helper).  With [V1, V2] = Q R the difference is
+    Q (R D R*) Q*, D = diag(lam, -lam), so its norm is |R D R*|_F, formed
+    without the cancellation of subtracting two nearly equal matrices."""
+    dev = "cuda"
+    W = torch.cat([torch.as_tensor(V1, device=dev), torch.as_tensor(V2, device=dev)], dim=1).to(torch.complex128)
+    la = torch.as_tensor(np.asarray(lam, dtype=np.float64), device=dev)
+    _, R = torch.linalg.qr(W, mode="r")
+    D = torch.cat([la, -la]).to(torch.complex128)
+    diff = torch.linalg.norm((R * D[None, :]) @ R.conj().T)
+    _, R2 = torch.linalg.qr(W[:, V1.shape[1]:], mode="r")
+    ref = torch.linalg.norm((R2 * la.to(torch.complex128)[None, :]) @ R2.conj().T)
+    return float(diff / ref)
 
 
 def source_digest():
@@ -115,6 +139,122 @@ def cpu_baseline_batch(trajs, budget_s=20.0):
     }
 
 
+def run_learned_report(args, torch):
+    """Learned start rotation against the other eigensolve starts.
+
+    Training data: RK4 stages of random XXZ chains (n = 14, r = 16, q-LLG,
+    couplings as the n = 22 workload, damping log-uniform in [0.01, 0.5]),
+    recorded by the library while stepping in FP64; the last tenth of the
+    trajectories is held out.  Evaluation: the n = 22 chain (config 5), RK4,
+    dt = 0.01, mixed precision, every start mode timed over the same steps and
+    compared with the FP64 direct-solve run."""
+    from paper_2508_21200_amd import Context, Net, net_sample_floats
+    from workloads import make_config
+
+    r, steps_per, n_traj = 16, args.train_steps, args.train_traj
+    sf = net_sample_floats(r)
+    buf = torch.zeros((4 * steps_per * n_traj, sf), dtype=torch.float32, device="cuda")
+    rng = np.random.default_rng(2024)
+    t0 = time.perf_counter()
+    total, bounds = 0, []
+    for t in range(n_traj):
+        cfg = make_config(5, traj=1000 + t, n=14)
+        kap = float(np.exp(rng.uniform(np.log(0.01), np.log(0.5))))
+        c = Context(precision="fp64")
+        c.set_hamiltonian(cfg["n"], cfg["bonds"], cfg["J"], cfg["h"])
+        c.set_rho(cfg["lam"], cfg["V"])
+        c.record(buf[total:])
+        c.step("qLLG", "RK4", 0.01, kap, steps_per)
+        total += c.record_count()
+        bounds.append(total)
+        c.close()
+        if t % 20 == 0:
+            print(f"[learned] recorded trajectory {t}: {total} samples", file=sys.stderr, flush=True)
+    t_rec = time.perf_counter() - t0
+    # trajectories split 80 / 10 / 10: training, validation (picks the step
+    # size), held-out test
+    n_tr, n_va = bounds[int(0.8 * n_traj) - 1], bounds[int(0.9 * n_traj) - 1]
+    train, val, held = buf[:n_tr], buf[n_tr:n_va], buf[n_va:total]
+
+    def excess(R, S):
+        """mean of loss(R) - loss(polar(T)) over samples S (host)."""
+        nin = 2 * r * r + 2
+        t = S[:, nin:].astype(np.float64)
+        T = (t[:, 0::2] + 1j * t[:, 1::2]).reshape(-1, r, r)
+        U, _, Wh = np.linalg.svd(T)
+        best = U @ Wh
+        d = lambda A: np.einsum("kca,kca->ka", np.conj(A), T)  # (A* T)_aa
+        return float(np.mean(np.sum(np.abs(d(best)) ** 2 - np.abs(d(R)) ** 2, axis=1)))
+
+    Sh, Sv = held.cpu().numpy(), val.cpu().numpy()
+    nin = 2 * r * r + 2
+    I = np.eye(r)
+    net = Net(r, seed=5)
+    p0 = net.params()
+    ex0 = excess(net.rotations(held), Sh)  # untrained: the analytic rotation
+    t1 = time.perf_counter()
+    sweep, best = [], None
+    for lr in args.train_lr:
+        net.set_params(p0)
+        losses = net.train(train, batch=256, epochs=args.train_epochs, lr=lr, seed=9)
+        ev = excess(net.rotations(val), Sv)
+        sweep.append({"lr": lr, "validation_excess": ev, "epoch_loss_first_last": [float(losses[0]),
+                                                                                   float(losses[-1])]})
+        if best is None or ev < best[1]:
+            best = (lr, ev, net.params())
+    net.set_params(best[2])
+    t_train = time.perf_counter() - t1
+    training = {"samples": int(n_tr), "validation": int(n_va - n_tr), "held_out": int(total - n_va),
+                "record_s": round(t_rec, 2), "train_s": round(t_train, 2), "epochs": args.train_epochs,
+                "lr_sweep": sweep, "lr": best[0],
+                "held_out_excess_loss": {"identity": excess(np.broadcast_to(I, (len(Sh), r, r)), Sh),
+                                         "analytic": ex0,
+                                         "network_trained": excess(net.rotations(held), Sh)}}
+    print(f"[learned] trained: {json.dumps(training)}", file=sys.stderr, flush=True)
+
+    cfg = make_config(5)
+    model, dt, kappa, steps, warm_steps = cfg["model"], cfg["dt"], cfg["kappa"], cfg["steps"], 2
+
+    def run(prec, warm):
+        c = Context(precision=prec, warm=warm, autotune_cache=args.tune_cache)
+        c.set_hamiltonian(cfg["n"], cfg["bonds"], cfg["J"], cfg["h"])
+        c.set_rho(cfg["lam"], cfg["V"])
+        if warm == "learned":
+            c.attach_net(net)
+        if not args.no_autotune:
+            c.autotune()
+        c.step(model, "RK4", dt, kappa, warm_steps)
+        c.synchronize()
+        s0 = c.stats()
+        a = time.perf_counter()
+        c.step(model, "RK4", dt, kappa, steps)
+        c.synchronize()
+        el = time.perf_counter() - a
+        s1 = c.stats()
+        V = c.get_rho()[1]
+        c.close()
+        de = {k: s1[k] - s0[k] for k in ("eigensolves", "warm_accepted", "warm_rejected", "warm_iterations")}
+        return V, el, de
+
+    Vref, _, _ = run("fp64", "plain")
+    modes = {}
+    for warm in ("plain", "analytic", "predict_identity", "predict_cayley", "learned"):
+        V, el, de = run("mixed", warm)
+        modes[warm] = {"ms_per_step": round(1e3 * el / steps, 4), "steps_per_s": round(steps / el, 2),
+                       "eigensolves": de["eigensolves"], "warm_accepted": de["warm_accepted"],
+                       "warm_rejected": de["warm_rejected"],
+                       "block_products_per_warm_solve": round(
+                           de["warm_iterations"] / max(1, de["warm_accepted"] + de["warm_rejected"]), 3),
+                       "rel_fro_vs_fp64_plain": rel_fro(torch, V, Vref, cfg["lam"])}
+        print(f"[learned] {warm}: {json.dumps(modes[warm])}", file=sys.stderr, flush=True)
+    net.close()
+    print(json.dumps({"report": "learned start rotation vs plain start",
+                      "workload": {"name": cfg["name"], "n": cfg["n"], "N": 2 ** cfg["n"], "r": cfg["r"],
+                                   "model": model, "kappa": kappa, "scheme": "RK4", "dt": dt,
+                                   "timed_steps": steps, "warmup_steps": warm_steps, "precision": "mixed"},
+                      "training": training, "modes": modes}))
+
+
 def run_batch(args, torch):
     """The batched workload: 64 independent XXZ-chain trajectories (n 12..16,
     r in {4, 8, 16}, half q-LL / half q-LLG, kappa log-uniform in [0.01, 1]),
@@ -154,12 +294,11 @@ def run_batch(args, torch):
     achieved = hv_bytes / (kms["hv_pass"] * 1e-3) / 1e9
     parity = None
     if not args.no_parity and precision == "mixed":
-        from oracle.metrics import rel_fro_error
         ref = Batch(trajs, precision="fp64")
         ref.step(scheme, dt, args.warmup + steps)
         worst = 0.0
         for q, t in enumerate(trajs):
-            worst = max(worst, rel_fro_error(b.get_rho(q)[1], t["lam"], ref.get_rho(q)[1], t["lam"]))
+            worst = max(worst, rel_fro(torch, b.get_rho(q)[1], ref.get_rho(q)[1], t["lam"]))
         parity = {"vs": "FP64 GPU batch, same inputs and step count", "rel_fro_worst_trajectory": worst}
         ref.close()
     cpu = None if args.no_cpu_baseline else cpu_baseline_batch(trajs)
@@ -209,6 +348,9 @@ def main():
         return
     if args.config == 4:
         run_batch(args, torch)
+        return
+    if args.learned_report:
+        run_learned_report(args, torch)
         return
     from paper_2508_21200_amd import Context
     from workloads import make_config
@@ -277,12 +419,11 @@ def main():
         if precision == "fp64":
             parity = {"vs": "self (fp64)", "rel_fro": 0.0}
         else:
-            from oracle.metrics import rel_fro_error
             ref = make_ctx("fp64")
             ref.step(model, scheme, dt, kappa, args.warmup + args.steps)
             _, Vr = ref.get_rho()
             parity = {"vs": "FP64 GPU path, same inputs and step count",
-                      "rel_fro": rel_fro_error(Vt, cfg["lam"], Vr, cfg["lam"])}
+                      "rel_fro": rel_fro(torch, Vt, Vr, cfg["lam"])}
             ref.close()
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(cfg)

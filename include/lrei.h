@@ -301,10 +301,12 @@ LREI_API lrei_status lrei_batch_synchronize(lrei_batch *b);
  * A network (lrei_net) is a multilayer perceptron for one rank r (1..16): 2 r^2 + 2 inputs
  * (Re, Im of G / |G|_F with G = u* H u the stage input basis' projected
  * generator, s |G|_F with s the stage's step over hbar, kappa), three hidden
- * layers of width 256 with SiLU, r^2 outputs parametrising a skew-Hermitian
- * A (A_aa = i o_a, then the upper off-diagonal entries row by row as
- * (re, im) pairs), and R = (I - A/2)^{-1} (I + A/2).  Parameters: one FP32
- * vector, W1 [in x 256] row-major, b1, W2, b2, W3, b3, W4 [256 x r^2], b4.
+ * layers of width 256 with SiLU, r^2 outputs o that correct the analytic
+ * generator -i s G: A is unpacked from o + o_an (A_aa = i o_a, then the
+ * upper off-diagonal entries row by row as (re, im) pairs; o_an the same
+ * parametrisation of -i s G read off the features), and
+ * R = (I - A/2)^{-1} (I + A/2).  Parameters: one FP32 vector, W1 [in x 256]
+ * row-major, b1, W2, b2, W3, b3, W4 [256 x r^2], b4.
  *
  * A training sample (net_sample_floats(r) = 2 r^2 + 2 + 2 r^2 floats) is the
  * features of one RK stage followed by T = u* u_next, r x r row-major (re, im)
@@ -318,8 +320,9 @@ LREI_API long long lrei_net_param_count(int r);
 
 /* New network on HIP device hip_device.  init: host array of
  * lrei_net_param_count(r) floats, or NULL for a seeded initialisation
- * (weights uniform in +-1/sqrt(fan_in), the output layer's times 0.1, zero
- * biases; splitmix64 from seed).  Errors: LREI_E_INVALID (r), LREI_E_DEVICE,
+ * (hidden-layer weights uniform in +-1/sqrt(fan_in), splitmix64 from seed;
+ * output layer and biases zero, so the new network gives the analytic
+ * rotation).  Errors: LREI_E_INVALID (r), LREI_E_DEVICE,
  * LREI_E_NOMEM; *out is NULL then. */
 LREI_API lrei_status lrei_net_create(lrei_net **out, int hip_device, int r, const float *init, uint64_t seed);
 LREI_API void lrei_net_destroy(lrei_net *m);

@@ -11,9 +11,12 @@ matrix).  What it computes, in the order the GPU path does:
   dimensionless step s |G|_F (s = c h / hbar, c the stage's step fraction) and
   the damping kappa: 2 r^2 + 2 reals;
 * a multilayer perceptron, three hidden layers of width 256 with SiLU
-  activations, whose r^2 outputs parametrise a skew-Hermitian A (r imaginary
-  diagonal entries, then the r (r - 1) / 2 upper off-diagonal entries as
-  (re, im) pairs, row by row);
+  activations, whose r^2 outputs o parametrise a skew-Hermitian correction
+  (r imaginary diagonal entries, then the r (r - 1) / 2 upper off-diagonal
+  entries as (re, im) pairs, row by row) to the analytic generator
+  -i s G: A = unpack(o + o_an(x)), o_an the same parametrisation of
+  -i s G read off the features (a network with zero output gives the
+  analytic rotation);
 * the Cayley map R = (I - A/2)^{-1} (I + A/2), a unitary r x r rotation;
 * the training target of a stage: T = u* u_next, the overlap of the input
   basis with the stage's output eigenvectors (u_next), and the loss
@@ -65,6 +68,23 @@ def features(G, step, kappa):
     nrm = np.linalg.norm(G)
     Gn = G / nrm if nrm > 0 else G
     return np.concatenate([Gn.real.ravel(), Gn.imag.ravel(), [step * nrm, kappa]])
+
+
+def analytic_params(x, r):
+    """r^2 reals of -i s G from the features x (G / |G| and s |G|)."""
+    x = np.asarray(x, dtype=np.float64)
+    sg = x[..., 2 * r * r]
+    gre = x[..., :r * r].reshape(x.shape[:-1] + (r, r))
+    gim = x[..., r * r:2 * r * r].reshape(x.shape[:-1] + (r, r))
+    o = np.zeros(x.shape[:-1] + (r * r,))
+    o[..., :r] = -sg[..., None] * np.diagonal(gre, axis1=-2, axis2=-1)
+    k = r
+    for a in range(r):
+        for b in range(a + 1, r):
+            o[..., k] = sg * gim[..., a, b]
+            o[..., k + 1] = -sg * gre[..., a, b]
+            k += 2
+    return o
 
 
 def unpack_skew(o, r):
@@ -130,6 +150,7 @@ def forward(params, X, r):
 
 def rotations(params, X, r):
     O, _, _ = forward(params, X, r)
+    O = O + analytic_params(X, r)
     return np.stack([cayley(unpack_skew(o, r)) for o in O])
 
 
@@ -151,8 +172,9 @@ def grad(params, X, T, r):
     gO = np.zeros_like(O)
     L = 0.0
     I = np.eye(r)
+    Oa = O + analytic_params(X, r)  # the analytic part does not depend on the parameters
     for k in range(B):
-        A = unpack_skew(O[k], r)
+        A = unpack_skew(Oa[k], r)
         M = I - A / 2
         R = np.linalg.solve(M, I + A / 2)
         s = np.einsum('ca,ca->a', np.conj(R), T[k])

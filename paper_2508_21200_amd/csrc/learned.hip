@@ -122,14 +122,18 @@ __global__ void k_gather(const float *__restrict__ samples, const int *__restric
 // One wave per sample: R = Cayley(A(o)), loss_b = sum_a (1 - |(R* T)_aa|^2),
 // gO_b = d(loss_b / B)/d o (through gA = M^{-H} gR (I + R)^H / 2,
 // gR = -2 T diag(conj s), s_a = (R* T)_aa).  Rout (optional): R as FP64 pairs.
-__global__ __launch_bounds__(64) void k_cayley_loss(const float *__restrict__ O, const float *__restrict__ T,
-                                                    int B, int r, float *__restrict__ gO,
-                                                    double *__restrict__ loss, double *__restrict__ Rout) {
+__global__ __launch_bounds__(64) void k_cayley_loss(const float *__restrict__ O, const float *__restrict__ X,
+                                                    const float *__restrict__ T, int B, int r,
+                                                    float *__restrict__ gO, double *__restrict__ loss,
+                                                    double *__restrict__ Rout) {
   __shared__ double2 aug[kNetMaxR * 2 * kNetMaxR], R[kNetMaxR * kNetMaxR], Mi[kNetMaxR * kNetMaxR];
   __shared__ double2 Tm[kNetMaxR * kNetMaxR], S[kNetMaxR], gA[kNetMaxR * kNetMaxR], Q[kNetMaxR * kNetMaxR];
+  __shared__ float o[kNetMaxR * kNetMaxR];
   const int b = blockIdx.x, lane = threadIdx.x, rr = r * r;
   if (b >= B) return;
-  const float *o = O + (long long)b * rr;
+  const float *x = X + (long long)b * net_in(r);
+  for (int e = lane; e < rr; e += 64) o[e] = O[(long long)b * rr + e] + analytic_param(x, r, e);
+  __builtin_amdgcn_wave_barrier();
   cayley_wave(o, r, aug, R, Mi);
   if (Rout)
     for (int e = lane; e < rr; e += 64) {
@@ -277,7 +281,7 @@ void batch_pass(lrei_net *m, int B, bool backward, double *Rout) {
   }
   gemm(B, rr, W, in, W, 0, L.W[3], rr, 0, (float *)m->O.p, rr, 0, nullptr, nullptr, nullptr, s);
   hipLaunchKernelGGL(k_add_bias, dim3((B * rr + 255) / 256), dim3(256), 0, s, (float *)m->O.p, L.b[3], B, rr);
-  hipLaunchKernelGGL(k_cayley_loss, dim3(B), dim3(64), 0, s, (const float *)m->O.p,
+  hipLaunchKernelGGL(k_cayley_loss, dim3(B), dim3(64), 0, s, (const float *)m->O.p, (const float *)m->X.p,
                      Rout ? (const float *)nullptr : (const float *)m->T.p, B, r, (float *)m->gO.p,
                      (double *)m->loss.p, Rout);
   if (!backward) return;
@@ -343,12 +347,13 @@ lrei_status lrei_net_create(lrei_net **out, int hip_device, int r, const float *
   if (init) {
     std::memcpy(p.data(), init, bytes);
   } else {
-    // uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)) weights (output layer x 0.1), zero biases
+    // hidden layers: uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)) weights; output
+    // layer zero (the untrained network gives the analytic rotation); zero biases
     uint64_t st = seed;
     long long off = 0;
     for (int l = 0; l < 4; ++l) {
       const int K = l == 0 ? net_in(r) : kNetWidth, N = l == 3 ? r * r : kNetWidth;
-      const double a = (l == 3 ? 0.1 : 1.0) / std::sqrt((double)K);
+      const double a = (l == 3 ? 0.0 : 1.0) / std::sqrt((double)K);
       for (long long i = 0; i < (long long)K * N; ++i) p[off + i] = (float)((2.0 * unit(st) - 1.0) * a);
       off += (long long)K * N;
       for (int i = 0; i < N; ++i) p[off + i] = 0.0f;

@@ -5,8 +5,10 @@
 // Network: x (2 r^2 + 2 reals) -> 3 hidden layers of width 256 with SiLU ->
 // r^2 reals o.  Parameters in one flat FP32 vector: W1 [in x 256] row-major,
 // b1, W2 [256 x 256], b2, W3, b3, W4 [256 x r^2], b4; a layer is h W + b.
-// o parametrises the skew-Hermitian A: A_aa = i o_a, then the upper
-// off-diagonal entries row by row as (re, im) pairs, A_ba = -conj(A_ab).
+// The network's output is a correction to the analytic generator -i s G
+// (G / |G| and s |G| are features): the skew-Hermitian A is unpacked from
+// o + o_an(x), with A_aa = i o_a, then the upper off-diagonal entries row by
+// row as (re, im) pairs, A_ba = -conj(A_ab).
 // R = (I - A/2)^{-1} (I + A/2) = 2 (I - A/2)^{-1} - I.
 #pragma once
 
@@ -27,6 +29,21 @@ __host__ __device__ inline long long net_param_count(int r) {
 __host__ __device__ inline int net_sample_floats(int r) { return net_in(r) + 2 * r * r; }
 
 __device__ inline float silu_f(float z) { return z / (1.0f + __expf(-z)); }
+
+// Entry e of o_an(x), the parametrisation of -i s G: -s G_aa on the diagonal,
+// (s Im G_ab, -s Re G_ab) for the upper pairs; x = (Re G/|G|, Im G/|G|, s |G|, kappa).
+__device__ inline float analytic_param(const float *x, int r, int e) {
+  const float sg = x[2 * r * r];
+  if (e < r) return -sg * x[e * r + e];
+  const int k = e - r, pidx = k >> 1;
+  int a = 0, rem = pidx;
+  while (rem >= r - a - 1) {
+    rem -= r - a - 1;
+    ++a;
+  }
+  const int b = a + 1 + rem;
+  return (k & 1) ? -sg * x[a * r + b] : sg * x[r * r + a * r + b];
+}
 
 // Forward pass of one sample by a workgroup of nt threads (nt a multiple of
 // 2 * kNetWidth is not required; every thread takes part).  x: inputs (LDS),

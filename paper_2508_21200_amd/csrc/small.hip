@@ -1663,7 +1663,9 @@ __device__ __attribute__((noinline)) void stage_rotation(const SmallRkParams &p,
   float *f = ar + q.f, *h0 = ar + q.h0, *h1 = ar + q.h1, *part = ar + q.part, *out = ar + q.out;
   double2 *aug = reinterpret_cast<double2 *>(ar + q.aug), *R = reinterpret_cast<double2 *>(ar + q.R);
   if (p.warm == LREI_WARM_LEARNED) {
-    net_forward_wg(p.net, r, f, h0, h1, part, out, NT);
+    net_forward_wg(p.net, r, f, h0, h1, part, out, NT);  // ends with a barrier
+    for (int e = threadIdx.x; e < r * r; e += NT) out[e] += analytic_param(f, r, e);
+    __syncthreads();
   } else if (p.warm == LREI_WARM_PREDICT_CAYLEY) {
     // A = -i s G: o_a = -s G_aa; upper pairs (re, im) = (s Im G_ab, -s Re G_ab)
     const double st = stage_step(p, j);

@@ -458,7 +458,14 @@ def test_warm_start_falls_back_on_large_steps():
     assert s["warm_accepted"] + s["warm_rejected"] <= s["eigensolves"]
 
 
-def test_learned_start_rotation_is_rejected():
-    from paper_2508_21200_amd import LreiError
-    with pytest.raises(LreiError):
-        _ctx(warm="learned")
+def test_warm_mode_out_of_range_is_rejected():
+    """Unknown start modes fail at creation; the learned mode is accepted
+    there and needs an attached network to step (tests/test_gpu_learned.py)."""
+    from paper_2508_21200_amd import Context, LreiError
+    from paper_2508_21200_amd import lrei as _l
+    _l.WARM["bogus"] = 7
+    try:
+        with pytest.raises(LreiError):
+            Context(precision="fp64", warm="bogus")
+    finally:
+        del _l.WARM["bogus"]

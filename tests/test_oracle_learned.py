@@ -168,6 +168,19 @@ def test_analytic_rotation_on_an_invariant_subspace():
         assert np.abs(L.analytic_rotation(G, t) - T).max() < 0.1 * (t * np.abs(G).max()) ** 3 * r ** 2
 
 
+def test_zero_network_gives_the_analytic_rotation():
+    rng = np.random.default_rng(8)
+    r = 3
+    G = rng.normal(size=(r, r)) + 1j * rng.normal(size=(r, r))
+    G = (G + G.conj().T) / 2
+    x = L.features(G, 0.02, 0.1)
+    p = np.zeros(L.n_params(r))
+    R = L.rotations(p, x[None, :], r)[0]
+    assert np.abs(R - L.analytic_rotation(G, 0.02)).max() < 1e-14
+    # and the analytic parametrisation is -i s G itself
+    assert np.abs(L.unpack_skew(L.analytic_params(x, r), r) + 1j * 0.02 * G).max() < 1e-14
+
+
 def test_features_layout():
     rng = np.random.default_rng(7)
     r = 3
