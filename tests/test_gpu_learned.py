@@ -159,6 +159,29 @@ def test_predictor_modes_keep_parity(warm):
         net.close()
 
 
+def test_untrained_network_steps_like_the_analytic_predictor():
+    """A new network has a zero output layer, so its rotation is the analytic
+    one: in-kernel inference must reproduce that predictor's solves (same
+    products, same acceptances) and its result up to FP32 feature rounding."""
+    from paper_2508_21200_amd import Net
+    r = 4
+    out = {}
+    for warm in ("predict_cayley", "learned"):
+        c, cfg = _chain_ctx(warm=warm, r=r)
+        net = Net(r, seed=3) if warm == "learned" else None
+        if net:
+            c.attach_net(net)
+        c.step("qLLG", "RK4", 0.01, 0.2, 4)
+        st = c.stats()
+        out[warm] = (c.get_rho()[1], st["warm_accepted"], st["warm_rejected"], st["warm_iterations"])
+        c.close()
+        if net:
+            net.close()
+    a, b = out["predict_cayley"], out["learned"]
+    assert a[1:] == b[1:]
+    assert rel_fro_error(a[0], cfg["lam"], b[0], cfg["lam"]) < 1e-12
+
+
 def test_learned_needs_an_attached_network():
     from paper_2508_21200_amd import LreiError, Net
     c, _ = _chain_ctx(warm="learned", r=4)
