@@ -295,6 +295,28 @@ LREI_API lrei_status lrei_batch_profile_kernels(lrei_batch *b, int scheme, doubl
 /* Blocks until all work queued by the batch has finished. */
 LREI_API lrei_status lrei_batch_synchronize(lrei_batch *b);
 
+/* Two-spin reduced density matrices R_kl = Tr_rest(rho) of the current state
+ * (Sec. 3.5: the partial trace over every spin but k and l) for n_pairs
+ * (1..4096) site pairs.  pairs (host): 2 n_pairs site indices, k != l, both
+ * < n.  out (host, 32 n_pairs doubles): per pair a 4 x 4 complex matrix,
+ * row-major, (re, im) pairs; row and column index q = 2 b_k + b_l, b the
+ * site's spin bit (0 = up).  One fused pass over the state per pair, FP64
+ * accumulation.  Errors: LREI_E_STATE (no state), LREI_E_INVALID (sites),
+ * LREI_E_NOMEM, LREI_E_DEVICE. */
+LREI_API lrei_status lrei_pair_density(lrei_ctx *ctx, int n_pairs, const int *pairs, double *out);
+
+/* Entanglement of a two-spin density matrix R (32 doubles laid out as
+ * above), computed on the host (Sec. 3.5 names these measures):
+ * concurrence max(0, l1 - l2 - l3 - l4) with l_i the square roots of the
+ * eigenvalues of R (sy x sy) conj(R) (sy x sy), descending (Wootters);
+ * negativity, the sum of |negative eigenvalues| of the partial transpose on
+ * the second spin (Vidal and Werner); chsh, the largest CHSH expectation
+ * 2 sqrt(m1 + m2) with m1 >= m2 the two largest eigenvalues of T^T T,
+ * T_ij = Tr(R s_i x s_j) (Horodecki).  Any output may be NULL.
+ * LREI_E_INVALID if R is NULL or not finite. */
+LREI_API lrei_status lrei_pair_entanglement(const double *R, double *concurrence, double *negativity,
+                                            double *chsh);
+
 /* ---- Learned start rotation (production form on top of the stage
  * eigensolve of Sec. 3.6; the paper has no such component) ----------------
  *

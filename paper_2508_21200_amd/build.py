@@ -6,7 +6,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["terms.cpp", "nspace.hip", "blocks.hip", "small.hip", "api.hip", "batch.hip", "learned.hip"]
+SOURCES = ["terms.cpp", "nspace.hip", "blocks.hip", "small.hip", "api.hip", "batch.hip", "learned.hip",
+           "entangle.cpp"]
 LIB = os.path.join(HERE, "liblrei.so")
 
 FLAGS = [

@@ -1073,6 +1073,45 @@ lrei_status lrei_get_rho(lrei_ctx *ctx, double *lambda, void *V, int v_is_device
   return LREI_OK;
 }
 
+lrei_status lrei_pair_density(lrei_ctx *ctx, int n_pairs, const int *pairs, double *out) {
+  if (!ctx) return LREI_E_INVALID;
+  if (!ctx->have_rho) return ctx->fail(LREI_E_STATE, "no state");
+  if (n_pairs < 1 || n_pairs > 4096 || !pairs || !out)
+    return ctx->fail(LREI_E_INVALID, "n_pairs must be 1..4096 with host pair and output arrays");
+  std::vector<int> bits(2 * (size_t)n_pairs);
+  for (int p = 0; p < n_pairs; ++p) {
+    const int k = pairs[2 * p], l = pairs[2 * p + 1];
+    if (k < 0 || l < 0 || k >= ctx->n || l >= ctx->n || k == l)
+      return ctx->fail(LREI_E_INVALID, "pair " + std::to_string(p) + ": sites must be distinct and < n");
+    bits[2 * p] = ctx->site_pos[k];
+    bits[2 * p + 1] = ctx->site_pos[l];
+  }
+  HIPCHK(hipSetDevice(ctx->device));
+  const int r = ctx->r;
+  const int grid = (int)std::min<long long>(256, std::max<long long>(1, (ctx->N / 4) / 1024));
+  DevBuf db, part, res;
+  if (!db.ensure(bits.size() * sizeof(int)) || !part.ensure((size_t)n_pairs * grid * 10 * sizeof(double2)) ||
+      !res.ensure((size_t)n_pairs * 16 * sizeof(double2)))
+    return ctx->fail(LREI_E_NOMEM, "device allocation failed");
+  hipError_t e = hipMemcpyAsync(ctx->lam_dev.p, ctx->lam.data(), r * sizeof(double), hipMemcpyHostToDevice,
+                                ctx->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(db.p, bits.data(), bits.size() * sizeof(int), hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) {
+    launch_pair_density(ctx->fp32, ctx->blocks[0].p, (const double *)ctx->lam_dev.p, ctx->N, r, (const int *)db.p,
+                        n_pairs, grid, (double2 *)part.p, (double2 *)res.p, ctx->stream);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(out, res.p, (size_t)n_pairs * 16 * sizeof(double2), hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  db.release();
+  part.release();
+  res.release();
+  if (e != hipSuccess) return ctx->fail(LREI_E_DEVICE, std::string("pair density: ") + hipGetErrorString(e));
+  return LREI_OK;
+}
+
 lrei_status lrei_observables(lrei_ctx *ctx, double *energy, double magnetization[3]) {
   if (!ctx) return LREI_E_INVALID;
   if (!ctx->have_rho) return ctx->fail(LREI_E_STATE, "no state");

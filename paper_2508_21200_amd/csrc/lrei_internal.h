@@ -141,6 +141,11 @@ void launch_convert(bool to_fp32, const void *src, void *dst, long long n_comple
 // dst rows = src rows moved by the site -> bit map pos (forward) or gathered back (inverse).
 void launch_permute(bool fp32, const void *src, void *dst, long long N, int r, const int *pos, int n, bool inverse,
                     hipStream_t s);
+// Two-spin reduced density matrices of n_pairs (bit k, bit l) pairs (bits:
+// device, 2 per pair) into out (device, n_pairs x 16 double2); partials: at
+// least n_pairs * grid * 10 double2.
+void launch_pair_density(bool fp32, const void *V, const double *lam, long long N, int r, const int *bits,
+                         int n_pairs, int grid, double2 *partials, double2 *out, hipStream_t s);
 void launch_magnetization(bool fp32, const void *V, const double *lam, long long N, int r, int n,
                           double2 *partials, int grid, hipStream_t s);
 int nspace_grid(long long N, int r);

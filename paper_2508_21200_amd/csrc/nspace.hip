@@ -751,6 +751,92 @@ __global__ __launch_bounds__(kThreads) void k_magnet(const void *Vp, const doubl
   }
 }
 
+// Two-spin reduced density matrices (Sec. 3.5), pair p = blockIdx.y with row
+// bits (bk, bl): the N/4 groups of rows that differ only in those two bits
+// each hold the four rows x_q (q = 2 b_k + b_l), and
+// R[q][q'] = sum over groups and columns a of lam_a V[x_q, a] conj(V[x_q', a]).
+// Lanes share a group as the magnetisation kernel shares a row (one column
+// each); the ten entries q <= q' are summed in FP64 and reduced in the
+// workgroup in a fixed order: partials[(p * gridDim.x + block) * 10 + e].
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_pair_density(const void *Vp, const double *lam, long long N, int r,
+                                                           const int *bits, double2 *partials) {
+  using C2 = typename Cplx<T>::type;
+  const C2 *V = reinterpret_cast<const C2 *>(Vp);
+  const int p = blockIdx.y, bk = bits[2 * p], bl = bits[2 * p + 1];
+  const int lo = bk < bl ? bk : bl, hi = bk < bl ? bl : bk;
+  const int L = pow2ceil(r), RW = 64 / L;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = lane % L, rsub = lane / L;
+  double acc[20];
+#pragma unroll
+  for (int e = 0; e < 20; ++e) acc[e] = 0.0;
+  const long long G = N >> 2;
+  if (col < r) {
+    const double lm = lam[col];
+    const long long per_block = (long long)kWaves * RW;
+    for (long long g0 = (long long)blockIdx.x * per_block; g0 < G; g0 += (long long)gridDim.x * per_block) {
+      const long long g = g0 + wave * RW + rsub;
+      if (g >= G) continue;
+      // g with zero bits inserted at lo, then at hi
+      long long x = ((g >> lo) << (lo + 1)) | (g & ((1LL << lo) - 1));
+      x = ((x >> hi) << (hi + 1)) | (x & ((1LL << hi) - 1));
+      C2 v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const long long xq = x | ((long long)(q >> 1) << bk) | ((long long)(q & 1) << bl);
+        v[q] = V[xq * r + col];
+      }
+      int e = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int q2 = q; q2 < 4; ++q2, ++e) {
+          // lam * v_q * conj(v_q2)
+          const double ar = v[q].x, ai = v[q].y, br = v[q2].x, bi = v[q2].y;
+          acc[2 * e] += lm * (ar * br + ai * bi);
+          acc[2 * e + 1] += lm * (ai * br - ar * bi);
+        }
+    }
+  }
+  __shared__ double red[kThreads];
+  for (int c = 0; c < 20; ++c) {
+    red[threadIdx.x] = acc[c];
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+      if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      double *out = reinterpret_cast<double *>(partials + ((long long)p * gridDim.x + blockIdx.x) * 10);
+      out[c] = red[0];
+    }
+    __syncthreads();
+  }
+}
+
+// out[p] (4 x 4 complex, row-major) = the sum over the pair's workgroup
+// partials in block order; the lower triangle by Hermitian symmetry.
+__global__ void k_pair_reduce(const double2 *partials, int grid, int n_pairs, double2 *out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_pairs * 10) return;
+  const int p = t / 10, e = t % 10;
+  double2 s = make_double2(0, 0);
+  for (int b = 0; b < grid; ++b) {
+    const double2 v = partials[((long long)p * grid + b) * 10 + e];
+    s.x += v.x;
+    s.y += v.y;
+  }
+  int q = 0, q2 = 0, k = e;
+  while (k >= 4 - q) {
+    k -= 4 - q;
+    ++q;
+  }
+  q2 = q + k;
+  out[p * 16 + q * 4 + q2] = s;
+  if (q2 != q) out[p * 16 + q2 * 4 + q] = make_double2(s.x, -s.y);
+}
+
 size_t cheb_lds(bool fp32, int r) { return 4 * (size_t)kTile * pad16(r) * (fp32 ? 4 : 8); }
 
 }  // namespace
@@ -1007,6 +1093,17 @@ void launch_permute(bool fp32, const void *src, void *dst, long long N, int r, c
   else
     hipLaunchKernelGGL(k_permute_rows<double2>, dim3((unsigned)blocks), dim3(256), 0, s, (const double2 *)src,
                        (double2 *)dst, N, r, pa, (int)inverse);
+}
+
+void launch_pair_density(bool fp32, const void *V, const double *lam, long long N, int r, const int *bits,
+                         int n_pairs, int grid, double2 *partials, double2 *out, hipStream_t s) {
+  if (fp32)
+    hipLaunchKernelGGL(k_pair_density<float>, dim3(grid, n_pairs), dim3(kThreads), 0, s, V, lam, N, r, bits, partials);
+  else
+    hipLaunchKernelGGL(k_pair_density<double>, dim3(grid, n_pairs), dim3(kThreads), 0, s, V, lam, N, r, bits,
+                       partials);
+  hipLaunchKernelGGL(k_pair_reduce, dim3((n_pairs * 10 + 255) / 256), dim3(256), 0, s, (const double2 *)partials,
+                     grid, n_pairs, out);
 }
 
 void launch_magnetization(bool fp32, const void *V, const double *lam, long long N, int r, int n,

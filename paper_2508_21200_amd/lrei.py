@@ -113,6 +113,8 @@ _SIGS = {
     "lrei_record": (ctypes.c_int, [_P, _P, ctypes.c_int]),
     "lrei_record_count": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int)]),
     "lrei_attach_net": (ctypes.c_int, [_P, _P]),
+    "lrei_pair_density": (ctypes.c_int, [_P, ctypes.c_int, _P, _P]),
+    "lrei_pair_entanglement": (ctypes.c_int, [_P, _P, _P, _P]),
 }
 
 
@@ -270,6 +272,13 @@ class Context:
     def synchronize(self):
         self._check(self.lib.lrei_synchronize(self.h))
 
+    def pair_density(self, pairs):
+        """Two-spin reduced density matrices, (n_pairs, 4, 4) complex."""
+        pr = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+        out = np.zeros((pr.shape[0], 4, 4), dtype=np.complex128)
+        self._check(self.lib.lrei_pair_density(self.h, pr.shape[0], pr.ctypes.data, out.ctypes.data))
+        return out
+
     def record(self, samples, capacity=None):
         """Records a training sample per RK stage into `samples` (a device
         float32 tensor of capacity x net_sample_floats(r)); None stops."""
@@ -293,6 +302,17 @@ class Context:
         """Network for warm="learned" (None detaches); it must outlive the attachment."""
         self._check(self.lib.lrei_attach_net(self.h, None if net is None else net.h))
         self._net = net
+
+
+def pair_entanglement(R):
+    """(concurrence, negativity, chsh) of a 4 x 4 two-spin density matrix."""
+    lib = load()
+    R = np.ascontiguousarray(np.asarray(R, dtype=np.complex128).reshape(4, 4))
+    c, n, b = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    st = lib.lrei_pair_entanglement(R.ctypes.data, ctypes.byref(c), ctypes.byref(n), ctypes.byref(b))
+    if st != LREI_OK:
+        raise LreiError(st, "invalid two-spin density matrix")
+    return c.value, n.value, b.value
 
 
 def net_sample_floats(r):
