@@ -96,3 +96,18 @@ def partial_eig_irlm(K, r, tol=1e-13):
     w, U = spla.eigsh(op, k=r, which="LA", ncv=max(2 * r + 1, 20), tol=tol)
     order = np.argsort(w)[::-1]
     return w[order], U[:, order]
+
+
+def state_from_factor(A, tol=1e-14):
+    """Initial partial eigendecomposition of rho_0 = A A* / Tr(A A*) (Sec. 3.6:
+    the run starts from rho_0 = V Lambda_0 V*, r = rank rho_0), by
+    Rayleigh-Ritz on the range of A: A = Q R, rho_0 = Q (R R*) Q* / Tr, so the
+    eigenpairs come from the small matrix R R*.  Eigenvalues at or below
+    tol * the largest are dropped (the rank).  Returns (lam descending, V)."""
+    A = np.asarray(A, dtype=np.complex128)
+    Q, R = np.linalg.qr(A)
+    w, U = np.linalg.eigh(R @ R.conj().T)
+    order = np.argsort(w)[::-1]
+    w, U = w[order], U[:, order]
+    keep = w > tol * w[0]
+    return w[keep] / np.sum(w[keep]), Q @ U[:, keep]
