@@ -426,6 +426,19 @@ def main():
                       "rel_fro": rel_fro(torch, Vt, Vr, cfg["lam"])}
             ref.close()
 
+    # two-spin reduced density matrices of 64 site pairs in one call (one fused
+    # pass over the state per pair; algorithmic bytes F per pair)
+    pairs = [(k, l) for k in range(cfg["n"]) for l in range(cfg["n"]) if k != l][:64]
+    ctx.pair_density(pairs)
+    t2 = time.perf_counter()
+    for _ in range(5):
+        ctx.pair_density(pairs)
+    t_pairs = (time.perf_counter() - t2) / 5
+    pair_obs = {"pairs": len(pairs), "ms_per_call": round(1e3 * t_pairs, 4),
+                "algorithmic_GBs": round(len(pairs) * F / t_pairs / 1e9, 1),
+                "note": "host wall clock of the synchronous ABI call (upload of the pair list, passes, "
+                        "reduction, copy-back)"}
+
     cpu = None if args.no_cpu_baseline else cpu_baseline(cfg)
     line = {
         "metric": "LREI steps/s (n=20, r=16)",
@@ -447,6 +460,7 @@ def main():
         "cpu_baseline": cpu,
         "parity": parity,
         "kernels_ms": {k: round(v, 5) for k, v in kms.items()},
+        "pair_density": pair_obs,
         "hv_tuning": None if tuning is None else {
             "epl": tuning["epl"], "grid": tuning["grid"], "win_bits": tuning["win_bits"],
             "n_sweeps": tuning["n_sweeps"], "ms": round(tuning["ms"], 5),

@@ -295,6 +295,29 @@ LREI_API lrei_status lrei_batch_profile_kernels(lrei_batch *b, int scheme, doubl
 /* Blocks until all work queued by the batch has finished. */
 LREI_API lrei_status lrei_batch_synchronize(lrei_batch *b);
 
+/* Rank r of the current state (LREI_E_STATE before a state is set). */
+LREI_API lrei_status lrei_get_rank(lrei_ctx *ctx, int *r);
+
+/* Sets rho = A A* / Tr(A A*) from a factor A (N x m complex128, row-major,
+ * natural basis order, host or device; columns need not be orthonormal),
+ * 1 <= m <= min(32, N): the partial eigendecomposition the run starts from
+ * (Sec. 3.6), computed on the GPU from the Gram matrix A* A; eigenvalues at or
+ * below 1e-14 of the largest are dropped, so r = rank rho (read it with
+ * lrei_get_rho).  Requires a Hamiltonian; errors as lrei_set_rho, plus
+ * LREI_E_INVALID for a zero factor. */
+LREI_API lrei_status lrei_set_rho_factor(lrei_ctx *ctx, int m, const void *A, int a_is_device);
+
+/* Maximally mixed admixture (Sec. 5, a full-rank state): from this call on
+ * the context's state is rho = p I / N + (1 - p) V Lambda V*, p in [0, 1)
+ * (0 by default).  lrei_step evolves the low-rank part V Lambda V* with
+ * damping (1 - p) kappa, which the paper shows gives the solution from
+ * rho; lrei_observables and lrei_pair_density report rho's values
+ * (Tr(A rho) = p Tr(A) / N + (1 - p) Tr(A V Lambda V*), with Tr(A) = 0 for
+ * the energy and the magnetisation; R_kl gains p I / 4); lrei_get_rho,
+ * lrei_set_rho and checkpoints hold the low-rank part only.  Resets an AB
+ * history.  LREI_E_INVALID if p is outside [0, 1). */
+LREI_API lrei_status lrei_set_mixing(lrei_ctx *ctx, double p);
+
 /* Two-spin reduced density matrices R_kl = Tr_rest(rho) of the current state
  * (Sec. 3.5: the partial trace over every spin but k and l) for n_pairs
  * (1..4096) site pairs.  pairs (host): 2 n_pairs site indices, k != l, both

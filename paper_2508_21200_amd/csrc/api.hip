@@ -55,6 +55,9 @@ struct lrei_ctx {
   DevBuf acc;                     // partial sums between sweeps
   DevBuf sched;                   // H.V tile-scheduling counters (16 ints, zero between launches)
 
+  // weight p of the maximally mixed part: the state is p I / N + (1 - p) V Lambda V*
+  double mix_p = 0.0;
+
   // learned start rotation: attached network, training-sample recorder
   const float *net = nullptr;
   int net_r = 0;
@@ -952,6 +955,9 @@ lrei_status lrei_step(lrei_ctx *ctx, int model, int scheme, double dt, double ka
   if (!(dt > 0) || !std::isfinite(dt)) return ctx->fail(LREI_E_INVALID, "dt must be positive and finite");
   if (!(kappa >= 0) || !std::isfinite(kappa)) return ctx->fail(LREI_E_INVALID, "kappa must be >= 0 and finite");
   if (n_steps < 0) return ctx->fail(LREI_E_INVALID, "n_steps must be >= 0");
+  // the low-rank part of a state with a maximally mixed admixture evolves with
+  // damping (1 - p) kappa (Sec. 5, a full-rank state)
+  kappa *= 1.0 - ctx->mix_p;
   if (!is_ab && ctx->opt.warm == LREI_WARM_LEARNED && (!ctx->net || ctx->net_r != ctx->r))
     return ctx->fail(LREI_E_STATE, "LREI_WARM_LEARNED needs an attached network of the state's rank");
   if (is_ab) {
@@ -1073,6 +1079,62 @@ lrei_status lrei_get_rho(lrei_ctx *ctx, double *lambda, void *V, int v_is_device
   return LREI_OK;
 }
 
+lrei_status lrei_get_rank(lrei_ctx *ctx, int *r) {
+  if (!ctx || !r) return LREI_E_INVALID;
+  if (!ctx->have_rho) return ctx->fail(LREI_E_STATE, "no state");
+  *r = ctx->r;
+  return LREI_OK;
+}
+
+lrei_status lrei_set_rho_factor(lrei_ctx *ctx, int m, const void *A, int a_is_device) {
+  if (!ctx) return LREI_E_INVALID;
+  if (ctx->N <= 0) return ctx->fail(LREI_E_STATE, "set the Hamiltonian first");
+  if (m < 1 || m > kMaxR || m > ctx->N || !A) return ctx->fail(LREI_E_INVALID, "need 1 <= m <= min(32, N) and A");
+  HIPCHK(hipSetDevice(ctx->device));
+  const long long N = ctx->N;
+  const int np = m * (m + 1) / 2;
+  const int grid = (int)std::min<long long>(256, std::max<long long>(1, N / 256));
+  DevBuf ad, part, cm, lamd, info, vd;
+  if ((!a_is_device && !ad.ensure((size_t)N * m * sizeof(double2))) ||
+      !part.ensure((size_t)grid * np * sizeof(double2)) || !cm.ensure((size_t)m * m * sizeof(double2)) ||
+      !lamd.ensure((size_t)m * sizeof(double)) || !info.ensure(sizeof(int)))
+    return ctx->fail(LREI_E_NOMEM, "device allocation failed");
+  const double2 *Ad = a_is_device ? (const double2 *)A : (const double2 *)ad.p;
+  hipError_t e = hipSuccess;
+  if (!a_is_device)
+    e = hipMemcpyAsync(ad.p, A, (size_t)N * m * sizeof(double2), hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) {
+    launch_factor_eig(Ad, N, m, (double2 *)part.p, grid, (double2 *)cm.p, (double *)lamd.p, (int *)info.p,
+                      ctx->stream);
+    e = hipGetLastError();
+  }
+  int rank = 0;
+  std::vector<double> lam(m);
+  if (e == hipSuccess) e = hipMemcpyAsync(&rank, info.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(lam.data(), lamd.p, m * sizeof(double), hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return ctx->fail(LREI_E_DEVICE, std::string("factor eigensolve: ") + hipGetErrorString(e));
+  if (rank < 1) return ctx->fail(LREI_E_INVALID, "the factor is zero or not finite");
+  if (!vd.ensure((size_t)N * rank * sizeof(double2))) return ctx->fail(LREI_E_NOMEM, "device allocation failed");
+  launch_factor_apply(Ad, N, m, (const double2 *)cm.p, rank, (double2 *)vd.p, ctx->stream);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  ad.release();
+  part.release();
+  if (e != hipSuccess) return ctx->fail(LREI_E_DEVICE, std::string("factor apply: ") + hipGetErrorString(e));
+  lam.resize(rank);
+  return lrei_set_rho(ctx, rank, lam.data(), vd.p, 1);
+}
+
+lrei_status lrei_set_mixing(lrei_ctx *ctx, double p) {
+  if (!ctx) return LREI_E_INVALID;
+  if (!(p >= 0.0 && p < 1.0)) return ctx->fail(LREI_E_INVALID, "p must be in [0, 1)");
+  ctx->mix_p = p;
+  ab_reset(ctx);      // the AB history holds right-hand sides at the old damping
+  ctx->drop_graph();  // the damping is a launch argument
+  return LREI_OK;
+}
+
 lrei_status lrei_pair_density(lrei_ctx *ctx, int n_pairs, const int *pairs, double *out) {
   if (!ctx) return LREI_E_INVALID;
   if (!ctx->have_rho) return ctx->fail(LREI_E_STATE, "no state");
@@ -1099,7 +1161,8 @@ lrei_status lrei_pair_density(lrei_ctx *ctx, int n_pairs, const int *pairs, doub
     e = hipMemcpyAsync(db.p, bits.data(), bits.size() * sizeof(int), hipMemcpyHostToDevice, ctx->stream);
   if (e == hipSuccess) {
     launch_pair_density(ctx->fp32, ctx->blocks[0].p, (const double *)ctx->lam_dev.p, ctx->N, r, (const int *)db.p,
-                        n_pairs, grid, (double2 *)part.p, (double2 *)res.p, ctx->stream);
+                        n_pairs, grid, (double2 *)part.p, (double2 *)res.p, 1.0 - ctx->mix_p, 0.25 * ctx->mix_p,
+                        ctx->stream);
     e = hipGetLastError();
   }
   if (e == hipSuccess)
@@ -1128,7 +1191,9 @@ lrei_status lrei_observables(lrei_ctx *ctx, double *energy, double magnetization
     const double e = ctx->terms.gershgorin > 0 ? ctx->terms.gershgorin : 1.0;
     double en = 0;
     for (int a = 0; a < r; ++a) en += ctx->lam[a] * g[r * r + a * r + a].x * e;
-    *energy = en;
+    // Tr(H) = 0 (every Pauli-string term is traceless): the maximally mixed
+    // part adds nothing
+    *energy = (1.0 - ctx->mix_p) * en;
   }
   if (magnetization) {
     HIPCHK(hipMemcpyAsync(ctx->lam_dev.p, ctx->lam.data(), r * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
@@ -1146,7 +1211,7 @@ lrei_status lrei_observables(lrei_ctx *ctx, double *energy, double magnetization
       my += h[2 * i].y;
       mz += h[2 * i + 1].x;
     }
-    const double f = 0.5 * ctx->hbar / ctx->n;
+    const double f = (1.0 - ctx->mix_p) * 0.5 * ctx->hbar / ctx->n;
     magnetization[0] = f * mx;
     magnetization[1] = f * my;
     magnetization[2] = f * mz;

@@ -141,11 +141,19 @@ void launch_convert(bool to_fp32, const void *src, void *dst, long long n_comple
 // dst rows = src rows moved by the site -> bit map pos (forward) or gathered back (inverse).
 void launch_permute(bool fp32, const void *src, void *dst, long long N, int r, const int *pos, int n, bool inverse,
                     hipStream_t s);
+// Initial state from a factor A (N x m, device, natural row order): Gram
+// partials (grid x m(m+1)/2) and the one-workgroup eigensolve giving C
+// (m x m), lam (m) and info[0] = rank; then V = A C[:, :r].
+void launch_factor_eig(const double2 *A, long long N, int m, double2 *partials, int grid, double2 *C, double *lam,
+                       int *info, hipStream_t s);
+void launch_factor_apply(const double2 *A, long long N, int m, const double2 *C, int r, double2 *V, hipStream_t s);
+
 // Two-spin reduced density matrices of n_pairs (bit k, bit l) pairs (bits:
-// device, 2 per pair) into out (device, n_pairs x 16 double2); partials: at
-// least n_pairs * grid * 10 double2.
+// device, 2 per pair) into out (device, n_pairs x 16 double2), each
+// scale * R + shift * I; partials: at least n_pairs * grid * 10 double2.
 void launch_pair_density(bool fp32, const void *V, const double *lam, long long N, int r, const int *bits,
-                         int n_pairs, int grid, double2 *partials, double2 *out, hipStream_t s);
+                         int n_pairs, int grid, double2 *partials, double2 *out, double scale, double shift,
+                         hipStream_t s);
 void launch_magnetization(bool fp32, const void *V, const double *lam, long long N, int r, int n,
                           double2 *partials, int grid, hipStream_t s);
 int nspace_grid(long long N, int r);

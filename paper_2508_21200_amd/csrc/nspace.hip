@@ -815,9 +815,11 @@ __global__ __launch_bounds__(kThreads) void k_pair_density(const void *Vp, const
   }
 }
 
-// out[p] (4 x 4 complex, row-major) = the sum over the pair's workgroup
-// partials in block order; the lower triangle by Hermitian symmetry.
-__global__ void k_pair_reduce(const double2 *partials, int grid, int n_pairs, double2 *out) {
+// out[p] (4 x 4 complex, row-major) = scale * (the sum over the pair's
+// workgroup partials in block order) + shift * I; the lower triangle by
+// Hermitian symmetry.
+__global__ void k_pair_reduce(const double2 *partials, int grid, int n_pairs, double scale, double shift,
+                              double2 *out) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n_pairs * 10) return;
   const int p = t / 10, e = t % 10;
@@ -833,6 +835,7 @@ __global__ void k_pair_reduce(const double2 *partials, int grid, int n_pairs, do
     ++q;
   }
   q2 = q + k;
+  s = make_double2(scale * s.x + (q == q2 ? shift : 0.0), scale * s.y);
   out[p * 16 + q * 4 + q2] = s;
   if (q2 != q) out[p * 16 + q2 * 4 + q] = make_double2(s.x, -s.y);
 }
@@ -1096,14 +1099,15 @@ void launch_permute(bool fp32, const void *src, void *dst, long long N, int r, c
 }
 
 void launch_pair_density(bool fp32, const void *V, const double *lam, long long N, int r, const int *bits,
-                         int n_pairs, int grid, double2 *partials, double2 *out, hipStream_t s) {
+                         int n_pairs, int grid, double2 *partials, double2 *out, double scale, double shift,
+                         hipStream_t s) {
   if (fp32)
     hipLaunchKernelGGL(k_pair_density<float>, dim3(grid, n_pairs), dim3(kThreads), 0, s, V, lam, N, r, bits, partials);
   else
     hipLaunchKernelGGL(k_pair_density<double>, dim3(grid, n_pairs), dim3(kThreads), 0, s, V, lam, N, r, bits,
                        partials);
   hipLaunchKernelGGL(k_pair_reduce, dim3((n_pairs * 10 + 255) / 256), dim3(256), 0, s, (const double2 *)partials,
-                     grid, n_pairs, out);
+                     grid, n_pairs, scale, shift, out);
 }
 
 void launch_magnetization(bool fp32, const void *V, const double *lam, long long N, int r, int n,

@@ -2339,4 +2339,104 @@ void launch_ab_cgs_coef(const double2 *c1g, int nU, int qx, int r, double2 *C, h
   hipLaunchKernelGGL(k_ab_cgs_coef, dim3(4), dim3(256), 0, s, c1g, nU, qx, r, C);
 }
 
+// ---------------------------------------------------------------------------
+// Initial state from a non-orthogonal factor A (N x m): the run starts from
+// the partial eigendecomposition of rho_0 = A A* / Tr(A A*) (Sec. 3.6).  The
+// eigenpairs of rho_0 are those of the Gram matrix G = A* A (the same
+// nonzero eigenvalues times Tr), with eigenvectors A W diag(w)^{-1/2}.
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// partials[block][pk(i, j)] = sum over the block's rows x of conj(A[x, i]) A[x, j], i <= j
+__global__ __launch_bounds__(NT) void k_factor_gram(const double2 *__restrict__ A, long long N, int m,
+                                                   double2 *__restrict__ partials) {
+  const int np = m * (m + 1) / 2;
+  for (int e = threadIdx.x; e < np; e += NT) {
+    int j = 0;
+    while ((j + 1) * (j + 2) / 2 <= e) ++j;
+    const int i = e - j * (j + 1) / 2;
+    double2 acc = make_double2(0, 0);
+    for (long long x = blockIdx.x; x < N; x += gridDim.x) acc = cadd(acc, cmulc(A[x * m + i], A[x * m + j]));
+    partials[(long long)blockIdx.x * np + e] = acc;
+  }
+}
+
+// One workgroup: G = the partials summed in block order, its eigenpairs by
+// Jacobi, descending; rank = #{w_a > 1e-14 w_1}; lam_a = w_a / sum_b w_b over
+// the kept ones; C (m x m, row-major) = W[:, a] / sqrt(w_a) for a < rank, 0
+// beyond.  info[0] = rank.
+__global__ __launch_bounds__(NT) void k_factor_eig(const double2 *__restrict__ partials, int grid, int m,
+                                                  double2 *__restrict__ C, double *__restrict__ lam,
+                                                  int *__restrict__ info) {
+  __shared__ double2 G[kMaxR * (kMaxR + 1) / 2], W[kMaxR * kMaxR];
+  __shared__ JacobiShared js;
+  __shared__ double w[kMaxR];
+  __shared__ int s_rank;
+  const int np = m * (m + 1) / 2;
+  for (int e = threadIdx.x; e < np; e += NT) {
+    double2 acc = make_double2(0, 0);
+    for (int b = 0; b < grid; ++b) acc = cadd(acc, partials[(long long)b * np + e]);
+    G[e] = acc;
+  }
+  __syncthreads();
+  jacobi(G, W, m, 1e-16, 60, js, true);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < m; ++k) js.order[k] = k;
+    for (int k = 0; k < m; ++k)
+      for (int l = k + 1; l < m; ++l)
+        if (G[pk(js.order[l], js.order[l])].x > G[pk(js.order[k], js.order[k])].x) {
+          const int t = js.order[k];
+          js.order[k] = js.order[l];
+          js.order[l] = t;
+        }
+    const double top = G[pk(js.order[0], js.order[0])].x;
+    int rank = 0;
+    double tr = 0;
+    for (int k = 0; k < m; ++k) {
+      w[k] = G[pk(js.order[k], js.order[k])].x;
+      if (w[k] > 1e-14 * top && top > 0) {
+        rank = k + 1;
+        tr += w[k];
+      }
+    }
+    for (int k = 0; k < m; ++k) lam[k] = k < rank ? w[k] / tr : 0.0;
+    s_rank = rank;
+    info[0] = rank;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < m * m; e += NT) {
+    const int i = e / m, a = e % m;
+    C[e] = a < s_rank ? cscale(1.0 / sqrt(w[a]), W[i * m + js.order[a]]) : make_double2(0, 0);
+  }
+}
+
+// V[x, b] = sum_i A[x, i] C[i, b] (N x r, row-major; C has leading dimension m)
+__global__ void k_factor_apply(const double2 *__restrict__ A, long long N, int m, const double2 *__restrict__ C,
+                               int r, double2 *__restrict__ V) {
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < N * r;
+       t += (long long)gridDim.x * blockDim.x) {
+    const long long x = t / r;
+    const int b = (int)(t % r);
+    double2 acc = make_double2(0, 0);
+    for (int i = 0; i < m; ++i) acc = cadd(acc, cmul(A[x * m + i], C[i * m + b]));
+    V[t] = acc;
+  }
+}
+
+}  // namespace
+
+void launch_factor_eig(const double2 *A, long long N, int m, double2 *partials, int grid, double2 *C, double *lam,
+                       int *info, hipStream_t s) {
+  hipLaunchKernelGGL(k_factor_gram, dim3(grid), dim3(NT), 0, s, A, N, m, partials);
+  hipLaunchKernelGGL(k_factor_eig, dim3(1), dim3(NT), 0, s, (const double2 *)partials, grid, m, C, lam, info);
+}
+
+void launch_factor_apply(const double2 *A, long long N, int m, const double2 *C, int r, double2 *V, hipStream_t s) {
+  const long long total = N * r;
+  const int grid = (int)std::min<long long>(4096, (total + 255) / 256);
+  hipLaunchKernelGGL(k_factor_apply, dim3(grid), dim3(256), 0, s, A, N, m, C, r, V);
+}
+
 }  // namespace lrei

@@ -114,6 +114,9 @@ _SIGS = {
     "lrei_record_count": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int)]),
     "lrei_attach_net": (ctypes.c_int, [_P, _P]),
     "lrei_pair_density": (ctypes.c_int, [_P, ctypes.c_int, _P, _P]),
+    "lrei_set_mixing": (ctypes.c_int, [_P, ctypes.c_double]),
+    "lrei_set_rho_factor": (ctypes.c_int, [_P, ctypes.c_int, _P, ctypes.c_int]),
+    "lrei_get_rank": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int)]),
     "lrei_pair_entanglement": (ctypes.c_int, [_P, _P, _P, _P]),
 }
 
@@ -271,6 +274,20 @@ class Context:
 
     def synchronize(self):
         self._check(self.lib.lrei_synchronize(self.h))
+
+    def set_rho_factor(self, A):
+        """rho = A A* / Tr(A A*) from a factor A (N x m, any columns); sets r = rank."""
+        if isinstance(A, np.ndarray):
+            A = np.ascontiguousarray(A, dtype=np.complex128)
+        p, dev = _ptr(A)
+        self._check(self.lib.lrei_set_rho_factor(self.h, A.shape[1], p, dev))
+        r = ctypes.c_int()
+        self._check(self.lib.lrei_get_rank(self.h, ctypes.byref(r)))
+        self.r = r.value
+
+    def set_mixing(self, p):
+        """State p I / N + (1 - p) V Lambda V* from now on (see lrei_set_mixing)."""
+        self._check(self.lib.lrei_set_mixing(self.h, float(p)))
 
     def pair_density(self, pairs):
         """Two-spin reduced density matrices, (n_pairs, 4, 4) complex."""

@@ -537,3 +537,59 @@ def test_pair_density_full_size():
         assert np.abs(Rg - Ro).max() < 1e-6
         assert abs(np.trace(Rg).real - 1.0) < 1e-6
     c.close()
+
+
+@pytest.mark.parametrize("model", ["qLL", "qLLG"])
+def test_maximally_mixed_admixture(model):
+    """rho = p I / N + (1 - p) V Lambda V*: the low-rank part follows the
+    oracle's run with damping (1 - p) kappa, and the observables and pair
+    matrices are those of the full state."""
+    from paper_2508_21200_amd import LreiError
+    from oracle.observables import pair_density
+    rng = np.random.default_rng(11)
+    n, r, p, kappa = 7, 3, 0.3, 0.4
+    bonds, J, h = _random_model(n, rng)
+    V, lam = _random_state(n, r, rng)
+    c = _ctx("fp64")
+    c.set_hamiltonian(n, bonds, J, h)
+    c.set_rho(lam, V)
+    c.set_mixing(p)
+    c.step(model, "RK4", 0.01, kappa, 4)
+    H = Hamiltonian(n, bonds, J, h)
+    Vo = oracle_run(H, V, lam, model, (1 - p) * kappa, 0.01, 4, "RK4")
+    assert rel_fro_error(c.get_rho()[1], lam, Vo, lam) < 1e-11
+    e, m = c.observables()
+    assert abs(e - (1 - p) * oracle_energy(H, Vo, lam)) < 1e-11
+    assert np.abs(m - (1 - p) * oracle_mag(n, Vo, lam)).max() < 1e-11
+    R = c.pair_density([(0, 3)])[0]
+    assert np.abs(R - (p * np.eye(4) / 4 + (1 - p) * pair_density(Vo, lam, n, 0, 3))).max() < 1e-12
+    for bad in (1.0, -0.1, float("nan")):
+        with pytest.raises(LreiError):
+            c.set_mixing(bad)
+    c.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_state_from_factor(prec):
+    """rho_0 = A A* / Tr from a non-orthogonal (and a rank-deficient) factor,
+    against the oracle's range Rayleigh-Ritz, then a step vs the oracle."""
+    from oracle.lowrank import state_from_factor
+    rng = np.random.default_rng(21)
+    n = 9
+    bonds, J, h = _random_model(n, rng)
+    B = rng.normal(size=(2 ** n, 4)) + 1j * rng.normal(size=(2 ** n, 4))
+    for A in (B, np.concatenate([B, B[:, 1:2] * (0.5 + 2j)], axis=1)):
+        c = _ctx(prec)
+        c.set_hamiltonian(n, bonds, J, h)
+        c.set_rho_factor(A)
+        lam_o, V_o = state_from_factor(A)
+        lam, V = c.get_rho()
+        assert lam.size == lam_o.size == 4
+        assert np.abs(lam - lam_o).max() < 1e-14
+        tol = 1e-12 if prec == "fp64" else 1e-6
+        assert rel_fro_error(V, lam, V_o, lam_o) < tol
+        c.step("qLL", "RK4", 0.01, 0.2, 2)
+        H = Hamiltonian(n, bonds, J, h)
+        Vs = oracle_run(H, V_o, lam_o, "qLL", 0.2, 0.01, 2, "RK4")
+        assert rel_fro_error(c.get_rho()[1], lam_o, Vs, lam_o) < (1e-11 if prec == "fp64" else 1e-5)
+        c.close()
