@@ -51,6 +51,9 @@ def parse():
     ap.add_argument("--learned-report", action="store_true",
                     help="train the learned start rotation on recorded n=14 chain stages and compare the "
                          "eigensolve start modes on the n=22 chain (config 5); prints one JSON line")
+    ap.add_argument("--rk-vs-ab", action="store_true",
+                    help="time LREI-RK4 and LREI-AB4 steps on triangular lattices n = 10..20 (r = 3 mixture of "
+                         "AF1, AF2, GHZ; DMI and transverse field of Sec. 5); prints one JSON line")
     ap.add_argument("--train-traj", type=int, default=100)
     ap.add_argument("--train-steps", type=int, default=200)
     ap.add_argument("--train-epochs", type=int, default=20)
@@ -137,6 +140,49 @@ def cpu_baseline_batch(trajs, budget_s=20.0):
                    f"{done} of {len(trajs)} trajectories, {t_all:.2f} s, scaled by summed N*r to the "
                    f"whole batch"),
     }
+
+
+def run_rk_vs_ab(args, torch):
+    """RK4 against AB4 step time (the paper's complexity comparison, Sec. 5).
+
+    Triangular lattices (rows x cols = n, periodic), J = 1, DMI d = 0.4 along
+    z, field 0.116 along x, q-LLG with kappa = 0.5, dt = 0.01, rank-3 start
+    0.5 |AF1> + 0.3 |AF2> + 0.2 |GHZ>, mixed precision.  AB4 is timed after
+    its three RK4 start-up steps."""
+    from paper_2508_21200_amd import Context
+    from workloads import triangular_lattice_bonds, af1_index, af2_index, ghz_vector, mixture_factor
+
+    shapes = [(2, 5), (3, 4), (2, 7), (4, 4), (3, 6), (4, 5)]
+    rows_out = []
+    for rows, cols in shapes:
+        n = rows * cols
+        N = 2 ** n
+        bonds = triangular_lattice_bonds(rows, cols, periodic=True)
+        Jt = np.eye(3) + np.array([[0.0, 0.4, 0.0], [-0.4, 0.0, 0.0], [0.0, 0.0, 0.0]])
+        J = np.repeat(Jt[None], bonds.shape[0], axis=0)
+        h = np.tile([0.116, 0.0, 0.0], (n, 1))
+        e1, e2 = np.zeros(N, complex), np.zeros(N, complex)
+        e1[af1_index(n)] = 1.0
+        e2[af2_index(n)] = 1.0
+        lam, V = mixture_factor([e1, e2, ghz_vector(n)], [0.5, 0.3, 0.2])
+        res = {"n": n, "lattice": f"{rows}x{cols} periodic triangular", "bonds": int(bonds.shape[0])}
+        for scheme, warm in (("RK4", 2), ("AB4", 5)):
+            c = Context(precision="mixed", autotune_cache=args.tune_cache)
+            c.set_hamiltonian(n, bonds, J, h)
+            c.set_rho(lam, V)
+            c.step("qLLG", scheme, 0.01, 0.5, warm)
+            c.synchronize()
+            steps = 20
+            a = time.perf_counter()
+            c.step("qLLG", scheme, 0.01, 0.5, steps)
+            c.synchronize()
+            res[f"{scheme}_ms_per_step"] = round(1e3 * (time.perf_counter() - a) / steps, 4)
+            c.close()
+        res["RK4_over_AB4"] = round(res["RK4_ms_per_step"] / res["AB4_ms_per_step"], 3)
+        rows_out.append(res)
+        print(f"[rk-vs-ab] {json.dumps(res)}", file=sys.stderr, flush=True)
+    print(json.dumps({"report": "LREI-RK4 vs LREI-AB4 step time", "model": "qLLG", "kappa": 0.5, "dt": 0.01,
+                      "r": 3, "precision": "mixed", "rows": rows_out}))
 
 
 def run_learned_report(args, torch):
@@ -351,6 +397,9 @@ def main():
         return
     if args.learned_report:
         run_learned_report(args, torch)
+        return
+    if args.rk_vs_ab:
+        run_rk_vs_ab(args, torch)
         return
     from paper_2508_21200_amd import Context
     from workloads import make_config

@@ -34,6 +34,15 @@ template <typename T> struct Cx;
 template <> struct Cx<double> { using type = double2; };
 template <> struct Cx<float> { using type = float2; };
 
+// The combination coefficients C (n_in r x n_out r) are the same for every
+// tile: they are staged once per workgroup in LDS after the tile planes when
+// the two fit in kBlocksLdsCap bytes (else every tile reads them from memory).
+constexpr size_t kBlocksLdsCap = 64 * 1024;
+__host__ __device__ inline size_t blocks_planes_bytes(bool fp32, int nb) { return (size_t)2 * nb * kPlane * (fp32 ? 4 : 8); }
+__host__ __device__ inline bool blocks_c_in_lds(bool fp32, int nin, int nout, int r) {
+  return blocks_planes_bytes(fp32, nin + nout) + (size_t)nin * nout * r * r * 16 <= kBlocksLdsCap;
+}
+
 __device__ inline d4v mfma64(double a, double b, d4v c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
@@ -59,6 +68,12 @@ __global__ __launch_bounds__(kBT) void k_blocks(BlocksArgs a) {
   const int r = a.r, nin = a.n_in, nout = a.n_out, nb = nin + nout;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int i = threadIdx.x; i < 2 * nb * kPlane; i += kBT) planes[i] = T(0);
+  const bool c_lds = blocks_c_in_lds(sizeof(T) == 4, nin, nout, r);
+  const int ldc = c_lds ? nout * r : a.ldc;
+  double2 *Cs = reinterpret_cast<double2 *>(smem + blocks_planes_bytes(sizeof(T) == 4, nb));
+  if (c_lds)
+    for (int e = threadIdx.x; e < nin * r * nout * r; e += kBT) Cs[e] = a.C[(size_t)(e / (nout * r)) * a.ldc + e % (nout * r)];
+  const double2 *Cm = c_lds ? Cs : a.C;
   __syncthreads();
 
   double acc[MI][8];
@@ -90,15 +105,20 @@ __global__ __launch_bounds__(kBT) void k_blocks(BlocksArgs a) {
       const int j = lane & 15;
       for (int i = 0; i < nin; ++i) {
         const T *xr = planes + (2 * i) * kPlane, *xi = planes + (2 * i + 1) * kPlane;
-        for (int kk = 0; kk < kBP; kk += 4) {
-          const int ak = kk + (lane >> 4);
+        double2 c[kBP / 4];
+#pragma unroll
+        for (int q = 0; q < kBP / 4; ++q) {  // the four coefficient loads together
+          const int ak = 4 * q + (lane >> 4);
+          c[q] = (ak < r && j < r) ? Cm[(size_t)(i * r + ak) * ldc + o * r + j] : make_double2(0, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < kBP / 4; ++q) {
+          const int ak = 4 * q + (lane >> 4);
           const double ar = (double)xr[(lane & 15) * kBP + ak], ai = (double)xi[(lane & 15) * kBP + ak];
-          double2 c = make_double2(0, 0);
-          if (ak < r && j < r) c = a.C[(size_t)(i * r + ak) * a.ldc + o * r + j];
-          ore = mfma64(ar, c.x, ore);
-          ore = mfma64(-ai, c.y, ore);
-          oim = mfma64(ar, c.y, oim);
-          oim = mfma64(ai, c.x, oim);
+          ore = mfma64(ar, c[q].x, ore);
+          ore = mfma64(-ai, c[q].y, ore);
+          oim = mfma64(ar, c[q].y, oim);
+          oim = mfma64(ai, c[q].x, oim);
         }
       }
       T *yr = planes + (2 * (nin + o)) * kPlane, *yi = planes + (2 * (nin + o) + 1) * kPlane;
@@ -161,22 +181,181 @@ __global__ __launch_bounds__(kBT) void k_blocks(BlocksArgs a) {
   }
 }
 
+// The same pass for small r on FP64 vector FMAs: with 16 x 16 MFMA tiles an
+// r-column block uses (r/16)^2 of each product, and on this chip the FP64
+// matrix rate is no higher than the vector rate, so up to r = 8 exact-size
+// vector products are faster.  Tiles of kSR = 64 rows with the blocks packed
+// at their own width r in LDS (block q: re at 2q kSR r, im at (2q + 1) kSR r,
+// row-major), the coefficients in LDS when planes and coefficients fit in
+// kSmallLdsCap bytes, the same partials layout; thread t accumulates Gram
+// entries t, t + kBT, ... in registers.
+constexpr int kSR = 64;
+constexpr size_t kSmallLdsCap = 96 * 1024;
+constexpr int kSmallEntries = (kMaxGrams * 8 * 8 + kBT - 1) / kBT;  // r <= 8
+__host__ __device__ inline size_t small_planes_bytes(bool fp32, int nb, int r) {
+  return (size_t)2 * nb * kSR * r * (fp32 ? 4 : 8);
+}
+__host__ __device__ inline bool small_c_in_lds(bool fp32, int nin, int nout, int r) {
+  return small_planes_bytes(fp32, nin + nout, r) + (size_t)nin * nout * r * r * 16 <= kSmallLdsCap;
+}
+
+// R: the block width r, a compile-time constant so that every index folds and
+// the inner products unroll; each thread's output and Gram entries are the
+// same in every tile, so their coordinates are computed once.
+constexpr int kOutPerThread = (kMaxIoBlocks * kSR * 8 + kBT - 1) / kBT;
+template <typename T, int R>
+__global__ __launch_bounds__(kBT) void k_blocks_small(BlocksArgs a) {
+  using C2 = typename Cx<T>::type;
+  extern __shared__ __align__(16) unsigned char smem[];
+  T *planes = reinterpret_cast<T *>(smem);
+  constexpr int rr = R * R, pl = kSR * R;
+  const int nin = a.n_in, nout = a.n_out, nb = nin + nout;
+  const bool c_lds = small_c_in_lds(sizeof(T) == 4, nin, nout, R);
+  const int ldc = c_lds ? nout * R : a.ldc;
+  double2 *Cs = reinterpret_cast<double2 *>(smem + small_planes_bytes(sizeof(T) == 4, nb, R));
+  if (c_lds)
+    for (int e = threadIdx.x; e < nin * R * nout * R; e += kBT) Cs[e] = a.C[(size_t)(e / (nout * R)) * a.ldc + e % (nout * R)];
+  const double2 *Cm = c_lds ? Cs : a.C;
+  const int n_ent = a.n_gram * rr;
+  double accr[kSmallEntries], acci[kSmallEntries];
+  int gx[kSmallEntries], gy[kSmallEntries];  // plane offsets of the entry's two columns
+#pragma unroll
+  for (int m = 0; m < kSmallEntries; ++m) {
+    accr[m] = acci[m] = 0.0;
+    const int e = threadIdx.x + m * kBT;
+    const int g = e < n_ent ? e / rr : 0, i = (e % rr) / R, j = e % R;
+    gx[m] = 2 * a.ga[g] * pl + i;
+    gy[m] = 2 * a.gb[g] * pl + j;
+  }
+  const int n_out_ent = nout * pl;
+  const long long N = a.N;
+  const long long num_tiles = (N + kSR - 1) / kSR;
+  for (long long k = 0;; ++k) {
+    const long long tile = btile(k, num_tiles, a.grid);
+    if (tile < 0) break;
+    const long long row0 = tile * kSR;
+    const bool full = row0 + kSR <= N;
+    // one tile of every input: kSR R consecutive complex values per block
+    for (int e = threadIdx.x; e < nin * pl; e += kBT) {
+      const int q = e / pl, rem = e - q * pl;
+      C2 v;
+      v.x = 0;
+      v.y = 0;
+      if (full || row0 + rem / R < N) v = reinterpret_cast<const C2 *>(a.in[q])[row0 * R + rem];
+      planes[(2 * q) * pl + rem] = v.x;
+      planes[(2 * q + 1) * pl + rem] = v.y;
+    }
+    __syncthreads();
+    // outputs: out_o[row][c] = sum_{i, k} in_i[row][k] C[i R + k][o R + c]
+#pragma unroll
+    for (int m = 0; m < kOutPerThread; ++m) {
+      const int e = threadIdx.x + m * kBT;
+      if (e >= n_out_ent) break;
+      const int o = e / pl, rem = e - o * pl, lr = rem / R, c = rem - lr * R;
+      double sr = 0, si = 0;
+      for (int i = 0; i < nin; ++i) {
+        const T *xr = planes + (2 * i) * pl + lr * R, *xi = xr + pl;
+        const double2 *cf = Cm + (size_t)(i * R) * ldc + o * R + c;
+#pragma unroll
+        for (int kk = 0; kk < R; ++kk) {
+          const double2 w = cf[kk * ldc];
+          const double ar = (double)xr[kk], ai = (double)xi[kk];
+          sr += ar * w.x - ai * w.y;
+          si += ar * w.y + ai * w.x;
+        }
+      }
+      C2 w;
+      w.x = (T)sr;
+      w.y = (T)si;
+      planes[(2 * (nin + o)) * pl + rem] = w.x;  // the rounded value, as stored
+      planes[(2 * (nin + o) + 1) * pl + rem] = w.y;
+      if (full || row0 + lr < N) reinterpret_cast<C2 *>(a.out[o])[row0 * R + rem] = w;
+    }
+    if (nout > 0) __syncthreads();
+    // Gram entries (g, i, j) += sum over the tile's rows of conj(X_a[row][i]) X_b[row][j]
+#pragma unroll
+    for (int m = 0; m < kSmallEntries; ++m) {
+      const int e = threadIdx.x + m * kBT;
+      if (e >= n_ent) break;
+      const T *xa = planes + gx[m], *xb = planes + gy[m];
+#pragma unroll 8
+      for (int lr = 0; lr < kSR; ++lr) {
+        const double ar = (double)xa[lr * R], ai = (double)xa[lr * R + pl];
+        const double br = (double)xb[lr * R], bi = (double)xb[lr * R + pl];
+        accr[m] += ar * br + ai * bi;
+        acci[m] += ar * bi - ai * br;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int m = 0; m < kSmallEntries; ++m) {
+    const int e = threadIdx.x + m * kBT;
+    if (e >= n_ent) break;
+    a.partials[(long long)e * a.grid + blockIdx.x] = make_double2(accr[m], acci[m]);
+  }
+}
+
+template <typename T>
+void launch_small(int r, const BlocksArgs &a, size_t lds, hipStream_t s) {
+  switch (r) {
+    case 1: hipLaunchKernelGGL((k_blocks_small<T, 1>), dim3(a.grid), dim3(kBT), lds, s, a); break;
+    case 2: hipLaunchKernelGGL((k_blocks_small<T, 2>), dim3(a.grid), dim3(kBT), lds, s, a); break;
+    case 3: hipLaunchKernelGGL((k_blocks_small<T, 3>), dim3(a.grid), dim3(kBT), lds, s, a); break;
+    case 4: hipLaunchKernelGGL((k_blocks_small<T, 4>), dim3(a.grid), dim3(kBT), lds, s, a); break;
+    case 5: hipLaunchKernelGGL((k_blocks_small<T, 5>), dim3(a.grid), dim3(kBT), lds, s, a); break;
+    case 6: hipLaunchKernelGGL((k_blocks_small<T, 6>), dim3(a.grid), dim3(kBT), lds, s, a); break;
+    case 7: hipLaunchKernelGGL((k_blocks_small<T, 7>), dim3(a.grid), dim3(kBT), lds, s, a); break;
+    default: hipLaunchKernelGGL((k_blocks_small<T, 8>), dim3(a.grid), dim3(kBT), lds, s, a); break;
+  }
+}
+
+template <typename T, int R>
+void set_small_attr(int cap) {
+  (void)hipFuncSetAttribute((const void *)k_blocks_small<T, R>, hipFuncAttributeMaxDynamicSharedMemorySize, cap);
+}
+
+template <typename T>
+void set_small_attrs(int cap) {
+  set_small_attr<T, 1>(cap);
+  set_small_attr<T, 2>(cap);
+  set_small_attr<T, 3>(cap);
+  set_small_attr<T, 4>(cap);
+  set_small_attr<T, 5>(cap);
+  set_small_attr<T, 6>(cap);
+  set_small_attr<T, 7>(cap);
+  set_small_attr<T, 8>(cap);
+}
+
 }  // namespace
 
 int blocks_grid(long long N) {
   const long long tiles = (N + kBR - 1) / kBR;
-  long long g = tiles < 512 ? tiles : 512;
+  long long g = tiles < 1024 ? tiles : 1024;
   if (g >= 8) g &= ~7LL;
   return (int)(g < 1 ? 1 : g);
 }
 
-size_t blocks_lds(bool fp32, int n_blocks) { return (size_t)2 * n_blocks * kPlane * (fp32 ? 4 : 8); }
+namespace {
+// the small-r path when r <= 8 and its planes fit in the LDS of a CU
+bool use_small(bool fp32, int nin, int nout, int r) {
+  return r <= 8 && small_planes_bytes(fp32, nin + nout, r) <= 160 * 1024;
+}
+}  // namespace
+
+size_t blocks_lds(bool fp32, int nin, int nout, int r) {
+  if (use_small(fp32, nin, nout, r))
+    return small_planes_bytes(fp32, nin + nout, r) +
+           (small_c_in_lds(fp32, nin, nout, r) ? (size_t)nin * nout * r * r * 16 : 0);
+  return blocks_planes_bytes(fp32, nin + nout) +
+         (blocks_c_in_lds(fp32, nin, nout, r) ? (size_t)nin * nout * r * r * 16 : 0);
+}
 
 bool launch_blocks(bool fp32, const BlocksArgs &a, hipStream_t s) {
   if (a.r < 1 || a.r > kBP || a.n_in < 0 || a.n_in > kMaxIoBlocks || a.n_out < 0 || a.n_out > kMaxIoBlocks ||
       a.n_gram < 0 || a.n_gram > kMaxGrams || a.grid < 1)
     return false;
-  const size_t lds = blocks_lds(fp32, a.n_in + a.n_out);
+  const size_t lds = blocks_lds(fp32, a.n_in, a.n_out, a.r);
   static bool attr = false;
   if (!attr) {
     const int cap = 160 * 1024;
@@ -184,9 +363,18 @@ bool launch_blocks(bool fp32, const BlocksArgs &a, hipStream_t s) {
     (void)hipFuncSetAttribute((const void *)k_blocks<float, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, cap);
     (void)hipFuncSetAttribute((const void *)k_blocks<double, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, cap);
     (void)hipFuncSetAttribute((const void *)k_blocks<double, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, cap);
+    set_small_attrs<float>(cap);
+    set_small_attrs<double>(cap);
     attr = true;
   }
   if (lds > 160 * 1024) return false;
+  if (use_small(fp32, a.n_in, a.n_out, a.r)) {
+    if (fp32)
+      launch_small<float>(a.r, a, lds, s);
+    else
+      launch_small<double>(a.r, a, lds, s);
+    return true;
+  }
   const bool few = a.n_gram <= kBW;
   if (fp32) {
     if (few) hipLaunchKernelGGL((k_blocks<float, 1>), dim3(a.grid), dim3(kBT), lds, s, a);

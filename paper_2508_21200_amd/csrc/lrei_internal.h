@@ -177,7 +177,7 @@ struct BlocksArgs {
 };
 bool launch_blocks(bool fp32, const BlocksArgs &a, hipStream_t s);
 int blocks_grid(long long N);
-size_t blocks_lds(bool fp32, int n_blocks);
+size_t blocks_lds(bool fp32, int nin, int nout, int r);
 
 // Parameters of the projected (small-space) step kernel.
 struct SmallRkParams {
