@@ -97,8 +97,10 @@ typedef struct {
   int warm;               /* lrei_warm, default LREI_WARM_ANALYTIC (RK steps; the AB
                              step always uses the direct solve)                     */
   int ab_bootstrap;       /* RK scheme for the first m-1 ABm steps, default LREI_RK4     */
-  int householder_mode;   /* 1: complement action through Householder reflectors (eq.
-                             3.3, Sec. 3.4), default; 0: orthogonal projector form      */
+  int householder_mode;   /* complement action W = V^ X12* (Sec. 3.4) in the projected
+                             coordinates: 0 (default) as (I - u u*) y diag(conj c),
+                             1 through the Householder reflectors of u (eq. 3.3);
+                             equal to rounding, 0 is faster on this GPU            */
   int use_graph;          /* 1: capture one step as a hipGraph and replay it (default)  */
   int deterministic;      /* ignored: every reduction runs in a fixed order, so results
                              are bitwise reproducible for a given launch shape        */

@@ -658,7 +658,7 @@ void lrei_default_options(lrei_options *o) {
   o->eig_max_sweeps = 40;
   o->warm = LREI_WARM_ANALYTIC;
   o->ab_bootstrap = LREI_RK4;
-  o->householder_mode = 1;
+  o->householder_mode = 0;
   o->use_graph = 1;
   o->deterministic = 1;
   o->autotune_cache = nullptr;

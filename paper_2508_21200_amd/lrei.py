@@ -156,7 +156,7 @@ class Context:
     """One LREI context (one trajectory) on a HIP device."""
 
     def __init__(self, device=0, stream=None, precision="fp64", eig_tol=1e-15, eig_max_sweeps=40,
-                 warm="analytic", householder_mode=1, use_graph=True, autotune_cache=None):
+                 warm="analytic", householder_mode=0, use_graph=True, autotune_cache=None):
         self.lib = load()
         opt = lrei_options()
         self.lib.lrei_default_options(ctypes.byref(opt))
@@ -424,7 +424,7 @@ class Batch:
     """
 
     def __init__(self, trajs, device=0, stream=None, precision="fp64", use_graph=True, hbar=1.0,
-                 householder_mode=1, warm="analytic"):
+                 householder_mode=0, warm="analytic"):
         self.lib = load()
         opt = lrei_options()
         self.lib.lrei_default_options(ctypes.byref(opt))
