@@ -18,6 +18,10 @@ What it computes, step by step in the paper's order (arXiv 2508.21200):
   definition: the r largest eigenpairs, computed exactly);
 * ``schemes``      LREI-RK (Sec. 3.6) and LREI-AB (Sec. 3.7) time steps with
   the spectrum held at Lambda_0;
+* ``adaptive``     step-size control from local error estimates (the
+  paper's future work, Sec. 6): embedded Heun-Euler 2(1) and
+  Bogacki-Shampine 3(2) pairs in LREI form, the tangent-projected error
+  estimate and the controller;
 * ``observables``  energy and magnetisation (eq. 3.6);
 * ``dense``        the dense EI method of Sec. 2 (eqs. 2.1-2.6), the dense
   commutator forms (eqs. 1.1, 1.2) and the pure-state solution (eq. 1.4);

@@ -6,7 +6,9 @@ The state is (V, lam0): rho = V diag(lam0) V*, lam0 fixed for all time
 Readings:
 * RK tableaux beyond RK2 are deferred by the paper to Butcher's book; we take
   RK1 = Euler, RK2 = the paper's Heun tableau (a21 = 1, b = (1/2, 1/2)),
-  RK3 = Kutta's third-order method, RK4 = the classical method.
+  RK3 = Kutta's third-order method, RK4 = the classical method; BS3 is the
+  third-order member of the Bogacki-Shampine 3(2) pair used for adaptive
+  stepping.
 * The AB2 coefficients as printed (3/2, -3/2) are garbled; the standard
   Adams-Bashforth coefficients are used: AB2 (3/2, -1/2), AB3 (23, -16, 5)/12,
   AB4 (55, -59, 37, -9)/24.
@@ -27,6 +29,10 @@ RK_TABLEAUX = {
     "RK4": (np.array([[0.0, 0.0, 0.0, 0.0], [0.5, 0.0, 0.0, 0.0], [0.0, 0.5, 0.0, 0.0],
                       [0.0, 0.0, 1.0, 0.0]]),
             np.array([1.0, 2.0, 2.0, 1.0]) / 6.0),
+    # Bogacki-Shampine (1989): the third-order solution of the adaptive pair
+    # in oracle/adaptive.py, as a fixed-step scheme
+    "BS3": (np.array([[0.0, 0.0, 0.0], [0.5, 0.0, 0.0], [0.0, 0.75, 0.0]]),
+            np.array([2.0, 3.0, 4.0]) / 9.0),
 }
 
 AB_COEFFS = {
