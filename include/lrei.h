@@ -58,6 +58,13 @@ typedef enum {
   LREI_AB2 = 12, LREI_AB3 = 13, LREI_AB4 = 14
 } lrei_scheme;
 
+/* Embedded Runge-Kutta pairs for adaptive stepping (lrei_evolve_adaptive).
+ * HE21: Heun's method (order 2) with Euler embedded (order 1).
+ * BS32: Bogacki-Shampine 3(2), order 3 with an order-2 solution that also
+ * weights the right-hand side at the new state; costs the same four H.V
+ * passes per attempt as an RK4 step and three stage eigensolves. */
+typedef enum { LREI_PAIR_HE21 = 21, LREI_PAIR_BS32 = 32 } lrei_pair;
+
 /* LREI_FP64: every N-space pass in complex FP64.
  * LREI_MIXED: N-space passes (H.V, Gram products, basis combination) in
  * complex FP32 with per-tile FP32 MFMA products accumulated across tiles in
@@ -166,6 +173,44 @@ LREI_API lrei_status lrei_set_rho(lrei_ctx *ctx, int r, const double *lambda, co
  * change restarts it with the bootstrap scheme.  On failure the state is that
  * of the last completed step. */
 LREI_API lrei_status lrei_step(lrei_ctx *ctx, int model, int scheme, double dt, double kappa, int n_steps);
+
+/* Outcome of lrei_evolve_adaptive. */
+typedef struct {
+  double t;          /* time advanced by the accepted steps (t_span when reached) */
+  double h_next;     /* step the controller proposes next                         */
+  double err_last;   /* error estimate of the last attempt (NaN: non-finite)      */
+  double err_max;    /* largest estimate among the accepted steps                 */
+  int accepted;      /* accepted steps                                            */
+  int rejected;      /* rejected attempts                                         */
+  int attempts;      /* attempts that ran                                         */
+  int reached;       /* 1: t_span reached                                         */
+} lrei_adapt_result;
+
+/* Advances the state by t_span > 0 with step-size control from local error
+ * estimates (the paper's outlook, Sec. 6), using the embedded pair `pair`
+ * (lrei_pair) in LREI form: each attempt is an LREI-RK step (Sec. 3.6) with
+ * the pair's higher-order weights; the two candidate matrices of eq. 3.9
+ * (weights b and b_hat) differ by E = h sum_l (b_l - b_hat_l) f(rho_l), and
+ * the estimate is the Frobenius norm of the part of E tangent to the
+ * fixed-spectrum manifold at the new state (the distance of the two projected
+ * candidates to first order).  An attempt is accepted when the estimate is
+ * <= tol (an absolute bound on the local error of rho in the Frobenius norm);
+ * the next step is h min(5, max(0.2, 0.9 (tol / err)^(1 / (q + 1)))), q the
+ * embedded order, without growth right after a rejection, clamped to
+ * [h_min, h_max] and to the time left; the last step ends on t_span exactly.
+ * The controller runs on the GPU between attempts (no host round trip per
+ * attempt); the host checks its state after each batch of attempts.
+ * Arguments: 0 < h_min <= h_init, h_min <= h_max, tol > 0, max_attempts >= 1;
+ * kappa >= 0.  `out` (may be NULL) receives the outcome in every case.
+ * Returns LREI_OK when t_span is reached; LREI_E_NOTCONVERGED when an attempt
+ * at h <= h_min is rejected or max_attempts attempts ran first: the state is
+ * then that of the last accepted step and out->t says how far it got.  A
+ * non-finite attempt counts as a rejection.  Invalidates the Adams-Bashforth
+ * history.  Mixed precision: tol should stay well above the FP32 storage
+ * rounding of the state (about 1e-6 relative). */
+LREI_API lrei_status lrei_evolve_adaptive(lrei_ctx *ctx, int model, int pair, double kappa, double t_span,
+                                          double tol, double h_init, double h_min, double h_max, int max_attempts,
+                                          lrei_adapt_result *out);
 
 /* Copies the current state out: lambda (r values, always Lambda_0, Sec. 3.6)
  * and V (N x r complex128, host or device pointer).  Either may be NULL. */

@@ -96,7 +96,12 @@ struct lrei_ctx {
   DevBuf ab_coords[2], ab_UUg, ab_c1g, ab_gBg, ab_Cb, ab_Cc, ab_work, ab_partials;
   int ab_grid = 1;
 
-  // captured step graph
+  // adaptive stepping: device-resident controller state (kCtlLen doubles);
+  // pass_skip is handed to the N-space passes of an attempt being enqueued
+  DevBuf ctl;
+  const double *pass_skip = nullptr;
+
+  // captured step graph (g_dt < 0: an adaptive attempt)
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int g_model = -1, g_scheme = -1;
@@ -202,6 +207,7 @@ int hv_launches(lrei_ctx *ctx, int r, int grid, int mode, const void *prev, cons
   a.partials = partials;
   a.grid = grid;
   a.partial_cap = partial_cap;
+  a.skip = ctx->pass_skip;
   const size_t ns = ctx->sweeps.size();
   int slots = 0;
   if (!sweeps || ns <= 1) {
@@ -376,9 +382,28 @@ SmallRkParams rk_params(lrei_ctx *ctx, int model, int scheme, double dt, double 
 // then stage j itself on the side stream, so that the extension of stage
 // j + 1 and the later passes overlap stage j; the combination after the last
 // stage.
+void enqueue_stages(lrei_ctx *ctx, const SmallRkParams &p);
+
 void enqueue_rk_step(lrei_ctx *ctx, int model, int scheme, double dt, double kappa) {
-  const SmallRkParams p = rk_params(ctx, model, scheme, dt, kappa);
-  const int s = p.s;
+  enqueue_stages(ctx, rk_params(ctx, model, scheme, dt, kappa));
+}
+
+// One attempt of an adaptive step: the stages of the pair's tableau (and the
+// error stage), the controller's decision on the device, the combination
+// (the old state again when the attempt is rejected).  Every kernel of the
+// attempt does nothing once the controller has reached t_end or failed.
+void enqueue_attempt(lrei_ctx *ctx, const SmallRkParams &p) {
+  launch_attempt_begin(p.ctl, ctx->stream);
+  ctx->pass_skip = p.ctl + kCtlSkip;
+  enqueue_stages(ctx, p);
+  ctx->pass_skip = nullptr;
+}
+
+// Passes, basis extensions and stages of one RK step (or adaptive attempt),
+// then the combination V_new = [P_0 .. P_{nblocks-1}] C.
+void enqueue_stages(lrei_ctx *ctx, const SmallRkParams &p) {
+  // an error stage that weights f at the new state needs one more pass
+  const int s = (p.ctl && p.err_stage == p.s) ? p.s + 1 : p.s;
   (void)hipEventRecord(ctx->ev_fork, ctx->stream);
   (void)hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0);
   (void)hipStreamWaitEvent(ctx->basis, ctx->ev_fork, 0);
@@ -399,8 +424,24 @@ void enqueue_rk_step(lrei_ctx *ctx, int model, int scheme, double dt, double kap
   (void)hipEventRecord(ctx->ev_join, ctx->side);
   (void)hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0);
   const void *bl[kMaxBlocks];
-  for (int i = 0; i <= s; ++i) bl[i] = ctx->blocks[i].p;
-  launch_combine(ctx->fp32, bl, s + 1, ctx->ws.Cfin, ctx->blocks[0].p, ctx->N, ctx->r, ctx->grid, ctx->stream);
+  for (int i = 0; i < p.nblocks; ++i) bl[i] = ctx->blocks[i].p;
+  launch_combine(ctx->fp32, bl, p.nblocks, ctx->ws.Cfin, ctx->blocks[0].p, ctx->N, ctx->r, ctx->grid, ctx->stream,
+                 p.ctl ? p.ctl + kCtlSkip : nullptr);
+}
+
+// Projected-step parameters of an adaptive attempt with an embedded pair.
+SmallRkParams adapt_params(lrei_ctx *ctx, int model, int pair, double kappa) {
+  SmallRkParams p = rk_params(ctx, model, LREI_RK4, 0.0, kappa);
+  int s = 0, err_stage = 0, q = 0;
+  pair_tableau(pair, s, p.a, p.b, p.e, err_stage, q);
+  p.s = s;
+  p.nblocks = err_stage == s ? s + 2 : s + 1;
+  p.err_stage = err_stage;
+  p.order_low = q;
+  p.ctl = (double *)ctx->ctl.p;
+  p.h = 0.0;  // the step comes from the controller state
+  p.lds_elems = small_lds_elems(p.nblocks * ctx->r, ctx->r);
+  return p;
 }
 
 // ---- ABm schemes -------------------------------------------------------------
@@ -721,6 +762,7 @@ void lrei_destroy(lrei_ctx *ctx) {
   ctx->partials.release();
   ctx->ws_buf.release();
   ctx->stats_buf.release();
+  ctx->ctl.release();
   ctx->lam_dev.release();
   ctx->dt.release();
   for (auto &set : ctx->ab_U)
@@ -1053,6 +1095,129 @@ lrei_status lrei_step(lrei_ctx *ctx, int model, int scheme, double dt, double ka
   ctx->stats.eig_phase_ms[4] = h[29];
   ctx->stats.eig_phase_ms[5] = h[30];
   return LREI_OK;
+}
+
+lrei_status lrei_evolve_adaptive(lrei_ctx *ctx, int model, int pair, double kappa, double t_span, double tol,
+                                 double h_init, double h_min, double h_max, int max_attempts,
+                                 lrei_adapt_result *out) {
+  if (!ctx) return LREI_E_INVALID;
+  if (out) {
+    *out = lrei_adapt_result{};
+    out->err_last = NAN;
+  }
+  if (!ctx->have_rho) return ctx->fail(LREI_E_STATE, "set rho before stepping");
+  if (model != LREI_QLL && model != LREI_QLLG) return ctx->fail(LREI_E_INVALID, "unknown model");
+  if (pair != LREI_PAIR_HE21 && pair != LREI_PAIR_BS32)
+    return ctx->fail(LREI_E_INVALID, "unknown embedded pair (LREI_PAIR_HE21, LREI_PAIR_BS32)");
+  if (!(t_span > 0) || !std::isfinite(t_span)) return ctx->fail(LREI_E_INVALID, "t_span must be positive and finite");
+  if (!(tol > 0) || !std::isfinite(tol)) return ctx->fail(LREI_E_INVALID, "tol must be positive and finite");
+  if (!(h_min > 0) || !(h_init >= h_min) || !(h_max >= h_min) || !std::isfinite(h_init) || std::isnan(h_max))
+    return ctx->fail(LREI_E_INVALID, "need 0 < h_min <= h_init and h_min <= h_max");
+  if (max_attempts < 1) return ctx->fail(LREI_E_INVALID, "max_attempts must be >= 1");
+  if (!(kappa >= 0) || !std::isfinite(kappa)) return ctx->fail(LREI_E_INVALID, "kappa must be >= 0 and finite");
+  kappa *= 1.0 - ctx->mix_p;  // damping of the low-rank part (full-rank admixture)
+  if (ctx->opt.warm == LREI_WARM_LEARNED && (!ctx->net || ctx->net_r != ctx->r))
+    return ctx->fail(LREI_E_STATE, "LREI_WARM_LEARNED needs an attached network of the state's rank");
+  HIPCHK(hipSetDevice(ctx->device));
+  ab_reset(ctx);
+  if (!ctx->ctl.ensure(kCtlLen * sizeof(double))) return ctx->fail(LREI_E_NOMEM, "allocation failed");
+  const auto t0 = std::chrono::steady_clock::now();
+  const size_t vbytes = (size_t)ctx->N * ctx->r * ctx->elem();
+  HIPCHK(hipMemcpyAsync(ctx->save.p, ctx->blocks[0].p, vbytes, hipMemcpyDeviceToDevice, ctx->stream));
+  double zeros[kStatsLen] = {0};
+  HIPCHK(hipMemcpyAsync(ctx->stats_buf.p, zeros, sizeof(zeros), hipMemcpyHostToDevice, ctx->stream));
+  double c[kCtlLen] = {0};
+  c[kCtlH] = std::min(std::min(h_init, h_max), t_span);
+  c[kCtlTEnd] = t_span;
+  c[kCtlTol] = tol;
+  c[kCtlHMin] = h_min;
+  c[kCtlHMax] = h_max;
+  HIPCHK(hipMemcpyAsync(ctx->ctl.p, c, sizeof(c), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  const SmallRkParams p = adapt_params(ctx, model, pair, kappa);
+  const bool use_graph = ctx->opt.use_graph != 0;
+  int launched = 0;
+  if (use_graph && !(ctx->exec && ctx->g_model == model && ctx->g_scheme == pair && ctx->g_dt < 0 &&
+                     ctx->g_kappa == kappa)) {
+    ctx->drop_graph();
+    // launch attributes are set on first use, outside capture: the eager
+    // attempt is the first attempt
+    enqueue_attempt(ctx, p);
+    HIPCHK(hipGetLastError());
+    ++launched;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    HIPCHK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+    enqueue_attempt(ctx, p);
+    HIPCHK(hipStreamEndCapture(ctx->stream, &ctx->graph));
+    HIPCHK(hipGraphInstantiate(&ctx->exec, ctx->graph, nullptr, nullptr, 0));
+    ctx->g_model = model;
+    ctx->g_scheme = pair;
+    ctx->g_dt = -1.0;
+    ctx->g_kappa = kappa;
+  }
+  // batches of attempts between reads of the controller state: as many as
+  // the current step needs to reach t_span (at most 16); attempts queued
+  // after the end do nothing
+  for (;;) {
+    HIPCHK(hipMemcpyAsync(c, ctx->ctl.p, sizeof(c), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (c[kCtlDone] != 0.0 || c[kCtlFailed] != 0.0 || launched >= max_attempts) break;
+    const double need = std::ceil((t_span - c[kCtlT]) / c[kCtlH]);
+    int batch = need >= 16.0 ? 16 : (need < 1.0 ? 1 : (int)need);
+    batch = std::min(batch, max_attempts - launched);
+    for (int k = 0; k < batch; ++k) {
+      if (use_graph)
+        HIPCHK(hipGraphLaunch(ctx->exec, ctx->stream));
+      else
+        enqueue_attempt(ctx, p);
+    }
+    HIPCHK(hipGetLastError());
+    launched += batch;
+  }
+  double h[kStatsLen];
+  lrei_status st = read_stats(ctx, h);
+  if (st != LREI_OK) return st;
+  const auto t1 = std::chrono::steady_clock::now();
+  if (h[13] != 0) {
+    HIPCHK(hipMemcpyAsync(ctx->blocks[0].p, ctx->save.p, vbytes, hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return ctx->fail(LREI_E_NOTCONVERGED,
+                     "Jacobi eigensolve hit the sweep limit; state restored to the start of the call");
+  }
+  const bool reached = c[kCtlDone] != 0.0;
+  if (out) {
+    out->t = c[kCtlT];
+    out->h_next = c[kCtlH];
+    out->err_last = c[kCtlErr];
+    out->err_max = c[kCtlErrMax];
+    out->accepted = (int)c[kCtlAccepted];
+    out->rejected = (int)c[kCtlRejected];
+    out->attempts = (int)c[kCtlAttempts];
+    out->reached = reached ? 1 : 0;
+  }
+  ctx->steps_done += (int64_t)c[kCtlAccepted];
+  ctx->stats.steps_done = ctx->steps_done;
+  ctx->stats.eigensolves += (int64_t)h[11];
+  ctx->stats.warm_accepted += (int64_t)h[9];
+  ctx->stats.warm_rejected += (int64_t)h[31];
+  ctx->stats.warm_iterations += (int64_t)h[12];
+  ctx->stats.dropped_directions = (int32_t)h[2];
+  ctx->stats.min_pivot_ratio = h[3];
+  ctx->stats.ortho_error = h[4];
+  ctx->stats.energy = h[5];
+  ctx->stats.last_step_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  for (int k = 0; k < 8; ++k) ctx->stats.phase_ms[k] = h[16 + k];
+  for (int k = 0; k < 4; ++k) ctx->stats.eig_phase_ms[k] = h[24 + k];
+  ctx->stats.eig_phase_ms[4] = h[29];
+  ctx->stats.eig_phase_ms[5] = h[30];
+  if (reached) return LREI_OK;
+  char msg[160];
+  if (c[kCtlFailed] != 0.0)
+    std::snprintf(msg, sizeof(msg), "an attempt at h <= h_min was rejected at t = %.6g; state of the last accepted step",
+                  c[kCtlT]);
+  else
+    std::snprintf(msg, sizeof(msg), "max_attempts reached at t = %.6g; state of the last accepted step", c[kCtlT]);
+  return ctx->fail(LREI_E_NOTCONVERGED, msg);
 }
 
 lrei_status lrei_get_rho(lrei_ctx *ctx, double *lambda, void *V, int v_is_device) {

@@ -68,6 +68,35 @@ inline void tableau(int scheme, int &s, double a[kMaxStages][kMaxStages], double
   }
 }
 
+// Embedded pairs for adaptive stepping: the tableau (a, b) that advances the
+// state, the error weights e = b - b_hat over the right-hand sides the
+// estimate uses, the stage that forms the estimate (s - 1, or s when b_hat
+// also weights f at the new state) and the order q of the embedded solution.
+// HE21: Heun with Euler embedded.  BS32: Bogacki-Shampine 3(2),
+// b_hat = (7/24, 1/4, 1/3, 1/8).
+inline bool pair_tableau(int pair, int &s, double a[kMaxStages][kMaxStages], double b[kMaxStages],
+                         double e[kMaxStages], int &err_stage, int &q) {
+  for (int i = 0; i < kMaxStages; ++i) {
+    b[i] = e[i] = 0;
+    for (int j = 0; j < kMaxStages; ++j) a[i][j] = 0;
+  }
+  switch (pair) {
+    case LREI_PAIR_HE21:
+      s = 2; a[1][0] = 1; b[0] = b[1] = 0.5;
+      e[0] = 0.5 - 1.0; e[1] = 0.5;
+      err_stage = 1; q = 1;
+      return true;
+    case LREI_PAIR_BS32:
+      s = 3; a[1][0] = 0.5; a[2][1] = 0.75;
+      b[0] = 2.0 / 9; b[1] = 3.0 / 9; b[2] = 4.0 / 9;
+      e[0] = 2.0 / 9 - 7.0 / 24; e[1] = 3.0 / 9 - 0.25; e[2] = 4.0 / 9 - 1.0 / 3; e[3] = -0.125;
+      err_stage = 3; q = 2;
+      return true;
+    default:
+      return false;
+  }
+}
+
 // Device copies of a term table: off-diagonal records in FP64 and FP32, the
 // diagonal terms and the per-row diagonal d(x) in both precisions.
 struct DevTerms {

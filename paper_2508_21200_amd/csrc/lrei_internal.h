@@ -89,6 +89,7 @@ struct ChebArgs {
   int *sched;
   int partial_cap;
   int chunks;           // set by prepare_cheb: Gram partial slots used (0: one per workgroup)
+  const double *skip;   // the pass does nothing while *skip != 0 (nullptr: always runs)
 };
 
 // Launches one H.V pass; returns the number of Gram partial slots written
@@ -121,6 +122,7 @@ struct CombineArgs {
   void *out;
   long long N;
   int r, grid;
+  const double *skip;  // nothing is written while *skip != 0 (nullptr: always runs)
 };
 // Batched combinations: every job has the same nb and padded width RP (16 or 32).
 void launch_combine_batch(bool fp32, int RP, int nblocks, const BatchLaunch &b, int total_wg, hipStream_t s);
@@ -135,7 +137,7 @@ void launch_reduce_batch(const BatchLaunch &b, int total_wg, hipStream_t s);
 void launch_diag_values(const DevDiagTerm *diag, int n_diag, long long N, double *d64, float *d32, hipStream_t s);
 int cheb_elems_per_lane(bool fp32, int r);
 void launch_combine(bool fp32, const void *const *blocks, int nblocks, const double2 *C, void *out,
-                    long long N, int r, int grid, hipStream_t s);
+                    long long N, int r, int grid, hipStream_t s, const double *skip = nullptr);
 void launch_reduce(const double2 *partials, int count, int len, double2 *out, hipStream_t s);
 void launch_convert(bool to_fp32, const void *src, void *dst, long long n_complex, hipStream_t s);
 // dst rows = src rows moved by the site -> bit map pos (forward) or gathered back (inverse).
@@ -179,6 +181,31 @@ bool launch_blocks(bool fp32, const BlocksArgs &a, hipStream_t s);
 int blocks_grid(long long N);
 size_t blocks_lds(bool fp32, int nin, int nout, int r);
 
+// Device-resident state of the step-size controller (adaptive stepping, one
+// double each).  The stage that forms the error estimate reads the step from
+// kCtlH, decides, and writes the next step; every kernel of an attempt does
+// nothing while kCtlSkip is set (copied from kCtlDone | kCtlFailed when the
+// attempt begins).
+enum CtlSlot {
+  kCtlH = 0,         // step of the next attempt
+  kCtlT,             // time reached (accepted steps)
+  kCtlTEnd,          // time to reach
+  kCtlTol,           // tolerance on the error estimate
+  kCtlHMin,
+  kCtlHMax,
+  kCtlErr,           // estimate of the last attempt
+  kCtlAccepted,
+  kCtlRejected,
+  kCtlDone,          // t_end reached
+  kCtlFailed,        // rejected at h <= h_min
+  kCtlSkip,
+  kCtlAfterReject,   // the last attempt was rejected (no growth of h next)
+  kCtlErrMax,        // largest estimate among accepted steps
+  kCtlAttempts,      // attempts that ran
+  kCtlLen = 16
+};
+void launch_attempt_begin(double *ctl, hipStream_t s);
+
 // Parameters of the projected (small-space) step kernel.
 struct SmallRkParams {
   int r, s, nblocks;      // nblocks = s + 1
@@ -199,6 +226,15 @@ struct SmallRkParams {
   float *rec;
   int *rec_count;
   int rec_cap;
+  // adaptive stepping (ctl == nullptr: fixed step h): controller state, the
+  // stage that forms the error estimate (s - 1, or s for a pair that also
+  // weights the right-hand side at the new state; that stage then forms no
+  // stage matrix), the error weights b - b_hat over f_0 .. f_{err_stage} and
+  // the order q of the embedded solution
+  double *ctl;
+  int err_stage;
+  int order_low;
+  double e[kMaxStages];
 };
 
 // Device layout of the small workspace (doubles).

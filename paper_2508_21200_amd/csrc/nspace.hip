@@ -492,6 +492,7 @@ __device__ __forceinline__ void cheb_body(const ChebArgs &a, int wg, unsigned ch
 template <typename T, int E, bool CPLX, int MI, bool DYN>
 __global__ __launch_bounds__(kThreads) void k_cheb(ChebArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
+  if (a.skip && *a.skip != 0.0) return;  // the same for every workgroup of the launch
   cheb_body<T, E, CPLX, MI, !DYN, DYN>(a, blockIdx.x, smem);
 }
 
@@ -618,6 +619,7 @@ __device__ __forceinline__ void combine_body(const CombineArgs &a, int wg, unsig
 template <typename T, int RP>
 __global__ __launch_bounds__(kThreads) void k_combine(CombineArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
+  if (a.skip && *a.skip != 0.0) return;
   combine_body<T, RP>(a, blockIdx.x, smem);
 }
 
@@ -1015,8 +1017,9 @@ void launch_diag_values(const DevDiagTerm *diag, int n_diag, long long N, double
 }
 
 void launch_combine(bool fp32, const void *const *blocks, int nblocks, const double2 *C, void *out,
-                    long long N, int r, int grid, hipStream_t s) {
+                    long long N, int r, int grid, hipStream_t s, const double *skip) {
   CombineArgs a;
+  a.skip = skip;
   for (int i = 0; i < kMaxBlocks; ++i) a.blocks[i] = i < nblocks ? blocks[i] : nullptr;
   a.nb = nblocks;
   a.C = C;

@@ -1446,7 +1446,8 @@ __device__ void rhs_coords(const double2 *u, const double2 *y, int m, int D, int
 }
 
 // Packed (lower, column-major) Hermitian stage matrix of order m:
-// K = u1 diag(lam) u1* + sum_l coef_l (z_l u_l* + u_l w_l*)   (eqs. 3.7-3.9),
+// K = u1 diag(lam) u1* + sum_l coef_l (z_l u_l* + u_l w_l*)   (eqs. 3.7-3.9;
+// lam == nullptr: without the first term),
 // formed as K = (P Q* + Q P*) / 2 over the factor pairs (P, Q) = (u1 diag(lam),
 // u1), (coef_l z_l, u_l), (coef_l u_l, w_l), so that K is Hermitian to the last
 // bit.  Lower 16 x 16 tiles, one per wave at a time, on FP64 MFMA with the
@@ -1475,6 +1476,7 @@ __device__ void stage_matrix(double2 *K, int m, int r, const double2 *u1, const 
       const double2 *P, *Q;
       double sc = 1.0;
       if (ch == 0) {
+        if (!lam) continue;  // no u1 diag(lam) u1* term
         P = u1;
         Q = u1;
       } else {
@@ -1598,13 +1600,16 @@ constexpr int kWarmRetry = 8;
 // hbar is the step the in-span rotation covers.  Features: Re, Im of G / |G|_F
 // (G = Herm(u* y), y = H u), s |G|_F, kappa.
 
+// The step of the current attempt: fixed, or the controller's (adaptive).
+__device__ inline double step_size(const SmallRkParams &p) { return p.ctl ? p.ctl[kCtlH] : p.h; }
+
 __device__ double stage_step(const SmallRkParams &p, int j) {
   double cin = 0, cout = 0;
   for (int l = 0; l < p.s; ++l) {
     cin += j > 0 ? p.a[j][l] : 0.0;
     cout += (j + 1 == p.s) ? p.b[l] : p.a[j + 1][l];
   }
-  return (cout - cin) * p.h / p.hbar;
+  return (cout - cin) * step_size(p) / p.hbar;
 }
 
 // G (r x r, Hermitian part of Gu = u* y, global) -> features f (2 r^2 + 2, LDS).
@@ -1697,8 +1702,81 @@ struct PhaseClock {
   double acc[8];
 };
 
+// ---- adaptive stepping: error estimate and step-size controller -----------
+//
+// The two candidate matrices of eq. 3.9 (weights b and the embedded b_hat)
+// differ by E = h sum_l e_l (z_l u_l* + u_l w_l*), e = b - b_hat, over the
+// right-hand sides f_0 .. f_k.  The projection onto the fixed spectrum keeps,
+// to first order, the part of E tangent to the fixed-spectrum manifold at the
+// new state ub:  |T(E)|^2 = 2 |E ub - ub M|^2 + sum_{i != j, lam_i != lam_j}
+// |M_ij|^2 with M = ub* E ub.  The estimate |T(E)|_F decides the attempt
+// (accept when <= tol) and the next step, h min(facmax, max(facmin,
+// 0.9 (tol / err)^(1 / (q + 1)))) clamped to [h_min, h_max] and to the time
+// left (Hairer, Norsett & Wanner, Sec. II.4); a rejected attempt keeps the
+// state (C = [I; 0]: V_new = P_0 = V).
+constexpr double kFac = 0.9, kFacMin = 0.2, kFacMax = 5.0;
+
+__device__ __attribute__((noinline)) void adapt_control(const SmallRkParams &p, const SmallWs &ws, int k, double h, const double2 *ub,
+                              double2 *E, double2 *EV, double2 *M, double *coef) {
+  __shared__ double red[NW];
+  __shared__ int s_accept;
+  const int r = p.r, D = p.nblocks * r;
+  if (threadIdx.x <= k) coef[threadIdx.x] = h * p.e[threadIdx.x];
+  __syncthreads();
+  stage_matrix(E, D, r, nullptr, nullptr, k + 1, ws.stage, (size_t)3 * D * r, ws.stage + D * r, (size_t)3 * D * r,
+               ws.stage + 2 * D * r, (size_t)3 * D * r, coef);
+  hemm_packed(EV, E, D, ub, r);
+  zgemm(M, r, ub, r, true, EV, r, r, r, D);  // M = ub* E ub
+  double part = 2.0 * resid_part(EV, ub, M, D, r);
+  for (int e = threadIdx.x; e < r * r; e += NT) {
+    const int i = e / r, c = e % r;
+    if (i != c && p.lam[i] != p.lam[c]) part += cabs2(M[e]);
+  }
+  int bad = 0;
+  for (int e = threadIdx.x; e < D * r; e += NT)
+    if (!isfinite(ws.Cfin[e].x) || !isfinite(ws.Cfin[e].y)) bad = 1;
+  bad = __syncthreads_or(bad);
+  const double sum = block_sum(part, red);
+  const double err = bad ? NAN : sqrt(sum);
+  if (threadIdx.x == 0) {
+    double *c = p.ctl;
+    const double t = c[kCtlT], t_end = c[kCtlTEnd], tol = c[kCtlTol];
+    const double h_min = c[kCtlHMin], h_max = c[kCtlHMax];
+    const bool last = h >= t_end - t;  // this attempt was clamped to end on t_end
+    const bool finite = isfinite(err);
+    const bool accept = finite && err <= tol;
+    double fac = !finite ? kFacMin : (err > 0.0 ? kFac * pow(tol / err, 1.0 / (p.order_low + 1)) : kFacMax);
+    fac = fmin(c[kCtlAfterReject] != 0.0 ? 1.0 : kFacMax, fmax(kFacMin, fac));
+    double h_new = fmin(h * fac, h_max);
+    double t_new = t;
+    if (accept) {
+      t_new = last ? t_end : t + h;
+      c[kCtlAccepted] += 1.0;
+      c[kCtlErrMax] = fmax(c[kCtlErrMax], err);
+    } else {
+      c[kCtlRejected] += 1.0;
+      if (h <= h_min) c[kCtlFailed] = 1.0;
+    }
+    h_new = fmax(h_new, h_min);
+    const bool done = accept && last;
+    c[kCtlH] = done ? h_new : fmin(h_new, t_end - t_new);
+    c[kCtlT] = t_new;
+    c[kCtlDone] = done ? 1.0 : 0.0;
+    c[kCtlErr] = err;
+    c[kCtlAfterReject] = accept ? 0.0 : 1.0;
+    c[kCtlAttempts] += 1.0;
+    s_accept = accept ? 1 : 0;
+  }
+  __syncthreads();
+  if (!s_accept)
+    for (int e = threadIdx.x; e < D * r; e += NT)
+      ws.Cfin[e] = make_double2(e / r == e % r ? 1.0 : 0.0, 0.0);
+  __syncthreads();
+}
+
 __device__ __forceinline__ void rk_basis(const SmallRkParams &p, const SmallWs &ws, int j, double2 *s_arena,
                                          StepShared &sh, PhaseClock &pc) {
+  if (p.ctl && p.ctl[kCtlSkip] != 0.0) return;  // an attempt after the end (uniform)
   const int r = p.r, nb = p.nblocks, D = nb * r, rr = r * r;
   double2 *G = ws.gamma, *R = ws.R, *Ri = ws.Rinv;
   double2 *S22 = ws.Hh;                 // 2r x 2r Schur complement / R22^{-1} scratch
@@ -1848,6 +1926,7 @@ __device__ __forceinline__ void rk_stage(const SmallRkParams &p, const SmallWs &
   double *stats = ws.stats;
   const int arena = p.lds_elems;
   const int k1 = (j + 2) * r;
+  if (p.ctl && p.ctl[kCtlSkip] != 0.0) return;  // an attempt after the end (uniform)
   if (threadIdx.x == 0) {
     pc.mark = now_ticks();
     for (int k = 3; k < 8; ++k) pc.acc[k] = 0.0;
@@ -1873,7 +1952,7 @@ __device__ __forceinline__ void rk_stage(const SmallRkParams &p, const SmallWs &
   }
 
   // ---- 3. stage j -------------------------------------------------------------
-  const double h = p.h;
+  const double h = step_size(p);
   const ModelCoef mc{p.model, p.kappa, p.hbar, p.lam};
   {
     double2 *u = ws.stage + (3 * j + 0) * D * r;
@@ -1908,6 +1987,12 @@ __device__ __forceinline__ void rk_stage(const SmallRkParams &p, const SmallWs &
       if (threadIdx.x == 0 && stats[28] < 0 && (f1 | f2 | f3)) stats[28] = 10 * j + (f1 ? 1 : (f2 ? 2 : 3));
     }
     lap(4);
+    if (j == s) {
+      // error stage of a pair that also weights f at the new state (u = that
+      // state): the estimate and the controller, no stage matrix
+      const int npl = D * (D + 1) / 2;
+      adapt_control(p, ws, j, h, u, npl <= arena ? s_arena : Kg, Yc, X11, sh.coef);
+    } else {
     // learned start rotation: the stage's features (recorded as a training
     // sample and/or fed to the network) and the predictor's rotation R (into
     // tmp), in the arena before the stage matrix takes it
@@ -1992,7 +2077,17 @@ __device__ __forceinline__ void rk_stage(const SmallRkParams &p, const SmallWs &
       for (int e = threadIdx.x; e < D * r; e += NT) t1[e] = ws.Cfin[e];
       __syncthreads();
       zgemm(ws.Cfin, r, Ri, D, false, t1, r, D, r, D);  // C = R^{-1} u_final
+      if (p.ctl && p.err_stage == s) {
+        // the error stage starts from the new state
+        double2 *un = ws.stage + (3 * s + 0) * D * r;
+        for (int e = threadIdx.x; e < D * r; e += NT) un[e] = t1[e];
+        __syncthreads();
+      } else if (p.ctl) {
+        const int npl = D * (D + 1) / 2;
+        adapt_control(p, ws, j, h, t1, npl <= arena ? s_arena : Kg, Yc, X11, sh.coef);
+      }
     }
+    }  // stage j < s
   }
   lap(7);
   int bad = 0;
@@ -2015,7 +2110,7 @@ __device__ __forceinline__ void rk_stage(const SmallRkParams &p, const SmallWs &
       stats[8] = s;  // eigensolves this step
       // running totals over the steps of one call (zeroed by the host per call)
       stats[11] += s;
-      stats[14] += bad;
+      if (!p.ctl) stats[14] += bad;  // adaptive: the controller rejects the attempt instead
       stats[15] += 1;
     }
   }
@@ -2091,6 +2186,18 @@ void launch_small_rk_basis(const SmallRkParams &p, const SmallWs &ws, int j, hip
 void launch_small_rk_stage(const SmallRkParams &p, const SmallWs &ws, int j, hipStream_t s) {
   small_rk_attrs();
   hipLaunchKernelGGL(k_small_rk, dim3(1), dim3(NT), (size_t)p.lds_elems * sizeof(double2), s, p, ws, j);
+}
+
+namespace {
+// Start of an adaptive attempt: every kernel of the attempt does nothing if
+// the integration has already ended or failed.
+__global__ void k_attempt_begin(double *ctl) {
+  if (threadIdx.x == 0) ctl[kCtlSkip] = (ctl[kCtlDone] != 0.0 || ctl[kCtlFailed] != 0.0) ? 1.0 : 0.0;
+}
+}  // namespace
+
+void launch_attempt_begin(double *ctl, hipStream_t s) {
+  hipLaunchKernelGGL(k_attempt_begin, dim3(1), dim3(64), 0, s, ctl);
 }
 
 // ---------------------------------------------------------------------------

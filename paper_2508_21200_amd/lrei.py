@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(_HERE, "liblrei.so")
 
 LREI_OK = 0
 LREI_E_INVALID = 1
+LREI_E_NOTCONVERGED = 3
 STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_NOMEM", 3: "E_NOTCONVERGED", 4: "E_DEVICE",
                 5: "E_STATE", 6: "E_NUMERIC"}
 MODELS = {"qLL": 0, "qLLG": 1}
@@ -62,6 +63,15 @@ class lrei_traj_desc(ctypes.Structure):
                 ("kappa", ctypes.c_double)]
 
 
+class lrei_adapt_result(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_double), ("h_next", ctypes.c_double), ("err_last", ctypes.c_double),
+                ("err_max", ctypes.c_double), ("accepted", ctypes.c_int), ("rejected", ctypes.c_int),
+                ("attempts", ctypes.c_int), ("reached", ctypes.c_int)]
+
+
+PAIRS = {"HE21": 21, "BS32": 32}
+
+
 class LreiError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
@@ -80,6 +90,9 @@ _SIGS = {
     "lrei_set_hamiltonian": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, _P, _P, ctypes.c_double]),
     "lrei_set_rho": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.c_int]),
     "lrei_step": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int]),
+    "lrei_evolve_adaptive": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                            ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                            ctypes.c_int, ctypes.POINTER(lrei_adapt_result)]),
     "lrei_get_rho": (ctypes.c_int, [_P, _P, _P, ctypes.c_int]),
     "lrei_observables": (ctypes.c_int, [_P, _P, _P]),
     "lrei_get_stats": (ctypes.c_int, [_P, ctypes.POINTER(lrei_stats)]),
@@ -213,6 +226,32 @@ class Context:
     def step(self, model, scheme, dt, kappa, n_steps=1):
         self._check(self.lib.lrei_step(self.h, MODELS[model], SCHEMES[scheme], float(dt), float(kappa),
                                        int(n_steps)))
+
+    def evolve_adaptive(self, model, kappa, t_span, tol, h_init, h_min=None, h_max=None, max_attempts=100000,
+                        pair="BS32"):
+        """Advances by t_span with step-size control (lrei_evolve_adaptive).
+        Returns a dict with t, h_next, err_last, err_max, accepted, rejected,
+        attempts and status ('done', 'h_min' or 'max_attempts'); other
+        failures raise LreiError."""
+        h_min = float(h_init) * 1e-6 if h_min is None else float(h_min)
+        h_max = float(t_span) if h_max is None else float(h_max)
+        res = lrei_adapt_result()
+        st = self.lib.lrei_evolve_adaptive(self.h, MODELS[model], PAIRS[pair], float(kappa), float(t_span),
+                                           float(tol), float(h_init), h_min, h_max, int(max_attempts),
+                                           ctypes.byref(res))
+        out = {k: getattr(res, k) for k, _ in lrei_adapt_result._fields_}
+        out["reached"] = bool(out["reached"])
+        if st == LREI_OK:
+            out["status"] = "done"
+            return out
+        msg = self.lib.lrei_last_error(self.h).decode() if st == LREI_E_NOTCONVERGED else ""
+        if msg.startswith("an attempt at h <= h_min"):
+            out["status"] = "h_min"
+        elif msg.startswith("max_attempts reached"):
+            out["status"] = "max_attempts"
+        else:
+            self._check(st)
+        return out
 
     def get_rho(self, out=None):
         lam = np.zeros(self.r, dtype=np.float64)

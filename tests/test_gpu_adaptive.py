@@ -1,0 +1,204 @@
+"""GPU parity of adaptive stepping (lrei_evolve_adaptive, through the C ABI)
+against the oracle's embedded-pair integration (oracle/adaptive.py).
+
+The controller's decisions are floating-point comparisons of the error
+estimate with tol; both sides take them in FP64 from estimates that agree to
+rounding, and every case asserts that the oracle's estimates stay well away
+from tol (relative margin >= 1e-3) so that the accept/reject sequence is
+unique.  FP64 path: attempt counts equal, final time exact, rho within 1e-10
+relative Frobenius.  Mixed path: rho within 1e-5 of the FP64 oracle.
+"""
+import numpy as np
+import pytest
+
+from oracle import adaptive as OA
+from oracle.hamiltonian import Hamiltonian
+from oracle.metrics import rel_fro_error
+from oracle.schemes import run as oracle_run
+from workloads import chain_bonds, dirichlet_spectrum, haar_factor, make_config
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(n, r, seed):
+    rng = np.random.default_rng(seed)
+    bonds = chain_bonds(n, periodic=True)
+    J = rng.normal(size=(bonds.shape[0], 3, 3)) * 0.5
+    h = rng.normal(size=(n, 3)) * 0.5
+    V = haar_factor(2 ** n, r, rng)
+    lam = dirichlet_spectrum(r, rng)
+    return bonds, J, h, V, lam
+
+
+def _ctx(n, bonds, J, h, V, lam, precision="fp64", **kw):
+    from paper_2508_21200_amd import Context
+    c = Context(precision=precision, **kw)
+    c.set_hamiltonian(n, bonds, J, h)
+    c.set_rho(lam, V)
+    return c
+
+
+def _oracle(n, bonds, J, h, V, lam, model, T, tol, h0, h_min, h_max, pair, max_attempts=100000):
+    H = Hamiltonian(n, bonds, J, h)
+    Vo, log = OA.evolve(H, V, lam, model, 0.5, T, tol, h0, h_min, h_max, max_attempts=max_attempts, pair=pair)
+    att = log[:-1]
+    margin = min(abs(x[2] / tol - 1.0) for x in att)
+    return Vo, log[-1], att, margin
+
+
+CASES = [
+    # n, r, pair, model, tol, t_span
+    (6, 3, "BS32", "qLLG", 1e-6, 0.3),
+    (6, 3, "HE21", "qLL", 1e-5, 0.3),
+    (6, 3, "BS32", "qLL", 1e-8, 0.1),
+    (10, 5, "BS32", "qLL", 1e-7, 0.2),   # several tiles, r not a multiple of 4
+    (10, 5, "HE21", "qLLG", 1e-5, 0.1),
+]
+
+
+@pytest.mark.parametrize("n,r,pair,model,tol,T", CASES)
+def test_adaptive_fp64_matches_oracle(n, r, pair, model, tol, T):
+    bonds, J, h, V, lam = _case(n, r, 40 + n + r)
+    Vo, status, att, margin = _oracle(n, bonds, J, h, V, lam, model, T, tol, 0.2, 1e-8, 1.0, pair)
+    assert status == "done" and margin > 1e-3
+    c = _ctx(n, bonds, J, h, V, lam)
+    res = c.evolve_adaptive(model, 0.5, T, tol, 0.2, h_min=1e-8, h_max=1.0, pair=pair)
+    n_rej = sum(not x[3] for x in att)
+    print(f"{pair} {model} n={n} r={r} tol={tol:g}: {res['attempts']} attempts ({res['rejected']} rejected), "
+          f"oracle {len(att)} ({n_rej}); err_max {res['err_max']:.3e}")
+    assert res["status"] == "done" and res["reached"]
+    assert res["t"] == T
+    assert (res["attempts"], res["rejected"], res["accepted"]) == (len(att), n_rej, len(att) - n_rej)
+    acc = [x for x in att if x[3]]
+    assert abs(res["err_max"] - max(x[2] for x in acc)) <= 1e-6 * res["err_max"]
+    assert abs(res["err_last"] - att[-1][2]) <= 1e-6 * att[-1][2] + 1e-300
+    err = rel_fro_error(c.get_rho()[1], lam, Vo, lam)
+    assert err < 1e-10, err
+    # the controller's proposal for the next call
+    _, _, hn, _, _ = OA.control(att[-1][2], att[-1][1], att[-1][0], T, tol, 1e-8, 1.0, OA.PAIRS[pair][4],
+                                len(att) > 1 and not att[-2][3])
+    assert abs(res["h_next"] - hn) <= 1e-9 * hn
+    c.close()
+
+
+def test_adaptive_mixed_within_bound():
+    n, r = 10, 5
+    bonds, J, h, V, lam = _case(n, r, 55)
+    Vo, status, att, _ = _oracle(n, bonds, J, h, V, lam, "qLLG", 0.2, 1e-6, 0.2, 1e-8, 1.0, "BS32")
+    c = _ctx(n, bonds, J, h, V, lam, precision="mixed")
+    res = c.evolve_adaptive("qLLG", 0.5, 0.2, 1e-6, 0.2, h_min=1e-8, h_max=1.0, pair="BS32")
+    assert res["status"] == "done" and res["t"] == 0.2
+    assert abs(res["accepted"] - sum(x[3] for x in att)) <= 2
+    err = rel_fro_error(c.get_rho()[1], lam, Vo, lam)
+    print(f"mixed: {res['attempts']} attempts, rel. Frobenius vs FP64 oracle {err:.2e}")
+    assert err < 1e-5
+    c.close()
+
+
+def test_adaptive_without_graph_is_identical():
+    n, r = 6, 3
+    bonds, J, h, V, lam = _case(n, r, 49)
+    out = []
+    for g in (True, False):
+        c = _ctx(n, bonds, J, h, V, lam, use_graph=g)
+        res = c.evolve_adaptive("qLLG", 0.5, 0.3, 1e-6, 0.2, h_min=1e-8, h_max=1.0)
+        out.append((res["attempts"], res["rejected"], c.get_rho()[1]))
+        c.close()
+    assert out[0][:2] == out[1][:2]
+    assert rel_fro_error(out[0][2], lam, out[1][2], lam) < 1e-14
+
+
+def test_adaptive_stops_at_h_min_with_last_accepted_state():
+    n, r = 6, 3
+    bonds, J, h, V, lam = _case(n, r, 49)
+    # a tolerance the floor on h cannot meet: the first rejection at h_min ends it
+    Vo, status, att, margin = _oracle(n, bonds, J, h, V, lam, "qLLG", 0.3, 1e-13, 0.05, 0.01, 1.0, "BS32")
+    assert status == "h_min" and margin > 1e-3
+    c = _ctx(n, bonds, J, h, V, lam)
+    res = c.evolve_adaptive("qLLG", 0.5, 0.3, 1e-13, 0.05, h_min=0.01, h_max=1.0)
+    assert res["status"] == "h_min" and not res["reached"]
+    assert res["attempts"] == len(att) and res["accepted"] == sum(x[3] for x in att)
+    assert res["t"] == pytest.approx(sum(x[1] for x in att if x[3]), abs=1e-15)
+    assert rel_fro_error(c.get_rho()[1], lam, Vo, lam) < 1e-10
+    # the context still steps afterwards (and is not stuck in the skip state)
+    res2 = c.evolve_adaptive("qLLG", 0.5, 0.05, 1e-6, 0.05, h_min=1e-8, h_max=1.0)
+    assert res2["status"] == "done" and res2["t"] == 0.05
+    c.close()
+
+
+def test_adaptive_max_attempts():
+    n, r = 6, 3
+    bonds, J, h, V, lam = _case(n, r, 49)
+    Vo, status, att, margin = _oracle(n, bonds, J, h, V, lam, "qLLG", 0.3, 1e-6, 0.2, 1e-8, 1.0, "BS32",
+                                      max_attempts=7)
+    assert status == "max_attempts" and margin > 1e-3
+    c = _ctx(n, bonds, J, h, V, lam)
+    res = c.evolve_adaptive("qLLG", 0.5, 0.3, 1e-6, 0.2, h_min=1e-8, h_max=1.0, max_attempts=7)
+    assert res["status"] == "max_attempts" and res["attempts"] == 7
+    assert rel_fro_error(c.get_rho()[1], lam, Vo, lam) < 1e-10
+    c.close()
+
+
+def test_adaptive_then_fixed_step():
+    """A fixed-step call after an adaptive one (the captured graphs differ)."""
+    n, r = 6, 3
+    bonds, J, h, V, lam = _case(n, r, 49)
+    Vo, _, _, _ = _oracle(n, bonds, J, h, V, lam, "qLLG", 0.1, 1e-6, 0.2, 1e-8, 1.0, "HE21")
+    c = _ctx(n, bonds, J, h, V, lam)
+    c.evolve_adaptive("qLLG", 0.5, 0.1, 1e-6, 0.2, h_min=1e-8, h_max=1.0, pair="HE21")
+    c.step("qLLG", "RK4", 0.02, 0.5, 3)
+    Vo = oracle_run(Hamiltonian(n, bonds, J, h), Vo, lam, "qLLG", 0.5, 0.02, 3, "RK4")
+    assert rel_fro_error(c.get_rho()[1], lam, Vo, lam) < 1e-10
+    c.close()
+
+
+def test_adaptive_argument_errors():
+    from paper_2508_21200_amd import LreiError
+    n, r = 6, 3
+    bonds, J, h, V, lam = _case(n, r, 49)
+    c = _ctx(n, bonds, J, h, V, lam)
+    bad = [dict(t_span=-1.0), dict(tol=0.0), dict(h_init=1e-9, h_min=1e-8), dict(h_max=1e-9, h_min=1e-8),
+           dict(max_attempts=0)]
+    for kw in bad:
+        args = dict(model="qLL", kappa=0.5, t_span=0.1, tol=1e-6, h_init=0.01, h_min=1e-8, h_max=1.0)
+        args.update(kw)
+        with pytest.raises(LreiError):
+            c.evolve_adaptive(**args)
+    st = c.lib.lrei_evolve_adaptive(c.h, 0, 99, 0.5, 0.1, 1e-6, 0.01, 1e-8, 1.0, 10, None)
+    assert st != 0 and "pair" in c.lib.lrei_last_error(c.h).decode()
+    c.close()
+
+
+def test_adaptive_full_size_headline_lattice():
+    """The 4 x 5 periodic Heisenberg lattice (n = 20, r = 16), mixed precision:
+    a short adaptive run reaches its end, keeps the factor orthonormal, and
+    agrees with fixed-step RK4 at a fine step to the tolerance's order."""
+    import torch
+    from paper_2508_21200_amd import Context
+    cfg = make_config(3)
+    V0 = torch.from_numpy(cfg["V"]).cuda()
+    T, tol = 0.02, 1e-6
+    c = Context(precision="mixed")
+    c.set_hamiltonian(cfg["n"], cfg["bonds"], cfg["J"], cfg["h"])
+    c.set_rho(cfg["lam"], V0)
+    res = c.evolve_adaptive("qLL", 0.5, T, tol, 0.01, h_min=1e-6, h_max=0.05)
+    assert res["status"] == "done" and res["t"] == T and res["accepted"] >= 1
+    _, Va = c.get_rho(torch.empty_like(V0))
+    c2 = Context(precision="mixed")
+    c2.set_hamiltonian(cfg["n"], cfg["bonds"], cfg["J"], cfg["h"])
+    c2.set_rho(cfg["lam"], V0)
+    c2.step("qLL", "RK4", 0.0025, 0.5, 8)
+    _, Vf = c2.get_rho(torch.empty_like(V0))
+    G = (Va.conj().T @ Va).cpu().numpy()
+    assert np.abs(G - np.eye(G.shape[0])).max() < 1e-5
+    lam = torch.from_numpy(np.asarray(cfg["lam"])).cuda().to(Va.dtype)
+    # distance of the two states, cancellation-free through QR of [Va, Vf]
+    Q, R = torch.linalg.qr(torch.cat([Va, Vf], dim=1))
+    k = Va.shape[1]
+    M = R[:, :k] @ torch.diag(lam) @ R[:, :k].conj().T - R[:, k:] @ torch.diag(lam) @ R[:, k:].conj().T
+    dist = torch.linalg.norm(M).item()
+    print(f"n=20 r=16 adaptive: {res['attempts']} attempts ({res['rejected']} rejected), distance to fine RK4 "
+          f"{dist:.2e}")
+    assert dist < 20 * tol * res["accepted"]
+    c.close()
+    c2.close()
