@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--rk-vs-ab", action="store_true",
                     help="time LREI-RK4 and LREI-AB4 steps on triangular lattices n = 10..20 (r = 3 mixture of "
                          "AF1, AF2, GHZ; DMI and transverse field of Sec. 5); prints one JSON line")
+    ap.add_argument("--adaptive-report", action="store_true",
+                    help="work-precision table: adaptive BS3(2) / HE2(1) against fixed-step RK4")
     ap.add_argument("--train-traj", type=int, default=100)
     ap.add_argument("--train-steps", type=int, default=200)
     ap.add_argument("--train-epochs", type=int, default=20)
@@ -183,6 +185,81 @@ def run_rk_vs_ab(args, torch):
         print(f"[rk-vs-ab] {json.dumps(res)}", file=sys.stderr, flush=True)
     print(json.dumps({"report": "LREI-RK4 vs LREI-AB4 step time", "model": "qLLG", "kappa": 0.5, "dt": 0.01,
                       "r": 3, "precision": "mixed", "rows": rows_out}))
+
+
+def run_adaptive_report(args, torch):
+    """Adaptive stepping against fixed-step RK4 at equal accuracy.
+
+    Two workloads: the 4 x 5 periodic Heisenberg lattice (n = 20, r = 16,
+    q-LL, kappa = 0.5, T = 0.16) and the 3 x 3 periodic triangular DMI lattice
+    (J = 1, d = 0.4 along z, field 0.116 along x, pure |AF1> start, q-LLG,
+    kappa = 0.5, T = 2: the damped dynamics slow down as the state relaxes).
+    Error: relative Frobenius distance of rho(T) from FP64 fixed-step RK4 at
+    a step 8 times below the finest one in the table.  Wall time of the whole
+    call (adaptive: including its reads of the controller state)."""
+    from paper_2508_21200_amd import Context
+    from workloads import make_config, triangular_lattice_bonds, af1_index, pure_factor
+
+    cfg = make_config(3)
+    n = 9
+    tb = triangular_lattice_bonds(3, 3, periodic=True)
+    Jt = np.eye(3) + np.array([[0.0, 0.4, 0.0], [-0.4, 0.0, 0.0], [0.0, 0.0, 0.0]])
+    tri = {"n": n, "bonds": tb, "J": np.repeat(Jt[None], tb.shape[0], axis=0), "h": np.tile([0.116, 0.0, 0.0], (n, 1)),
+           "lam": np.array([1.0]), "V": pure_factor(n, index=af1_index(n))}
+    loads = [("heisenberg_square4x5_n20_r16", cfg, "qLL", 0.16, [0.04, 0.02, 0.01], [1e-6, 1e-7, 1e-8, 1e-9],
+              ["fp64", "mixed"]),
+             ("triangular3x3_dmi_pure_af1", tri, "qLLG", 2.0, [0.1, 0.05, 0.025, 0.0125],
+              [1e-4, 1e-5, 1e-6, 1e-7, 1e-8], ["fp64"])]
+    rows = []
+    for name, w, model, T, hs, tols, precs in loads:
+        V0 = torch.from_numpy(np.ascontiguousarray(w["V"])).cuda()
+
+        def ctx(prec):
+            c = Context(precision=prec, autotune_cache=args.tune_cache)
+            c.set_hamiltonian(w["n"], w["bonds"], w["J"], w["h"])
+            c.set_rho(w["lam"], V0)
+            return c
+
+        href = hs[-1] / 8
+        c = ctx("fp64")
+        c.step(model, "RK4", href, 0.5, int(round(T / href)))
+        Vref = c.get_rho(torch.empty_like(V0))[1].clone()
+        c.close()
+        for prec in precs:
+            def record(method, param, fn):
+                c = ctx(prec)
+                # launch attributes and graph capture outside the timing
+                if method == "RK4":
+                    c.step(model, "RK4", param, 0.5, 1)
+                else:
+                    c.evolve_adaptive(model, 0.5, 1e-3, 1.0, 1e-3, h_min=1e-9, h_max=1.0, pair=method)
+                c.set_rho(w["lam"], V0)
+                c.synchronize()
+                a = time.perf_counter()
+                info = fn(c)
+                c.synchronize()
+                ms = 1e3 * (time.perf_counter() - a)
+                err = rel_fro(torch, c.get_rho(torch.empty_like(V0))[1], Vref, w["lam"])
+                c.close()
+                row = {"workload": name, "precision": prec, "method": method, "param": param, "ms": round(ms, 2),
+                       "rel_err": float(err)}
+                row.update(info)
+                rows.append(row)
+                print(f"[adaptive] {json.dumps(row)}", file=sys.stderr, flush=True)
+
+            for dt in hs:
+                steps = int(round(T / dt))
+                record("RK4", dt, lambda c, dt=dt, steps=steps: (c.step(model, "RK4", dt, 0.5, steps),
+                                                                 {"steps": steps, "passes": 4 * steps})[1])
+            for pair in ("BS32", "HE21"):
+                for tol in tols:
+                    def run(c, tol=tol, pair=pair):
+                        r = c.evolve_adaptive(model, 0.5, T, tol, hs[0] / 4, h_min=1e-9, h_max=T, pair=pair)
+                        passes = (4 if pair == "BS32" else 2) * r["attempts"]
+                        return {"steps": r["accepted"], "rejected": r["rejected"], "passes": passes,
+                                "status": r["status"]}
+                    record(pair, tol, run)
+    print(json.dumps({"report": "adaptive stepping vs fixed-step RK4", "kappa": 0.5, "rows": rows}))
 
 
 def run_learned_report(args, torch):
@@ -400,6 +477,9 @@ def main():
         return
     if args.rk_vs_ab:
         run_rk_vs_ab(args, torch)
+        return
+    if args.adaptive_report:
+        run_adaptive_report(args, torch)
         return
     from paper_2508_21200_amd import Context
     from workloads import make_config
