@@ -84,10 +84,15 @@ def rel_fro(torch, V1, V2, lam):
 
 
 def source_digest():
-    """Digest of the N-space kernel source; a stored traffic figure is only used while it matches."""
+    """Digest of the sources that decide the H.V pass's memory traffic (the
+    N-space kernels and the host code that lays out the rows); a stored
+    traffic figure is only used while it matches."""
     import hashlib
-    with open(os.path.join(ROOT, "paper_2508_21200_amd", "csrc", "nspace.hip"), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in ("nspace.hip", "api.hip"):
+        with open(os.path.join(ROOT, "paper_2508_21200_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def cpu_baseline(cfg, n_rows=1 << 17, repeats=4):
