@@ -32,8 +32,11 @@ GPU path:
   last accepted step lands on t_end exactly.  A rejection at h <= h_min
   stops the integration; a non-finite estimate counts as a rejection.
 
-Pairs: Heun-Euler 2(1) (Heun's method with Euler embedded) and
-Bogacki-Shampine 3(2) (Bogacki & Shampine, Appl. Math. Lett. 2, 1989), FSAL.
+Pairs: Heun-Euler 2(1) (Heun's method with Euler embedded), Bogacki-Shampine
+3(2) (Bogacki & Shampine, Appl. Math. Lett. 2, 1989), FSAL, and the classical
+RK4 with an order-3 solution that replaces the last stage's weight by the
+right-hand side at the new state, b_hat = (1, 2, 2, 0, 1) / 6 (FSAL; the
+difference of the two is h (f(rho_new) - f(rho_4)) / 6).
 """
 import math
 
@@ -52,6 +55,9 @@ PAIRS = {
     "BS32": (np.array([[0.0, 0.0, 0.0], [0.5, 0.0, 0.0], [0.0, 0.75, 0.0]]),
              np.array([2.0, 3.0, 4.0]) / 9.0,
              np.array([7.0 / 24.0, 0.25, 1.0 / 3.0, 0.125]), 3, 2, True),
+    "RK43": (np.array([[0.0, 0.0, 0.0, 0.0], [0.5, 0.0, 0.0, 0.0], [0.0, 0.5, 0.0, 0.0], [0.0, 0.0, 1.0, 0.0]]),
+             np.array([1.0, 2.0, 2.0, 1.0]) / 6.0,
+             np.array([1.0, 2.0, 2.0, 0.0, 1.0]) / 6.0, 4, 3, True),
 }
 
 
