@@ -62,8 +62,11 @@ typedef enum {
  * HE21: Heun's method (order 2) with Euler embedded (order 1).
  * BS32: Bogacki-Shampine 3(2), order 3 with an order-2 solution that also
  * weights the right-hand side at the new state; costs the same four H.V
- * passes per attempt as an RK4 step and three stage eigensolves. */
-typedef enum { LREI_PAIR_HE21 = 21, LREI_PAIR_BS32 = 32 } lrei_pair;
+ * passes per attempt as an RK4 step and three stage eigensolves.
+ * RK43: the classical RK4 step with the order-3 solution
+ * b_hat = (1, 2, 2, 0, 1) / 6 (its last weight on the right-hand side at the
+ * new state): five H.V passes and four stage eigensolves per attempt. */
+typedef enum { LREI_PAIR_HE21 = 21, LREI_PAIR_BS32 = 32, LREI_PAIR_RK43 = 43 } lrei_pair;
 
 /* LREI_FP64: every N-space pass in complex FP64.
  * LREI_MIXED: N-space passes (H.V, Gram products, basis combination) in

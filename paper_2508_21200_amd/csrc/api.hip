@@ -1161,8 +1161,8 @@ lrei_status lrei_evolve_adaptive(lrei_ctx *ctx, int model, int pair, double kapp
   }
   if (!ctx->have_rho) return ctx->fail(LREI_E_STATE, "set rho before stepping");
   if (model != LREI_QLL && model != LREI_QLLG) return ctx->fail(LREI_E_INVALID, "unknown model");
-  if (pair != LREI_PAIR_HE21 && pair != LREI_PAIR_BS32)
-    return ctx->fail(LREI_E_INVALID, "unknown embedded pair (LREI_PAIR_HE21, LREI_PAIR_BS32)");
+  if (pair != LREI_PAIR_HE21 && pair != LREI_PAIR_BS32 && pair != LREI_PAIR_RK43)
+    return ctx->fail(LREI_E_INVALID, "unknown embedded pair (LREI_PAIR_HE21, LREI_PAIR_BS32, LREI_PAIR_RK43)");
   if (!(t_span > 0) || !std::isfinite(t_span)) return ctx->fail(LREI_E_INVALID, "t_span must be positive and finite");
   if (!(tol > 0) || !std::isfinite(tol)) return ctx->fail(LREI_E_INVALID, "tol must be positive and finite");
   if (!(h_min > 0) || !(h_init >= h_min) || !(h_max >= h_min) || !std::isfinite(h_init) || std::isnan(h_max))

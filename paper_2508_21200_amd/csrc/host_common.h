@@ -73,7 +73,7 @@ inline void tableau(int scheme, int &s, double a[kMaxStages][kMaxStages], double
 // estimate uses, the stage that forms the estimate (s - 1, or s when b_hat
 // also weights f at the new state) and the order q of the embedded solution.
 // HE21: Heun with Euler embedded.  BS32: Bogacki-Shampine 3(2),
-// b_hat = (7/24, 1/4, 1/3, 1/8).
+// b_hat = (7/24, 1/4, 1/3, 1/8).  RK43: classical RK4, b_hat of order 3.
 inline bool pair_tableau(int pair, int &s, double a[kMaxStages][kMaxStages], double b[kMaxStages],
                          double e[kMaxStages], int &err_stage, int &q) {
   for (int i = 0; i < kMaxStages; ++i) {
@@ -91,6 +91,13 @@ inline bool pair_tableau(int pair, int &s, double a[kMaxStages][kMaxStages], dou
       b[0] = 2.0 / 9; b[1] = 3.0 / 9; b[2] = 4.0 / 9;
       e[0] = 2.0 / 9 - 7.0 / 24; e[1] = 3.0 / 9 - 0.25; e[2] = 4.0 / 9 - 1.0 / 3; e[3] = -0.125;
       err_stage = 3; q = 2;
+      return true;
+    case LREI_PAIR_RK43:
+      // the classical RK4 step; b_hat = (1, 2, 2, 0, 1) / 6 moves the last
+      // weight to f at the new state
+      tableau(LREI_RK4, s, a, b);
+      e[3] = 1.0 / 6; e[4] = -1.0 / 6;
+      err_stage = 4; q = 3;
       return true;
     default:
       return false;

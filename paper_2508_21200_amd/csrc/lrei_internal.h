@@ -53,7 +53,7 @@ struct DevDiagTerm {
 
 // Maximum supported sizes.
 constexpr int kMaxR = 32;
-constexpr int kMaxStages = 4;               // RK4
+constexpr int kMaxStages = 5;               // RK4, and the error stage of its embedded pair
 constexpr int kMaxBlocks = 8;               // Krylov blocks in the projected basis
 constexpr int kMaxDim = kMaxBlocks * kMaxR; // projected dimension bound
 

@@ -1100,7 +1100,7 @@ struct StepShared {
   unsigned char drop[kTriDim];
   double minpiv, dev;
   int ndrop;
-  double coef[kMaxAb];
+  double coef[kMaxStages > kMaxAb ? kMaxStages : kMaxAb];  // stage or AB weights, or error weights
 };
 
 // Cholesky of the n x n Hermitian block G (leading dimension ldg) into the

@@ -69,7 +69,7 @@ class lrei_adapt_result(ctypes.Structure):
                 ("attempts", ctypes.c_int), ("reached", ctypes.c_int)]
 
 
-PAIRS = {"HE21": 21, "BS32": 32}
+PAIRS = {"HE21": 21, "BS32": 32, "RK43": 43}
 
 
 class LreiError(RuntimeError):

@@ -53,6 +53,9 @@ CASES = [
     (6, 3, "BS32", "qLL", 1e-8, 0.1),
     (10, 5, "BS32", "qLL", 1e-7, 0.2),   # several tiles, r not a multiple of 4
     (10, 5, "HE21", "qLLG", 1e-5, 0.1),
+    (6, 3, "RK43", "qLLG", 1e-8, 0.3),
+    (6, 3, "RK43", "qLL", 1e-6, 0.3),
+    (10, 5, "RK43", "qLL", 1e-9, 0.2),  # D = 6 r: five passes per attempt
 ]
 
 
@@ -81,12 +84,13 @@ def test_adaptive_fp64_matches_oracle(n, r, pair, model, tol, T):
     c.close()
 
 
-def test_adaptive_mixed_within_bound():
+@pytest.mark.parametrize("pair", ["BS32", "RK43"])
+def test_adaptive_mixed_within_bound(pair):
     n, r = 10, 5
     bonds, J, h, V, lam = _case(n, r, 55)
-    Vo, status, att, _ = _oracle(n, bonds, J, h, V, lam, "qLLG", 0.2, 1e-6, 0.2, 1e-8, 1.0, "BS32")
+    Vo, status, att, _ = _oracle(n, bonds, J, h, V, lam, "qLLG", 0.2, 1e-6, 0.2, 1e-8, 1.0, pair)
     c = _ctx(n, bonds, J, h, V, lam, precision="mixed")
-    res = c.evolve_adaptive("qLLG", 0.5, 0.2, 1e-6, 0.2, h_min=1e-8, h_max=1.0, pair="BS32")
+    res = c.evolve_adaptive("qLLG", 0.5, 0.2, 1e-6, 0.2, h_min=1e-8, h_max=1.0, pair=pair)
     assert res["status"] == "done" and res["t"] == 0.2
     assert abs(res["accepted"] - sum(x[3] for x in att)) <= 2
     err = rel_fro_error(c.get_rho()[1], lam, Vo, lam)
@@ -181,7 +185,7 @@ def test_adaptive_full_size_headline_lattice():
     c = Context(precision="mixed")
     c.set_hamiltonian(cfg["n"], cfg["bonds"], cfg["J"], cfg["h"])
     c.set_rho(cfg["lam"], V0)
-    res = c.evolve_adaptive("qLL", 0.5, T, tol, 0.01, h_min=1e-6, h_max=0.05)
+    res = c.evolve_adaptive("qLL", 0.5, T, tol, 0.01, h_min=1e-6, h_max=0.05, pair="RK43")
     assert res["status"] == "done" and res["t"] == T and res["accepted"] >= 1
     _, Va = c.get_rho(torch.empty_like(V0))
     c2 = Context(precision="mixed")
