@@ -55,7 +55,7 @@ def parse():
                     help="time LREI-RK4 and LREI-AB4 steps on triangular lattices n = 10..20 (r = 3 mixture of "
                          "AF1, AF2, GHZ; DMI and transverse field of Sec. 5); prints one JSON line")
     ap.add_argument("--adaptive-report", action="store_true",
-                    help="work-precision table: adaptive BS3(2) / HE2(1) against fixed-step RK4")
+                    help="work-precision table: adaptive RK4(3) / BS3(2) / HE2(1) against fixed-step RK4")
     ap.add_argument("--train-traj", type=int, default=100)
     ap.add_argument("--train-steps", type=int, default=200)
     ap.add_argument("--train-epochs", type=int, default=20)
@@ -256,11 +256,11 @@ def run_adaptive_report(args, torch):
                 steps = int(round(T / dt))
                 record("RK4", dt, lambda c, dt=dt, steps=steps: (c.step(model, "RK4", dt, 0.5, steps),
                                                                  {"steps": steps, "passes": 4 * steps})[1])
-            for pair in ("BS32", "HE21"):
+            for pair in ("RK43", "BS32", "HE21"):
                 for tol in tols:
                     def run(c, tol=tol, pair=pair):
                         r = c.evolve_adaptive(model, 0.5, T, tol, hs[0] / 4, h_min=1e-9, h_max=T, pair=pair)
-                        passes = (4 if pair == "BS32" else 2) * r["attempts"]
+                        passes = {"RK43": 5, "BS32": 4, "HE21": 2}[pair] * r["attempts"]
                         return {"steps": r["accepted"], "rejected": r["rejected"], "passes": passes,
                                 "status": r["status"]}
                     record(pair, tol, run)
