@@ -228,7 +228,7 @@ class Context:
                                        int(n_steps)))
 
     def evolve_adaptive(self, model, kappa, t_span, tol, h_init, h_min=None, h_max=None, max_attempts=100000,
-                        pair="BS32"):
+                        pair="RK43"):
         """Advances by t_span with step-size control (lrei_evolve_adaptive).
         Returns a dict with t, h_next, err_last, err_max, accepted, rejected,
         attempts and status ('done', 'h_min' or 'max_attempts'); other

@@ -105,7 +105,7 @@ def test_adaptive_without_graph_is_identical():
     out = []
     for g in (True, False):
         c = _ctx(n, bonds, J, h, V, lam, use_graph=g)
-        res = c.evolve_adaptive("qLLG", 0.5, 0.3, 1e-6, 0.2, h_min=1e-8, h_max=1.0)
+        res = c.evolve_adaptive("qLLG", 0.5, 0.3, 1e-6, 0.2, h_min=1e-8, h_max=1.0, pair="BS32")
         out.append((res["attempts"], res["rejected"], c.get_rho()[1]))
         c.close()
     assert out[0][:2] == out[1][:2]
@@ -119,7 +119,7 @@ def test_adaptive_stops_at_h_min_with_last_accepted_state():
     Vo, status, att, margin = _oracle(n, bonds, J, h, V, lam, "qLLG", 0.3, 1e-13, 0.05, 0.01, 1.0, "BS32")
     assert status == "h_min" and margin > 1e-3
     c = _ctx(n, bonds, J, h, V, lam)
-    res = c.evolve_adaptive("qLLG", 0.5, 0.3, 1e-13, 0.05, h_min=0.01, h_max=1.0)
+    res = c.evolve_adaptive("qLLG", 0.5, 0.3, 1e-13, 0.05, h_min=0.01, h_max=1.0, pair="BS32")
     assert res["status"] == "h_min" and not res["reached"]
     assert res["attempts"] == len(att) and res["accepted"] == sum(x[3] for x in att)
     assert res["t"] == pytest.approx(sum(x[1] for x in att if x[3]), abs=1e-15)
@@ -137,7 +137,7 @@ def test_adaptive_max_attempts():
                                       max_attempts=7)
     assert status == "max_attempts" and margin > 1e-3
     c = _ctx(n, bonds, J, h, V, lam)
-    res = c.evolve_adaptive("qLLG", 0.5, 0.3, 1e-6, 0.2, h_min=1e-8, h_max=1.0, max_attempts=7)
+    res = c.evolve_adaptive("qLLG", 0.5, 0.3, 1e-6, 0.2, h_min=1e-8, h_max=1.0, max_attempts=7, pair="BS32")
     assert res["status"] == "max_attempts" and res["attempts"] == 7
     assert rel_fro_error(c.get_rho()[1], lam, Vo, lam) < 1e-10
     c.close()
