@@ -173,8 +173,9 @@ LREI_API lrei_status lrei_set_rho(lrei_ctx *ctx, int r, const double *lambda, co
  * (q-LL: eq. 1.1 through eq. 4.1; q-LLG: eq. 1.2 through eq. 3.2), using the
  * LREI-RK (Sec. 3.6) or LREI-AB (Sec. 3.7) scheme.  Adams-Bashforth history
  * carries over between calls with the same model, scheme, dt and kappa; any
- * change restarts it with the bootstrap scheme.  On failure the state is that
- * of the last completed step. */
+ * change restarts it with the bootstrap scheme.  On a numerical failure
+ * (LREI_E_NUMERIC, LREI_E_NOTCONVERGED) the state is restored to that at the
+ * start of the call and the Adams-Bashforth history is dropped. */
 LREI_API lrei_status lrei_step(lrei_ctx *ctx, int model, int scheme, double dt, double kappa, int n_steps);
 
 /* Outcome of lrei_evolve_adaptive. */
