@@ -84,6 +84,25 @@ def test_adaptive_fp64_matches_oracle(n, r, pair, model, tol, T):
     c.close()
 
 
+@pytest.mark.parametrize("n,r,pair,model,tol,T,seed", [
+    (8, 32, "RK43", "qLLG", 1e-7, 0.1, 7),  # D = 6 r = 192: the projected step's global-memory paths
+    (7, 1, "BS32", "qLL", 1e-8, 0.2, 8),    # rank one (a pure state)
+    (7, 1, "HE21", "qLLG", 1e-6, 0.1, 9),
+])
+def test_adaptive_edge_ranks(n, r, pair, model, tol, T, seed):
+    bonds, J, h, V, lam = _case(n, r, seed)
+    Vo, status, att, margin = _oracle(n, bonds, J, h, V, lam, model, T, tol, 0.2, 1e-8, 1.0, pair)
+    assert status == "done" and margin > 1e-2
+    c = _ctx(n, bonds, J, h, V, lam)
+    res = c.evolve_adaptive(model, 0.5, T, tol, 0.2, h_min=1e-8, h_max=1.0, pair=pair)
+    assert res["status"] == "done" and res["t"] == T
+    assert (res["attempts"], res["rejected"]) == (len(att), sum(not x[3] for x in att))
+    err = rel_fro_error(c.get_rho()[1], lam, Vo, lam)
+    print(f"{pair} n={n} r={r}: {res['attempts']} attempts, rel. Frobenius vs oracle {err:.2e}")
+    assert err < 1e-10
+    c.close()
+
+
 @pytest.mark.parametrize("pair", ["BS32", "RK43"])
 def test_adaptive_mixed_within_bound(pair):
     n, r = 10, 5
