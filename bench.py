@@ -85,11 +85,11 @@ def rel_fro(torch, V1, V2, lam):
 
 def source_digest():
     """Digest of the sources that decide the H.V pass's memory traffic (the
-    N-space kernels and the host code that lays out the rows); a stored
-    traffic figure is only used while it matches."""
+    N-space kernels and the site -> row-bit order); a stored traffic figure is
+    only used while it matches."""
     import hashlib
     h = hashlib.sha256()
-    for name in ("nspace.hip", "api.hip"):
+    for name in ("nspace.hip", "site_order.cpp"):
         with open(os.path.join(ROOT, "paper_2508_21200_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]

@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 SOURCES = ["terms.cpp", "nspace.hip", "blocks.hip", "small.hip", "api.hip", "batch.hip", "learned.hip",
-           "entangle.cpp"]
+           "entangle.cpp", "site_order.cpp"]
 LIB = os.path.join(HERE, "liblrei.so")
 
 FLAGS = [

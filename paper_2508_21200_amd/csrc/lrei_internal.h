@@ -181,6 +181,10 @@ bool launch_blocks(bool fp32, const BlocksArgs &a, hipStream_t s);
 int blocks_grid(long long N);
 size_t blocks_lds(bool fp32, int nin, int nout, int r);
 
+// Site -> row-bit order of the internal storage (site_order.cpp): pos[site]
+// is the row bit that holds the site.
+std::vector<int> choose_site_order(int n, int n_bonds, const int32_t *bond_ij);
+
 // Device-resident state of the step-size controller (adaptive stepping, one
 // double each).  The stage that forms the error estimate reads the step from
 // kCtlH, decides, and writes the next step; every kernel of an attempt does
