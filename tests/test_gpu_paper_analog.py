@@ -59,3 +59,66 @@ def test_convergence_orders(model):
     # for the same order, RK is more accurate than AB (Sec. 5)
     for m in (2, 3, 4):
         assert table[f"RK{m}"][-1] < table[f"AB{m}"][-1]
+
+
+def _traces(model, dt, steps, every, lam, V, n, bonds, J, h, kappa=0.5):
+    """Magnetisation (1/n) sum_i <S_i> and the concurrence of sites (0, 1)
+    every `every` steps, from the GPU path (FP64)."""
+    from paper_2508_21200_amd import Context, pair_entanglement
+    c = Context(precision="fp64")
+    c.set_hamiltonian(n, bonds, J, h)
+    c.set_rho(lam, V)
+    out = []
+    for k in range(0, steps + 1, every):
+        if k > 0:
+            c.step(model, "RK4", dt, kappa, every)
+        _, m = c.observables()
+        R = c.pair_density([[0, 1]])[0]
+        out.append((k * dt, m.copy(), pair_entanglement(R)[0]))
+    rho = c.get_rho()[1]
+    c.close()
+    return out, rho
+
+
+def test_qll_vs_qllg_pure_and_mixed():
+    """Sec. 5's comparison of the two models at kappa = 0.5: from the pure
+    |AF2> state, q-LLG at time t equals q-LL at t / (1 + kappa^2) (eq. 1.4;
+    LREI-RK4 keeps it exactly when the q-LLG step is (1 + kappa^2) times the
+    q-LL step), for the magnetisation and the nearest-neighbour concurrence;
+    from 0.75 |AF2><AF2| + 0.25 |GHZ><GHZ| the two no longer coincide under
+    that rescaling.  The mixed runs are checked against the oracle at the end."""
+    from workloads import af2_index, ghz_vector, mixture_factor
+    n, bonds, J, h = paper_analog()
+    kappa, dt, steps, every = 0.5, 0.01, 200, 20
+    s = 1.0 + kappa ** 2
+    e_af2 = np.zeros(2 ** n, complex)
+    e_af2[af2_index(n)] = 1.0
+    cases = {"pure": (np.array([1.0]), e_af2[:, None]),
+             "mixed": mixture_factor([e_af2, ghz_vector(n)], [0.75, 0.25])}
+    H = Hamiltonian(n, bonds, J, h)
+    table = {}
+    for name, (lam, V) in cases.items():
+        tl, rho_ll = _traces("qLL", dt, steps, every, lam, V, n, bonds, J, h)
+        tg, rho_lg = _traces("qLLG", dt * s, steps, every, lam, V, n, bonds, J, h)
+        dm = max(np.abs(a[1] - b[1]).max() for a, b in zip(tl, tg))
+        dc = max(abs(a[2] - b[2]) for a, b in zip(tl, tg))
+        table[name] = (tl, tg, dm, dc)
+        print(f"\n{name}: q-LL at t vs q-LLG at (1 + kappa^2) t, t = 0 .. {steps * dt}: "
+              f"max |dM| {dm:.3e}, max |d concurrence(0,1)| {dc:.3e}")
+        print("| t | M q-LL (x, y, z) | M q-LLG at (1 + kappa^2) t | C01 q-LL | C01 q-LLG |")
+        print("|---|---|---|---|---|")
+        for a, b in zip(tl, tg):
+            print(f"| {a[0]:.2f} | {a[1][0]:+.6f}, {a[1][1]:+.6f}, {a[1][2]:+.6f} | "
+                  f"{b[1][0]:+.6f}, {b[1][1]:+.6f}, {b[1][2]:+.6f} | {a[2]:.6f} | {b[2]:.6f} |")
+        if name == "mixed":
+            Vo = oracle_run_rk4(H, V, lam, "qLL", kappa, dt, steps)
+            assert rel_fro_error(rho_ll, lam, Vo, lam) < 1e-10
+            Vo = oracle_run_rk4(H, V, lam, "qLLG", kappa, dt * s, steps)
+            assert rel_fro_error(rho_lg, lam, Vo, lam) < 1e-10
+    assert table["pure"][2] < 1e-10 and table["pure"][3] < 1e-10
+    assert table["mixed"][2] > 1e-3 or table["mixed"][3] > 1e-3
+
+
+def oracle_run_rk4(H, V, lam, model, kappa, dt, steps):
+    from oracle.schemes import run
+    return run(H, V, lam, model, kappa, dt, steps, "RK4")
