@@ -56,6 +56,8 @@ def parse():
                          "AF1, AF2, GHZ; DMI and transverse field of Sec. 5); prints one JSON line")
     ap.add_argument("--adaptive-report", action="store_true",
                     help="work-precision table: adaptive RK4(3) / BS3(2) / HE2(1) against fixed-step RK4")
+    ap.add_argument("--scaling-report", action="store_true",
+                    help="q-LLG RK4 step time with observables against n (triangular lattices) and r = 1..4")
     ap.add_argument("--train-traj", type=int, default=100)
     ap.add_argument("--train-steps", type=int, default=200)
     ap.add_argument("--train-epochs", type=int, default=20)
@@ -265,6 +267,68 @@ def run_adaptive_report(args, torch):
                                 "status": r["status"]}
                     record(pair, tol, run)
     print(json.dumps({"report": "adaptive stepping vs fixed-step RK4", "kappa": 0.5, "rows": rows}))
+
+
+def run_scaling_report(args, torch):
+    """Step time against the number of spins and the rank (the paper's
+    complexity test, Sec. 5): periodic triangular lattices, J = 1, DMI
+    d = 0.4 along z, field 0.116 along x, q-LLG with kappa = 0.5, LREI-RK4,
+    dt = 0.01, mixed precision; the rank-r start is the mixture of |AF1>,
+    |AF2>, |GHZ>, |W> with weights (1), (0.75, 0.25), (0.5, 0.3, 0.2) or
+    (0.4, 0.3, 0.2, 0.1), built on the device.  Per step: the RK4 step, the
+    energy and magnetisation, and the two-spin state and concurrence of
+    sites (0, 1)."""
+    from paper_2508_21200_amd import Context, pair_entanglement
+    from workloads import triangular_lattice_bonds, af1_index, af2_index
+
+    weights = {1: [1.0], 2: [0.75, 0.25], 3: [0.5, 0.3, 0.2], 4: [0.4, 0.3, 0.2, 0.1]}
+    shapes = [(3, 4), (4, 4), (4, 5), (4, 6), (2, 13), (4, 7)]
+    rows_out = []
+    for rows, cols in shapes:
+        n = rows * cols
+        N = 1 << n
+        bonds = triangular_lattice_bonds(rows, cols, periodic=True)
+        Jt = np.eye(3) + np.array([[0.0, 0.4, 0.0], [-0.4, 0.0, 0.0], [0.0, 0.0, 0.0]])
+        J = np.repeat(Jt[None], bonds.shape[0], axis=0)
+        h = np.tile([0.116, 0.0, 0.0], (n, 1))
+        for r in (1, 2, 3, 4):
+            lam = np.array(weights[r])
+            V = torch.zeros((N, r), dtype=torch.complex128, device="cuda")
+            V[af1_index(n), 0] = 1.0
+            if r > 1:
+                V[af2_index(n), 1] = 1.0
+            if r > 2:
+                V[0, 2] = V[N - 1, 2] = 2 ** -0.5
+            if r > 3:
+                V[torch.tensor([1 << i for i in range(n)], device="cuda"), 3] = n ** -0.5
+            c = Context(precision="mixed", autotune_cache=args.tune_cache)
+            c.set_hamiltonian(n, bonds, J, h)
+            c.set_rho(lam, V)
+            del V
+            torch.cuda.empty_cache()
+            c.step("qLLG", "RK4", 0.01, 0.5, 1)
+            c.observables()
+            c.pair_density([[0, 1]])
+            c.synchronize()
+            steps = 5 if n >= 24 else 20
+            a = time.perf_counter()
+            c.step("qLLG", "RK4", 0.01, 0.5, steps)
+            c.synchronize()
+            bare = 1e3 * (time.perf_counter() - a) / steps
+            a = time.perf_counter()
+            for _ in range(steps):
+                c.step("qLLG", "RK4", 0.01, 0.5, 1)
+                e, m = c.observables()
+                conc = pair_entanglement(c.pair_density([[0, 1]])[0])[0]
+            full = 1e3 * (time.perf_counter() - a) / steps
+            c.close()
+            res = {"n": n, "lattice": f"{rows}x{cols} periodic triangular", "bonds": int(bonds.shape[0]), "r": r,
+                   "ms_per_step": round(bare, 3), "ms_per_step_with_observables": round(full, 3),
+                   "energy": round(e, 6), "concurrence_01": round(conc, 6)}
+            rows_out.append(res)
+            print(f"[scaling] {json.dumps(res)}", file=sys.stderr, flush=True)
+    print(json.dumps({"report": "LREI-RK4 q-LLG step time against n and r", "kappa": 0.5, "dt": 0.01,
+                      "precision": "mixed", "rows": rows_out}))
 
 
 def run_learned_report(args, torch):
@@ -485,6 +549,9 @@ def main():
         return
     if args.adaptive_report:
         run_adaptive_report(args, torch)
+        return
+    if args.scaling_report:
+        run_scaling_report(args, torch)
         return
     from paper_2508_21200_amd import Context
     from workloads import make_config
