@@ -593,3 +593,49 @@ def test_state_from_factor(prec):
         Vs = oracle_run(H, V_o, lam_o, "qLL", 0.2, 0.01, 2, "RK4")
         assert rel_fro_error(c.get_rho()[1], lam_o, Vs, lam_o) < (1e-11 if prec == "fp64" else 1e-5)
         c.close()
+
+
+def test_full_size_step_properties():
+    """The 4x5 lattice workload at full size (n = 20, r = 16) in the launch
+    configuration the benchmark times (mixed storage, autotuned H.V shape,
+    captured step graph): properties that hold at any size, since the
+    oracle's own full-size step takes minutes.
+    * mixed against FP64 after 10 RK4 steps: <= 1e-5 relative Frobenius;
+    * kappa = 0 conserves Tr(rho H) along the exact flow and LREI-RK4 keeps
+      it to O(h^4); kappa = 0.5 drives it down (the oracle on the 3 x 4
+      lattice over 10 steps of h = 0.01: 7e-8 against 0.24): the drift at
+      kappa = 0 stays below 1e-4 of the change at kappa = 0.5 (FP64);
+    * the support stays orthonormal (FP64 to 1e-12, mixed to its FP32
+      storage rounding)."""
+    import torch
+    from tests_support_rel import rel_fro_gpu
+    cfg = make_config(3)
+    V0 = torch.from_numpy(cfg["V"]).cuda()
+    out = {}
+    for prec in ("fp64", "mixed"):
+        c = _ctx(prec)
+        c.set_hamiltonian(cfg["n"], cfg["bonds"], cfg["J"], cfg["h"])
+        c.set_rho(cfg["lam"], V0)
+        if prec == "mixed":
+            c.autotune()
+        c.step("qLL", "RK4", 0.01, 0.5, 10)
+        _, V = c.get_rho(torch.empty_like(V0))
+        G = (V.conj().T @ V).cpu().numpy()
+        dev = np.abs(G - np.eye(G.shape[0])).max()
+        assert dev < (1e-12 if prec == "fp64" else 1e-6), (prec, dev)
+        out[prec] = V
+        c.close()
+    err = rel_fro_gpu(out["mixed"], out["fp64"], cfg["lam"])
+    print(f"n=20 r=16, 10 RK4 steps: mixed vs FP64 {err:.2e}")
+    assert err < 1e-5
+    e = {}
+    for kappa in (0.0, 0.5):
+        c = _ctx("fp64")
+        c.set_hamiltonian(cfg["n"], cfg["bonds"], cfg["J"], cfg["h"])
+        c.set_rho(cfg["lam"], V0)
+        e0, _ = c.observables()
+        c.step("qLL", "RK4", 0.01, kappa, 10)
+        e[kappa] = c.observables()[0] - e0
+        c.close()
+    print(f"energy change over 10 steps: kappa = 0 {e[0.0]:.3e}, kappa = 0.5 {e[0.5]:.3e}")
+    assert abs(e[0.0]) <= 1e-4 * abs(e[0.5])
