@@ -115,6 +115,14 @@ typedef struct {
   int deterministic;      /* ignored: every reduction runs in a fixed order, so results
                              are bitwise reproducible for a given launch shape        */
   const char *autotune_cache; /* path of the autotuner's text cache file, or NULL     */
+  double mixed_pivot_floor; /* LREI_MIXED: the FP32-stored Krylov blocks resolve a new
+                             direction only while its Cholesky pivot stays well above
+                             their rounding; when the smallest pivot ratio of an RK
+                             step (lrei_stats.min_pivot_ratio) falls below this floor
+                             the context moves to FP64 storage for the rest of its
+                             life (checked every 16 steps and at the end of a call;
+                             lrei_stats.precision_promoted reports it).  Default 2e-6;
+                             0 disables the check                                    */
 } lrei_options;
 
 typedef struct {
@@ -127,7 +135,8 @@ typedef struct {
   int64_t warm_iterations;       /* stage-matrix block products of the warm start
                                     (subspace iterations, plus one per predictor)      */
   int32_t dropped_directions;    /* Krylov directions dropped as dependent (last step)  */
-  int32_t reserved;
+  int32_t precision_promoted;    /* 1 once a LREI_MIXED context has moved to FP64
+                                    storage (lrei_options.mixed_pivot_floor)           */
   double min_pivot_ratio;        /* smallest Cholesky pivot / Gram diagonal (last step) */
   double ortho_error;            /* max |V*V - I| at the start of the last step         */
   double energy;                 /* Tr(Lambda_0 V* H V) at the start of the last step   */

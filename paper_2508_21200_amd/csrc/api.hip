@@ -430,6 +430,74 @@ void enqueue_stages(lrei_ctx *ctx, const SmallRkParams &p) {
                  p.ctl ? p.ctl + kCtlSkip : nullptr);
 }
 
+// Steps between two checks of the mixed-precision conditioning floor.
+constexpr int kGuardSteps = 16;
+
+// k RK steps: replays of the captured step graph (captured first if the step
+// differs from the last one captured), or eager launches.
+lrei_status run_rk_steps(lrei_ctx *ctx, int model, int scheme, double dt, double kappa, int k) {
+  if (ctx->opt.use_graph == 0) {
+    for (int i = 0; i < k; ++i) enqueue_rk_step(ctx, model, scheme, dt, kappa);
+    return LREI_OK;
+  }
+  int first = 0;
+  if (!(ctx->exec && ctx->g_model == model && ctx->g_scheme == scheme && ctx->g_dt == dt && ctx->g_kappa == kappa)) {
+    ctx->drop_graph();
+    // launch attributes are set on first use, outside capture; this eager
+    // step counts as the first step
+    enqueue_rk_step(ctx, model, scheme, dt, kappa);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    HIPCHK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+    enqueue_rk_step(ctx, model, scheme, dt, kappa);
+    HIPCHK(hipStreamEndCapture(ctx->stream, &ctx->graph));
+    HIPCHK(hipGraphInstantiate(&ctx->exec, ctx->graph, nullptr, nullptr, 0));
+    ctx->g_model = model;
+    ctx->g_scheme = scheme;
+    ctx->g_dt = dt;
+    ctx->g_kappa = kappa;
+    first = 1;
+  }
+  for (int i = first; i < k; ++i) HIPCHK(hipGraphLaunch(ctx->exec, ctx->stream));
+  return LREI_OK;
+}
+
+void ab_reset(lrei_ctx *ctx);
+
+// Moves a LREI_MIXED context to FP64 storage: the state is widened exactly,
+// the N-space buffers are reallocated for FP64, the captured graphs, the
+// tuned H.V shape and the AB history are dropped.  The rollback copy of the
+// current call becomes the state at this point.
+lrei_status promote_fp64(lrei_ctx *ctx) {
+  const size_t n = (size_t)ctx->N * ctx->r;
+  void *wide = nullptr;
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (hipMalloc(&wide, n * sizeof(double2)) != hipSuccess)
+    return ctx->fail(LREI_E_NOMEM, "device allocation for the FP64 promotion failed");
+  launch_convert(false, ctx->blocks[0].p, wide, (long long)n, ctx->stream);
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) {
+    (void)hipFree(wide);
+    return check_hip(ctx, e, "FP64 promotion");
+  }
+  ctx->drop_graph();
+  ab_reset(ctx);
+  ctx->fp32 = false;
+  ctx->epl = 0;
+  ctx->hv_grid = 0;
+  lrei_status st = alloc_state(ctx, ctx->r, false);
+  if (st == LREI_OK) {
+    e = hipMemcpyAsync(ctx->blocks[0].p, wide, n * sizeof(double2), hipMemcpyDeviceToDevice, ctx->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(ctx->save.p, wide, n * sizeof(double2), hipMemcpyDeviceToDevice, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) st = check_hip(ctx, e, "FP64 promotion");
+  }
+  (void)hipFree(wide);
+  if (st == LREI_OK) ctx->stats.precision_promoted = 1;
+  return st;
+}
+
 // Projected-step parameters of an adaptive attempt with an embedded pair.
 SmallRkParams adapt_params(lrei_ctx *ctx, int model, int pair, double kappa) {
   SmallRkParams p = rk_params(ctx, model, LREI_RK4, 0.0, kappa);
@@ -660,6 +728,7 @@ void lrei_default_options(lrei_options *o) {
   o->use_graph = 1;
   o->deterministic = 1;
   o->autotune_cache = nullptr;
+  o->mixed_pivot_floor = 2e-6;
 }
 
 lrei_status lrei_create(lrei_ctx **out, int hip_device, void *hip_stream, const lrei_options *opt) {
@@ -672,6 +741,10 @@ lrei_status lrei_create(lrei_ctx **out, int hip_device, void *hip_stream, const 
   lrei_default_options(&ctx->opt);
   if (opt) ctx->opt = *opt;
   if (ctx->opt.precision != LREI_FP64 && ctx->opt.precision != LREI_MIXED) {
+    delete ctx;
+    return LREI_E_INVALID;
+  }
+  if (!(ctx->opt.mixed_pivot_floor >= 0) || !std::isfinite(ctx->opt.mixed_pivot_floor)) {
     delete ctx;
     return LREI_E_INVALID;
   }
@@ -990,31 +1063,29 @@ lrei_status lrei_step(lrei_ctx *ctx, int model, int scheme, double dt, double ka
   double zeros[kStatsLen] = {0};
   HIPCHK(hipMemcpyAsync(ctx->stats_buf.p, zeros, sizeof(zeros), hipMemcpyHostToDevice, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
-  const bool use_graph = ctx->opt.use_graph != 0;
   if (is_ab) {
     for (int k = 0; k < n_steps; ++k) enqueue_ab_step(ctx);
-  } else if (use_graph) {
-    if (!(ctx->exec && ctx->g_model == model && ctx->g_scheme == scheme && ctx->g_dt == dt && ctx->g_kappa == kappa)) {
-      ctx->drop_graph();
-      // launch attributes are set on first use, outside capture
-      enqueue_rk_step(ctx, model, scheme, dt, kappa);
-      HIPCHK(hipGetLastError());
-      HIPCHK(hipStreamSynchronize(ctx->stream));
-      HIPCHK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
-      enqueue_rk_step(ctx, model, scheme, dt, kappa);
-      HIPCHK(hipStreamEndCapture(ctx->stream, &ctx->graph));
-      HIPCHK(hipGraphInstantiate(&ctx->exec, ctx->graph, nullptr, nullptr, 0));
-      ctx->g_model = model;
-      ctx->g_scheme = scheme;
-      ctx->g_dt = dt;
-      ctx->g_kappa = kappa;
-      // the eager step above counts as the first step
-      for (int k = 1; k < n_steps; ++k) HIPCHK(hipGraphLaunch(ctx->exec, ctx->stream));
-    } else {
-      for (int k = 0; k < n_steps; ++k) HIPCHK(hipGraphLaunch(ctx->exec, ctx->stream));
-    }
   } else {
-    for (int k = 0; k < n_steps; ++k) enqueue_rk_step(ctx, model, scheme, dt, kappa);
+    // mixed precision: every kGuardSteps steps (and at the end) the smallest
+    // Cholesky pivot ratio of the last step is checked against the floor
+    // below which the FP32 blocks no longer resolve the Krylov directions
+    const bool guard = ctx->fp32 && ctx->opt.mixed_pivot_floor > 0;
+    int left = n_steps;
+    while (left > 0) {
+      const int k = guard && ctx->fp32 ? std::min(left, kGuardSteps) : left;
+      lrei_status rs = run_rk_steps(ctx, model, scheme, dt, kappa, k);
+      if (rs != LREI_OK) return rs;
+      left -= k;
+      if (guard && ctx->fp32) {
+        double piv = 1.0;
+        HIPCHK(hipMemcpyAsync(&piv, ctx->ws.stats + 3, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        if (piv < ctx->opt.mixed_pivot_floor) {
+          rs = promote_fp64(ctx);
+          if (rs != LREI_OK) return rs;
+        }
+      }
+    }
   }
   HIPCHK(hipGetLastError());
   double h[kStatsLen];
@@ -1025,7 +1096,8 @@ lrei_status lrei_step(lrei_ctx *ctx, int model, int scheme, double dt, double ka
   const bool failed = h[13] != 0, bad = h[14] != 0;
   if (failed || bad) {
     ab_reset(ctx);  // the history no longer matches the restored state
-    HIPCHK(hipMemcpyAsync(ctx->blocks[0].p, ctx->save.p, vbytes, hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->blocks[0].p, ctx->save.p, (size_t)ctx->N * ctx->r * ctx->elem(),
+                          hipMemcpyDeviceToDevice, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     char where[96] = "";
     if (h[28] >= 0)
@@ -1091,14 +1163,18 @@ lrei_status lrei_evolve_adaptive(lrei_ctx *ctx, int model, int pair, double kapp
   c[kCtlHMax] = h_max;
   HIPCHK(hipMemcpyAsync(ctx->ctl.p, c, sizeof(c), hipMemcpyHostToDevice, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
-  const SmallRkParams p = adapt_params(ctx, model, pair, kappa);
+  SmallRkParams p = adapt_params(ctx, model, pair, kappa);
   const bool use_graph = ctx->opt.use_graph != 0;
+  const bool guard = ctx->fp32 && ctx->opt.mixed_pivot_floor > 0;
   int launched = 0;
-  if (use_graph && !(ctx->exec && ctx->g_model == model && ctx->g_scheme == pair && ctx->g_dt < 0 &&
-                     ctx->g_kappa == kappa)) {
+  // the captured attempt (captured first when the attempt differs from the
+  // last one captured; the eager attempt that sets the launch attributes,
+  // outside capture, is an attempt of its own)
+  auto ensure_graph = [&]() -> lrei_status {
+    if (!use_graph || (ctx->exec && ctx->g_model == model && ctx->g_scheme == pair && ctx->g_dt < 0 &&
+                       ctx->g_kappa == kappa))
+      return LREI_OK;
     ctx->drop_graph();
-    // launch attributes are set on first use, outside capture: the eager
-    // attempt is the first attempt
     enqueue_attempt(ctx, p);
     HIPCHK(hipGetLastError());
     ++launched;
@@ -1111,13 +1187,31 @@ lrei_status lrei_evolve_adaptive(lrei_ctx *ctx, int model, int pair, double kapp
     ctx->g_scheme = pair;
     ctx->g_dt = -1.0;
     ctx->g_kappa = kappa;
-  }
+    return LREI_OK;
+  };
   // batches of attempts between reads of the controller state: as many as
   // the current step needs to reach t_span (at most 16); attempts queued
-  // after the end do nothing
+  // after the end do nothing.  Mixed precision: the conditioning floor is
+  // checked after every batch (the last attempt's smallest pivot ratio).
   for (;;) {
+    lrei_status gs = ensure_graph();
+    if (gs != LREI_OK) return gs;
     HIPCHK(hipMemcpyAsync(c, ctx->ctl.p, sizeof(c), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (guard && ctx->fp32 && c[kCtlAttempts] > 0) {
+      double piv = 1.0;
+      HIPCHK(hipMemcpyAsync(&piv, ctx->ws.stats + 3, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+      HIPCHK(hipStreamSynchronize(ctx->stream));
+      if (piv < ctx->opt.mixed_pivot_floor) {
+        gs = promote_fp64(ctx);
+        if (gs != LREI_OK) return gs;
+        p = adapt_params(ctx, model, pair, kappa);
+        gs = ensure_graph();
+        if (gs != LREI_OK) return gs;
+        HIPCHK(hipMemcpyAsync(c, ctx->ctl.p, sizeof(c), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+      }
+    }
     if (c[kCtlDone] != 0.0 || c[kCtlFailed] != 0.0 || launched >= max_attempts) break;
     const double need = std::ceil((t_span - c[kCtlT]) / c[kCtlH]);
     int batch = need >= 16.0 ? 16 : (need < 1.0 ? 1 : (int)need);
@@ -1136,7 +1230,8 @@ lrei_status lrei_evolve_adaptive(lrei_ctx *ctx, int model, int pair, double kapp
   if (st != LREI_OK) return st;
   const auto t1 = std::chrono::steady_clock::now();
   if (h[13] != 0) {
-    HIPCHK(hipMemcpyAsync(ctx->blocks[0].p, ctx->save.p, vbytes, hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->blocks[0].p, ctx->save.p, (size_t)ctx->N * ctx->r * ctx->elem(),
+                          hipMemcpyDeviceToDevice, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return ctx->fail(LREI_E_NOTCONVERGED,
                      "Jacobi eigensolve hit the sweep limit; state restored to the start of the call");

@@ -29,20 +29,20 @@ class lrei_options(ctypes.Structure):
                 ("eig_max_sweeps", ctypes.c_int), ("warm", ctypes.c_int),
                 ("ab_bootstrap", ctypes.c_int), ("householder_mode", ctypes.c_int),
                 ("use_graph", ctypes.c_int), ("deterministic", ctypes.c_int),
-                ("autotune_cache", ctypes.c_char_p)]
+                ("autotune_cache", ctypes.c_char_p), ("mixed_pivot_floor", ctypes.c_double)]
 
 
 class lrei_stats(ctypes.Structure):
     _fields_ = [("steps_done", ctypes.c_int64), ("eigensolves", ctypes.c_int64),
                 ("warm_accepted", ctypes.c_int64), ("warm_rejected", ctypes.c_int64),
                 ("warm_iterations", ctypes.c_int64), ("dropped_directions", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("min_pivot_ratio", ctypes.c_double),
+                ("precision_promoted", ctypes.c_int32), ("min_pivot_ratio", ctypes.c_double),
                 ("ortho_error", ctypes.c_double), ("energy", ctypes.c_double),
                 ("last_step_ms", ctypes.c_double), ("phase_ms", ctypes.c_double * 8),
                 ("eig_phase_ms", ctypes.c_double * 6)]
 
     def as_dict(self):
-        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        d = {k: getattr(self, k) for k, _ in self._fields_}
         d["phase_ms"] = list(self.phase_ms)
         d["eig_phase_ms"] = list(self.eig_phase_ms)
         return d
@@ -169,10 +169,13 @@ class Context:
     """One LREI context (one trajectory) on a HIP device."""
 
     def __init__(self, device=0, stream=None, precision="fp64", eig_tol=1e-15, eig_max_sweeps=40,
-                 warm="analytic", householder_mode=0, use_graph=True, autotune_cache=None):
+                 warm="analytic", householder_mode=0, use_graph=True, autotune_cache=None,
+                 mixed_pivot_floor=None):
         self.lib = load()
         opt = lrei_options()
         self.lib.lrei_default_options(ctypes.byref(opt))
+        if mixed_pivot_floor is not None:
+            opt.mixed_pivot_floor = float(mixed_pivot_floor)
         opt.precision = PRECISIONS[precision]
         opt.eig_tol = eig_tol
         opt.eig_max_sweeps = eig_max_sweeps

@@ -639,3 +639,69 @@ def test_full_size_step_properties():
         c.close()
     print(f"energy change over 10 steps: kappa = 0 {e[0.0]:.3e}, kappa = 0.5 {e[0.5]:.3e}")
     assert abs(e[0.0]) <= 1e-4 * abs(e[0.5])
+
+
+def test_mixed_conditioning_guard_long_run():
+    """The 4x5 lattice workload (n = 20, r = 16) over 400 RK4 steps: as the
+    damped state relaxes, the Krylov basis grows ill-conditioned (the
+    smallest Cholesky pivot ratio falls from 5e-6 to 3e-7) and the FP32
+    blocks stop resolving it; without the guard the mixed run leaves the
+    1e-5 bound, with it (default floor 2e-6) the context moves to FP64
+    storage in time and stays within it."""
+    import torch
+    from tests_support_rel import rel_fro_gpu
+    cfg = make_config(3)
+    V0 = torch.from_numpy(cfg["V"]).cuda()
+    res = {}
+    for name, prec, floor in (("fp64", "fp64", None), ("guarded", "mixed", None), ("unguarded", "mixed", 0.0)):
+        c = _ctx(prec, mixed_pivot_floor=floor)
+        c.set_hamiltonian(cfg["n"], cfg["bonds"], cfg["J"], cfg["h"])
+        c.set_rho(cfg["lam"], V0)
+        c.step("qLL", "RK4", 0.01, 0.5, 400)
+        res[name] = (c.get_rho(torch.empty_like(V0))[1], c.stats())
+        c.close()
+    e_g = rel_fro_gpu(res["guarded"][0], res["fp64"][0], cfg["lam"])
+    e_u = rel_fro_gpu(res["unguarded"][0], res["fp64"][0], cfg["lam"])
+    print(f"400 steps: guarded {e_g:.2e} (promoted {res['guarded'][1]['precision_promoted']}), "
+          f"unguarded {e_u:.2e}, FP64 min pivot ratio {res['fp64'][1]['min_pivot_ratio']:.2e}")
+    assert res["guarded"][1]["precision_promoted"] == 1
+    assert res["unguarded"][1]["precision_promoted"] == 0
+    assert e_g < 1e-5
+    assert e_u > e_g
+
+
+def test_mixed_promotion_mechanics():
+    """A floor above every pivot ratio promotes a mixed context at the first
+    check (after 16 steps): the run continues in FP64 and matches the oracle
+    to the mixed bound; observables, pair matrices, AB steps and adaptive
+    stepping work afterwards, and an adaptive run promotes the same way."""
+    rng = np.random.default_rng(21)
+    n, r = 8, 4
+    bonds, J, h = _random_model(n, rng)
+    V, lam = _random_state(n, r, rng)
+    H = Hamiltonian(n, bonds, J, h)
+    c = _ctx("mixed", mixed_pivot_floor=1.0)
+    c.set_hamiltonian(n, bonds, J, h)
+    c.set_rho(lam, V)
+    c.step("qLLG", "RK4", 0.01, 0.3, 24)
+    assert c.stats()["precision_promoted"] == 1
+    Vo = oracle_run(H, V, lam, "qLLG", 0.3, 0.01, 24, "RK4")
+    assert rel_fro_error(c.get_rho()[1], lam, Vo, lam) < 1e-5
+    c.observables()
+    c.pair_density([[0, 1]])
+    c.step("qLLG", "AB3", 0.01, 0.3, 4)
+    c.step("qLLG", "RK4", 0.01, 0.3, 2)
+    c.close()
+    c = _ctx("mixed", mixed_pivot_floor=1.0)
+    c.set_hamiltonian(n, bonds, J, h)
+    c.set_rho(lam, V)
+    res = c.evolve_adaptive("qLLG", 0.3, 0.2, 1e-6, 0.01, h_min=1e-8, h_max=1.0, pair="RK43")
+    assert res["status"] == "done" and c.stats()["precision_promoted"] == 1
+    Vo, log = OA_evolve(H, V, lam, "qLLG", 0.3, 0.2, 1e-6, 0.01, 1e-8, 1.0, "RK43")
+    assert rel_fro_error(c.get_rho()[1], lam, Vo, lam) < 1e-5
+    c.close()
+
+
+def OA_evolve(H, V, lam, model, kappa, T, tol, h0, h_min, h_max, pair):
+    from oracle import adaptive
+    return adaptive.evolve(H, V, lam, model, kappa, T, tol, h0, h_min, h_max, pair=pair)
