@@ -97,7 +97,7 @@ def source_digest():
     return h.hexdigest()[:16]
 
 
-def cpu_baseline(cfg, n_rows=1 << 17, repeats=4):
+def cpu_baseline(cfg, n_rows=3 << 16, repeats=4):
     """The CPU oracle timed on a bounded sample of the same workload.
 
     Sample: the oracle's matrix-free H.V (Pauli-string gather) evaluated on
