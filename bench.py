@@ -116,7 +116,7 @@ def cpu_baseline(cfg, n_rows=3 << 16, repeats=4):
     return {
         "value": 1.0 / t_step, "unit": "steps/s", "cores": 1, "kind": "oracle",
         "sample": (f"oracle H.V on {n_rows} random rows x {repeats} (one per RK4 stage) of the "
-                   f"n={cfg['n']} r={cfg['r']} state, scaled x{N // n_rows} to all rows; "
+                   f"n={cfg['n']} r={cfg['r']} state, scaled x{N / n_rows:.3g} to all rows; "
                    f"excludes the oracle's Householder and eigensolve work, so the true oracle "
                    f"step rate is lower; measured {t:.2f} s, numpy single-threaded gathers"),
     }
