@@ -450,8 +450,11 @@ def run_learned_report(args, torch):
         de = {k: s1[k] - s0[k] for k in ("eigensolves", "warm_accepted", "warm_rejected", "warm_iterations")}
         return V, el, de
 
-    Vref, _, _ = run("fp64", "plain")
-    modes = {}
+    Vref, el_ref, de_ref = run("fp64", "plain")
+    modes = {"fp64_plain": {"ms_per_step": round(1e3 * el_ref / steps, 4), "steps_per_s": round(steps / el_ref, 2),
+                            "eigensolves": de_ref["eigensolves"], "precision": "fp64",
+                            "note": "the plain FP64 GPU path: direct solve, FP64 storage (the reference)"}}
+    print(f"[learned] fp64_plain: {json.dumps(modes['fp64_plain'])}", file=sys.stderr, flush=True)
     for warm in ("plain", "analytic", "predict_identity", "predict_cayley", "learned"):
         V, el, de = run("mixed", warm)
         modes[warm] = {"ms_per_step": round(1e3 * el / steps, 4), "steps_per_s": round(steps / el, 2),
