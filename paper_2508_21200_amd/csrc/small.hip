@@ -459,14 +459,28 @@ __device__ inline double rcp_nr(double b) {
 }
 
 // Number of eigenvalues of the real symmetric tridiagonal (d, e) below s, by
-// the ratio form of the Sturm sequence (pivots of LDL^T of T - s I).
+// the ratio form of the Sturm sequence (pivots of LDL^T of T - s I).  The
+// recurrence is a serial chain; (d, e^2) are read eight entries ahead of it.
 __device__ inline int sturm_count(const TriShared &ts, int m, double s, double pivmin) {
+  constexpr int B = 8;
   double q = ts.d[0] - s;
   int c = q < 0.0;
-  for (int i = 1; i < m; ++i) {
-    if (fabs(q) < pivmin) q = -pivmin;
-    q = (ts.d[i] - s) - ts.e2[i - 1] * rcp_nr(q);
-    c += q < 0.0;
+  for (int i0 = 1; i0 < m; i0 += B) {
+    double dd[B], ee[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const int i = i0 + u < m ? i0 + u : m - 1;
+      dd[u] = ts.d[i];
+      ee[u] = ts.e2[i - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      if (i0 + u < m) {
+        if (fabs(q) < pivmin) q = -pivmin;
+        q = (dd[u] - s) - ee[u] * rcp_nr(q);
+        c += q < 0.0;
+      }
+    }
   }
   return c;
 }
@@ -593,10 +607,15 @@ __device__ void eig_top(double2 *A, int m, int r, double2 *u, int ldu, int rows_
   }
   __syncthreads();
   // ---- multisection: G lanes per eigenvalue (32 when r <= 16, else 16), all
-  // within one wave; each round splits the bracket into G + 1 parts
+  // within one wave; each round splits the bracket into G + 1 parts.  The
+  // shifts only seed the inverse iteration below: 33^8 and 17^10 parts bring
+  // them within ~1e-12 of the Gershgorin width, and two inverse iterations
+  // then shrink a component along another eigenvector by (shift error / gap)^2,
+  // below FP64 rounding for any gap above 1e-6 of the norm (eigenvalues closer
+  // than 1e-3 of the norm are re-orthogonalised as a cluster).
   {
     const int G = r <= NT / 32 ? 32 : kGroup;
-    const int rounds = G == 32 ? 11 : 14;
+    const int rounds = G == 32 ? 8 : 10;
     const int k = threadIdx.x / G, t = threadIdx.x % G;
     const double pivmin = 1e-290;
     if (k < r) {
@@ -633,39 +652,73 @@ __device__ void eig_top(double2 *A, int m, int r, double2 *u, int ldu, int rows_
       for (int i = 0; i < m; ++i) X[i * SL + k] = 1.0 + 0.25 * (double)((7 * i + 3 * k) % 11);
     for (int it = 0; it < 2; ++it) {
       if (act) {
-        double u0 = ts.d[0] - lam, u1 = m > 1 ? ts.ae[0] : 0.0, u2 = 0.0;
+        double u0 = ts.d[0] - lam, u1 = m > 1 ? ts.ae[0] : 0.0;
         double rc = X[0 * SL + k];
-        for (int i = 0; i + 1 < m; ++i) {
-          const double an = ts.ae[i], bn = ts.d[i + 1] - lam, cn = (i + 2 < m) ? ts.ae[i + 1] : 0.0;
-          const double rn = X[(i + 1) * SL + k];
-          if (fabs(u0) >= fabs(an)) {
-            const double piv = u0 != 0.0 ? u0 : tiny;
-            const double f = an / piv;
-            U0[i * SL + k] = piv; U1[i * SL + k] = u1; U2[i * SL + k] = u2;
-            X[i * SL + k] = rc;
-            const double nu0 = bn - f * u1, nu1 = cn - f * u2;
-            rc = rn - f * rc;
-            u0 = nu0; u1 = nu1; u2 = 0.0;
-          } else {
-            const double f = u0 / an;
-            U0[i * SL + k] = an; U1[i * SL + k] = bn; U2[i * SL + k] = cn;
-            X[i * SL + k] = rn;
-            const double nu0 = u1 - f * bn, nu1 = u2 - f * cn;
-            rc = rc - f * rn;
-            u0 = nu0; u1 = nu1; u2 = 0.0;
+        // Elimination with row interchanges: the chain runs through u0, u1
+        // and rc; the tridiagonal and the right-hand side are read a block of
+        // IB rows ahead (row i + 1 of X is read before row i is written).  U0
+        // keeps the reciprocal of each pivot (hardware reciprocal refined by a
+        // Newton step), so no division sits on the chain here or in the
+        // back-substitution.  Pivots below 1e-290 are replaced by tiny.
+        constexpr int IB = 8;
+        constexpr double kFloor = 1e-290;
+        for (int i0 = 0; i0 + 1 < m; i0 += IB) {
+          double an_[IB], ian_[IB], bn_[IB], cn_[IB], rn_[IB];
+#pragma unroll
+          for (int q = 0; q < IB; ++q) {
+            const int i = i0 + q + 1 < m ? i0 + q : m - 2;
+            an_[q] = ts.ae[i];
+            ian_[q] = an_[q] > kFloor ? rcp_nr(an_[q]) : 0.0;
+            bn_[q] = ts.d[i + 1] - lam;
+            cn_[q] = (i + 2 < m) ? ts.ae[i + 1] : 0.0;
+            rn_[q] = X[(i + 1) * SL + k];
+          }
+#pragma unroll
+          for (int q = 0; q < IB; ++q) {
+            const int i = i0 + q;
+            if (i + 1 >= m) break;
+            const double an = an_[q], bn = bn_[q], cn = cn_[q], rn = rn_[q];
+            // keep row i as the pivot row unless the subdiagonal is larger
+            const bool keep = fabs(u0) >= an || !(an > kFloor);
+            const double piv = fabs(u0) > kFloor ? u0 : tiny;
+            const double ip = keep ? rcp_nr(piv) : ian_[q];
+            const double f = (keep ? an : u0) * ip;
+            U0[i * SL + k] = ip;
+            U1[i * SL + k] = keep ? u1 : bn;
+            U2[i * SL + k] = keep ? 0.0 : cn;
+            X[i * SL + k] = keep ? rc : rn;
+            const double nu0 = keep ? bn - f * u1 : u1 - f * bn;
+            const double nu1 = keep ? cn : -f * cn;
+            rc = keep ? rn - f * rc : rc - f * rn;
+            u0 = nu0;
+            u1 = nu1;
           }
         }
-        U0[(m - 1) * SL + k] = u0 != 0.0 ? u0 : tiny;
-        X[(m - 1) * SL + k] = rc;
-        double x2 = 0.0, x1 = X[(m - 1) * SL + k] / U0[(m - 1) * SL + k];
+        const double ipl = rcp_nr(fabs(u0) > kFloor ? u0 : tiny);
+        double x2 = 0.0, x1 = rc * ipl;
         X[(m - 1) * SL + k] = x1;
         double nrm = x1 * x1;
-        for (int i = m - 2; i >= 0; --i) {
-          const double xi = (X[i * SL + k] - U1[i * SL + k] * x1 - U2[i * SL + k] * x2) / U0[i * SL + k];
-          X[i * SL + k] = xi;
-          nrm += xi * xi;
-          x2 = x1;
-          x1 = xi;
+        // back-substitution, rows read a block ahead of the chain through x1, x2
+        for (int i0 = m - 2; i0 >= 0; i0 -= IB) {
+          double r_[IB], a_[IB], b_[IB], c_[IB];
+#pragma unroll
+          for (int q = 0; q < IB; ++q) {
+            const int i = i0 - q >= 0 ? i0 - q : 0;
+            r_[q] = X[i * SL + k];
+            a_[q] = U0[i * SL + k];
+            b_[q] = U1[i * SL + k];
+            c_[q] = U2[i * SL + k];
+          }
+#pragma unroll
+          for (int q = 0; q < IB; ++q) {
+            const int i = i0 - q;
+            if (i < 0) break;
+            const double xi = (r_[q] - b_[q] * x1 - c_[q] * x2) * a_[q];
+            X[i * SL + k] = xi;
+            nrm += xi * xi;
+            x2 = x1;
+            x1 = xi;
+          }
         }
         const double inv = 1.0 / sqrt(nrm);
         for (int i = 0; i < m; ++i) X[i * SL + k] *= inv;
