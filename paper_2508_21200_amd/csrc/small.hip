@@ -1151,6 +1151,7 @@ struct StepShared {
   double2 vec[4 * kMaxR];
   double hbeta[kTriDim];
   unsigned char drop[kTriDim];
+  double rkk[kTriDim];  // Cholesky: the diagonal of R (1 for a dropped direction)
   double minpiv, dev;
   int ndrop;
   double coef[kMaxStages > kMaxAb ? kMaxStages : kMaxAb];  // stage or AB weights, or error weights
@@ -1172,32 +1173,42 @@ __device__ void chol_drop(const double2 *G, int ldg, const double2 *orig, int ld
     sh.ndrop = 0;
   }
   __syncthreads();
+  // Right-looking elimination with one barrier per column: the trailing
+  // block is updated with the unscaled row k, C_ij -= conj(C_ki) C_kj / piv,
+  // and the rows are scaled by 1 / R_kk only at the end (row k is not written
+  // again after step k).  Threads form a 16 x 32 grid over the upper triangle.
   for (int k = 0; k < n; ++k) {
     const double piv = C[k * ldc + k].x, og = orig[k * ldo].x;
     const bool dropped = !(piv > 1e-13 * og) || !(og > 0);
     if (threadIdx.x == 0) {
       drop[k] = dropped;
+      sh.rkk[k] = dropped ? 1.0 : sqrt(piv);
       if (dropped)
         sh.ndrop += 1;
       else
         sh.minpiv = fmin(sh.minpiv, piv / og);
     }
-    const double rkk = dropped ? 1.0 : sqrt(piv);
-    const int w = n - k - 1;
-    for (int j = k + 1 + threadIdx.x; j < n; j += NT)
-      C[k * ldc + j] = dropped ? make_double2(0, 0) : cscale(1.0 / rkk, C[k * ldc + j]);
-    if (in_lds) lds_barrier(); else __syncthreads();
-    if (!dropped)
-      for (int e = threadIdx.x; e < w * w; e += NT) {
-        const int i = k + 1 + e / w, j = k + 1 + e % w;
-        if (j >= i) C[i * ldc + j] = csub(C[i * ldc + j], cmulc(C[k * ldc + i], C[k * ldc + j]));
+    if (!dropped) {
+      const double ip = 1.0 / piv;
+      for (int i = k + 1 + (threadIdx.x >> 5); i < n; i += NT / 32) {
+        const double2 cki = cscale(ip, cconj(C[k * ldc + i]));
+        for (int j = i + (threadIdx.x & 31); j < n; j += 32)
+          C[i * ldc + j] = csub(C[i * ldc + j], cmul(cki, C[k * ldc + j]));
       }
-    if (threadIdx.x == 0) C[k * ldc + k] = make_double2(rkk, 0.0);
+    }
     if (in_lds) lds_barrier(); else __syncthreads();
   }
+  // R: diagonal rkk, row k above it C_kj / rkk (zero for a dropped direction),
+  // zero below (in place when C is R: each entry is read and written by one
+  // thread)
   for (int e = threadIdx.x; e < n * n; e += NT) {
     const int i = e / n, j = e % n;
-    R[i * ldr + j] = i > j ? make_double2(0, 0) : C[i * ldc + j];
+    double2 v = make_double2(0, 0);
+    if (i == j)
+      v = make_double2(sh.rkk[i], 0.0);
+    else if (i < j && !drop[i])
+      v = cscale(1.0 / sh.rkk[i], C[i * ldc + j]);
+    R[i * ldr + j] = v;
   }
   __syncthreads();
 }
