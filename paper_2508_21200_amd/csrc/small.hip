@@ -1232,6 +1232,39 @@ __device__ void upper_inverse(const double2 *R, int ldr, double2 *Ri, int ldi, i
   }
   for (int e = threadIdx.x; e < n * n; e += NT) Is[(e / n) * li + e % n] = make_double2(0, 0);
   __syncthreads();
+  // In LDS, G lanes (4, 8 or 16, an aligned part of a 16-lane row) share a
+  // column: each sums every G-th product and a DPP reduction within the group
+  // completes the sum, so the chain per entry is n / G products long.  Lane 0
+  // of the group writes the entry, which the group's lanes read back in the
+  // next steps (LDS accesses of one wave complete in order).
+  const int lg = n <= 16 ? 4 : n <= 32 ? 4 : n <= 64 ? 3 : n <= 128 ? 2 : 0;
+  if (in_lds && lg > 0 && (n << lg) <= NT) {
+    const int G = 1 << lg, c = threadIdx.x >> lg, t = threadIdx.x & (G - 1);
+    if (c < n) {
+      if (t == 0) Is[c * li + c] = cdiv(make_double2(1, 0), Rs[c * lr + c]);
+      for (int i = c - 1; i >= 0; --i) {
+        double sr = 0, si = 0;
+        for (int k = i + 1 + t; k <= c; k += G) {
+          const double2 a = Rs[i * lr + k], b = Is[k * li + c];
+          sr += a.x * b.x - a.y * b.y;
+          si += a.x * b.y + a.y * b.x;
+        }
+        sr += dpp_d<0xB1>(sr);
+        si += dpp_d<0xB1>(si);
+        sr += dpp_d<0x4E>(sr);
+        si += dpp_d<0x4E>(si);
+        if (lg >= 3) {
+          sr += dpp_d<0x141>(sr);
+          si += dpp_d<0x141>(si);
+        }
+        if (lg >= 4) {
+          sr += dpp_d<0x140>(sr);
+          si += dpp_d<0x140>(si);
+        }
+        if (t == 0) Is[i * li + c] = cdiv(make_double2(-sr, -si), Rs[i * lr + i]);
+      }
+    }
+  } else
   for (int c = threadIdx.x; c < n; c += NT) {
     Is[c * li + c] = cdiv(make_double2(1, 0), Rs[c * lr + c]);
     for (int i = c - 1; i >= 0; --i) {
