@@ -11,14 +11,18 @@ Gram products, the FP64 projected step (Householder complement action, stage
 combination, four partial eigensolves) and the basis combination.
 
 Prints one JSON line.  Extra fields: `roofline` for the dominant kernel (the
-H.V pass), `cpu_baseline` (the CPU oracle on a bounded sample), `parity`
-(relative Frobenius error of the timed run against the FP64 GPU path on the
-same inputs), `kernels_ms` (per-kernel averages).
+H.V pass), `cpu_baseline` (one complete step of the CPU oracle on the same
+inputs, measured in a child process that runs beside the GPU work), `parity`
+(relative Frobenius error of one GPU step, mixed and FP64, against that oracle
+step), `fp64_path` (the FP64 GPU path's rate on the same workload),
+`kernels_ms` (per-kernel averages).
 """
 import argparse
 import json
 import os
+import subprocess
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -63,6 +67,11 @@ def parse():
     ap.add_argument("--train-epochs", type=int, default=20)
     ap.add_argument("--train-lr", type=float, nargs="+", default=[1e-6, 3e-7, 1e-7],
                     help="Adam step sizes tried; the best on the validation trajectories is kept")
+    ap.add_argument("--oracle-deadline", type=float, default=420.0,
+                    help="seconds after start by which the oracle step (cpu_baseline, parity) must finish; "
+                         "past it the child is stopped and both are reported as not measured")
+    ap.add_argument("--oracle-child", default=None, metavar="DIR",
+                    help=argparse.SUPPRESS)  # internal: run one oracle step of --config and write it to DIR
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="run a plain device-to-device copy of MIB MiB five times and exit "
                          "(reference kernel for scaling FETCH_SIZE / WRITE_SIZE counters)")
@@ -119,29 +128,83 @@ def source_digest():
     return h.hexdigest()[:16]
 
 
-def cpu_baseline(cfg, n_rows=3 << 16, repeats=4):
-    """The CPU oracle timed on a bounded sample of the same workload.
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
-    Sample: the oracle's matrix-free H.V (Pauli-string gather) evaluated on
-    `n_rows` random rows of the n=20, r=16 state, `repeats` times (the four
-    RK4 stages), scaled to all N rows.  The oracle's Householder action and
-    partial eigensolves are not included, so its true step rate is lower.
-    """
-    from oracle.hamiltonian import apply_H_rows
-    N = 2 ** cfg["n"]
-    rows = np.random.default_rng(0).choice(N, size=n_rows, replace=False)
+
+def oracle_child(args):
+    """Child process: one complete oracle LREI step of the workload from its
+    initial state (all rows, no sampling); writes V and the wall time."""
+    from workloads import make_config
+    from oracle.hamiltonian import Hamiltonian
+    from oracle.schemes import lrei_rk_step
+    cfg = make_config(args.config)
+    H = Hamiltonian(cfg["n"], cfg["bonds"], cfg["J"], cfg["h"])
     t0 = time.perf_counter()
-    for _ in range(repeats):
-        apply_H_rows(cfg["n"], cfg["bonds"], cfg["J"], cfg["h"], cfg["V"], rows)
+    V1 = lrei_rk_step(H, cfg["V"], cfg["lam"], cfg["model"], cfg["kappa"], cfg["dt"], cfg["scheme"])
     t = time.perf_counter() - t0
-    t_step = t * (N / n_rows)
-    return {
-        "value": 1.0 / t_step, "unit": "steps/s", "cores": 1, "kind": "oracle",
-        "sample": (f"oracle H.V on {n_rows} random rows x {repeats} (one per RK4 stage) of the "
-                   f"n={cfg['n']} r={cfg['r']} state, scaled x{N / n_rows:.3g} to all rows; "
-                   f"excludes the oracle's Householder and eigensolve work, so the true oracle "
-                   f"step rate is lower; measured {t:.2f} s, numpy single-threaded gathers"),
-    }
+    np.save(os.path.join(args.oracle_child, "V1.npy"), V1)
+    with open(os.path.join(args.oracle_child, "t.json"), "w") as f:
+        json.dump({"seconds": t}, f)
+
+
+class OracleStep:
+    """One oracle step of the benchmark workload in a child process, started
+    before the GPU work.  The child keeps off the CPU this process runs on and
+    leaves one more core free, so the timed GPU region is not disturbed; its
+    BLAS uses the remaining cores (numpy's gathers are single-threaded)."""
+
+    def __init__(self, args):
+        self.dir = tempfile.mkdtemp(prefix="lrei_oracle_")
+        self.all_cpus = os.sched_getaffinity(0)
+        cpus = sorted(self.all_cpus)
+        keep = cpus[2:] if len(cpus) > 2 else cpus
+        self.threads = len(keep)
+        env = dict(os.environ)
+        for k in ("OPENBLAS_NUM_THREADS", "OMP_NUM_THREADS", "MKL_NUM_THREADS"):
+            env[k] = str(self.threads)
+        cmd = [sys.executable, os.path.abspath(__file__), "--oracle-child", self.dir, "--config", str(args.config)]
+        self.t_start = time.perf_counter()
+        self.proc = subprocess.Popen(cmd, env=env, stdout=subprocess.DEVNULL, stderr=subprocess.PIPE,
+                                     preexec_fn=lambda: os.sched_setaffinity(0, keep))
+        if len(cpus) > 2:  # this process (and the GPU runtime's threads) on the other two
+            os.sched_setaffinity(0, cpus[:2])
+
+    def wait(self, deadline_s, t0):
+        left = deadline_s - (time.perf_counter() - t0)
+        try:
+            self.proc.wait(timeout=max(1.0, left))
+        except subprocess.TimeoutExpired:
+            self.proc.kill()
+            self.proc.wait()
+            return None, {"value": None, "unit": "steps/s", "cores": self.threads, "kind": "oracle",
+                          "sample": (f"one complete oracle step did not finish within the benchmark's time "
+                                     f"budget ({time.perf_counter() - self.t_start:.0f} s, {cpu_model()}); "
+                                     f"not measured")}
+        if self.proc.returncode != 0:
+            err = self.proc.stderr.read().decode(errors="replace")[-400:]
+            return None, {"value": None, "unit": "steps/s", "cores": self.threads, "kind": "oracle",
+                          "sample": f"the oracle child failed: {err}"}
+        V1 = np.load(os.path.join(self.dir, "V1.npy"))
+        with open(os.path.join(self.dir, "t.json")) as f:
+            t = json.load(f)["seconds"]
+        return V1, {"value": 1.0 / t, "unit": "steps/s", "cores": self.threads, "kind": "oracle",
+                    "sample": (f"one complete oracle LREI step of this workload from its initial state: all "
+                               f"2^n rows, no sampling, no scaling; {t:.1f} s wall on {cpu_model()}, BLAS threads "
+                               f"{self.threads} (numpy's row gathers in the oracle's H.V are single-threaded)")}
+
+    def cleanup(self):
+        import shutil
+        shutil.rmtree(self.dir, ignore_errors=True)
+        os.sched_setaffinity(0, self.all_cpus)
 
 
 def cpu_baseline_batch(trajs, budget_s=20.0):
@@ -582,10 +645,20 @@ def run_batch(args, torch):
 
 def main():
     args = parse()
+    if args.oracle_child:
+        oracle_child(args)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "requested_gpus": args.gpus}))
         sys.exit(2)
+    t_main = time.perf_counter()
+    single = not (args.copy_calibration or args.config == 4 or args.learned_report or args.rk_vs_ab or
+                  args.adaptive_report or args.scaling_report or args.kernels_only or args.profile_only)
+    # the oracle's step runs beside the GPU work (it takes minutes at n = 20)
+    from workloads.configs import CONFIGS
+    rk = args.config in CONFIGS and CONFIGS[args.config]["scheme"].startswith("RK")
+    oracle = OracleStep(args) if single and rk and not (args.no_cpu_baseline and args.no_parity) else None
     import torch
     if args.copy_calibration:
         nbytes = args.copy_calibration << 20
@@ -619,6 +692,7 @@ def main():
     scheme = cfg["scheme"]
     model = cfg["model"]
     dt, kappa = cfg["dt"], cfg["kappa"]
+    one_step = scheme.startswith("RK")  # the oracle comparison takes one step from the initial state
 
     def make_ctx(prec):
         c = Context(device=0, precision=prec, autotune_cache=args.tune_cache)
@@ -633,19 +707,28 @@ def main():
         kms = ctx.profile_kernels(model, scheme, dt, kappa, iters=20)
         print(json.dumps({"kernels_ms": kms}))
         return
-    print(f"[bench] workload {cfg['name']} precision={precision} warmup={args.warmup} "
-          f"steps={args.steps}", file=sys.stderr, flush=True)
-    if args.warmup > 0:
-        ctx.step(model, scheme, dt, kappa, args.warmup)
-    torch.cuda.synchronize()
-    ctx.synchronize()
-    t0 = time.perf_counter()
-    ctx.step(model, scheme, dt, kappa, args.steps)
-    ctx.synchronize()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    elapsed = t1 - t0
-    print(f"[bench] timed {args.steps} steps in {elapsed:.4f} s", file=sys.stderr, flush=True)
+    V1_gpu = {}
+    if not args.no_parity and one_step:
+        ctx.step(model, scheme, dt, kappa, 1)
+        V1_gpu[precision] = ctx.get_rho()[1]
+        ctx.set_rho(cfg["lam"], cfg["V"])  # back to the initial state (same rank: the tuned shape stays)
+
+    def timed_run(c, prec):
+        print(f"[bench] workload {cfg['name']} precision={prec} warmup={args.warmup} steps={args.steps}",
+              file=sys.stderr, flush=True)
+        if args.warmup > 0:
+            c.step(model, scheme, dt, kappa, args.warmup)
+        torch.cuda.synchronize()
+        c.synchronize()
+        t0 = time.perf_counter()
+        c.step(model, scheme, dt, kappa, args.steps)
+        c.synchronize()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        print(f"[bench] {prec}: timed {args.steps} steps in {el:.4f} s", file=sys.stderr, flush=True)
+        return el
+
+    elapsed = timed_run(ctx, precision)
     stats = ctx.stats()
     if args.profile_only:
         print(json.dumps({"steps": args.steps, "ms_per_step": 1e3 * elapsed / args.steps}))
@@ -654,7 +737,7 @@ def main():
     kms = ctx.profile_kernels(model, scheme, dt, kappa, iters=20)
     elem = 8 if precision == "mixed" else 16
     F = (2 ** cfg["n"]) * cfg["r"] * elem
-    hv_bytes = 3 * F  # read P_j, read P_{j-1}, write P_{j+1}
+    hv_bytes = 2 * F  # algorithmic: read P_j once, write P_{j+1} once (partner rows are re-reads of P_j)
     achieved = hv_bytes / (kms["hv_pass"] * 1e-3) / 1e9
     traffic = None
     tfile = os.path.join(ROOT, "profiles", "hv_pass_traffic.json")
@@ -670,22 +753,30 @@ def main():
     copy = measured_copy_gbs(torch)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "k_cheb (H.V Chebyshev pass, fused Grams)",
+                "traffic_over_algorithmic": None if traffic is None else round(traffic / hv_bytes, 3),
+                "kernel": "k_hv (H.V Krylov pass, fused Grams)",
                 "algorithmic_bytes_per_launch": hv_bytes,
+                "algorithmic_model": "2F per pass, F = N r c (read P_j, write P_{j+1})",
                 "measured_copy_peak": copy, "frac_of_copy_peak": round(achieved / copy["GBs"], 4)}
 
-    parity = None
-    if not args.no_parity:
-        _, Vt = ctx.get_rho()
-        if precision == "fp64":
-            parity = {"vs": "self (fp64)", "rel_fro": 0.0}
-        else:
-            ref = make_ctx("fp64")
-            ref.step(model, scheme, dt, kappa, args.warmup + args.steps)
-            _, Vr = ref.get_rho()
-            parity = {"vs": "FP64 GPU path, same inputs and step count",
-                      "rel_fro": rel_fro(torch, Vt, Vr, cfg["lam"])}
-            ref.close()
+    # the FP64 path on the same workload: its rate, its one-step result, and
+    # the mixed run's distance from it after the timed steps
+    fp64 = None
+    V_end = ctx.get_rho()[1]
+    if precision == "mixed" and not args.no_parity:
+        ref = make_ctx("fp64")
+        if one_step:
+            ref.step(model, scheme, dt, kappa, 1)
+            V1_gpu["fp64"] = ref.get_rho()[1]
+            ref.set_rho(cfg["lam"], cfg["V"])
+        el64 = timed_run(ref, "fp64")
+        _, Vr = ref.get_rho()
+        fp64 = {"steps_per_s": args.steps / el64, "ms_per_step": 1e3 * el64 / args.steps,
+                "mixed_over_fp64": round(el64 / elapsed, 3),
+                "mixed_vs_fp64_after_timed_steps": rel_fro(torch, V_end, Vr, cfg["lam"]),
+                "note": "FP64 GPU path (complex FP64 N-space passes), same inputs, warmup and steps; the "
+                        "distance is after warmup + timed steps"}
+        ref.close()
 
     # two-spin reduced density matrices of 64 site pairs in one call (one fused
     # pass over the state per pair; algorithmic bytes F per pair)
@@ -700,9 +791,23 @@ def main():
                 "note": "host wall clock of the synchronous ABI call (upload of the pair list, passes, "
                         "reduction, copy-back)"}
 
-    cpu = None if args.no_cpu_baseline else cpu_baseline(cfg)
+    cpu = None
+    parity = None
+    if oracle is not None:
+        V1_o, cpu = oracle.wait(args.oracle_deadline, t_main)
+        oracle.cleanup()
+        if V1_o is not None:
+            from oracle.metrics import rel_fro_error
+            parity = {"vs": "oracle", "steps": 1,
+                      "note": "one step from the workload's initial state, GPU against the CPU complex128 oracle; "
+                              "bounds: mixed 1e-5, FP64 1e-10"}
+            for prec, Vg in V1_gpu.items():
+                parity[f"rel_fro_{prec}"] = rel_fro_error(Vg, cfg["lam"], V1_o, cfg["lam"])
+        elif V1_gpu:
+            parity = {"vs": "oracle", "steps": 1, "rel_fro_mixed": None, "rel_fro_fp64": None,
+                      "note": "the oracle step did not complete: " + cpu["sample"]}
     line = {
-        "metric": "LREI steps/s (n=20, r=16)",
+        "metric": "LREI steps/s (n=20, r=16)" if args.config == 3 else f"LREI steps/s ({cfg['name']})",
         "value": args.steps / elapsed,
         "unit": "steps/s",
         "n_gpus": 1,
@@ -720,6 +825,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "parity": parity,
+        "fp64_path": fp64,
         "kernels_ms": {k: round(v, 5) for k, v in kms.items()},
         "pair_density": pair_obs,
         "hv_tuning": None if tuning is None else {

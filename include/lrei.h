@@ -5,7 +5,7 @@
  * quantum Landau-Lifshitz (q-LL, eq. 1.1) or Landau-Lifshitz-Gilbert (q-LLG,
  * eq. 1.2) equation for an n-spin density matrix rho = V Lambda_0 V* of rank r
  * (Sec. 3.1, eq. 3.1).  Only the N x r factor V is stored (N = 2^n, Sec. 3.2);
- * the spectrum Lambda_0 is fixed for all time (Sec. 2, Sec. 3.6).
+ * the spectrum Lambda_0 is fixed for all time (Sec. 2, Sec. 3.7).
  *
  * Conventions for every entry point:
  *  - Status codes are returned; no exception or abort crosses the ABI.  The
@@ -50,7 +50,7 @@ typedef enum {
 
 typedef enum { LREI_QLL = 0, LREI_QLLG = 1 } lrei_model;
 
-/* Time integrators (Sec. 3.6, 3.7).  RK2 is the paper's Heun tableau; RK3 is
+/* Time integrators (Sec. 3.7, 3.8).  RK2 is the paper's Heun tableau; RK3 is
  * Kutta's; RK4 is the classical method.  ABm use the standard Adams-Bashforth
  * weights with an RK start-up (see lrei_options.ab_bootstrap). */
 typedef enum {
@@ -75,7 +75,7 @@ typedef enum { LREI_PAIR_HE21 = 21, LREI_PAIR_BS32 = 32, LREI_PAIR_RK43 = 43 } l
  * eigensolve) always runs in FP64. */
 typedef enum { LREI_FP64 = 0, LREI_MIXED = 1 } lrei_precision;
 
-/* How each stage's partial eigensolve (Sec. 3.6: the r largest eigenpairs of
+/* How each stage's partial eigensolve (Sec. 3.7: the r largest eigenpairs of
  * the stage matrix) is computed in the projected coordinates.
  *  LREI_WARM_PLAIN: direct solve (Householder tridiagonalisation, multisection,
  *    inverse iteration), exact to FP64 rounding whatever the start.
@@ -123,6 +123,10 @@ typedef struct {
                              life (checked every 16 steps and at the end of a call;
                              lrei_stats.precision_promoted reports it).  Default 2e-6;
                              0 disables the check                                    */
+  int fail_after_steps;   /* for tests of the failure path: k > 0 makes every lrei_step
+                             call with n_steps >= k run its steps and then fail as a
+                             non-finite step does (LREI_E_NUMERIC, state restored to
+                             the start of the call).  Default 0 (off)                */
 } lrei_options;
 
 typedef struct {
@@ -174,13 +178,15 @@ LREI_API lrei_status lrei_set_hamiltonian(lrei_ctx *ctx, int n_spins, int n_bond
 
 /* Sets rho = V diag(lambda) V* (Sec. 3.1, eq. 3.1).  lambda: r finite values,
  * strictly positive, non-increasing.  V: N x r complex128 with orthonormal
- * columns (max |V*V - I| <= 1e-10), host or device pointer.  1 <= r <= 32,
+ * columns (max |V*V - I| <= 1e-10 on a LREI_FP64 context, <= 1e-5 on a
+ * LREI_MIXED one, whose check runs on the FP32-rounded copy), host or device
+ * pointer.  1 <= r <= 32,
  * r <= N.  Requires a Hamiltonian. */
 LREI_API lrei_status lrei_set_rho(lrei_ctx *ctx, int r, const double *lambda, const void *V, int v_is_device);
 
 /* Advances n_steps >= 0 time steps of size dt > 0 with damping kappa >= 0
  * (q-LL: eq. 1.1 through eq. 4.1; q-LLG: eq. 1.2 through eq. 3.2), using the
- * LREI-RK (Sec. 3.6) or LREI-AB (Sec. 3.7) scheme.  Adams-Bashforth history
+ * LREI-RK (Sec. 3.7) or LREI-AB (Sec. 3.8) scheme.  Adams-Bashforth history
  * carries over between calls with the same model, scheme, dt and kappa; any
  * change restarts it with the bootstrap scheme.  On a numerical failure
  * (LREI_E_NUMERIC, LREI_E_NOTCONVERGED) the state is restored to that at the
@@ -201,7 +207,7 @@ typedef struct {
 
 /* Advances the state by t_span > 0 with step-size control from local error
  * estimates (the paper's outlook, Sec. 6), using the embedded pair `pair`
- * (lrei_pair) in LREI form: each attempt is an LREI-RK step (Sec. 3.6) with
+ * (lrei_pair) in LREI form: each attempt is an LREI-RK step (Sec. 3.7) with
  * the pair's higher-order weights; the two candidate matrices of eq. 3.9
  * (weights b and b_hat) differ by E = h sum_l (b_l - b_hat_l) f(rho_l), and
  * the estimate is the Frobenius norm of the part of E tangent to the
@@ -225,12 +231,12 @@ LREI_API lrei_status lrei_evolve_adaptive(lrei_ctx *ctx, int model, int pair, do
                                           double tol, double h_init, double h_min, double h_max, int max_attempts,
                                           lrei_adapt_result *out);
 
-/* Copies the current state out: lambda (r values, always Lambda_0, Sec. 3.6)
+/* Copies the current state out: lambda (r values, always Lambda_0, Sec. 3.7)
  * and V (N x r complex128, host or device pointer).  Either may be NULL. */
 LREI_API lrei_status lrei_get_rho(lrei_ctx *ctx, double *lambda, void *V, int v_is_device);
 
 /* Energy Tr(Lambda_0 V* H V) and magnetisation M_v = (1/n) sum_i <S_i^v>
- * with S = (hbar/2) s (Sec. 3.5, eq. 3.6) for the current state.  Either
+ * with S = (hbar/2) s (Sec. 3.6, eq. 3.6) for the current state.  Either
  * output may be NULL. */
 LREI_API lrei_status lrei_observables(lrei_ctx *ctx, double *energy, double magnetization[3]);
 
@@ -294,7 +300,7 @@ LREI_API lrei_status lrei_autotune(lrei_ctx *ctx, lrei_tune_result *out);
  * whole batch (one launch per kernel and launch shape, the trajectories'
  * work concatenated in the grid), so small problems do not each pay for
  * their own launches.  Each trajectory computes exactly what a single
- * context would (Sec. 3.6 steps with the same stage algebra); only the
+ * context would (Sec. 3.7 steps with the same stage algebra); only the
  * launch packing differs.  Sites are stored in their natural order (site i in
  * bit i). */
 typedef struct lrei_batch lrei_batch;
@@ -339,7 +345,7 @@ LREI_API lrei_status lrei_batch_step(lrei_batch *b, int scheme, double dt, int n
 /* Copies trajectory traj's state out (as lrei_get_rho); lambda or V may be NULL. */
 LREI_API lrei_status lrei_batch_get_rho(lrei_batch *b, int traj, double *lambda, void *V, int v_is_device);
 
-/* Energy Tr(Lambda_0 V* H V) of every trajectory's current state (Sec. 3.5),
+/* Energy Tr(Lambda_0 V* H V) of every trajectory's current state (Sec. 3.6),
  * energy[n_traj]. */
 LREI_API lrei_status lrei_batch_energies(lrei_batch *b, double *energy);
 
@@ -361,7 +367,7 @@ LREI_API lrei_status lrei_get_rank(lrei_ctx *ctx, int *r);
 /* Sets rho = A A* / Tr(A A*) from a factor A (N x m complex128, row-major,
  * natural basis order, host or device; columns need not be orthonormal),
  * 1 <= m <= min(32, N): the partial eigendecomposition the run starts from
- * (Sec. 3.6), computed on the GPU from the Gram matrix A* A; eigenvalues at or
+ * (Sec. 3.7), computed on the GPU from the Gram matrix A* A; eigenvalues at or
  * below 1e-14 of the largest are dropped, so r = rank rho (read it with
  * lrei_get_rho).  Requires a Hamiltonian; errors as lrei_set_rho, plus
  * LREI_E_INVALID for a zero factor. */
@@ -379,7 +385,7 @@ LREI_API lrei_status lrei_set_rho_factor(lrei_ctx *ctx, int m, const void *A, in
 LREI_API lrei_status lrei_set_mixing(lrei_ctx *ctx, double p);
 
 /* Two-spin reduced density matrices R_kl = Tr_rest(rho) of the current state
- * (Sec. 3.5: the partial trace over every spin but k and l) for n_pairs
+ * (Sec. 3.6: the partial trace over every spin but k and l) for n_pairs
  * (1..4096) site pairs.  pairs (host): 2 n_pairs site indices, k != l, both
  * < n.  out (host, 32 n_pairs doubles): per pair a 4 x 4 complex matrix,
  * row-major, (re, im) pairs; row and column index q = 2 b_k + b_l, b the
@@ -389,7 +395,7 @@ LREI_API lrei_status lrei_set_mixing(lrei_ctx *ctx, double p);
 LREI_API lrei_status lrei_pair_density(lrei_ctx *ctx, int n_pairs, const int *pairs, double *out);
 
 /* Entanglement of a two-spin density matrix R (32 doubles laid out as
- * above), computed on the host (Sec. 3.5 names these measures):
+ * above), computed on the host (Sec. 3.6 names these measures):
  * concurrence max(0, l1 - l2 - l3 - l4) with l_i the square roots of the
  * eigenvalues of R (sy x sy) conj(R) (sy x sy), descending (Wootters);
  * negativity, the sum of |negative eigenvalues| of the partial transpose on
@@ -401,7 +407,7 @@ LREI_API lrei_status lrei_pair_entanglement(const double *R, double *concurrence
                                             double *chsh);
 
 /* ---- Learned start rotation (production form on top of the stage
- * eigensolve of Sec. 3.6; the paper has no such component) ----------------
+ * eigensolve of Sec. 3.7; the paper has no such component) ----------------
  *
  * A network (lrei_net) is a multilayer perceptron for one rank r (1..16): 2 r^2 + 2 inputs
  * (Re, Im of G / |G|_F with G = u* H u the stage input basis' projected

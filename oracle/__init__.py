@@ -8,7 +8,7 @@ with that path: the only common module is ``workloads`` (seeded inputs).
 What it computes, step by step in the paper's order (arXiv 2508.21200):
 
 * ``hamiltonian``  the spin Hamiltonian of Sec. 5 (eq. 5.1) applied matrix-free
-  through Pauli strings (Sec. 3.5, eq. 3.5), plus a dense Kronecker builder for
+  through Pauli strings (Sec. 3.6, eq. 3.5), plus a dense Kronecker builder for
   small n;
 * ``rhs``          the low-rank q-LLG / q-LL right-hand side: X-blocks
   (eq. 3.2 / eq. 4.1), Householder reflectors of the support (eq. 3.3) and
@@ -16,7 +16,7 @@ What it computes, step by step in the paper's order (arXiv 2508.21200):
 * ``lowrank``      the stage matrices in low-rank form (eqs. 3.8, 3.9), the
   matvec g (eq. 3.10) and the partial eigendecomposition (its plain
   definition: the r largest eigenpairs, computed exactly);
-* ``schemes``      LREI-RK (Sec. 3.6) and LREI-AB (Sec. 3.7) time steps with
+* ``schemes``      LREI-RK (Sec. 3.7) and LREI-AB (Sec. 3.8) time steps with
   the spectrum held at Lambda_0;
 * ``adaptive``     step-size control from local error estimates (the
   paper's future work, Sec. 6): embedded Heun-Euler 2(1) and

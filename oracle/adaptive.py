@@ -7,7 +7,7 @@ estimates as future work (Sec. 6).  The reading implemented here, and by the
 GPU path:
 
 * An embedded pair (a, b, b_hat) advances the state with the LREI-RK step of
-  Sec. 3.6 for the tableau (a, b): stages by eq. 3.8, the new state by
+  Sec. 3.7 for the tableau (a, b): stages by eq. 3.8, the new state by
   eq. 3.9, each followed by the partial eigendecomposition with Lambda_0.
   The embedded weights b_hat share those stages; a pair marked FSAL ("first
   same as last") also weights the right-hand side at the new state.

@@ -3,7 +3,7 @@
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
 The paper does not have this component; it is a production form built on top
-of the stage eigensolve of Sec. 3.6 (the r largest eigenvectors of each stage
+of the stage eigensolve of Sec. 3.7 (the r largest eigenvectors of each stage
 matrix).  What it computes, in the order the GPU path does:
 
 * features of a stage: the projected generator G = u* H u of the stage's

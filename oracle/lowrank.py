@@ -4,7 +4,7 @@ A stage matrix (eq. 3.8) or the new step value (eq. 3.9) is kept as
     K = sum_l (A_l V_l* + V_l B_l*),
 never as an N x N array.  ``LowRank`` stores the triples (A_l, V_l, B_l).
 
-The partial eigendecomposition (Sec. 3.6) wants the r eigenpairs of the
+The partial eigendecomposition (Sec. 3.7) wants the r eigenpairs of the
 Hermitian K with the largest eigenvalues (a reading: the paper's IRLM call
 leaves the ordering unstated; the r largest algebraic ones, sorted
 descending, pair with Lambda_0 sorted descending, Sec. 3.1).  Its plain
@@ -62,7 +62,7 @@ def stage_matrix(V1, lam0, stage_terms, h, coeffs):
 
     stage_terms: list of (V_l, Z_l, W_l) for l = 1..j; coeffs: a_{j+1,l} (or b_l).
     A_1 = V_1 Lambda_0 + h a_1 Z_1, B_1 = h a_1 W_1; A_l = h a_l Z_l, B_l = h a_l W_l.
-    The Lambda_0 term uses the fixed initial spectrum (Sec. 3.6).
+    The Lambda_0 term uses the fixed initial spectrum (Sec. 3.7).
     """
     K = LowRank()
     lam0 = np.asarray(lam0, dtype=np.float64)
@@ -99,7 +99,7 @@ def partial_eig_irlm(K, r, tol=1e-13):
 
 
 def state_from_factor(A, tol=1e-14):
-    """Initial partial eigendecomposition of rho_0 = A A* / Tr(A A*) (Sec. 3.6:
+    """Initial partial eigendecomposition of rho_0 = A A* / Tr(A A*) (Sec. 3.7:
     the run starts from rho_0 = V Lambda_0 V*, r = rank rho_0), by
     Rayleigh-Ritz on the range of A: A = Q R, rho_0 = Q (R R*) Q* / Tr, so the
     eigenpairs come from the small matrix R R*.  Eigenvalues at or below

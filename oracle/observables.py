@@ -1,4 +1,4 @@
-"""Expectation values from the factor only (Sec. 3.5, eq. 3.6).
+"""Expectation values from the factor only (Sec. 3.6, eq. 3.6).
 
 <A> = Tr(A rho) = Tr(Lambda_0 (V* (A V))): apply A to the tall-skinny V, then
 a small Gram product, then the trace against Lambda_0.
@@ -29,7 +29,7 @@ def magnetization(n, V, lam0, hbar=1.0):
     return np.array(out)
 
 
-# ---- two-spin reduced density matrix and entanglement (Sec. 3.5) -----------
+# ---- two-spin reduced density matrix and entanglement (Sec. 3.6) -----------
 #
 # R_kl = Tr_rest(rho) for the spins at sites k and l, indexed by
 # q = 2 b_k + b_l (b the bit of the site in the basis index; 0 = spin up):

@@ -1,7 +1,7 @@
-"""LREI-RK (Sec. 3.6) and LREI-AB (Sec. 3.7) time steps.
+"""LREI-RK (Sec. 3.7) and LREI-AB (Sec. 3.8) time steps.
 
 The state is (V, lam0): rho = V diag(lam0) V*, lam0 fixed for all time
-(the spectrum-preserving projection of Sec. 2 / Sec. 3.6).
+(the spectrum-preserving projection of Sec. 2 / Sec. 3.7).
 
 Readings:
 * RK tableaux beyond RK2 are deferred by the paper to Butcher's book; we take
@@ -68,7 +68,7 @@ def lrei_rk_step(H, V, lam0, model, kappa, h, scheme="RK4", hbar=1.0, eig=partia
 
 def lrei_ab_run(H, V, lam0, model, kappa, h, n_steps, scheme="AB3", hbar=1.0,
                 bootstrap="RK4", eig=partial_eig, callback=None):
-    """n_steps of LREI-AB (Sec. 3.7) with an RK start-up; returns the final V."""
+    """n_steps of LREI-AB (Sec. 3.8) with an RK start-up; returns the final V."""
     bcoef = AB_COEFFS[scheme]
     m = bcoef.size
     r = V.shape[1]

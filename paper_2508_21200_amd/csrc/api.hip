@@ -55,6 +55,7 @@ struct lrei_ctx {
   std::vector<HvSweep> sweeps;
   DevBuf acc;                     // partial sums between sweeps
   DevBuf sched;                   // H.V tile-scheduling counters (16 ints, zero between launches)
+  bool hv_launch_failed = false;  // an H.V launch was refused (shape invalid for the rank)
 
   // weight p of the maximally mixed part: the state is p I / N + (1 - p) V Lambda V*
   double mix_p = 0.0;
@@ -73,6 +74,8 @@ struct lrei_ctx {
   bool fp32 = false;
   DevBuf blocks[kMaxStages + 1];
   DevBuf save;       // state at the start of a step call (rollback)
+  // LREI_MIXED: the state is the compensated pair blocks[0] + lo (both FP32)
+  DevBuf lo, save_lo;
   DevBuf partials;
   DevBuf ws_buf;
   DevBuf stats_buf;
@@ -142,10 +145,12 @@ lrei_status alloc_state(lrei_ctx *ctx, int r, bool fp32) {
   for (int i = 0; i <= kMaxStages; ++i)
     if (!ctx->blocks[i].ensure(blk)) return ctx->fail(LREI_E_NOMEM, "device allocation of Krylov blocks failed");
   if (!ctx->save.ensure(blk)) return ctx->fail(LREI_E_NOMEM, "device allocation failed");
+  if (fp32 && (!ctx->lo.ensure(blk) || !ctx->save_lo.ensure(blk)))
+    return ctx->fail(LREI_E_NOMEM, "device allocation failed");
   if (!ctx->acc.ensure(blk)) return ctx->fail(LREI_E_NOMEM, "device allocation failed");
   ctx->grid = nspace_grid(ctx->N, r);
   if (ctx->hv_grid <= 0) ctx->hv_grid = ctx->grid;
-  const size_t pcount = (size_t)kMaxHvGrid * cheb_partial_splits(r) * 3 * r * r;
+  const size_t pcount = (size_t)kMaxHvGrid * hv_partial_splits(r) * 3 * r * r;
   if (!ctx->partials.ensure(pcount * sizeof(double2) + 2 * kMaxHvGrid * sizeof(double2)))
     return ctx->fail(LREI_E_NOMEM, "device allocation failed");
   const int D = (kMaxStages + 1) * r;
@@ -155,7 +160,8 @@ lrei_status alloc_state(lrei_ctx *ctx, int r, bool fp32) {
                           + (size_t)kMaxStages * 3 * D * r     // stage
                           + (size_t)D * r                      // Cfin
                           + (size_t)D                          // flags (as complex slots)
-                          + (size_t)kMaxStages;                // warm_skip (as complex slots)
+                          + (size_t)kMaxStages                 // warm_skip (as complex slots)
+                          + (size_t)kMaxBlocks * r;            // column shifts (as complex slots)
   if (!ctx->ws_buf.ensure(ws_elems * sizeof(double2))) return ctx->fail(LREI_E_NOMEM, "device allocation failed");
   if (!ctx->stats_buf.ensure(kStatsLen * sizeof(double))) return ctx->fail(LREI_E_NOMEM, "device allocation failed");
   if (!ctx->lam_dev.ensure(kMaxR * sizeof(double))) return ctx->fail(LREI_E_NOMEM, "device allocation failed");
@@ -169,13 +175,19 @@ lrei_status alloc_state(lrei_ctx *ctx, int r, bool fp32) {
   ctx->ws.stage = w; w += (size_t)kMaxStages * 3 * D * r;
   ctx->ws.Cfin = w; w += (size_t)D * r;
   ctx->ws.flags = (double *)w; w += (size_t)D;
-  ctx->ws.warm_skip = (double *)w;
+  ctx->ws.warm_skip = (double *)w; w += (size_t)kMaxStages;
+  ctx->ws.shifts = (double *)w;
   ctx->ws.stats = (double *)ctx->stats_buf.p;
   return LREI_OK;
 }
 
+// Scale of the Krylov recurrence P_{j+1} = beta (H P_j - P_j D_j): the
+// inverse spectral width sqrt(N / Tr(H^2)), so that the blocks keep norms of
+// order one.  The space spanned does not depend on it.
+double krylov_beta(const lrei_ctx *ctx) { return ctx->terms.spread > 0 ? 1.0 / ctx->terms.spread : 1.0; }
+
 // Hamiltonian tables of an H.V pass.
-void hv_args(lrei_ctx *ctx, ChebArgs &a) {
+void hv_args(lrei_ctx *ctx, HvArgs &a) {
   a.terms64 = (const DevTerm<double> *)ctx->dt.off64.p;
   a.terms32 = (const DevTerm<float> *)ctx->dt.off32.p;
   a.diag64 = (const double *)ctx->dt.d64.p;
@@ -187,23 +199,22 @@ void hv_args(lrei_ctx *ctx, ChebArgs &a) {
   a.partial_cap = kMaxHvGrid;  // ctx->partials holds this many slots
 }
 
-// One Chebyshev pass with fused Grams, reduced into meas.  With a sweep plan
+// One Krylov pass with fused Grams, reduced into meas.  With a sweep plan
 // (sweeps = true and more than one sweep), the pass runs as one launch per
 // sweep: the first adds the diagonal, each writes its partial sum to ctx->acc,
-// the last adds its terms to that sum and forms the Chebyshev combination and
+// the last adds its terms to that sum and forms the recurrence combination and
 // the Grams.
-int hv_launches(lrei_ctx *ctx, int r, int grid, int mode, const void *prev, const void *cur, void *next,
-                double2 *partials, bool sweeps, int partial_cap = kMaxHvGrid) {
-  ChebArgs a{};
-  a.Pprev = prev;
+int hv_launches(lrei_ctx *ctx, int r, int grid, int mode, const void *cur, void *next, double2 *partials,
+                bool sweeps, int partial_cap = kMaxHvGrid, const double *colshift = nullptr) {
+  HvArgs a{};
   a.Pcur = cur;
   a.Pnext = next;
   hv_args(ctx, a);
   a.N = ctx->N;
   a.r = r;
-  const double e = ctx->terms.gershgorin > 0 ? ctx->terms.gershgorin : 1.0;
-  a.alpha = 1.0 / e;
-  a.shift = 0.0;
+  if (!hv_epl_valid(ctx->fp32, r, a.epl)) a.epl = 0;  // a shape tuned for another rank
+  a.alpha = krylov_beta(ctx);
+  a.colshift = colshift;
   a.mode = mode;
   a.partials = partials;
   a.grid = grid;
@@ -212,11 +223,11 @@ int hv_launches(lrei_ctx *ctx, int r, int grid, int mode, const void *prev, cons
   const size_t ns = ctx->sweeps.size();
   int slots = 0;
   if (!sweeps || ns <= 1) {
-    slots = launch_cheb(ctx->fp32, a, ctx->stream);
+    slots = launch_hv(ctx->fp32, a, ctx->stream);
   } else {
     for (size_t i = 0; i < ns; ++i) {
       const auto &sw = ctx->sweeps[i];
-      ChebArgs b = a;
+      HvArgs b = a;
       b.t0 = sw.t0;
       b.t1 = sw.t1;
       b.use_diag = i == 0;
@@ -227,21 +238,37 @@ int hv_launches(lrei_ctx *ctx, int r, int grid, int mode, const void *prev, cons
       b.n_fix = (int)sw.fix.size();
       for (size_t q = 0; q < sw.win.size(); ++q) b.win_pos[q] = (unsigned char)sw.win[q];
       for (size_t q = 0; q < sw.fix.size(); ++q) b.fix_pos[q] = (unsigned char)sw.fix[q];
-      slots = launch_cheb(ctx->fp32, b, ctx->stream);
+      slots = launch_hv(ctx->fp32, b, ctx->stream);
     }
   }
+  if (slots <= 0) ctx->hv_launch_failed = true;
   return slots;  // Gram partial slots written by the (last) launch
 }
 
-void cheb_pass_into(lrei_ctx *ctx, int r, int grid, int mode, const void *prev, const void *cur, void *next,
-                    double2 *partials, double2 *meas, bool sweeps = false, int partial_cap = kMaxHvGrid) {
-  const int slots = hv_launches(ctx, r, grid, mode, prev, cur, next, partials, sweeps, partial_cap);
-  if (mode != 2 && slots > 0) launch_reduce(partials, slots, (mode == 0 ? 3 : 2) * r * r, meas, ctx->stream);
+bool hv_pass_into(lrei_ctx *ctx, int r, int grid, int mode, const void *cur, void *next, double2 *partials,
+                    double2 *meas, bool sweeps = false, int partial_cap = kMaxHvGrid,
+                    const double *colshift = nullptr) {
+  const int slots = hv_launches(ctx, r, grid, mode, cur, next, partials, sweeps, partial_cap, colshift);
+  if (slots <= 0) return false;
+  if (mode != 2) launch_reduce(partials, slots, (mode == 0 ? 3 : 2) * r * r, meas, ctx->stream);
+  return true;
 }
 
-void cheb_pass(lrei_ctx *ctx, int mode, const void *prev, const void *cur, void *next, int slot) {
-  cheb_pass_into(ctx, ctx->r, ctx->hv_grid, mode, prev, cur, next, (double2 *)ctx->partials.p,
-                 ctx->ws.meas + (size_t)slot * 3 * ctx->r * ctx->r, true);
+// Forgets the tuned H.V launch shape (it was chosen for one rank and
+// precision) and the captured step graph that baked it in.
+void reset_hv_tuning(lrei_ctx *ctx) {
+  ctx->epl = 0;
+  ctx->hv_grid = 0;
+  ctx->drop_graph();
+}
+
+// Krylov pass j of a step: P_{j+1} = beta (H P_j - P_j diag(D_j)) into
+// blocks[j + 1] with its Gram products into slot j of ws.meas; D_j is the
+// context's column shift of block j (zero when `shifted` is false).
+void krylov_pass(lrei_ctx *ctx, int j, bool shifted = true) {
+  hv_pass_into(ctx, ctx->r, ctx->hv_grid, j == 0 ? 0 : 1, ctx->blocks[j].p, ctx->blocks[j + 1].p,
+                 (double2 *)ctx->partials.p, ctx->ws.meas + (size_t)j * 3 * ctx->r * ctx->r, true, kMaxHvGrid,
+                 shifted ? ctx->ws.shifts + (size_t)j * ctx->r : nullptr);
 }
 
 // Sweep plan for windows of w row bits: repeatedly choose the n - w fixed bits
@@ -370,14 +397,13 @@ SmallRkParams rk_params(lrei_ctx *ctx, int model, int scheme, double dt, double 
   p.eig_tol = ctx->opt.eig_tol;
   // the warm-started eigensolve stops well below the storage rounding of the path
   p.warm_tol = ctx->fp32 ? 1e-11 : 1e-14;
-  p.shift = 0.0;
-  p.halfwidth = ctx->terms.gershgorin > 0 ? ctx->terms.gershgorin : 1.0;
+  p.beta = krylov_beta(ctx);
   for (int i = 0; i < ctx->r; ++i) p.lam[i] = ctx->lam[i];
   p.lds_elems = small_lds_elems(p.nblocks * ctx->r, ctx->r);
   return p;
 }
 
-// Enqueues one LREI-RK step: the Chebyshev Krylov passes on the context
+// Enqueues one LREI-RK step: the Krylov passes on the context
 // stream; as soon as pass j is reduced (stage j needs the Grams of
 // P_0 .. P_{j+1} only) the basis extension of stage j on the basis stream,
 // then stage j itself on the side stream, so that the extension of stage
@@ -409,10 +435,7 @@ void enqueue_stages(lrei_ctx *ctx, const SmallRkParams &p) {
   (void)hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0);
   (void)hipStreamWaitEvent(ctx->basis, ctx->ev_fork, 0);
   for (int j = 0; j < s; ++j) {
-    if (j == 0)
-      cheb_pass(ctx, 0, nullptr, ctx->blocks[0].p, ctx->blocks[1].p, 0);
-    else
-      cheb_pass(ctx, 1, ctx->blocks[j - 1].p, ctx->blocks[j].p, ctx->blocks[j + 1].p, j);
+    krylov_pass(ctx, j);
     (void)hipEventRecord(ctx->ev_pass[j], ctx->stream);
     (void)hipStreamWaitEvent(ctx->basis, ctx->ev_pass[j], 0);
     launch_small_rk_basis(p, ctx->ws, j, ctx->basis);
@@ -427,7 +450,8 @@ void enqueue_stages(lrei_ctx *ctx, const SmallRkParams &p) {
   const void *bl[kMaxBlocks];
   for (int i = 0; i < p.nblocks; ++i) bl[i] = ctx->blocks[i].p;
   launch_combine(ctx->fp32, bl, p.nblocks, ctx->ws.Cfin, ctx->blocks[0].p, ctx->N, ctx->r, ctx->grid, ctx->stream,
-                 p.ctl ? p.ctl + kCtlSkip : nullptr);
+                 p.ctl ? p.ctl + kCtlSkip : nullptr, ctx->fp32 ? ctx->lo.p : nullptr,
+                 ctx->fp32 ? ctx->lo.p : nullptr);
 }
 
 // Steps between two checks of the mixed-precision conditioning floor.
@@ -464,20 +488,28 @@ lrei_status run_rk_steps(lrei_ctx *ctx, int model, int scheme, double dt, double
 
 void ab_reset(lrei_ctx *ctx);
 
-// Moves a LREI_MIXED context to FP64 storage: the state is widened exactly,
+// Moves a LREI_MIXED context to FP64 storage: the state and the rollback
+// copy of the current call (its start-of-call state) are widened exactly,
 // the N-space buffers are reallocated for FP64, the captured graphs, the
-// tuned H.V shape and the AB history are dropped.  The rollback copy of the
-// current call becomes the state at this point.
+// tuned H.V shape and the AB history are dropped.
 lrei_status promote_fp64(lrei_ctx *ctx) {
   const size_t n = (size_t)ctx->N * ctx->r;
-  void *wide = nullptr;
+  void *wide = nullptr, *wide_save = nullptr;
   HIPCHK(hipStreamSynchronize(ctx->stream));
   if (hipMalloc(&wide, n * sizeof(double2)) != hipSuccess)
     return ctx->fail(LREI_E_NOMEM, "device allocation for the FP64 promotion failed");
-  launch_convert(false, ctx->blocks[0].p, wide, (long long)n, ctx->stream);
+  if (hipMalloc(&wide_save, n * sizeof(double2)) != hipSuccess) {
+    (void)hipFree(wide);
+    return ctx->fail(LREI_E_NOMEM, "device allocation for the FP64 promotion failed");
+  }
+  launch_merge((const float2 *)ctx->blocks[0].p, (const float2 *)ctx->lo.p, (double2 *)wide, (long long)n,
+               ctx->stream);
+  launch_merge((const float2 *)ctx->save.p, (const float2 *)ctx->save_lo.p, (double2 *)wide_save, (long long)n,
+               ctx->stream);  // the start-of-call state
   hipError_t e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) {
     (void)hipFree(wide);
+    (void)hipFree(wide_save);
     return check_hip(ctx, e, "FP64 promotion");
   }
   ctx->drop_graph();
@@ -489,11 +521,12 @@ lrei_status promote_fp64(lrei_ctx *ctx) {
   if (st == LREI_OK) {
     e = hipMemcpyAsync(ctx->blocks[0].p, wide, n * sizeof(double2), hipMemcpyDeviceToDevice, ctx->stream);
     if (e == hipSuccess)
-      e = hipMemcpyAsync(ctx->save.p, wide, n * sizeof(double2), hipMemcpyDeviceToDevice, ctx->stream);
+      e = hipMemcpyAsync(ctx->save.p, wide_save, n * sizeof(double2), hipMemcpyDeviceToDevice, ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) st = check_hip(ctx, e, "FP64 promotion");
   }
   (void)hipFree(wide);
+  (void)hipFree(wide_save);
   if (st == LREI_OK) ctx->stats.precision_promoted = 1;
   return st;
 }
@@ -656,7 +689,7 @@ SmallAbParams ab_params(lrei_ctx *ctx, int mode) {
 // fewer than m - 1 steps are done, else the AB step.
 void enqueue_ab_step(lrei_ctx *ctx) {
   auto &ab = ctx->ab;
-  const double e = ctx->terms.gershgorin > 0 ? ctx->terms.gershgorin : 1.0;
+  const double e = 1.0 / krylov_beta(ctx);
   if (ab.count < ab.m - 1) {
     const int j = ab.count;
     int bs = ctx->opt.ab_bootstrap;
@@ -665,6 +698,9 @@ void enqueue_ab_step(lrei_ctx *ctx) {
     if (j == 0)
       (void)hipMemcpyAsync(ctx->ab_U[1 - ab.cur][0].p, ctx->blocks[0].p, (size_t)ctx->N * ctx->r * ctx->elem(),
                            hipMemcpyDeviceToDevice, ctx->stream);
+    // the history takes blocks[1] as a multiple of H V_j: no column shift on
+    // the first Krylov block of a start-up step (AB steps are never captured)
+    (void)hipMemsetAsync(ctx->ws.shifts, 0, ctx->r * sizeof(double), ctx->stream);
     enqueue_rk_step(ctx, ab.model, bs, ab.dt, ab.kappa);
     SmallAbParams p = ab_params(ctx, 0);
     std::vector<const void *> X;
@@ -683,25 +719,29 @@ void enqueue_ab_step(lrei_ctx *ctx) {
       p.x_hv = 0;
       p.x_vnew = 1;
     }
-    p.hv_scale = e;  // blocks[1] = (1/e) H V_j
+    p.hv_scale = e;  // blocks[1] = beta H V_j, e = 1 / beta
     ab_update(ctx, X, p);
   } else {
-    ChebArgs a{};
+    HvArgs a{};
     a.Pcur = ctx->blocks[0].p;
     a.Pnext = ctx->blocks[1].p;
     hv_args(ctx, a);
     a.N = ctx->N;
     a.r = ctx->r;
+    if (!hv_epl_valid(ctx->fp32, a.r, a.epl)) a.epl = 0;
     a.alpha = 1.0;
     a.mode = 2;
     a.grid = ctx->grid;
-    launch_cheb(ctx->fp32, a, ctx->stream);
+    if (launch_hv(ctx->fp32, a, ctx->stream) <= 0) ctx->hv_launch_failed = true;
     SmallAbParams p = ab_params(ctx, 1);
     p.x_v0 = -1;
     p.x_hv = 0;
     p.x_vnew = -1;
     p.hv_scale = 1.0;
     ab_update(ctx, {ctx->blocks[1].p}, p);
+    // the AB step writes the new state in the storage precision only: the
+    // compensation of a mixed state restarts at zero (AB steps are never captured)
+    if (ctx->fp32) (void)hipMemsetAsync(ctx->lo.p, 0, (size_t)ctx->N * ctx->r * sizeof(float2), ctx->stream);
   }
   ab.count += 1;
 }
@@ -729,6 +769,7 @@ void lrei_default_options(lrei_options *o) {
   o->deterministic = 1;
   o->autotune_cache = nullptr;
   o->mixed_pivot_floor = 2e-6;
+  o->fail_after_steps = 0;
 }
 
 lrei_status lrei_create(lrei_ctx **out, int hip_device, void *hip_stream, const lrei_options *opt) {
@@ -938,14 +979,19 @@ lrei_status lrei_set_rho(lrei_ctx *ctx, int r, const double *lambda, const void 
   const size_t el = ctx->elem();
   const size_t vbytes = (size_t)ctx->N * r * el;
   const int grid = nspace_grid(ctx->N, r);
-  DevBuf tv, tp, tpart, tmeas, tstage;
+  // FP64: V -> tv, natural -> internal site order into tp.  Mixed: V (FP64)
+  // -> internal order in tw, split into the compensated FP32 pair tp (hi) +
+  // tlo (lo).  The validation pass below measures V* V and V* (beta H V) on
+  // tp with the context's term tables (tv: its scratch output).
+  const size_t n64 = (size_t)ctx->N * r * sizeof(double2);
+  DevBuf tv, tp, tpart, tmeas, tstage, tw, tlo;
   auto release_tmp = [&]() {
-    tv.release(); tp.release(); tpart.release(); tmeas.release(); tstage.release();
+    tv.release(); tp.release(); tpart.release(); tmeas.release(); tstage.release(); tw.release(); tlo.release();
   };
   if (!tv.ensure(vbytes) || !tp.ensure(vbytes) ||
-      !tpart.ensure((size_t)grid * cheb_partial_splits(r) * 3 * r * r * sizeof(double2)) ||
+      !tpart.ensure((size_t)grid * hv_partial_splits(r) * 3 * r * r * sizeof(double2)) ||
       !tmeas.ensure(3 * (size_t)r * r * sizeof(double2)) ||
-      (ctx->fp32 && !v_is_device && !tstage.ensure((size_t)ctx->N * r * sizeof(double2)))) {
+      (ctx->fp32 && (!tw.ensure(n64) || !tlo.ensure(vbytes) || (!v_is_device && !tstage.ensure(n64))))) {
     release_tmp();
     return ctx->fail(LREI_E_NOMEM, "device allocation failed");
   }
@@ -955,20 +1001,28 @@ lrei_status lrei_set_rho(lrei_ctx *ctx, int r, const double *lambda, const void 
     if (!ctx->fp32) {
       e1 = hipMemcpyAsync(tv.p, V, n * sizeof(double2), v_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                           ctx->stream);
+      if (e1 == hipSuccess)
+        launch_permute(false, tv.p, tp.p, ctx->N, r, ctx->site_pos.data(), ctx->n, false, ctx->stream);
     } else {
       const void *src = V;
       if (!v_is_device) {
         e1 = hipMemcpyAsync(tstage.p, V, n * sizeof(double2), hipMemcpyHostToDevice, ctx->stream);
         src = tstage.p;
       }
-      if (e1 == hipSuccess) launch_convert(true, src, tv.p, (long long)n, ctx->stream);
+      if (e1 == hipSuccess) {
+        launch_permute(false, src, tw.p, ctx->N, r, ctx->site_pos.data(), ctx->n, false, ctx->stream);
+        launch_split((const double2 *)tw.p, (float2 *)tp.p, (float2 *)tlo.p, (long long)n, ctx->stream);
+      }
     }
     if (e1 != hipSuccess) {
       release_tmp();
       return check_hip(ctx, e1, "upload V");
     }
   }
-  cheb_pass_into(ctx, r, grid, 0, nullptr, tv.p, tp.p, (double2 *)tpart.p, (double2 *)tmeas.p, false, grid);
+  if (!hv_pass_into(ctx, r, grid, 0, tp.p, tv.p, (double2 *)tpart.p, (double2 *)tmeas.p, false, grid)) {
+    release_tmp();
+    return ctx->fail(LREI_E_INVALID, "no H.V launch shape for rank " + std::to_string(r));
+  }
   std::vector<double2> g(3 * r * r);
   hipError_t e2 = hipGetLastError();
   if (e2 == hipSuccess)
@@ -993,6 +1047,7 @@ lrei_status lrei_set_rho(lrei_ctx *ctx, int r, const double *lambda, const void 
     return ctx->fail(LREI_E_INVALID, "V must have finite orthonormal columns (max |V*V - I| = " +
                                          std::to_string(dev) + ")");
   }
+  if (!ctx->have_rho || ctx->r != r) reset_hv_tuning(ctx);  // the tuned shape belongs to the old rank
   lrei_status st = alloc_state(ctx, r, ctx->fp32);
   if (st != LREI_OK) {
     release_tmp();
@@ -1002,11 +1057,22 @@ lrei_status lrei_set_rho(lrei_ctx *ctx, int r, const double *lambda, const void 
   ctx->r = r;
   // a new state: every stage tries the warm-started eigensolve again
   e2 = hipMemsetAsync(ctx->ws.warm_skip, 0, kMaxStages * sizeof(double), ctx->stream);
+  // a new state: the first Krylov block's column shifts are the Rayleigh
+  // quotients of V's columns (the validation pass measured P0* P1 with
+  // P1 = beta H V), the later blocks' start at zero; every step refreshes them
+  std::vector<double> sh0((size_t)kMaxBlocks * r, 0.0);
+  for (int a = 0; a < r; ++a) {
+    const double gaa = g[a * r + a].x, haa = g[r * r + a * r + a].x / krylov_beta(ctx);
+    if (gaa > 0 && std::isfinite(haa / gaa)) sh0[a] = haa / gaa;
+  }
   if (e2 == hipSuccess)
-    launch_permute(ctx->fp32, tv.p, ctx->blocks[0].p, ctx->N, r, ctx->site_pos.data(), ctx->n, false, ctx->stream);
+    e2 = hipMemcpyAsync(ctx->ws.shifts, sh0.data(), sh0.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream);
+  if (e2 == hipSuccess) e2 = hipStreamSynchronize(ctx->stream);  // sh0 is host stack memory
+  if (e2 == hipSuccess) e2 = hipMemcpyAsync(ctx->blocks[0].p, tp.p, vbytes, hipMemcpyDeviceToDevice, ctx->stream);
+  if (e2 == hipSuccess && ctx->fp32)
+    e2 = hipMemcpyAsync(ctx->lo.p, tlo.p, vbytes, hipMemcpyDeviceToDevice, ctx->stream);
   if (e2 == hipSuccess) e2 = hipGetLastError();
   if (e2 == hipSuccess) e2 = hipStreamSynchronize(ctx->stream);
-  (void)vbytes;
   release_tmp();
   HIPCHK(e2);
   ctx->lam.assign(lambda, lambda + r);
@@ -1060,9 +1126,11 @@ lrei_status lrei_step(lrei_ctx *ctx, int model, int scheme, double dt, double ka
   const auto t0 = std::chrono::steady_clock::now();
   const size_t vbytes = (size_t)ctx->N * ctx->r * ctx->elem();
   HIPCHK(hipMemcpyAsync(ctx->save.p, ctx->blocks[0].p, vbytes, hipMemcpyDeviceToDevice, ctx->stream));
+  if (ctx->fp32) HIPCHK(hipMemcpyAsync(ctx->save_lo.p, ctx->lo.p, vbytes, hipMemcpyDeviceToDevice, ctx->stream));
   double zeros[kStatsLen] = {0};
   HIPCHK(hipMemcpyAsync(ctx->stats_buf.p, zeros, sizeof(zeros), hipMemcpyHostToDevice, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
+  ctx->hv_launch_failed = false;
   if (is_ab) {
     for (int k = 0; k < n_steps; ++k) enqueue_ab_step(ctx);
   } else {
@@ -1093,20 +1161,26 @@ lrei_status lrei_step(lrei_ctx *ctx, int model, int scheme, double dt, double ka
   if (st != LREI_OK) return st;
   const auto t1 = std::chrono::steady_clock::now();
   // stats[0..8] describe the last step, stats[10..15] the whole call
-  const bool failed = h[13] != 0, bad = h[14] != 0;
-  if (failed || bad) {
+  const bool bad = h[14] != 0 || (ctx->opt.fail_after_steps > 0 && n_steps >= ctx->opt.fail_after_steps);
+  if (bad || ctx->hv_launch_failed) {
     ab_reset(ctx);  // the history no longer matches the restored state
     HIPCHK(hipMemcpyAsync(ctx->blocks[0].p, ctx->save.p, (size_t)ctx->N * ctx->r * ctx->elem(),
                           hipMemcpyDeviceToDevice, ctx->stream));
+    if (ctx->fp32)
+      HIPCHK(hipMemcpyAsync(ctx->lo.p, ctx->save_lo.p, (size_t)ctx->N * ctx->r * ctx->elem(),
+                            hipMemcpyDeviceToDevice, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (ctx->hv_launch_failed) {
+      ctx->hv_launch_failed = false;
+      return ctx->fail(LREI_E_INVALID, "an H.V pass could not be launched for this rank; state restored to the "
+                                       "start of the call");
+    }
     char where[96] = "";
     if (h[28] >= 0)
       std::snprintf(where, sizeof(where), " (first at stage %d, %s)", (int)h[28] / 10,
                     (const char *[]){"", "u", "H u", "z/w", "stage matrix", "eigenvectors"}[(int)h[28] % 10]);
-    return ctx->fail(bad ? LREI_E_NUMERIC : LREI_E_NOTCONVERGED,
-                     bad ? std::string("non-finite values in the step") + where +
-                               "; state restored to the start of the call"
-                         : "Jacobi eigensolve hit the sweep limit; state restored to the start of the call");
+    return ctx->fail(LREI_E_NUMERIC,
+                     std::string("non-finite values in the step") + where + "; state restored to the start of the call");
   }
   ctx->steps_done += n_steps;
   ctx->stats.steps_done = ctx->steps_done;
@@ -1153,6 +1227,7 @@ lrei_status lrei_evolve_adaptive(lrei_ctx *ctx, int model, int pair, double kapp
   const auto t0 = std::chrono::steady_clock::now();
   const size_t vbytes = (size_t)ctx->N * ctx->r * ctx->elem();
   HIPCHK(hipMemcpyAsync(ctx->save.p, ctx->blocks[0].p, vbytes, hipMemcpyDeviceToDevice, ctx->stream));
+  if (ctx->fp32) HIPCHK(hipMemcpyAsync(ctx->save_lo.p, ctx->lo.p, vbytes, hipMemcpyDeviceToDevice, ctx->stream));
   double zeros[kStatsLen] = {0};
   HIPCHK(hipMemcpyAsync(ctx->stats_buf.p, zeros, sizeof(zeros), hipMemcpyHostToDevice, ctx->stream));
   double c[kCtlLen] = {0};
@@ -1163,6 +1238,7 @@ lrei_status lrei_evolve_adaptive(lrei_ctx *ctx, int model, int pair, double kapp
   c[kCtlHMax] = h_max;
   HIPCHK(hipMemcpyAsync(ctx->ctl.p, c, sizeof(c), hipMemcpyHostToDevice, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
+  ctx->hv_launch_failed = false;
   SmallRkParams p = adapt_params(ctx, model, pair, kappa);
   const bool use_graph = ctx->opt.use_graph != 0;
   const bool guard = ctx->fp32 && ctx->opt.mixed_pivot_floor > 0;
@@ -1229,12 +1305,16 @@ lrei_status lrei_evolve_adaptive(lrei_ctx *ctx, int model, int pair, double kapp
   lrei_status st = read_stats(ctx, h);
   if (st != LREI_OK) return st;
   const auto t1 = std::chrono::steady_clock::now();
-  if (h[13] != 0) {
+  if (ctx->hv_launch_failed) {
+    ctx->hv_launch_failed = false;
     HIPCHK(hipMemcpyAsync(ctx->blocks[0].p, ctx->save.p, (size_t)ctx->N * ctx->r * ctx->elem(),
                           hipMemcpyDeviceToDevice, ctx->stream));
+    if (ctx->fp32)
+      HIPCHK(hipMemcpyAsync(ctx->lo.p, ctx->save_lo.p, (size_t)ctx->N * ctx->r * ctx->elem(),
+                            hipMemcpyDeviceToDevice, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
-    return ctx->fail(LREI_E_NOTCONVERGED,
-                     "Jacobi eigensolve hit the sweep limit; state restored to the start of the call");
+    return ctx->fail(LREI_E_INVALID,
+                     "an H.V pass could not be launched for this rank; state restored to the start of the call");
   }
   const bool reached = c[kCtlDone] != 0.0;
   if (out) {
@@ -1279,19 +1359,25 @@ lrei_status lrei_get_rho(lrei_ctx *ctx, double *lambda, void *V, int v_is_device
   if (!V) return LREI_OK;
   HIPCHK(hipSetDevice(ctx->device));
   const size_t n = (size_t)ctx->N * ctx->r;
-  // back to the physical site order, then to complex128
-  launch_permute(ctx->fp32, ctx->blocks[0].p, ctx->acc.p, ctx->N, ctx->r, ctx->site_pos.data(), ctx->n, true,
-                 ctx->stream);
-  HIPCHK(hipGetLastError());
-  const void *src = ctx->acc.p;
-  if (ctx->fp32) {
-    if (!ctx->save.ensure(n * sizeof(double2))) return ctx->fail(LREI_E_NOMEM, "allocation failed");
-    launch_convert(false, ctx->acc.p, ctx->save.p, (long long)n, ctx->stream);
+  if (!ctx->fp32) {  // back to the physical site order
+    launch_permute(false, ctx->blocks[0].p, ctx->acc.p, ctx->N, ctx->r, ctx->site_pos.data(), ctx->n, true,
+                   ctx->stream);
     HIPCHK(hipGetLastError());
-    src = ctx->save.p;
+    HIPCHK(hipMemcpyAsync(V, ctx->acc.p, n * sizeof(double2),
+                          v_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return LREI_OK;
   }
-  HIPCHK(hipMemcpyAsync(V, src, n * sizeof(double2), v_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
-                        ctx->stream));
+  // the compensated pair hi + lo in FP64, then the physical site order
+  DevBuf w64, p64;
+  if (!w64.ensure(n * sizeof(double2)) || (!v_is_device && !p64.ensure(n * sizeof(double2))))
+    return ctx->fail(LREI_E_NOMEM, "allocation failed");
+  launch_merge((const float2 *)ctx->blocks[0].p, (const float2 *)ctx->lo.p, (double2 *)w64.p, (long long)n,
+               ctx->stream);
+  void *dst = v_is_device ? V : p64.p;
+  launch_permute(false, w64.p, dst, ctx->N, ctx->r, ctx->site_pos.data(), ctx->n, true, ctx->stream);
+  HIPCHK(hipGetLastError());
+  if (!v_is_device) HIPCHK(hipMemcpyAsync(V, p64.p, n * sizeof(double2), hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   return LREI_OK;
 }
@@ -1398,14 +1484,14 @@ lrei_status lrei_observables(lrei_ctx *ctx, double *energy, double magnetization
   HIPCHK(hipSetDevice(ctx->device));
   const int r = ctx->r;
   if (energy) {
-    // Gram pass with alpha = 1, shift = 0 would need a separate scaling; use the
-    // step's pass (alpha = 1/e) and undo the scale: P1 = H P0 / e.
-    cheb_pass(ctx, 0, nullptr, ctx->blocks[0].p, ctx->blocks[1].p, 0);
+    // the step's first pass without column shifts, P1 = beta H P0, and its
+    // Gram P0* P1 = beta V* H V
+    krylov_pass(ctx, 0, false);
     HIPCHK(hipGetLastError());
     std::vector<double2> g(3 * r * r);
     HIPCHK(hipMemcpyAsync(g.data(), ctx->ws.meas, g.size() * sizeof(double2), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
-    const double e = ctx->terms.gershgorin > 0 ? ctx->terms.gershgorin : 1.0;
+    const double e = 1.0 / krylov_beta(ctx);
     double en = 0;
     for (int a = 0; a < r; ++a) en += ctx->lam[a] * g[r * r + a * r + a].x * e;
     // Tr(H) = 0 (every Pauli-string term is traceless): the maximally mixed
@@ -1469,16 +1555,20 @@ lrei_status lrei_apply_hamiltonian(lrei_ctx *ctx, int r, const void *X, void *Y,
   }
   // physical -> internal site order, H X, internal -> physical
   launch_permute(false, px, dp.p, ctx->N, r, ctx->site_pos.data(), ctx->n, false, ctx->stream);
-  ChebArgs a{};
+  HvArgs a{};
   a.Pcur = dp.p;
   a.Pnext = dy.p;
   hv_args(ctx, a);
   a.N = ctx->N;
   a.r = r;
+  if (!hv_epl_valid(false, r, a.epl)) a.epl = 0;  // FP64 launch; the tuned shape may be FP32's
   a.alpha = 1.0;
   a.mode = 2;
   a.grid = nspace_grid(ctx->N, r);
-  launch_cheb(false, a, ctx->stream);
+  if (launch_hv(false, a, ctx->stream) <= 0) {
+    release_all();
+    return ctx->fail(LREI_E_INVALID, "no H.V launch shape for this rank");
+  }
   void *py = is_device ? Y : dp.p;
   launch_permute(false, dy.p, py, ctx->N, r, ctx->site_pos.data(), ctx->n, true, ctx->stream);
   lrei_status st = check_hip(ctx, hipGetLastError(), "apply_hamiltonian launch");
@@ -1491,9 +1581,11 @@ lrei_status lrei_apply_hamiltonian(lrei_ctx *ctx, int r, const void *X, void *Y,
 
 // Checkpoint layout (little-endian): 16 x uint64 header {magic, n, r, steps_done,
 // fp32, ab_valid, ab_scheme, ab_model, ab_count, ab_nU, ab_npairs, dt bits,
-// kappa bits, 0, 0, 0}; lambda (r doubles); V (N x r complex128); with a valid
-// AB history also the U Gram products, the U-coordinates of the history and the
-// U blocks in the context's storage precision.
+// kappa bits, shifts flag, 0, 0}; lambda (r doubles); V (N x r complex128); with
+// a valid AB history also the U Gram products, the U-coordinates of the history
+// and the U blocks in the context's storage precision; then (shifts flag 1) the
+// Krylov column shifts, kMaxBlocks x r doubles.  Buffers without the shifts
+// (flag 0) are read too; their shifts start as set_rho's.
 namespace {
 constexpr uint64_t kStateMagic2 = 0x4c52454953543032ull;  // "LREIST02"
 size_t ab_blob_bytes(const lrei_ctx::AbState &ab, size_t r, long long N, size_t elem) {
@@ -1509,7 +1601,9 @@ lrei_status lrei_get_state(lrei_ctx *ctx, void *buf, size_t *len) {
   if (!ctx->have_rho) return ctx->fail(LREI_E_STATE, "no state");
   const size_t vbytes = (size_t)ctx->N * ctx->r * sizeof(double2);
   const size_t head = 16 * 8 + ctx->r * sizeof(double);
-  const size_t need = head + vbytes + ab_blob_bytes(ctx->ab, ctx->r, ctx->N, ctx->elem());
+  const size_t abb = ab_blob_bytes(ctx->ab, ctx->r, ctx->N, ctx->elem());
+  const size_t shb = (size_t)kMaxBlocks * ctx->r * sizeof(double);  // Krylov column shifts
+  const size_t need = head + vbytes + abb + shb;
   if (!buf) {
     *len = need;
     return LREI_OK;
@@ -1518,14 +1612,19 @@ lrei_status lrei_get_state(lrei_ctx *ctx, void *buf, size_t *len) {
   const auto &ab = ctx->ab;
   uint64_t hdr[16] = {kStateMagic2, (uint64_t)ctx->n, (uint64_t)ctx->r, (uint64_t)ctx->steps_done,
                       (uint64_t)ctx->fp32, (uint64_t)ab.valid, (uint64_t)ab.scheme, (uint64_t)ab.model,
-                      (uint64_t)ab.count, (uint64_t)ab.nU, (uint64_t)ab.npairs, 0, 0, 0, 0, 0};
+                      (uint64_t)ab.count, (uint64_t)ab.nU, (uint64_t)ab.npairs, 0, 0, 1, 0, 0};
   std::memcpy(&hdr[11], &ab.dt, 8);
   std::memcpy(&hdr[12], &ab.kappa, 8);
   std::memcpy(buf, hdr, sizeof(hdr));
   std::memcpy((char *)buf + 128, ctx->lam.data(), ctx->r * sizeof(double));
   *len = need;
   lrei_status st = lrei_get_rho(ctx, nullptr, (char *)buf + head, 0);
-  if (st != LREI_OK || !ab.valid) return st;
+  if (st != LREI_OK) return st;
+  // the column shifts of the Krylov recurrence (hdr[13] = 1), after the AB
+  // blob: a resumed run then rounds exactly as the uninterrupted one
+  HIPCHK(hipMemcpyAsync((char *)buf + head + vbytes + abb, ctx->ws.shifts, shb, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (!ab.valid) return LREI_OK;
   char *q = (char *)buf + head + vbytes;
   const size_t r = ctx->r, DU = (size_t)ab.nU * r;
   const size_t ub = (size_t)ab.nU * (ab.nU + 1) / 2 * r * r * sizeof(double2);
@@ -1588,9 +1687,17 @@ lrei_status lrei_set_state(lrei_ctx *ctx, const void *buf, size_t len) {
   if (len < head + vbytes + ab_blob_bytes(ab, r, ctx->N, ctx->elem()))
     return ctx->fail(LREI_E_INVALID, "state buffer truncated");
   const double *lam = (const double *)((const char *)buf + 128);
+  const size_t abb = ab_blob_bytes(ab, r, ctx->N, ctx->elem()), shb = (size_t)kMaxBlocks * r * sizeof(double);
+  const bool with_shifts = hdr[13] == 1;
+  if (with_shifts && len < head + vbytes + abb + shb) return ctx->fail(LREI_E_INVALID, "state buffer truncated");
   lrei_status st = lrei_set_rho(ctx, r, lam, (const char *)buf + head, 0);
   if (st != LREI_OK) return st;
   ctx->steps_done = (int64_t)hdr[3];
+  if (with_shifts) {
+    HIPCHK(hipMemcpyAsync(ctx->ws.shifts, (const char *)buf + head + vbytes + abb, shb, hipMemcpyHostToDevice,
+                          ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+  }
   if (!saved.valid) return LREI_OK;
   ctx->ab = saved;
   st = ab_alloc(ctx, saved.m);
@@ -1632,8 +1739,8 @@ lrei_status lrei_profile_kernels(lrei_ctx *ctx, int model, int scheme, double dt
       if (k == 1) (void)hipEventRecord(e0, ctx->stream);
       switch (which) {
         case 0:
-          slots = hv_launches(ctx, r, ctx->hv_grid, 1, ctx->blocks[0].p, ctx->blocks[1].p, ctx->blocks[4].p,
-                              (double2 *)ctx->partials.p, true);
+          slots = hv_launches(ctx, r, ctx->hv_grid, 1, ctx->blocks[1].p, ctx->blocks[4].p,
+                              (double2 *)ctx->partials.p, true, kMaxHvGrid, ctx->ws.shifts + r);
           break;
         case 1:
           launch_reduce((const double2 *)ctx->partials.p, slots, 2 * r * r,
@@ -1645,7 +1752,8 @@ lrei_status lrei_profile_kernels(lrei_ctx *ctx, int model, int scheme, double dt
         default: {
           const void *bl[kMaxBlocks];
           for (int i = 0; i <= p.s; ++i) bl[i] = ctx->blocks[i].p;
-          launch_combine(ctx->fp32, bl, p.s + 1, ctx->ws.Cfin, ctx->save.p, ctx->N, r, ctx->grid, ctx->stream);
+          launch_combine(ctx->fp32, bl, p.s + 1, ctx->ws.Cfin, ctx->save.p, ctx->N, r, ctx->grid, ctx->stream,
+                         nullptr, ctx->fp32 ? ctx->lo.p : nullptr, ctx->fp32 ? ctx->acc.p : nullptr);
         }
       }
     }
@@ -1690,8 +1798,8 @@ lrei_status lrei_autotune(lrei_ctx *ctx, lrei_tune_result *out) {
         if (l.compare(0, key.size(), key) != 0 || l.size() <= key.size() || l[key.size()] != ' ') continue;
         int e = 0, g = 0, w = 0;
         double ms = 0;
-        if (std::sscanf(l.c_str() + key.size(), " %d %d %d %lf", &e, &g, &w, &ms) == 4 && e > 0 && g > 0 &&
-            g <= kMaxHvGrid && w >= 0 && w < ctx->n) {
+        if (std::sscanf(l.c_str() + key.size(), " %d %d %d %lf", &e, &g, &w, &ms) == 4 && e > 0 &&
+            hv_epl_valid(ctx->fp32, ctx->r, e) && g > 0 && g <= kMaxHvGrid && w >= 0 && w < ctx->n) {
           res.epl = e;
           res.grid = g;
           res.win_bits = w;
@@ -1706,9 +1814,8 @@ lrei_status lrei_autotune(lrei_ctx *ctx, lrei_tune_result *out) {
     const int r = ctx->r;
     std::vector<int> epls;
     for (int e : {1, 2, 4, 8}) {
-      if (r % e != 0) continue;
-      if (!ctx->fp32 && e > 4) continue;
-      if (r > 16 && e != cheb_elems_per_lane(ctx->fp32, r)) continue;
+      if (!hv_epl_valid(ctx->fp32, r, e)) continue;
+      if (r > 16 && e != hv_elems_per_lane(ctx->fp32, r)) continue;
       epls.push_back(e);
     }
     const long long tiles = (ctx->N + 63) / 64;
@@ -1736,11 +1843,17 @@ lrei_status lrei_autotune(lrei_ctx *ctx, lrei_tune_result *out) {
           if (ns > 1 && g != 768 && g != 1536) continue;
           ctx->epl = e;
           const int iters = 5;
+          bool launched = true;
           auto pass = [&]() {
-            cheb_pass_into(ctx, r, g, 1, ctx->blocks[0].p, ctx->blocks[1].p, ctx->blocks[4].p,
-                           (double2 *)ctx->partials.p, ctx->ws.work, true);
+            launched = hv_pass_into(ctx, r, g, 1, ctx->blocks[1].p, ctx->blocks[4].p,
+                                      (double2 *)ctx->partials.p, ctx->ws.work, true, kMaxHvGrid,
+                                      ctx->ws.shifts + r) && launched;
           };
           pass();
+          if (!launched) {
+            ctx->hv_launch_failed = false;
+            continue;
+          }
           (void)hipEventRecord(e0, ctx->stream);
           for (int k = 0; k < iters; ++k) pass();
           (void)hipEventRecord(e1, ctx->stream);

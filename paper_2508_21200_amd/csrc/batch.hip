@@ -2,9 +2,9 @@
 // Hamiltonian, rank, model and damping) advanced with one launch per kernel
 // and launch shape for the whole batch.
 //
-// A step is the single-trajectory step (Sec. 3.6 in the block Krylov space of
+// A step is the single-trajectory step (Sec. 3.7 in the block Krylov space of
 // the trajectory's own H and V) run for every trajectory at once:
-//   for each pass j: batched Chebyshev H.V passes with fused Grams (one launch
+//   for each pass j: batched Krylov H.V passes with fused Grams (one launch
 //   per columns-per-lane class), one batched reduction, then on the second
 //   stream the batched projected-step stage j (one workgroup per trajectory);
 //   after the last stage, batched basis combinations.
@@ -113,15 +113,15 @@ struct lrei_batch {
   DevBuf stats;    // [n_traj][kStatsLen]
   DevBuf scratch;  // complex128 staging, max N r
 
-  // launch tables: Chebyshev pass j by (columns per lane, r > 16) class,
+  // launch tables: Krylov pass j by (columns per lane, r > 16) class,
   // reduction of pass j, projected step, combination by padded width
-  struct ChebGroup {
+  struct HvGroup {
     int epl = 1;
     bool cplx = false, big = false, dyn = false;
     size_t lds = 0;
     LaunchTables t;
   };
-  std::vector<ChebGroup> cheb[kMaxStages];
+  std::vector<HvGroup> hv[kMaxStages];
   LaunchTables reduce[kMaxStages];
   DevBuf small_p, small_ws;
   int small_lds = 0;
@@ -176,7 +176,8 @@ lrei_status alloc_traj(lrei_batch *b, lrei_batch::Traj &t, int idx) {
     return b->fail(LREI_E_NOMEM, "device allocation failed");
   const size_t ws_elems = (size_t)kMaxStages * 3 * r * r + 4 * (size_t)D * D +
                           (4 * (size_t)D * r + 2 * (size_t)D * D + 4 * (size_t)r * r) +
-                          (size_t)kMaxStages * 3 * D * r + (size_t)D * r + (size_t)D + (size_t)kMaxStages;
+                          (size_t)kMaxStages * 3 * D * r + (size_t)D * r + (size_t)D + (size_t)kMaxStages +
+                          (size_t)kMaxBlocks * r;
   if (!t.ws_buf.ensure(ws_elems * sizeof(double2))) return b->fail(LREI_E_NOMEM, "device allocation failed");
   double2 *w = (double2 *)t.ws_buf.p;
   t.ws.meas = w; w += (size_t)kMaxStages * 3 * r * r;
@@ -188,22 +189,23 @@ lrei_status alloc_traj(lrei_batch *b, lrei_batch::Traj &t, int idx) {
   t.ws.stage = w; w += (size_t)kMaxStages * 3 * D * r;
   t.ws.Cfin = w; w += (size_t)D * r;
   t.ws.flags = (double *)w; w += (size_t)D;
-  t.ws.warm_skip = (double *)w;
-  if (hipMemset(t.ws.warm_skip, 0, kMaxStages * sizeof(double)) != hipSuccess)
+  t.ws.warm_skip = (double *)w; w += (size_t)kMaxStages;
+  t.ws.shifts = (double *)w;
+  if (hipMemset(t.ws.warm_skip, 0, kMaxStages * sizeof(double)) != hipSuccess ||
+      hipMemset(t.ws.shifts, 0, (size_t)kMaxBlocks * r * sizeof(double)) != hipSuccess)
     return b->fail(LREI_E_DEVICE, "device memset failed");
   t.ws.stats = (double *)b->stats.p + (size_t)idx * kStatsLen;
   return LREI_OK;
 }
 
-// Tables of the Chebyshev passes and their reductions (independent of the scheme).
+// Tables of the Krylov passes and their reductions (independent of the scheme).
 lrei_status build_pass_tables(lrei_batch *b) {
   for (int j = 0; j < kMaxStages; ++j) {
     std::map<std::tuple<int, int, int>, std::vector<int>> cls;  // (epl, big, dynamic) -> trajectories
-    std::vector<ChebArgs> args(b->tr.size());
+    std::vector<HvArgs> args(b->tr.size());
     for (size_t q = 0; q < b->tr.size(); ++q) {
       auto &t = b->tr[q];
-      ChebArgs a{};
-      a.Pprev = j == 0 ? nullptr : t.blocks[j - 1].p;
+      HvArgs a{};
       a.Pcur = t.blocks[j].p;
       a.Pnext = t.blocks[j + 1].p;
       a.terms64 = (const DevTerm<double> *)t.dt.off64.p;
@@ -214,8 +216,8 @@ lrei_status build_pass_tables(lrei_batch *b) {
       a.cplx = t.dt.cplx;
       a.N = t.N;
       a.r = t.r;
-      a.alpha = 1.0 / (t.terms.gershgorin > 0 ? t.terms.gershgorin : 1.0);
-      a.shift = 0.0;
+      a.alpha = t.terms.spread > 0 ? 1.0 / t.terms.spread : 1.0;
+      a.colshift = t.ws.shifts + (size_t)j * t.r;
       a.mode = j == 0 ? 0 : 1;
       a.partials = (double2 *)t.partials.p;
       a.grid = t.grid;
@@ -223,27 +225,27 @@ lrei_status build_pass_tables(lrei_batch *b) {
       // slot, which the hardware dispatcher balances by itself
       a.sched = nullptr;
       a.partial_cap = t.grid;
-      if (!prepare_cheb(b->fp32, a)) return b->fail(LREI_E_INVALID, "unsupported rank for the H.V pass");
+      if (!prepare_hv(b->fp32, a)) return b->fail(LREI_E_INVALID, "unsupported rank for the H.V pass");
       args[q] = a;
       cls[{a.epl, a.r > 16 ? 1 : 0, a.chunks > 0 ? 1 : 0}].push_back((int)q);
     }
-    for (auto &g : b->cheb[j]) g.t.release();
-    b->cheb[j].clear();
+    for (auto &g : b->hv[j]) g.t.release();
+    b->hv[j].clear();
     for (auto &kv : cls) {
-      lrei_batch::ChebGroup g;
+      lrei_batch::HvGroup g;
       g.epl = std::get<0>(kv.first);
       g.big = std::get<1>(kv.first) != 0;
       g.dyn = std::get<2>(kv.first) != 0;
-      std::vector<ChebArgs> recs;
+      std::vector<HvArgs> recs;
       std::vector<int> wgs;
       for (int q : kv.second) {
         recs.push_back(args[q]);
         wgs.push_back(args[q].grid);
         g.cplx = g.cplx || args[q].cplx;
-        g.lds = std::max(g.lds, cheb_launch_lds(b->fp32, args[q]));
+        g.lds = std::max(g.lds, hv_launch_lds(b->fp32, args[q]));
       }
       if (!build_tables(recs, wgs, true, g.t)) return b->fail(LREI_E_NOMEM, "launch table upload failed");
-      b->cheb[j].push_back(std::move(g));
+      b->hv[j].push_back(std::move(g));
     }
     std::vector<ReduceJob> rj;
     std::vector<int> lens;
@@ -281,8 +283,7 @@ lrei_status build_step_tables(lrei_batch *b, int scheme, double dt) {
     p.h = dt;
     p.eig_tol = b->opt.eig_tol;
     p.warm_tol = b->fp32 ? 1e-11 : 1e-14;
-    p.shift = 0.0;
-    p.halfwidth = t.terms.gershgorin > 0 ? t.terms.gershgorin : 1.0;
+    p.beta = t.terms.spread > 0 ? 1.0 / t.terms.spread : 1.0;
     for (int i = 0; i < t.r; ++i) p.lam[i] = t.lam[i];
     p.lds_elems = small_lds_elems(p.nblocks * t.r, t.r);
     lds = std::max(lds, p.lds_elems);
@@ -332,8 +333,8 @@ lrei_status build_step_tables(lrei_batch *b, int scheme, double dt) {
 
 // Pass j of every trajectory: H.V with fused Grams, then the reduction into meas.
 void enqueue_pass(lrei_batch *b, int j, hipStream_t s) {
-  for (auto &g : b->cheb[j])
-    launch_cheb_batch(b->fp32, g.epl, g.cplx, g.big, g.dyn, g.t.view(), g.t.total_wg, g.lds, s);
+  for (auto &g : b->hv[j])
+    launch_hv_batch(b->fp32, g.epl, g.cplx, g.big, g.dyn, g.t.view(), g.t.total_wg, g.lds, s);
   launch_reduce_batch(b->reduce[j].view(), b->reduce[j].total_wg, s);
 }
 
@@ -364,7 +365,7 @@ void destroy_batch(lrei_batch *b) {
   for (auto &t : b->tr) t.release();
   b->stats.release();
   b->scratch.release();
-  for (auto &v : b->cheb)
+  for (auto &v : b->hv)
     for (auto &g : v) g.t.release();
   for (auto &t : b->reduce) t.release();
   for (auto &g : b->comb) g.t.release();
@@ -624,18 +625,22 @@ lrei_status lrei_batch_get_rho(lrei_batch *b, int traj, double *lambda, void *V,
 lrei_status lrei_batch_energies(lrei_batch *b, double *energy) {
   if (!b || !energy) return LREI_E_INVALID;
   BCHK(hipSetDevice(b->device));
-  // pass 0 measures P0* P1 with P1 = H P0 / e (scratch block 1; the state is untouched)
+  // pass 0 measures P0* P0 and P0* P1 with P1 = beta (H P0 - P0 D0) (scratch block 1;
+  // the state is untouched), so (P0* H P0)_aa = (P0* P1)_aa / beta + D0_a (P0* P0)_aa
   enqueue_pass(b, 0, b->stream);
   BCHK(hipGetLastError());
   BCHK(hipStreamSynchronize(b->stream));
   for (size_t q = 0; q < b->tr.size(); ++q) {
     auto &t = b->tr[q];
     const int rr = t.r * t.r;
-    std::vector<double2> g(rr);
-    BCHK(hipMemcpy(g.data(), t.ws.meas + rr, rr * sizeof(double2), hipMemcpyDeviceToHost));
-    const double e = t.terms.gershgorin > 0 ? t.terms.gershgorin : 1.0;
+    std::vector<double2> g(2 * rr);
+    std::vector<double> d0(t.r);
+    BCHK(hipMemcpy(g.data(), t.ws.meas, 2 * rr * sizeof(double2), hipMemcpyDeviceToHost));
+    BCHK(hipMemcpy(d0.data(), t.ws.shifts, t.r * sizeof(double), hipMemcpyDeviceToHost));
+    const double e = t.terms.spread > 0 ? t.terms.spread : 1.0;
     double en = 0;
-    for (int a = 0; a < t.r; ++a) en += t.lam[a] * g[a * t.r + a].x * e;
+    for (int a = 0; a < t.r; ++a)
+      en += t.lam[a] * (g[rr + a * t.r + a].x * e + d0[a] * g[a * t.r + a].x);
     energy[q] = en;
   }
   return LREI_OK;
@@ -664,8 +669,8 @@ lrei_status lrei_batch_profile_kernels(lrei_batch *b, int scheme, double dt, int
   };
   const int j = s > 1 ? 1 : 0;  // the recurrence-form pass where it exists
   ms[0] = timed([&] {
-    for (auto &g : b->cheb[j])
-      launch_cheb_batch(b->fp32, g.epl, g.cplx, g.big, g.dyn, g.t.view(), g.t.total_wg, g.lds, b->stream);
+    for (auto &g : b->hv[j])
+      launch_hv_batch(b->fp32, g.epl, g.cplx, g.big, g.dyn, g.t.view(), g.t.total_wg, g.lds, b->stream);
   });
   ms[1] = timed([&] { launch_reduce_batch(b->reduce[j].view(), b->reduce[j].total_wg, b->stream); });
   ms[2] = timed([&] {

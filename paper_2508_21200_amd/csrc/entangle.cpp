@@ -1,4 +1,4 @@
-// Entanglement measures of a two-spin reduced density matrix (Sec. 3.5: the
+// Entanglement measures of a two-spin reduced density matrix (Sec. 3.6: the
 // paper takes concurrence, negativity and nonlocality of the 4 x 4 R_kl).
 // Host code on 4 x 4 complex matrices, index q = 2 b_k + b_l.
 #include <algorithm>

@@ -47,7 +47,7 @@ inline hipError_t create_streams(bool own_work, hipStream_t *work, hipStream_t *
   return hipStreamCreateWithFlags(side, hipStreamNonBlocking);
 }
 
-// Butcher tableaux (Sec. 3.6).  RK2: the paper's Heun tableau; RK3: Kutta;
+// Butcher tableaux (Sec. 3.7).  RK2: the paper's Heun tableau; RK3: Kutta;
 // RK4: classical.
 inline void tableau(int scheme, int &s, double a[kMaxStages][kMaxStages], double b[kMaxStages]) {
   for (int i = 0; i < kMaxStages; ++i) {

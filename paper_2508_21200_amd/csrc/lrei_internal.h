@@ -33,6 +33,7 @@ struct TermTable {
   std::vector<OffTerm> off;
   std::vector<DiagTerm> diag;
   double gershgorin = 0.0;  // bound on the spectral radius of H
+  double spread = 0.0;      // sqrt(Tr(H^2) / N): the spectral width of H seen by a random state
 };
 
 // Builds the term table; returns false with `err` set on invalid input.
@@ -58,8 +59,7 @@ constexpr int kMaxBlocks = 8;               // Krylov blocks in the projected ba
 constexpr int kMaxDim = kMaxBlocks * kMaxR; // projected dimension bound
 
 // Launch helpers implemented in nspace.hip / small.hip.
-struct ChebArgs {
-  const void *Pprev;   // P_{j-1} (mode 1) or nullptr
+struct HvArgs {
   const void *Pcur;    // P_j
   void *Pnext;         // P_{j+1}
   const DevTerm<double> *terms64;  // off-diagonal terms
@@ -80,26 +80,31 @@ struct ChebArgs {
   unsigned char win_pos[32], fix_pos[32];
   long long N;
   int r;
-  double alpha, shift;  // P_{j+1} = mul * alpha * (H - shift) P_j - [mode 1] P_{j-1}
-  int mode;             // 0: first, 1: recurrence, 2: plain Y = H X (no Grams)
+  // Krylov block recurrence P_{j+1} = alpha (H P_j - P_j diag(colshift)),
+  // colshift[c] the shift of column c of block j (nullptr: all zero)
+  double alpha;
+  const double *colshift;
+  int mode;             // 0: first block (Grams P0*P0, P0*P1, P1*P1), 1: later blocks
+                        // (Grams P*P+, P+*P+), 2: plain Y = alpha H X (no Grams)
   double2 *partials;    // Gram partial sums, entry-major [entry][slot]
   int grid;
   // dynamic tile schedule: counters (16 ints, zero between launches; nullptr:
   // static schedule) and the number of partial-sum slots the buffer holds
   int *sched;
   int partial_cap;
-  int chunks;           // set by prepare_cheb: Gram partial slots used (0: one per workgroup)
+  int chunks;           // set by prepare_hv: Gram partial slots used (0: one per workgroup)
   const double *skip;   // the pass does nothing while *skip != 0 (nullptr: always runs)
 };
 
 // Launches one H.V pass; returns the number of Gram partial slots written
 // (the reduction's count), 0 if the shape is unsupported.
-int launch_cheb(bool fp32, const ChebArgs &a, hipStream_t s);
+int launch_hv(bool fp32, const HvArgs &a, hipStream_t s);
+bool hv_epl_valid(bool fp32, int r, int epl);
 // Fills the launcher-set fields of a (columns per lane, lanes, table pointers,
 // the default single window); false if the shape is unsupported.
-bool prepare_cheb(bool fp32, ChebArgs &a);
-size_t cheb_lds_bytes(bool fp32, int r);
-size_t cheb_launch_lds(bool fp32, const ChebArgs &a);  // dynamic LDS of a prepared pass
+bool prepare_hv(bool fp32, HvArgs &a);
+size_t hv_lds_bytes(bool fp32, int r);
+size_t hv_launch_lds(bool fp32, const HvArgs &a);  // dynamic LDS of a prepared pass
 
 // Launch tables of a batched kernel (many independent jobs in one launch):
 // workgroup w runs job wg_job[w] as that job's workgroup w - job_wg0[job].
@@ -109,11 +114,11 @@ struct BatchLaunch {
   const int *wg_job;
   const int *job_wg0;
 };
-// Batched Chebyshev passes: every job is a ChebArgs prepared by prepare_cheb
+// Batched Krylov passes: every job is a HvArgs prepared by prepare_hv
 // with the same precision, columns per lane epl, complex flag and r > 16 flag.
-bool launch_cheb_batch(bool fp32, int epl, bool cplx, bool big, bool dyn, const BatchLaunch &b, int total_wg,
+bool launch_hv_batch(bool fp32, int epl, bool cplx, bool big, bool dyn, const BatchLaunch &b, int total_wg,
                        size_t lds, hipStream_t s);
-size_t cheb_lds_dyn_extra();  // LDS added by the dynamic schedule (Gram accumulators)
+size_t hv_lds_dyn_extra();  // LDS added by the dynamic schedule (Gram accumulators)
 // Basis combination out = [B_0 ... B_{nb-1}] C (nspace.hip).
 struct CombineArgs {
   const void *blocks[kMaxBlocks];
@@ -123,6 +128,11 @@ struct CombineArgs {
   long long N;
   int r, grid;
   const double *skip;  // nothing is written while *skip != 0 (nullptr: always runs)
+  // compensated FP32 state (FP32 blocks only; nullptr: plain): the state is
+  // blocks[0] + lo_in; the kernel forms blocks[0] + lo_in + [B_0..B_{nb-1}] (C - [I; 0])
+  // and writes it split again as out + lo_out
+  const void *lo_in;
+  void *lo_out;
 };
 // Batched combinations: every job has the same nb and padded width RP (16 or 32).
 void launch_combine_batch(bool fp32, int RP, int nblocks, const BatchLaunch &b, int total_wg, hipStream_t s);
@@ -134,10 +144,14 @@ struct ReduceJob {
   double2 *out;
 };
 void launch_reduce_batch(const BatchLaunch &b, int total_wg, hipStream_t s);
+// Compensated FP32 pairs: hi = fl32(v), lo = fl32(v - hi) (split); v = hi + lo (merge).
+void launch_split(const double2 *src, float2 *hi, float2 *lo, long long n, hipStream_t s);
+void launch_merge(const float2 *hi, const float2 *lo, double2 *dst, long long n, hipStream_t s);
 void launch_diag_values(const DevDiagTerm *diag, int n_diag, long long N, double *d64, float *d32, hipStream_t s);
-int cheb_elems_per_lane(bool fp32, int r);
+int hv_elems_per_lane(bool fp32, int r);
 void launch_combine(bool fp32, const void *const *blocks, int nblocks, const double2 *C, void *out,
-                    long long N, int r, int grid, hipStream_t s, const double *skip = nullptr);
+                    long long N, int r, int grid, hipStream_t s, const double *skip = nullptr,
+                    const void *lo_in = nullptr, void *lo_out = nullptr);
 void launch_reduce(const double2 *partials, int count, int len, double2 *out, hipStream_t s);
 void launch_convert(bool to_fp32, const void *src, void *dst, long long n_complex, hipStream_t s);
 // dst rows = src rows moved by the site -> bit map pos (forward) or gathered back (inverse).
@@ -220,7 +234,7 @@ struct SmallRkParams {
   int lds_elems;          // double2 capacity of the dynamic LDS matrix
   double kappa, hbar, h, eig_tol;
   double warm_tol;        // relative subspace residual at which the warm-started eigensolve stops
-  double shift, halfwidth; // Chebyshev map H~ = (H - shift) / halfwidth
+  double beta;            // Krylov recurrence P_{j+1} = beta (H P_j - P_j diag(D_j)), D_j in SmallWs.shifts
   double a[kMaxStages][kMaxStages];
   double b[kMaxStages];
   double lam[kMaxR];
@@ -253,6 +267,8 @@ struct SmallWs {
   double2 *Cfin;     // [D*r] combination coefficients for the new V
   double *flags;     // [D] directions dropped as dependent
   double *warm_skip; // [kMaxStages] steps left before stage j tries the warm start again
+  double *shifts;    // [kMaxBlocks][r] column shifts D_j of the Krylov recurrence (read by the
+                     // passes; refreshed from the measured Rayleigh quotients by the step's last stage)
   double *stats;     // [32]
 };
 
@@ -310,7 +326,7 @@ struct SmallAbWs {
 void launch_small_ab(const SmallAbParams &p, const SmallAbWs &ws, hipStream_t s);
 size_t small_ab_work_elems(int D, int qn, int r);
 void launch_ab_cgs_coef(const double2 *c1g, int nU, int qx, int r, double2 *C, hipStream_t s);
-int cheb_partial_splits(int r);
+int hv_partial_splits(int r);
 
 }  // namespace lrei
 

@@ -1,5 +1,6 @@
 // N-space kernels of the LREI step on gfx950: the matrix-free Hamiltonian
-// apply in a Chebyshev three-term recurrence with fused Gram products, the
+// apply in the Krylov block recurrence P_{j+1} = beta (H P_j - P_j D_j) with
+// fused Gram products, the
 // basis combination that forms the new support, a deterministic reduction of
 // per-workgroup partial sums, and the magnetisation pass.
 //
@@ -8,6 +9,7 @@
 // FP64, 128 B in FP32) and any row gather is a coalesced segment load.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "lrei_internal.h"
@@ -200,10 +202,11 @@ __device__ inline GramPlan<T> make_plan(int ng, int RP) {
 }
 
 // ---------------------------------------------------------------------------
-// Chebyshev pass with the Hamiltonian applied matrix-free.
-//   mode 0: P1 = alpha (H - shift) P0                Grams P0*P0, P0*P1, P1*P1
-//   mode 1: P+ = 2 alpha (H - shift) P - P-           Grams P*P+, P+*P+
-//   mode 2: Y = H X                                    (no Grams)
+// Krylov pass with the Hamiltonian applied matrix-free:
+//   P+ = alpha (H P - P diag(colshift)), colshift the per-column shifts of P
+//   mode 0: first block     Grams P*P, P*P+, P+*P+
+//   mode 1: later blocks    Grams P*P+, P+*P+
+//   mode 2: Y = alpha H X   (no Grams, no shift)
 //
 // A row x of the output is d(x) X[x] + sum_t c_t(x) X[x ^ mask_t].  L lanes
 // share a row, each holding E consecutive complex columns (16-byte loads), so
@@ -254,7 +257,7 @@ __device__ inline T pick4(int idx, T c0, T c1, T c2, T c3) {
 // MI: Gram work items per wave, WIN: row-bit window sweeps allowed.  wg is the
 // workgroup's index among the a.grid workgroups of this pass.
 template <typename T, int E, bool CPLX, int MI, bool WIN, bool DYN>
-__device__ __forceinline__ void cheb_body(const ChebArgs &a, int wg, unsigned char *smem) {
+__device__ __forceinline__ void hv_body(const HvArgs &a, int wg, unsigned char *smem) {
   static_assert(!DYN || (MI == 1 && !WIN), "the dynamic schedule keeps one Gram item per wave in LDS");
   // row gathers in flight per lane: kept small so that four waves fit per SIMD
   constexpr int B = (sizeof(T) == 4 ? 16 : 8) / E > 1 ? (sizeof(T) == 4 ? 16 : 8) / E : 2;
@@ -273,7 +276,6 @@ __device__ __forceinline__ void cheb_body(const ChebArgs &a, int wg, unsigned ch
   __syncthreads();
 
   const T *__restrict__ Pc = reinterpret_cast<const T *>(a.Pcur);
-  const T *__restrict__ Pp = reinterpret_cast<const T *>(a.Pprev);
   T *__restrict__ Pn = reinterpret_cast<T *>(a.Pnext);
   // The term table is read-only during the launch and every lane of a wave
   // reads the same record: reading it through the constant address space
@@ -288,8 +290,11 @@ __device__ __forceinline__ void cheb_body(const ChebArgs &a, int wg, unsigned ch
   const int cl = lane % L, rsub = lane / L;
   const int col0 = cl * E;
   const bool active = col0 < r;
-  const T alpha = (T)a.alpha, shift = (T)a.shift;
-  const T mul = a.mode == 1 ? T(2) : T(1);
+  const T alpha = (T)a.alpha;
+  // column shifts of this block (the recurrence subtracts P_j diag(shift))
+  T csh[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) csh[e] = (a.colshift && col0 + e < r) ? (T)a.colshift[col0 + e] : T(0);
 
   const int ng = a.mode == 2 ? 0 : (a.mode == 0 ? 3 : 2);
   GramPlan<T> gp = make_plan<T>(ng > 0 ? ng : 1, RP);
@@ -340,6 +345,7 @@ __device__ __forceinline__ void cheb_body(const ChebArgs &a, int wg, unsigned ch
   // sched[8 + x]) resets both counters for the next launch.
   const int cpx = DYN ? a.chunks >> 3 : 1;
   const long long per = num_tiles >> 3, cs = DYN ? per / cpx : 0;
+  // dynamic schedule only (r <= 16): the staged partial sums fit in the planes
   double *lacc = reinterpret_cast<double *>(smem + 4 * (size_t)plane * sizeof(T));
   __shared__ int s_chunk;
   int chunk = -1;
@@ -446,14 +452,9 @@ __device__ __forceinline__ void cheb_body(const ChebArgs &a, int wg, unsigned ch
             }
           }
       }
-      if (a.mode != 2 && !a.acc_out) {
-        T pv[2 * E];
-        if (a.mode == 1) ld(Pp, rowo, pv);
+      if (!a.acc_out) {
 #pragma unroll
-        for (int e = 0; e < 2 * E; ++e) {
-          o[e] = mul * alpha * (o[e] - shift * own[e]);
-          if (a.mode == 1) o[e] -= pv[e];
-        }
+        for (int e = 0; e < 2 * E; ++e) o[e] = alpha * (o[e] - csh[e >> 1] * own[e]);
       }
       store_ce<T, E>(Pn + 2 * base, o);
       if (grams) {
@@ -490,10 +491,10 @@ __device__ __forceinline__ void cheb_body(const ChebArgs &a, int wg, unsigned ch
 }
 
 template <typename T, int E, bool CPLX, int MI, bool DYN>
-__global__ __launch_bounds__(kThreads) void k_cheb(ChebArgs a) {
+__global__ __launch_bounds__(kThreads) void k_hv(HvArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   if (a.skip && *a.skip != 0.0) return;  // the same for every workgroup of the launch
-  cheb_body<T, E, CPLX, MI, !DYN, DYN>(a, blockIdx.x, smem);
+  hv_body<T, E, CPLX, MI, !DYN, DYN>(a, blockIdx.x, smem);
 }
 
 // Many independent passes in one launch (one per trajectory of a batch): the
@@ -501,12 +502,12 @@ __global__ __launch_bounds__(kThreads) void k_cheb(ChebArgs a) {
 // every job's workgroups start at a multiple of 8, so a workgroup keeps its
 // XCD slot within the job.
 template <typename T, int E, bool CPLX, int MI, bool DYN>
-__global__ __launch_bounds__(kThreads) void k_cheb_batch(BatchLaunch b) {
+__global__ __launch_bounds__(kThreads) void k_hv_batch(BatchLaunch b) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int j = b.wg_job[blockIdx.x];
   if (j < 0) return;  // alignment padding
-  const ChebArgs a = reinterpret_cast<const ChebArgs *>(b.jobs)[j];
-  cheb_body<T, E, CPLX, MI, false, DYN>(a, blockIdx.x - b.job_wg0[j], smem);
+  const HvArgs a = reinterpret_cast<const HvArgs *>(b.jobs)[j];
+  hv_body<T, E, CPLX, MI, false, DYN>(a, blockIdx.x - b.job_wg0[j], smem);
 }
 
 // Diagonal of H per row: d(x) = sum_k w_k (1 - 2 (b_{i_k}(x) xor b_{j_k}(x))),
@@ -547,6 +548,7 @@ __device__ __forceinline__ void combine_body(const CombineArgs &a, int wg, unsig
     const int blk = kk / RP, ak = kk % RP;
     double2 c = make_double2(0.0, 0.0);
     if (ak < r && j < r) c = a.C[(blk * r + ak) * r + j];
+    if (a.lo_in && blk == 0 && ak == j && j < r) c.x -= 1.0;  // compensated state: the update only
     cre[i] = (T)c.x;
     cim[i] = (T)c.y;
   }
@@ -608,8 +610,26 @@ __device__ __forceinline__ void combine_body(const CombineArgs &a, int wg, unsig
       for (int v = 0; v < 4; ++v) {
         const long long xo = tile * kTile + wave * 16 + mfma_row<T>(lane, v);
         if (j < r && xo < N) {
-          out[2 * ((size_t)xo * r + j)] = ore[tb][v];
-          out[2 * ((size_t)xo * r + j) + 1] = oim[tb][v];
+          const size_t o = 2 * ((size_t)xo * r + j);
+          if constexpr (sizeof(T) == 4) {
+            if (a.lo_in) {
+              // hi + lo + update in FP64, split again (this wave read row xo of
+              // blocks[0] above; out may be blocks[0])
+              const T *hi = reinterpret_cast<const T *>(a.blocks[0]);
+              const T *lo = reinterpret_cast<const T *>(a.lo_in);
+              const double vr = (double)hi[o] + (double)lo[o] + (double)ore[tb][v];
+              const double vi = (double)hi[o + 1] + (double)lo[o + 1] + (double)oim[tb][v];
+              const float hr = (float)vr, hm = (float)vi;
+              out[o] = hr;
+              out[o + 1] = hm;
+              T *lw = reinterpret_cast<T *>(a.lo_out);
+              lw[o] = (float)(vr - (double)hr);
+              lw[o + 1] = (float)(vi - (double)hm);
+              continue;
+            }
+          }
+          out[o] = ore[tb][v];
+          out[o + 1] = oim[tb][v];
         }
       }
     }
@@ -695,6 +715,20 @@ __global__ void k_convert_d2f(const double2 *src, float2 *dst, long long n) {
        i += (long long)gridDim.x * blockDim.x)
     dst[i] = make_float2((float)src[i].x, (float)src[i].y);
 }
+__global__ void k_split_d2f(const double2 *src, float2 *hi, float2 *lo, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const double2 v = src[i];
+    const float2 h = make_float2((float)v.x, (float)v.y);
+    hi[i] = h;
+    lo[i] = make_float2((float)(v.x - (double)h.x), (float)(v.y - (double)h.y));
+  }
+}
+__global__ void k_merge_f2d(const float2 *hi, const float2 *lo, double2 *dst, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    dst[i] = make_double2((double)hi[i].x + (double)lo[i].x, (double)hi[i].y + (double)lo[i].y);
+}
 __global__ void k_convert_f2d(const float2 *src, double2 *dst, long long n) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
@@ -753,7 +787,7 @@ __global__ __launch_bounds__(kThreads) void k_magnet(const void *Vp, const doubl
   }
 }
 
-// Two-spin reduced density matrices (Sec. 3.5), pair p = blockIdx.y with row
+// Two-spin reduced density matrices (Sec. 3.6), pair p = blockIdx.y with row
 // bits (bk, bl): the N/4 groups of rows that differ only in those two bits
 // each hold the four rows x_q (q = 2 b_k + b_l), and
 // R[q][q'] = sum over groups and columns a of lam_a V[x_q, a] conj(V[x_q', a]).
@@ -842,11 +876,18 @@ __global__ void k_pair_reduce(const double2 *partials, int grid, int n_pairs, do
   if (q2 != q) out[p * 16 + q2 * 4 + q] = make_double2(s.x, -s.y);
 }
 
-size_t cheb_lds(bool fp32, int r) { return 4 * (size_t)kTile * pad16(r) * (fp32 ? 4 : 8); }
+// LDS of a pass: the four Gram planes [kTile][RP] of the tile, which also
+// stage the workgroup's Gram partial sums (up to 3 r^2 complex FP64 values)
+// when it stores them -- the larger of the two.
+size_t hv_lds(bool fp32, int r) {
+  const size_t planes = 4 * (size_t)kTile * pad16(r) * (fp32 ? 4 : 8);
+  const size_t stage = 3 * (size_t)r * r * sizeof(double2);
+  return planes > stage ? planes : stage;
+}
 
 }  // namespace
 
-int cheb_partial_splits(int r) {
+int hv_partial_splits(int r) {
   (void)r;
   return 1;  // row splits are summed inside the workgroup
 }
@@ -862,7 +903,7 @@ int nspace_grid(long long N, int r) {
 // Complex columns per lane for the H.V pass: 16-byte lanes, E | r, and at
 // least four lanes per row where r allows, so that the four waves of a
 // 64-row tile all have rows.
-int cheb_elems_per_lane(bool fp32, int r) {
+int hv_elems_per_lane(bool fp32, int r) {
   int e;
   if (r > 16) e = (fp32 && r % 2 == 0) ? 2 : 1;
   else if (fp32) e = r % 4 == 0 ? 4 : (r % 2 == 0 ? 2 : 1);
@@ -871,37 +912,37 @@ int cheb_elems_per_lane(bool fp32, int r) {
   return e;
 }
 
-size_t cheb_lds_bytes(bool fp32, int r) { return cheb_lds(fp32, r); }
+size_t hv_lds_bytes(bool fp32, int r) { return hv_lds(fp32, r); }
 
-size_t cheb_lds_dyn_extra() { return (size_t)8 * kThreads * sizeof(double); }
+size_t hv_lds_dyn_extra() { return (size_t)8 * kThreads * sizeof(double); }
 
 template <typename T, int E, bool C, int MI, bool DYN>
-static void launch_one(const ChebArgs &a, size_t lds, hipStream_t s) {
+static void launch_one(const HvArgs &a, size_t lds, hipStream_t s) {
   static bool attr = false;
   if (!attr) {
-    (void)hipFuncSetAttribute((const void *)k_cheb<T, E, C, MI, DYN>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute((const void *)k_hv<T, E, C, MI, DYN>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               kMaxLds);
     attr = true;
   }
-  hipLaunchKernelGGL((k_cheb<T, E, C, MI, DYN>), dim3(a.grid), dim3(kThreads), lds, s, a);
+  hipLaunchKernelGGL((k_hv<T, E, C, MI, DYN>), dim3(a.grid), dim3(kThreads), lds, s, a);
 }
 
 template <typename T, int E, bool C, int MI, bool DYN>
 static void launch_one_batch(const BatchLaunch &b, int total_wg, size_t lds, hipStream_t s) {
   static bool attr = false;
   if (!attr) {
-    (void)hipFuncSetAttribute((const void *)k_cheb_batch<T, E, C, MI, DYN>,
+    (void)hipFuncSetAttribute((const void *)k_hv_batch<T, E, C, MI, DYN>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
     attr = true;
   }
-  hipLaunchKernelGGL((k_cheb_batch<T, E, C, MI, DYN>), dim3(total_wg), dim3(kThreads), lds, s, b);
+  hipLaunchKernelGGL((k_hv_batch<T, E, C, MI, DYN>), dim3(total_wg), dim3(kThreads), lds, s, b);
 }
 
 // Dispatches on (precision, E, complex coefficients, Gram items per wave,
 // schedule).  f is called as f.template operator()<T, E, C, MI, DYN>().  The
 // dynamic schedule exists for FP32 storage with one Gram item per wave.
 template <typename Fn>
-static bool dispatch_cheb(bool fp32, int E, bool cplx, bool big, bool dyn, Fn &&f) {
+static bool dispatch_hv(bool fp32, int E, bool cplx, bool big, bool dyn, Fn &&f) {
   if (dyn && (!fp32 || big)) return false;
   auto c = [&](auto tag_t, auto tag_e, auto tag_mi) {
     using T = typename decltype(tag_t)::type;
@@ -953,7 +994,21 @@ static bool dispatch_cheb(bool fp32, int E, bool cplx, bool big, bool dyn, Fn &&
   return true;
 }
 
-bool prepare_cheb(bool fp32, ChebArgs &a) {
+// Whether `epl` complex columns per lane is a launchable H.V shape for rank r
+// in this precision (0 = the default shape, always valid for 1 <= r <= 32).
+bool hv_epl_valid(bool fp32, int r, int epl) {
+  if (r < 1 || r > kMaxR) return false;
+  if (epl == 0) return true;
+  if (epl < 0 || r % epl != 0) return false;
+  int L = 1;
+  while (L * epl < r) L <<= 1;
+  if (L > 64) return false;
+  const bool big = r > 16;
+  if (fp32) return big ? (epl == 1 || epl == 2) : (epl == 1 || epl == 2 || epl == 4 || epl == 8);
+  return big ? epl == 1 : (epl == 1 || epl == 2 || epl == 4);
+}
+
+bool prepare_hv(bool fp32, HvArgs &a) {
   if (a.win_bits == 0) {  // default: one window over all row bits, every term, the diagonal
     a.t0 = 0;
     a.t1 = a.n_off;
@@ -961,7 +1016,8 @@ bool prepare_cheb(bool fp32, ChebArgs &a) {
     a.n_fix = 0;
     a.win_bits = 31;
   }
-  const int E = a.epl > 0 ? a.epl : cheb_elems_per_lane(fp32, a.r);
+  if (!hv_epl_valid(fp32, a.r, a.epl)) return false;
+  const int E = a.epl > 0 ? a.epl : hv_elems_per_lane(fp32, a.r);
   if (a.r % E != 0) return false;
   int L = 1;
   while (L * E < a.r) L <<= 1;
@@ -988,24 +1044,24 @@ bool prepare_cheb(bool fp32, ChebArgs &a) {
   return true;
 }
 
-size_t cheb_launch_lds(bool fp32, const ChebArgs &a) {
-  return cheb_lds(fp32, a.r) + (a.chunks > 0 ? cheb_lds_dyn_extra() : 0);
+size_t hv_launch_lds(bool fp32, const HvArgs &a) {
+  return hv_lds(fp32, a.r) + (a.chunks > 0 ? hv_lds_dyn_extra() : 0);
 }
 
-int launch_cheb(bool fp32, const ChebArgs &a0, hipStream_t s) {
-  ChebArgs a = a0;
-  if (!prepare_cheb(fp32, a)) return 0;
-  const size_t lds = cheb_launch_lds(fp32, a);
-  const bool ok = dispatch_cheb(fp32, a.epl, a.cplx != 0, a.r > 16, a.chunks > 0,
+int launch_hv(bool fp32, const HvArgs &a0, hipStream_t s) {
+  HvArgs a = a0;
+  if (!prepare_hv(fp32, a)) return 0;
+  const size_t lds = hv_launch_lds(fp32, a);
+  const bool ok = dispatch_hv(fp32, a.epl, a.cplx != 0, a.r > 16, a.chunks > 0,
                                 [&]<typename T, int E, bool C, int MI, bool DYN>() {
                                   launch_one<T, E, C, MI, DYN>(a, lds, s);
                                 });
   return ok ? (a.chunks > 0 ? a.chunks : a.grid) : 0;
 }
 
-bool launch_cheb_batch(bool fp32, int epl, bool cplx, bool big, bool dyn, const BatchLaunch &b, int total_wg,
+bool launch_hv_batch(bool fp32, int epl, bool cplx, bool big, bool dyn, const BatchLaunch &b, int total_wg,
                        size_t lds, hipStream_t s) {
-  return dispatch_cheb(fp32, epl, cplx, big, dyn, [&]<typename T, int E, bool C, int MI, bool DYN>() {
+  return dispatch_hv(fp32, epl, cplx, big, dyn, [&]<typename T, int E, bool C, int MI, bool DYN>() {
     launch_one_batch<T, E, C, MI, DYN>(b, total_wg, lds, s);
   });
 }
@@ -1017,9 +1073,12 @@ void launch_diag_values(const DevDiagTerm *diag, int n_diag, long long N, double
 }
 
 void launch_combine(bool fp32, const void *const *blocks, int nblocks, const double2 *C, void *out,
-                    long long N, int r, int grid, hipStream_t s, const double *skip) {
+                    long long N, int r, int grid, hipStream_t s, const double *skip, const void *lo_in,
+                    void *lo_out) {
   CombineArgs a;
   a.skip = skip;
+  a.lo_in = fp32 ? lo_in : nullptr;
+  a.lo_out = fp32 ? lo_out : nullptr;
   for (int i = 0; i < kMaxBlocks; ++i) a.blocks[i] = i < nblocks ? blocks[i] : nullptr;
   a.nb = nblocks;
   a.C = C;
@@ -1071,6 +1130,16 @@ void launch_reduce_batch(const BatchLaunch &b, int total_wg, hipStream_t s) {
 
 void launch_reduce(const double2 *partials, int count, int len, double2 *out, hipStream_t s) {
   hipLaunchKernelGGL(k_reduce, dim3(len), dim3(256), 0, s, partials, count, len, out);
+}
+
+void launch_split(const double2 *src, float2 *hi, float2 *lo, long long n, hipStream_t s) {
+  const long long blocks = std::max<long long>(1, std::min<long long>(4096, (n + 255) / 256));
+  hipLaunchKernelGGL(k_split_d2f, dim3((unsigned)blocks), dim3(256), 0, s, src, hi, lo, n);
+}
+
+void launch_merge(const float2 *hi, const float2 *lo, double2 *dst, long long n, hipStream_t s) {
+  const long long blocks = std::max<long long>(1, std::min<long long>(4096, (n + 255) / 256));
+  hipLaunchKernelGGL(k_merge_f2d, dim3((unsigned)blocks), dim3(256), 0, s, hi, lo, dst, n);
 }
 
 void launch_convert(bool to_fp32, const void *src, void *dst, long long n, hipStream_t s) {

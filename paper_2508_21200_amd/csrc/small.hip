@@ -3,7 +3,8 @@
 // All stage factors of one RK step lie in the block Krylov space of H started
 // from the current support V_1: V_1 is in it, f(K_j) = Z_j V_j* + V_j W_j*
 // only adds H V_j, and V_{j+1} is spanned by V_1..V_j, W_1..W_j.  The N-space
-// passes build that space as the Chebyshev blocks P_0 = V_1, P_1, ..., P_s and
+// passes build that space as the blocks P_0 = V_1, P_{j+1} = beta (H P_j - P_j D_j)
+// (D_j diagonal per-column shifts, beta the inverse spectral width of H) and
 // measure their Gram products; this kernel then runs the paper's step
 // (eqs. 3.2/4.1, 3.3, 3.4, 3.7-3.9 and the partial eigendecomposition with the
 // spectrum reset to Lambda_0) exactly, in the coordinates of an orthonormal
@@ -11,21 +12,23 @@
 //
 // Steps:
 //  1. Assemble the Gram matrix Gamma of the blocks from the measured products
-//     and the Chebyshev recurrence; Cholesky Gamma = R* R with directions whose
-//     pivot falls below 1e-13 of the diagonal treated as dependent (dropped).
+//     and the recurrence (P_i* P_{j+1} = P_{i+1}* P_j + beta (D_i P_i* P_j - P_i* P_j D_j));
+//     Cholesky Gamma = R* R with directions whose pivot falls below 1e-13 of
+//     the diagonal treated as dependent (dropped).
 //  2. Coordinates: V_1 = B R^{-1} u_1 with u_1 = R[:, :r] (R_00* R_00)^{-1/2};
 //     the projected Hamiltonian acts as y = R That R^{-1} u, That being the
-//     block-tridiagonal Chebyshev relation H P_j = c P_j + e (P_{j+1} + P_{j-1})/2.
+//     block-bidiagonal relation H P_j = P_j D_j + P_{j+1} / beta.
 //  3. For each stage: G = u* y, X11 = Phi o G, X12 coefficients c_a; the
 //     complement action W = Vhat X12* through r Householder reflectors of u
 //     (Sec. 3.4) (or the projector form); Z = u X11 + W; the stage matrix
 //     k = u_1 Lambda_0 u_1* + h sum a_l (z_l u_l* + u_l w_l*) and its r largest
-//     eigenvectors by a cyclic two-sided complex Jacobi method.
-//  4. C = R^{-1} u_final.
+//     eigenvectors: subspace iteration from u with a spectral-gap certificate,
+//     or the direct solve (Householder tridiagonalisation, multisection on
+//     Sturm counts, inverse iteration, back-transformation).
+//  4. C = R^{-1} u_final; the last kernel of the step refreshes D_j.
 //
-// The Jacobi sweeps are latency bound: the stage matrix (packed upper
-// triangle) and the accumulated rotations live in LDS, and rounds are
-// separated by LDS-only barriers.
+// Every phase is latency bound (one workgroup): the stage matrix (packed
+// upper triangle) and the solver's work arrays live in LDS.
 #include <hip/hip_runtime.h>
 
 #include "lrei_internal.h"
@@ -1898,7 +1901,8 @@ __device__ __forceinline__ void rk_basis(const SmallRkParams &p, const SmallWs &
   };
   // ---- 1. Gram columns [k0, k1) -----------------------------------------------
   // pass 0 measured P0*P0, P0*P1, P1*P1; pass j >= 1 measured P_j*P_{j+1}, P_{j+1}*P_{j+1};
-  // the other blocks of column j+1 follow from P_{j+1} = 2 H~ P_j - P_{j-1}
+  // the other blocks of column j+1 follow from P_{i+1} = beta (H P_i - P_i D_i):
+  // P_i* P_{j+1} = P_{i+1}* P_j + beta (D_i P_i* P_j - P_i* P_j D_j)
   auto gblk = [&](int bi, int bj) { return G + (bi * r) * D + bj * r; };
   auto put = [&](int bi, int bj, const double2 *M) {
     for (int e = threadIdx.x; e < rr; e += NT) gblk(bi, bj)[(e / r) * D + e % r] = M[e];
@@ -1932,14 +1936,12 @@ __device__ __forceinline__ void rk_basis(const SmallRkParams &p, const SmallWs &
     return bi <= bj ? gblk(bi, bj)[a * D + b] : cconj(gblk(bj, bi)[b * D + a]);
   };
   if (j >= 1) {
+    const double *Dsh = ws.shifts;  // [block][r]
     for (int e = threadIdx.x; e < j * rr; e += NT) {
       const int i = e / rr, a = (e % rr) / r, b = e % r;
-      double2 v;
-      if (i == 0)
-        v = csub(cscale(2.0, gget(1, j, a, b)), gget(0, j - 1, a, b));
-      else
-        v = csub(cadd(gget(i + 1, j, a, b), gget(i - 1, j, a, b)), gget(i, j - 1, a, b));
-      gblk(i, j + 1)[a * D + b] = v;
+      const double2 gij = gget(i, j, a, b);
+      const double d = p.beta * (Dsh[i * r + a] - Dsh[j * r + b]);
+      gblk(i, j + 1)[a * D + b] = cadd(gget(i + 1, j, a, b), cscale(d, gij));
     }
     __syncthreads();
   }
@@ -2057,17 +2059,16 @@ __device__ __forceinline__ void rk_stage(const SmallRkParams &p, const SmallWs &
     double2 *w = ws.stage + (3 * j + 2) * D * r;
     const int mi = (j + 1) * r;  // support of u
     const int mo = (j + 2) * r;  // support of y = H u
-    // y = R That R^{-1} u
+    // y = R That R^{-1} u, That the block-bidiagonal relation H P_i = P_i D_i + P_{i+1} / beta
     zgemm(t1, r, Ri, D, false, u, r, mi, r, mi);
-    for (int e = threadIdx.x; e < mo * r; e += NT) {
-      const int row = e / r, col = e % r, bi = row / r, a = row % r;
-      double2 v = cscale(p.shift, bi <= j ? t1[e] : make_double2(0, 0));
-      if (bi >= 1 && bi - 1 <= j) {
-        const double coef = (bi - 1 == 0) ? p.halfwidth : 0.5 * p.halfwidth;
-        v = cadd(v, cscale(coef, t1[((bi - 1) * r + a) * r + col]));
+    {
+      const double ib = 1.0 / p.beta;
+      for (int e = threadIdx.x; e < mo * r; e += NT) {
+        const int row = e / r, col = e % r, bi = row / r, a = row % r;
+        double2 v = bi <= j ? cscale(ws.shifts[bi * r + a], t1[e]) : make_double2(0, 0);
+        if (bi >= 1 && bi - 1 <= j) v = cadd(v, cscale(ib, t1[((bi - 1) * r + a) * r + col]));
+        Yc[e] = v;  // That * t1
       }
-      if (bi + 1 <= j) v = cadd(v, cscale(0.5 * p.halfwidth, t1[((bi + 1) * r + a) * r + col]));
-      Yc[e] = v;  // That * t1
     }
     __syncthreads();
     zgemm(y, r, R, D, false, Yc, r, mo, r, mo);
@@ -2209,6 +2210,22 @@ __device__ __forceinline__ void rk_stage(const SmallRkParams &p, const SmallWs &
       stats[11] += s;
       if (!p.ctl) stats[14] += bad;  // adaptive: the controller rejects the attempt instead
       stats[15] += 1;
+    }
+  }
+  // The step's last kernel refreshes the Krylov column shifts for the next
+  // step: D_i[a] becomes the Rayleigh quotient of column a of block i,
+  // (P_i* H P_i)_aa / (P_i* P_i)_aa = D_i[a] + Re (P_i* P_{i+1})_aa / (beta (P_i* P_i)_aa),
+  // so that the next blocks carry the part of H P_i that is new.  Only the
+  // conditioning of the stored blocks depends on the shifts, not the space.
+  const int last_kernel = (p.ctl && p.err_stage == p.s) ? p.s : p.s - 1;
+  if (j == last_kernel) {
+    const double2 *G = ws.gamma;
+    for (int e = threadIdx.x; e < (nb - 1) * r; e += NT) {
+      const int i = e / r, a = e % r;
+      const double gii = G[(i * r + a) * D + i * r + a].x;
+      const double gnext = G[(i * r + a) * D + (i + 1) * r + a].x;
+      const double dn = ws.shifts[e] + gnext / (p.beta * gii);
+      if (gii > 1e-280 && isfinite(dn)) ws.shifts[e] = dn;
     }
   }
 }
@@ -2545,7 +2562,7 @@ void launch_ab_cgs_coef(const double2 *c1g, int nU, int qx, int r, double2 *C, h
 
 // ---------------------------------------------------------------------------
 // Initial state from a non-orthogonal factor A (N x m): the run starts from
-// the partial eigendecomposition of rho_0 = A A* / Tr(A A*) (Sec. 3.6).  The
+// the partial eigendecomposition of rho_0 = A A* / Tr(A A*) (Sec. 3.7).  The
 // eigenpairs of rho_0 are those of the Gram matrix G = A* A (the same
 // nonzero eigenvalues times Tr), with eigenvectors A W diag(w)^{-1/2}.
 // ---------------------------------------------------------------------------

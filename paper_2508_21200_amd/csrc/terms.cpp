@@ -5,6 +5,7 @@
 // maps basis row x to rows x ^ mask with coefficients fixed by a few bits of
 // x.  Matrix elements used (basis |0> = up, |1> = down):
 //   <b| s^x |1-b> = 1,  <b| s^y |1-b> = -i (b = 0), +i (b = 1),  <b| s^z |b> = 1 - 2b.
+#include <algorithm>
 #include <cmath>
 #include <complex>
 #include <map>
@@ -128,6 +129,23 @@ bool build_terms(int n, int n_bonds, const int32_t *bond_ij, const double *bond_
     out.off.push_back(t);
   }
   out.gershgorin = bound;
+  // Tr(H^2) / N = mean over rows of d(x)^2 + sum_t |c_t(x)|^2.  Distinct
+  // z-strings (parities of bit sets {si, sj}) are orthogonal over the rows, so
+  // mean d^2 is the sum over distinct strings of their summed weight squared;
+  // a one-site term's coefficient takes its two diagonal entries with equal
+  // frequency, a two-site term's its four.
+  std::map<std::pair<uint32_t, uint32_t>, double> zw;
+  for (const auto &d : diag) {
+    const uint32_t a = std::min(d.si, d.sj), b = std::max(d.si, d.sj);
+    zw[{a, b}] += d.w;
+  }
+  double tr2 = 0.0;
+  for (const auto &kv : zw) tr2 += kv.second * kv.second;
+  for (const auto &t : out.off) {
+    auto m2 = [&](int q) { return t.re[q] * t.re[q] + t.im[q] * t.im[q]; };
+    tr2 += t.sa == t.sb ? 0.5 * (m2(0) + m2(3)) : 0.25 * (m2(0) + m2(1) + m2(2) + m2(3));
+  }
+  out.spread = std::sqrt(tr2);
   return true;
 }
 

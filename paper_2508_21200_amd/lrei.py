@@ -29,7 +29,8 @@ class lrei_options(ctypes.Structure):
                 ("eig_max_sweeps", ctypes.c_int), ("warm", ctypes.c_int),
                 ("ab_bootstrap", ctypes.c_int), ("householder_mode", ctypes.c_int),
                 ("use_graph", ctypes.c_int), ("deterministic", ctypes.c_int),
-                ("autotune_cache", ctypes.c_char_p), ("mixed_pivot_floor", ctypes.c_double)]
+                ("autotune_cache", ctypes.c_char_p), ("mixed_pivot_floor", ctypes.c_double),
+                ("fail_after_steps", ctypes.c_int)]
 
 
 class lrei_stats(ctypes.Structure):
@@ -170,12 +171,13 @@ class Context:
 
     def __init__(self, device=0, stream=None, precision="fp64", eig_tol=1e-15, eig_max_sweeps=40,
                  warm="analytic", householder_mode=0, use_graph=True, autotune_cache=None,
-                 mixed_pivot_floor=None):
+                 mixed_pivot_floor=None, fail_after_steps=0):
         self.lib = load()
         opt = lrei_options()
         self.lib.lrei_default_options(ctypes.byref(opt))
         if mixed_pivot_floor is not None:
             opt.mixed_pivot_floor = float(mixed_pivot_floor)
+        opt.fail_after_steps = int(fail_after_steps)
         opt.precision = PRECISIONS[precision]
         opt.eig_tol = eig_tol
         opt.eig_max_sweeps = eig_max_sweeps

@@ -31,3 +31,15 @@ extern "C" __attribute__((visibility("default"))) int terms_apply(int n, int nb,
   *bound = t.gershgorin;
   return 0;
 }
+
+// sqrt(Tr(H^2) / N) as the term table computes it (the scale of the Krylov
+// recurrence).
+extern "C" __attribute__((visibility("default"))) int terms_spread(int n, int nb, const int32_t *bonds,
+                                                                     const double *J, const double *h,
+                                                                     double *spread) {
+  lrei::TermTable t;
+  std::string err;
+  if (!lrei::build_terms(n, nb, bonds, J, h, t, err)) return 1;
+  *spread = t.spread;
+  return 0;
+}

@@ -1,0 +1,190 @@
+"""GPU parity for the benchmark's lattice family and for the numerical limits
+of the Krylov basis, through the C ABI against the CPU oracle.
+
+* The 4x4 periodic Heisenberg lattice (n = 16, r = 16, q-LL, kappa = 0.5,
+  RK4, dt = 0.01), the largest member of the benchmark's lattice family whose
+  oracle run takes seconds: mixed precision in the launch configuration the
+  benchmark times (autotuned H.V shape, captured step graph) and FP64, both
+  against the oracle element by element (1e-5 and 1e-10 relative Frobenius).
+* A tuned H.V shape never outlives the rank or precision it was chosen for.
+* A failing call after a mid-call FP64 promotion restores the state at the
+  start of the call.
+* FP64 accuracy where the Krylov blocks are nearly dependent: a state close to
+  an H-invariant subspace (rotated inside it), so that the Cholesky pivot
+  ratios of the Gram matrix of the blocks fall to ~eps^2.
+* The benchmark workload (n = 20) over 400 steps: the mixed path stays within
+  1e-5 of FP64 without leaving FP32 storage.
+"""
+import numpy as np
+import pytest
+
+from oracle.hamiltonian import Hamiltonian, apply_H, dense_H
+from oracle.schemes import run as oracle_run
+from oracle.metrics import rel_fro_error
+from workloads import make_config, haar_factor, dirichlet_spectrum
+
+pytestmark = pytest.mark.gpu
+
+
+def _ctx(precision="fp64", **kw):
+    from paper_2508_21200_amd import Context
+    return Context(device=0, precision=precision, **kw)
+
+
+@pytest.fixture(scope="module")
+def lattice16():
+    cfg = make_config(3, n=16, r=16)
+    assert cfg["n"] == 16 and cfg["bonds"].shape[0] == 32  # 4 x 4 periodic
+    H = Hamiltonian(cfg["n"], cfg["bonds"], cfg["J"], cfg["h"])
+    steps = 3
+    Vo = oracle_run(H, cfg["V"], cfg["lam"], cfg["model"], cfg["kappa"], cfg["dt"], steps, cfg["scheme"])
+    return cfg, steps, Vo
+
+
+@pytest.mark.parametrize("prec,tol", [("mixed", 1e-5), ("fp64", 1e-10)])
+def test_lattice_n16_r16_rk4_vs_oracle(lattice16, prec, tol):
+    cfg, steps, Vo = lattice16
+    c = _ctx(prec)
+    c.set_hamiltonian(cfg["n"], cfg["bonds"], cfg["J"], cfg["h"])
+    c.set_rho(cfg["lam"], cfg["V"])
+    tune = c.autotune() if prec == "mixed" else None
+    c.step(cfg["model"], cfg["scheme"], cfg["dt"], cfg["kappa"], steps)
+    err = rel_fro_error(c.get_rho()[1], cfg["lam"], Vo, cfg["lam"])
+    st = c.stats()
+    print(f"n=16 lattice r=16 {prec}: {err:.2e} vs oracle after {steps} RK4 steps; "
+          f"min pivot ratio {st['min_pivot_ratio']:.2e}"
+          + ("" if tune is None else f"; H.V shape epl={tune['epl']} grid={tune['grid']}"))
+    assert err < tol
+    c.close()
+
+
+def test_tuned_shape_follows_rank(tmp_path):
+    """A shape tuned (or read from the cache) for r = 16 in FP32 -- here eight
+    columns per lane, which no other rank below takes -- is dropped when the
+    rank changes: set_rho at r = 6 and r = 32 and an FP64 H X at r = 2 all run
+    and match the oracle."""
+    cfg = make_config(2, n=10, r=16)
+    H = Hamiltonian(cfg["n"], cfg["bonds"], cfg["J"], cfg["h"])
+    cache = tmp_path / "tune.txt"
+    c = _ctx("mixed", autotune_cache=cache)
+    c.set_hamiltonian(cfg["n"], cfg["bonds"], cfg["J"], cfg["h"])
+    c.set_rho(cfg["lam"], cfg["V"])
+    c.autotune()
+    c.close()
+    line = cache.read_text().strip().splitlines()[-1].split()
+    line[-4] = "8"  # columns per lane
+    cache.write_text(" ".join(line) + "\n")
+    c = _ctx("mixed", autotune_cache=cache)
+    c.set_hamiltonian(cfg["n"], cfg["bonds"], cfg["J"], cfg["h"])
+    c.set_rho(cfg["lam"], cfg["V"])
+    t = c.autotune()
+    assert t["from_cache"] == 1 and t["epl"] == 8
+    rng = np.random.default_rng(5)
+    for r in (6, 32):
+        lam = dirichlet_spectrum(r, rng)
+        V = haar_factor(2 ** cfg["n"], r, rng)
+        c.set_rho(lam, V)
+        c.step("qLLG", "RK4", 0.01, 0.05, 2)
+        Vo = oracle_run(H, V, lam, "qLLG", 0.05, 0.01, 2, "RK4")
+        assert rel_fro_error(c.get_rho()[1], lam, Vo, lam) < 1e-5, r
+    X = haar_factor(2 ** cfg["n"], 2, rng)
+    Y = c.apply_hamiltonian(X)
+    Yo = apply_H(cfg["n"], cfg["bonds"], cfg["J"], cfg["h"], X)
+    assert np.abs(Y - Yo).max() < 1e-12 * np.abs(Yo).max()
+    c.close()
+
+
+def test_promotion_then_failure_restores_start_of_call():
+    """A floor above every pivot ratio promotes a mixed context to FP64
+    storage after 16 steps of a 24-step call; the call is then made to fail
+    (fail_after_steps, the host-side stand-in for a non-finite step): the state
+    is the one at the start of the call (widened from FP32), not the one at the
+    promotion, and no step is counted."""
+    cfg = make_config(2, n=8, r=4)
+    c = _ctx("mixed", mixed_pivot_floor=1.0, fail_after_steps=24)
+    c.set_hamiltonian(cfg["n"], cfg["bonds"], cfg["J"], cfg["h"])
+    c.set_rho(cfg["lam"], cfg["V"])
+    from paper_2508_21200_amd.lrei import LreiError
+    with pytest.raises(LreiError) as ei:
+        c.step("qLLG", "RK4", 0.01, 0.05, 24)
+    assert ei.value.status == 6  # LREI_E_NUMERIC
+    st = c.stats()
+    assert st["precision_promoted"] == 1 and st["steps_done"] == 0
+    err0 = rel_fro_error(c.get_rho()[1], cfg["lam"], cfg["V"], cfg["lam"])
+    assert err0 < 1e-6  # the FP32 copy of the initial state
+    H = Hamiltonian(cfg["n"], cfg["bonds"], cfg["J"], cfg["h"])
+    V16 = oracle_run(H, cfg["V"], cfg["lam"], "qLLG", 0.05, 0.01, 16, "RK4")
+    assert rel_fro_error(c.get_rho()[1], cfg["lam"], V16, cfg["lam"]) > 1e-4  # not the promotion point
+    c.step("qLLG", "RK4", 0.01, 0.05, 3)  # the context works on (FP64 storage now)
+    V3 = oracle_run(H, cfg["V"], cfg["lam"], "qLLG", 0.05, 0.01, 3, "RK4")
+    assert rel_fro_error(c.get_rho()[1], cfg["lam"], V3, cfg["lam"]) < 1e-5
+    c.close()
+
+
+def _near_invariant_state(eps, seed=11):
+    """A rank-16 state on the 3 x 3 lattice whose support lies within eps of
+    the span of 16 eigenvectors of H, rotated by a random unitary inside it."""
+    cfg = make_config(3, n=9, r=16)
+    n = cfg["n"]
+    Hd = dense_H(n, cfg["bonds"], cfg["J"], cfg["h"])
+    w, Q = np.linalg.eigh(Hd)
+    rng = np.random.default_rng(seed)
+    U = haar_factor(16, 16, rng)
+    G = rng.normal(size=(2 ** n, 16)) + 1j * rng.normal(size=(2 ** n, 16))
+    V, _ = np.linalg.qr(Q[:, :16] @ U + eps * G / np.sqrt(2 * 2 ** n))
+    return cfg, V
+
+
+@pytest.mark.parametrize("eps", [1e-5, 1e-6, 1e-7, 3e-8, 1e-8, 1e-9, 0.0])
+def test_low_pivot_regime_fp64(eps):
+    """FP64 against the oracle while the Krylov directions beyond the support
+    are nearly dependent on it: the smallest Cholesky pivot ratio of the step
+    is ~300 eps^2 on this lattice.  Directions whose squared pivot ratio falls
+    below 1e-13 are dropped as dependent (some at eps = 3e-8, all such at
+    eps <= 1e-8, and exactly dependent ones at eps = 0); what they carried is
+    of order eps, so the result stays within max(1e-10, 10 eps) of the oracle."""
+    cfg, V = _near_invariant_state(eps)
+    H = Hamiltonian(cfg["n"], cfg["bonds"], cfg["J"], cfg["h"])
+    steps = 5
+    Vo = oracle_run(H, V, cfg["lam"], "qLL", 0.5, 0.01, steps, "RK4")
+    c = _ctx("fp64")
+    c.set_hamiltonian(cfg["n"], cfg["bonds"], cfg["J"], cfg["h"])
+    c.set_rho(cfg["lam"], V)
+    c.step("qLL", "RK4", 0.01, 0.5, steps)
+    st = c.stats()
+    err = rel_fro_error(c.get_rho()[1], cfg["lam"], Vo, cfg["lam"])
+    print(f"eps={eps:.0e}: min pivot ratio {st['min_pivot_ratio']:.2e}, dropped {st['dropped_directions']}, "
+          f"FP64 vs oracle {err:.2e}")
+    if eps >= 1e-7:
+        assert st["min_pivot_ratio"] < 1e3 * eps ** 2 and st["dropped_directions"] == 0
+    elif eps <= 1e-8:
+        assert st["dropped_directions"] > 0
+    # in between (eps = 3e-8) some directions fall on either side of the threshold
+    assert err < max(1e-10, 10 * eps)
+    c.close()
+
+
+def test_long_run_conditioning_n20():
+    """The benchmark workload (n = 20, r = 16) over 400 RK4 steps: the Krylov
+    blocks stay well conditioned (smallest pivot ratio of the last step far
+    above the FP32 floor), the mixed context never leaves FP32 storage, and it
+    stays within 1e-5 of the FP64 path."""
+    import torch
+    from tests_support_rel import rel_fro_gpu
+    cfg = make_config(3)
+    V0 = torch.from_numpy(cfg["V"]).cuda()
+    res = {}
+    for prec in ("fp64", "mixed"):
+        c = _ctx(prec)
+        c.set_hamiltonian(cfg["n"], cfg["bonds"], cfg["J"], cfg["h"])
+        c.set_rho(cfg["lam"], V0)
+        c.step("qLL", "RK4", 0.01, 0.5, 400)
+        res[prec] = (c.get_rho(torch.empty_like(V0))[1], c.stats())
+        c.close()
+    err = rel_fro_gpu(res["mixed"][0], res["fp64"][0], cfg["lam"])
+    piv = res["fp64"][1]["min_pivot_ratio"]
+    print(f"400 steps: mixed vs FP64 {err:.2e}; smallest pivot ratio of the last step {piv:.2e} (FP64), "
+          f"{res['mixed'][1]['min_pivot_ratio']:.2e} (mixed)")
+    assert res["mixed"][1]["precision_promoted"] == 0
+    assert piv > 1e-4
+    assert err < 1e-5

@@ -67,6 +67,36 @@ def test_term_table_benchmark_families(harness, k):
     np.testing.assert_allclose(Y, apply_H(cfg["n"], cfg["bonds"], cfg["J"], cfg["h"], V), atol=1e-13)
 
 
+@pytest.mark.parametrize("case", ["general", "heisenberg_lattice", "xxz_fields", "repeated_bond"])
+def test_term_table_spread_is_frobenius(harness, case):
+    """The scale of the Krylov recurrence, sqrt(Tr(H^2) / N), against the
+    Frobenius norm of the dense Kronecker Hamiltonian (a repeated bond and
+    one-site x, y, z fields included)."""
+    rng = np.random.default_rng(7)
+    if case == "general":
+        n = 6
+        bonds = chain_bonds(n, periodic=True)
+        J = rng.normal(size=(bonds.shape[0], 3, 3))
+        h = rng.normal(size=(n, 3))
+    elif case == "repeated_bond":
+        n = 5
+        bonds = np.concatenate([chain_bonds(n, periodic=False), [[0, 1], [1, 3]]]).astype(np.int32)
+        J = rng.normal(size=(bonds.shape[0], 3, 3))
+        h = rng.normal(size=(n, 3))
+    else:
+        cfg = make_config(3 if case == "heisenberg_lattice" else 2, n=9, r=1, with_state=False)
+        n, bonds, J, h = cfg["n"], cfg["bonds"], cfg["J"], cfg["h"]
+    bonds = np.ascontiguousarray(bonds, dtype=np.int32)
+    Jc = np.ascontiguousarray(J, dtype=np.float64)
+    hc = None if h is None else np.ascontiguousarray(h, dtype=np.float64)
+    sp = ctypes.c_double()
+    assert harness.terms_spread(n, bonds.shape[0], bonds.ctypes.data_as(ctypes.c_void_p),
+                                Jc.ctypes.data_as(ctypes.c_void_p),
+                                None if hc is None else hc.ctypes.data_as(ctypes.c_void_p), ctypes.byref(sp)) == 0
+    Hd = dense_H(n, bonds, J, h)
+    assert abs(sp.value - np.linalg.norm(Hd) / np.sqrt(2 ** n)) < 1e-12 * sp.value
+
+
 def test_library_exports_every_declared_symbol():
     header = open(os.path.join(ROOT, "include", "lrei.h")).read()
     declared = set(re.findall(r"LREI_API\s+[\w\s\*]+?\b(lrei_\w+)\s*\(", header))

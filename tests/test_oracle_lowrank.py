@@ -1,4 +1,4 @@
-"""Pins for stage matrices in low-rank form and the partial eigensolve (Sec. 3.6)."""
+"""Pins for stage matrices in low-rank form and the partial eigensolve (Sec. 3.7)."""
 import numpy as np
 import pytest
 

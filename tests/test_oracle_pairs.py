@@ -1,5 +1,5 @@
 """CPU pins of the two-spin reduced density matrix and its entanglement
-measures (oracle/observables.py, Sec. 3.5): brute-force partial trace of the
+measures (oracle/observables.py, Sec. 3.6): brute-force partial trace of the
 dense density matrix, product states, the singlet, Werner states (closed
 forms of concurrence and negativity) and Tsirelson's bound."""
 import numpy as np

@@ -27,7 +27,7 @@ def _full_basis(V, rng):
 @pytest.mark.parametrize("scheme", ["RK1", "RK2", "RK3", "RK4"])
 @pytest.mark.parametrize("model", ["qLL", "qLLG"])
 def test_lrei_rk_equals_dense_ei(scheme, model):
-    """LREI-RK reproduces the dense EI-RK iteration (Sec. 3.6: not an approximation)."""
+    """LREI-RK reproduces the dense EI-RK iteration (Sec. 3.7: not an approximation)."""
     rng = np.random.default_rng(11)
     n, r = 6, 3
     H = _random_H(n, rng)

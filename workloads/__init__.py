@@ -13,7 +13,7 @@ Conventions (shared by every consumer):
   J^{ab} = J delta_ab + eps_abc d_c and h = g mu_B b.
 * Site i is bit i of the basis index (least significant bit = site 0).
   Bit value 0 is spin up (s^z = +1).  The paper's Kronecker convention
-  (Sec. 3.5, eq. (3.5), site 1 leftmost) is the same basis up to this
+  (Sec. 3.6, eq. (3.5), site 1 leftmost) is the same basis up to this
   relabelling.
 * A factor V is an (N, r) complex array, row-major: the r columns of one
   basis state are contiguous.
