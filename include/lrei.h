@@ -248,6 +248,21 @@ LREI_API lrei_status lrei_get_stats(lrei_ctx *ctx, lrei_stats *stats);
  * sparsity of H"), in FP64. */
 LREI_API lrei_status lrei_apply_hamiltonian(lrei_ctx *ctx, int r, const void *X, void *Y, int is_device);
 
+/* Y = H X as lrei_apply_hamiltonian with device pointers, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): it allocates nothing and does not
+ * synchronise.  X and Y are device arrays of the caller (N x r complex128,
+ * natural site order, Y != X); the work is enqueued on the context's stream
+ * and Y is complete when that stream reaches this point (lrei_synchronize).
+ * The site-order copies of X and H X live in a static device array of
+ * 64 MiB per GPU, held until the process ends: 2 N r complex128 values must
+ * fit (N r <= 2^21), else LREI_E_INVALID.  Every call on one GPU uses the
+ * same array, so calls that overlap on one GPU (other streams, other
+ * contexts, other host threads) race; calls on one stream are ordered.
+ * Errors: LREI_E_STATE without a Hamiltonian, LREI_E_INVALID (r outside
+ * 1..32, null pointers, too large), LREI_E_DEVICE. */
+LREI_API lrei_status lrei_apply_hamiltonian_noalloc(lrei_ctx *ctx, int r, const void *X, void *Y);
+
 /* Checkpoint: the state (n, r, lambda, V, step counter, AB history) as an
  * opaque byte string.  With buf == NULL, *len receives the size needed. */
 LREI_API lrei_status lrei_get_state(lrei_ctx *ctx, void *buf, size_t *len);

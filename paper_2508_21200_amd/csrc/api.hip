@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -20,6 +21,33 @@ using namespace lrei;
 namespace {
 
 constexpr uint64_t kStateMagic = 0x4c52454953543031ull;  // "LREIST01"
+
+// Device scratch of lrei_apply_hamiltonian_noalloc: the input and the product
+// in the internal site order, 2 N r complex128 values at most.  Each GPU the
+// library runs on holds its own copy until the process ends; host code never
+// uses the array's name as an address, only the per-device address that
+// hipGetSymbolAddress returns (resolved when a context is created).
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+constexpr int kMaxDevices = 64;
+void *g_scratch_addr[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+// Resolves this device's address of the scratch array (hip_device current).
+hipError_t resolve_scratch(int hip_device) {
+  if (hip_device < 0 || hip_device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_addr[hip_device]) return hipSuccess;
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e == hipSuccess && ptr) g_scratch_addr[hip_device] = ptr;
+  return e == hipSuccess && !ptr ? hipErrorInvalidSymbol : e;
+}
 
 }  // namespace
 
@@ -813,6 +841,7 @@ lrei_status lrei_create(lrei_ctx **out, int hip_device, void *hip_stream, const 
   for (auto &e : ctx->ev_pass) ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
   for (auto &e : ctx->ev_basis) ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
   ok = ok && ctx->sched.ensure(16 * sizeof(int)) && hipMemset(ctx->sched.p, 0, 16 * sizeof(int)) == hipSuccess;
+  ok = ok && resolve_scratch(hip_device) == hipSuccess;
   if (!ok) {
     lrei_destroy(ctx);
     return LREI_E_DEVICE;
@@ -1528,6 +1557,51 @@ lrei_status lrei_get_stats(lrei_ctx *ctx, lrei_stats *s) {
   return LREI_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Y = H X on the context stream for device blocks in the natural site order:
+// X -> internal order (ta), H (FP64 pass, mode 2) into tb, back to the natural
+// order into Y (Y may alias ta).  Returns false if no launch shape fits r.
+bool enqueue_apply_h(lrei_ctx *ctx, int r, const void *X, void *Y, void *ta, void *tb) {
+  launch_permute(false, X, ta, ctx->N, r, ctx->site_pos.data(), ctx->n, false, ctx->stream);
+  HvArgs a{};
+  a.Pcur = ta;
+  a.Pnext = tb;
+  hv_args(ctx, a);
+  a.N = ctx->N;
+  a.r = r;
+  if (!hv_epl_valid(false, r, a.epl)) a.epl = 0;  // FP64 launch; the tuned shape may be FP32's
+  a.alpha = 1.0;
+  a.mode = 2;
+  a.grid = nspace_grid(ctx->N, r);
+  if (launch_hv(false, a, ctx->stream) <= 0) return false;
+  launch_permute(false, tb, Y, ctx->N, r, ctx->site_pos.data(), ctx->n, true, ctx->stream);
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+lrei_status lrei_apply_hamiltonian_noalloc(lrei_ctx *ctx, int r, const void *X, void *Y) {
+  if (!ctx) return LREI_E_INVALID;
+  if (!ctx->have_h) return ctx->fail(LREI_E_STATE, "no Hamiltonian");
+  if (r < 1 || r > kMaxR || !X || !Y) return ctx->fail(LREI_E_INVALID, "bad arguments");
+  const size_t bytes = (size_t)ctx->N * r * sizeof(double2);
+  if (2 * bytes > kScratchBytes)
+    return ctx->fail(LREI_E_INVALID, "N r = " + std::to_string(ctx->N * r) + " complex values exceed the " +
+                                         std::to_string(kScratchBytes / (2 * sizeof(double2))) +
+                                         " that the static scratch holds (2 N r complex128 <= 64 MiB)");
+  char *base = (char *)g_scratch_addr[ctx->device];  // resolved by lrei_create on this device
+  if (!base) return ctx->fail(LREI_E_DEVICE, "scratch address not resolved on this device");
+  HIPCHK(hipSetDevice(ctx->device));
+  if (!enqueue_apply_h(ctx, r, X, Y, base, base + bytes))
+    return ctx->fail(LREI_E_INVALID, "no H.V launch shape for this rank");
+  return check_hip(ctx, hipGetLastError(), "apply_hamiltonian_noalloc launch");
+}
+
 lrei_status lrei_apply_hamiltonian(lrei_ctx *ctx, int r, const void *X, void *Y, int is_device) {
   if (!ctx) return LREI_E_INVALID;
   if (!ctx->have_h) return ctx->fail(LREI_E_STATE, "no Hamiltonian");
@@ -1553,24 +1627,11 @@ lrei_status lrei_apply_hamiltonian(lrei_ctx *ctx, int r, const void *X, void *Y,
     }
     px = dx.p;
   }
-  // physical -> internal site order, H X, internal -> physical
-  launch_permute(false, px, dp.p, ctx->N, r, ctx->site_pos.data(), ctx->n, false, ctx->stream);
-  HvArgs a{};
-  a.Pcur = dp.p;
-  a.Pnext = dy.p;
-  hv_args(ctx, a);
-  a.N = ctx->N;
-  a.r = r;
-  if (!hv_epl_valid(false, r, a.epl)) a.epl = 0;  // FP64 launch; the tuned shape may be FP32's
-  a.alpha = 1.0;
-  a.mode = 2;
-  a.grid = nspace_grid(ctx->N, r);
-  if (launch_hv(false, a, ctx->stream) <= 0) {
+  void *py = is_device ? Y : dp.p;
+  if (!enqueue_apply_h(ctx, r, px, py, dp.p, dy.p)) {
     release_all();
     return ctx->fail(LREI_E_INVALID, "no H.V launch shape for this rank");
   }
-  void *py = is_device ? Y : dp.p;
-  launch_permute(false, dy.p, py, ctx->N, r, ctx->site_pos.data(), ctx->n, true, ctx->stream);
   lrei_status st = check_hip(ctx, hipGetLastError(), "apply_hamiltonian launch");
   if (st == LREI_OK && !is_device)
     st = check_hip(ctx, hipMemcpyAsync(Y, dp.p, bytes, hipMemcpyDeviceToHost, ctx->stream), "copy back");

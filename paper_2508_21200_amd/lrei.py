@@ -98,6 +98,7 @@ _SIGS = {
     "lrei_observables": (ctypes.c_int, [_P, _P, _P]),
     "lrei_get_stats": (ctypes.c_int, [_P, ctypes.POINTER(lrei_stats)]),
     "lrei_apply_hamiltonian": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.c_int]),
+    "lrei_apply_hamiltonian_noalloc": (ctypes.c_int, [_P, ctypes.c_int, _P, _P]),
     "lrei_get_state": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_size_t)]),
     "lrei_set_state": (ctypes.c_int, [_P, _P, ctypes.c_size_t]),
     "lrei_profile_kernels": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
@@ -286,6 +287,16 @@ class Context:
         py, _ = _ptr(out)
         self._check(self.lib.lrei_apply_hamiltonian(self.h, X.shape[1], px, py, dev))
         return out
+
+    def apply_hamiltonian_noalloc(self, X, Y):
+        """Y = H X into the caller's device tensors (complex128, N x r,
+        contiguous) without device allocation; enqueued on the context's
+        stream (call synchronize() before reading Y)."""
+        assert X.is_cuda and Y.is_cuda and X.is_contiguous() and Y.is_contiguous()
+        assert X.shape == Y.shape and X.dim() == 2
+        self._check(self.lib.lrei_apply_hamiltonian_noalloc(self.h, int(X.shape[1]), ctypes.c_void_p(X.data_ptr()),
+                                                             ctypes.c_void_p(Y.data_ptr())))
+        return Y
 
     def get_state(self):
         n = ctypes.c_size_t()
