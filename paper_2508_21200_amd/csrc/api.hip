@@ -102,8 +102,10 @@ struct lrei_ctx {
   bool fp32 = false;
   DevBuf blocks[kMaxStages + 1];
   DevBuf save;       // state at the start of a step call (rollback)
-  // LREI_MIXED: the state is the compensated pair blocks[0] + lo (both FP32)
+  // LREI_MIXED: the state is the compensated pair blocks[0] (FP32) + lo
+  // (bfloat16 pairs, 4 bytes per element)
   DevBuf lo, save_lo;
+  size_t lo_bytes() const { return (size_t)N * r * 4; }
   DevBuf partials;
   DevBuf ws_buf;
   DevBuf stats_buf;
@@ -173,7 +175,8 @@ lrei_status alloc_state(lrei_ctx *ctx, int r, bool fp32) {
   for (int i = 0; i <= kMaxStages; ++i)
     if (!ctx->blocks[i].ensure(blk)) return ctx->fail(LREI_E_NOMEM, "device allocation of Krylov blocks failed");
   if (!ctx->save.ensure(blk)) return ctx->fail(LREI_E_NOMEM, "device allocation failed");
-  if (fp32 && (!ctx->lo.ensure(blk) || !ctx->save_lo.ensure(blk)))
+  const size_t lob = (size_t)ctx->N * r * 4;  // bfloat16 (re, im) per element
+  if (fp32 && (!ctx->lo.ensure(lob) || !ctx->save_lo.ensure(lob)))
     return ctx->fail(LREI_E_NOMEM, "device allocation failed");
   if (!ctx->acc.ensure(blk)) return ctx->fail(LREI_E_NOMEM, "device allocation failed");
   ctx->grid = nspace_grid(ctx->N, r);
@@ -530,9 +533,9 @@ lrei_status promote_fp64(lrei_ctx *ctx) {
     (void)hipFree(wide);
     return ctx->fail(LREI_E_NOMEM, "device allocation for the FP64 promotion failed");
   }
-  launch_merge((const float2 *)ctx->blocks[0].p, (const float2 *)ctx->lo.p, (double2 *)wide, (long long)n,
+  launch_merge((const float2 *)ctx->blocks[0].p, ctx->lo.p, (double2 *)wide, (long long)n,
                ctx->stream);
-  launch_merge((const float2 *)ctx->save.p, (const float2 *)ctx->save_lo.p, (double2 *)wide_save, (long long)n,
+  launch_merge((const float2 *)ctx->save.p, ctx->save_lo.p, (double2 *)wide_save, (long long)n,
                ctx->stream);  // the start-of-call state
   hipError_t e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) {
@@ -769,7 +772,7 @@ void enqueue_ab_step(lrei_ctx *ctx) {
     ab_update(ctx, {ctx->blocks[1].p}, p);
     // the AB step writes the new state in the storage precision only: the
     // compensation of a mixed state restarts at zero (AB steps are never captured)
-    if (ctx->fp32) (void)hipMemsetAsync(ctx->lo.p, 0, (size_t)ctx->N * ctx->r * sizeof(float2), ctx->stream);
+    if (ctx->fp32) (void)hipMemsetAsync(ctx->lo.p, 0, ctx->lo_bytes(), ctx->stream);
   }
   ab.count += 1;
 }
@@ -1020,7 +1023,8 @@ lrei_status lrei_set_rho(lrei_ctx *ctx, int r, const double *lambda, const void 
   if (!tv.ensure(vbytes) || !tp.ensure(vbytes) ||
       !tpart.ensure((size_t)grid * hv_partial_splits(r) * 3 * r * r * sizeof(double2)) ||
       !tmeas.ensure(3 * (size_t)r * r * sizeof(double2)) ||
-      (ctx->fp32 && (!tw.ensure(n64) || !tlo.ensure(vbytes) || (!v_is_device && !tstage.ensure(n64))))) {
+      (ctx->fp32 && (!tw.ensure(n64) || !tlo.ensure((size_t)ctx->N * r * 4) ||
+                     (!v_is_device && !tstage.ensure(n64))))) {
     release_tmp();
     return ctx->fail(LREI_E_NOMEM, "device allocation failed");
   }
@@ -1040,7 +1044,7 @@ lrei_status lrei_set_rho(lrei_ctx *ctx, int r, const double *lambda, const void 
       }
       if (e1 == hipSuccess) {
         launch_permute(false, src, tw.p, ctx->N, r, ctx->site_pos.data(), ctx->n, false, ctx->stream);
-        launch_split((const double2 *)tw.p, (float2 *)tp.p, (float2 *)tlo.p, (long long)n, ctx->stream);
+        launch_split((const double2 *)tw.p, (float2 *)tp.p, tlo.p, (long long)n, ctx->stream);
       }
     }
     if (e1 != hipSuccess) {
@@ -1099,7 +1103,7 @@ lrei_status lrei_set_rho(lrei_ctx *ctx, int r, const double *lambda, const void 
   if (e2 == hipSuccess) e2 = hipStreamSynchronize(ctx->stream);  // sh0 is host stack memory
   if (e2 == hipSuccess) e2 = hipMemcpyAsync(ctx->blocks[0].p, tp.p, vbytes, hipMemcpyDeviceToDevice, ctx->stream);
   if (e2 == hipSuccess && ctx->fp32)
-    e2 = hipMemcpyAsync(ctx->lo.p, tlo.p, vbytes, hipMemcpyDeviceToDevice, ctx->stream);
+    e2 = hipMemcpyAsync(ctx->lo.p, tlo.p, (size_t)ctx->N * r * 4, hipMemcpyDeviceToDevice, ctx->stream);
   if (e2 == hipSuccess) e2 = hipGetLastError();
   if (e2 == hipSuccess) e2 = hipStreamSynchronize(ctx->stream);
   release_tmp();
@@ -1155,7 +1159,7 @@ lrei_status lrei_step(lrei_ctx *ctx, int model, int scheme, double dt, double ka
   const auto t0 = std::chrono::steady_clock::now();
   const size_t vbytes = (size_t)ctx->N * ctx->r * ctx->elem();
   HIPCHK(hipMemcpyAsync(ctx->save.p, ctx->blocks[0].p, vbytes, hipMemcpyDeviceToDevice, ctx->stream));
-  if (ctx->fp32) HIPCHK(hipMemcpyAsync(ctx->save_lo.p, ctx->lo.p, vbytes, hipMemcpyDeviceToDevice, ctx->stream));
+  if (ctx->fp32) HIPCHK(hipMemcpyAsync(ctx->save_lo.p, ctx->lo.p, ctx->lo_bytes(), hipMemcpyDeviceToDevice, ctx->stream));
   double zeros[kStatsLen] = {0};
   HIPCHK(hipMemcpyAsync(ctx->stats_buf.p, zeros, sizeof(zeros), hipMemcpyHostToDevice, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -1196,8 +1200,7 @@ lrei_status lrei_step(lrei_ctx *ctx, int model, int scheme, double dt, double ka
     HIPCHK(hipMemcpyAsync(ctx->blocks[0].p, ctx->save.p, (size_t)ctx->N * ctx->r * ctx->elem(),
                           hipMemcpyDeviceToDevice, ctx->stream));
     if (ctx->fp32)
-      HIPCHK(hipMemcpyAsync(ctx->lo.p, ctx->save_lo.p, (size_t)ctx->N * ctx->r * ctx->elem(),
-                            hipMemcpyDeviceToDevice, ctx->stream));
+      HIPCHK(hipMemcpyAsync(ctx->lo.p, ctx->save_lo.p, ctx->lo_bytes(), hipMemcpyDeviceToDevice, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     if (ctx->hv_launch_failed) {
       ctx->hv_launch_failed = false;
@@ -1256,7 +1259,7 @@ lrei_status lrei_evolve_adaptive(lrei_ctx *ctx, int model, int pair, double kapp
   const auto t0 = std::chrono::steady_clock::now();
   const size_t vbytes = (size_t)ctx->N * ctx->r * ctx->elem();
   HIPCHK(hipMemcpyAsync(ctx->save.p, ctx->blocks[0].p, vbytes, hipMemcpyDeviceToDevice, ctx->stream));
-  if (ctx->fp32) HIPCHK(hipMemcpyAsync(ctx->save_lo.p, ctx->lo.p, vbytes, hipMemcpyDeviceToDevice, ctx->stream));
+  if (ctx->fp32) HIPCHK(hipMemcpyAsync(ctx->save_lo.p, ctx->lo.p, ctx->lo_bytes(), hipMemcpyDeviceToDevice, ctx->stream));
   double zeros[kStatsLen] = {0};
   HIPCHK(hipMemcpyAsync(ctx->stats_buf.p, zeros, sizeof(zeros), hipMemcpyHostToDevice, ctx->stream));
   double c[kCtlLen] = {0};
@@ -1339,8 +1342,7 @@ lrei_status lrei_evolve_adaptive(lrei_ctx *ctx, int model, int pair, double kapp
     HIPCHK(hipMemcpyAsync(ctx->blocks[0].p, ctx->save.p, (size_t)ctx->N * ctx->r * ctx->elem(),
                           hipMemcpyDeviceToDevice, ctx->stream));
     if (ctx->fp32)
-      HIPCHK(hipMemcpyAsync(ctx->lo.p, ctx->save_lo.p, (size_t)ctx->N * ctx->r * ctx->elem(),
-                            hipMemcpyDeviceToDevice, ctx->stream));
+      HIPCHK(hipMemcpyAsync(ctx->lo.p, ctx->save_lo.p, ctx->lo_bytes(), hipMemcpyDeviceToDevice, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return ctx->fail(LREI_E_INVALID,
                      "an H.V pass could not be launched for this rank; state restored to the start of the call");
@@ -1401,7 +1403,7 @@ lrei_status lrei_get_rho(lrei_ctx *ctx, double *lambda, void *V, int v_is_device
   DevBuf w64, p64;
   if (!w64.ensure(n * sizeof(double2)) || (!v_is_device && !p64.ensure(n * sizeof(double2))))
     return ctx->fail(LREI_E_NOMEM, "allocation failed");
-  launch_merge((const float2 *)ctx->blocks[0].p, (const float2 *)ctx->lo.p, (double2 *)w64.p, (long long)n,
+  launch_merge((const float2 *)ctx->blocks[0].p, ctx->lo.p, (double2 *)w64.p, (long long)n,
                ctx->stream);
   void *dst = v_is_device ? V : p64.p;
   launch_permute(false, w64.p, dst, ctx->N, ctx->r, ctx->site_pos.data(), ctx->n, true, ctx->stream);

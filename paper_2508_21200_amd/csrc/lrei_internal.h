@@ -129,8 +129,9 @@ struct CombineArgs {
   int r, grid;
   const double *skip;  // nothing is written while *skip != 0 (nullptr: always runs)
   // compensated FP32 state (FP32 blocks only; nullptr: plain): the state is
-  // blocks[0] + lo_in; the kernel forms blocks[0] + lo_in + [B_0..B_{nb-1}] (C - [I; 0])
-  // and writes it split again as out + lo_out
+  // blocks[0] + lo_in (lo as bfloat16 pairs); the kernel forms
+  // blocks[0] + lo_in + [B_0..B_{nb-1}] (C - [I; 0]) in FP64 and writes it split
+  // again as out + lo_out
   const void *lo_in;
   void *lo_out;
 };
@@ -144,9 +145,10 @@ struct ReduceJob {
   double2 *out;
 };
 void launch_reduce_batch(const BatchLaunch &b, int total_wg, hipStream_t s);
-// Compensated FP32 pairs: hi = fl32(v), lo = fl32(v - hi) (split); v = hi + lo (merge).
-void launch_split(const double2 *src, float2 *hi, float2 *lo, long long n, hipStream_t s);
-void launch_merge(const float2 *hi, const float2 *lo, double2 *dst, long long n, hipStream_t s);
+// Compensated FP32 state: hi = fl32(v), lo = bf16(v - hi) as (re, im) pairs of
+// uint16 (split); v = hi + lo (merge).  hi + lo holds v to ~2^-33 relative.
+void launch_split(const double2 *src, float2 *hi, void *lo, long long n, hipStream_t s);
+void launch_merge(const float2 *hi, const void *lo, double2 *dst, long long n, hipStream_t s);
 void launch_diag_values(const DevDiagTerm *diag, int n_diag, long long N, double *d64, float *d32, hipStream_t s);
 int hv_elems_per_lane(bool fp32, int r);
 void launch_combine(bool fp32, const void *const *blocks, int nblocks, const double2 *C, void *out,

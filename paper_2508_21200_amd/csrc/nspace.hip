@@ -37,6 +37,15 @@ __host__ __device__ inline int pow2ceil(int v) {
 }
 __host__ __device__ inline int pad16(int v) { return (v + 15) & ~15; }
 
+// bfloat16 (the upper half of an IEEE float) for the low part of a
+// compensated state: round to nearest even on the way in (finite values).
+__device__ inline uint16_t to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ inline float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
 // 16x16x4 MFMA wrappers.  Operand lanes: A[i][k] in lane i + 16k, B[k][j] in
 // lane j + 16k.  Result D[i][j] sits in lane j + 16g, register v, with
 // i = 4v + g for f64 and i = 4g + v for f32 (measured on gfx950).
@@ -614,17 +623,15 @@ __device__ __forceinline__ void combine_body(const CombineArgs &a, int wg, unsig
           if constexpr (sizeof(T) == 4) {
             if (a.lo_in) {
               // hi + lo + update in FP64, split again (this wave read row xo of
-              // blocks[0] above; out may be blocks[0])
-              const T *hi = reinterpret_cast<const T *>(a.blocks[0]);
-              const T *lo = reinterpret_cast<const T *>(a.lo_in);
-              const double vr = (double)hi[o] + (double)lo[o] + (double)ore[tb][v];
-              const double vi = (double)hi[o + 1] + (double)lo[o + 1] + (double)oim[tb][v];
+              // blocks[0] above; out may be blocks[0]); lo is bfloat16
+              const float2 h = *reinterpret_cast<const float2 *>(reinterpret_cast<const T *>(a.blocks[0]) + o);
+              const ushort2 l = reinterpret_cast<const ushort2 *>(a.lo_in)[o / 2];
+              const double vr = (double)h.x + (double)from_bf16(l.x) + (double)ore[tb][v];
+              const double vi = (double)h.y + (double)from_bf16(l.y) + (double)oim[tb][v];
               const float hr = (float)vr, hm = (float)vi;
-              out[o] = hr;
-              out[o + 1] = hm;
-              T *lw = reinterpret_cast<T *>(a.lo_out);
-              lw[o] = (float)(vr - (double)hr);
-              lw[o + 1] = (float)(vi - (double)hm);
+              *reinterpret_cast<float2 *>(out + o) = make_float2(hr, hm);
+              reinterpret_cast<ushort2 *>(a.lo_out)[o / 2] =
+                  make_ushort2(to_bf16((float)(vr - (double)hr)), to_bf16((float)(vi - (double)hm)));
               continue;
             }
           }
@@ -715,19 +722,19 @@ __global__ void k_convert_d2f(const double2 *src, float2 *dst, long long n) {
        i += (long long)gridDim.x * blockDim.x)
     dst[i] = make_float2((float)src[i].x, (float)src[i].y);
 }
-__global__ void k_split_d2f(const double2 *src, float2 *hi, float2 *lo, long long n) {
+__global__ void k_split_d2f(const double2 *src, float2 *hi, ushort2 *lo, long long n) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
     const double2 v = src[i];
     const float2 h = make_float2((float)v.x, (float)v.y);
     hi[i] = h;
-    lo[i] = make_float2((float)(v.x - (double)h.x), (float)(v.y - (double)h.y));
+    lo[i] = make_ushort2(to_bf16((float)(v.x - (double)h.x)), to_bf16((float)(v.y - (double)h.y)));
   }
 }
-__global__ void k_merge_f2d(const float2 *hi, const float2 *lo, double2 *dst, long long n) {
+__global__ void k_merge_f2d(const float2 *hi, const ushort2 *lo, double2 *dst, long long n) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
-    dst[i] = make_double2((double)hi[i].x + (double)lo[i].x, (double)hi[i].y + (double)lo[i].y);
+    dst[i] = make_double2((double)hi[i].x + (double)from_bf16(lo[i].x), (double)hi[i].y + (double)from_bf16(lo[i].y));
 }
 __global__ void k_convert_f2d(const float2 *src, double2 *dst, long long n) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
@@ -1132,14 +1139,14 @@ void launch_reduce(const double2 *partials, int count, int len, double2 *out, hi
   hipLaunchKernelGGL(k_reduce, dim3(len), dim3(256), 0, s, partials, count, len, out);
 }
 
-void launch_split(const double2 *src, float2 *hi, float2 *lo, long long n, hipStream_t s) {
+void launch_split(const double2 *src, float2 *hi, void *lo, long long n, hipStream_t s) {
   const long long blocks = std::max<long long>(1, std::min<long long>(4096, (n + 255) / 256));
-  hipLaunchKernelGGL(k_split_d2f, dim3((unsigned)blocks), dim3(256), 0, s, src, hi, lo, n);
+  hipLaunchKernelGGL(k_split_d2f, dim3((unsigned)blocks), dim3(256), 0, s, src, hi, (ushort2 *)lo, n);
 }
 
-void launch_merge(const float2 *hi, const float2 *lo, double2 *dst, long long n, hipStream_t s) {
+void launch_merge(const float2 *hi, const void *lo, double2 *dst, long long n, hipStream_t s) {
   const long long blocks = std::max<long long>(1, std::min<long long>(4096, (n + 255) / 256));
-  hipLaunchKernelGGL(k_merge_f2d, dim3((unsigned)blocks), dim3(256), 0, s, hi, lo, dst, n);
+  hipLaunchKernelGGL(k_merge_f2d, dim3((unsigned)blocks), dim3(256), 0, s, hi, (const ushort2 *)lo, dst, n);
 }
 
 void launch_convert(bool to_fp32, const void *src, void *dst, long long n, hipStream_t s) {
