@@ -754,7 +754,7 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "traffic_over_algorithmic": None if traffic is None else round(traffic / hv_bytes, 3),
-                "kernel": "k_hv (H.V Krylov pass, fused Grams)",
+                "kernel": "k_hv_tile" if (tuning or {}).get("tile_bits") else "k_hv",
                 "algorithmic_bytes_per_launch": hv_bytes,
                 "algorithmic_model": "2F per pass, F = N r c (read P_j, write P_{j+1})",
                 "measured_copy_peak": copy, "frac_of_copy_peak": round(achieved / copy["GBs"], 4)}
@@ -829,9 +829,10 @@ def main():
         "kernels_ms": {k: round(v, 5) for k, v in kms.items()},
         "pair_density": pair_obs,
         "hv_tuning": None if tuning is None else {
-            "epl": tuning["epl"], "grid": tuning["grid"], "win_bits": tuning["win_bits"],
-            "n_sweeps": tuning["n_sweeps"], "ms": round(tuning["ms"], 5),
-            "tried": [[e, g, w, round(t, 5)] for e, g, w, t in tuning["tried"]]},
+            "epl": tuning["epl"], "grid": tuning["grid"], "tile_bits": tuning["tile_bits"],
+            "tile_waves": tuning["tile_waves"], "ms": round(tuning["ms"], 5),
+            "tried": [[e, g, tile, round(t, 5)] for (e, g, w, t), tile in zip(tuning["tried"], tuning["tried_tile"])],
+            "tried_fields": "columns per lane, workgroups, 100 tile_bits + waves (0: untiled), ms"},
         "eig_stats": {k: stats[k] for k in ("eigensolves", "warm_accepted", "warm_rejected", "warm_iterations",
                                             "dropped_directions", "min_pivot_ratio", "ortho_error")},
         "projected_phase_ms_per_step": dict(zip(

@@ -127,6 +127,13 @@ typedef struct {
                              call with n_steps >= k run its steps and then fail as a
                              non-finite step does (LREI_E_NUMERIC, state restored to
                              the start of the call).  Default 0 (off)                */
+  int site_order;         /* the site -> row-bit order of the internal storage:
+                             0 (default) the order that keeps the bonds of the three
+                             top-bit sites (which pick the XCD a row block runs on)
+                             few and puts their neighbours in the low bits; 1 the
+                             10-site cluster with the most bonds inside it in the low
+                             bits, for the tiled H.V pass (LDS tiles of up to 2^10
+                             rows).  Results are unaffected; only speed changes    */
 } lrei_options;
 
 typedef struct {
@@ -294,6 +301,10 @@ typedef struct {
   int n_tried;             /* variants timed (at most 64)                                */
   int tried_epl[64], tried_grid[64], tried_win[64];
   double tried_ms[64];
+  int tile_bits;           /* tiled pass: 2^tile_bits rows of P held in LDS per workgroup
+                              (0: the untiled pass)                                      */
+  int tile_waves;          /* tiled pass: waves per workgroup (8 or 16)                  */
+  int tried_tile[64];      /* per variant: 100 tile_bits + tile_waves, 0 if untiled      */
 } lrei_tune_result;
 
 /* Chooses the launch shape of the matrix-free H.V pass (eq. 5.1 applied in

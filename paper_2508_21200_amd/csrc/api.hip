@@ -73,6 +73,8 @@ struct lrei_ctx {
   DevTerms dt;                    // device term tables and d(x) per row
   int epl = 0;                    // H.V columns per lane (0: default)
   int hv_grid = 0;                // H.V workgroups per launch (0: default)
+  int hv_tile_bits = 0;           // tiled pass: 2^bits rows per LDS tile (0: untiled)
+  int hv_tile_waves = 16;         // tiled pass: waves per workgroup
   // H.V sweep plan: each sweep applies the terms whose flip masks lie in its
   // window of row bits (one sweep = all bits, all terms)
   struct HvSweep {
@@ -217,6 +219,16 @@ lrei_status alloc_state(lrei_ctx *ctx, int r, bool fp32) {
 // order one.  The space spanned does not depend on it.
 double krylov_beta(const lrei_ctx *ctx) { return ctx->terms.spread > 0 ? 1.0 / ctx->terms.spread : 1.0; }
 
+// Off-diagonal terms that flip only bits below k (a prefix of the table,
+// which is sorted by the highest bit a term flips).
+int local_terms(const lrei_ctx *ctx, int k) {
+  int c = 0;
+  for (const auto &t : ctx->terms.off)
+    if ((t.mask >> k) == 0) ++c;
+    else break;
+  return c;
+}
+
 // Hamiltonian tables of an H.V pass.
 void hv_args(lrei_ctx *ctx, HvArgs &a) {
   a.terms64 = (const DevTerm<double> *)ctx->dt.off64.p;
@@ -253,6 +265,11 @@ int hv_launches(lrei_ctx *ctx, int r, int grid, int mode, const void *cur, void 
   a.skip = ctx->pass_skip;
   const size_t ns = ctx->sweeps.size();
   int slots = 0;
+  if (mode != 2 && ns <= 1 && ctx->hv_tile_bits > 0) {  // the tiled pass
+    a.tile_bits = ctx->hv_tile_bits;
+    a.tile_waves = ctx->hv_tile_waves;
+    a.n_local = local_terms(ctx, ctx->hv_tile_bits);
+  }
   if (!sweeps || ns <= 1) {
     slots = launch_hv(ctx->fp32, a, ctx->stream);
   } else {
@@ -290,6 +307,7 @@ bool hv_pass_into(lrei_ctx *ctx, int r, int grid, int mode, const void *cur, voi
 void reset_hv_tuning(lrei_ctx *ctx) {
   ctx->epl = 0;
   ctx->hv_grid = 0;
+  ctx->hv_tile_bits = 0;
   ctx->drop_graph();
 }
 
@@ -548,6 +566,7 @@ lrei_status promote_fp64(lrei_ctx *ctx) {
   ctx->fp32 = false;
   ctx->epl = 0;
   ctx->hv_grid = 0;
+  ctx->hv_tile_bits = 0;
   lrei_status st = alloc_state(ctx, ctx->r, false);
   if (st == LREI_OK) {
     e = hipMemcpyAsync(ctx->blocks[0].p, wide, n * sizeof(double2), hipMemcpyDeviceToDevice, ctx->stream);
@@ -801,6 +820,7 @@ void lrei_default_options(lrei_options *o) {
   o->autotune_cache = nullptr;
   o->mixed_pivot_floor = 2e-6;
   o->fail_after_steps = 0;
+  o->site_order = 0;
 }
 
 lrei_status lrei_create(lrei_ctx **out, int hip_device, void *hip_stream, const lrei_options *opt) {
@@ -817,6 +837,10 @@ lrei_status lrei_create(lrei_ctx **out, int hip_device, void *hip_stream, const 
     return LREI_E_INVALID;
   }
   if (!(ctx->opt.mixed_pivot_floor >= 0) || !std::isfinite(ctx->opt.mixed_pivot_floor)) {
+    delete ctx;
+    return LREI_E_INVALID;
+  }
+  if (ctx->opt.site_order != 0 && ctx->opt.site_order != 1) {
     delete ctx;
     return LREI_E_INVALID;
   }
@@ -943,7 +967,9 @@ lrei_status lrei_set_hamiltonian(lrei_ctx *ctx, int n_spins, int n_bonds, const 
   if (ctx->have_rho && n_spins != ctx->n)
     return ctx->fail(LREI_E_STATE, "n_spins differs from the current state; set a new rho after changing n");
   // terms in the internal site order
-  const std::vector<int> pos = choose_site_order(n_spins, n_bonds, bond_ij);
+  const std::vector<int> pos = ctx->opt.site_order == 1
+                                   ? choose_site_order_cluster(n_spins, n_bonds, bond_ij, kClusterBits)
+                                   : choose_site_order(n_spins, n_bonds, bond_ij);
   // a bond whose sites swap order gets the transposed tensor (J^{ab} s^a_i s^b_j)
   std::vector<int32_t> pbonds(2 * (size_t)n_bonds);
   std::vector<double> pJ(bond_J ? bond_J : (const double *)nullptr, bond_J ? bond_J + 9 * (size_t)n_bonds : nullptr);
@@ -967,6 +993,11 @@ lrei_status lrei_set_hamiltonian(lrei_ctx *ctx, int n_spins, int n_bonds, const 
   std::string e;
   if (!build_terms(n_spins, n_bonds, pbonds.data(), pJ.data(), site_h ? ph.data() : nullptr, t, e))
     return ctx->fail(LREI_E_INVALID, e);
+  // terms by the highest row bit they flip: for any tile of 2^k rows the
+  // terms that stay inside it are a prefix of the table
+  std::stable_sort(t.off.begin(), t.off.end(), [](const OffTerm &x, const OffTerm &y) {
+    return 31 - __builtin_clz(x.mask) < 31 - __builtin_clz(y.mask);
+  });
   HIPCHK(hipSetDevice(ctx->device));
   DevTerms dt;
   const lrei_status ust = upload_terms(t, 1LL << n_spins, ctx->stream, dt, e);
@@ -983,6 +1014,8 @@ lrei_status lrei_set_hamiltonian(lrei_ctx *ctx, int n_spins, int n_bonds, const 
     launch_permute(ctx->fp32, ctx->blocks[0].p, ctx->acc.p, ctx->N, ctx->r, ctx->site_pos.data(), n_spins, true,
                    ctx->stream);
     launch_permute(ctx->fp32, ctx->acc.p, ctx->blocks[0].p, ctx->N, ctx->r, pos.data(), n_spins, false, ctx->stream);
+    // the low part of a compensated state is not moved: it restarts at zero
+    if (ctx->fp32) HIPCHK(hipMemsetAsync(ctx->lo.p, 0, ctx->lo_bytes(), ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     ab_reset(ctx);
   }
@@ -1853,19 +1886,28 @@ lrei_status lrei_autotune(lrei_ctx *ctx, lrei_tune_result *out) {
   lrei_tune_result res{};
   const std::string key = tune_key(ctx);
   const char *cache = ctx->opt.autotune_cache;
+  const int r = ctx->r;
+  auto tile_valid = [&](int e, int g, int tile) {
+    if (tile == 0) return true;
+    const int tb = tile / 100, tw = tile % 100;
+    return hv_tile_ok(ctx->fp32, r, e, tb, tw, ctx->N, g);
+  };
   if (cache) {
     if (FILE *f = std::fopen(cache, "r")) {
       char line[512];
       while (std::fgets(line, sizeof(line), f)) {
         const std::string l(line);
         if (l.compare(0, key.size(), key) != 0 || l.size() <= key.size() || l[key.size()] != ' ') continue;
-        int e = 0, g = 0, w = 0;
+        int e = 0, g = 0, w = 0, tile = 0;
         double ms = 0;
-        if (std::sscanf(l.c_str() + key.size(), " %d %d %d %lf", &e, &g, &w, &ms) == 4 && e > 0 &&
-            hv_epl_valid(ctx->fp32, ctx->r, e) && g > 0 && g <= kMaxHvGrid && w >= 0 && w < ctx->n) {
+        if (std::sscanf(l.c_str() + key.size(), " %d %d %d %d %lf", &e, &g, &w, &tile, &ms) == 5 && e > 0 &&
+            hv_epl_valid(ctx->fp32, r, e) && g > 0 && g <= kMaxHvGrid && w >= 0 && w < ctx->n && tile >= 0 &&
+            (tile == 0 || w == 0) && tile_valid(e, g, tile)) {
           res.epl = e;
           res.grid = g;
           res.win_bits = w;
+          res.tile_bits = tile / 100;
+          res.tile_waves = tile % 100;
           res.ms = ms;
           res.from_cache = 1;
         }
@@ -1874,79 +1916,94 @@ lrei_status lrei_autotune(lrei_ctx *ctx, lrei_tune_result *out) {
     }
   }
   if (!res.from_cache) {
-    const int r = ctx->r;
+    // candidates (epl, grid, window, tile = 100 tile_bits + waves): the untiled
+    // pass over columns per lane and grids, and the tiled pass over columns per
+    // lane, waves, the three largest tiles that fit LDS and one or two
+    // workgroups per CU
+    struct Cand { int e, g, w, tile; };
+    std::vector<Cand> cands;
     std::vector<int> epls;
     for (int e : {1, 2, 4, 8}) {
       if (!hv_epl_valid(ctx->fp32, r, e)) continue;
       if (r > 16 && e != hv_elems_per_lane(ctx->fp32, r)) continue;
       epls.push_back(e);
     }
-    const long long tiles = (ctx->N + 63) / 64;
-    std::vector<int> grids;
-    for (int g : {256, 512, 768, 1024, 1280, 1536, 2048})
-      if (g <= tiles && g <= kMaxHvGrid) grids.push_back(g);
-    if (grids.empty()) grids.push_back(nspace_grid(ctx->N, r));
-    // window sizes: one sweep, and windows small enough to leave room in an XCD's L2
-    std::vector<int> wins = {0};
-    for (int w : {16, 15, 14, 13})
-      if (w < ctx->n && ctx->n - w >= 3) wins.push_back(w);
-    // valid data in the pass inputs: P = P- = the current state
+    const long long tiles64 = (ctx->N + 63) / 64;
+    for (int e : epls)
+      for (int g : {256, 512, 768, 1024, 1280, 1536, 2048})
+        if (g <= tiles64 && g <= kMaxHvGrid) cands.push_back({e, g, 0, 0});
+    if (cands.empty())
+      for (int e : epls) cands.push_back({e, nspace_grid(ctx->N, r), 0, 0});
+    for (int e : epls)
+      for (int waves : {16, 8}) {
+        int kmax = 0;
+        for (int kb = 4; kb <= ctx->n; ++kb)
+          if (hv_tile_ok(ctx->fp32, r, e, kb, waves, ctx->N, 8)) kmax = kb;
+        for (int kb = kmax; kb >= 4 && kb > kmax - 3; --kb) {
+          const long long ntile = ctx->N >> kb;  // small problems: one workgroup per tile
+          for (int g : {256, 512, (int)std::min<long long>(ntile, 255)})
+            if (hv_tile_ok(ctx->fp32, r, e, kb, waves, ctx->N, g) &&
+                (g <= 256 || 2 * hv_tile_lds(ctx->fp32, r, e, kb, waves) <= (size_t)kMaxTileLds))
+              cands.push_back({e, g, 0, 100 * kb + waves});
+        }
+      }
+    // valid data in the pass input: the current state
     const size_t vbytes = (size_t)ctx->N * r * ctx->elem();
     HIPCHK(hipMemcpyAsync(ctx->blocks[1].p, ctx->blocks[0].p, vbytes, hipMemcpyDeviceToDevice, ctx->stream));
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     double best = 1e300;
-    for (int w : wins) {
-      lrei_status st = hv_set_plan(ctx, w);
-      if (st != LREI_OK) continue;
-      const int ns = (int)ctx->sweeps.size();
-      for (int e : epls)
-        for (int g : grids) {
-          if (ns > 1 && g != 768 && g != 1536) continue;
-          ctx->epl = e;
-          const int iters = 5;
-          bool launched = true;
-          auto pass = [&]() {
-            launched = hv_pass_into(ctx, r, g, 1, ctx->blocks[1].p, ctx->blocks[4].p,
-                                      (double2 *)ctx->partials.p, ctx->ws.work, true, kMaxHvGrid,
-                                      ctx->ws.shifts + r) && launched;
-          };
-          pass();
-          if (!launched) {
-            ctx->hv_launch_failed = false;
-            continue;
-          }
-          (void)hipEventRecord(e0, ctx->stream);
-          for (int k = 0; k < iters; ++k) pass();
-          (void)hipEventRecord(e1, ctx->stream);
-          HIPCHK(hipEventSynchronize(e1));
-          HIPCHK(hipGetLastError());
-          float t = 0;
-          (void)hipEventElapsedTime(&t, e0, e1);
-          const double ms = (double)t / iters;
-          if (res.n_tried < 64) {
-            res.tried_epl[res.n_tried] = e;
-            res.tried_grid[res.n_tried] = g;
-            res.tried_win[res.n_tried] = w;
-            res.tried_ms[res.n_tried] = ms;
-            res.n_tried++;
-          }
-          if (ms < best) {
-            best = ms;
-            res.epl = e;
-            res.grid = g;
-            res.win_bits = w;
-            res.ms = ms;
-          }
-        }
+    lrei_status st0 = hv_set_plan(ctx, 0);
+    if (st0 != LREI_OK) return st0;
+    for (const Cand &c : cands) {
+      if (res.n_tried >= 64) break;
+      ctx->epl = c.e;
+      ctx->hv_tile_bits = c.tile / 100;
+      ctx->hv_tile_waves = c.tile % 100;
+      const int iters = 5;
+      bool launched = true;
+      auto pass = [&]() {
+        launched = hv_pass_into(ctx, r, c.g, 1, ctx->blocks[1].p, ctx->blocks[4].p, (double2 *)ctx->partials.p,
+                                ctx->ws.work, true, kMaxHvGrid, ctx->ws.shifts + r) &&
+                   launched;
+      };
+      pass();
+      if (!launched) {
+        ctx->hv_launch_failed = false;
+        continue;
+      }
+      (void)hipEventRecord(e0, ctx->stream);
+      for (int k = 0; k < iters; ++k) pass();
+      (void)hipEventRecord(e1, ctx->stream);
+      HIPCHK(hipEventSynchronize(e1));
+      HIPCHK(hipGetLastError());
+      float t = 0;
+      (void)hipEventElapsedTime(&t, e0, e1);
+      const double ms = (double)t / iters;
+      res.tried_epl[res.n_tried] = c.e;
+      res.tried_grid[res.n_tried] = c.g;
+      res.tried_win[res.n_tried] = c.w;
+      res.tried_tile[res.n_tried] = c.tile;
+      res.tried_ms[res.n_tried] = ms;
+      res.n_tried++;
+      if (ms < best) {
+        best = ms;
+        res.epl = c.e;
+        res.grid = c.g;
+        res.win_bits = c.w;
+        res.tile_bits = c.tile / 100;
+        res.tile_waves = c.tile % 100;
+        res.ms = ms;
+      }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (res.epl == 0) return ctx->fail(LREI_E_DEVICE, "no H.V variant could be launched");
     if (cache)
       if (FILE *f = std::fopen(cache, "a")) {
-        std::fprintf(f, "%s %d %d %d %.6f\n", key.c_str(), res.epl, res.grid, res.win_bits, res.ms);
+        std::fprintf(f, "%s %d %d %d %d %.6f\n", key.c_str(), res.epl, res.grid, res.win_bits,
+                     res.tile_bits > 0 ? 100 * res.tile_bits + res.tile_waves : 0, res.ms);
         std::fclose(f);
       }
   }
@@ -1955,6 +2012,8 @@ lrei_status lrei_autotune(lrei_ctx *ctx, lrei_tune_result *out) {
   res.n_sweeps = (int)ctx->sweeps.size();
   ctx->epl = res.epl;
   ctx->hv_grid = res.grid;
+  ctx->hv_tile_bits = res.tile_bits;
+  ctx->hv_tile_waves = res.tile_bits > 0 ? res.tile_waves : 16;
   ctx->drop_graph();
   if (out) *out = res;
   return LREI_OK;

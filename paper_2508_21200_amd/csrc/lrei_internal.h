@@ -94,6 +94,12 @@ struct HvArgs {
   int partial_cap;
   int chunks;           // set by prepare_hv: Gram partial slots used (0: one per workgroup)
   const double *skip;   // the pass does nothing while *skip != 0 (nullptr: always runs)
+  // tiled pass (tile_bits > 0): workgroups of 64 * tile_waves threads hold
+  // 2^tile_bits rows of P_j in LDS; terms [0, n_local) flip bits below
+  // tile_bits only (the term table is sorted by highest flipped bit)
+  int tile_bits;
+  int tile_waves;
+  int n_local;
 };
 
 // Launches one H.V pass; returns the number of Gram partial slots written
@@ -176,6 +182,11 @@ void launch_magnetization(bool fp32, const void *V, const double *lam, long long
                           double2 *partials, int grid, hipStream_t s);
 int nspace_grid(long long N, int r);
 constexpr int kMaxHvGrid = 2048;  // largest H.V launch the partial-sum buffer holds
+constexpr int kMaxTileLds = 160 * 1024;  // LDS of one workgroup on gfx950
+// Tiled pass: LDS bytes of a launch shape, and whether the shape is launchable
+// (rank, columns per lane, tile bits, waves, rows, workgroups).
+size_t hv_tile_lds(bool fp32, int r, int E, int tile_bits, int waves);
+bool hv_tile_ok(bool fp32, int r, int E, int tile_bits, int waves, long long N, int grid);
 
 // Generic block pass (blocks.hip): out_o = sum_i in_i C[i, o] and Gram
 // products over the listed (a, b) pairs of [inputs..., outputs...], r <= 16.
@@ -200,6 +211,10 @@ size_t blocks_lds(bool fp32, int nin, int nout, int r);
 // Site -> row-bit order of the internal storage (site_order.cpp): pos[site]
 // is the row bit that holds the site.
 std::vector<int> choose_site_order(int n, int n_bonds, const int32_t *bond_ij);
+// The same for the tiled H.V pass: the k_cluster-site set with the most inner
+// bonds in the low bits, greedy growth order within and after it.
+std::vector<int> choose_site_order_cluster(int n, int n_bonds, const int32_t *bond_ij, int k_cluster);
+constexpr int kClusterBits = 10;  // tile rows of the tiled pass at r = 16 in FP32: 2^10
 
 // Device-resident state of the step-size controller (adaptive stepping, one
 // double each).  The stage that forms the error estimate reads the step from

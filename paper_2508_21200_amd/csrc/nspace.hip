@@ -519,6 +519,226 @@ __global__ __launch_bounds__(kThreads) void k_hv_batch(BatchLaunch b) {
   hv_body<T, E, CPLX, MI, false, DYN>(a, blockIdx.x - b.job_wg0[j], smem);
 }
 
+// ---------------------------------------------------------------------------
+// Tiled Krylov pass.  A workgroup of W waves walks tiles of R = 2^k
+// consecutive rows: it loads the tile of P_j into LDS (each row's 16-byte
+// chunks XOR-swizzled by the low row bits, so the rows that one load
+// instruction gathers fall on different banks), then every row's output
+//   P+[x] = alpha (d(x) P[x] + sum_t c_t(x) P[x ^ m_t] - P[x] diag(shift))
+// takes the partner rows of the terms t < n_local (flip masks below 2^k) from
+// LDS and gathers those of the other terms from global memory.  Each wave
+// stages its RW output rows in an LDS slice of its own and adds their Gram
+// products (P*P+, P+*P+; P*P too in mode 0) on MFMA, per tile in T and across
+// tiles in FP64; the waves' sums meet in LDS in a fixed order at the end.
+// Rows are 16-byte multiples (FP32: r even), r <= 16.
+// ---------------------------------------------------------------------------
+template <typename T, int E, bool CPLX, int W>
+__global__ __launch_bounds__(64 * W) void k_hv_tile(HvArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  if (a.skip && *a.skip != 0.0) return;
+  using A4 = typename Acc4<T>::type;
+  constexpr int NTH = 64 * W;
+  constexpr int CB = 2 * sizeof(T);  // bytes per complex
+  constexpr int LB = E * CB;         // bytes per lane per row
+  constexpr int B = (sizeof(T) == 4 ? 16 : 8) / E > 1 ? (sizeof(T) == 4 ? 16 : 8) / E : 2;
+  static_assert(LB % 16 == 0, "lanes move whole 16-byte chunks");
+  const int r = a.r;
+  const int L = a.lanes, RW = 64 / L;
+  const int kb = a.tile_bits, R = 1 << kb;
+  const int rowb = r * CB, cpr = rowb >> 4;
+  const int smask = (cpr & (cpr - 1)) == 0 ? cpr - 1 : 0;
+  unsigned char *tile = smem;
+  T *stage = reinterpret_cast<T *>(smem + (size_t)R * rowb);  // [W][RW][r] complex
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int cl = lane % L, rsub = lane / L;
+  const int col0 = cl * E;
+  const bool active = col0 < r;
+  const T alpha = (T)a.alpha;
+  T csh[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) csh[e] = (a.colshift && col0 + e < r) ? (T)a.colshift[col0 + e] : T(0);
+  const T *__restrict__ Pc = reinterpret_cast<const T *>(a.Pcur);
+  T *__restrict__ Pn = reinterpret_cast<T *>(a.Pnext);
+  using TermC = const __attribute__((address_space(4))) DevTerm<T>;
+  TermC *terms = (TermC *)(a.terms);
+  const T *__restrict__ dv = reinterpret_cast<const T *>(a.diagv);
+  const int nloc = a.n_local, noff = a.n_off;
+  const int ng = a.mode == 0 ? 3 : 2;
+
+  // LDS row access: the E complex columns of this lane (LB / 16 chunks)
+  auto lds_ld = [&](int row, T (&v)[2 * E]) {
+    const unsigned char *rp = tile + (size_t)row * rowb;
+    const int c0 = (col0 * CB) >> 4;
+#pragma unroll
+    for (int q = 0; q < LB / 16; ++q) {
+      const uint4 w = *reinterpret_cast<const uint4 *>(rp + (((c0 + q) ^ (row & smask)) << 4));
+      const T *f = reinterpret_cast<const T *>(&w);
+#pragma unroll
+      for (int h = 0; h < 16 / (int)sizeof(T); ++h) v[q * (16 / sizeof(T)) + h] = f[h];
+    }
+  };
+  auto g_ld = [&](const T *P, size_t ro, T (&v)[2 * E]) { load_ce<T, E>(P + 2 * (ro + col0), v); };
+
+  double acc[3][8];
+#pragma unroll
+  for (int g = 0; g < 3; ++g)
+#pragma unroll
+    for (int v = 0; v < 8; ++v) acc[g][v] = 0.0;
+
+  const long long num_tiles = a.N >> kb;
+  const int wg = blockIdx.x;
+  for (long long k = 0;; ++k) {
+    const long long tid = tile_of(k, num_tiles, a.grid, wg);
+    if (tid < 0) break;
+    const long long base = tid << kb;
+    __syncthreads();  // the previous tile's rows are no longer read
+    {
+      const unsigned char *src = reinterpret_cast<const unsigned char *>(Pc) + (size_t)base * rowb;
+      for (int j = threadIdx.x; j < R * cpr; j += NTH) {
+        const int row = j / cpr, c = j - row * cpr;
+        *reinterpret_cast<uint4 *>(tile + (size_t)row * rowb + ((c ^ (row & smask)) << 4)) =
+            *reinterpret_cast<const uint4 *>(src + ((size_t)j << 4));
+      }
+    }
+    __syncthreads();
+    A4 tre[3], tim[3];
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {
+      tre[g] = A4{0, 0, 0, 0};
+      tim[g] = A4{0, 0, 0, 0};
+    }
+    for (int it = 0; it < R / (W * RW); ++it) {
+      const int lr0 = it * W * RW + wave * RW;  // this wave's first row of the iteration
+      const int lr = lr0 + rsub;
+      const uint32_t xu = (uint32_t)(base + lr);
+      T own[2 * E], o[2 * E];
+#pragma unroll
+      for (int e = 0; e < 2 * E; ++e) own[e] = o[e] = T(0);
+      if (active) {
+        lds_ld(lr, own);
+        const T d = dv[xu];
+#pragma unroll
+        for (int e = 0; e < 2 * E; ++e) o[e] = d * own[e];
+        // terms inside the tile: partners from LDS; the others from global memory
+        for (int part = 0; part < 2; ++part) {
+          const int t0 = part == 0 ? 0 : nloc, t1 = part == 0 ? nloc : noff;
+          for (int t = t0; t < t1; t += B) {
+            T y[B][2 * E];
+            T cr[B], ci[B];
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+              cr[u] = T(0);
+              ci[u] = T(0);
+#pragma unroll
+              for (int e = 0; e < 2 * E; ++e) y[u][e] = T(0);
+              if (t + u < t1) {
+                TermC &tm = terms[t + u];
+                const int idx = (int)(((xu >> tm.sa) & 1u) | (((xu >> tm.sb) & 1u) << 1));
+                cr[u] = pick4(idx, tm.re[0], tm.re[1], tm.re[2], tm.re[3]);
+                if (CPLX) ci[u] = pick4(idx, tm.im[0], tm.im[1], tm.im[2], tm.im[3]);
+                if (cr[u] != T(0) || ci[u] != T(0)) {
+                  if (part == 0)
+                    lds_ld(lr ^ (int)tm.mask, y[u]);
+                  else
+                    g_ld(Pc, (size_t)(xu ^ tm.mask) * r, y[u]);
+                }
+              }
+            }
+#pragma unroll
+            for (int u = 0; u < B; ++u)
+#pragma unroll
+              for (int e = 0; e < E; ++e) {
+                o[2 * e] += cr[u] * y[u][2 * e];
+                o[2 * e + 1] += cr[u] * y[u][2 * e + 1];
+                if (CPLX) {
+                  o[2 * e] -= ci[u] * y[u][2 * e + 1];
+                  o[2 * e + 1] += ci[u] * y[u][2 * e];
+                }
+              }
+          }
+        }
+#pragma unroll
+        for (int e = 0; e < 2 * E; ++e) o[e] = alpha * (o[e] - csh[e >> 1] * own[e]);
+        store_ce<T, E>(Pn + 2 * ((size_t)xu * r + col0), o);
+        // this wave's slice of the output rows for the Gram products
+        T *sp = stage + 2 * ((size_t)(wave * RW + rsub) * r + col0);
+#pragma unroll
+        for (int e = 0; e < 2 * E; ++e) sp[e] = o[e];
+      }
+      __builtin_amdgcn_wave_barrier();  // the slice is read across lanes of this wave below
+      // Grams over the wave's RW rows: lane i + 16 q holds column i of row 4 s + q
+      const int gi = lane & 15, gq = lane >> 4;
+      for (int s4 = 0; s4 < RW; s4 += 4) {
+        T xr = T(0), xi = T(0), yr = T(0), yi = T(0);
+        if (gi < r) {
+          const int row = lr0 + s4 + gq;
+          const int byte = gi * CB;
+          const T *xp = reinterpret_cast<const T *>(tile + (size_t)row * rowb +
+                                                    ((((byte >> 4) ^ (row & smask)) << 4) | (byte & 15)));
+          xr = xp[0];
+          xi = xp[1];
+          const T *yp = stage + 2 * ((size_t)(wave * RW + s4 + gq) * r + gi);
+          yr = yp[0];
+          yi = yp[1];
+        }
+        // G_XY = sum conj(x) y, G_YY, G_XX (mode 0)
+        tre[0] = mfma(xr, yr, tre[0]);
+        tre[0] = mfma(xi, yi, tre[0]);
+        tim[0] = mfma(xr, yi, tim[0]);
+        tim[0] = mfma(-xi, yr, tim[0]);
+        tre[1] = mfma(yr, yr, tre[1]);
+        tre[1] = mfma(yi, yi, tre[1]);
+        tim[1] = mfma(yr, yi, tim[1]);
+        tim[1] = mfma(-yi, yr, tim[1]);
+        if (ng == 3) {
+          tre[2] = mfma(xr, xr, tre[2]);
+          tre[2] = mfma(xi, xi, tre[2]);
+          tim[2] = mfma(xr, xi, tim[2]);
+          tim[2] = mfma(-xi, xr, tim[2]);
+        }
+      }
+      __builtin_amdgcn_wave_barrier();  // the slice is rewritten next iteration
+    }
+#pragma unroll
+    for (int g = 0; g < 3; ++g)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        acc[g][v] += (double)tre[g][v];
+        acc[g][4 + v] += (double)tim[g][v];
+      }
+  }
+  // waves' sums in a fixed order, then the workgroup's partials (entry-major;
+  // Gram order of the pass: mode 0 P*P, P*P+, P+*P+; mode 1 P*P+, P+*P+)
+  __syncthreads();
+  double2 *red = reinterpret_cast<double2 *>(smem);
+  for (int w = 0; w < W; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int g = 0; g < 3; ++g) {
+        if (g >= ng) break;
+        const int slot = ng == 3 ? (g == 2 ? 0 : (g == 0 ? 1 : 2)) : (g == 0 ? 0 : 1);
+        const int b = lane & 15;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int arow = mfma_row<T>(lane, v);
+          if (arow < r && b < r) {
+            const int e = (slot * r + arow) * r + b;
+            const double2 val = make_double2(acc[g][v], acc[g][4 + v]);
+            if (w == 0) {
+              red[e] = val;
+            } else {
+              red[e].x += val.x;
+              red[e].y += val.y;
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < ng * r * r; e += NTH) a.partials[(long long)e * a.grid + wg] = red[e];
+}
+
 // Diagonal of H per row: d(x) = sum_k w_k (1 - 2 (b_{i_k}(x) xor b_{j_k}(x))),
 // bit 31 of a row index being 0 (one-site terms use j_k = 31).
 __global__ void k_diag_values(const DevDiagTerm *diag, int n_diag, long long N, double *d64, float *d32) {
@@ -1015,6 +1235,33 @@ bool hv_epl_valid(bool fp32, int r, int epl) {
   return big ? epl == 1 : (epl == 1 || epl == 2 || epl == 4);
 }
 
+// Lanes per row of the tiled pass for E columns per lane.
+static int tile_lanes(int r, int E) {
+  int L = 1;
+  while (L * E < r) L <<= 1;
+  return L;
+}
+
+size_t hv_tile_lds(bool fp32, int r, int E, int tile_bits, int waves) {
+  const size_t cb = fp32 ? 8 : 16;
+  const int L = tile_lanes(r, E);
+  return ((size_t)1 << tile_bits) * r * cb + (size_t)waves * (64 / L) * r * cb;
+}
+
+bool hv_tile_ok(bool fp32, int r, int E, int tile_bits, int waves, long long N, int grid) {
+  if (r < 1 || r > 16 || E < 1 || r % E != 0) return false;
+  if (fp32 ? (r % 2 != 0 || (E != 2 && E != 4)) : (E != 1 && E != 2)) return false;
+  if (waves != 8 && waves != 16) return false;
+  const int L = tile_lanes(r, E);
+  if (L > 16) return false;  // at least 4 rows per wave for the 16 x 16 x 4 Gram products
+  const long long R = 1LL << tile_bits;
+  if (tile_bits < 4 || R < (long long)waves * (64 / L) || N % R != 0) return false;
+  const long long tiles = N / R;
+  if (tiles % 8 != 0 || grid < 8 || grid % 8 != 0 || grid > tiles || grid > kMaxHvGrid) return false;
+  const size_t red = 3 * (size_t)r * r * sizeof(double2);  // the final reduction reuses the tile's LDS
+  return hv_tile_lds(fp32, r, E, tile_bits, waves) <= (size_t)kMaxTileLds && R * r * (fp32 ? 8 : 16) >= (long long)red;
+}
+
 bool prepare_hv(bool fp32, HvArgs &a) {
   if (a.win_bits == 0) {  // default: one window over all row bits, every term, the diagonal
     a.t0 = 0;
@@ -1025,6 +1272,17 @@ bool prepare_hv(bool fp32, HvArgs &a) {
   }
   if (!hv_epl_valid(fp32, a.r, a.epl)) return false;
   const int E = a.epl > 0 ? a.epl : hv_elems_per_lane(fp32, a.r);
+  if (a.tile_bits > 0) {  // tiled pass: one window, static tile schedule, Grams always
+    if (a.mode == 2 || a.acc_out || a.n_fix != 0 || a.t0 != 0 || a.t1 != a.n_off ||
+        !hv_tile_ok(fp32, a.r, E, a.tile_bits, a.tile_waves, a.N, a.grid) || a.n_local < 0 || a.n_local > a.n_off)
+      return false;
+    a.epl = E;
+    a.lanes = tile_lanes(a.r, E);
+    a.terms = fp32 ? (const void *)a.terms32 : (const void *)a.terms64;
+    a.diagv = fp32 ? (const void *)a.diag32 : (const void *)a.diag64;
+    a.chunks = 0;
+    return true;
+  }
   if (a.r % E != 0) return false;
   int L = 1;
   while (L * E < a.r) L <<= 1;
@@ -1052,13 +1310,53 @@ bool prepare_hv(bool fp32, HvArgs &a) {
 }
 
 size_t hv_launch_lds(bool fp32, const HvArgs &a) {
+  if (a.tile_bits > 0) return hv_tile_lds(fp32, a.r, a.epl, a.tile_bits, a.tile_waves);
   return hv_lds(fp32, a.r) + (a.chunks > 0 ? hv_lds_dyn_extra() : 0);
+}
+
+template <typename T, int E, bool C, int W>
+static void launch_tile_one(const HvArgs &a, size_t lds, hipStream_t s) {
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void *)k_hv_tile<T, E, C, W>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              kMaxTileLds);
+    attr = true;
+  }
+  hipLaunchKernelGGL((k_hv_tile<T, E, C, W>), dim3(a.grid), dim3(64 * W), lds, s, a);
+}
+
+static bool launch_tile(bool fp32, const HvArgs &a, size_t lds, hipStream_t s) {
+  const bool c = a.cplx != 0, w16 = a.tile_waves == 16;
+  auto go = [&](auto tag_t, auto tag_e) {
+    using T = typename decltype(tag_t)::type;
+    constexpr int EE = decltype(tag_e)::value;
+    if (c) {
+      if (w16) launch_tile_one<T, EE, true, 16>(a, lds, s);
+      else launch_tile_one<T, EE, true, 8>(a, lds, s);
+    } else {
+      if (w16) launch_tile_one<T, EE, false, 16>(a, lds, s);
+      else launch_tile_one<T, EE, false, 8>(a, lds, s);
+    }
+  };
+  struct F32 { using type = float; };
+  struct F64 { using type = double; };
+  if (fp32) {
+    if (a.epl == 4) go(F32{}, std::integral_constant<int, 4>{});
+    else if (a.epl == 2) go(F32{}, std::integral_constant<int, 2>{});
+    else return false;
+  } else {
+    if (a.epl == 2) go(F64{}, std::integral_constant<int, 2>{});
+    else if (a.epl == 1) go(F64{}, std::integral_constant<int, 1>{});
+    else return false;
+  }
+  return true;
 }
 
 int launch_hv(bool fp32, const HvArgs &a0, hipStream_t s) {
   HvArgs a = a0;
   if (!prepare_hv(fp32, a)) return 0;
   const size_t lds = hv_launch_lds(fp32, a);
+  if (a.tile_bits > 0) return launch_tile(fp32, a, lds, s) ? a.grid : 0;
   const bool ok = dispatch_hv(fp32, a.epl, a.cplx != 0, a.r > 16, a.chunks > 0,
                                 [&]<typename T, int E, bool C, int MI, bool DYN>() {
                                   launch_one<T, E, C, MI, DYN>(a, lds, s);

@@ -30,7 +30,7 @@ class lrei_options(ctypes.Structure):
                 ("ab_bootstrap", ctypes.c_int), ("householder_mode", ctypes.c_int),
                 ("use_graph", ctypes.c_int), ("deterministic", ctypes.c_int),
                 ("autotune_cache", ctypes.c_char_p), ("mixed_pivot_floor", ctypes.c_double),
-                ("fail_after_steps", ctypes.c_int)]
+                ("fail_after_steps", ctypes.c_int), ("site_order", ctypes.c_int)]
 
 
 class lrei_stats(ctypes.Structure):
@@ -54,7 +54,8 @@ class lrei_tune_result(ctypes.Structure):
                 ("n_sweeps", ctypes.c_int), ("ms", ctypes.c_double),
                 ("from_cache", ctypes.c_int), ("n_tried", ctypes.c_int),
                 ("tried_epl", ctypes.c_int * 64), ("tried_grid", ctypes.c_int * 64),
-                ("tried_win", ctypes.c_int * 64), ("tried_ms", ctypes.c_double * 64)]
+                ("tried_win", ctypes.c_int * 64), ("tried_ms", ctypes.c_double * 64),
+                ("tile_bits", ctypes.c_int), ("tile_waves", ctypes.c_int), ("tried_tile", ctypes.c_int * 64)]
 
 
 class lrei_traj_desc(ctypes.Structure):
@@ -172,13 +173,14 @@ class Context:
 
     def __init__(self, device=0, stream=None, precision="fp64", eig_tol=1e-15, eig_max_sweeps=40,
                  warm="analytic", householder_mode=0, use_graph=True, autotune_cache=None,
-                 mixed_pivot_floor=None, fail_after_steps=0):
+                 mixed_pivot_floor=None, fail_after_steps=0, site_order=0):
         self.lib = load()
         opt = lrei_options()
         self.lib.lrei_default_options(ctypes.byref(opt))
         if mixed_pivot_floor is not None:
             opt.mixed_pivot_floor = float(mixed_pivot_floor)
         opt.fail_after_steps = int(fail_after_steps)
+        opt.site_order = int(site_order)
         opt.precision = PRECISIONS[precision]
         opt.eig_tol = eig_tol
         opt.eig_max_sweeps = eig_max_sweeps
@@ -323,9 +325,10 @@ class Context:
         t = lrei_tune_result()
         self._check(self.lib.lrei_autotune(self.h, ctypes.byref(t)))
         return {"epl": t.epl, "grid": t.grid, "win_bits": t.win_bits, "n_sweeps": t.n_sweeps, "ms": t.ms,
-                "from_cache": bool(t.from_cache),
+                "from_cache": bool(t.from_cache), "tile_bits": t.tile_bits, "tile_waves": t.tile_waves,
                 "tried": [(t.tried_epl[i], t.tried_grid[i], t.tried_win[i], t.tried_ms[i])
-                          for i in range(t.n_tried)]}
+                          for i in range(t.n_tried)],
+                "tried_tile": [t.tried_tile[i] for i in range(t.n_tried)]}
 
     def synchronize(self):
         self._check(self.lib.lrei_synchronize(self.h))

@@ -43,3 +43,10 @@ extern "C" __attribute__((visibility("default"))) int terms_spread(int n, int nb
   *spread = t.spread;
   return 0;
 }
+
+// The site -> row-bit map of the tiled pass's cluster order.
+extern "C" __attribute__((visibility("default"))) void site_order_cluster(int n, int nb, const int32_t *bonds,
+                                                                          int k, int *pos) {
+  const std::vector<int> p = lrei::choose_site_order_cluster(n, nb, bonds, k);
+  for (int i = 0; i < n; ++i) pos[i] = p[i];
+}

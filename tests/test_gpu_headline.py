@@ -72,7 +72,7 @@ def test_tuned_shape_follows_rank(tmp_path):
     c.autotune()
     c.close()
     line = cache.read_text().strip().splitlines()[-1].split()
-    line[-4] = "8"  # columns per lane
+    line[-5], line[-3], line[-2] = "8", "0", "0"  # eight columns per lane, one window, untiled
     cache.write_text(" ".join(line) + "\n")
     c = _ctx("mixed", autotune_cache=cache)
     c.set_hamiltonian(cfg["n"], cfg["bonds"], cfg["J"], cfg["h"])
@@ -92,6 +92,42 @@ def test_tuned_shape_follows_rank(tmp_path):
     Yo = apply_H(cfg["n"], cfg["bonds"], cfg["J"], cfg["h"], X)
     assert np.abs(Y - Yo).max() < 1e-12 * np.abs(Yo).max()
     c.close()
+
+
+@pytest.mark.parametrize("prec,case,order", [("mixed", "lattice_r16", 1), ("fp64", "lattice_r16", 0),
+                                             ("mixed", "chain_r8", 1), ("fp64", "chain_r4", 0)])
+def test_tiled_pass_matches_oracle(tmp_path, prec, case, order):
+    """The tiled H.V pass (rows of a 2^k-row tile in LDS, the terms inside the
+    tile served from there) in every tile size and wave count the autotuner
+    may pick, forced through its cache, under both site orders (the cluster
+    order puts the most bonds inside a tile): 2 RK4 steps against the oracle."""
+    cfg_id, n, r = {"lattice_r16": (3, 16, 16), "chain_r8": (2, 15, 8), "chain_r4": (2, 14, 4)}[case]
+    cfg = make_config(cfg_id, n=n, r=r)
+    n = cfg["n"]
+    H = Hamiltonian(n, cfg["bonds"], cfg["J"], cfg["h"])
+    Vo = oracle_run(H, cfg["V"], cfg["lam"], cfg["model"], cfg["kappa"], 0.01, 2, "RK4")
+    cache = tmp_path / "tune.txt"
+    c = _ctx(prec, autotune_cache=cache, site_order=order)
+    c.set_hamiltonian(n, cfg["bonds"], cfg["J"], cfg["h"])
+    c.set_rho(cfg["lam"], cfg["V"])
+    t = c.autotune()
+    c.close()
+    tiled = sorted({(e, g, tile) for (e, g, w, ms), tile in zip(t["tried"], t["tried_tile"]) if tile})
+    assert tiled, "no tiled shape was launchable"
+    key = cache.read_text().strip().splitlines()[-1].split()[:-5]
+    tol = 1e-10 if prec == "fp64" else 1e-5
+    for e, g, tile in tiled:
+        cache.write_text(" ".join(key + [str(e), str(g), "0", str(tile), "0.1"]) + "\n")
+        c = _ctx(prec, autotune_cache=cache, site_order=order)
+        c.set_hamiltonian(n, cfg["bonds"], cfg["J"], cfg["h"])
+        c.set_rho(cfg["lam"], cfg["V"])
+        got = c.autotune()
+        assert got["from_cache"] and got["tile_bits"] == tile // 100 and got["tile_waves"] == tile % 100
+        c.step(cfg["model"], "RK4", 0.01, cfg["kappa"], 2)
+        err = rel_fro_error(c.get_rho()[1], cfg["lam"], Vo, cfg["lam"])
+        print(f"{case} {prec} epl={e} grid={g} tile={tile}: {err:.2e}")
+        assert err < tol, (e, g, tile, err)
+        c.close()
 
 
 def test_promotion_then_failure_restores_start_of_call():

@@ -19,7 +19,8 @@ LIB = os.path.join(ROOT, "paper_2508_21200_amd", "liblrei.so")
 def harness(tmp_path_factory):
     out = tmp_path_factory.mktemp("h") / "libterms.so"
     src = [os.path.join(ROOT, "tests", "host", "terms_apply.cpp"),
-           os.path.join(ROOT, "paper_2508_21200_amd", "csrc", "terms.cpp")]
+           os.path.join(ROOT, "paper_2508_21200_amd", "csrc", "terms.cpp"),
+           os.path.join(ROOT, "paper_2508_21200_amd", "csrc", "site_order.cpp")]
     cmd = ["/opt/rocm/bin/hipcc", "-x", "c++", "-O1", "-std=c++17", "-fPIC", "-shared",
            "-I" + os.path.join(ROOT, "include"), "-I/opt/rocm/include",
            "-D__HIP_PLATFORM_AMD__"] + src + ["-o", str(out)]
@@ -95,6 +96,37 @@ def test_term_table_spread_is_frobenius(harness, case):
                                 None if hc is None else hc.ctypes.data_as(ctypes.c_void_p), ctypes.byref(sp)) == 0
     Hd = dense_H(n, bonds, J, h)
     assert abs(sp.value - np.linalg.norm(Hd) / np.sqrt(2 ** n)) < 1e-12 * sp.value
+
+
+@pytest.mark.parametrize("case", ["square4x5", "square4x4", "chain16", "triangular3x4"])
+def test_cluster_site_order(harness, case):
+    """The tiled pass's site order is a permutation whose first k = 10 sites
+    hold as many bonds as the best k-subset (brute force over all of them for
+    these sizes), and every prefix is a connected-first growth (each prefix
+    site after the first has a bond into the earlier ones, where possible)."""
+    import itertools
+    from workloads import triangular_lattice_bonds
+    if case == "square4x5":
+        bonds = square_lattice_bonds(4, 5, periodic=True)
+    elif case == "square4x4":
+        bonds = square_lattice_bonds(4, 4, periodic=True)
+    elif case == "chain16":
+        bonds = chain_bonds(16, periodic=False)
+    else:
+        bonds = triangular_lattice_bonds(3, 4, periodic=True)
+    bonds = np.ascontiguousarray(bonds, dtype=np.int32)
+    n = int(bonds.max()) + 1
+    k = 10
+    pos = np.zeros(n, dtype=np.int32)
+    harness.site_order_cluster(n, bonds.shape[0], bonds.ctypes.data_as(ctypes.c_void_p), k,
+                               pos.ctypes.data_as(ctypes.c_void_p))
+    assert sorted(pos.tolist()) == list(range(n))
+    low = {q for q in range(n) if pos[q] < k}
+    inside = sum(1 for i, j in bonds if i in low and j in low)
+    best = max(sum(1 for i, j in bonds if i in S and j in S) for S in map(set, itertools.combinations(range(n), k)))
+    assert inside == best
+    if case == "square4x5":
+        assert best == 15  # two neighbouring rows of the torus
 
 
 def test_library_exports_every_declared_symbol():
