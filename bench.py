@@ -179,10 +179,18 @@ class OracleStep:
             os.sched_setaffinity(0, cpus[:2])
 
     def wait(self, deadline_s, t0):
-        left = deadline_s - (time.perf_counter() - t0)
-        try:
-            self.proc.wait(timeout=max(1.0, left))
-        except subprocess.TimeoutExpired:
+        """Waits for the child until `deadline_s` after `t0`, printing a
+        progress line every 30 s."""
+        while self.proc.poll() is None:
+            left = deadline_s - (time.perf_counter() - t0)
+            if left <= 0:
+                break
+            try:
+                self.proc.wait(timeout=min(30.0, left))
+            except subprocess.TimeoutExpired:
+                print(f"[bench] oracle step still running ({time.perf_counter() - self.t_start:.0f} s)",
+                      file=sys.stderr, flush=True)
+        if self.proc.poll() is None:
             self.proc.kill()
             self.proc.wait()
             return None, {"value": None, "unit": "steps/s", "cores": self.threads, "kind": "oracle",
