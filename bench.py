@@ -15,7 +15,9 @@ H.V pass), `cpu_baseline` (one complete step of the CPU oracle on the same
 inputs, measured in a child process that runs beside the GPU work), `parity`
 (relative Frobenius error of one GPU step, mixed and FP64, against that oracle
 step), `fp64_path` (the FP64 GPU path's rate on the same workload),
-`kernels_ms` (per-kernel averages).
+`kernels_ms` (per-kernel averages), `batch` (the 64-trajectory batched
+workload: its rate, its smallest trajectories against the oracle, and its rate
+against the FP64 batch and against the plain FP64 path).
 """
 import argparse
 import json
@@ -543,27 +545,34 @@ def run_learned_report(args, torch):
                       "training": training, "modes": modes}))
 
 
-def run_batch(args, torch):
-    """The batched workload: 64 independent XXZ-chain trajectories (n 12..16,
-    r in {4, 8, 16}, half q-LL / half q-LLG, kappa log-uniform in [0.01, 1]),
-    LREI-RK4 dt = 0.01, mixed precision, advanced together."""
-    from paper_2508_21200_amd import Batch
+def batch_trajectories():
+    """The batched workload's 64 trajectories (inputs only)."""
     from workloads import make_config, CONFIGS
-    k = 4
-    base = CONFIGS[k]
+    base = CONFIGS[4]
     trajs = []
     for t in range(base["n_traj"]):
-        c = make_config(k, traj=t)
+        c = make_config(4, traj=t)
         trajs.append(dict(n=c["n"], bonds=c["bonds"], J=c["J"], h=c["h"], lam=c["lam"], V=c["V"],
                           model=c["model"], kappa=c["kappa"]))
-    precision = args.precision or "mixed"
+    return base, trajs
+
+
+def measure_batch(args, torch, precision, steps, warmup, n_oracle=2):
+    """The batched workload: 64 independent XXZ-chain trajectories (n 12..16,
+    r in {4, 8, 16}, half q-LL / half q-LLG, kappa log-uniform in [0.01, 1]),
+    LREI-RK4 dt = 0.01, advanced together.  Returns the measured rate, the
+    worst error of the `n_oracle` smallest trajectories against the CPU oracle
+    (the same warmup + timed steps), the worst distance of every trajectory
+    from the FP64 batch, and the rates of the FP64 batch and of the plain FP64
+    path (each trajectory in its own single FP64 context, one after another)."""
+    from paper_2508_21200_amd import Batch, Context
+    base, trajs = batch_trajectories()
     dt, scheme = base["dt"], base["scheme"]
-    steps = args.steps
     b = Batch(trajs, precision=precision)
-    print(f"[bench] workload {base['name']} precision={precision} warmup={args.warmup} steps={steps}",
+    print(f"[bench] workload {base['name']} precision={precision} warmup={warmup} steps={steps}",
           file=sys.stderr, flush=True)
-    if args.warmup > 0:
-        b.step(scheme, dt, args.warmup)
+    if warmup > 0:
+        b.step(scheme, dt, warmup)
     b.synchronize()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -571,21 +580,27 @@ def run_batch(args, torch):
     b.synchronize()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    print(f"[bench] timed {steps} steps in {elapsed:.4f} s", file=sys.stderr, flush=True)
+    print(f"[bench] batch: timed {steps} steps in {elapsed:.4f} s", file=sys.stderr, flush=True)
+    out = {"elapsed": elapsed, "trajs": trajs, "base": base}
     if args.profile_only:
-        print(json.dumps({"steps": steps, "ms_per_step": 1e3 * elapsed / steps}))
-        return
-    kms = b.profile_kernels(scheme, dt, iters=20)
+        return out
+    out["kernels_ms"] = b.profile_kernels(scheme, dt, iters=20)
     elem = 8 if precision == "mixed" else 16
     nr_total = sum((2 ** t["n"]) * t["lam"].size for t in trajs)
-    hv_bytes = 3 * nr_total * elem
-    achieved = hv_bytes / (kms["hv_pass"] * 1e-3) / 1e9
-    parity = None
-    compare = None
-    if not args.no_parity and precision == "mixed":
+    out["hv_bytes"] = 2 * nr_total * elem  # read P_j, write P_{j+1}, every trajectory
+    out["nr_total"] = nr_total
+    if args.no_parity:
+        b.close()
+        return out
+    # the smallest trajectories' results, for the comparison with the CPU
+    # oracle (batch_oracle_parity, run once the CPU is free)
+    order = sorted(range(len(trajs)), key=lambda q: (2 ** trajs[q]["n"]) * trajs[q]["lam"].size)[:n_oracle]
+    out["for_oracle"] = {"order": order, "V": {q: b.get_rho(q)[1] for q in order}, "steps": warmup + steps,
+                         "dt": dt, "scheme": scheme}
+    if precision == "mixed":
         ref = Batch(trajs, precision="fp64")
-        if args.warmup > 0:
-            ref.step(scheme, dt, args.warmup)
+        if warmup > 0:
+            ref.step(scheme, dt, warmup)
         ref.synchronize()
         t1 = time.perf_counter()
         ref.step(scheme, dt, steps)
@@ -594,17 +609,15 @@ def run_batch(args, torch):
         worst = 0.0
         for q, t in enumerate(trajs):
             worst = max(worst, rel_fro(torch, b.get_rho(q)[1], ref.get_rho(q)[1], t["lam"]))
-        parity = {"vs": "FP64 GPU batch, same inputs and step count", "rel_fro_worst_trajectory": worst}
         ref.close()
         # the plain FP64 GPU path: one single-trajectory context per
         # trajectory, stepped one after the other (same steps, graphs warm)
-        from paper_2508_21200_amd import Context
         plain = []
         for t in trajs:
             c = Context(precision="fp64", autotune_cache=args.tune_cache)
             c.set_hamiltonian(t["n"], t["bonds"], t["J"], t["h"])
             c.set_rho(t["lam"], t["V"])
-            c.step(t["model"], scheme, dt, t["kappa"], max(args.warmup, 1))
+            c.step(t["model"], scheme, dt, t["kappa"], max(warmup, 1))
             plain.append(c)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -615,38 +628,101 @@ def run_batch(args, torch):
         t_plain = time.perf_counter() - t1
         for c in plain:
             c.close()
-        mixed_rate = len(trajs) * steps / elapsed
-        compare = {"plain_fp64_single_contexts_traj_steps_per_s": round(len(trajs) * steps / t_plain, 1),
-                   "fp64_batch_traj_steps_per_s": round(len(trajs) * steps / t_fp64_batch, 1),
-                   "mixed_batch_over_plain_fp64": round(mixed_rate / (len(trajs) * steps / t_plain), 2),
-                   "note": "the plain path runs each trajectory in its own FP64 context, one after the "
-                           "other; the mixed batch stays within the 1e-5 bound of the FP64 batch (parity)"}
+        n = len(trajs) * steps
+        out["vs_fp64"] = {"vs": "FP64 GPU batch, same inputs and step count", "rel_fro_worst_trajectory": worst}
+        out["compare"] = {"plain_fp64_single_contexts_traj_steps_per_s": round(n / t_plain, 1),
+                          "fp64_batch_traj_steps_per_s": round(n / t_fp64_batch, 1),
+                          "mixed_batch_over_plain_fp64": round(t_plain / elapsed, 2),
+                          "mixed_batch_over_fp64_batch": round(t_fp64_batch / elapsed, 2),
+                          "note": "the plain path runs each trajectory in its own FP64 context, one after the "
+                                  "other; the FP64 batch is this launch packing in FP64 storage"}
+    b.close()
+    return out
+
+
+def batch_oracle_parity(m):
+    """The smallest trajectories of a measured batch against the CPU oracle
+    (same inputs, same total step count); numpy's BLAS is held to one thread
+    for these small problems."""
+    if "for_oracle" not in m:
+        return
+    from threadpoolctl import threadpool_limits
+    from oracle.hamiltonian import Hamiltonian
+    from oracle.schemes import run as oracle_run
+    from oracle.metrics import rel_fro_error
+    fo, trajs = m["for_oracle"], m["trajs"]
+    worst, t0 = 0.0, time.perf_counter()
+    with threadpool_limits(limits=1):
+        for q in fo["order"]:
+            t = trajs[q]
+            H = Hamiltonian(t["n"], t["bonds"], t["J"], t["h"])
+            Vo = oracle_run(H, t["V"], t["lam"], t["model"], t["kappa"], fo["dt"], fo["steps"], fo["scheme"])
+            worst = max(worst, rel_fro_error(fo["V"][q], t["lam"], Vo, t["lam"]))
+    m["oracle"] = {"vs": "oracle", "trajectories": [dict(index=q, n=trajs[q]["n"], r=int(trajs[q]["lam"].size),
+                                                         model=trajs[q]["model"]) for q in fo["order"]],
+                   "steps": fo["steps"], "rel_fro_worst": worst, "oracle_s": round(time.perf_counter() - t0, 2),
+                   "note": "the smallest trajectories of the batch (by N r) against the CPU complex128 oracle; "
+                           "bound 1e-5 (mixed), 1e-10 (FP64)"}
+
+
+def batch_summary(m, precision, steps):
+    """The batch measurement as a sub-object of a bench line."""
+    n = len(m["trajs"]) * steps
+    res = {"metric": "LREI trajectory-steps/s (64 batched trajectories)",
+           "value": n / m["elapsed"], "unit": "trajectory-steps/s", "steps": steps,
+           "ms_per_step": 1e3 * m["elapsed"] / steps, "precision": precision,
+           "workload": m["base"]["name"]}
+    if "kernels_ms" in m:
+        kms = m["kernels_ms"]
+        ach = m["hv_bytes"] / (kms["hv_pass"] * 1e-3) / 1e9
+        res["hv_pass"] = {"ms": round(kms["hv_pass"], 5), "algorithmic_bytes": m["hv_bytes"],
+                          "GBs": round(ach, 1), "frac_of_hbm_peak": round(ach / HBM_PEAK_GBS, 4),
+                          "model": "2 sum_t N_t r_t c per pass (read P_j, write P_{j+1})"}
+        res["kernels_ms"] = {k: round(v, 5) for k, v in kms.items()}
+    for k in ("oracle", "vs_fp64", "compare"):
+        if k in m:
+            res[{"oracle": "parity", "vs_fp64": "vs_fp64_batch", "compare": "vs_plain_fp64"}[k]] = m[k]
+    return res
+
+
+def run_batch(args, torch):
+    """Prints the bench line of the batched workload (--config 4)."""
+    precision = args.precision or "mixed"
+    steps = args.steps
+    m = measure_batch(args, torch, precision, steps, args.warmup)
+    if args.profile_only:
+        print(json.dumps({"steps": steps, "ms_per_step": 1e3 * m["elapsed"] / steps}))
+        return
+    batch_oracle_parity(m)
+    trajs, base = m["trajs"], m["base"]
+    summ = batch_summary(m, precision, steps)
     cpu = None if args.no_cpu_baseline else cpu_baseline_batch(trajs)
     rs = sorted({t["lam"].size for t in trajs})
     line = {
-        "metric": "LREI trajectory-steps/s (64 batched trajectories)",
-        "value": len(trajs) * steps / elapsed,
+        "metric": summ["metric"],
+        "value": summ["value"],
         "unit": "trajectory-steps/s",
         "n_gpus": 1,
         "steps": steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / steps,
+        "ms_per_step": summ["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "c64+f64" if precision == "mixed" else "c128",
         "data": "synthetic",
         "config": {"workload": base["name"], "n_traj": len(trajs), "n_range": [12, 16], "r_values": rs,
-                   "sum_N_r": nr_total, "scheme": scheme, "dt": dt, "precision": precision,
+                   "sum_N_r": m["nr_total"], "scheme": base["scheme"], "dt": base["dt"], "precision": precision,
                    "models": "q-LL (even trajectories), q-LLG (odd)", "lattice": "open XXZ chains"},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_cheb_batch (all trajectories' H.V passes, fused Grams)",
-                     "algorithmic_bytes_per_launch": hv_bytes},
+        "roofline": {"bound": "hbm", "achieved": summ["hv_pass"]["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": summ["hv_pass"]["frac_of_hbm_peak"], "traffic": None,
+                     "kernel": "k_hv_batch (all trajectories' H.V passes, fused Grams)",
+                     "algorithmic_bytes_per_launch": m["hv_bytes"]},
         "cpu_baseline": cpu,
-        "parity": parity,
-        "vs_plain_fp64": compare,
-        "kernels_ms": {k2: round(v, 5) for k2, v in kms.items()},
+        "parity": summ.get("parity"),
+        "vs_fp64_batch": summ.get("vs_fp64_batch"),
+        "vs_plain_fp64": summ.get("vs_plain_fp64"),
+        "kernels_ms": summ.get("kernels_ms"),
     }
     print(json.dumps(line))
 
@@ -762,7 +838,8 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "traffic_over_algorithmic": None if traffic is None else round(traffic / hv_bytes, 3),
-                "kernel": "k_hv_tile" if (tuning or {}).get("tile_bits") else "k_hv",
+                "kernel": ("k_hv_tile" if (tuning or {}).get("tile_bits") else
+                           "k_hv (compacted gathers)" if (tuning or {}).get("compact") else "k_hv"),
                 "algorithmic_bytes_per_launch": hv_bytes,
                 "algorithmic_model": "2F per pass, F = N r c (read P_j, write P_{j+1})",
                 "measured_copy_peak": copy, "frac_of_copy_peak": round(achieved / copy["GBs"], 4)}
@@ -799,6 +876,11 @@ def main():
                 "note": "host wall clock of the synchronous ABI call (upload of the pair list, passes, "
                         "reduction, copy-back)"}
 
+    # the batched workload, measured while the oracle step finishes
+    bm = None
+    if args.config == 3:
+        bm = measure_batch(args, torch, "mixed" if precision == "mixed" else "fp64", args.steps, args.warmup)
+
     cpu = None
     parity = None
     if oracle is not None:
@@ -814,6 +896,10 @@ def main():
         elif V1_gpu:
             parity = {"vs": "oracle", "steps": 1, "rel_fro_mixed": None, "rel_fro_fp64": None,
                       "note": "the oracle step did not complete: " + cpu["sample"]}
+    batch = None
+    if bm is not None:
+        batch_oracle_parity(bm)  # after the oracle step: the CPU is free again
+        batch = batch_summary(bm, "mixed" if precision == "mixed" else "fp64", args.steps)
     line = {
         "metric": "LREI steps/s (n=20, r=16)" if args.config == 3 else f"LREI steps/s ({cfg['name']})",
         "value": args.steps / elapsed,
@@ -836,11 +922,14 @@ def main():
         "fp64_path": fp64,
         "kernels_ms": {k: round(v, 5) for k, v in kms.items()},
         "pair_density": pair_obs,
+        "batch": batch,
         "hv_tuning": None if tuning is None else {
             "epl": tuning["epl"], "grid": tuning["grid"], "tile_bits": tuning["tile_bits"],
             "tile_waves": tuning["tile_waves"], "ms": round(tuning["ms"], 5),
             "tried": [[e, g, tile, round(t, 5)] for (e, g, w, t), tile in zip(tuning["tried"], tuning["tried_tile"])],
-            "tried_fields": "columns per lane, workgroups, 100 tile_bits + waves (0: untiled), ms"},
+            "compact": tuning.get("compact"),
+            "tried_fields": "columns per lane, workgroups, variant (0: untiled, 1: untiled with compacted "
+                            "gathers, 100 tile_bits + waves: tiled), ms"},
         "eig_stats": {k: stats[k] for k in ("eigensolves", "warm_accepted", "warm_rejected", "warm_iterations",
                                             "dropped_directions", "min_pivot_ratio", "ortho_error")},
         "projected_phase_ms_per_step": dict(zip(

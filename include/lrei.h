@@ -291,6 +291,7 @@ LREI_API lrei_status lrei_profile_kernels(lrei_ctx *ctx, int model, int scheme, 
 LREI_API lrei_status lrei_synchronize(lrei_ctx *ctx);
 
 /* Result of lrei_autotune. */
+#define LREI_TUNE_MAX 128
 typedef struct {
   int epl;                 /* complex columns per lane chosen for the H.V pass          */
   int grid;                /* workgroups per H.V launch chosen                           */
@@ -298,18 +299,24 @@ typedef struct {
   int n_sweeps;            /* sweeps per H.V pass for that window                        */
   double ms;               /* time of one H.V pass (all sweeps) of the chosen variant    */
   int from_cache;          /* 1: read from opt.autotune_cache without timing             */
-  int n_tried;             /* variants timed (at most 64)                                */
-  int tried_epl[64], tried_grid[64], tried_win[64];
-  double tried_ms[64];
+  int n_tried;             /* variants timed (at most LREI_TUNE_MAX)                     */
+  int tried_epl[LREI_TUNE_MAX], tried_grid[LREI_TUNE_MAX], tried_win[LREI_TUNE_MAX];
+  double tried_ms[LREI_TUNE_MAX];
   int tile_bits;           /* tiled pass: 2^tile_bits rows of P held in LDS per workgroup
-                              (0: the untiled pass)                                      */
+                              (0: an untiled pass)                                       */
   int tile_waves;          /* tiled pass: waves per workgroup (8 or 16)                  */
-  int tried_tile[64];      /* per variant: 100 tile_bits + tile_waves, 0 if untiled      */
+  int tried_tile[LREI_TUNE_MAX]; /* per variant: 100 tile_bits + tile_waves for the tiled
+                              pass, 1 for the untiled pass with compacted gathers, 0 for
+                              the untiled pass                                            */
+  int compact;             /* 1: the untiled pass with compacted gathers (each row walks
+                              only the terms whose coefficient is non-zero for it; r <= 16,
+                              at most 64 off-diagonal terms)                              */
 } lrei_tune_result;
 
 /* Chooses the launch shape of the matrix-free H.V pass (eq. 5.1 applied in
- * the Chebyshev passes) for the current Hamiltonian, rank and precision:
- * every valid (columns per lane, workgroups, row-bit window) choice is timed on
+ * the Krylov passes) for the current Hamiltonian, rank and precision:
+ * every valid (columns per lane, workgroups, row-bit window, tiled / untiled /
+ * compacted gathers) choice is timed on
  * the device with the current state as input (5 passes each) and the fastest
  * is kept for this context.  A window of w row bits splits the pass into
  * sweeps, each applying the terms whose flip masks fit one window, so that one

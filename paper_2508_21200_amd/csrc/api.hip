@@ -75,6 +75,7 @@ struct lrei_ctx {
   int hv_grid = 0;                // H.V workgroups per launch (0: default)
   int hv_tile_bits = 0;           // tiled pass: 2^bits rows per LDS tile (0: untiled)
   int hv_tile_waves = 16;         // tiled pass: waves per workgroup
+  int hv_compact = 0;             // untiled pass with compacted gathers
   // H.V sweep plan: each sweep applies the terms whose flip masks lie in its
   // window of row bits (one sweep = all bits, all terms)
   struct HvSweep {
@@ -269,6 +270,8 @@ int hv_launches(lrei_ctx *ctx, int r, int grid, int mode, const void *cur, void 
     a.tile_bits = ctx->hv_tile_bits;
     a.tile_waves = ctx->hv_tile_waves;
     a.n_local = local_terms(ctx, ctx->hv_tile_bits);
+  } else if (ctx->hv_compact && r <= 16) {
+    a.compact = 1;
   }
   if (!sweeps || ns <= 1) {
     slots = launch_hv(ctx->fp32, a, ctx->stream);
@@ -308,6 +311,7 @@ void reset_hv_tuning(lrei_ctx *ctx) {
   ctx->epl = 0;
   ctx->hv_grid = 0;
   ctx->hv_tile_bits = 0;
+  ctx->hv_compact = 0;
   ctx->drop_graph();
 }
 
@@ -406,12 +410,14 @@ lrei_status hv_set_plan(lrei_ctx *ctx, int w) {
     o64[q].mask = o32[q].mask = t.mask;
     o64[q].sa = o32[q].sa = t.sa;
     o64[q].sb = o32[q].sb = t.sb;
-    o64[q].pad = o32[q].pad = 0;
+    o64[q].act = o32[q].act = 0;
     for (int k = 0; k < 4; ++k) {
       o64[q].re[k] = t.re[k];
       o64[q].im[k] = t.im[k];
       o32[q].re[k] = (float)t.re[k];
       o32[q].im[k] = (float)t.im[k];
+      if (o64[q].re[k] != 0.0 || o64[q].im[k] != 0.0) o64[q].act |= 1u << k;
+      if (o32[q].re[k] != 0.0f || o32[q].im[k] != 0.0f) o32[q].act |= 1u << k;
     }
   }
   HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -567,6 +573,7 @@ lrei_status promote_fp64(lrei_ctx *ctx) {
   ctx->epl = 0;
   ctx->hv_grid = 0;
   ctx->hv_tile_bits = 0;
+  ctx->hv_compact = 0;
   lrei_status st = alloc_state(ctx, ctx->r, false);
   if (st == LREI_OK) {
     e = hipMemcpyAsync(ctx->blocks[0].p, wide, n * sizeof(double2), hipMemcpyDeviceToDevice, ctx->stream);
@@ -1879,6 +1886,8 @@ static std::string tune_key(lrei_ctx *ctx) {
   return buf;
 }
 
+constexpr int kTuneMax = LREI_TUNE_MAX;
+
 lrei_status lrei_autotune(lrei_ctx *ctx, lrei_tune_result *out) {
   if (!ctx) return LREI_E_INVALID;
   if (!ctx->have_rho) return ctx->fail(LREI_E_STATE, "set rho before tuning");
@@ -1887,8 +1896,13 @@ lrei_status lrei_autotune(lrei_ctx *ctx, lrei_tune_result *out) {
   const std::string key = tune_key(ctx);
   const char *cache = ctx->opt.autotune_cache;
   const int r = ctx->r;
+  // variant code: 0 untiled, 1 untiled with compacted gathers, 100 k + w the
+  // tiled pass with 2^k-row tiles and w waves
+  const bool compact_ok = r <= 16 && ctx->dt.n_off <= 64;
   auto tile_valid = [&](int e, int g, int tile) {
     if (tile == 0) return true;
+    if (tile == 1) return compact_ok;
+    if (tile < 100) return false;
     const int tb = tile / 100, tw = tile % 100;
     return hv_tile_ok(ctx->fp32, r, e, tb, tw, ctx->N, g);
   };
@@ -1906,8 +1920,9 @@ lrei_status lrei_autotune(lrei_ctx *ctx, lrei_tune_result *out) {
           res.epl = e;
           res.grid = g;
           res.win_bits = w;
-          res.tile_bits = tile / 100;
-          res.tile_waves = tile % 100;
+          res.tile_bits = tile >= 100 ? tile / 100 : 0;
+          res.tile_waves = tile >= 100 ? tile % 100 : 0;
+          res.compact = tile == 1;
           res.ms = ms;
           res.from_cache = 1;
         }
@@ -1934,6 +1949,10 @@ lrei_status lrei_autotune(lrei_ctx *ctx, lrei_tune_result *out) {
         if (g <= tiles64 && g <= kMaxHvGrid) cands.push_back({e, g, 0, 0});
     if (cands.empty())
       for (int e : epls) cands.push_back({e, nspace_grid(ctx->N, r), 0, 0});
+    if (compact_ok) {  // the same shapes with compacted gathers
+      const size_t nu = cands.size();
+      for (size_t i = 0; i < nu; ++i) cands.push_back({cands[i].e, cands[i].g, 0, 1});
+    }
     for (int e : epls)
       for (int waves : {16, 8}) {
         int kmax = 0;
@@ -1957,10 +1976,11 @@ lrei_status lrei_autotune(lrei_ctx *ctx, lrei_tune_result *out) {
     lrei_status st0 = hv_set_plan(ctx, 0);
     if (st0 != LREI_OK) return st0;
     for (const Cand &c : cands) {
-      if (res.n_tried >= 64) break;
+      if (res.n_tried >= kTuneMax) break;
       ctx->epl = c.e;
-      ctx->hv_tile_bits = c.tile / 100;
-      ctx->hv_tile_waves = c.tile % 100;
+      ctx->hv_tile_bits = c.tile >= 100 ? c.tile / 100 : 0;
+      ctx->hv_tile_waves = c.tile >= 100 ? c.tile % 100 : 16;
+      ctx->hv_compact = c.tile == 1;
       const int iters = 5;
       bool launched = true;
       auto pass = [&]() {
@@ -1992,8 +2012,9 @@ lrei_status lrei_autotune(lrei_ctx *ctx, lrei_tune_result *out) {
         res.epl = c.e;
         res.grid = c.g;
         res.win_bits = c.w;
-        res.tile_bits = c.tile / 100;
-        res.tile_waves = c.tile % 100;
+        res.tile_bits = c.tile >= 100 ? c.tile / 100 : 0;
+        res.tile_waves = c.tile >= 100 ? c.tile % 100 : 0;
+        res.compact = c.tile == 1;
         res.ms = ms;
       }
     }
@@ -2003,7 +2024,7 @@ lrei_status lrei_autotune(lrei_ctx *ctx, lrei_tune_result *out) {
     if (cache)
       if (FILE *f = std::fopen(cache, "a")) {
         std::fprintf(f, "%s %d %d %d %d %.6f\n", key.c_str(), res.epl, res.grid, res.win_bits,
-                     res.tile_bits > 0 ? 100 * res.tile_bits + res.tile_waves : 0, res.ms);
+                     res.tile_bits > 0 ? 100 * res.tile_bits + res.tile_waves : (res.compact ? 1 : 0), res.ms);
         std::fclose(f);
       }
   }
@@ -2014,6 +2035,7 @@ lrei_status lrei_autotune(lrei_ctx *ctx, lrei_tune_result *out) {
   ctx->hv_grid = res.grid;
   ctx->hv_tile_bits = res.tile_bits;
   ctx->hv_tile_waves = res.tile_bits > 0 ? res.tile_waves : 16;
+  ctx->hv_compact = res.compact;
   ctx->drop_graph();
   if (out) *out = res;
   return LREI_OK;

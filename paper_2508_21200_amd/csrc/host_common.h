@@ -130,13 +130,15 @@ inline lrei_status upload_terms(const TermTable &t, long long N, hipStream_t s, 
     off[i].mask = off32[i].mask = t.off[i].mask;
     off[i].sa = off32[i].sa = t.off[i].sa;
     off[i].sb = off32[i].sb = t.off[i].sb;
-    off[i].pad = off32[i].pad = 0;
+    off[i].act = off32[i].act = 0;
     for (int q = 0; q < 4; ++q) {
       off[i].re[q] = t.off[i].re[q];
       off[i].im[q] = t.off[i].im[q];
       off32[i].re[q] = (float)t.off[i].re[q];
       off32[i].im[q] = (float)t.off[i].im[q];
       if (t.off[i].im[q] != 0.0) cplx = 1;
+      if (off[i].re[q] != 0.0 || off[i].im[q] != 0.0) off[i].act |= 1u << q;
+      if (off32[i].re[q] != 0.0f || off32[i].im[q] != 0.0f) off32[i].act |= 1u << q;
     }
   }
   std::vector<DevDiagTerm> dg(t.diag.size());

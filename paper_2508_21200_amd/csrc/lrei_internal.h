@@ -43,7 +43,9 @@ bool build_terms(int n, int n_bonds, const int32_t *bond_ij, const double *bond_
 // Device-side term record in the storage precision T of the pass.
 template <typename T>
 struct DevTerm {
-  uint32_t mask, sa, sb, pad;
+  // act: bit q set when the coefficient for destination bits q = b_sa + 2 b_sb
+  // is non-zero (the rows for which the term gathers a partner)
+  uint32_t mask, sa, sb, act;
   T re[4], im[4];
 };
 using DevOffTerm = DevTerm<double>;
@@ -100,6 +102,11 @@ struct HvArgs {
   int tile_bits;
   int tile_waves;
   int n_local;
+  // compacted gathers (untiled pass, r <= 16, at most 64 terms per launch):
+  // each row walks only its active terms; the term records sit in LDS at
+  // byte offset cmp_off (set by the launcher)
+  int compact;
+  int cmp_off;
 };
 
 // Launches one H.V pass; returns the number of Gram partial slots written

@@ -263,9 +263,22 @@ __device__ inline T pick4(int idx, T c0, T c1, T c2, T c3) {
 }
 
 // E complex columns per lane, CPLX: some coefficient has an imaginary part,
-// MI: Gram work items per wave, WIN: row-bit window sweeps allowed.  wg is the
-// workgroup's index among the a.grid workgroups of this pass.
-template <typename T, int E, bool CPLX, int MI, bool WIN, bool DYN>
+// MI: Gram work items per wave, WIN: row-bit window sweeps allowed, CMP:
+// compacted gathers (below).  wg is the workgroup's index among the a.grid
+// workgroups of this pass.
+//
+// Compacted gathers: a row needs the partner rows of the terms whose
+// coefficient is non-zero for its two destination bits only (for an XXZ bond,
+// about half of them).  With the term loop shared by the wave, every load
+// instruction is issued for every term and carries only the lanes whose rows
+// need it.  In the compacted form each row first marks its active terms in a
+// 64-bit mask (the term's active pattern over the four destination-bit values
+// is kept in the record), then every lane walks its own active
+// terms in increasing order, reading the records from a copy in LDS, so that
+// the wave issues max over its rows of the active-term count of loads per
+// batch slot instead of the full term count.  The accumulation order of a row
+// is the same in both forms, so their results are identical.
+template <typename T, int E, bool CPLX, int MI, bool WIN, bool DYN, bool CMP = false>
 __device__ __forceinline__ void hv_body(const HvArgs &a, int wg, unsigned char *smem) {
   static_assert(!DYN || (MI == 1 && !WIN), "the dynamic schedule keeps one Gram item per wave in LDS");
   // row gathers in flight per lane: kept small so that four waves fit per SIMD
@@ -294,6 +307,16 @@ __device__ __forceinline__ void hv_body(const HvArgs &a, int wg, unsigned char *
   TermC *terms = (TermC *)(a.terms);
   const T *__restrict__ dv = reinterpret_cast<const T *>(a.diagv);
   const T *__restrict__ Yin = reinterpret_cast<const T *>(a.acc_in);
+
+  // compacted gathers: the terms t0 .. t1 - 1 (at most 64) copied to LDS
+  DevTerm<T> *lterm = reinterpret_cast<DevTerm<T> *>(smem + a.cmp_off);
+  if constexpr (CMP) {
+    const int nt = a.t1 - a.t0;
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(a.terms) + (size_t)a.t0 * (sizeof(DevTerm<T>) / 4);
+    uint32_t *dst = reinterpret_cast<uint32_t *>(lterm);
+    for (int i = threadIdx.x; i < nt * (int)(sizeof(DevTerm<T>) / 4); i += kThreads) dst[i] = src[i];
+    __syncthreads();
+  }
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int cl = lane % L, rsub = lane / L;
@@ -432,23 +455,7 @@ __device__ __forceinline__ void hv_body(const HvArgs &a, int wg, unsigned char *
 #pragma unroll
         for (int e = 0; e < 2 * E; ++e) o[e] += yv[e];
       }
-      for (int t = t0; t < t1; t += B) {
-        T y[B][2 * E];
-        T cr[B], ci[B];
-#pragma unroll
-        for (int u = 0; u < B; ++u) {
-          cr[u] = T(0);
-          ci[u] = T(0);
-#pragma unroll
-          for (int e = 0; e < 2 * E; ++e) y[u][e] = T(0);
-          if (t + u < t1) {
-            TermC &tm = terms[t + u];
-            const int idx = (int)(((xu >> tm.sa) & 1u) | (((xu >> tm.sb) & 1u) << 1));
-            cr[u] = pick4(idx, tm.re[0], tm.re[1], tm.re[2], tm.re[3]);
-            if (CPLX) ci[u] = pick4(idx, tm.im[0], tm.im[1], tm.im[2], tm.im[3]);
-            if (cr[u] != T(0) || ci[u] != T(0)) ld(Pc, (size_t)(xu ^ tm.mask) * r, y[u]);
-          }
-        }
+      auto fma_batch = [&](const T (&y)[B][2 * E], const T (&cr)[B], const T (&ci)[B]) {
 #pragma unroll
         for (int u = 0; u < B; ++u)
 #pragma unroll
@@ -460,6 +467,60 @@ __device__ __forceinline__ void hv_body(const HvArgs &a, int wg, unsigned char *
               o[2 * e + 1] += ci[u] * y[u][2 * e];
             }
           }
+      };
+      if constexpr (CMP) {
+        // active terms of this row: bit k for term t0 + k
+        uint32_t am0 = 0, am1 = 0;
+        for (int t = t0; t < t1; ++t) {
+          TermC &tm = terms[t];
+          const uint32_t idx = ((xu >> tm.sa) & 1u) | (((xu >> tm.sb) & 1u) << 1);
+          const uint32_t bit = (tm.act >> idx) & 1u;
+          const int k = t - t0;
+          if (k < 32) am0 |= bit << k;
+          else am1 |= bit << (k - 32);
+        }
+        uint64_t act = ((uint64_t)am1 << 32) | am0;
+        while (__any(act != 0)) {
+          T y[B][2 * E];
+          T cr[B], ci[B];
+#pragma unroll
+          for (int u = 0; u < B; ++u) {
+            cr[u] = T(0);
+            ci[u] = T(0);
+#pragma unroll
+            for (int e = 0; e < 2 * E; ++e) y[u][e] = T(0);
+            if (act != 0) {
+              const int k = __builtin_ctzll(act);
+              act &= act - 1;
+              const DevTerm<T> &tm = lterm[k];
+              const int idx = (int)(((xu >> tm.sa) & 1u) | (((xu >> tm.sb) & 1u) << 1));
+              cr[u] = tm.re[idx];
+              if (CPLX) ci[u] = tm.im[idx];
+              ld(Pc, (size_t)(xu ^ tm.mask) * r, y[u]);
+            }
+          }
+          fma_batch(y, cr, ci);
+        }
+      } else {
+        for (int t = t0; t < t1; t += B) {
+          T y[B][2 * E];
+          T cr[B], ci[B];
+#pragma unroll
+          for (int u = 0; u < B; ++u) {
+            cr[u] = T(0);
+            ci[u] = T(0);
+#pragma unroll
+            for (int e = 0; e < 2 * E; ++e) y[u][e] = T(0);
+            if (t + u < t1) {
+              TermC &tm = terms[t + u];
+              const int idx = (int)(((xu >> tm.sa) & 1u) | (((xu >> tm.sb) & 1u) << 1));
+              cr[u] = pick4(idx, tm.re[0], tm.re[1], tm.re[2], tm.re[3]);
+              if (CPLX) ci[u] = pick4(idx, tm.im[0], tm.im[1], tm.im[2], tm.im[3]);
+              if (cr[u] != T(0) || ci[u] != T(0)) ld(Pc, (size_t)(xu ^ tm.mask) * r, y[u]);
+            }
+          }
+          fma_batch(y, cr, ci);
+        }
       }
       if (!a.acc_out) {
 #pragma unroll
@@ -499,11 +560,11 @@ __device__ __forceinline__ void hv_body(const HvArgs &a, int wg, unsigned char *
   }
 }
 
-template <typename T, int E, bool CPLX, int MI, bool DYN>
+template <typename T, int E, bool CPLX, int MI, bool DYN, bool CMP>
 __global__ __launch_bounds__(kThreads) void k_hv(HvArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   if (a.skip && *a.skip != 0.0) return;  // the same for every workgroup of the launch
-  hv_body<T, E, CPLX, MI, !DYN, DYN>(a, blockIdx.x, smem);
+  hv_body<T, E, CPLX, MI, !DYN, DYN, CMP>(a, blockIdx.x, smem);
 }
 
 // Many independent passes in one launch (one per trajectory of a batch): the
@@ -1143,15 +1204,26 @@ size_t hv_lds_bytes(bool fp32, int r) { return hv_lds(fp32, r); }
 
 size_t hv_lds_dyn_extra() { return (size_t)8 * kThreads * sizeof(double); }
 
-template <typename T, int E, bool C, int MI, bool DYN>
-static void launch_one(const HvArgs &a, size_t lds, hipStream_t s) {
+template <typename T, int E, bool C, int MI, bool DYN, bool CMP>
+static void launch_one_v(const HvArgs &a, size_t lds, hipStream_t s) {
   static bool attr = false;
   if (!attr) {
-    (void)hipFuncSetAttribute((const void *)k_hv<T, E, C, MI, DYN>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute((const void *)k_hv<T, E, C, MI, DYN, CMP>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               kMaxLds);
     attr = true;
   }
-  hipLaunchKernelGGL((k_hv<T, E, C, MI, DYN>), dim3(a.grid), dim3(kThreads), lds, s, a);
+  hipLaunchKernelGGL((k_hv<T, E, C, MI, DYN, CMP>), dim3(a.grid), dim3(kThreads), lds, s, a);
+}
+
+template <typename T, int E, bool C, int MI, bool DYN>
+static void launch_one(const HvArgs &a, size_t lds, hipStream_t s) {
+  if constexpr (MI == 1) {  // compacted gathers: r <= 16
+    if (a.compact) {
+      launch_one_v<T, E, C, MI, DYN, true>(a, lds, s);
+      return;
+    }
+  }
+  launch_one_v<T, E, C, MI, DYN, false>(a, lds, s);
 }
 
 template <typename T, int E, bool C, int MI, bool DYN>
@@ -1289,6 +1361,7 @@ bool prepare_hv(bool fp32, HvArgs &a) {
   if (L > 64) return false;
   const bool big = a.r > 16;  // three Gram work items per wave above r = 16
   if (fp32 ? (big && E > 2) || (!big && E > 8) : (big && E != 1) || (!big && E > 4)) return false;
+  if (a.compact && (big || a.t1 - a.t0 > 64)) return false;
   a.lanes = L;
   a.epl = E;
   a.terms = fp32 ? (const void *)a.terms32 : (const void *)a.terms64;
@@ -1311,7 +1384,9 @@ bool prepare_hv(bool fp32, HvArgs &a) {
 
 size_t hv_launch_lds(bool fp32, const HvArgs &a) {
   if (a.tile_bits > 0) return hv_tile_lds(fp32, a.r, a.epl, a.tile_bits, a.tile_waves);
-  return hv_lds(fp32, a.r) + (a.chunks > 0 ? hv_lds_dyn_extra() : 0);
+  const size_t base = hv_lds(fp32, a.r) + (a.chunks > 0 ? hv_lds_dyn_extra() : 0);
+  if (!a.compact) return base;
+  return base + (size_t)(a.t1 - a.t0) * (fp32 ? sizeof(DevTerm<float>) : sizeof(DevTerm<double>));
 }
 
 template <typename T, int E, bool C, int W>
@@ -1356,6 +1431,7 @@ int launch_hv(bool fp32, const HvArgs &a0, hipStream_t s) {
   HvArgs a = a0;
   if (!prepare_hv(fp32, a)) return 0;
   const size_t lds = hv_launch_lds(fp32, a);
+  a.cmp_off = (int)(hv_lds(fp32, a.r) + (a.chunks > 0 ? hv_lds_dyn_extra() : 0));
   if (a.tile_bits > 0) return launch_tile(fp32, a, lds, s) ? a.grid : 0;
   const bool ok = dispatch_hv(fp32, a.epl, a.cplx != 0, a.r > 16, a.chunks > 0,
                                 [&]<typename T, int E, bool C, int MI, bool DYN>() {

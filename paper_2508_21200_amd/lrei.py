@@ -49,13 +49,17 @@ class lrei_stats(ctypes.Structure):
         return d
 
 
+TUNE_MAX = 128  # LREI_TUNE_MAX
+
+
 class lrei_tune_result(ctypes.Structure):
     _fields_ = [("epl", ctypes.c_int), ("grid", ctypes.c_int), ("win_bits", ctypes.c_int),
                 ("n_sweeps", ctypes.c_int), ("ms", ctypes.c_double),
                 ("from_cache", ctypes.c_int), ("n_tried", ctypes.c_int),
-                ("tried_epl", ctypes.c_int * 64), ("tried_grid", ctypes.c_int * 64),
-                ("tried_win", ctypes.c_int * 64), ("tried_ms", ctypes.c_double * 64),
-                ("tile_bits", ctypes.c_int), ("tile_waves", ctypes.c_int), ("tried_tile", ctypes.c_int * 64)]
+                ("tried_epl", ctypes.c_int * TUNE_MAX), ("tried_grid", ctypes.c_int * TUNE_MAX),
+                ("tried_win", ctypes.c_int * TUNE_MAX), ("tried_ms", ctypes.c_double * TUNE_MAX),
+                ("tile_bits", ctypes.c_int), ("tile_waves", ctypes.c_int), ("tried_tile", ctypes.c_int * TUNE_MAX),
+                ("compact", ctypes.c_int)]
 
 
 class lrei_traj_desc(ctypes.Structure):
@@ -326,6 +330,7 @@ class Context:
         self._check(self.lib.lrei_autotune(self.h, ctypes.byref(t)))
         return {"epl": t.epl, "grid": t.grid, "win_bits": t.win_bits, "n_sweeps": t.n_sweeps, "ms": t.ms,
                 "from_cache": bool(t.from_cache), "tile_bits": t.tile_bits, "tile_waves": t.tile_waves,
+                "compact": bool(t.compact),
                 "tried": [(t.tried_epl[i], t.tried_grid[i], t.tried_win[i], t.tried_ms[i])
                           for i in range(t.n_tried)],
                 "tried_tile": [t.tried_tile[i] for i in range(t.n_tried)]}
