@@ -5,8 +5,8 @@
 // samples are recorded by the RK stage kernel (features of the stage and the
 // overlap T = u* u_next of its input basis with its output eigenvectors);
 // training minimises the mean over a batch of sum_a (1 - |(R* T)_aa|^2) with
-// Adam.  Forward: four layer products (tiled FP32 GEMM with the bias and SiLU
-// fused); per-sample Cayley map, loss and its gradient with respect to the
+// Adam.  Forward: four layer products (tiled FP32 GEMM on MFMA with the bias
+// and SiLU fused); per-sample Cayley map, loss and its gradient with respect to the
 // network outputs (one wave per sample, FP64); backward: the layer products
 // transposed, with SiLU' fused, and column sums for the biases.
 #include <hip/hip_runtime.h>
@@ -41,60 +41,80 @@ namespace {
 
 constexpr int kGemmT = 64, kGemmK = 16;
 
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
 // C[M x N] = op(A)[M x K] op(B)[K x N]; op(A)(m, k) = ta ? A[k lda + m] : A[m lda + k],
 // op(B)(k, n) = tb ? B[n ldb + k] : B[k ldb + n].  Epilogue ep: 0 store; 1 add
 // bias[n], store Z = C and H = silu(C); 2 multiply by silu'(Zp[m ldc + n]).
+// A workgroup of four waves forms a 64 x 64 tile of C: K is walked in chunks
+// of 16 staged in LDS (transposed operands are gathered there), and each wave
+// accumulates a 32 x 32 quarter as 2 x 2 FP32 16 x 16 x 4 MFMA tiles.  Operand
+// lanes: A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k; the result
+// D[4 g + v][j] sits in lane j + 16 g, register v.
 __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const float *__restrict__ A, int lda, int ta,
                                               const float *__restrict__ B, int ldb, int tb, float *__restrict__ C,
                                               int ldc, int ep, const float *__restrict__ bias, float *__restrict__ H,
                                               const float *__restrict__ Zp) {
   __shared__ float As[kGemmK][kGemmT + 4], Bs[kGemmK][kGemmT + 4];
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;  // the wave's quarter of the tile
   const int m0 = blockIdx.y * kGemmT, n0 = blockIdx.x * kGemmT;
-  float acc[4][4] = {};
+  f4_t acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = f4_t{0.0f, 0.0f, 0.0f, 0.0f};
   for (int k0 = 0; k0 < K; k0 += kGemmK) {
     for (int e = threadIdx.x; e < kGemmK * kGemmT; e += 256) {
-      const int kk = e / kGemmT, mm = e % kGemmT;
+      // consecutive threads walk the operand's contiguous index (k for A
+      // stored by rows of op(A), m for a transposed A; likewise for B)
+      const int kk = ta ? e / kGemmT : e % kGemmK, mm = ta ? e % kGemmT : e / kGemmK;
       const int gm = m0 + mm, gk = k0 + kk;
       As[kk][mm] = (gm < M && gk < K) ? (ta ? A[(long long)gk * lda + gm] : A[(long long)gm * lda + gk]) : 0.0f;
-      const int gn = n0 + mm;
-      Bs[kk][mm] = (gn < N && gk < K) ? (tb ? B[(long long)gn * ldb + gk] : B[(long long)gk * ldb + gn]) : 0.0f;
+      const int kb = tb ? e % kGemmK : e / kGemmT, nn = tb ? e / kGemmK : e % kGemmT;
+      const int gn = n0 + nn, gkb = k0 + kb;
+      Bs[kb][nn] = (gn < N && gkb < K) ? (tb ? B[(long long)gn * ldb + gkb] : B[(long long)gkb * ldb + gn]) : 0.0f;
     }
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < kGemmK; ++kk) {
-      float a[4], b[4];
+    for (int kk = 0; kk < kGemmK; kk += 4) {
+      float a[2], b[2];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kk][ty * 4 + i];
+      for (int t = 0; t < 2; ++t) {
+        a[t] = As[kk + lk][wm + 16 * t + li];
+        b[t] = Bs[kk + lk][wn + 16 * t + li];
+      }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx * 4 + j];
+      for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+        for (int tj = 0; tj < 2; ++tj)
+          acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ti], b[tj], acc[ti][tj], 0, 0, 0);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int gm = m0 + ty * 4 + i, gn = n0 + tx * 4 + j;
-      if (gm >= M || gn >= N) continue;
-      const long long q = (long long)gm * ldc + gn;
-      float v = acc[i][j];
-      if (ep == 1) {
-        v += bias[gn];
-        C[q] = v;
-        H[q] = silu_f(v);
-      } else if (ep == 2) {
-        const float z = Zp[q];
-        const float s = 1.0f / (1.0f + __expf(-z));
-        C[q] = v * s * (1.0f + z * (1.0f - s));
-      } else {
-        C[q] = v;
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int gm = m0 + wm + 16 * ti + 4 * lk + v, gn = n0 + wn + 16 * tj + li;
+        if (gm >= M || gn >= N) continue;
+        const long long q = (long long)gm * ldc + gn;
+        float val = acc[ti][tj][v];
+        if (ep == 1) {
+          val += bias[gn];
+          C[q] = val;
+          H[q] = silu_f(val);
+        } else if (ep == 2) {
+          const float z = Zp[q];
+          const float sg = 1.0f / (1.0f + __expf(-z));
+          C[q] = val * sg * (1.0f + z * (1.0f - sg));
+        } else {
+          C[q] = val;
+        }
       }
-    }
 }
 
 void gemm(int M, int N, int K, const float *A, int lda, int ta, const float *B, int ldb, int tb, float *C, int ldc,
