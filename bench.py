@@ -64,6 +64,9 @@ def parse():
                     help="work-precision table: adaptive RK4(3) / BS3(2) / HE2(1) against fixed-step RK4")
     ap.add_argument("--scaling-report", action="store_true",
                     help="q-LLG RK4 step time with observables against n (triangular lattices) and r = 1..4")
+    ap.add_argument("--train-only", action="store_true",
+                    help="with --learned-report: record and train only (no evaluation runs); for counter "
+                         "collection on the training kernels")
     ap.add_argument("--train-traj", type=int, default=100)
     ap.add_argument("--train-steps", type=int, default=200)
     ap.add_argument("--train-epochs", type=int, default=20)
@@ -498,6 +501,10 @@ def run_learned_report(args, torch):
                                          "analytic": ex0,
                                          "network_trained": excess(net.rotations(held), Sh)}}
     print(f"[learned] trained: {json.dumps(training)}", file=sys.stderr, flush=True)
+    if args.train_only:
+        net.close()
+        print(json.dumps({"report": "learned start rotation: training only", "training": training}))
+        return
 
     cfg = make_config(5)
     model, dt, kappa, steps, warm_steps = cfg["model"], cfg["dt"], cfg["kappa"], cfg["steps"], 2
