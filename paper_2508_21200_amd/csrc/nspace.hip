@@ -243,6 +243,27 @@ __device__ inline void load_ce(const T *p, T (&v)[2 * E]) {
     }
   }
 }
+// Streaming stores of a pass's output block: written once, read by the next
+// pass; the non-temporal hint keeps them from displacing the L2 lines that
+// are reused (the pass's partner rows, the projected step's workspace).
+typedef float f2n_t __attribute__((ext_vector_type(2)));
+typedef float f4n_t __attribute__((ext_vector_type(4)));
+typedef double d2n_t __attribute__((ext_vector_type(2)));
+template <typename T, int E>
+__device__ inline void store_ce_nt(T *p, const T (&v)[2 * E]) {
+  if constexpr (sizeof(T) == 4 && E == 1) {
+    __builtin_nontemporal_store(f2n_t{v[0], v[1]}, reinterpret_cast<f2n_t *>(p));
+  } else if constexpr (sizeof(T) == 4) {
+#pragma unroll
+    for (int k = 0; k < E / 2; ++k)
+      __builtin_nontemporal_store(f4n_t{v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]},
+                                  reinterpret_cast<f4n_t *>(p) + k);
+  } else {
+#pragma unroll
+    for (int k = 0; k < E; ++k)
+      __builtin_nontemporal_store(d2n_t{v[2 * k], v[2 * k + 1]}, reinterpret_cast<d2n_t *>(p) + k);
+  }
+}
 template <typename T, int E>
 __device__ inline void store_ce(T *p, const T (&v)[2 * E]) {
   if constexpr (sizeof(T) == 4 && E == 1) {
@@ -526,7 +547,7 @@ __device__ __forceinline__ void hv_body(const HvArgs &a, int wg, unsigned char *
 #pragma unroll
         for (int e = 0; e < 2 * E; ++e) o[e] = alpha * (o[e] - csh[e >> 1] * own[e]);
       }
-      store_ce<T, E>(Pn + 2 * base, o);
+      store_ce_nt<T, E>(Pn + 2 * base, o);
       if (grams) {
         const int gl = by_window ? lr : (int)(x - row0);
 #pragma unroll
