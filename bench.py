@@ -578,6 +578,11 @@ def measure_batch(args, torch, precision, steps, warmup, n_oracle=2):
     b = Batch(trajs, precision=precision)
     print(f"[bench] workload {base['name']} precision={precision} warmup={warmup} steps={steps}",
           file=sys.stderr, flush=True)
+    tune = None
+    if not args.no_autotune:
+        tune = b.autotune(iters=10)
+        print(f"[bench] batch H.V shapes: {tune['ms_default']:.4f} -> {tune['ms']:.4f} ms per pass, "
+              f"{tune['choice']}", file=sys.stderr, flush=True)
     if warmup > 0:
         b.step(scheme, dt, warmup)
     b.synchronize()
@@ -589,6 +594,11 @@ def measure_batch(args, torch, precision, steps, warmup, n_oracle=2):
     elapsed = time.perf_counter() - t0
     print(f"[bench] batch: timed {steps} steps in {elapsed:.4f} s", file=sys.stderr, flush=True)
     out = {"elapsed": elapsed, "trajs": trajs, "base": base}
+    if tune is not None:
+        out["hv_tuning"] = {"ms_default": round(tune["ms_default"], 5), "ms": round(tune["ms"], 5),
+                            "choice": {str(r): c for r, c in tune["choice"].items()},
+                            "tried": len(tune["tried"]),
+                            "note": "one batched pass + its reduction, every rank class (lrei_batch_autotune)"}
     if args.profile_only:
         return out
     out["kernels_ms"] = b.profile_kernels(scheme, dt, iters=20)
@@ -606,6 +616,8 @@ def measure_batch(args, torch, precision, steps, warmup, n_oracle=2):
                          "dt": dt, "scheme": scheme}
     if precision == "mixed":
         ref = Batch(trajs, precision="fp64")
+        if not args.no_autotune:
+            ref.autotune(iters=10)
         if warmup > 0:
             ref.step(scheme, dt, warmup)
         ref.synchronize()
@@ -686,6 +698,8 @@ def batch_summary(m, precision, steps):
                           "GBs": round(ach, 1), "frac_of_hbm_peak": round(ach / HBM_PEAK_GBS, 4),
                           "model": "2 sum_t N_t r_t c per pass (read P_j, write P_{j+1})"}
         res["kernels_ms"] = {k: round(v, 5) for k, v in kms.items()}
+    if "hv_tuning" in m:
+        res["hv_tuning"] = m["hv_tuning"]
     for k in ("oracle", "vs_fp64", "compare"):
         if k in m:
             res[{"oracle": "parity", "vs_fp64": "vs_fp64_batch", "compare": "vs_plain_fp64"}[k]] = m[k]
@@ -730,6 +744,7 @@ def run_batch(args, torch):
         "vs_fp64_batch": summ.get("vs_fp64_batch"),
         "vs_plain_fp64": summ.get("vs_plain_fp64"),
         "kernels_ms": summ.get("kernels_ms"),
+        "hv_tuning": summ.get("hv_tuning"),
     }
     print(json.dumps(line))
 

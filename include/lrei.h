@@ -384,7 +384,7 @@ LREI_API lrei_status lrei_batch_energies(lrei_batch *b, double *energy);
 
 /* Measurement: average per-launch-set times (ms) over `iters` repetitions,
  * with HIP events on the batch's stream, of the kernels of one step of the
- * whole batch:  ms[0] one Chebyshev H.V pass (recurrence form) with fused
+ * whole batch:  ms[0] one Krylov H.V pass (recurrence form) with fused
  * Grams, all launch classes; ms[1] its reduction; ms[2] the s stages of the
  * projected step run back to back; ms[3] the basis combinations (written to
  * the rollback copies, so the state is unchanged).  Needs a completed
@@ -393,6 +393,39 @@ LREI_API lrei_status lrei_batch_profile_kernels(lrei_batch *b, int scheme, doubl
 
 /* Blocks until all work queued by the batch has finished. */
 LREI_API lrei_status lrei_batch_synchronize(lrei_batch *b);
+
+#define LREI_BATCH_TUNE_CLASSES 32
+
+typedef struct {
+  int n_classes;                       /* distinct ranks r in the batch                */
+  int rank[LREI_BATCH_TUNE_CLASSES];   /* class k's rank, ascending                    */
+  int epl[LREI_BATCH_TUNE_CLASSES];    /* chosen complex columns per lane (0: default) */
+  int wg_cap[LREI_BATCH_TUNE_CLASSES]; /* chosen cap on workgroups per trajectory and
+                                          pass (one per 64-row tile up to the cap; 256
+                                          by default)                                  */
+  double ms_default;                   /* one batched Krylov pass of every trajectory
+                                          and its Gram reduction, shapes as on entry   */
+  double ms;                           /* the same with the chosen shapes              */
+  int n_tried;                         /* candidates timed (records kept for at most
+                                          LREI_TUNE_MAX)                               */
+  int tried_rank[LREI_TUNE_MAX], tried_epl[LREI_TUNE_MAX], tried_cap[LREI_TUNE_MAX];
+  double tried_ms[LREI_TUNE_MAX];
+} lrei_batch_tune_result;
+
+/* Chooses the launch shape of the batched H.V pass (eq. 5.1 in the Krylov
+ * passes of Sec. 3.7) per rank class: for each distinct r in turn, every
+ * valid columns-per-lane value and workgroup cap (16 .. 1024 per trajectory)
+ * is set for all trajectories of that rank, and one pass of the whole batch
+ * plus its reduction is timed on the device (`iters` >= 1 repetitions after
+ * one warm-up, HIP events on the batch stream); the fastest is kept, then the
+ * next class is tuned with it in place.  Overwrites only the scratch Krylov
+ * blocks; the state is untouched.  Results change at rounding level (the
+ * Gram partial sums are split over a different number of workgroups); the
+ * captured step graph is rebuilt on the next lrei_batch_step.  out may be
+ * NULL.  On failure the shapes from before the call are restored; should
+ * that rebuild fail too, every later call on b returns LREI_E_STATE.
+ * Errors: LREI_E_INVALID, LREI_E_NOMEM, LREI_E_DEVICE, LREI_E_STATE. */
+LREI_API lrei_status lrei_batch_autotune(lrei_batch *b, int iters, lrei_batch_tune_result *out);
 
 /* Rank r of the current state (LREI_E_STATE before a state is set). */
 LREI_API lrei_status lrei_get_rank(lrei_ctx *ctx, int *r);

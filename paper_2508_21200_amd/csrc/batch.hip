@@ -13,6 +13,7 @@
 // a multiple of 8, so the XCD-aware tile mapping holds within a trajectory.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -30,7 +31,7 @@ using namespace lrei;
 namespace {
 
 constexpr int kMaxTraj = 1024;
-constexpr int kBatchMaxGrid = 256;  // workgroups per trajectory and pass
+constexpr int kBatchMaxGrid = 256;  // default cap on workgroups per trajectory and pass
 
 // Tables of one batched launch: per-job records and the workgroup -> job map.
 struct LaunchTables {
@@ -71,9 +72,11 @@ bool build_tables(const std::vector<Rec> &recs, const std::vector<int> &wgs, boo
   return true;
 }
 
-int batch_grid(long long N) {
+// Workgroups of one trajectory's pass: one per 64-row tile up to cap, a
+// multiple of 8 from 8 on (the XCD slots).
+int batch_grid(long long N, int cap = kBatchMaxGrid) {
   const long long tiles = (N + 63) / 64;
-  long long g = tiles < kBatchMaxGrid ? tiles : kBatchMaxGrid;
+  long long g = tiles < cap ? tiles : cap;
   if (g >= 8) g &= ~7LL;
   return (int)(g < 1 ? 1 : g);
 }
@@ -94,6 +97,7 @@ struct lrei_batch {
 
   struct Traj {
     int n = 0, r = 0, model = 0, grid = 1;
+    int hv_epl = 0, hv_cap = kBatchMaxGrid;  // H.V pass shape: columns per lane (0: default), workgroup cap
     long long N = 0;
     double kappa = 0;
     std::vector<double> lam;
@@ -136,6 +140,7 @@ struct lrei_batch {
 
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  bool unusable = false;  // launch tables could not be rebuilt after a failed autotune
 
   lrei_status fail(lrei_status st, const std::string &m) {
     err = m;
@@ -198,9 +203,12 @@ lrei_status alloc_traj(lrei_batch *b, lrei_batch::Traj &t, int idx) {
   return LREI_OK;
 }
 
-// Tables of the Krylov passes and their reductions (independent of the scheme).
-lrei_status build_pass_tables(lrei_batch *b) {
+// Tables of the Krylov passes and their reductions (independent of the scheme):
+// every pass, or pass j_only alone.  Each trajectory's pass takes its own
+// shape (hv_epl, hv_cap); its Gram partial buffer grows to the grid.
+lrei_status build_pass_tables(lrei_batch *b, int j_only = -1) {
   for (int j = 0; j < kMaxStages; ++j) {
+    if (j_only >= 0 && j != j_only) continue;
     std::map<std::tuple<int, int, int>, std::vector<int>> cls;  // (epl, big, dynamic) -> trajectories
     std::vector<HvArgs> args(b->tr.size());
     for (size_t q = 0; q < b->tr.size(); ++q) {
@@ -219,12 +227,15 @@ lrei_status build_pass_tables(lrei_batch *b) {
       a.alpha = t.terms.spread > 0 ? 1.0 / t.terms.spread : 1.0;
       a.colshift = t.ws.shifts + (size_t)j * t.r;
       a.mode = j == 0 ? 0 : 1;
+      a.epl = t.hv_epl;
+      a.grid = batch_grid(t.N, t.hv_cap);
+      if (!t.partials.ensure((size_t)a.grid * 3 * t.r * t.r * sizeof(double2)))
+        return b->fail(LREI_E_NOMEM, "device allocation failed");
       a.partials = (double2 *)t.partials.p;
-      a.grid = t.grid;
       // static tile schedule: a batched launch holds many workgroups per CU
       // slot, which the hardware dispatcher balances by itself
       a.sched = nullptr;
-      a.partial_cap = t.grid;
+      a.partial_cap = a.grid;
       if (!prepare_hv(b->fp32, a)) return b->fail(LREI_E_INVALID, "unsupported rank for the H.V pass");
       args[q] = a;
       cls[{a.epl, a.r > 16 ? 1 : 0, a.chunks > 0 ? 1 : 0}].push_back((int)q);
@@ -551,6 +562,7 @@ const char *lrei_batch_last_error(const lrei_batch *b) { return b ? b->err.c_str
 
 lrei_status lrei_batch_step(lrei_batch *b, int scheme, double dt, int n_steps) {
   if (!b) return LREI_E_INVALID;
+  if (b->unusable) return b->fail(LREI_E_STATE, "batch unusable: its launch tables could not be rebuilt");
   if (!(scheme >= LREI_RK1 && scheme <= LREI_RK4))
     return b->fail(LREI_E_INVALID, "batched stepping supports RK1..RK4");
   if (!(dt > 0) || !std::isfinite(dt)) return b->fail(LREI_E_INVALID, "dt must be positive and finite");
@@ -624,6 +636,7 @@ lrei_status lrei_batch_get_rho(lrei_batch *b, int traj, double *lambda, void *V,
 
 lrei_status lrei_batch_energies(lrei_batch *b, double *energy) {
   if (!b || !energy) return LREI_E_INVALID;
+  if (b->unusable) return b->fail(LREI_E_STATE, "batch unusable: its launch tables could not be rebuilt");
   BCHK(hipSetDevice(b->device));
   // pass 0 measures P0* P0 and P0* P1 with P1 = beta (H P0 - P0 D0) (scratch block 1;
   // the state is untouched), so (P0* H P0)_aa = (P0* P1)_aa / beta + D0_a (P0* P0)_aa
@@ -648,6 +661,7 @@ lrei_status lrei_batch_energies(lrei_batch *b, double *energy) {
 
 lrei_status lrei_batch_profile_kernels(lrei_batch *b, int scheme, double dt, int iters, double ms[4]) {
   if (!b || !ms || iters < 1) return LREI_E_INVALID;
+  if (b->unusable) return b->fail(LREI_E_STATE, "batch unusable: its launch tables could not be rebuilt");
   if (scheme != b->cur_scheme || dt != b->cur_dt)
     return b->fail(LREI_E_STATE, "run lrei_batch_step with this scheme and dt first");
   BCHK(hipSetDevice(b->device));
@@ -685,6 +699,130 @@ lrei_status lrei_batch_profile_kernels(lrei_batch *b, int scheme, double dt, int
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   BCHK(he);
+  return LREI_OK;
+}
+
+lrei_status lrei_batch_autotune(lrei_batch *b, int iters, lrei_batch_tune_result *out) {
+  if (!b || iters < 1) return LREI_E_INVALID;
+  if (b->unusable) return b->fail(LREI_E_STATE, "batch unusable: its launch tables could not be rebuilt");
+  BCHK(hipSetDevice(b->device));
+  BCHK(hipStreamSynchronize(b->stream));
+  BCHK(hipStreamSynchronize(b->side));
+  std::vector<int> ranks;
+  for (auto &t : b->tr)
+    if (std::find(ranks.begin(), ranks.end(), t.r) == ranks.end()) ranks.push_back(t.r);
+  std::sort(ranks.begin(), ranks.end());
+  std::vector<std::pair<int, int>> saved;
+  for (auto &t : b->tr) saved.push_back({t.hv_epl, t.hv_cap});
+  auto set_class = [&](int r, int epl, int cap) {
+    for (auto &t : b->tr)
+      if (t.r == r) {
+        t.hv_epl = epl;
+        t.hv_cap = cap;
+      }
+  };
+  // on any failure: the shapes from before the call, every table rebuilt
+  auto restore = [&](lrei_status st) {
+    (void)hipStreamSynchronize(b->stream);
+    for (size_t q = 0; q < b->tr.size(); ++q) {
+      b->tr[q].hv_epl = saved[q].first;
+      b->tr[q].hv_cap = saved[q].second;
+    }
+    const std::string e = b->err;
+    if (build_pass_tables(b) != LREI_OK) b->unusable = true;
+    b->drop_graph();
+    b->err = e;
+    return st;
+  };
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return b->fail(LREI_E_DEVICE, "event creation failed");
+  }
+  // one recurrence-form pass of every trajectory (all launch classes) and its
+  // reduction, on the batch stream; the state block is only read
+  constexpr int j = 1;
+  auto timed = [&](double &ms) -> bool {
+    auto once = [&] {
+      for (auto &g : b->hv[j])
+        launch_hv_batch(b->fp32, g.epl, g.cplx, g.big, g.dyn, g.t.view(), g.t.total_wg, g.lds, b->stream);
+      launch_reduce_batch(b->reduce[j].view(), b->reduce[j].total_wg, b->stream);
+    };
+    once();
+    (void)hipEventRecord(e0, b->stream);
+    for (int i = 0; i < iters; ++i) once();
+    (void)hipEventRecord(e1, b->stream);
+    if (hipEventSynchronize(e1) != hipSuccess || hipGetLastError() != hipSuccess) return false;
+    float t = 0;
+    (void)hipEventElapsedTime(&t, e0, e1);
+    ms = (double)t / iters;
+    return true;
+  };
+  auto finish = [&](lrei_status st) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return st == LREI_OK ? st : restore(st);
+  };
+  lrei_batch_tune_result res{};
+  lrei_status st = build_pass_tables(b, j);
+  if (st != LREI_OK) return finish(st);
+  double best = 0;
+  if (!timed(best)) return finish(b->fail(LREI_E_DEVICE, "timing the batched pass failed"));
+  res.ms_default = best;
+  static const int kCaps[] = {16, 32, 64, 128, 256, 512, 1024};
+  for (int r : ranks) {
+    int best_epl = 0, best_cap = kBatchMaxGrid;
+    for (auto &t : b->tr)
+      if (t.r == r) {
+        best_epl = t.hv_epl;
+        best_cap = t.hv_cap;
+        break;
+      }
+    std::vector<std::vector<int>> seen_grids[9];  // per columns-per-lane value
+    for (int epl : {1, 2, 4, 8}) {
+      if (!hv_epl_valid(b->fp32, r, epl)) continue;
+      for (int cap : kCaps) {
+        std::vector<int> grids;
+        for (auto &t : b->tr)
+          if (t.r == r) grids.push_back(batch_grid(t.N, cap));
+        auto &seen = seen_grids[epl];
+        if (std::find(seen.begin(), seen.end(), grids) != seen.end()) continue;  // same launch as a smaller cap
+        seen.push_back(grids);
+        set_class(r, epl, cap);
+        st = build_pass_tables(b, j);
+        if (st != LREI_OK) return finish(st);
+        double ms = 0;
+        if (!timed(ms)) return finish(b->fail(LREI_E_DEVICE, "timing the batched pass failed"));
+        if (res.n_tried < LREI_TUNE_MAX) {
+          res.tried_rank[res.n_tried] = r;
+          res.tried_epl[res.n_tried] = epl;
+          res.tried_cap[res.n_tried] = cap;
+          res.tried_ms[res.n_tried] = ms;
+          ++res.n_tried;
+        }
+        if (ms < best) {
+          best = ms;
+          best_epl = epl;
+          best_cap = cap;
+        }
+      }
+    }
+    set_class(r, best_epl, best_cap);
+    if (res.n_classes < LREI_BATCH_TUNE_CLASSES) {
+      res.rank[res.n_classes] = r;
+      res.epl[res.n_classes] = best_epl;
+      res.wg_cap[res.n_classes] = best_cap;
+      ++res.n_classes;
+    }
+  }
+  st = build_pass_tables(b, j);
+  if (st != LREI_OK) return finish(st);
+  if (!timed(res.ms)) return finish(b->fail(LREI_E_DEVICE, "timing the batched pass failed"));
+  st = build_pass_tables(b);  // every pass with the chosen shapes
+  if (st != LREI_OK) return finish(st);
+  b->drop_graph();
+  finish(LREI_OK);
+  if (out) *out = res;
   return LREI_OK;
 }
 

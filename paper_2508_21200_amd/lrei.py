@@ -62,6 +62,17 @@ class lrei_tune_result(ctypes.Structure):
                 ("compact", ctypes.c_int)]
 
 
+BATCH_TUNE_CLASSES = 32
+
+
+class lrei_batch_tune_result(ctypes.Structure):
+    _fields_ = [("n_classes", ctypes.c_int), ("rank", ctypes.c_int * BATCH_TUNE_CLASSES),
+                ("epl", ctypes.c_int * BATCH_TUNE_CLASSES), ("wg_cap", ctypes.c_int * BATCH_TUNE_CLASSES),
+                ("ms_default", ctypes.c_double), ("ms", ctypes.c_double), ("n_tried", ctypes.c_int),
+                ("tried_rank", ctypes.c_int * TUNE_MAX), ("tried_epl", ctypes.c_int * TUNE_MAX),
+                ("tried_cap", ctypes.c_int * TUNE_MAX), ("tried_ms", ctypes.c_double * TUNE_MAX)]
+
+
 class lrei_traj_desc(ctypes.Structure):
     _fields_ = [("n_spins", ctypes.c_int), ("n_bonds", ctypes.c_int), ("bond_ij", ctypes.c_void_p),
                 ("bond_J", ctypes.c_void_p), ("site_h", ctypes.c_void_p), ("r", ctypes.c_int),
@@ -119,6 +130,7 @@ _SIGS = {
     "lrei_batch_energies": (ctypes.c_int, [_P, _P]),
     "lrei_batch_profile_kernels": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_double, ctypes.c_int, _P]),
     "lrei_batch_synchronize": (ctypes.c_int, [_P]),
+    "lrei_batch_autotune": (ctypes.c_int, [_P, ctypes.c_int, _P]),
     "lrei_net_param_count": (ctypes.c_longlong, [ctypes.c_int]),
     "lrei_net_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, ctypes.c_int, _P, ctypes.c_uint64]),
     "lrei_net_destroy": (None, [_P]),
@@ -564,6 +576,16 @@ class Batch:
         ms = (ctypes.c_double * 4)()
         self._check(self.lib.lrei_batch_profile_kernels(self.h, SCHEMES[scheme], float(dt), int(iters), ms))
         return dict(hv_pass=ms[0], reduce=ms[1], projected_step=ms[2], combine=ms[3])
+
+    def autotune(self, iters=10):
+        """Chooses the batched H.V launch shape per rank class (lrei_batch_autotune);
+        returns the choice per rank and every timing."""
+        t = lrei_batch_tune_result()
+        self._check(self.lib.lrei_batch_autotune(self.h, int(iters), ctypes.byref(t)))
+        return {"ms_default": t.ms_default, "ms": t.ms,
+                "choice": {t.rank[k]: {"epl": t.epl[k], "wg_cap": t.wg_cap[k]} for k in range(t.n_classes)},
+                "tried": [(t.tried_rank[i], t.tried_epl[i], t.tried_cap[i], t.tried_ms[i])
+                          for i in range(min(t.n_tried, TUNE_MAX))]}
 
     def energies(self):
         e = np.zeros(len(self.shapes), dtype=np.float64)

@@ -115,6 +115,41 @@ def test_batch_mixed_within_1e5():
         assert err < 1e-5
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_autotune_keeps_parity(precision):
+    """lrei_batch_autotune between steps: every candidate shape it times runs on
+    the device, the chosen shapes cover every rank of the batch, and after it
+    (the step graph captured again) every trajectory still matches the oracle
+    (FP64 1e-11, mixed 1e-5) and, in FP64, the untuned batch to 1e-12 (the Gram
+    partial sums split differently)."""
+    from paper_2508_21200_amd import Batch
+    trajs = _mixed_batch()
+    ref = Batch(trajs, precision=precision)
+    ref.step("RK4", 0.01, 3)
+    b = Batch(trajs, precision=precision)
+    b.step("RK4", 0.01, 2)
+    res = b.autotune(iters=3)
+    print(f"{precision}: default {res['ms_default']:.4f} ms, tuned {res['ms']:.4f} ms, "
+          f"{len(res['tried'])} tried, choice {res['choice']}")
+    ranks = sorted({int(t["lam"].size) for t in trajs})
+    assert sorted(res["choice"]) == ranks
+    assert len(res["tried"]) >= len(ranks)
+    assert res["ms_default"] > 0 and res["ms"] > 0
+    assert all(ms > 0 for _, _, _, ms in res["tried"])
+    b.step("RK4", 0.01, 1)
+    tol = 1e-11 if precision == "fp64" else 1e-5
+    for q, t in enumerate(trajs):
+        Vg = b.get_rho(q)[1]
+        Vo = _oracle(t, "RK4", 0.01, 3)
+        err = rel_fro_error(Vg, t["lam"], Vo, t["lam"])
+        print(f"tuned {precision} traj {q} n={t['n']} r={t['lam'].size}: {err:.3e}")
+        assert err < tol
+        if precision == "fp64":
+            assert rel_fro_error(Vg, t["lam"], ref.get_rho(q)[1], t["lam"]) < 1e-12
+    b.close()
+    ref.close()
+
+
 def test_batch_energies():
     from paper_2508_21200_amd import Batch
     trajs = _mixed_batch()

@@ -149,3 +149,30 @@ def test_create_without_gpu_fails_cleanly():
     h = ctypes.c_void_p()
     st = lib.lrei_create(ctypes.byref(h), 0, None, None)
     assert st == 4 and not h.value  # LREI_E_DEVICE
+
+
+@pytest.mark.parametrize("name", ["lrei_options", "lrei_stats", "lrei_tune_result", "lrei_batch_tune_result",
+                                  "lrei_traj_desc", "lrei_adapt_result"])
+def test_binding_structs_match_the_header(name, tmp_path):
+    """Every ctypes structure of the binding has the C struct's size and each
+    field its offset (a C program built from include/lrei.h prints them)."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    from paper_2508_21200_amd import lrei
+    cls = getattr(lrei, name)
+    fields = [f[0] for f in cls._fields_]
+    cname = {"lambda_": "lambda"}
+    src = ['#include <stdio.h>', '#include <stddef.h>', '#include "lrei.h"', "int main(void) {",
+           f'  printf("%zu\\n", sizeof({name}));']
+    src += [f'  printf("%zu\\n", offsetof({name}, {cname.get(f, f)}));' for f in fields]
+    src += ["  return 0;", "}"]
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(src) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)], check=True)
+    vals = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    assert vals[0] == ctypes.sizeof(cls), (name, vals[0], ctypes.sizeof(cls))
+    for f, off in zip(fields, vals[1:]):
+        assert getattr(cls, f).offset == off, (name, f)
