@@ -959,7 +959,7 @@ def main():
             [round(v / args.steps, 4) for v in stats["phase_ms"]])),
         "eigensolve_parts_ms_per_step": dict(zip(
             ["tridiagonalisation", "multisection", "inverse_iteration", "back_transform",
-             "tridiag_Av", "tridiag_update"],
+             "warm_solver", "warm_ritz_step"],
             [round(v / args.steps, 4) for v in stats["eig_phase_ms"]])),
     }
     print(json.dumps(line))

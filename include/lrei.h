@@ -155,11 +155,12 @@ typedef struct {
   double phase_ms[8];            /* projected-step kernel time by phase over the last
                                     call: Gram/Cholesky setup, Cholesky, R^-1, H u,
                                     Householder, stage matrix, eigensolve, tail      */
-  double eig_phase_ms[6];        /* direct-eigensolver time over the last call by part:
-                                    tridiagonalisation, multisection, inverse
-                                    iteration, back-transform; and of the
-                                    tridiagonalisation: its A v products, its
-                                    rank-2 updates                                  */
+  double eig_phase_ms[6];        /* eigensolver time over the last call by part:
+                                    the direct solver's tridiagonalisation,
+                                    multisection, inverse iteration and
+                                    back-transform; the warm-started solver's
+                                    whole time (accepted or not) and its Ritz
+                                    step                                            */
 } lrei_stats;
 
 /* Fills *opt with the defaults listed above. */

@@ -131,7 +131,7 @@ __device__ inline double2 phi(double d, int model, double kappa, double hbar) {
 // operands read from memory (LDS or global).  C must not overlap A or B.
 // Ends with a barrier.
 typedef double d4v_g __attribute__((ext_vector_type(4)));
-__device__ void zgemm(double2 *C, int ldc, const double2 *A, int lda, bool ah, const double2 *B, int ldb, int M,
+__device__ __forceinline__ void zgemm(double2 *C, int ldc, const double2 *A, int lda, bool ah, const double2 *B, int ldb, int M,
                       int N, int K) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
@@ -319,7 +319,7 @@ __device__ int jacobi(double2 *A, double2 *V, int m, double tol, int max_sweeps,
 // wave only; A, V and js in LDS): each round costs wave-level
 // synchronisation instead of workgroup barriers, which is what dominates
 // for r x r problems.  Same rotations, same arithmetic per element.
-__device__ int jacobi_wave(double2 *A, double2 *V, int m, double tol, int max_sweeps, JacobiShared &js) {
+__device__ __forceinline__ int jacobi_wave(double2 *A, double2 *V, int m, double tol, int max_sweeps, JacobiShared &js) {
   const int lane = threadIdx.x & 63;
   const int mp = m + (m & 1), np = mp / 2;
   for (int e = lane; e < m * m; e += 64)
@@ -446,7 +446,7 @@ struct TriShared {
   double glo, ghi, tnorm;
   uint64_t tmark;
   double tacc[7];  // real-time ticks: tridiagonalisation, multisection, inverse iteration, back-transform,
-                   // and inside the tridiagonalisation: reflector, A v, rank-2 update
+                   // (unused), and the warm-started solver: whole, its Ritz step
 };
 
 // packed lower triangle, column-major: element (i, j), i >= j
@@ -491,8 +491,8 @@ __device__ inline int sturm_count(const TriShared &ts, int m, double s, double p
 // u (rows_out x r, ld ldu) <- eigenvectors of the r largest eigenvalues of A,
 // descending.  scr: >= 4 * m * SL doubles (SL = 16 for r <= 16, else 32), used
 // for the inverse-iteration LU and the back-transform.
-__device__ void eig_top(double2 *A, int m, int r, double2 *u, int ldu, int rows_out, double *scr, bool lds,
-                        TriShared &ts) {
+__device__ __forceinline__ void eig_top(double2 *A, int m, int r, double2 *u, int ldu, int rows_out, double *scr,
+                                        bool lds, TriShared &ts) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   auto tlap = [&](int slot) {
     __syncthreads();
@@ -503,9 +503,11 @@ __device__ void eig_top(double2 *A, int m, int r, double2 *u, int ldu, int rows_
     }
   };
   if (threadIdx.x == 0) ts.tmark = now_ticks();
-  // ---- Householder tridiagonalisation.  Threads form a 16 x 32 grid: half-wave
-  // hw owns rows k+1+hw, +16, ...; its lane hl walks columns k+1+hl, +32, ...
-  const int hw = threadIdx.x >> 5, hl = threadIdx.x & 31;
+  // ---- Householder tridiagonalisation.  A v and the rank-2 update give each
+  // trailing row to a group of 8 lanes (64 rows at a time), the lanes of a
+  // group walking the row's columns with stride 8: at m <= 64 every thread
+  // has at most 8 elements and the row sums are 3-step DPP reductions.
+  const int grow = threadIdx.x >> 3, gsub = threadIdx.x & 7;
   for (int k = 0; k + 2 < m; ++k) {
     if (wave == 0) {
       double s2 = 0;
@@ -536,50 +538,52 @@ __device__ void eig_top(double2 *A, int m, int r, double2 *u, int ldu, int rows_
       }
     }
     if (lds) lds_barrier(); else __syncthreads();
-    uint64_t t_a = 0;
-    if (threadIdx.x == 0) t_a = now_ticks();
     const double beta = ts.beta[k];
     if (beta != 0.0) {
-      // p = beta A22 v: half-wave rows, lane-strided columns, half-wave reduction
+      // p = beta A22 v, and this wave's part of v^H p
       double2 kp = make_double2(0, 0);
-      for (int i = k + 1 + hw; i < m; i += NT / 32) {
+      for (int i0 = k + 1; i0 < m; i0 += NT / 8) {
+        const int i = i0 + grow;
         double sr = 0, si = 0;
-        for (int j = k + 1 + hl; j < m; j += 32) {
-          const int hi = i > j ? i : j, lo = i > j ? j : i;
-          double2 a = A[pl(hi, lo, m)];
-          if (i < j) a.y = -a.y;
-          const double2 v = ts.v[j];
-          sr += a.x * v.x - a.y * v.y;
-          si += a.x * v.y + a.y * v.x;
+        if (i < m) {
+          for (int j = k + 1 + gsub; j < m; j += 8) {
+            const int hi = i > j ? i : j, lo = i > j ? j : i;
+            double2 a = A[pl(hi, lo, m)];
+            if (i < j) a.y = -a.y;
+            const double2 v = ts.v[j];
+            sr += a.x * v.x - a.y * v.y;
+            si += a.x * v.y + a.y * v.x;
+          }
         }
-        sr = sum32(sr);
-        si = sum32(si);
-        const double2 pi = make_double2(beta * sr, beta * si);
-        if (hl == 0) ts.p[i] = pi;
-        kp = cadd(kp, cmulc(ts.v[i], pi));
+        sr += dpp_d<0xB1>(sr);  // sum over the 8 lanes of the group
+        si += dpp_d<0xB1>(si);
+        sr += dpp_d<0x4E>(sr);
+        si += dpp_d<0x4E>(si);
+        sr += dpp_d<0x141>(sr);
+        si += dpp_d<0x141>(si);
+        if (i < m && gsub == 0) {
+          const double2 pi = make_double2(beta * sr, beta * si);
+          ts.p[i] = pi;
+          kp = cadd(kp, cmulc(ts.v[i], pi));
+        }
       }
-      if (hl == 0) ts.kpart[hw] = kp;
+      kp = wave_sum(kp);
+      if (lane == 0) ts.kpart[wave] = kp;
       if (lds) lds_barrier(); else __syncthreads();
-      uint64_t t_b = 0;
-      if (threadIdx.x == 0) {
-        t_b = now_ticks();
-        ts.tacc[5] += (double)(t_b - t_a);
-      }
       // K = (beta/2) v^H p (fixed summation order); w = p - K v
       double2 ks = make_double2(0, 0);
-      for (int q = 0; q < NT / 32; ++q) ks = cadd(ks, ts.kpart[q]);
+      for (int q = 0; q < NW; ++q) ks = cadd(ks, ts.kpart[q]);
       const double2 K = cscale(0.5 * beta, ks);
       // lower triangle of the trailing block: A_ij -= v_i conj(w_j) + w_i conj(v_j)
-      for (int i = k + 1 + hw; i < m; i += NT / 32) {
+      for (int i = k + 1 + grow; i < m; i += NT / 8) {
         const double2 vi = ts.v[i], wi = csub(ts.p[i], cmul(K, vi));
-        for (int j = k + 1 + hl; j <= i; j += 32) {
+        for (int j = k + 1 + gsub; j <= i; j += 8) {
           const double2 vj = ts.v[j], wj = csub(ts.p[j], cmul(K, vj));
           const int q = pl(i, j, m);
           A[q] = csub(A[q], cadd(cmul(vi, cconj(wj)), cmul(wi, cconj(vj))));
         }
       }
       if (lds) lds_barrier(); else __syncthreads();
-      if (threadIdx.x == 0) ts.tacc[6] += (double)(now_ticks() - t_b);
     }
   }
   tlap(0);
@@ -832,7 +836,7 @@ __device__ double block_sum(double v, double *red) {
 
 // Y (m x r, ld r) = K X for the packed Hermitian K; one 16 x 16 MFMA tile per
 // wave.  Ends with a barrier.
-__device__ void hemm_packed(double2 *Y, const double2 *K, int m, const double2 *X, int r) {
+__device__ __forceinline__ void hemm_packed(double2 *Y, const double2 *K, int m, const double2 *X, int r) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int mt = (m + 15) / 16, nt = (r + 15) / 16;
@@ -895,7 +899,7 @@ __device__ double resid_part(const double2 *Y, const double2 *X, const double2 *
 
 // X (m x r) <- X R^{-1} with X* X = R* R (Cholesky QR); C: r x r scratch.
 // Returns false (workgroup-uniform) if X* X is not numerically positive definite.
-__device__ bool chol_qr(double2 *X, int m, int r, double2 *C) {
+__device__ __forceinline__ bool chol_qr(double2 *X, int m, int r, double2 *C) {
   zgemm(C, r, X, r, true, X, r, r, r, m);  // C = X* X (ends with a barrier)
   // upper Cholesky factor in place, right-looking, all threads on each update
   for (int k = 0; k < r; ++k) {
@@ -927,12 +931,13 @@ __device__ bool chol_qr(double2 *X, int m, int r, double2 *C) {
 }
 
 // X (m x r) <- its polar factor X (X* X)^{-1/2} by Newton-Schulz steps
-// X <- X (3 I - X* X) / 2 (products on MFMA; the error squares each step).
+// X <- X (3 I - X* X) / 2 (products on MFMA; the error squares each step:
+// a step taken from |X* X - I| <= 1e-8 is the last one).
 // X and Y (m x r) swap roles as the iteration proceeds.  Returns false
 // (workgroup-uniform; X spans the same space) if X* X is too far from I for
 // the iteration or it does not settle.  For r <= 16 one wave forms X* X, its
 // distance from I and the step matrix in registers: two barriers per step.
-__device__ bool polar_ns(double2 *&X, double2 *&Y, int m, int r, double2 *C, double *red, int *flag) {
+__device__ __forceinline__ bool polar_ns(double2 *&X, double2 *&Y, int m, int r, double2 *C, double *red, int *flag) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int k = 0; k < 8; ++k) {
     if (r <= 16) {
@@ -966,7 +971,7 @@ __device__ bool polar_ns(double2 *&X, double2 *&Y, int m, int r, double2 *C, dou
           }
         }
         dv = max64(dv);
-        if (lane == 0) *flag = dv <= 4e-16 ? 1 : ((!(dv < 0.25) || k == 7) ? 2 : 0);
+        if (lane == 0) *flag = dv <= 4e-16 ? 1 : (dv <= 1e-8 ? 3 : ((!(dv < 0.25) || k == 7) ? 2 : 0));
       }
       __syncthreads();
     } else {
@@ -985,7 +990,7 @@ __device__ bool polar_ns(double2 *&X, double2 *&Y, int m, int r, double2 *C, dou
       for (int w = 0; w < NW; ++w) dev = fmax(dev, red[w]);
       for (int e = threadIdx.x; e < r * r; e += NT)  // C <- (3 I - C) / 2
         C[e] = e / r == e % r ? make_double2(1.5 - 0.5 * C[e].x, -0.5 * C[e].y) : cscale(-0.5, C[e]);
-      if (threadIdx.x == 0) *flag = dev <= 4e-16 ? 1 : ((!(dev < 0.25) || k == 7) ? 2 : 0);
+      if (threadIdx.x == 0) *flag = dev <= 4e-16 ? 1 : (dev <= 1e-8 ? 3 : ((!(dev < 0.25) || k == 7) ? 2 : 0));
       __syncthreads();
     }
     const int f = *flag;
@@ -996,6 +1001,77 @@ __device__ bool polar_ns(double2 *&X, double2 *&Y, int m, int r, double2 *C, dou
     double2 *t = X;
     X = Y;
     Y = t;
+    if (f == 3) return true;  // |X* X - I| <= 1e-8 before the step: about 1e-16 after it
+  }
+  return false;
+}
+
+// Largest value over the workgroup of one value per thread; every thread
+// gets the result.
+__device__ double block_max(double v, double *red) {
+  v = max64(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double t = red[0];
+  for (int w = 1; w < NW; ++w) t = fmax(t, red[w]);
+  return t;
+}
+
+// Eigenvectors of the Hermitian r x r G (ld r) by Newton refinement from
+// Z = I: with P = Z* Z, S = Z* G Z and theta_i = S_ii / P_ii, the correction
+// Z <- Z (I + E), E_ij = (S_ij - theta_j P_ij) / (theta_j - theta_i) (i != j),
+// E_ii = (1 - P_ii) / 2, removes the off-diagonal of S and the departure of
+// Z from orthonormality to first order together (the iterative refinement
+// of an eigendecomposition of Ogita and Aishima), so that the error squares
+// each step while the off-diagonal of G is small against the gaps of its
+// eigenvalues.  The Ritz step's G is close to diagonal (the subspace
+// iteration starts from the previous stage's eigenvectors), where this takes
+// three or four steps of three small products instead of Jacobi sweeps.
+// ZT (r x 2r, ld 2r) holds Z and G Z, PS (r x 2r, ld 2r) P and S, E (r x r)
+// the correction; theta (r) the eigenvalues.  On return Z (first r columns of
+// ZT) is orthonormal to rounding and diagonalises G to the same order.
+// Returns false (workgroup-uniform) if the step does not contract (close
+// eigenvalues), leaving G intact for another method.
+__device__ bool ritz_refine(const double2 *G, int r, double2 *ZT, double2 *PS, double2 *E, double *theta,
+                            double *red) {
+  const int r2 = 2 * r;
+  for (int e = threadIdx.x; e < r * r; e += NT) {
+    const int i = e / r, c = e % r;
+    ZT[i * r2 + c] = make_double2(i == c ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  for (int it = 0; it < 8; ++it) {
+    zgemm(ZT + r, r2, G, r, false, ZT, r2, r, r, r);  // G Z beside Z
+    zgemm(PS, r2, ZT, r2, true, ZT, r2, r, r2, r);    // [P | S] = Z* [Z | G Z]
+    for (int i = threadIdx.x; i < r; i += NT) theta[i] = PS[i * r2 + r + i].x / PS[i * r2 + i].x;
+    __syncthreads();
+    double off = 0;
+    for (int e = threadIdx.x; e < r * r; e += NT) {
+      const int i = e / r, j = e % r;
+      const double2 pij = PS[i * r2 + j];
+      double2 v;
+      if (i == j) {
+        v = make_double2(0.5 * (1.0 - pij.x), 0.0);
+      } else {
+        const double2 sij = PS[i * r2 + r + j];
+        const double inv = 1.0 / (theta[j] - theta[i]);
+        v = make_double2((sij.x - theta[j] * pij.x) * inv, (sij.y - theta[j] * pij.y) * inv);
+        const double a = sqrt(cabs2(v));
+        off = fmax(off, a == a ? a : 1e300);  // a NaN counts as no contraction
+      }
+      E[e] = v;
+    }
+    off = block_max(off, red);  // ends with a barrier: E is visible
+    if (!(off < 0.5)) return false;
+    zgemm(ZT + r, r2, ZT, r2, false, E, r, r, r, r);  // Z E
+    for (int e = threadIdx.x; e < r * r; e += NT) {
+      const int i = e / r, c = e % r;
+      ZT[i * r2 + c] = cadd(ZT[i * r2 + c], ZT[i * r2 + r + c]);
+    }
+    __syncthreads();
+    if (off < 1e-8) return true;  // the update just applied leaves an error of order off^2
   }
   return false;
 }
@@ -1018,7 +1094,8 @@ __device__ inline bool warm_fits(int m, int r, int arena_elems) {
 // else over K.  iters: iterations run.
 __device__ __forceinline__ bool warm_top(double2 *K, int m, int r, const double2 *S, int lds_in, double2 *u, int ldu,
                          int rows_out, double2 *arena, int arena_elems, int maxit, double tol, JacobiShared &js,
-                         int &iters, const double2 *rot = nullptr, const double *lam = nullptr) {
+                         int &iters, const double2 *rot = nullptr, const double *lam = nullptr,
+                         double *ritz_ticks = nullptr) {
   __shared__ double red[NW];
   __shared__ double s_lb[kMaxR];
   __shared__ int s_flag;
@@ -1108,10 +1185,35 @@ __device__ __forceinline__ bool warm_top(double2 *K, int m, int r, const double2
     for (int a = 0; a < r; ++a) lb = fmin(lb, s_lb[a]);
     if (!(lb - res > T + res + 1e-13 * sqrt(kn2))) return false;
   }
-  // Ritz vectors: G = Z diag(theta) Z*, theta descending, by cyclic Jacobi (G is
-  // close to diagonal: few sweeps) on its packed upper triangle
+  // Ritz vectors: G = Z diag(theta) Z*, theta descending, by Newton refinement
+  // (ZT over Y, [P | S] over the small problem's scratch, E over C), else by
+  // cyclic Jacobi (G is close to diagonal: few sweeps) on its packed upper
+  // triangle
   double2 *Gp = (npl + warm_need(m, r) + warm_small(r) <= arena_elems) ? C + r * r : K;
   double2 *Zj = Gp + r * (r + 1) / 2, *Z = Zj + r * r;
+  __shared__ double s_theta[kMaxR];
+  uint64_t t_ritz = 0;
+  if (threadIdx.x == 0) t_ritz = now_ticks();
+  auto ritz_done = [&] {
+    if (threadIdx.x == 0 && ritz_ticks) *ritz_ticks += (double)(now_ticks() - t_ritz);
+  };
+  if (m >= 2 * r && ritz_refine(G, r, Y, Gp, C, s_theta, red)) {
+    if (threadIdx.x < r) {  // rank by eigenvalue, descending (ties by index)
+      const int a = threadIdx.x;
+      int rank = 0;
+      for (int b = 0; b < r; ++b)
+        rank += (s_theta[b] > s_theta[a] || (s_theta[b] == s_theta[a] && b < a)) ? 1 : 0;
+      js.order[rank] = a;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < r * r; e += NT) C[e] = Y[(e / r) * 2 * r + js.order[e % r]];
+    __syncthreads();
+    zgemm(u, ldu, X, r, false, C, r, m, r, r);  // u = X Z
+    for (int e = threadIdx.x; e < (rows_out - m) * r; e += NT) u[(m + e / r) * ldu + e % r] = make_double2(0, 0);
+    __syncthreads();
+    ritz_done();
+    return true;
+  }
   for (int e = threadIdx.x; e < r * r; e += NT) {
     const int i = e / r, j = e % r;
     if (i <= j) Gp[pk(i, j)] = G[e];
@@ -1135,13 +1237,14 @@ __device__ __forceinline__ bool warm_top(double2 *K, int m, int r, const double2
   zgemm(u, ldu, X, r, false, Z, r, m, r, r);  // u = X Z
   for (int e = threadIdx.x; e < (rows_out - m) * r; e += NT) u[(m + e / r) * ldu + e % r] = make_double2(0, 0);
   __syncthreads();
+  ritz_done();
   return true;
 }
 
 // ----- pieces shared by the RK and AB projected-step kernels -------------------
 
 // 1 if any of the n complex values is not finite (workgroup-uniform).
-__device__ int any_nonfinite(const double2 *x, int n) {
+__device__ __forceinline__ int any_nonfinite(const double2 *x, int n) {
   int bad = 0;
   for (int e = threadIdx.x; e < n; e += NT)
     if (!isfinite(x[e].x) || !isfinite(x[e].y)) bad = 1;
@@ -1557,12 +1660,95 @@ __device__ inline d4v_s mfma_d(double a, double b, d4v_s c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 // Term l's factors are u0 + l*su, z0 + l*sz, w0 + l*sw; coef[l] may be in LDS.
-__device__ void stage_matrix(double2 *K, int m, int r, const double2 *u1, const double *lam, int nterm,
+__device__ __forceinline__ void stage_matrix(double2 *K, int m, int r, const double2 *u1, const double *lam, int nterm,
                              const double2 *u0, size_t su, const double2 *z0, size_t sz, const double2 *w0,
-                             size_t sw, const double *coef) {
+                             size_t sw, const double *coef, double2 *stg = nullptr, int stg_words = 0) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int mt = (m + 15) / 16, ntile = mt * (mt + 1) / 2;
   const int li = lane & 15, lk = lane >> 4;
+  const int ldp = r + 1;  // odd row pitch in 16-byte words: the 16 rows of a tile fall on distinct banks
+  if (stg && ntile <= 2 * NW && 2 * m * ldp <= stg_words) {
+    // Channel by channel: the workgroup copies the channel's two factor blocks
+    // (global, m x r each) into LDS with coalesced loads, then every wave adds
+    // the channel to its (at most two) tiles, kept in registers across the
+    // channels.  The factors are read from global memory once per channel
+    // instead of once per tile.  stg may overlap K.
+    double2 *Ps = stg, *Qs = stg + m * ldp;
+    d4v_s kre[2], kim[2];
+    int ra[2], rb[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      kre[q] = d4v_s{0, 0, 0, 0};
+      kim[q] = d4v_s{0, 0, 0, 0};
+      int ta = 0, rem = wave + q * NW;
+      while (rem > ta) {
+        rem -= ta + 1;
+        ++ta;
+      }
+      ra[q] = ta * 16 + li;
+      rb[q] = rem * 16 + li;
+    }
+    for (int ch = 0; ch < 1 + 2 * nterm; ++ch) {
+      const double2 *P, *Q;
+      double sc = 1.0;
+      if (ch == 0) {
+        if (!lam) continue;  // no u1 diag(lam) u1* term
+        P = u1;
+        Q = u1;
+      } else {
+        const int l = (ch - 1) / 2;
+        sc = coef[l];
+        if (sc == 0.0) continue;
+        P = (ch & 1) ? z0 + l * sz : u0 + l * su;
+        Q = (ch & 1) ? u0 + l * su : w0 + l * sw;
+      }
+      __syncthreads();  // the previous channel's products have read the blocks
+      for (int e = threadIdx.x; e < m * r; e += NT) {
+        const int i = e / r, c = e % r;
+        Ps[i * ldp + c] = P[e];
+        if (ch > 0) Qs[i * ldp + c] = Q[e];
+      }
+      __syncthreads();
+      const double2 *Qx = ch > 0 ? Qs : Ps;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        if (wave + q * NW >= ntile) break;  // the same for the whole wave
+        for (int kk = 0; kk < r; kk += 4) {
+          const int c = kk + lk;
+          const double sv = ch == 0 ? (c < r ? lam[c] : 0.0) : sc;
+          const bool ok = c < r;
+          const double2 z = make_double2(0, 0);
+          const double2 pa = (ok && ra[q] < m) ? Ps[ra[q] * ldp + c] : z, qa = (ok && ra[q] < m) ? Qx[ra[q] * ldp + c] : z;
+          const double2 pb = (ok && rb[q] < m) ? Ps[rb[q] * ldp + c] : z, qb = (ok && rb[q] < m) ? Qx[rb[q] * ldp + c] : z;
+          // (s pa) conj(qb) + qa conj(s pb)
+          const double a1r = sv * pa.x, a1i = sv * pa.y, b1r = qb.x, b1i = -qb.y;
+          const double a2r = qa.x, a2i = qa.y, b2r = sv * pb.x, b2i = -sv * pb.y;
+          kre[q] = mfma_d(a1r, b1r, kre[q]);
+          kre[q] = mfma_d(-a1i, b1i, kre[q]);
+          kim[q] = mfma_d(a1r, b1i, kim[q]);
+          kim[q] = mfma_d(a1i, b1r, kim[q]);
+          kre[q] = mfma_d(a2r, b2r, kre[q]);
+          kre[q] = mfma_d(-a2i, b2i, kre[q]);
+          kim[q] = mfma_d(a2r, b2i, kim[q]);
+          kim[q] = mfma_d(a2i, b2r, kim[q]);
+        }
+      }
+    }
+    __syncthreads();  // K may overlap the staging blocks
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      if (wave + q * NW >= ntile) break;
+      const int ta = (ra[q] - li) / 16, tb = (rb[q] - li) / 16;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = ta * 16 + 4 * v + lk, col = tb * 16 + li;
+        if (row < m && col <= row)
+          K[pl(row, col, m)] = make_double2(0.5 * kre[q][v], row == col ? 0.0 : 0.5 * kim[q][v]);
+      }
+    }
+    __syncthreads();
+    return;
+  }
   for (int t = wave; t < ntile; t += NW) {
     int ta = 0, rem = t;
     while (rem > ta) {
@@ -2124,8 +2310,14 @@ __device__ __forceinline__ void rk_stage(const SmallRkParams &p, const SmallWs &
     double *scr = jl ? reinterpret_cast<double *>(s_arena + npl) : reinterpret_cast<double *>(Vj);
     if (threadIdx.x <= j) sh.coef[threadIdx.x] = h * (last ? p.b[threadIdx.x] : p.a[j + 1][threadIdx.x]);
     __syncthreads();
-    stage_matrix(K, m, r, u1, p.lam, j + 1, ws.stage, (size_t)3 * D * r, ws.stage + D * r, (size_t)3 * D * r,
-                 ws.stage + 2 * D * r, (size_t)3 * D * r, sh.coef);
+    // the arena branch passes s_arena itself, so that the compiler sees LDS
+    // accesses (a pointer chosen at run time is generic: flat instructions)
+    if (jl)
+      stage_matrix(s_arena, m, r, u1, p.lam, j + 1, ws.stage, (size_t)3 * D * r, ws.stage + D * r,
+                   (size_t)3 * D * r, ws.stage + 2 * D * r, (size_t)3 * D * r, sh.coef, s_arena, arena);
+    else
+      stage_matrix(Kg, m, r, u1, p.lam, j + 1, ws.stage, (size_t)3 * D * r, ws.stage + D * r, (size_t)3 * D * r,
+                   ws.stage + 2 * D * r, (size_t)3 * D * r, sh.coef);
     lap(5);
     {
       int fk = 0;
@@ -2148,8 +2340,11 @@ __device__ __forceinline__ void rk_stage(const SmallRkParams &p, const SmallWs &
         if (threadIdx.x == 0) ws.warm_skip[j] = skip - 1.0;
       } else {
         int its = 0;
-        solved = warm_top(K, m, r, u, r, unext, r, D, s_arena, arena, 10, p.warm_tol, sh.js, its,
-                          use_rot ? tmp : nullptr, p.lam);
+        uint64_t t_w = 0;
+        if (threadIdx.x == 0) t_w = now_ticks();
+        solved = warm_top(s_arena, m, r, u, r, unext, r, D, s_arena, arena, 10, p.warm_tol, sh.js, its,
+                          use_rot ? tmp : nullptr, p.lam, &sh.ts.tacc[6]);
+        if (threadIdx.x == 0) sh.ts.tacc[5] += (double)(now_ticks() - t_w);
         if (threadIdx.x == 0) {
           stats[solved ? 9 : 31] += 1;
           stats[12] += its;
@@ -2157,7 +2352,12 @@ __device__ __forceinline__ void rk_stage(const SmallRkParams &p, const SmallWs &
         }
       }
     }
-    if (!solved) eig_top(K, m, r, unext, r, D, scr, jl, sh.ts);
+    if (!solved) {
+      if (jl)
+        eig_top(s_arena, m, r, unext, r, D, reinterpret_cast<double *>(s_arena + npl), true, sh.ts);
+      else
+        eig_top(Kg, m, r, unext, r, D, scr, false, sh.ts);
+    }
     if (record && s_slot < p.rec_cap) {  // training target T = u* u_next
       zgemm(X11, r, u, r, true, unext, r, r, r, D);
       float *dst = p.rec + (size_t)s_slot * net_sample_floats(r) + net_in(r);

@@ -402,6 +402,31 @@ def test_rk4_large_rank(r, hmode):
     assert err < 1e-11
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_rk4_degenerate_spectrum(precision):
+    """Lambda_0 with an exactly repeated and a nearly repeated pair: the warm
+    solver's Ritz step meets eigenvalue gaps of order h (the Newton refinement
+    of the Ritz vectors may not contract there and the Jacobi solve takes
+    over).  rho = V Lambda_0 V* is unique however a repeated pair's vectors
+    are rotated; 4 RK4 steps against the oracle."""
+    n, r = 9, 8
+    rng = np.random.default_rng(1300)
+    bonds, J, h = _random_model(n, rng)
+    V = haar_factor(2 ** n, r, rng)
+    lam = np.array([0.3, 0.2, 0.2, 0.12, 0.1 + 1e-9, 0.1, 0.05, 0.03])
+    lam = lam / lam.sum()
+    ctx = _ctx(precision)
+    ctx.set_hamiltonian(n, bonds, J, h)
+    ctx.set_rho(lam, V)
+    ctx.step("qLL", "RK4", 0.01, 0.5, 4)
+    st = ctx.stats()
+    H = Hamiltonian(n, bonds, J, h)
+    Vo = oracle_run(H, V, lam, "qLL", 0.5, 0.01, 4, "RK4")
+    err = rel_fro_error(ctx.get_rho()[1], lam, Vo, lam)
+    print(f"{precision}: {err:.3e}, warm accepted {st['warm_accepted']} of {st['eigensolves']}")
+    assert err < (1e-11 if precision == "fp64" else 1e-5)
+
+
 @pytest.mark.parametrize("r", [20, 27, 32])
 def test_rk4_large_rank_mixed(r):
     """Mixed precision above r = 16 (two columns per lane, three Gram items
