@@ -1648,6 +1648,89 @@ __device__ void rhs_coords(const double2 *u, const double2 *y, int m, int D, int
   __syncthreads();
 }
 
+// The stage's y = R That R^{-1} u and f = z u* + u w* (projector form of the
+// complement action; eqs. 3.2 / 4.1, 3.3-3.5) with every operand but R and
+// R^{-1} in the LDS arena L (>= 4 D r + 2 r^2 words): the same products as
+// rhs_coords, without the global round trips of its scratch blocks.  Writes
+// z, w (D rows, rows >= mo zero) and Gr; bad[0..2] report non-finite u, y,
+// z or w (workgroup-uniform).  Part one: u to LDS and y; part two: the rest.
+struct StageLds {
+  double2 *u, *y, *t, *c, *G, *X;
+};
+__device__ __forceinline__ StageLds stage_lds_layout(double2 *L, int D, int mo, int r) {
+  StageLds a;
+  a.u = L;
+  a.y = a.u + mo * r;
+  a.t = a.y + mo * r;
+  a.c = a.t + D * r;
+  a.G = a.c + mo * r;
+  a.X = a.G + r * r;
+  return a;
+}
+__device__ __forceinline__ void stage_hu_lds(const StageLds &a, const double2 *u, const double2 *R, const double2 *Ri,
+                                             const double *shifts, double beta, int j, int mi, int mo, int D, int r,
+                                             const unsigned char *drop, int *bad) {
+  int b0 = 0;
+  for (int e = threadIdx.x; e < mo * r; e += NT) {
+    const double2 v = u[e];
+    if (!isfinite(v.x) || !isfinite(v.y)) b0 = 1;
+    a.u[e] = v;
+  }
+  bad[0] = __syncthreads_or(b0);
+  zgemm(a.t, r, Ri, D, false, a.u, r, mi, r, mi);  // t = R^{-1} u
+  const double ib = 1.0 / beta;
+  for (int e = threadIdx.x; e < mo * r; e += NT) {
+    const int row = e / r, col = e % r, bi = row / r, q = row % r;
+    double2 v = bi <= j ? cscale(shifts[bi * r + q], a.t[e]) : make_double2(0, 0);
+    if (bi >= 1 && bi - 1 <= j) v = cadd(v, cscale(ib, a.t[((bi - 1) * r + q) * r + col]));
+    a.c[e] = v;  // That t
+  }
+  __syncthreads();
+  zgemm(a.y, r, R, D, false, a.c, r, mo, r, mo);
+  int b1 = 0;
+  for (int e = threadIdx.x; e < mo * r; e += NT) {
+    if (drop[e / r]) a.y[e] = make_double2(0, 0);
+    const double2 v = a.y[e];
+    if (!isfinite(v.x) || !isfinite(v.y)) b1 = 1;
+  }
+  bad[1] = __syncthreads_or(b1);
+}
+__device__ __forceinline__ void stage_rhs_lds(const StageLds &a, int mo, int D, int r, const ModelCoef &mc,
+                                              double2 *z, double2 *w, double2 *Gr, StepShared &sh, double *energy,
+                                              int *bad) {
+  const int rr = r * r;
+  double2 *cvec = sh.vec;  // c_a = phi(lam_a)
+  if (threadIdx.x < r) cvec[threadIdx.x] = phi(mc.lam[threadIdx.x], mc.model, mc.kappa, mc.hbar);
+  zgemm(a.G, r, a.u, r, true, a.y, r, r, r, mo);  // G = u* y
+  for (int e = threadIdx.x; e < rr; e += NT) {
+    const int p = e / r, q = e % r;
+    const double2 g1 = a.G[p * r + q], g2 = a.G[q * r + p];
+    const double2 gs = make_double2(0.5 * (g1.x + g2.x), 0.5 * (g1.y - g2.y));
+    a.X[e] = p == q ? make_double2(0, 0) : cmul(phi(mc.lam[p] - mc.lam[q], mc.model, mc.kappa, mc.hbar), gs);
+    Gr[e] = g1;
+  }
+  if (energy && threadIdx.x == 0) {
+    double en = 0;
+    for (int q = 0; q < r; ++q) en += mc.lam[q] * a.G[q * r + q].x;
+    *energy = en;
+  }
+  __syncthreads();
+  zgemm(a.t, r, a.u, r, false, a.G, r, mo, r, r);  // u G
+  zgemm(a.c, r, a.u, r, false, a.X, r, mo, r, r);  // u X11
+  int b2 = 0;
+  for (int e = threadIdx.x; e < D * r; e += NT) {
+    double2 wv = make_double2(0, 0), zv = make_double2(0, 0);
+    if (e < mo * r) {
+      wv = cmul(csub(a.y[e], a.t[e]), cconj(cvec[e % r]));  // w = (y - u G) diag(conj c)
+      zv = cadd(a.c[e], wv);                                // z = u X11 + w
+      if (!isfinite(wv.x) || !isfinite(wv.y) || !isfinite(zv.x) || !isfinite(zv.y)) b2 = 1;
+    }
+    w[e] = wv;
+    z[e] = zv;
+  }
+  bad[2] = __syncthreads_or(b2);
+}
+
 // Packed (lower, column-major) Hermitian stage matrix of order m:
 // K = u1 diag(lam) u1* + sum_l coef_l (z_l u_l* + u_l w_l*)   (eqs. 3.7-3.9;
 // lam == nullptr: without the first term),
@@ -2245,6 +2328,18 @@ __device__ __forceinline__ void rk_stage(const SmallRkParams &p, const SmallWs &
     double2 *w = ws.stage + (3 * j + 2) * D * r;
     const int mi = (j + 1) * r;  // support of u
     const int mo = (j + 2) * r;  // support of y = H u
+    // first non-finite value: stats[28] = 10 * stage + phase (1 u, 2 y, 3 z/w, 4 K, 5 eigenvectors)
+    if (threadIdx.x == 0 && j == 0) stats[28] = -1;
+    if (p.householder_mode == 0 && 4 * D * r + 2 * rr <= arena) {
+      // the stage's right-hand side with its operands in LDS
+      const StageLds a = stage_lds_layout(s_arena, D, mo, r);
+      int bad[3];
+      stage_hu_lds(a, u, R, Ri, ws.shifts, p.beta, j, mi, mo, D, r, sh.drop, bad);
+      lap(3);
+      stage_rhs_lds(a, mo, D, r, mc, z, w, Gr, sh, j == 0 ? &stats[5] : nullptr, bad);
+      if (threadIdx.x == 0 && stats[28] < 0 && (bad[0] | bad[1] | bad[2]))
+        stats[28] = 10 * j + (bad[0] ? 1 : (bad[1] ? 2 : 3));
+    } else {
     // y = R That R^{-1} u, That the block-bidiagonal relation H P_i = P_i D_i + P_{i+1} / beta
     zgemm(t1, r, Ri, D, false, u, r, mi, r, mi);
     {
@@ -2263,12 +2358,11 @@ __device__ __forceinline__ void rk_stage(const SmallRkParams &p, const SmallWs &
     lap(3);
     rhs_coords(u, y, mo, D, r, mc, p.householder_mode, z, w, Gr, X11, t1, Uh, Yc, s_arena, arena, sh,
                j == 0 ? &stats[5] : nullptr);
-    // first non-finite value: stats[28] = 10 * stage + phase (1 u, 2 y, 3 z/w, 4 K, 5 eigenvectors)
-    if (threadIdx.x == 0 && j == 0) stats[28] = -1;
     {
       const int f1 = any_nonfinite(u, D * r), f2 = any_nonfinite(y, D * r);
       const int f3 = any_nonfinite(z, D * r) | any_nonfinite(w, D * r);
       if (threadIdx.x == 0 && stats[28] < 0 && (f1 | f2 | f3)) stats[28] = 10 * j + (f1 ? 1 : (f2 ? 2 : 3));
+    }
     }
     lap(4);
     if (j == s) {
