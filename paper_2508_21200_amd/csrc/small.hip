@@ -461,6 +461,13 @@ __device__ inline double rcp_nr(double b) {
   return r * fma(-b, r, 2.0);
 }
 
+// 1/sqrt(a) (a > 0 and normal) from the hardware reciprocal square root refined
+// by one Newton step, y (3 - a y^2) / 2.
+__device__ inline double rsq_nr(double a) {
+  const double y = __builtin_amdgcn_rsq(a);
+  return y * fma(-0.5 * a * y, y, 1.5);
+}
+
 // Number of eigenvalues of the real symmetric tridiagonal (d, e) below s, by
 // the ratio form of the Sturm sequence (pivots of LDL^T of T - s I).  The
 // recurrence is a serial chain; (d, e^2) are read eight entries ahead of it.
@@ -519,18 +526,31 @@ __device__ __forceinline__ void eig_top(double2 *A, int m, int r, double2 *u, in
       s2 = wave_sum_d(s2);
       if (lane == 0) {
         const double2 x0 = A[pl(k + 1, k, m)];
-        const double nx = sqrt(s2), ax0 = sqrt(cabs2(x0));
         if (!(s2 > 1e-300)) {
           // column already reduced (below any meaningful scale): no reflector,
           // the negligible remainder below the subdiagonal is dropped
           ts.beta[k] = 0.0;
           ts.e[k] = x0;
         } else {
-          const double2 ph = ax0 > 0 ? cscale(1.0 / ax0, x0) : make_double2(1, 0);
-          const double2 alpha = cscale(-nx, ph);
-          const double2 v0 = csub(x0, alpha);
-          const double vv = s2 - ax0 * ax0 + cabs2(v0);
-          ts.beta[k] = 2.0 / vv;
+          // alpha = -|x| x0 / |x0|, v0 = x0 - alpha = (1 + |x| / |x0|) x0, so
+          // |v|^2 = |v0|^2 + |x|^2 - |x0|^2 = nx^2 + 2 nx ax0 + s2 with the
+          // computed nx = |x|; square roots and quotients as reciprocal square
+          // roots and reciprocals with a Newton step (short dependent chains)
+          const double c2 = cabs2(x0);
+          const double nx = s2 * rsq_nr(s2);
+          double2 alpha, v0;
+          double ax0 = 0.0;
+          if (c2 > 1e-300) {
+            const double ia = rsq_nr(c2);
+            ax0 = c2 * ia;
+            const double q = nx * ia;
+            alpha = cscale(-q, x0);
+            v0 = cscale(1.0 + q, x0);
+          } else {
+            alpha = make_double2(-nx, 0.0);
+            v0 = make_double2(nx, 0.0);
+          }
+          ts.beta[k] = 2.0 * rcp_nr(fma(nx, nx + 2.0 * ax0, s2));
           ts.e[k] = alpha;
           A[pl(k + 1, k, m)] = v0;  // the reflector vector stays in column k
           ts.v[k + 1] = v0;
@@ -544,17 +564,28 @@ __device__ __forceinline__ void eig_top(double2 *A, int m, int r, double2 *u, in
       double2 kp = make_double2(0, 0);
       for (int i0 = k + 1; i0 < m; i0 += NT / 8) {
         const int i = i0 + grow;
-        double sr = 0, si = 0;
+        double sr = 0, si = 0, sr2 = 0, si2 = 0;  // two chains: FP64 adds wait on each other
         if (i < m) {
-          for (int j = k + 1 + gsub; j < m; j += 8) {
+          for (int j = k + 1 + gsub; j < m; j += 16) {
             const int hi = i > j ? i : j, lo = i > j ? j : i;
             double2 a = A[pl(hi, lo, m)];
             if (i < j) a.y = -a.y;
             const double2 v = ts.v[j];
-            sr += a.x * v.x - a.y * v.y;
-            si += a.x * v.y + a.y * v.x;
+            sr = fma(a.x, v.x, fma(-a.y, v.y, sr));
+            si = fma(a.x, v.y, fma(a.y, v.x, si));
+            const int j2 = j + 8;
+            if (j2 < m) {
+              const int hi2 = i > j2 ? i : j2, lo2 = i > j2 ? j2 : i;
+              double2 a2 = A[pl(hi2, lo2, m)];
+              if (i < j2) a2.y = -a2.y;
+              const double2 v2 = ts.v[j2];
+              sr2 = fma(a2.x, v2.x, fma(-a2.y, v2.y, sr2));
+              si2 = fma(a2.x, v2.y, fma(a2.y, v2.x, si2));
+            }
           }
         }
+        sr += sr2;
+        si += si2;
         sr += dpp_d<0xB1>(sr);  // sum over the 8 lanes of the group
         si += dpp_d<0xB1>(si);
         sr += dpp_d<0x4E>(sr);
@@ -571,8 +602,14 @@ __device__ __forceinline__ void eig_top(double2 *A, int m, int r, double2 *u, in
       if (lane == 0) ts.kpart[wave] = kp;
       if (lds) lds_barrier(); else __syncthreads();
       // K = (beta/2) v^H p (fixed summation order); w = p - K v
-      double2 ks = make_double2(0, 0);
-      for (int q = 0; q < NW; ++q) ks = cadd(ks, ts.kpart[q]);
+      double2 kq[NW];
+#pragma unroll
+      for (int q = 0; q < NW; ++q) kq[q] = ts.kpart[q];
+#pragma unroll
+      for (int h = NW / 2; h > 0; h >>= 1)  // pairwise, fixed order
+#pragma unroll
+        for (int q = 0; q < h; ++q) kq[q] = cadd(kq[q], kq[q + h]);
+      const double2 ks = kq[0];
       const double2 K = cscale(0.5 * beta, ks);
       // lower triangle of the trailing block: A_ij -= v_i conj(w_j) + w_i conj(v_j)
       for (int i = k + 1 + grow; i < m; i += NT / 8) {
