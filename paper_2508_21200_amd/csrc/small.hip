@@ -1132,7 +1132,7 @@ __device__ inline bool warm_fits(int m, int r, int arena_elems) {
 __device__ __forceinline__ bool warm_top(double2 *K, int m, int r, const double2 *S, int lds_in, double2 *u, int ldu,
                          int rows_out, double2 *arena, int arena_elems, int maxit, double tol, JacobiShared &js,
                          int &iters, const double2 *rot = nullptr, const double *lam = nullptr,
-                         double *ritz_ticks = nullptr) {
+                         double *ritz_ticks = nullptr, bool refine = true) {
   __shared__ double red[NW];
   __shared__ double s_lb[kMaxR];
   __shared__ int s_flag;
@@ -1234,7 +1234,7 @@ __device__ __forceinline__ bool warm_top(double2 *K, int m, int r, const double2
   auto ritz_done = [&] {
     if (threadIdx.x == 0 && ritz_ticks) *ritz_ticks += (double)(now_ticks() - t_ritz);
   };
-  if (m >= 2 * r && ritz_refine(G, r, Y, Gp, C, s_theta, red)) {
+  if (refine && m >= 2 * r && ritz_refine(G, r, Y, Gp, C, s_theta, red)) {
     if (threadIdx.x < r) {  // rank by eigenvalue, descending (ties by index)
       const int a = threadIdx.x;
       int rank = 0;
@@ -1243,7 +1243,16 @@ __device__ __forceinline__ bool warm_top(double2 *K, int m, int r, const double2
       js.order[rank] = a;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < r * r; e += NT) C[e] = Y[(e / r) * 2 * r + js.order[e % r]];
+    // each column's phase: its component along the corresponding vector of X
+    // real and positive (the vectors stay in the phases of the stage's start
+    // basis, independent of the rounding of the refinement)
+    for (int e = threadIdx.x; e < r * r; e += NT) {
+      const int a = js.order[e % r];
+      const double2 d = Y[a * 2 * r + a];
+      const double n = sqrt(cabs2(d));
+      const double2 ph = n > 0 ? make_double2(d.x / n, -d.y / n) : make_double2(1, 0);
+      C[e] = cmul(Y[(e / r) * 2 * r + a], ph);
+    }
     __syncthreads();
     zgemm(u, ldu, X, r, false, C, r, m, r, r);  // u = X Z
     for (int e = threadIdx.x; e < (rows_out - m) * r; e += NT) u[(m + e / r) * ldu + e % r] = make_double2(0, 0);
@@ -2474,7 +2483,11 @@ __device__ __forceinline__ void rk_stage(const SmallRkParams &p, const SmallWs &
         uint64_t t_w = 0;
         if (threadIdx.x == 0) t_w = now_ticks();
         solved = warm_top(s_arena, m, r, u, r, unext, r, D, s_arena, arena, 10, p.warm_tol, sh.js, its,
-                          use_rot ? tmp : nullptr, p.lam, &sh.ts.tacc[6]);
+                          use_rot ? tmp : nullptr, p.lam, &sh.ts.tacc[6],
+                          // the learned start's inputs depend on the eigenvectors'
+                          // phases: the paths that record or use it keep the phase
+                          // convention of the Jacobi rotations it was trained with
+                          !(record || use_rot));
         if (threadIdx.x == 0) sh.ts.tacc[5] += (double)(now_ticks() - t_w);
         if (threadIdx.x == 0) {
           stats[solved ? 9 : 31] += 1;
