@@ -194,7 +194,7 @@ lrei_status alloc_state(lrei_ctx *ctx, int r, bool fp32) {
                           + (size_t)kMaxStages * 3 * D * r     // stage
                           + (size_t)D * r                      // Cfin
                           + (size_t)D                          // flags (as complex slots)
-                          + (size_t)kMaxStages                 // warm_skip (as complex slots)
+                          + (size_t)kMaxStages                 // warm_skip: 2 kMaxStages doubles
                           + (size_t)kMaxBlocks * r;            // column shifts (as complex slots)
   if (!ctx->ws_buf.ensure(ws_elems * sizeof(double2))) return ctx->fail(LREI_E_NOMEM, "device allocation failed");
   if (!ctx->stats_buf.ensure(kStatsLen * sizeof(double))) return ctx->fail(LREI_E_NOMEM, "device allocation failed");
@@ -1129,7 +1129,7 @@ lrei_status lrei_set_rho(lrei_ctx *ctx, int r, const double *lambda, const void 
   }
   ctx->r = r;
   // a new state: every stage tries the warm-started eigensolve again
-  e2 = hipMemsetAsync(ctx->ws.warm_skip, 0, kMaxStages * sizeof(double), ctx->stream);
+  e2 = hipMemsetAsync(ctx->ws.warm_skip, 0, 2 * kMaxStages * sizeof(double), ctx->stream);
   // a new state: the first Krylov block's column shifts are the Rayleigh
   // quotients of V's columns (the validation pass measured P0* P1 with
   // P1 = beta H V), the later blocks' start at zero; every step refreshes them

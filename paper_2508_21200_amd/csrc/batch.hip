@@ -196,7 +196,7 @@ lrei_status alloc_traj(lrei_batch *b, lrei_batch::Traj &t, int idx) {
   t.ws.flags = (double *)w; w += (size_t)D;
   t.ws.warm_skip = (double *)w; w += (size_t)kMaxStages;
   t.ws.shifts = (double *)w;
-  if (hipMemset(t.ws.warm_skip, 0, kMaxStages * sizeof(double)) != hipSuccess ||
+  if (hipMemset(t.ws.warm_skip, 0, 2 * kMaxStages * sizeof(double)) != hipSuccess ||
       hipMemset(t.ws.shifts, 0, (size_t)kMaxBlocks * r * sizeof(double)) != hipSuccess)
     return b->fail(LREI_E_DEVICE, "device memset failed");
   t.ws.stats = (double *)b->stats.p + (size_t)idx * kStatsLen;

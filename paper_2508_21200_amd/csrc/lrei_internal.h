@@ -290,7 +290,8 @@ struct SmallWs {
   double2 *stage;    // [kMaxStages][3][D*r] u, z, w per stage
   double2 *Cfin;     // [D*r] combination coefficients for the new V
   double *flags;     // [D] directions dropped as dependent
-  double *warm_skip; // [kMaxStages] steps left before stage j tries the warm start again
+  double *warm_skip; // [2][kMaxStages] steps left before stage j tries the warm start again,
+                     // and the span of stage j's last skip (doubled on each rejection in a row)
   double *shifts;    // [kMaxBlocks][r] column shifts D_j of the Krylov recurrence (read by the
                      // passes; refreshed from the measured Rayleigh quotients by the step's last stage)
   double *stats;     // [32]

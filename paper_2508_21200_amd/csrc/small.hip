@@ -2005,7 +2005,8 @@ __device__ void householder_qr(double2 *M, int m, int q, double2 *Q, double2 *Rm
 // phase timers (100 MHz real-time counter): slots 0..2 the extension, 3..7 the
 // stage, each part adding only its own slots into stats[16..23]
 // steps a stage goes to the direct eigensolver after a rejected warm start
-constexpr int kWarmRetry = 8;
+constexpr int kWarmRetry = 8;     // steps on the direct solve after a first rejected warm start
+constexpr int kWarmRetryMax = 64;  // ... doubled after each further rejection, up to this
 
 // ---- learned start rotation: features and rotation of a stage -------------
 //
@@ -2472,8 +2473,10 @@ __device__ __forceinline__ void rk_stage(const SmallRkParams &p, const SmallWs &
       // subspace iteration from the stage's input basis u, in the LDS arena
       // after K (over the direct solver's scratch, which it rebuilds if it
       // runs).  A stage whose last attempt was rejected goes to the direct
-      // solver for the next kWarmRetry steps: the spectrum of a stage matrix
-      // changes little from one step to the next.
+      // solver for the next kWarmRetry steps, twice as many after each
+      // further rejection in a row (up to kWarmRetryMax; an accepted attempt
+      // resets it): the spectrum of a stage matrix changes little from one
+      // step to the next.  warm_skip[kMaxStages + j] keeps the current span.
       const double skip = ws.warm_skip[j];
       __syncthreads();  // every thread has read the counter before it changes
       if (skip > 0.0) {
@@ -2492,7 +2495,10 @@ __device__ __forceinline__ void rk_stage(const SmallRkParams &p, const SmallWs &
         if (threadIdx.x == 0) {
           stats[solved ? 9 : 31] += 1;
           stats[12] += its;
-          ws.warm_skip[j] = solved ? 0.0 : (double)kWarmRetry;
+          const double span = solved ? 0.0 : fmin((double)kWarmRetryMax, fmax((double)kWarmRetry,
+                                                                               2.0 * ws.warm_skip[kMaxStages + j]));
+          ws.warm_skip[j] = span;
+          ws.warm_skip[kMaxStages + j] = span;
         }
       }
     }
