@@ -624,30 +624,44 @@ __device__ __forceinline__ void eig_top(double2 *A, int m, int r, double2 *u, in
     }
   }
   tlap(0);
-  // ---- real tridiagonal: d, |e|, phases
-  if (threadIdx.x == 0) {
-    if (m >= 2) ts.e[m - 2] = A[pl(m - 1, m - 2, m)];
-    double2 ph = make_double2(1, 0);
-    double lo = 1e300, hi = -1e300;
-    for (int i = 0; i < m; ++i) {
-      ts.d[i] = A[pl(i, i, m)].x;
-      ts.ph[i] = ph;
-      if (i + 1 < m) {
-        const double a = sqrt(cabs2(ts.e[i]));
-        ts.ae[i] = a;
-        ts.e2[i] = a * a;
-        if (a > 0) ph = cmul(ph, cscale(1.0 / a, ts.e[i]));
-      }
+  // ---- real tridiagonal: d, |e|, phases.  The moduli and unit phase factors
+  // in parallel; their running product (ph_i = prod_{k<i} e_k / |e_k|) by one
+  // thread, in the same order; the Gershgorin bounds by wave reductions.
+  if (threadIdx.x == 0 && m >= 2) ts.e[m - 2] = A[pl(m - 1, m - 2, m)];
+  __syncthreads();
+  double2 *unit = ts.p;  // free after the tridiagonalisation
+  for (int i = threadIdx.x; i < m; i += NT) {
+    ts.d[i] = A[pl(i, i, m)].x;
+    if (i + 1 < m) {
+      const double a = sqrt(cabs2(ts.e[i]));
+      ts.ae[i] = a;
+      ts.e2[i] = a * a;
+      unit[i] = a > 0 ? cscale(1.0 / a, ts.e[i]) : make_double2(1, 0);
     }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double2 ph = make_double2(1, 0);
     for (int i = 0; i < m; ++i) {
+      ts.ph[i] = ph;
+      if (i + 1 < m && ts.ae[i] > 0) ph = cmul(ph, unit[i]);
+    }
+  }
+  if (wave == 0) {
+    double lo = 1e300, hi = -1e300;
+    for (int i = lane; i < m; i += 64) {
       const double rad = (i > 0 ? ts.ae[i - 1] : 0.0) + (i + 1 < m ? ts.ae[i] : 0.0);
       lo = fmin(lo, ts.d[i] - rad);
       hi = fmax(hi, ts.d[i] + rad);
     }
-    const double tn = fmax(fabs(lo), fabs(hi));
-    ts.tnorm = tn > 0 ? tn : 1.0;
-    ts.glo = lo - 1e-14 * ts.tnorm;
-    ts.ghi = hi + 1e-14 * ts.tnorm;
+    lo = -max64(-lo);
+    hi = max64(hi);
+    if (lane == 0) {
+      const double tn = fmax(fabs(lo), fabs(hi));
+      ts.tnorm = tn > 0 ? tn : 1.0;
+      ts.glo = lo - 1e-14 * ts.tnorm;
+      ts.ghi = hi + 1e-14 * ts.tnorm;
+    }
   }
   __syncthreads();
   // ---- multisection: G lanes per eigenvalue (32 when r <= 16, else 16), all
