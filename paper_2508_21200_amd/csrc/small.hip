@@ -708,6 +708,10 @@ __device__ __forceinline__ void eig_top(double2 *A, int m, int r, double2 *u, in
     const double tiny = 1e-15 * ts.tnorm;
     if (act)
       for (int i = 0; i < m; ++i) X[i * SL + k] = 1.0 + 0.25 * (double)((7 * i + 3 * k) % 11);
+    bool near = false;  // lane k: some eigenvalue j < k lies within 1e-3 of the norm
+    if (act)
+      for (int j = 0; j < k; ++j) near = near || fabs(lam - ts.lam[j]) < 1e-3 * ts.tnorm;
+    const unsigned long long close = __ballot(near);
     for (int it = 0; it < 2; ++it) {
       if (act) {
         double u0 = ts.d[0] - lam, u1 = m > 1 ? ts.ae[0] : 0.0;
@@ -781,8 +785,10 @@ __device__ __forceinline__ void eig_top(double2 *A, int m, int r, double2 *u, in
         const double inv = 1.0 / sqrt(nrm);
         for (int i = 0; i < m; ++i) X[i * SL + k] *= inv;
       }
-      // modified Gram-Schmidt within clusters of close eigenvalues (whole wave)
+      // modified Gram-Schmidt within clusters of close eigenvalues (whole wave);
+      // `close` (bit kk: eigenvalue kk has a close earlier one) skips the rest
       for (int kk = 1; kk < r; ++kk) {
+        if (!((close >> kk) & 1ull)) continue;  // the same in every lane
         bool any = false;
         for (int j = 0; j < kk; ++j) {
           if (fabs(ts.lam[kk] - ts.lam[j]) >= 1e-3 * ts.tnorm) continue;
