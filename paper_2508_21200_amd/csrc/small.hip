@@ -1465,15 +1465,16 @@ __device__ void lowdin(double2 *u, int m, int r, double2 *S, double2 *Lw, double
   const int rr = r * r;
   zgemm(S, r, u, r, true, u, r, r, r, m);
   __syncthreads();
-  if (threadIdx.x == 0) {
+  {  // max |S - I| over the entries, by every thread and a workgroup maximum
+    __shared__ double red[NW];
     double dev = 0;
-    for (int a = 0; a < r; ++a)
-      for (int b = 0; b < r; ++b) {
-        double2 g = S[a * r + b];
-        if (a == b) g.x -= 1.0;
-        dev = fmax(dev, sqrt(cabs2(g)));
-      }
-    sh.dev = dev;
+    for (int e = threadIdx.x; e < rr; e += NT) {
+      double2 g = S[e];
+      if (e / r == e % r) g.x -= 1.0;
+      dev = fmax(dev, sqrt(cabs2(g)));
+    }
+    dev = block_max(dev, red);
+    if (threadIdx.x == 0) sh.dev = dev;
   }
   __syncthreads();
   if (!(sh.dev > 1e-14)) return;
