@@ -1457,13 +1457,17 @@ __device__ void upper_inverse(const double2 *R, int ldr, double2 *Ri, int ldi, i
   }
 }
 
-// u (m x r) <- u (u* u)^{-1/2} when max|u* u - I| > 1e-14 (Lowdin), by an r x r
-// Jacobi eigendecomposition.  S, Lw, T: r x r, r x r, m x r scratch (global);
-// the packed Jacobi matrices use the LDS arena (>= 2 r^2 elements).
-__device__ void lowdin(double2 *u, int m, int r, double2 *S, double2 *Lw, double2 *T, double2 *arena,
-                       StepShared &sh, double tol, int max_sweeps) {
+// u (m x r) <- u (u* u)^{-1/2} when max|u* u - I| > 1e-14 (Lowdin), by the
+// series below or an r x r Jacobi eigendecomposition.  S, Lw, T: r x r, r x r,
+// m x r scratch (in the LDS arena after its first 3 r^2 elements where they
+// fit, else global); u is copied to T once and every product reads T; the
+// packed Jacobi matrices and the series terms use the arena's start.
+__device__ __forceinline__ void lowdin(double2 *u, int m, int r, double2 *S, double2 *Lw, double2 *T,
+                                       double2 *arena, StepShared &sh, double tol, int max_sweeps) {
   const int rr = r * r;
-  zgemm(S, r, u, r, true, u, r, r, r, m);
+  for (int e = threadIdx.x; e < m * r; e += NT) T[e] = u[e];
+  __syncthreads();
+  zgemm(S, r, T, r, true, T, r, r, r, m);
   __syncthreads();
   {  // max |S - I| over the entries, by every thread and a workgroup maximum
     __shared__ double red[NW];
@@ -1514,7 +1518,6 @@ __device__ void lowdin(double2 *u, int m, int r, double2 *S, double2 *Lw, double
       Lw[e] = acc;
     }
   }
-  for (int e = threadIdx.x; e < m * r; e += NT) T[e] = u[e];
   __syncthreads();
   zgemm(u, r, T, r, false, Lw, r, m, r, r);
   __syncthreads();
@@ -2383,7 +2386,11 @@ __device__ __forceinline__ void rk_stage(const SmallRkParams &p, const SmallWs &
   if (j == 0) {
     for (int e = threadIdx.x; e < D * r; e += NT) u1[e] = R[(e / r) * D + e % r];
     __syncthreads();
-    lowdin(u1, D, r, tmp, Lw, t1, s_arena, sh, p.eig_tol, p.max_sweeps);
+    if (D * r + 5 * rr <= arena)  // scratch in the arena, after the series' three terms
+      lowdin(u1, D, r, s_arena + 3 * rr + D * r, s_arena + 4 * rr + D * r, s_arena + 3 * rr, s_arena, sh,
+             p.eig_tol, p.max_sweeps);
+    else
+      lowdin(u1, D, r, tmp, Lw, t1, s_arena, sh, p.eig_tol, p.max_sweeps);
     if (threadIdx.x == 0) stats[4] = sh.dev;
   }
 
