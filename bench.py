@@ -38,7 +38,7 @@ HBM_PEAK_GBS = 8000.0
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", type=int, default=3,
                     help="3: the n=20 lattice (default); 4: 64 batched trajectories; 2, 5: other single "
@@ -949,7 +949,7 @@ def main():
             "epl": tuning["epl"], "grid": tuning["grid"], "tile_bits": tuning["tile_bits"],
             "tile_waves": tuning["tile_waves"], "ms": round(tuning["ms"], 5),
             "tried": [[e, g, tile, round(t, 5)] for (e, g, w, t), tile in zip(tuning["tried"], tuning["tried_tile"])],
-            "compact": tuning.get("compact"),
+            "compact": tuning.get("compact"), "overlap_grid": tuning.get("overlap_grid"),
             "tried_fields": "columns per lane, workgroups, variant (0: untiled, 1: untiled with compacted "
                             "gathers, 100 tile_bits + waves: tiled), ms"},
         "eig_stats": {k: stats[k] for k in ("eigensolves", "warm_accepted", "warm_rejected", "warm_iterations",

@@ -312,6 +312,10 @@ typedef struct {
   int compact;             /* 1: the untiled pass with compacted gathers (each row walks
                               only the terms whose coefficient is non-zero for it; r <= 16,
                               at most 64 off-diagonal terms)                              */
+  int overlap_grid;        /* workgroups of the passes of a step after the first, which
+                              run beside the one-workgroup stage kernels: grid less the
+                              workgroups of two CUs per XCD when grid fills every CU and
+                              the pass takes the dynamic chunk schedule, else grid        */
 } lrei_tune_result;
 
 /* Chooses the launch shape of the matrix-free H.V pass (eq. 5.1 applied in

@@ -76,6 +76,11 @@ struct lrei_ctx {
   int hv_tile_bits = 0;           // tiled pass: 2^bits rows per LDS tile (0: untiled)
   int hv_tile_waves = 16;         // tiled pass: waves per workgroup
   int hv_compact = 0;             // untiled pass with compacted gathers
+  int num_cus = 0;                // compute units of the device
+  // grid of the passes that overlap stage kernels, cached for one pass shape
+  struct {
+    int grid = -1, epl = -1, r = -1, compact = -1, fp32 = -1, result = 0;
+  } overlap;
   // H.V sweep plan: each sweep applies the terms whose flip masks lie in its
   // window of row bits (one sweep = all bits, all terms)
   struct HvSweep {
@@ -310,6 +315,7 @@ bool hv_pass_into(lrei_ctx *ctx, int r, int grid, int mode, const void *cur, voi
 void reset_hv_tuning(lrei_ctx *ctx) {
   ctx->epl = 0;
   ctx->hv_grid = 0;
+  ctx->overlap = {};
   ctx->hv_tile_bits = 0;
   ctx->hv_compact = 0;
   ctx->drop_graph();
@@ -318,8 +324,43 @@ void reset_hv_tuning(lrei_ctx *ctx) {
 // Krylov pass j of a step: P_{j+1} = beta (H P_j - P_j diag(D_j)) into
 // blocks[j + 1] with its Gram products into slot j of ws.meas; D_j is the
 // context's column shift of block j (zero when `shifted` is false).
+// Grid of a pass that runs beside the step's stage kernels.  A stage kernel
+// is one workgroup that needs a whole CU (all of its vector registers); while
+// a pass holds every CU the stage waits for the pass to drain.  When the
+// tuned grid fills the chip, such passes leave two CUs of each of the 8 XCDs
+// free: (CUs - 16) x the workgroups a CU holds.  Only the dynamic chunk
+// schedule, which balances any grid that is a multiple of 8, takes it.
+int overlap_grid(lrei_ctx *ctx) {
+  auto &o = ctx->overlap;
+  const int r = ctx->r, fp32 = ctx->fp32 ? 1 : 0;
+  if (o.grid == ctx->hv_grid && o.epl == ctx->epl && o.r == r && o.compact == ctx->hv_compact && o.fp32 == fp32)
+    return o.result;
+  o.grid = ctx->hv_grid;
+  o.epl = ctx->epl;
+  o.r = r;
+  o.compact = ctx->hv_compact;
+  o.fp32 = fp32;
+  o.result = ctx->hv_grid;
+  const int cus = ctx->num_cus;
+  if (ctx->hv_tile_bits > 0 || ctx->sweeps.size() > 1 || cus <= 16 || cus % 8 != 0) return o.result;
+  HvArgs a{};
+  hv_args(ctx, a);
+  a.N = ctx->N;
+  a.r = r;
+  if (!hv_epl_valid(ctx->fp32, r, a.epl)) a.epl = 0;
+  a.mode = 1;
+  a.grid = ctx->hv_grid;
+  a.compact = ctx->hv_compact && r <= 16;
+  bool dyn = false;
+  const int per_cu = hv_resident_per_cu(ctx->fp32, a, &dyn);
+  if (!dyn || per_cu <= 0 || ctx->hv_grid < cus * per_cu) return o.result;
+  a.grid = (cus - 16) * per_cu;
+  if (hv_resident_per_cu(ctx->fp32, a, &dyn) > 0 && dyn) o.result = a.grid;
+  return o.result;
+}
+
 void krylov_pass(lrei_ctx *ctx, int j, bool shifted = true) {
-  hv_pass_into(ctx, ctx->r, ctx->hv_grid, j == 0 ? 0 : 1, ctx->blocks[j].p, ctx->blocks[j + 1].p,
+  hv_pass_into(ctx, ctx->r, j == 0 ? ctx->hv_grid : overlap_grid(ctx), j == 0 ? 0 : 1, ctx->blocks[j].p, ctx->blocks[j + 1].p,
                  (double2 *)ctx->partials.p, ctx->ws.meas + (size_t)j * 3 * ctx->r * ctx->r, true, kMaxHvGrid,
                  shifted ? ctx->ws.shifts + (size_t)j * ctx->r : nullptr);
 }
@@ -572,6 +613,7 @@ lrei_status promote_fp64(lrei_ctx *ctx) {
   ctx->fp32 = false;
   ctx->epl = 0;
   ctx->hv_grid = 0;
+  ctx->overlap = {};
   ctx->hv_tile_bits = 0;
   ctx->hv_compact = 0;
   lrei_status st = alloc_state(ctx, ctx->r, false);
@@ -864,6 +906,10 @@ lrei_status lrei_create(lrei_ctx **out, int hip_device, void *hip_stream, const 
   }
   if (hip_stream) ctx->stream = (hipStream_t)hip_stream;
   ctx->own_stream = !hip_stream;
+  if (hipDeviceGetAttribute(&ctx->num_cus, hipDeviceAttributeMultiprocessorCount, hip_device) != hipSuccess) {
+    delete ctx;
+    return LREI_E_DEVICE;
+  }
   if (create_streams(!hip_stream, &ctx->stream, &ctx->side) != hipSuccess ||
       hipStreamCreateWithFlags(&ctx->basis, hipStreamNonBlocking) != hipSuccess) {
     lrei_destroy(ctx);
@@ -2036,6 +2082,7 @@ lrei_status lrei_autotune(lrei_ctx *ctx, lrei_tune_result *out) {
   ctx->hv_tile_bits = res.tile_bits;
   ctx->hv_tile_waves = res.tile_bits > 0 ? res.tile_waves : 16;
   ctx->hv_compact = res.compact;
+  res.overlap_grid = overlap_grid(ctx);
   ctx->drop_graph();
   if (out) *out = res;
   return LREI_OK;

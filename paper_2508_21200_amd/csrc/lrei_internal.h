@@ -118,6 +118,10 @@ bool hv_epl_valid(bool fp32, int r, int epl);
 bool prepare_hv(bool fp32, HvArgs &a);
 size_t hv_lds_bytes(bool fp32, int r);
 size_t hv_launch_lds(bool fp32, const HvArgs &a);  // dynamic LDS of a prepared pass
+// Workgroups of the (unprepared) pass a that fit on one CU at once, 0 if the
+// shape is unsupported or is a tiled pass; *dynamic tells whether the pass
+// takes the dynamic chunk schedule.
+int hv_resident_per_cu(bool fp32, const HvArgs &a, bool *dynamic);
 
 // Launch tables of a batched kernel (many independent jobs in one launch):
 // workgroup w runs job wg_job[w] as that job's workgroup w - job_wg0[job].
@@ -311,6 +315,14 @@ inline int small_lds_elems(int D, int r) {
   if (3 * D * r > need) need = 3 * D * r;
   if (2 * r * r > need) need = 2 * r * r;
   return need < kSmallLdsElems ? need : kSmallLdsElems;
+}
+// LDS capacity (double2 elements) of a basis extension: its Cholesky factor
+// and triangular inverse stage at most 2 (2r)^2 elements (the first stage's two
+// blocks), so it asks for no more than that and fits on a CU beside more
+// workgroups of a running pass than a stage does.
+__host__ __device__ inline int small_basis_lds_elems(int lds_elems, int r) {
+  const int need = 8 * r * r;
+  return need < lds_elems ? need : lds_elems;
 }
 void launch_small_rk(const SmallRkParams &p, const SmallWs &ws, hipStream_t s);
 // Stage j of an RK step in two launches: the basis extension (needs the Grams

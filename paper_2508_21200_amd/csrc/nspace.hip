@@ -396,13 +396,15 @@ __device__ __forceinline__ void hv_body(const HvArgs &a, int wg, unsigned char *
   // does not depend on which workgroup took which chunk.  Each workgroup
   // makes one failing take; the slot's last one to finish (counted in
   // sched[8 + x]) resets both counters for the next launch.
+  // Chunk c of a slot holds tiles c, c + cpx, ... below per: per / cpx or one
+  // more, so any chunk count up to per covers the slot.
   const int cpx = DYN ? a.chunks >> 3 : 1;
-  const long long per = num_tiles >> 3, cs = DYN ? per / cpx : 0;
+  const long long per = num_tiles >> 3;
   // dynamic schedule only (r <= 16): the staged partial sums fit in the planes
   double *lacc = reinterpret_cast<double *>(smem + 4 * (size_t)plane * sizeof(T));
   __shared__ int s_chunk;
   int chunk = -1;
-  long long kc = cs;
+  long long kc = 0, kn = 0;  // tiles of the current chunk done / in it
   if constexpr (DYN) {
     for (int v = 0; v < 8; ++v) lacc[v * kThreads + threadIdx.x] = 0.0;
   }
@@ -410,7 +412,7 @@ __device__ __forceinline__ void hv_body(const HvArgs &a, int wg, unsigned char *
     long long row0 = 0;
     uint32_t tbase = 0;
     if constexpr (DYN) {
-      if (kc == cs) {
+      if (kc == kn) {
         if (grams && chunk >= 0) {  // the finished chunk's partial sums
           double av[1][8];
 #pragma unroll
@@ -434,6 +436,7 @@ __device__ __forceinline__ void hv_body(const HvArgs &a, int wg, unsigned char *
           break;
         }
         kc = 0;
+        kn = (per - chunk + cpx - 1) / cpx;
       }
       row0 = ((long long)xcd * per + chunk + kc * cpx) * kTile;
       ++kc;
@@ -1393,9 +1396,9 @@ bool prepare_hv(bool fp32, HvArgs &a) {
   const long long tiles = (a.N + kTile - 1) / kTile;
   const bool grams = a.mode != 2 && !a.acc_out;
   const long long cap = grams ? (a.partial_cap > 0 ? a.partial_cap : a.grid) : (1LL << 40);
-  if (fp32 && !big && a.sched && a.n_fix == 0 && a.grid >= 8 && a.grid % 8 == 0) {
+  if (fp32 && !big && a.sched && a.n_fix == 0 && a.grid >= 8 && a.grid % 8 == 0 && tiles % 8 == 0) {
     for (long long ch = 2LL * a.grid; ch >= a.grid; ch /= 2)
-      if (ch <= cap && tiles % ch == 0) {
+      if (ch <= cap && ch <= tiles) {  // every chunk holds at least one tile
         a.chunks = (int)ch;
         break;
       }
@@ -1459,6 +1462,24 @@ int launch_hv(bool fp32, const HvArgs &a0, hipStream_t s) {
                                   launch_one<T, E, C, MI, DYN>(a, lds, s);
                                 });
   return ok ? (a.chunks > 0 ? a.chunks : a.grid) : 0;
+}
+
+int hv_resident_per_cu(bool fp32, const HvArgs &a0, bool *dynamic) {
+  HvArgs a = a0;
+  *dynamic = false;
+  if (!prepare_hv(fp32, a) || a.tile_bits > 0) return 0;
+  const size_t lds = hv_launch_lds(fp32, a);
+  int n = 0;
+  const bool ok = dispatch_hv(fp32, a.epl, a.cplx != 0, a.r > 16, a.chunks > 0,
+                              [&]<typename T, int E, bool C, int MI, bool DYN>() {
+                                const void *f = (const void *)k_hv<T, E, C, MI, DYN, false>;
+                                if constexpr (MI == 1)
+                                  if (a.compact) f = (const void *)k_hv<T, E, C, MI, DYN, true>;
+                                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, kThreads, lds) != hipSuccess)
+                                  n = 0;
+                              });
+  *dynamic = ok && a.chunks > 0;
+  return ok ? n : 0;
 }
 
 bool launch_hv_batch(bool fp32, int epl, bool cplx, bool big, bool dyn, const BatchLaunch &b, int total_wg,

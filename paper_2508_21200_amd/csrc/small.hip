@@ -2223,7 +2223,7 @@ __device__ __forceinline__ void rk_basis(const SmallRkParams &p, const SmallWs &
   double2 *t1 = ws.Hh + 4 * rr;         // k0 x r products (k0 <= s r; fits after S22 in D x D)
   double *flags = ws.flags;             // [D] dropped directions
   double *stats = ws.stats;
-  const int arena = p.lds_elems;
+  const int arena = small_basis_lds_elems(p.lds_elems, r);
   const int k0 = j == 0 ? 0 : (j + 1) * r;  // first new column of the Gram matrix
   const int k1 = (j + 2) * r;               // end of the new columns
   const int nn = k1 - k0;
@@ -2664,15 +2664,17 @@ void small_rk_attrs() {
 void launch_small_rk(const SmallRkParams &p, const SmallWs &ws, hipStream_t s) {
   small_rk_attrs();
   const size_t lds = (size_t)p.lds_elems * sizeof(double2);
+  const size_t lds_basis = (size_t)small_basis_lds_elems(p.lds_elems, p.r) * sizeof(double2);
   for (int j = 0; j < p.s; ++j) {
-    hipLaunchKernelGGL(k_small_rk_basis, dim3(1), dim3(NT), lds, s, p, ws, j);
+    hipLaunchKernelGGL(k_small_rk_basis, dim3(1), dim3(NT), lds_basis, s, p, ws, j);
     hipLaunchKernelGGL(k_small_rk, dim3(1), dim3(NT), lds, s, p, ws, j);
   }
 }
 
 void launch_small_rk_basis(const SmallRkParams &p, const SmallWs &ws, int j, hipStream_t s) {
   small_rk_attrs();
-  hipLaunchKernelGGL(k_small_rk_basis, dim3(1), dim3(NT), (size_t)p.lds_elems * sizeof(double2), s, p, ws, j);
+  hipLaunchKernelGGL(k_small_rk_basis, dim3(1), dim3(NT),
+                     (size_t)small_basis_lds_elems(p.lds_elems, p.r) * sizeof(double2), s, p, ws, j);
 }
 
 void launch_small_rk_stage(const SmallRkParams &p, const SmallWs &ws, int j, hipStream_t s) {

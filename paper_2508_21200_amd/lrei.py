@@ -59,7 +59,7 @@ class lrei_tune_result(ctypes.Structure):
                 ("tried_epl", ctypes.c_int * TUNE_MAX), ("tried_grid", ctypes.c_int * TUNE_MAX),
                 ("tried_win", ctypes.c_int * TUNE_MAX), ("tried_ms", ctypes.c_double * TUNE_MAX),
                 ("tile_bits", ctypes.c_int), ("tile_waves", ctypes.c_int), ("tried_tile", ctypes.c_int * TUNE_MAX),
-                ("compact", ctypes.c_int)]
+                ("compact", ctypes.c_int), ("overlap_grid", ctypes.c_int)]
 
 
 BATCH_TUNE_CLASSES = 32
@@ -342,7 +342,7 @@ class Context:
         self._check(self.lib.lrei_autotune(self.h, ctypes.byref(t)))
         return {"epl": t.epl, "grid": t.grid, "win_bits": t.win_bits, "n_sweeps": t.n_sweeps, "ms": t.ms,
                 "from_cache": bool(t.from_cache), "tile_bits": t.tile_bits, "tile_waves": t.tile_waves,
-                "compact": bool(t.compact),
+                "compact": bool(t.compact), "overlap_grid": t.overlap_grid,
                 "tried": [(t.tried_epl[i], t.tried_grid[i], t.tried_win[i], t.tried_ms[i])
                           for i in range(t.n_tried)],
                 "tried_tile": [t.tried_tile[i] for i in range(t.n_tried)]}
