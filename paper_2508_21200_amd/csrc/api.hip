@@ -321,6 +321,16 @@ void reset_hv_tuning(lrei_ctx *ctx) {
   ctx->drop_graph();
 }
 
+// Workgroups of the basis combination.  A CU holds twice as many of its
+// workgroups as of the H.V pass's, and the combination's block reads need
+// that many waves in flight: twice the pass grid, at most the tile count.
+int combine_grid(const lrei_ctx *ctx) {
+  const long long tiles = (ctx->N + 63) / 64;
+  long long g = 2LL * ctx->grid;
+  if (g > tiles) g = tiles >= 8 ? (tiles & ~7LL) : tiles;
+  return (int)(g < 1 ? 1 : g);
+}
+
 // Krylov pass j of a step: P_{j+1} = beta (H P_j - P_j diag(D_j)) into
 // blocks[j + 1] with its Gram products into slot j of ws.meas; D_j is the
 // context's column shift of block j (zero when `shifted` is false).
@@ -545,7 +555,8 @@ void enqueue_stages(lrei_ctx *ctx, const SmallRkParams &p) {
   (void)hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0);
   const void *bl[kMaxBlocks];
   for (int i = 0; i < p.nblocks; ++i) bl[i] = ctx->blocks[i].p;
-  launch_combine(ctx->fp32, bl, p.nblocks, ctx->ws.Cfin, ctx->blocks[0].p, ctx->N, ctx->r, ctx->grid, ctx->stream,
+  launch_combine(ctx->fp32, bl, p.nblocks, ctx->ws.Cfin, ctx->blocks[0].p, ctx->N, ctx->r, combine_grid(ctx),
+                 ctx->stream,
                  p.ctl ? p.ctl + kCtlSkip : nullptr, ctx->fp32 ? ctx->lo.p : nullptr,
                  ctx->fp32 ? ctx->lo.p : nullptr);
 }
@@ -1901,7 +1912,7 @@ lrei_status lrei_profile_kernels(lrei_ctx *ctx, int model, int scheme, double dt
         default: {
           const void *bl[kMaxBlocks];
           for (int i = 0; i <= p.s; ++i) bl[i] = ctx->blocks[i].p;
-          launch_combine(ctx->fp32, bl, p.s + 1, ctx->ws.Cfin, ctx->save.p, ctx->N, r, ctx->grid, ctx->stream,
+          launch_combine(ctx->fp32, bl, p.s + 1, ctx->ws.Cfin, ctx->save.p, ctx->N, r, combine_grid(ctx), ctx->stream,
                          nullptr, ctx->fp32 ? ctx->lo.p : nullptr, ctx->fp32 ? ctx->acc.p : nullptr);
         }
       }
