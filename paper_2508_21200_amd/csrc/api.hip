@@ -79,7 +79,7 @@ struct lrei_ctx {
   int num_cus = 0;                // compute units of the device
   // grid of the passes that overlap stage kernels, cached for one pass shape
   struct {
-    int grid = -1, epl = -1, r = -1, compact = -1, fp32 = -1, result = 0;
+    int grid = -1, epl = -1, r = -1, compact = -1, fp32 = -1, tile_bits = -1, sweeps = -1, result = 0;
   } overlap;
   // H.V sweep plan: each sweep applies the terms whose flip masks lie in its
   // window of row bits (one sweep = all bits, all terms)
@@ -343,8 +343,12 @@ int combine_grid(const lrei_ctx *ctx) {
 int overlap_grid(lrei_ctx *ctx) {
   auto &o = ctx->overlap;
   const int r = ctx->r, fp32 = ctx->fp32 ? 1 : 0;
-  if (o.grid == ctx->hv_grid && o.epl == ctx->epl && o.r == r && o.compact == ctx->hv_compact && o.fp32 == fp32)
+  const int ns = (int)ctx->sweeps.size();
+  if (o.grid == ctx->hv_grid && o.epl == ctx->epl && o.r == r && o.compact == ctx->hv_compact && o.fp32 == fp32 &&
+      o.tile_bits == ctx->hv_tile_bits && o.sweeps == ns)
     return o.result;
+  o.tile_bits = ctx->hv_tile_bits;
+  o.sweeps = ns;
   o.grid = ctx->hv_grid;
   o.epl = ctx->epl;
   o.r = r;
@@ -352,7 +356,7 @@ int overlap_grid(lrei_ctx *ctx) {
   o.fp32 = fp32;
   o.result = ctx->hv_grid;
   const int cus = ctx->num_cus;
-  if (ctx->hv_tile_bits > 0 || ctx->sweeps.size() > 1 || cus <= 16 || cus % 8 != 0) return o.result;
+  if (ctx->hv_tile_bits > 0 || ns > 1 || cus <= 16 || cus % 8 != 0) return o.result;
   HvArgs a{};
   hv_args(ctx, a);
   a.N = ctx->N;

@@ -53,8 +53,15 @@ def test_lattice_n16_r16_rk4_vs_oracle(lattice16, prec, tol):
     st = c.stats()
     print(f"n=16 lattice r=16 {prec}: {err:.2e} vs oracle after {steps} RK4 steps; "
           f"min pivot ratio {st['min_pivot_ratio']:.2e}"
-          + ("" if tune is None else f"; H.V shape epl={tune['epl']} grid={tune['grid']}"))
+          + ("" if tune is None else f"; H.V shape epl={tune['epl']} grid={tune['grid']} "
+             f"(passes beside the stages: {tune['overlap_grid']})"))
     assert err < tol
+    if tune is not None:
+        # the passes beside the stage kernels run at a grid of their own (a
+        # multiple of 8, at most the tuned one); at 2^16 rows (1024 tiles) a
+        # smaller one gives chunks of unequal size, covered by the bound above
+        og = tune["overlap_grid"]
+        assert 0 < og <= tune["grid"] and og % 8 == 0
     c.close()
 
 
