@@ -1324,6 +1324,7 @@ struct StepShared {
   double hbeta[kTriDim];
   unsigned char drop[kTriDim];
   double rkk[kTriDim];  // Cholesky: the diagonal of R (1 for a dropped direction)
+  double gdiag[kTriDim];  // Cholesky: the full Gram's diagonal entries of the factored columns
   double minpiv, dev;
   int ndrop;
   double coef[kMaxStages > kMaxAb ? kMaxStages : kMaxAb];  // stage or AB weights, or error weights
@@ -1340,6 +1341,8 @@ __device__ void chol_drop(const double2 *G, int ldg, const double2 *orig, int ld
   double2 *C = in_lds ? arena : R;
   const int ldc = in_lds ? n : ldr;
   for (int e = threadIdx.x; e < n * n; e += NT) C[(e / n) * ldc + e % n] = G[(e / n) * ldg + e % n];
+  // the reference diagonal, read once instead of once per column
+  for (int k = threadIdx.x; k < n; k += NT) sh.gdiag[k] = orig[k * ldo].x;
   if (threadIdx.x == 0) {
     sh.minpiv = 1.0;
     sh.ndrop = 0;
@@ -1350,7 +1353,7 @@ __device__ void chol_drop(const double2 *G, int ldg, const double2 *orig, int ld
   // and the rows are scaled by 1 / R_kk only at the end (row k is not written
   // again after step k).  Threads form a 16 x 32 grid over the upper triangle.
   for (int k = 0; k < n; ++k) {
-    const double piv = C[k * ldc + k].x, og = orig[k * ldo].x;
+    const double piv = C[k * ldc + k].x, og = sh.gdiag[k];
     const bool dropped = !(piv > 1e-13 * og) || !(og > 0);
     if (threadIdx.x == 0) {
       drop[k] = dropped;
