@@ -2612,7 +2612,7 @@ __device__ __forceinline__ void rk_stage(const SmallRkParams &p, const SmallWs &
 }
 
 // Basis extension of stage j (one workgroup).
-__global__ __launch_bounds__(NT) void k_small_rk_basis(SmallRkParams p, SmallWs ws, int j) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6))) void k_small_rk_basis(SmallRkParams p, SmallWs ws, int j) {
   extern __shared__ __align__(16) double2 s_arena[];
   __shared__ StepShared sh;
   __shared__ PhaseClock pc;
