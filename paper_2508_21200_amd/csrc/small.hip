@@ -1539,7 +1539,7 @@ struct ModelCoef {
 // z = u X11 + w.  z, w are written with D rows (rows >= m zero).
 // Scratch: Gr, X11 (r x r), t1, Uh, Yc (m x r, global); LDS arena >= 3 m r
 // elements keeps the reflector work in LDS.  *energy (if set) = sum lam_a G_aa.
-__device__ void rhs_coords(const double2 *u, const double2 *y, int m, int D, int r, const ModelCoef &mc, int hmode,
+__device__ __forceinline__ void rhs_coords(const double2 *u, const double2 *y, int m, int D, int r, const ModelCoef &mc, int hmode,
                            double2 *z, double2 *w, double2 *Gr, double2 *X11, double2 *t1, double2 *Uh,
                            double2 *Yc, double2 *arena, int arena_elems, StepShared &sh, double *energy) {
   const int rr = r * r;
@@ -2105,7 +2105,7 @@ __device__ inline RotScratch rot_scratch(int r) {
 // The predictor's rotation R (r x r, written to Rg in global memory): I,
 // Cayley(-i s G), or the network's.  ar: the arena (features at its start).
 // Ends with a barrier.
-__device__ __attribute__((noinline)) void stage_rotation(const SmallRkParams &p, int j, const double2 *Gu, int r,
+__device__ __forceinline__ void stage_rotation(const SmallRkParams &p, int j, const double2 *Gu, int r,
                                                        float *ar, double2 *Rg) {
   const RotScratch q = rot_scratch(r);
   float *f = ar + q.f, *h0 = ar + q.h0, *h1 = ar + q.h1, *part = ar + q.part, *out = ar + q.out;
@@ -2159,7 +2159,7 @@ struct PhaseClock {
 // state (C = [I; 0]: V_new = P_0 = V).
 constexpr double kFac = 0.9, kFacMin = 0.2, kFacMax = 5.0;
 
-__device__ __attribute__((noinline)) void adapt_control(const SmallRkParams &p, const SmallWs &ws, int k, double h, const double2 *ub,
+__device__ __forceinline__ void adapt_control(const SmallRkParams &p, const SmallWs &ws, int k, double h, const double2 *ub,
                               double2 *E, double2 *EV, double2 *M, double *coef) {
   __shared__ double red[NW];
   __shared__ int s_accept;
