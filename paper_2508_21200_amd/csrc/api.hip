@@ -331,12 +331,10 @@ int combine_grid(const lrei_ctx *ctx) {
   return (int)(g < 1 ? 1 : g);
 }
 
-// Krylov pass j of a step: P_{j+1} = beta (H P_j - P_j diag(D_j)) into
-// blocks[j + 1] with its Gram products into slot j of ws.meas; D_j is the
-// context's column shift of block j (zero when `shifted` is false).
 // Grid of a pass that runs beside the step's stage kernels.  A stage kernel
-// is one workgroup that needs a whole CU (all of its vector registers); while
-// a pass holds every CU the stage waits for the pass to drain.  When the
+// is one workgroup that needs most of a CU's vector registers and LDS (room
+// for at most one pass workgroup beside it); while a pass holds every slot
+// of every CU the stage waits for the pass to drain.  When the
 // tuned grid fills the chip, such passes leave two CUs of each of the 8 XCDs
 // free: (CUs - 16) x the workgroups a CU holds.  Only the dynamic chunk
 // schedule, which balances any grid that is a multiple of 8, takes it.
@@ -373,6 +371,9 @@ int overlap_grid(lrei_ctx *ctx) {
   return o.result;
 }
 
+// Krylov pass j of a step: P_{j+1} = beta (H P_j - P_j diag(D_j)) into
+// blocks[j + 1] with its Gram products into slot j of ws.meas; D_j is the
+// context's column shift of block j (zero when `shifted` is false).
 void krylov_pass(lrei_ctx *ctx, int j, bool shifted = true) {
   hv_pass_into(ctx, ctx->r, j == 0 ? ctx->hv_grid : overlap_grid(ctx), j == 0 ? 0 : 1, ctx->blocks[j].p, ctx->blocks[j + 1].p,
                  (double2 *)ctx->partials.p, ctx->ws.meas + (size_t)j * 3 * ctx->r * ctx->r, true, kMaxHvGrid,
